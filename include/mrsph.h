@@ -1,0 +1,183 @@
+/*
+ * mrsph: multi-resolution SPH for fluid-structure interaction on AMD Instinct
+ * MI355X (gfx950).  The method is that of Zhang, Rezavand & Hu,
+ * "A multi-resolution SPH method for fluid-structure interactions"
+ * (arXiv:1911.13255): a weakly-compressible fluid at smoothing length h_F,
+ * a total-Lagrangian elastic solid at h_S <= h_F integrated kappa times per
+ * fluid acoustic step, and a coupling force built from the solid's
+ * time-averaged velocity and acceleration inside a position-based Verlet
+ * scheme (Algorithm 1).
+ *
+ * Conventions for every entry point below:
+ *  - Return value: SPH_OK (0), a negative SPH_E_* error, or a positive info
+ *    code.  No C++ exception crosses this interface.
+ *  - Asynchrony: calls that advance the simulation only enqueue kernels on the
+ *    context's stream.  Errors raised inside kernels (NaN, inverted solid
+ *    element, neighbour-capacity overflow) are latched in device memory and
+ *    reported by sph_sync and by sph_read/sph_scalars, which synchronise.
+ *  - Memory: all device memory is one caller-owned arena of sph_arena_bytes()
+ *    bytes (e.g. a uint8 tensor).  The library never allocates or frees device
+ *    memory; it frees only the host context it allocated in sph_init.
+ *  - Host arrays passed in are read during the call only.
+ *  - Threading: one context per stream; calls on one context are not
+ *    thread-safe.  Contexts are independent.
+ *  - Units are SI; positions are row-major (n, dim) float64.
+ */
+#ifndef MRSPH_H
+#define MRSPH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_OK 0
+#define SPH_E_ARG (-1)      /* invalid argument or scene description */
+#define SPH_E_HIP (-2)      /* a HIP runtime call failed */
+#define SPH_E_ORDER (-3)    /* call out of sequence (e.g. before sph_init) */
+#define SPH_E_CAPACITY (-4) /* a fixed-capacity neighbour table overflowed */
+#define SPH_E_UNSTABLE (-5) /* NaN/Inf in the state or det F <= 0 */
+
+typedef struct sph_ctx sph_ctx;
+
+/* One scene.  Fluid, wall and solid particle sets with their materials.
+ * Solid particles are free ones first; the last n_clamp form the rigid base
+ * block that holds the structure (u = 0, v = 0, F = I at all times). */
+typedef struct {
+  int dim;                               /* 2 or 3; all scenes of a context share it */
+  int n_fluid, n_wall, n_solid, n_clamp; /* particle counts */
+  double dp_f, dp_s, h_ratio;            /* spacings; h = h_ratio * dp (1.3 in the paper) */
+  double rho0_f, c_f, eta, gamma;        /* fluid reference density, sound speed, dynamic viscosity, Tait exponent */
+  double g[3];                           /* body acceleration */
+  double rho0_s, E, nu;                  /* solid density, Young's modulus, Poisson ratio */
+  double cfl_ac, cfl_ad, cfl_s, u_ref;   /* acoustic, advection and solid CFL numbers; velocity floor of dt_ad */
+  double lo[3], hi[3];                   /* cell-grid box; particles outside it stay valid */
+  int periodic[3];                       /* periodic axes (box length = hi - lo; >= 3 cells of 2 h_F) */
+  double hydro_H;                        /* initial hydrostatic surface height along the last axis */
+  double inflow_U0, inflow_ts, inflow_H, inflow_len; /* inflow buffer (inflow_len = 0: none) */
+  const double *x_fluid, *v_fluid;       /* (n_fluid, dim); v_fluid may be NULL */
+  const double *x_wall, *nrm_wall;       /* (n_wall, dim): wall positions and unit normals into the fluid */
+  const double *x_solid, *v_solid;       /* (n_solid, dim); v_solid may be NULL */
+} sph_scene;
+
+typedef struct {
+  int riemann;        /* 1: low-dissipation Riemann solver (Section 2.2); 0: simple averages */
+  int density_reinit; /* 0 off; 1 rho = rho0 max(1, psi/psi0); 2 rho = max(rho, rho0 psi/psi0) */
+  int max_solid_nbr;  /* capacity of the solid reference neighbour table; 0 = default (40 in 2D, 128 in 3D) */
+  int solid_block;    /* threads per scene in the solid sub-step kernel; 0 = default */
+} sph_options;
+
+/* Field ids for sph_read / sph_write (FP64, original particle order).
+ * Vectors are (n, dim), tensors (n, dim, dim) row-major. */
+enum {
+  SPH_F_X = 0,    /* fluid position */
+  SPH_F_V = 1,    /* fluid velocity */
+  SPH_F_RHO = 2,  /* fluid density */
+  SPH_F_DRHO = 3, /* fluid density rate kept for the next half step */
+  SPH_F_A = 4,    /* fluid acceleration of the last step (read only) */
+  SPH_F_P = 5,    /* fluid mid-step pressure of the last step (read only) */
+  SPH_F_NNB = 6,  /* (fluid, wall + solid) neighbours within 2 h_F at the last rebuild (read only) */
+  SPH_S_U = 10,   /* solid displacement */
+  SPH_S_V = 11,   /* solid velocity */
+  SPH_S_A = 12,   /* solid acceleration of the last sub-step */
+  SPH_S_F = 13,   /* deformation gradient */
+  SPH_S_DF = 14,  /* rate of the deformation gradient */
+  SPH_S_FF = 15,  /* force from the fluid (read only) */
+  SPH_S_VBAR = 16,/* time-averaged velocity over the last acoustic step */
+  SPH_S_ABAR = 17,/* time-averaged acceleration over the last acoustic step */
+  SPH_S_N = 18,   /* current surface normal (read only) */
+  SPH_S_B = 19,   /* correction matrix (read only) */
+  SPH_S_N0 = 20,  /* reference surface normal (read only) */
+  SPH_S_X0 = 21   /* reference position (read only) */
+};
+
+/* Bytes of device memory needed by sph_init for these scenes and options;
+ * 0 on invalid input. */
+size_t sph_arena_bytes(const sph_scene *scenes, int n_scenes, const sph_options *opt);
+
+/* Set up the scenes (Algorithm 1, before the time loop): fluid state with a
+ * hydrostatic initial density, reference configuration of the solid with its
+ * neighbour table, FP64 correction matrices B and reference normals.
+ * dev_arena: device pointer to arena_bytes >= sph_arena_bytes() bytes, owned
+ * by the caller and kept alive until sph_destroy.  stream: a hipStream_t
+ * (NULL selects the null stream, which sph_advance cannot graph-capture).
+ * On success *out holds the new context.  Synchronises before returning. */
+int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void *dev_arena,
+             size_t arena_bytes, void *stream, sph_ctx **out);
+
+/* Start of an advection step where one is due, per scene (Algorithm 1, outer
+ * loop; Section 3.2, advection criterion): advection time step, cell-linked
+ * lists (Morton-ordered counting sort of the fluid and of walls + solid into
+ * cells of 2 h_F), frozen pair geometry, density reinitialisation, update of
+ * the solid surface normals.  Scenes with no advection step due are left as
+ * they are.  Enqueue only. */
+int neighbor_build(sph_ctx *ctx);
+
+/* One fluid acoustic step of the position-based Verlet scheme (Section 3.3):
+ * half step in density and position, momentum with the Riemann pressure,
+ * viscous and coupling forces at h_F (Section 3.1), full step in velocity,
+ * continuity with the new velocity, second half step.  Enqueue only. */
+int fluid_step(sph_ctx *ctx);
+
+/* Pressure and viscous forces of the fluid on the solid (Section 2.2,
+ * Eqs. F:p and F:v at h_F), as exact negatives of the fluid-side pair terms
+ * of the same step.  Must follow fluid_step.  Enqueue only. */
+int couple(sph_ctx *ctx);
+
+/* kappa solid sub-steps of the position-based Verlet scheme with the fluid
+ * force held constant (Section 3.3), Neo-Hookean stress (Section 2.1) and
+ * the corrected total-Lagrangian momentum equation at h_S (Section 3.1);
+ * then the time-averaged velocity and acceleration (Section 3.2) and the
+ * end-of-step time bookkeeping.  Must follow couple.  Enqueue only. */
+int solid_substeps(sph_ctx *ctx);
+
+/* n acoustic steps of Algorithm 1 (neighbor_build, fluid_step, couple,
+ * solid_substeps); the first call captures one step into a HIP graph that
+ * later calls replay.  Enqueue only. */
+int sph_advance(sph_ctx *ctx, int n_steps);
+
+/* Copy a field of one scene to host memory in original particle order
+ * (FP64).  host must hold n * (1 | dim | dim*dim) doubles.  Synchronises. */
+int sph_read(sph_ctx *ctx, int field, int scene, double *host);
+
+/* Overwrite a state field of one scene from host memory (FP64, original
+ * order).  Writing positions or velocities marks the scene for a rebuild at
+ * the next neighbor_build.  Synchronises. */
+int sph_write(sph_ctx *ctx, int field, int scene, const double *host);
+
+/* Scene time state: out[0..7] = t, dt_ac, dt_ad, dt_s, adv_accum, kappa,
+ * need_rebuild, max fluid speed.  Synchronises. */
+int sph_scalars(sph_ctx *ctx, int scene, double *out);
+
+/* Overwrite t, dt_ad, adv_accum and need_rebuild of one scene from
+ * in[0], in[2], in[4], in[6] (the other entries are ignored).  Synchronises. */
+int sph_set_scalars(sph_ctx *ctx, int scene, const double *in);
+
+/* Counters of one scene (scene = -1: sum over scenes): out[0..7] =
+ * fluid-fluid pairs, fluid-wall pairs, fluid-solid pairs (at the last
+ * rebuild), solid reference pairs, acoustic steps, rebuilds, solid sub-steps,
+ * particle interactions evaluated.  Synchronises. */
+int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out);
+
+/* FP64 reductions of one scene: out[0..2] fluid momentum, out[3..5] solid
+ * momentum, out[6] fluid kinetic energy, out[7] solid kinetic energy,
+ * out[8] solid strain energy, out[9..11] sum of the fluid force on the solid,
+ * out[12..14] sum of the solid force on the fluid re-evaluated from the last
+ * fluid step's mid-point state (valid between couple and solid_substeps).
+ * Synchronises. */
+int sph_reduce(sph_ctx *ctx, int scene, double *out);
+
+/* Wait for the stream; return the first latched device error, if any. */
+int sph_sync(sph_ctx *ctx);
+
+/* Text of the last error of this context (static storage of the context). */
+const char *sph_last_error(const sph_ctx *ctx);
+
+/* Release the host context.  The arena stays the caller's. */
+void sph_destroy(sph_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRSPH_H */

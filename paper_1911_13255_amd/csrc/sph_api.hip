@@ -1,0 +1,675 @@
+// C-ABI of the multi-resolution SPH FSI library (declared in include/mrsph.h):
+// arena planning, scene set-up, the Algorithm 1 entry points, graph capture
+// of one acoustic step, and FP64 state I/O in original particle order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mrsph.h"
+#include "sph_kernels.h"
+
+using namespace mrsph;
+
+struct sph_ctx {
+  Dev D;
+  hipStream_t stream;
+  int n_scenes, dim;
+  std::vector<ScenePar> par;
+  LaunchCfg cfg;
+  hipGraph_t graph;
+  hipGraphExec_t graph_exec;
+  int graph_failed;
+  size_t stage_doubles;
+  char err[512];
+};
+
+namespace {
+
+const size_t kAlign = 256;
+
+struct Plan {
+  int dim = 0, n_scenes = 0;
+  int nf = 0, nw = 0, ns = 0, nb = 0, ncell = 0, maxn = 0;
+  int max_count = 0;
+  std::vector<ScenePar> par;
+  std::vector<int> rank_to_lin, cell_scene, bs_scene;
+  LaunchCfg cfg{256, 256, 256};
+};
+
+double psi0_lattice(int d, double h_ratio) {
+  // number density of an unbounded lattice of unit spacing at h = h_ratio
+  double h = h_ratio, s = 0.0;
+  double alpha = d == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+  int R = (int)std::ceil(2.0 * h_ratio) + 1;
+  for (int i = -R; i <= R; ++i)
+    for (int j = -R; j <= R; ++j)
+      for (int k = (d == 3 ? -R : 0); k <= (d == 3 ? R : 0); ++k) {
+        double r = std::sqrt((double)(i * i + j * j + k * k));
+        double q = r / h;
+        if (q >= 2.0) continue;
+        double t = 1.0 - 0.5 * q;
+        s += alpha * t * t * t * t * (1.0 + 2.0 * q);
+      }
+  return s;
+}
+
+uint64_t morton_code(int d, const int *c) {
+  uint64_t code = 0;
+  for (int bit = 0; bit < 21; ++bit)
+    for (int k = 0; k < d; ++k) code |= (uint64_t)((c[k] >> bit) & 1) << (bit * d + k);
+  return code;
+}
+
+bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std::string &err) {
+  if (!sc || n <= 0) {
+    err = "no scenes";
+    return false;
+  }
+  P.dim = sc[0].dim;
+  P.n_scenes = n;
+  if (P.dim != 2 && P.dim != 3) {
+    err = "dim must be 2 or 3";
+    return false;
+  }
+  sph_options o{1, 1, 0, 0};
+  if (opt) o = *opt;
+  P.maxn = o.max_solid_nbr > 0 ? o.max_solid_nbr : (P.dim == 2 ? 40 : 128);
+  int max_solid_scene = 0;
+  for (int s = 0; s < n; ++s) {
+    const sph_scene &S = sc[s];
+    if (S.dim != P.dim) {
+      err = "all scenes must share dim";
+      return false;
+    }
+    if (S.n_fluid < 0 || S.n_wall < 0 || S.n_solid < 0 || S.n_clamp < 0 || S.n_clamp > S.n_solid) {
+      err = "invalid particle counts";
+      return false;
+    }
+    if ((S.n_fluid && !S.x_fluid) || (S.n_wall && (!S.x_wall || !S.nrm_wall)) || (S.n_solid && !S.x_solid)) {
+      err = "missing particle arrays";
+      return false;
+    }
+    if (!(S.dp_f > 0) || !(S.dp_s > 0) || !(S.h_ratio > 0) || !(S.rho0_f > 0) || !(S.c_f > 0) ||
+        !(S.gamma > 0) || !(S.rho0_s > 0) || !(S.E > 0) || !(S.nu > -1.0 && S.nu < 0.5)) {
+      err = "invalid material or resolution parameters";
+      return false;
+    }
+    ScenePar p;
+    std::memset(&p, 0, sizeof p);
+    double hf = S.h_ratio * S.dp_f, hs = S.h_ratio * S.dp_s;
+    int nc = 1;
+    for (int k = 0; k < 3; ++k) {
+      if (k < P.dim) {
+        double ext = S.hi[k] - S.lo[k];
+        if (!(ext > 0)) {
+          err = "empty box";
+          return false;
+        }
+        int m = (int)std::floor(ext / (2.0 * hf));
+        if (m < 1) m = 1;
+        if (S.periodic[k] && m < 3) {
+          err = "periodic axis needs at least 3 cells of 2 h_F";
+          return false;
+        }
+        if (m > 1048576) {
+          err = "grid too large";
+          return false;
+        }
+        p.ncell[k] = m;
+        p.csd[k] = ext / m;
+        p.lo[k] = S.lo[k];
+        p.len[k] = ext;
+        p.periodic[k] = S.periodic[k] ? 1 : 0;
+      } else {
+        p.ncell[k] = 1;
+        p.csd[k] = 1.0;
+        p.lo[k] = 0.0;
+        p.len[k] = 1.0;
+      }
+      p.cs[k] = (float)p.csd[k];
+      nc *= p.ncell[k];
+    }
+    if ((double)P.ncell + nc > 2.0e9) {
+      err = "too many cells";
+      return false;
+    }
+    p.f_begin = P.nf;
+    p.f_count = S.n_fluid;
+    p.w_begin = P.nw;
+    p.w_count = S.n_wall;
+    p.s_begin = P.ns;
+    p.s_count = S.n_solid;
+    p.s_nclamp = S.n_clamp;
+    p.b_begin = P.nb;
+    p.b_count = S.n_wall + S.n_solid - S.n_clamp;
+    p.cell_begin = P.ncell;
+    p.ncell_total = nc;
+    double d = P.dim;
+    p.hf = (float)hf;
+    p.inv_hf = (float)(1.0 / hf);
+    p.r2max_f = (float)(4.0 * hf * hf);
+    p.alpha_f = (float)(P.dim == 2 ? 7.0 / (4.0 * M_PI * hf * hf) : 21.0 / (16.0 * M_PI * hf * hf * hf));
+    p.hs = (float)hs;
+    p.inv_hs = (float)(1.0 / hs);
+    p.r2max_s = (float)(4.0 * hs * hs);
+    p.alpha_s = (float)(P.dim == 2 ? 7.0 / (4.0 * M_PI * hs * hs) : 21.0 / (16.0 * M_PI * hs * hs * hs));
+    p.rho0 = (float)S.rho0_f;
+    p.c = (float)S.c_f;
+    p.eta = (float)S.eta;
+    p.gamma = (float)S.gamma;
+    p.p_coef = (float)(S.rho0_f * S.c_f * S.c_f / S.gamma);
+    p.gam_inv_rho0c2 = (float)(S.gamma / (S.rho0_f * S.c_f * S.c_f));
+    for (int k = 0; k < 3; ++k) p.g[k] = k < P.dim ? (float)S.g[k] : 0.0f;
+    p.Vf = (float)std::pow(S.dp_f, d);
+    p.Vs = (float)std::pow(S.dp_s, d);
+    p.psi0d = psi0_lattice(P.dim, S.h_ratio);
+    p.psi0 = (float)p.psi0d;
+    p.dpf = S.dp_f;
+    p.dps = S.dp_s;
+    // Lame parameters from E and nu (E = 2 mu (1 + nu) = 3 K (1 - 2 nu))
+    double mu = S.E / (2.0 * (1.0 + S.nu));
+    double lam = S.E * S.nu / ((1.0 + S.nu) * (1.0 - 2.0 * S.nu));
+    double K = lam + 2.0 * mu / 3.0;
+    p.rho0s = (float)S.rho0_s;
+    p.mu = (float)mu;
+    p.lam = (float)lam;
+    p.c_s = (float)std::sqrt(K / S.rho0_s);
+    p.cfl_ac = (float)S.cfl_ac;
+    p.cfl_ad = (float)S.cfl_ad;
+    p.cfl_s = (float)S.cfl_s;
+    p.u_ref = (float)S.u_ref;
+    p.dt_visc = S.eta > 0 ? S.cfl_ad * hf * hf * S.rho0_f / S.eta : 0.0;
+    p.in_U0 = (float)S.inflow_U0;
+    p.in_ts = (float)S.inflow_ts;
+    p.in_H = (float)S.inflow_H;
+    p.in_len = (float)S.inflow_len;
+    p.riemann = o.riemann ? 1 : 0;
+    p.reinit = o.density_reinit;
+    // Morton order of the scene's cells
+    std::vector<std::pair<uint64_t, int>> codes(nc);
+    for (int lin = 0; lin < nc; ++lin) {
+      int c[3] = {lin % p.ncell[0], (lin / p.ncell[0]) % p.ncell[1], lin / (p.ncell[0] * p.ncell[1])};
+      codes[lin] = {morton_code(P.dim, c), lin};
+    }
+    std::sort(codes.begin(), codes.end());
+    for (int r = 0; r < nc; ++r) {
+      P.rank_to_lin.push_back(codes[r].second);
+      P.cell_scene.push_back(s);
+    }
+    for (int q = 0; q < p.b_count; ++q) P.bs_scene.push_back(s);
+    P.nf += S.n_fluid;
+    P.nw += S.n_wall;
+    P.ns += S.n_solid;
+    P.nb += p.b_count;
+    P.ncell += nc;
+    P.max_count = std::max(P.max_count, std::max(S.n_fluid, std::max(S.n_wall, S.n_solid)));
+    max_solid_scene = std::max(max_solid_scene, S.n_solid);
+    P.par.push_back(p);
+  }
+  int bs = o.solid_block;
+  if (bs <= 0) {
+    bs = 64;
+    while (bs < max_solid_scene && bs < 1024) bs *= 2;
+  }
+  if (bs < 64 || bs > 1024 || (bs & (bs - 1))) {
+    err = "solid_block must be a power of two in [64, 1024]";
+    return false;
+  }
+  P.cfg.block_solid = bs;
+  P.cfg.block_pair = P.nf < 65536 ? 64 : 256;
+  P.cfg.block_couple = 64;
+  return true;
+}
+
+// Assign arena offsets; with base == nullptr only the size is computed.
+size_t carve(char *base, const Plan &P, Dev &D) {
+  size_t off = 0;
+  auto take = [&](auto *&ptr, size_t count) {
+    using T = std::remove_reference_t<decltype(*ptr)>;
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    ptr = reinterpret_cast<T *>(base + off);
+    off += std::max<size_t>(count, 1) * sizeof(T);
+  };
+  size_t nf = P.nf, nw = P.nw, ns = P.ns, nb = P.nb, nc = P.ncell, S = P.n_scenes;
+  take(D.par, S);
+  take(D.st, S);
+  take(D.f_scene, nf);
+  take(D.f_lin, nf);
+  take(D.f_id, nf);
+  take(D.f_pos, nf);
+  take(D.f_off, nf);
+  take(D.f_posd, nf);
+  take(D.f_va, nf);
+  take(D.f_vb, nf);
+  take(D.f_vs, nf);
+  take(D.f_acc, nf);
+  take(D.f_drho, nf);
+  take(D.f_p, nf);
+  take(D.f_nnb, nf);
+  take(D.fs_lin, nf);
+  take(D.fs_slot, nf);
+  take(D.fs_id, nf);
+  take(D.f_perm, nf);
+  take(D.fs_off, nf);
+  take(D.fs_va, nf);
+  take(D.fs_drho, nf);
+  take(D.fs_m, nf);
+  take(D.fc_count, nc);
+  take(D.bc_count, nc);
+  take(D.rank_to_lin, nc);
+  take(D.cell_scene, nc);
+  take(D.fc_se, nc);
+  take(D.bc_se, nc);
+  take(D.w_lin, nw);
+  take(D.w_scene, nw);
+  take(D.w_off, nw);
+  take(D.w_nrm, nw);
+  take(D.b_pos, nb);
+  take(D.b_vbar, nb);
+  take(D.b_nrm, nb);
+  take(D.b_posd, nb);
+  take(D.b_perm, nb);
+  take(D.bs_lin, nb);
+  take(D.bs_slot, nb);
+  take(D.bs_scene, nb);
+  take(D.bs_off, nb);
+  take(D.s_scene, ns);
+  take(D.s_lin0, ns);
+  take(D.s_bslot, ns);
+  take(D.s_blin, ns);
+  take(D.s_cnt, ns);
+  take(D.s_off0, 3 * ns);
+  double **dvec[] = {&D.s_u, &D.s_v, &D.s_du, &D.s_dv};
+  for (double **p : dvec) take(*p, 3 * ns);
+  double **dten[] = {&D.s_H, &D.s_dF, &D.s_B, &D.s_PB};
+  for (double **p : dten) take(*p, 9 * ns);
+  float **vec[] = {&D.s_a, &D.s_fF, &D.s_vbar, &D.s_abar, &D.s_n0, &D.s_n};
+  for (float **p : vec) take(*p, 3 * ns);
+  take(D.s_r0d, 3 * ns);
+  take(D.s_nbr, (size_t)P.maxn * ns);
+  take(D.stage, 9 * (size_t)std::max(P.max_count, 64) + 64);
+  take(D.red, 16 * 1024);
+  return off + kAlign;
+}
+
+#define HIPCHK(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      std::snprintf(ctx->err, sizeof ctx->err, "%s: %s", #call, hipGetErrorString(e_));   \
+      return SPH_E_HIP;                                                                   \
+    }                                                                                     \
+  } while (0)
+
+int check_launch(sph_ctx *ctx, const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    std::snprintf(ctx->err, sizeof ctx->err, "%s: %s", what, hipGetErrorString(e));
+    return SPH_E_HIP;
+  }
+  return SPH_OK;
+}
+
+int field_width(int dim, int field) {
+  switch (field) {
+  case SPH_F_X: case SPH_F_V: case SPH_F_A: case SPH_S_U: case SPH_S_V: case SPH_S_A: case SPH_S_FF:
+  case SPH_S_VBAR: case SPH_S_ABAR: case SPH_S_N: case SPH_S_N0: case SPH_S_X0:
+    return dim;
+  case SPH_F_RHO: case SPH_F_DRHO: case SPH_F_P:
+    return 1;
+  case SPH_F_NNB:
+    return 2;
+  case SPH_S_F: case SPH_S_DF: case SPH_S_B:
+    return dim * dim;
+  }
+  return 0;
+}
+
+int read_states(sph_ctx *ctx, std::vector<SceneState> &st) {
+  st.resize(ctx->n_scenes);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy(st.data(), ctx->D.st, sizeof(SceneState) * ctx->n_scenes, hipMemcpyDeviceToHost));
+  return SPH_OK;
+}
+
+int enqueue_step(sph_ctx *ctx) {
+  launch_rebuild(ctx->D, ctx->cfg, ctx->stream);
+  launch_fluid_force(ctx->D, ctx->cfg, ctx->stream);
+  launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream);
+  launch_couple(ctx->D, ctx->cfg, ctx->stream);
+  launch_solid(ctx->D, ctx->cfg, ctx->stream);
+  return check_launch(ctx, "acoustic step");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sph_arena_bytes(const sph_scene *scenes, int n_scenes, const sph_options *opt) {
+  Plan P;
+  std::string err;
+  if (!make_plan(scenes, n_scenes, opt, P, err)) return 0;
+  Dev D;
+  std::memset(&D, 0, sizeof D);
+  return carve(nullptr, P, D);
+}
+
+int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void *dev_arena, size_t arena_bytes,
+             void *stream, sph_ctx **out) {
+  if (!out) return SPH_E_ARG;
+  *out = nullptr;
+  Plan P;
+  std::string perr;
+  if (!make_plan(scenes, n_scenes, opt, P, perr)) return SPH_E_ARG;
+  sph_ctx *ctx = new sph_ctx();
+  std::memset(&ctx->D, 0, sizeof ctx->D);
+  ctx->stream = (hipStream_t)stream;
+  ctx->n_scenes = n_scenes;
+  ctx->dim = P.dim;
+  ctx->par = P.par;
+  ctx->cfg = P.cfg;
+  ctx->graph = nullptr;
+  ctx->graph_exec = nullptr;
+  ctx->graph_failed = 0;
+  ctx->err[0] = 0;
+  size_t need = carve(nullptr, P, ctx->D);
+  if (!dev_arena || arena_bytes < need) {
+    std::snprintf(ctx->err, sizeof ctx->err, "arena too small: %zu < %zu", arena_bytes, need);
+    delete ctx;
+    return SPH_E_ARG;
+  }
+  char *base = (char *)(((uintptr_t)dev_arena + kAlign - 1) / kAlign * kAlign);
+  carve(base, P, ctx->D);
+  Dev &D = ctx->D;
+  D.n_scenes = n_scenes;
+  D.dim = P.dim;
+  D.nf = P.nf;
+  D.nw = P.nw;
+  D.ns = P.ns;
+  D.nb = P.nb;
+  D.ncell = P.ncell;
+  D.maxn = P.maxn;
+  ctx->stage_doubles = 9 * (size_t)std::max(P.max_count, 64) + 64;
+  hipStream_t st = ctx->stream;
+  int rc = SPH_OK;
+  auto fail = [&](int code) {
+    sph_destroy(ctx);
+    return code;
+  };
+#define HIPCHK_INIT(call)                                                               \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      std::fprintf(stderr, "mrsph: %s: %s\n", #call, hipGetErrorString(e_));            \
+      return fail(SPH_E_HIP);                                                           \
+    }                                                                                   \
+  } while (0)
+  HIPCHK_INIT(hipMemcpyAsync(D.par, P.par.data(), sizeof(ScenePar) * n_scenes, hipMemcpyHostToDevice, st));
+  std::vector<SceneState> s0(n_scenes);
+  std::memset(s0.data(), 0, sizeof(SceneState) * n_scenes);
+  for (auto &x : s0) x.need_rebuild = 1;
+  HIPCHK_INIT(hipMemcpyAsync(D.st, s0.data(), sizeof(SceneState) * n_scenes, hipMemcpyHostToDevice, st));
+  if (P.ncell) {
+    HIPCHK_INIT(hipMemcpyAsync(D.rank_to_lin, P.rank_to_lin.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
+    HIPCHK_INIT(hipMemcpyAsync(D.cell_scene, P.cell_scene.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
+    HIPCHK_INIT(hipMemsetAsync(D.fc_count, 0, sizeof(int) * P.ncell, st));
+    HIPCHK_INIT(hipMemsetAsync(D.bc_count, 0, sizeof(int) * P.ncell, st));
+    HIPCHK_INIT(hipMemsetAsync(D.fc_se, 0, sizeof(int2) * P.ncell, st));
+    HIPCHK_INIT(hipMemsetAsync(D.bc_se, 0, sizeof(int2) * P.ncell, st));
+  }
+  if (P.nb)
+    HIPCHK_INIT(hipMemcpyAsync(D.bs_scene, P.bs_scene.data(), sizeof(int) * P.nb, hipMemcpyHostToDevice, st));
+  for (int s = 0; s < n_scenes; ++s) {
+    const sph_scene &S = scenes[s];
+    int d = P.dim;
+    size_t n1 = (size_t)d * std::max(S.n_fluid, std::max(S.n_wall, S.n_solid));
+    double *x_d = D.stage, *v_d = D.stage + n1;
+    if (S.n_fluid) {
+      HIPCHK_INIT(hipMemcpyAsync(x_d, S.x_fluid, sizeof(double) * d * S.n_fluid, hipMemcpyHostToDevice, st));
+      if (S.v_fluid)
+        HIPCHK_INIT(hipMemcpyAsync(v_d, S.v_fluid, sizeof(double) * d * S.n_fluid, hipMemcpyHostToDevice, st));
+      double gabs = 0.0;
+      for (int k = 0; k < d; ++k) gabs += S.g[k] * S.g[k];
+      launch_init_scene(D, s, x_d, v_d, S.v_fluid ? 1 : 0, std::sqrt(gabs), S.hydro_H, std::pow(S.dp_f, d),
+                        S.n_fluid, st);
+    }
+    if (S.n_wall) {
+      HIPCHK_INIT(hipMemcpyAsync(x_d, S.x_wall, sizeof(double) * d * S.n_wall, hipMemcpyHostToDevice, st));
+      HIPCHK_INIT(hipMemcpyAsync(v_d, S.nrm_wall, sizeof(double) * d * S.n_wall, hipMemcpyHostToDevice, st));
+      launch_init_walls(D, s, x_d, v_d, S.n_wall, st);
+    }
+    if (S.n_solid) {
+      HIPCHK_INIT(hipMemcpyAsync(x_d, S.x_solid, sizeof(double) * d * S.n_solid, hipMemcpyHostToDevice, st));
+      if (S.v_solid)
+        HIPCHK_INIT(hipMemcpyAsync(v_d, S.v_solid, sizeof(double) * d * S.n_solid, hipMemcpyHostToDevice, st));
+      launch_init_solid(D, s, x_d, v_d, S.v_solid ? 1 : 0, S.n_solid, st);
+      launch_solid_reference(D, s, S.n_solid, st);
+    }
+    // the staging buffer is reused by the next scene: wait for this one
+    HIPCHK_INIT(hipStreamSynchronize(st));
+    if ((rc = check_launch(ctx, "scene set-up")) != SPH_OK) return fail(rc);
+  }
+  launch_solid_B(D, st);
+  launch_refresh_vmax(D, st);
+  if ((rc = check_launch(ctx, "reference configuration")) != SPH_OK) return fail(rc);
+  HIPCHK_INIT(hipStreamSynchronize(st));
+  // reference pair counts per scene
+  if (P.ns) {
+    std::vector<int> cnt(P.ns);
+    HIPCHK_INIT(hipMemcpy(cnt.data(), D.s_cnt, sizeof(int) * P.ns, hipMemcpyDeviceToHost));
+    std::vector<SceneState> stv(n_scenes);
+    HIPCHK_INIT(hipMemcpy(stv.data(), D.st, sizeof(SceneState) * n_scenes, hipMemcpyDeviceToHost));
+    for (int s = 0; s < n_scenes; ++s) {
+      unsigned long long tot = 0;
+      for (int a = 0; a < P.par[s].s_count; ++a) tot += cnt[P.par[s].s_begin + a];
+      stv[s].n_ss = tot;
+      if (stv[s].err & ERR_CAPACITY) {
+        std::snprintf(ctx->err, sizeof ctx->err, "solid neighbour table overflow in scene %d (max_solid_nbr %d)", s,
+                      P.maxn);
+        return fail(SPH_E_CAPACITY);
+      }
+    }
+    HIPCHK_INIT(hipMemcpy(D.st, stv.data(), sizeof(SceneState) * n_scenes, hipMemcpyHostToDevice));
+  }
+#undef HIPCHK_INIT
+  *out = ctx;
+  return SPH_OK;
+}
+
+int neighbor_build(sph_ctx *ctx) {
+  if (!ctx) return SPH_E_ORDER;
+  launch_rebuild(ctx->D, ctx->cfg, ctx->stream);
+  return check_launch(ctx, "neighbor_build");
+}
+
+int fluid_step(sph_ctx *ctx) {
+  if (!ctx) return SPH_E_ORDER;
+  launch_fluid_force(ctx->D, ctx->cfg, ctx->stream);
+  launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream);
+  return check_launch(ctx, "fluid_step");
+}
+
+int couple(sph_ctx *ctx) {
+  if (!ctx) return SPH_E_ORDER;
+  launch_couple(ctx->D, ctx->cfg, ctx->stream);
+  return check_launch(ctx, "couple");
+}
+
+int solid_substeps(sph_ctx *ctx) {
+  if (!ctx) return SPH_E_ORDER;
+  launch_solid(ctx->D, ctx->cfg, ctx->stream);
+  return check_launch(ctx, "solid_substeps");
+}
+
+int sph_advance(sph_ctx *ctx, int n_steps) {
+  if (!ctx) return SPH_E_ORDER;
+  if (n_steps < 0) return SPH_E_ARG;
+  if (!ctx->graph_exec && !ctx->graph_failed && ctx->stream) {
+    // capture one acoustic step; every decision inside it is taken on the device
+    hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      enqueue_step(ctx);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(ctx->stream, &g);
+      if (e == hipSuccess && g) {
+        hipGraphExec_t ge = nullptr;
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) {
+          ctx->graph = g;
+          ctx->graph_exec = ge;
+        } else {
+          (void)hipGraphDestroy(g);
+        }
+      }
+    }
+    if (!ctx->graph_exec) {
+      ctx->graph_failed = 1;
+      (void)hipGetLastError();
+    }
+  }
+  for (int k = 0; k < n_steps; ++k) {
+    if (ctx->graph_exec) {
+      HIPCHK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    } else {
+      int rc = enqueue_step(ctx);
+      if (rc != SPH_OK) return rc;
+    }
+  }
+  return SPH_OK;
+}
+
+int sph_read(sph_ctx *ctx, int field, int scene, double *host) {
+  if (!ctx) return SPH_E_ORDER;
+  if (scene < 0 || scene >= ctx->n_scenes || !host) return SPH_E_ARG;
+  int w = field_width(ctx->dim, field);
+  if (!w) return SPH_E_ARG;
+  const ScenePar &p = ctx->par[scene];
+  int n = field < 10 ? p.f_count : p.s_count;
+  if (n == 0) return SPH_OK;
+  launch_read(ctx->D, scene, field, n, ctx->D.stage, ctx->stream);
+  int rc = check_launch(ctx, "sph_read");
+  if (rc != SPH_OK) return rc;
+  HIPCHK(hipMemcpyAsync(host, ctx->D.stage, sizeof(double) * w * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return SPH_OK;
+}
+
+int sph_write(sph_ctx *ctx, int field, int scene, const double *host) {
+  if (!ctx) return SPH_E_ORDER;
+  if (scene < 0 || scene >= ctx->n_scenes || !host) return SPH_E_ARG;
+  static const int writable[] = {SPH_F_X, SPH_F_V, SPH_F_RHO, SPH_F_DRHO, SPH_S_U, SPH_S_V,
+                                 SPH_S_A, SPH_S_F, SPH_S_DF, SPH_S_VBAR, SPH_S_ABAR};
+  bool ok = false;
+  for (int f : writable) ok |= (f == field);
+  if (!ok) return SPH_E_ARG;
+  int w = field_width(ctx->dim, field);
+  const ScenePar &p = ctx->par[scene];
+  int n = field < 10 ? p.f_count : p.s_count;
+  if (n == 0) return SPH_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->D.stage, host, sizeof(double) * w * (size_t)n, hipMemcpyHostToDevice, ctx->stream));
+  launch_write(ctx->D, scene, field, n, ctx->D.stage, ctx->stream);
+  if (field != SPH_F_RHO && field != SPH_F_DRHO) launch_set_rebuild(ctx->D, scene, ctx->stream);
+  if (field == SPH_F_V) launch_refresh_vmax(ctx->D, ctx->stream);
+  int rc = check_launch(ctx, "sph_write");
+  if (rc != SPH_OK) return rc;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return SPH_OK;
+}
+
+int sph_scalars(sph_ctx *ctx, int scene, double *out) {
+  if (!ctx) return SPH_E_ORDER;
+  if (scene < 0 || scene >= ctx->n_scenes || !out) return SPH_E_ARG;
+  std::vector<SceneState> st;
+  int rc = read_states(ctx, st);
+  if (rc != SPH_OK) return rc;
+  const SceneState &S = st[scene];
+  float vm;
+  std::memcpy(&vm, &S.vmax_prev, sizeof vm);
+  double v[8] = {S.t, S.dt_ac, S.dt_ad, S.dt_s, S.adv_accum, (double)S.kappa, (double)S.need_rebuild, (double)vm};
+  std::memcpy(out, v, sizeof v);
+  return SPH_OK;
+}
+
+int sph_set_scalars(sph_ctx *ctx, int scene, const double *in) {
+  if (!ctx) return SPH_E_ORDER;
+  if (scene < 0 || scene >= ctx->n_scenes || !in) return SPH_E_ARG;
+  std::vector<SceneState> st;
+  int rc = read_states(ctx, st);
+  if (rc != SPH_OK) return rc;
+  SceneState &S = st[scene];
+  S.t = in[0];
+  S.dt_ad = in[2];
+  S.adv_accum = in[4];
+  S.need_rebuild = in[6] != 0.0;
+  HIPCHK(hipMemcpy(ctx->D.st + scene, &S, sizeof(SceneState), hipMemcpyHostToDevice));
+  return SPH_OK;
+}
+
+int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out) {
+  if (!ctx) return SPH_E_ORDER;
+  if (scene < -1 || scene >= ctx->n_scenes || !out) return SPH_E_ARG;
+  std::vector<SceneState> st;
+  int rc = read_states(ctx, st);
+  if (rc != SPH_OK) return rc;
+  unsigned long long o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int s = 0; s < ctx->n_scenes; ++s) {
+    if (scene >= 0 && s != scene) continue;
+    const SceneState &S = st[s];
+    unsigned long long v[8] = {S.n_ff, S.n_fw, S.n_fs, S.n_ss, S.steps, S.rebuilds, S.substeps, S.interactions};
+    for (int k = 0; k < 8; ++k) o[k] += v[k];
+  }
+  std::memcpy(out, o, sizeof o);
+  return SPH_OK;
+}
+
+int sph_reduce(sph_ctx *ctx, int scene, double *out) {
+  if (!ctx) return SPH_E_ORDER;
+  if (scene < 0 || scene >= ctx->n_scenes || !out) return SPH_E_ARG;
+  const ScenePar &p = ctx->par[scene];
+  int n = std::max(p.f_count, p.s_count);
+  int nb = std::max(1, std::min(1024, (n + 255) / 256));
+  double *dst = ctx->D.stage;
+  launch_reduce(ctx->D, scene, nb, dst, ctx->stream);
+  int rc = check_launch(ctx, "sph_reduce");
+  if (rc != SPH_OK) return rc;
+  double buf[16];
+  HIPCHK(hipMemcpyAsync(buf, dst, sizeof buf, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::memcpy(out, buf, 15 * sizeof(double));
+  return SPH_OK;
+}
+
+int sph_sync(sph_ctx *ctx) {
+  if (!ctx) return SPH_E_ORDER;
+  std::vector<SceneState> st;
+  int rc = read_states(ctx, st);
+  if (rc != SPH_OK) return rc;
+  for (int s = 0; s < ctx->n_scenes; ++s) {
+    int e = st[s].err;
+    if (e) {
+      std::snprintf(ctx->err, sizeof ctx->err, "scene %d: %s%s%s%s", s, (e & ERR_NAN_FLUID) ? "non-finite fluid state " : "",
+                    (e & ERR_NAN_SOLID) ? "non-finite solid state " : "", (e & ERR_JACOBIAN) ? "det F <= 0 " : "",
+                    (e & ERR_CAPACITY) ? "neighbour table overflow" : "");
+      return (e & ERR_CAPACITY) ? SPH_E_CAPACITY : SPH_E_UNSTABLE;
+    }
+  }
+  return SPH_OK;
+}
+
+const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+void sph_destroy(sph_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,33 @@
+// Host-side launchers of the HIP kernels (sph_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sph_types.h"
+
+namespace mrsph {
+
+struct LaunchCfg {
+  int block_pair;    // threads per block of the fluid pair kernels
+  int block_couple;  // threads per block of the coupling kernel
+  int block_solid;   // threads per scene of the solid sub-step kernel
+};
+
+void launch_init_scene(const Dev &D, int s, const double *x_f, const double *v_f, int has_vf, double gabs,
+                       double hydroH, double dpd, int nf, hipStream_t st);
+void launch_init_walls(const Dev &D, int s, const double *x, const double *n, int nw, hipStream_t st);
+void launch_init_solid(const Dev &D, int s, const double *x, const double *v, int has_v, int ns,
+                       hipStream_t st);
+void launch_solid_reference(const Dev &D, int s, int ns_scene, hipStream_t st);
+void launch_solid_B(const Dev &D, hipStream_t st);
+void launch_refresh_vmax(const Dev &D, hipStream_t st);
+void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
+void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
+void launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
+void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
+void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
+void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t st);
+void launch_write(const Dev &D, int s, int field, int n, const double *in, hipStream_t st);
+void launch_reduce(const Dev &D, int s, int nblocks, double *out, hipStream_t st);
+void launch_set_rebuild(const Dev &D, int s, hipStream_t st);
+
+}  // namespace mrsph

@@ -1,0 +1,1463 @@
+// HIP kernels of the multi-resolution SPH FSI method for gfx950.
+//
+// Neighbour sums are gathers: every particle sums over the 3^d cells of edge
+// >= 2 h_F around the cell it was binned in at the last rebuild, so no pair
+// force is scattered and no floating-point atomic is used.  Pair geometry
+// comes from the positions frozen at the last rebuild (the kernel values and
+// gradients of the paper's advection step), held as FP32 offsets from the
+// cell origin.
+#include <hip/hip_runtime.h>
+
+#include "sph_kernels.h"
+#include "sph_physics.h"
+
+namespace mrsph {
+
+// ------------------------------------------------------------------ helpers
+
+// Blocks are handed to the 8 XCDs round-robin; remap so that each XCD works
+// on one contiguous range of (Morton-sorted) particles and its own L2 holds
+// their neighbours.
+__device__ __forceinline__ int xcd_block() {
+  int nb = gridDim.x, b = blockIdx.x;
+  int full = (nb / 8) * 8;
+  if (b >= full) return b;
+  int per = full / 8;
+  return (b % 8) * per + b / 8;
+}
+
+__device__ __forceinline__ int particle_index() { return xcd_block() * blockDim.x + threadIdx.x; }
+
+__device__ __forceinline__ int wrapi(int n, int N) { return n < 0 ? n + N : (n >= N ? n - N : n); }
+
+__device__ __forceinline__ void decode_cell(const ScenePar &P, int lin, int *c) {
+  c[0] = lin % P.ncell[0];
+  int r = lin / P.ncell[0];
+  c[1] = r % P.ncell[1];
+  c[2] = r / P.ncell[1];
+}
+
+__device__ __forceinline__ int encode_cell(const ScenePar &P, const int *c) {
+  return c[0] + P.ncell[0] * (c[1] + P.ncell[1] * c[2]);
+}
+
+// Visit the 3^d neighbouring cells of cell `lin`; fn(neighbour linear index,
+// geometric offset of its origin from this cell's origin).
+template <int DIM, typename Fn>
+__device__ __forceinline__ void visit_cells(const ScenePar &P, int lin, Fn &&fn) {
+  int c[3];
+  decode_cell(P, lin, c);
+  const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    int n2 = c[2] + dz;
+    if (DIM == 3) {
+      if (P.periodic[2]) n2 = wrapi(n2, P.ncell[2]);
+      else if (n2 < 0 || n2 >= P.ncell[2]) continue;
+    }
+    for (int dy = -1; dy <= 1; ++dy) {
+      int n1 = c[1] + dy;
+      if (P.periodic[1]) n1 = wrapi(n1, P.ncell[1]);
+      else if (n1 < 0 || n1 >= P.ncell[1]) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        int n0 = c[0] + dx;
+        if (P.periodic[0]) n0 = wrapi(n0, P.ncell[0]);
+        else if (n0 < 0 || n0 >= P.ncell[0]) continue;
+        float sh[3] = {(float)dx * P.cs[0], (float)dy * P.cs[1], (float)dz * P.cs[2]};
+        fn(n0 + P.ncell[0] * (n1 + P.ncell[1] * n2), sh);
+      }
+    }
+  }
+}
+
+// Re-express (cell c, offset off) so that the offset lies in [0, cs) where the
+// grid allows: periodic axes wrap, other axes clamp to the edge cell and keep
+// the remainder in the offset (the 3^d search stays complete either way).
+// Returns false (and leaves a zero offset) for a non-finite position.
+template <int DIM>
+__device__ __forceinline__ bool renormalise(const ScenePar &P, int *c, double *off) {
+  bool ok = true;
+  for (int k = 0; k < DIM; ++k) {
+    if (!isfinite(off[k])) {
+      off[k] = 0.0;
+      ok = false;
+    }
+    // bounded so that the integer cell arithmetic cannot overflow
+    double q = fmin(fmax(floor(off[k] / P.csd[k]), -1.0e7), 1.0e7);
+    c[k] += (int)q;
+    off[k] -= q * P.csd[k];
+    if (P.periodic[k]) {
+      c[k] %= P.ncell[k];
+      if (c[k] < 0) c[k] += P.ncell[k];
+    } else if (c[k] < 0) {
+      off[k] += (double)c[k] * P.csd[k];
+      c[k] = 0;
+    } else if (c[k] >= P.ncell[k]) {
+      off[k] += (double)(c[k] - (P.ncell[k] - 1)) * P.csd[k];
+      c[k] = P.ncell[k] - 1;
+    }
+  }
+  return ok;
+}
+
+// FP64 absolute position -> (cell, FP64 offset)
+template <int DIM>
+__device__ __forceinline__ void locate(const ScenePar &P, const double *x, int *c, double *off) {
+  c[0] = c[1] = c[2] = 0;
+  off[0] = off[1] = off[2] = 0.0;
+  for (int k = 0; k < DIM; ++k) {
+    double s = x[k] - P.lo[k];
+    if (P.periodic[k]) s -= P.len[k] * floor(s / P.len[k]);
+    double q = floor(s / P.csd[k]);
+    if (q < 0) q = 0;
+    if (q > P.ncell[k] - 1) q = P.ncell[k] - 1;
+    c[k] = (int)q;
+    off[k] = s - q * P.csd[k];
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ double absolute(const ScenePar &P, int lin, double off, int k) {
+  int c[3];
+  decode_cell(P, lin, c);
+  double x = P.lo[k] + c[k] * P.csd[k] + (double)off;
+  if (P.periodic[k]) x = P.lo[k] + (x - P.lo[k]) - P.len[k] * floor((x - P.lo[k]) / P.len[k]);
+  return x;
+}
+
+__device__ __forceinline__ float get4(float4 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+__device__ __forceinline__ double get4(double4 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+// atomic max of a non-negative float through its bit pattern
+__device__ __forceinline__ void atomic_max_pos(unsigned int *addr, float v) {
+  atomicMax(addr, __float_as_uint(v));
+}
+
+// ------------------------------------------------------------------ init
+
+// Initial fluid state: cell-relative position, hydrostatic density
+// p = rho0 |g| (H - y_last) through the inverse Tait equation, mass rho dp^d.
+template <int DIM>
+__global__ void k_init_fluid(Dev D, int s, const double *x, const double *v, int has_v, double gabs,
+                             double hydroH, double dpd) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const ScenePar &P = D.par[s];
+  if (i >= P.f_count) return;
+  int gi = P.f_begin + i;
+  int c[3];
+  double off[3];
+  locate<DIM>(P, x + (size_t)DIM * i, c, off);
+  double pr = gabs > 0.0 ? (double)P.rho0 * gabs * (hydroH - x[(size_t)DIM * i + DIM - 1]) : 0.0;
+  // FP64 inverse equation of state for the initial state
+  double s1 = 1.0 + (double)P.gamma * pr / ((double)P.rho0 * (double)P.c * (double)P.c);
+  double eps = s1 > 0.0 ? pow(s1, 1.0 / (double)P.gamma) - 1.0 : -1.0;
+  double m = (double)P.rho0 * (1.0 + eps) * dpd;
+  D.f_scene[gi] = s;
+  D.f_lin[gi] = encode_cell(P, c);
+  D.f_id[gi] = i;
+  D.f_pos[gi] = make_float4((float)off[0], (float)off[1], (float)off[2], (float)m);
+  D.f_off[gi] = make_double4(off[0], off[1], off[2], 0.0);
+  D.f_posd[gi] = D.f_off[gi];
+  float vv[3] = {0.0f, 0.0f, 0.0f};
+  if (has_v)
+    for (int k = 0; k < DIM; ++k) vv[k] = (float)v[(size_t)DIM * i + k];
+  D.f_va[gi] = make_float4(vv[0], vv[1], vv[2], (float)eps);
+  D.f_vb[gi] = D.f_va[gi];
+  D.f_acc[gi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  D.f_drho[gi] = 0.0f;
+  D.f_p[gi] = 0.0f;
+}
+
+template <int DIM>
+__global__ void k_init_walls(Dev D, int s, const double *x, const double *n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const ScenePar &P = D.par[s];
+  if (i >= P.w_count) return;
+  int gi = P.w_begin + i;
+  int c[3];
+  double off[3];
+  locate<DIM>(P, x + (size_t)DIM * i, c, off);
+  D.w_lin[gi] = encode_cell(P, c);
+  D.w_scene[gi] = s;
+  D.w_off[gi] = make_double4(off[0], off[1], off[2], 0.0);
+  float nn[3] = {0.0f, 0.0f, 0.0f};
+  for (int k = 0; k < DIM; ++k) nn[k] = (float)n[(size_t)DIM * i + k];
+  D.w_nrm[gi] = make_float4(nn[0], nn[1], nn[2], 0.0f);
+}
+
+template <int DIM>
+__global__ void k_init_solid(Dev D, int s, const double *x, const double *v, int has_v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const ScenePar &P = D.par[s];
+  if (i >= P.s_count) return;
+  int a = P.s_begin + i;
+  int NS = D.ns;
+  int c[3];
+  double off[3];
+  locate<DIM>(P, x + (size_t)DIM * i, c, off);
+  D.s_scene[a] = s;
+  D.s_lin0[a] = encode_cell(P, c);
+  bool clamp = i >= P.s_count - P.s_nclamp;
+  for (int k = 0; k < 3; ++k) D.s_r0d[3 * (size_t)a + k] = k < DIM ? x[(size_t)DIM * i + k] : 0.0;
+  for (int k = 0; k < DIM; ++k) {
+    D.s_off0[k * NS + a] = off[k];
+    D.s_u[k * NS + a] = 0.0;
+    D.s_v[k * NS + a] = (has_v && !clamp) ? v[(size_t)DIM * i + k] : 0.0;
+    D.s_a[k * NS + a] = 0.0f;
+    D.s_fF[k * NS + a] = 0.0f;
+    D.s_vbar[k * NS + a] = 0.0f;
+    D.s_abar[k * NS + a] = 0.0f;
+    D.s_du[k * NS + a] = 0.0;
+    D.s_dv[k * NS + a] = 0.0;
+  }
+  for (int k = 0; k < DIM * DIM; ++k) {
+    D.s_H[k * NS + a] = 0.0;
+    D.s_dF[k * NS + a] = 0.0;
+    D.s_PB[k * NS + a] = 0.0;
+  }
+  D.s_bslot[a] = -1;
+  D.s_blin[a] = 0;
+}
+
+// Reference neighbour table of the solid (Section 2.2, corrected
+// configuration), by exhaustive search over the scene's solid in FP64 with
+// ascending neighbour index: b != a with |r0_a - r0_b| < 2 h_S, stored as
+// (V_b grad_a W(r0_ab, h_S), b).  Tiles of reference positions go through LDS.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_solid_neighbours(Dev D, int s) {
+  __shared__ double tile[256 * 3];
+  const ScenePar &P = D.par[s];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int a = P.s_begin + i;
+  bool active = i < P.s_count;
+  double xa[3] = {0.0, 0.0, 0.0};
+  if (active)
+    for (int k = 0; k < 3; ++k) xa[k] = D.s_r0d[3 * (size_t)a + k];
+  double h = P.hs, r2max = 4.0 * h * h;
+  double alpha = DIM == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+  int cnt = 0;
+  int NS = D.ns;
+  for (int t0 = 0; t0 < P.s_count; t0 += 256) {
+    __syncthreads();
+    int tb = t0 + threadIdx.x;
+    if (tb < P.s_count)
+      for (int k = 0; k < 3; ++k) tile[3 * threadIdx.x + k] = D.s_r0d[3 * (size_t)(P.s_begin + tb) + k];
+    __syncthreads();
+    int tn = min(256, P.s_count - t0);
+    if (!active) continue;
+    for (int q = 0; q < tn; ++q) {
+      int ib = t0 + q;
+      if (ib == i) continue;
+      double r[3];
+      double r2 = 0.0;
+      for (int k = 0; k < DIM; ++k) {
+        r[k] = xa[k] - tile[3 * q + k];
+        r2 += r[k] * r[k];
+      }
+      if (r2 >= r2max) continue;
+      if (cnt < D.maxn) {
+        double rr = sqrt(r2);
+        double qq = rr / h, t = 1.0 - 0.5 * qq;
+        double dW = -5.0 * alpha * qq * t * t * t / h;
+        double Vb = P.Vs;
+        float g[3] = {0.0f, 0.0f, 0.0f};
+        for (int k = 0; k < DIM; ++k) g[k] = (float)(Vb * r[k] / rr * dW);
+        D.s_nbr[(size_t)cnt * NS + a] = make_float4(g[0], g[1], g[2], __int_as_float(P.s_begin + ib));
+      }
+      cnt++;
+    }
+  }
+  if (active) {
+    D.s_cnt[a] = cnt < D.maxn ? cnt : D.maxn;
+    if (cnt > D.maxn) atomicOr(&D.st[s].err, (int)ERR_CAPACITY);
+  }
+}
+
+// Correction matrix B_a = (sum_b V_b (r0_b - r0_a) (x) grad_a W_ab)^-1 in FP64
+// (Section 2.2; the volume V_b makes B dimensionless) and the reference
+// surface normal n0 = normalise(-sum_b V_b grad_a W_ab), zero where the sum
+// times h_S is below 0.01 (the mid-plane of a thin plate).
+template <int DIM>
+__global__ void k_solid_B(Dev D) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  const ScenePar &P = D.par[D.s_scene[a]];
+  int NS = D.ns;
+  double h = P.hs;
+  double alpha = DIM == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+  double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ns[3] = {0, 0, 0};
+  double xa[3];
+  for (int k = 0; k < 3; ++k) xa[k] = D.s_r0d[3 * (size_t)a + k];
+  int cnt = D.s_cnt[a];
+  for (int q = 0; q < cnt; ++q) {
+    int b = __float_as_int(D.s_nbr[(size_t)q * NS + a].w);
+    double r[3], r2 = 0.0;
+    for (int k = 0; k < DIM; ++k) {
+      r[k] = xa[k] - D.s_r0d[3 * (size_t)b + k];
+      r2 += r[k] * r[k];
+    }
+    double rr = sqrt(r2);
+    double qq = rr / h, t = 1.0 - 0.5 * qq;
+    double dW = -5.0 * alpha * qq * t * t * t / h;
+    double Vb = P.Vs;
+    for (int i = 0; i < DIM; ++i) {
+      double gi = r[i] / rr * dW;
+      ns[i] -= Vb * gi;
+      for (int j = 0; j < DIM; ++j) A[i * DIM + j] += Vb * (-r[i]) * (r[j] / rr * dW);
+    }
+  }
+  double Bm[9];
+  if (cnt == 0) {
+    for (int k = 0; k < DIM * DIM; ++k) Bm[k] = (k % (DIM + 1) == 0) ? 1.0 : 0.0;
+  } else if (DIM == 2) {
+    double det = A[0] * A[3] - A[1] * A[2];
+    Bm[0] = A[3] / det;
+    Bm[1] = -A[1] / det;
+    Bm[2] = -A[2] / det;
+    Bm[3] = A[0] / det;
+  } else {
+    double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                 A[2] * (A[3] * A[7] - A[4] * A[6]);
+    Bm[0] = (A[4] * A[8] - A[5] * A[7]) / det;
+    Bm[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+    Bm[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    Bm[3] = (A[5] * A[6] - A[3] * A[8]) / det;
+    Bm[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    Bm[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    Bm[6] = (A[3] * A[7] - A[4] * A[6]) / det;
+    Bm[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    Bm[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+  }
+  for (int k = 0; k < DIM * DIM; ++k) D.s_B[k * NS + a] = Bm[k];
+  double nn = 0.0;
+  for (int k = 0; k < DIM; ++k) nn += ns[k] * ns[k];
+  nn = sqrt(nn);
+  for (int k = 0; k < DIM; ++k) {
+    float v = (nn * h >= 0.01) ? (float)(ns[k] / nn) : 0.0f;
+    D.s_n0[k * NS + a] = v;
+    D.s_n[k * NS + a] = v;
+  }
+}
+
+// Max fluid speed of each scene and the acoustic time step that follows
+// (Section 3.2, acoustic criterion); one block per scene.
+__global__ void k_refresh_vmax(Dev D) {
+  __shared__ float red[256];
+  int s = blockIdx.x;
+  const ScenePar &P = D.par[s];
+  float m = 0.0f;
+  for (int i = threadIdx.x; i < P.f_count; i += blockDim.x) {
+    float4 v = D.f_va[P.f_begin + i];
+    m = fmaxf(m, sqrtf(v.x * v.x + v.y * v.y + v.z * v.z));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    SceneState &S = D.st[s];
+    S.vmax_prev = __float_as_uint(red[0]);
+    S.vmax_next = 0u;
+    S.dt_ac = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)red[0]);
+  }
+}
+
+// ------------------------------------------------------------------ rebuild
+
+// Advection step start (Algorithm 1; Section 3.2, advection criterion):
+// dt_ad = cfl_ad min(h / max(|v|max, U_ref), h^2 rho0 / eta).
+__global__ void k_rebuild_begin(Dev D) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= D.n_scenes) return;
+  SceneState &S = D.st[s];
+  const ScenePar &P = D.par[s];
+  S.rebuilding = S.need_rebuild;
+  if (!S.need_rebuild) return;
+  double vm = fmax((double)__uint_as_float(S.vmax_prev), (double)P.u_ref);
+  double dt = (double)P.cfl_ad * (double)P.hf / vm;
+  if (P.dt_visc > 0.0) dt = fmin(dt, P.dt_visc);
+  S.dt_ad = dt;
+  S.adv_accum = 0.0;
+  S.need_rebuild = 0;
+  S.rebuilds += 1;
+  S.n_ff = S.n_fw = S.n_fs = 0;
+}
+
+// Bin the fluid of rebuilding scenes: new cell and offset from the current
+// position, slot within the cell, and a copy of the state by old index.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_fluid_bin(Dev D) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.nf) return;
+  int s = D.f_scene[i];
+  if (!D.st[s].rebuilding) return;
+  const ScenePar &P = D.par[s];
+  int c[3];
+  decode_cell(P, D.f_lin[i], c);
+  double4 o = D.f_off[i];
+  double off[3] = {o.x, o.y, o.z};
+  if (!renormalise<DIM>(P, c, off)) atomicOr(&D.st[s].err, (int)ERR_NAN_FLUID);
+  int lin = encode_cell(P, c);
+  D.fs_lin[i] = lin;
+  D.fs_off[i] = make_double4(off[0], off[1], off[2], 0.0);
+  D.fs_slot[i] = atomicAdd(&D.fc_count[P.cell_begin + lin], 1);
+  D.fs_va[i] = D.f_va[i];
+  D.fs_drho[i] = D.f_drho[i];
+  D.fs_id[i] = D.f_id[i];
+  D.fs_m[i] = D.f_pos[i].w;
+}
+
+// Bin walls and free solid particles of rebuilding scenes into the fluid grid.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_bnd_bin(Dev D) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= D.nb) return;
+  int s = D.bs_scene[q];
+  if (!D.st[s].rebuilding) return;
+  const ScenePar &P = D.par[s];
+  int local = q - P.b_begin;
+  int c[3];
+  double off[3];
+  int NS = D.ns;
+  if (local < P.w_count) {
+    int w = P.w_begin + local;
+    decode_cell(P, D.w_lin[w], c);
+    double4 o = D.w_off[w];
+    off[0] = o.x;
+    off[1] = o.y;
+    off[2] = o.z;
+  } else {
+    int a = P.s_begin + (local - P.w_count);
+    decode_cell(P, D.s_lin0[a], c);
+    off[0] = off[1] = off[2] = 0.0;
+    for (int k = 0; k < DIM; ++k) off[k] = D.s_off0[k * NS + a] + D.s_u[k * NS + a];
+    if (!renormalise<DIM>(P, c, off)) atomicOr(&D.st[s].err, (int)ERR_NAN_SOLID);
+  }
+  int lin = encode_cell(P, c);
+  D.bs_lin[q] = lin;
+  D.bs_off[q] = make_double4(off[0], off[1], off[2], 0.0);
+  D.bs_slot[q] = atomicAdd(&D.bc_count[P.cell_begin + lin], 1);
+}
+
+// Exclusive scan of the cell counts of one rebuilding scene in Morton order
+// (one block per scene), giving each cell's [start, end); counts are reset.
+__global__ void __launch_bounds__(1024) k_scan_cells(Dev D) {
+  __shared__ int sf[1024], sb[1024];
+  int s = blockIdx.x;
+  if (!D.st[s].rebuilding) return;
+  const ScenePar &P = D.par[s];
+  int n = P.ncell_total, cb = P.cell_begin;
+  int T = blockDim.x, t = threadIdx.x;
+  int chunk = (n + T - 1) / T;
+  int r0 = min(n, t * chunk), r1 = min(n, r0 + chunk);
+  int lf = 0, lb = 0;
+  for (int r = r0; r < r1; ++r) {
+    int lin = D.rank_to_lin[cb + r];
+    lf += D.fc_count[cb + lin];
+    lb += D.bc_count[cb + lin];
+  }
+  sf[t] = lf;
+  sb[t] = lb;
+  __syncthreads();
+  // inclusive Hillis-Steele scan
+  for (int w = 1; w < T; w <<= 1) {
+    int vf = t >= w ? sf[t - w] : 0;
+    int vb = t >= w ? sb[t - w] : 0;
+    __syncthreads();
+    sf[t] += vf;
+    sb[t] += vb;
+    __syncthreads();
+  }
+  int pf = P.f_begin + sf[t] - lf, pb = P.b_begin + sb[t] - lb;
+  for (int r = r0; r < r1; ++r) {
+    int lin = D.rank_to_lin[cb + r];
+    int cf = D.fc_count[cb + lin], cbn = D.bc_count[cb + lin];
+    D.fc_se[cb + lin] = make_int2(pf, pf + cf);
+    D.bc_se[cb + lin] = make_int2(pb, pb + cbn);
+    pf += cf;
+    pb += cbn;
+    D.fc_count[cb + lin] = 0;
+    D.bc_count[cb + lin] = 0;
+  }
+}
+
+__global__ void k_fluid_scatter(Dev D) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.nf) return;
+  int s = D.f_scene[i];
+  if (!D.st[s].rebuilding) return;
+  const ScenePar &P = D.par[s];
+  D.f_perm[D.fc_se[P.cell_begin + D.fs_lin[i]].x + D.fs_slot[i]] = i;
+}
+
+__global__ void k_bnd_scatter(Dev D) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= D.nb) return;
+  int s = D.bs_scene[q];
+  if (!D.st[s].rebuilding) return;
+  const ScenePar &P = D.par[s];
+  D.b_perm[D.bc_se[P.cell_begin + D.bs_lin[q]].x + D.bs_slot[q]] = q;
+}
+
+// Deterministic order inside each cell: by original index (fluid) and by
+// source index (walls, then solid).  Insertion sort; cells hold a handful.
+__global__ void k_cell_sort(Dev D) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D.ncell) return;
+  int s = D.cell_scene[c];
+  if (!D.st[s].rebuilding) return;
+  int2 se = D.fc_se[c];
+  for (int k = se.x + 1; k < se.y; ++k) {
+    int v = D.f_perm[k];
+    int key = D.fs_id[v];
+    int j = k - 1;
+    while (j >= se.x && D.fs_id[D.f_perm[j]] > key) {
+      D.f_perm[j + 1] = D.f_perm[j];
+      --j;
+    }
+    D.f_perm[j + 1] = v;
+  }
+  int2 be = D.bc_se[c];
+  for (int k = be.x + 1; k < be.y; ++k) {
+    int v = D.b_perm[k];
+    int j = k - 1;
+    while (j >= be.x && D.b_perm[j] > v) {
+      D.b_perm[j + 1] = D.b_perm[j];
+      --j;
+    }
+    D.b_perm[j + 1] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fluid_gather(Dev D) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.nf) return;
+  int s = D.f_scene[k];
+  if (!D.st[s].rebuilding) return;
+  int o = D.f_perm[k];
+  double4 off = D.fs_off[o];
+  D.f_lin[k] = D.fs_lin[o];
+  D.f_id[k] = D.fs_id[o];
+  D.f_pos[k] = make_float4((float)off.x, (float)off.y, (float)off.z, D.fs_m[o]);
+  D.f_posd[k] = off;
+  D.f_off[k] = off;
+  D.f_va[k] = D.fs_va[o];
+  D.f_drho[k] = D.fs_drho[o];
+}
+
+// Boundary particles in cell order: frozen offset, volume, averaged velocity
+// with the hydrostatic factor max(0, (abar - g).n), normal.  For the solid the
+// normal is updated from the deformation (n = normalise(F^-T n0)) and the
+// current volume is V0 det F.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_bnd_gather(Dev D) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.nb) return;
+  int s = D.bs_scene[k];
+  if (!D.st[s].rebuilding) return;
+  const ScenePar &P = D.par[s];
+  int q = D.b_perm[k];
+  int local = q - P.b_begin;
+  double4 off = D.bs_off[q];
+  int NS = D.ns;
+  float n[3] = {0.0f, 0.0f, 0.0f}, vb[3] = {0.0f, 0.0f, 0.0f}, ab[3] = {0.0f, 0.0f, 0.0f};
+  float V, Vref;
+  if (local < P.w_count) {
+    float4 wn = D.w_nrm[P.w_begin + local];
+    n[0] = wn.x;
+    n[1] = wn.y;
+    n[2] = wn.z;
+    V = P.Vf;
+    Vref = P.Vf;
+  } else {
+    int a = P.s_begin + (local - P.w_count);
+    float H[9], Fi[9];
+    for (int c = 0; c < DIM * DIM; ++c) H[c] = (float)D.s_H[c * NS + a];
+    float J;
+    if (DIM == 2) {
+      float f00 = 1.0f + H[0], f01 = H[1], f10 = H[2], f11 = 1.0f + H[3];
+      J = 1.0f + (H[0] + H[3] + (H[0] * H[3] - H[1] * H[2]));
+      // F^-T = (1/J) [[f11, -f10], [-f01, f00]]
+      Fi[0] = f11;
+      Fi[1] = -f10;
+      Fi[2] = -f01;
+      Fi[3] = f00;
+    } else {
+      float F[9];
+      for (int c = 0; c < 9; ++c) F[c] = H[c] + ((c % 4 == 0) ? 1.0f : 0.0f);
+      float tr = H[0] + H[4] + H[8];
+      float m2 = (H[0] * H[4] - H[1] * H[3]) + (H[0] * H[8] - H[2] * H[6]) + (H[4] * H[8] - H[5] * H[7]);
+      float d3 = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                 H[2] * (H[3] * H[7] - H[4] * H[6]);
+      J = 1.0f + tr + m2 + d3;
+      // cofactor matrix = J F^-T
+      Fi[0] = F[4] * F[8] - F[5] * F[7];
+      Fi[1] = F[5] * F[6] - F[3] * F[8];
+      Fi[2] = F[3] * F[7] - F[4] * F[6];
+      Fi[3] = F[2] * F[7] - F[1] * F[8];
+      Fi[4] = F[0] * F[8] - F[2] * F[6];
+      Fi[5] = F[1] * F[6] - F[0] * F[7];
+      Fi[6] = F[1] * F[5] - F[2] * F[4];
+      Fi[7] = F[2] * F[3] - F[0] * F[5];
+      Fi[8] = F[0] * F[4] - F[1] * F[3];
+    }
+    float n0[3] = {0.0f, 0.0f, 0.0f};
+    for (int c = 0; c < DIM; ++c) n0[c] = D.s_n0[c * NS + a];
+    float l2 = 0.0f;
+    for (int i = 0; i < DIM; ++i) {
+      float v = 0.0f;
+      for (int j = 0; j < DIM; ++j) v += Fi[i * DIM + j] * n0[j];
+      n[i] = v;
+      l2 += v * v;
+    }
+    float inv = l2 > 0.0f ? rsqrtf(l2) : 0.0f;
+    for (int i = 0; i < DIM; ++i) {
+      n[i] *= inv;
+      D.s_n[i * NS + a] = n[i];
+      vb[i] = D.s_vbar[i * NS + a];
+      ab[i] = D.s_abar[i * NS + a];
+    }
+    V = P.Vs * J;
+    Vref = -P.Vs;
+    D.s_bslot[a] = k;
+    D.s_blin[a] = D.bs_lin[q];
+  }
+  float sa = 0.0f;
+  for (int i = 0; i < DIM; ++i) sa += (ab[i] - P.g[i]) * n[i];
+  sa = fmaxf(0.0f, sa);
+  D.b_pos[k] = make_float4((float)off.x, (float)off.y, (float)off.z, V);
+  D.b_posd[k] = off;
+  D.b_vbar[k] = make_float4(vb[0], vb[1], vb[2], sa);
+  D.b_nrm[k] = make_float4(n[0], n[1], n[2], Vref);
+}
+
+// Wave-level add of a per-scene counter (lanes of one wave almost always
+// share the scene).
+__device__ __forceinline__ void scene_add_u64(unsigned long long *ctr, int s, unsigned long long v, bool active) {
+  int s0 = __shfl(s, 0);
+  bool uniform = __all(s == s0 || !active);
+  if (uniform) {
+    unsigned long long tot = active ? v : 0ull;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_down(tot, off);
+    if (threadIdx.x % 64 == 0 && tot) atomicAdd(ctr + 0, tot);
+  } else if (active && v) {
+    atomicAdd(ctr, v);
+  }
+}
+
+// Density reinitialisation and pair counts at the start of an advection step
+// (Algorithm 1).  psi_i = sum_j V_ref,j W_ij over fluid (self included), walls
+// and free solid; mode 1: rho = rho0 max(1, psi/psi0); mode 2: rho =
+// max(rho, rho0 psi/psi0).  The pair counts feed the interaction counters.
+// The sum is an FP64 island: the pressure that follows is rho0 c^2 times the
+// relative excess of psi, so FP32 rounding of W would appear as pressure
+// noise; distances are formed in FP64 from the stored FP32 offsets.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_reinit(Dev D) {
+  int i = particle_index();
+  bool active = i < D.nf;
+  int s = active ? D.f_scene[i] : 0;
+  if (active && !D.st[s].rebuilding) active = false;
+  unsigned long long nff = 0, nfw = 0, nfs = 0;
+  if (active) {
+    const ScenePar &P = D.par[s];
+    float4 pi = D.f_pos[i];
+    double4 qi = D.f_posd[i];
+    const double h = P.hf, inv_h = 1.0 / h;
+    const double alpha = DIM == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+    const double Vf = DIM == 2 ? (double)P.dpf * P.dpf : (double)P.dpf * P.dpf * P.dpf;
+    const double Vs = DIM == 2 ? (double)P.dps * P.dps : (double)P.dps * P.dps * P.dps;
+    auto W64 = [&](double r) {
+      double q = r * inv_h, t = fmax(0.0, 1.0 - 0.5 * q);
+      return alpha * t * t * t * t * (1.0 + 2.0 * q);
+    };
+    double psi = Vf * alpha;
+    int cb = P.cell_begin;
+    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh) {
+      // the same cell offset in FP64 (sh is an exact multiple of the FP32 cell size)
+      double shd[3];
+      for (int k = 0; k < 3; ++k) shd[k] = (double)(sh[k] / P.cs[k]) * P.csd[k];
+      int2 se = D.fc_se[cb + nl];
+      for (int j = se.x; j < se.y; ++j) {
+        if (j == i) continue;
+        float4 pj = D.f_pos[j];
+        // pair membership decided in FP32 exactly as in the force passes
+        float rx = (pi.x - pj.x) - sh[0], ry = (pi.y - pj.y) - sh[1];
+        float rz = DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f;
+        float r2 = rx * rx + ry * ry + rz * rz;
+        if (r2 >= P.r2max_f) continue;
+        double4 qj = D.f_posd[j];
+        double dx = (qi.x - qj.x) - shd[0], dy = (qi.y - qj.y) - shd[1];
+        double dz = DIM == 3 ? (qi.z - qj.z) - shd[2] : 0.0;
+        psi += Vf * W64(sqrt(dx * dx + dy * dy + dz * dz));
+        nff++;
+      }
+      int2 be = D.bc_se[cb + nl];
+      for (int k = be.x; k < be.y; ++k) {
+        float4 pb = D.b_pos[k];
+        float rx = (pi.x - pb.x) - sh[0], ry = (pi.y - pb.y) - sh[1];
+        float rz = DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f;
+        float r2 = rx * rx + ry * ry + rz * rz;
+        if (r2 >= P.r2max_f) continue;
+        double4 qb = D.b_posd[k];
+        double dx = (qi.x - qb.x) - shd[0], dy = (qi.y - qb.y) - shd[1];
+        double dz = DIM == 3 ? (qi.z - qb.z) - shd[2] : 0.0;
+        bool wall = D.b_nrm[k].w > 0.0f;
+        psi += (wall ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy + dz * dz));
+        if (wall) nfw++;
+        else nfs++;
+      }
+    });
+    D.f_nnb[i] = make_int2((int)nff, (int)(nfw + nfs));
+    if (P.reinit) {
+      float4 va = D.f_va[i];
+      double e = psi / P.psi0d - 1.0;
+      va.w = P.reinit == 2 ? fmaxf(va.w, (float)e) : (float)fmax(0.0, e);
+      D.f_va[i] = va;
+    }
+  }
+  SceneState *S = &D.st[s];
+  scene_add_u64(&S->n_ff, s, nff, active);
+  scene_add_u64(&S->n_fw, s, nfw, active);
+  scene_add_u64(&S->n_fs, s, nfs, active);
+}
+
+// ------------------------------------------------------------------ fluid step
+
+// Fluid acoustic step, first part (Section 3.3, Eqs. verlet-first-half and
+// verlet-first-mediate; Section 3.1 momentum): half step of density (kept as
+// eps) and position, Riemann pressure and viscous forces from fluid
+// neighbours, coupling forces from walls and solid, gravity, full step of
+// velocity.  Writes (v^{n+1}, eps^{n+1/2}), the mid-point pressure and the
+// acceleration; v^n stays in f_va for the coupling and continuity passes.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
+  int i = particle_index();
+  if (i >= D.nf) return;
+  int s = D.f_scene[i];
+  const ScenePar &P = D.par[s];
+  float dt = (float)D.st[s].dt_ac;
+  float4 pi = D.f_pos[i];
+  float4 va = D.f_va[i];
+  float ehi = va.w + 0.5f * dt * D.f_drho[i];
+  float rhoi = P.rho0 * (1.0f + ehi);
+  float p_i = eos_p(ehi, P);
+  float mi = pi.w;
+  float Vi = mi / rhoi;
+  float vi[3] = {va.x, va.y, va.z};
+  float fsum[3] = {0.0f, 0.0f, 0.0f};
+  int cb = P.cell_begin;
+  visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh) {
+    int2 se = D.fc_se[cb + nl];
+    for (int j = se.x; j < se.y; ++j) {
+      if (j == i) continue;
+      float4 pj = D.f_pos[j];
+      float r[3] = {(pi.x - pj.x) - sh[0], (pi.y - pj.y) - sh[1], DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f};
+      float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      if (r2 >= P.r2max_f) continue;
+      float4 vj4 = D.f_va[j];
+      float ehj = vj4.w + 0.5f * dt * D.f_drho[j];
+      float rhoj = P.rho0 * (1.0f + ehj);
+      float p_j = eos_p(ehj, P);
+      float Vj = pj.w / rhoj;
+      float rr = sqrtf(r2);
+      float inv_r = 1.0f / rr;
+      float e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
+      float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
+      float vj[3] = {vj4.x, vj4.y, vj4.z};
+      float Ps = riemann_pressure<DIM>(P, rhoi, rhoj, p_i, p_j, vi, vj, e);
+      float VV = Vi * Vj * dW;
+      float cpress = -2.0f * VV * Ps;
+      float cvisc = 2.0f * P.eta * VV * inv_r;
+      for (int k = 0; k < DIM; ++k) fsum[k] += cpress * e[k] + cvisc * (vi[k] - vj[k]);
+    }
+    int2 be = D.bc_se[cb + nl];
+    for (int k = be.x; k < be.y; ++k) {
+      float4 pb = D.b_pos[k];
+      float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
+      float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      if (r2 >= P.r2max_f) continue;
+      float f[3];
+      coupling_force<DIM>(P, mi, ehi, p_i, vi, r, pb, D.b_vbar[k], D.b_nrm[k], f);
+      for (int q = 0; q < DIM; ++q) fsum[q] += f[q];
+    }
+  });
+  float a[3] = {0.0f, 0.0f, 0.0f}, vn[3] = {vi[0], vi[1], vi[2]};
+  for (int k = 0; k < DIM; ++k) {
+    a[k] = fsum[k] / mi + P.g[k];
+    vn[k] = vi[k] + dt * a[k];
+  }
+  double4 off = D.f_off[i];
+  const double hdt = 0.5 * D.st[s].dt_ac;
+  off.x += hdt * vi[0];
+  off.y += hdt * vi[1];
+  if (DIM == 3) off.z += hdt * vi[2];
+  D.f_off[i] = off;
+  D.f_vb[i] = make_float4(vn[0], vn[1], vn[2], ehi);
+  D.f_vs[i] = make_float4(vi[0], vi[1], vi[2], ehi);
+  D.f_p[i] = p_i;
+  D.f_acc[i] = make_float4(a[0], a[1], a[2], 0.0f);
+}
+
+// Force of the fluid on each free solid particle (Section 2.2, F:p and F:v at
+// h_F): the exact negatives of the fluid-side pair terms, from the same
+// mid-point snapshot (v^n, eps^{n+1/2}, p^{n+1/2}) and the same frozen geometry.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_couple(Dev D) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  int s = D.s_scene[a];
+  const ScenePar &P = D.par[s];
+  int NS = D.ns;
+  int local = a - P.s_begin;
+  float fa[3] = {0.0f, 0.0f, 0.0f};
+  int k = D.s_bslot[a];
+  if (local < P.s_count - P.s_nclamp && k >= 0) {
+    float4 pb = D.b_pos[k], bv = D.b_vbar[k], bn = D.b_nrm[k];
+    int cb = P.cell_begin;
+    visit_cells<DIM>(P, D.s_blin[a], [&](int nl, const float *sh) {
+      int2 se = D.fc_se[cb + nl];
+      for (int i = se.x; i < se.y; ++i) {
+        float4 pi = D.f_pos[i];
+        // same rounding as the fluid side's (p_i - p_b) - shift
+        float r[3] = {(pi.x - pb.x) + sh[0], (pi.y - pb.y) + sh[1], DIM == 3 ? (pi.z - pb.z) + sh[2] : 0.0f};
+        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (r2 >= P.r2max_f) continue;
+        float4 vs = D.f_vs[i];
+        float vi[3] = {vs.x, vs.y, vs.z};
+        float f[3];
+        coupling_force<DIM>(P, pi.w, vs.w, D.f_p[i], vi, r, pb, bv, bn, f);
+        for (int q = 0; q < DIM; ++q) fa[q] -= f[q];
+      }
+    });
+  }
+  for (int q = 0; q < DIM; ++q) D.s_fF[q * NS + a] = fa[q];
+}
+
+// Fluid acoustic step, second part (Section 3.1 continuity with the Riemann
+// interface velocity; Section 3.3, Eq. verlet-first-final): density rate with
+// v^{n+1} at the mid-point density, plus rho_i sum_a V_a (v_i - vbar_a).grad W
+// for walls and solid; second half step of position and density; inflow
+// buffer; max speed for the next acoustic step.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
+  int i = particle_index();
+  bool active = i < D.nf;
+  int s = active ? D.f_scene[i] : 0;
+  float speed = 0.0f;
+  if (active) {
+    const ScenePar &P = D.par[s];
+    SceneState &S = D.st[s];
+    float dt = (float)S.dt_ac;
+    float4 pi = D.f_pos[i];
+    float4 vb = D.f_vb[i];
+    float ehi = vb.w;
+    float rhoi = P.rho0 * (1.0f + ehi);
+    float p_i = D.f_p[i];
+    float vi[3] = {vb.x, vb.y, vb.z};
+    float drho = 0.0f;
+    int cb = P.cell_begin;
+    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh) {
+      int2 se = D.fc_se[cb + nl];
+      for (int j = se.x; j < se.y; ++j) {
+        if (j == i) continue;
+        float4 pj = D.f_pos[j];
+        float r[3] = {(pi.x - pj.x) - sh[0], (pi.y - pj.y) - sh[1], DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f};
+        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (r2 >= P.r2max_f) continue;
+        float4 vj4 = D.f_vb[j];
+        float rhoj = P.rho0 * (1.0f + vj4.w);
+        float p_j = D.f_p[j];
+        float Vj = pj.w / rhoj;
+        float rr = sqrtf(r2);
+        float inv_r = 1.0f / rr;
+        float e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
+        float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
+        float vj[3] = {vj4.x, vj4.y, vj4.z};
+        drho += 2.0f * rhoi * Vj * riemann_dv_dot_e<DIM>(P, rhoi, rhoj, p_i, p_j, vi, vj, e) * dW;
+      }
+      int2 be = D.bc_se[cb + nl];
+      for (int k = be.x; k < be.y; ++k) {
+        float4 pb = D.b_pos[k];
+        float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
+        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (r2 >= P.r2max_f) continue;
+        float4 bv = D.b_vbar[k];
+        float rr = sqrtf(r2);
+        float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
+        float dv = (vi[0] - bv.x) * r[0] + (vi[1] - bv.y) * r[1];
+        if (DIM == 3) dv += (vi[2] - bv.z) * r[2];
+        drho += rhoi * pb.w * (dv / rr) * dW;
+      }
+    });
+    float de = drho / P.rho0;
+    float enew = ehi + 0.5f * dt * de;
+    double4 off = D.f_off[i];
+    const double hdt = 0.5 * S.dt_ac;
+    off.x += hdt * vi[0];
+    off.y += hdt * vi[1];
+    if (DIM == 3) off.z += hdt * vi[2];
+    if (P.in_len > 0.0f) {
+      // inflow buffer at the start of the first axis (periodic channel)
+      int lin = D.f_lin[i];
+      double x0 = absolute<DIM>(P, lin, off.x, 0);
+      if (x0 - P.lo[0] < (double)P.in_len) {
+        double y = absolute<DIM>(P, lin, off.y, 1);
+        double t = S.t + S.dt_ac;
+        double ub = t <= (double)P.in_ts ? 0.5 * (double)P.in_U0 * (1.0 - cos(0.5 * M_PI * t)) : (double)P.in_U0;
+        double H = P.in_H;
+        double u = (y > 0.0 && y < H) ? 6.0 * ub * y * (H - y) / (H * H) : 0.0;
+        vi[0] = (float)u;
+        vi[1] = 0.0f;
+        vi[2] = 0.0f;
+      }
+    }
+    D.f_off[i] = off;
+    D.f_va[i] = make_float4(vi[0], vi[1], vi[2], enew);
+    D.f_drho[i] = de;
+    speed = sqrtf(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
+    if (!(isfinite(speed) && isfinite(enew))) atomicOr(&S.err, (int)ERR_NAN_FLUID);
+  }
+  // per-scene max speed: one atomic per wave when the wave is in one scene
+  int s0 = __shfl(s, 0);
+  bool uniform = __all(s == s0 || !active);
+  if (uniform) {
+    float m = active ? speed : 0.0f;
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_down(m, off));
+    if (threadIdx.x % 64 == 0 && m > 0.0f) atomic_max_pos(&D.st[s0].vmax_next, m);
+  } else if (active) {
+    atomic_max_pos(&D.st[s].vmax_next, speed);
+  }
+}
+
+// ------------------------------------------------------------------ solid sub-steps
+
+// kappa solid sub-steps of the position-based Verlet scheme (Section 3.3,
+// Eqs. verlet-*-solid) for one scene per block, the fluid force held constant:
+//   F += dt/2 dF/dt;  u += dt/2 v;  P B from the Neo-Hookean stress;
+//   a = [sum_b V_a V_b (P_a B_a + P_b B_b) grad0_a W_ab + f^F_a] / m_a + g;  v += dt a;
+//   dF/dt = sum_b V_b (v_b - v_a) (x) (B_a grad0_a W_ab);  F += dt/2 dF/dt;  u += dt/2 v;
+// with dt_S = cfl_s min(h_S / (c_S + |v|max), sqrt(h_S / |a|max)) and kappa =
+// floor(dt_ac / dt_S) + 1 equal sub-steps summing to dt_ac.  Afterwards the
+// averages vbar = du / dt_ac and abar = dv / dt_ac over the acoustic step
+// (Section 3.2) are handed to the boundary particles, and thread 0 closes the
+// acoustic step (time, advection accumulator, next dt_ac, counters).
+constexpr int KAPPA_MAX = 4096;
+
+template <int DIM>
+__global__ void __launch_bounds__(1024) k_solid(Dev D) {
+  __shared__ float red[2][1024];
+  __shared__ int kap_sh;
+  __shared__ double del_sh;
+  int s = blockIdx.x;
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  const int NS = D.ns;
+  const int base = P.s_begin, n = P.s_count, nfree = P.s_count - P.s_nclamp;
+  const int T = blockDim.x, t = threadIdx.x;
+  double dt_ac = S.dt_ac;
+  float vm = 0.0f, am = 0.0f;
+  for (int l = t; l < nfree; l += T) {
+    int a = base + l;
+    float v2 = 0.0f, a2 = 0.0f;
+    for (int k = 0; k < DIM; ++k) {
+      float v = (float)D.s_v[k * NS + a], q = D.s_a[k * NS + a];
+      v2 += v * v;
+      a2 += q * q;
+    }
+    vm = fmaxf(vm, sqrtf(v2));
+    am = fmaxf(am, sqrtf(a2));
+  }
+  red[0][t] = vm;
+  red[1][t] = am;
+  __syncthreads();
+  for (int w = T / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      red[0][t] = fmaxf(red[0][t], red[0][t + w]);
+      red[1][t] = fmaxf(red[1][t], red[1][t + w]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    double dts = (double)P.cfl_s * (double)P.hs / ((double)P.c_s + (double)red[0][0]);
+    if (red[1][0] > 0.0f) dts = fmin(dts, (double)P.cfl_s * sqrt((double)P.hs / (double)red[1][0]));
+    // kappa is bounded: a collapsed solid step is reported, not iterated
+    double ratio = dt_ac / dts;
+    int kap;
+    if (!(ratio >= 0.0) || !(dt_ac > 0.0) || ratio > (double)(KAPPA_MAX - 1)) {
+      kap = (ratio >= 0.0 && dt_ac > 0.0) ? KAPPA_MAX : 1;
+      atomicOr(&S.err, (int)ERR_NAN_SOLID);
+    } else {
+      kap = (int)floor(ratio) + 1;
+    }
+    kap_sh = kap;
+    del_sh = dt_ac / kap;
+    S.dt_s = dts;
+    S.kappa = kap;
+  }
+  __syncthreads();
+  const int kap = kap_sh;
+  const double del = del_sh;
+  const double hd = 0.5 * del;
+  const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
+  for (int l = t; l < n; l += T) {
+    int a = base + l;
+    for (int k = 0; k < DIM; ++k) {
+      D.s_du[k * NS + a] = 0.0;
+      D.s_dv[k * NS + a] = 0.0;
+    }
+    if (l >= nfree)
+      for (int k = 0; k < DIM * DIM; ++k) D.s_PB[k * NS + a] = 0.0;
+  }
+  for (int sub = 0; sub < kap; ++sub) {
+    // first half: F, u; Neo-Hookean stress
+    for (int l = t; l < nfree; l += T) {
+      int a = base + l;
+      double H[9], B[9], PB[9];
+      for (int k = 0; k < DIM * DIM; ++k) {
+        H[k] = D.s_H[k * NS + a] + hd * D.s_dF[k * NS + a];
+        D.s_H[k * NS + a] = H[k];
+        B[k] = D.s_B[k * NS + a];
+      }
+      for (int k = 0; k < DIM; ++k) {
+        double inc = hd * D.s_v[k * NS + a];
+        D.s_u[k * NS + a] += inc;
+        D.s_du[k * NS + a] += inc;
+      }
+      double J;
+      nh_PB<DIM, double>(H, B, (double)P.mu, (double)P.lam, PB, J);
+      if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
+      for (int k = 0; k < DIM * DIM; ++k) D.s_PB[k * NS + a] = PB[k];
+    }
+    __syncthreads();
+    // momentum, velocity
+    for (int l = t; l < nfree; l += T) {
+      int a = base + l;
+      double PBa[9];
+      for (int k = 0; k < DIM * DIM; ++k) PBa[k] = D.s_PB[k * NS + a];
+      double acc[3] = {0.0, 0.0, 0.0};
+      int cnt = D.s_cnt[a];
+      for (int q = 0; q < cnt; ++q) {
+        float4 g = D.s_nbr[(size_t)q * NS + a];
+        int b = __float_as_int(g.w);
+        double gv[3] = {g.x, g.y, g.z};
+        for (int i = 0; i < DIM; ++i) {
+          double sum = 0.0;
+          for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + D.s_PB[(i * DIM + j) * NS + b]) * gv[j];
+          acc[i] += sum;
+        }
+      }
+      for (int k = 0; k < DIM; ++k) {
+        double ak = ((double)P.Vs * acc[k] + (double)D.s_fF[k * NS + a]) * m_inv + (double)P.g[k];
+        D.s_a[k * NS + a] = (float)ak;
+        double dv = del * ak;
+        D.s_v[k * NS + a] += dv;
+        D.s_dv[k * NS + a] += dv;
+      }
+    }
+    __syncthreads();
+    // deformation rate with the new velocity, second half
+    for (int l = t; l < nfree; l += T) {
+      int a = base + l;
+      double va[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < DIM; ++k) va[k] = D.s_v[k * NS + a];
+      double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      int cnt = D.s_cnt[a];
+      for (int q = 0; q < cnt; ++q) {
+        float4 g = D.s_nbr[(size_t)q * NS + a];
+        int b = __float_as_int(g.w);
+        double gv[3] = {g.x, g.y, g.z};
+        for (int i = 0; i < DIM; ++i) {
+          double dvi = D.s_v[i * NS + b] - va[i];
+          for (int j = 0; j < DIM; ++j) G[i * DIM + j] += dvi * gv[j];
+        }
+      }
+      // (v_b - v_a) (x) (B grad W) summed = G B^T
+      for (int i = 0; i < DIM; ++i)
+        for (int j = 0; j < DIM; ++j) {
+          double sum = 0.0;
+          for (int k = 0; k < DIM; ++k) sum += G[i * DIM + k] * D.s_B[(j * DIM + k) * NS + a];
+          D.s_dF[(i * DIM + j) * NS + a] = sum;
+          D.s_H[(i * DIM + j) * NS + a] += hd * sum;
+        }
+      for (int k = 0; k < DIM; ++k) {
+        double inc = hd * va[k];
+        D.s_u[k * NS + a] += inc;
+        D.s_du[k * NS + a] += inc;
+      }
+    }
+    __syncthreads();
+  }
+  // time averages over the acoustic step, handed to the boundary particles
+  const double inv_dt = 1.0 / dt_ac;
+  for (int l = t; l < nfree; l += T) {
+    int a = base + l;
+    float vbar[3] = {0.0f, 0.0f, 0.0f}, abar[3] = {0.0f, 0.0f, 0.0f}, nn[3] = {0.0f, 0.0f, 0.0f};
+    bool bad = false;
+    for (int k = 0; k < DIM; ++k) {
+      vbar[k] = (float)(D.s_du[k * NS + a] * inv_dt);
+      abar[k] = (float)(D.s_dv[k * NS + a] * inv_dt);
+      D.s_vbar[k * NS + a] = vbar[k];
+      D.s_abar[k * NS + a] = abar[k];
+      nn[k] = D.s_n[k * NS + a];
+      bad |= !isfinite(vbar[k]) || !isfinite(abar[k]);
+    }
+    if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
+    int kslot = D.s_bslot[a];
+    if (kslot >= 0) {
+      double H[9];
+      for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
+      double J;
+      if (DIM == 2) J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
+      else
+        J = (1.0 + H[0]) * ((1.0 + H[4]) * (1.0 + H[8]) - H[5] * H[7]) - H[1] * (H[3] * (1.0 + H[8]) - H[5] * H[6]) +
+            H[2] * (H[3] * H[7] - (1.0 + H[4]) * H[6]);
+      float sa = 0.0f;
+      for (int k = 0; k < DIM; ++k) sa += (abar[k] - P.g[k]) * nn[k];
+      float4 bp = D.b_pos[kslot];
+      bp.w = (float)(P.Vs * J);
+      D.b_pos[kslot] = bp;
+      D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
+    }
+  }
+  if (t == 0) {
+    unsigned long long inter = 2ull * (S.n_ff + S.n_fw + S.n_fs) + S.n_fs + 2ull * (unsigned long long)kap * S.n_ss;
+    if (S.rebuilding && P.reinit) inter += S.n_ff + S.n_fw + S.n_fs;
+    S.interactions += inter;
+    S.substeps += kap;
+    S.steps += 1;
+    S.t += dt_ac;
+    S.adv_accum += dt_ac;
+    if (S.adv_accum >= S.dt_ad) S.need_rebuild = 1;
+    S.rebuilding = 0;
+    float vmax = __uint_as_float(S.vmax_next);
+    S.vmax_prev = S.vmax_next;
+    S.vmax_next = 0u;
+    S.dt_ac = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)vmax);
+  }
+}
+
+// ------------------------------------------------------------------ state I/O
+
+template <int DIM>
+__global__ void k_read_fluid(Dev D, int s, int field, double *out) {
+  const ScenePar &P = D.par[s];
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= P.f_count) return;
+  int i = P.f_begin + l;
+  int id = D.f_id[i];
+  switch (field) {
+  case 0: {
+    double4 o = D.f_off[i];
+    for (int k = 0; k < DIM; ++k) out[(size_t)DIM * id + k] = absolute<DIM>(P, D.f_lin[i], get4(o, k), k);
+  } break;
+  case 1: {
+    float4 v = D.f_va[i];
+    for (int k = 0; k < DIM; ++k) out[(size_t)DIM * id + k] = get4(v, k);
+  } break;
+  case 2: out[id] = (double)P.rho0 * (1.0 + (double)D.f_va[i].w); break;
+  case 3: out[id] = (double)P.rho0 * (double)D.f_drho[i]; break;
+  case 4: {
+    float4 v = D.f_acc[i];
+    for (int k = 0; k < DIM; ++k) out[(size_t)DIM * id + k] = get4(v, k);
+  } break;
+  case 5: out[id] = D.f_p[i]; break;
+  case 6: {
+    int2 c = D.f_nnb[i];
+    out[2 * (size_t)id] = c.x;
+    out[2 * (size_t)id + 1] = c.y;
+  } break;
+  }
+}
+
+template <int DIM>
+__global__ void k_write_fluid(Dev D, int s, int field, const double *in) {
+  const ScenePar &P = D.par[s];
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= P.f_count) return;
+  int i = P.f_begin + l;
+  int id = D.f_id[i];
+  switch (field) {
+  case 0: {
+    // offset from the particle's current cell; the next rebuild renormalises
+    int c[3];
+    decode_cell(P, D.f_lin[i], c);
+    double o[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < DIM; ++k) {
+      double x = in[(size_t)DIM * id + k] - P.lo[k];
+      double rel = x - c[k] * P.csd[k];
+      if (P.periodic[k]) rel -= P.len[k] * floor(rel / P.len[k] + 0.5);
+      o[k] = rel;
+    }
+    D.f_off[i] = make_double4(o[0], o[1], o[2], 0.0);
+  } break;
+  case 1: {
+    float4 v = D.f_va[i];
+    v.x = (float)in[(size_t)DIM * id];
+    v.y = (float)in[(size_t)DIM * id + 1];
+    if (DIM == 3) v.z = (float)in[(size_t)DIM * id + 2];
+    D.f_va[i] = v;
+  } break;
+  case 2: {
+    float4 v = D.f_va[i];
+    v.w = (float)(in[id] / (double)P.rho0 - 1.0);
+    D.f_va[i] = v;
+  } break;
+  case 3: D.f_drho[i] = (float)(in[id] / (double)P.rho0); break;
+  }
+}
+
+template <int DIM>
+__global__ void k_read_solid(Dev D, int s, int field, double *out) {
+  const ScenePar &P = D.par[s];
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= P.s_count) return;
+  int a = P.s_begin + l, NS = D.ns;
+  const float *src = nullptr;
+  int w = DIM;
+  switch (field) {
+  case 10:
+  case 11: {
+    const double *sd = field == 10 ? D.s_u : D.s_v;
+    for (int k = 0; k < DIM; ++k) out[(size_t)DIM * l + k] = sd[k * NS + a];
+    return;
+  }
+  case 12: src = D.s_a; break;
+  case 14:
+  case 19: {
+    const double *sd = field == 14 ? D.s_dF : D.s_B;
+    for (int k = 0; k < DIM * DIM; ++k) out[(size_t)DIM * DIM * l + k] = sd[k * NS + a];
+    return;
+  }
+  case 15: src = D.s_fF; break;
+  case 16: src = D.s_vbar; break;
+  case 17: src = D.s_abar; break;
+  case 18: src = D.s_n; break;
+  case 20: src = D.s_n0; break;
+  case 13:
+    for (int k = 0; k < DIM * DIM; ++k)
+      out[(size_t)DIM * DIM * l + k] = D.s_H[k * NS + a] + ((k % (DIM + 1) == 0) ? 1.0 : 0.0);
+    return;
+  case 21:
+    for (int k = 0; k < DIM; ++k) out[(size_t)DIM * l + k] = D.s_r0d[3 * (size_t)a + k];
+    return;
+  default: return;
+  }
+  for (int k = 0; k < w; ++k) out[(size_t)w * l + k] = src[k * NS + a];
+}
+
+template <int DIM>
+__global__ void k_write_solid(Dev D, int s, int field, const double *in) {
+  const ScenePar &P = D.par[s];
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= P.s_count) return;
+  int a = P.s_begin + l, NS = D.ns;
+  float *dst = nullptr;
+  int w = DIM;
+  switch (field) {
+  case 10:
+  case 11: {
+    double *dd = field == 10 ? D.s_u : D.s_v;
+    for (int k = 0; k < DIM; ++k) dd[k * NS + a] = in[(size_t)DIM * l + k];
+    return;
+  }
+  case 12: dst = D.s_a; break;
+  case 14:
+    for (int k = 0; k < DIM * DIM; ++k) D.s_dF[k * NS + a] = in[(size_t)DIM * DIM * l + k];
+    return;
+  case 16: dst = D.s_vbar; break;
+  case 17: dst = D.s_abar; break;
+  case 13:
+    for (int k = 0; k < DIM * DIM; ++k)
+      D.s_H[k * NS + a] = in[(size_t)DIM * DIM * l + k] - ((k % (DIM + 1) == 0) ? 1.0 : 0.0);
+    return;
+  default: return;
+  }
+  for (int k = 0; k < w; ++k) dst[k * NS + a] = (float)in[(size_t)w * l + k];
+}
+
+// ------------------------------------------------------------------ FP64 reductions
+
+// Per-block FP64 partial sums for one scene (deterministic two-pass):
+// [0..2] fluid m v, [3..5] solid m v, [6] fluid KE, [7] solid KE,
+// [8] strain energy sum V0 W(F), [9..11] sum f^F, [12..14] solid-on-fluid
+// coupling force re-evaluated from the mid-point state.
+constexpr int NRED = 16;
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_reduce_partial(Dev D, int s) {
+  __shared__ double sh[NRED][256];
+  const ScenePar &P = D.par[s];
+  double acc[NRED];
+  for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
+  int NS = D.ns;
+  int stride = gridDim.x * blockDim.x;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < P.f_count; l += stride) {
+    int i = P.f_begin + l;
+    float4 v = D.f_va[i];
+    double m = D.f_pos[i].w;
+    double vv[3] = {v.x, v.y, v.z};
+    for (int k = 0; k < DIM; ++k) {
+      acc[k] += m * vv[k];
+      acc[6] += 0.5 * m * vv[k] * vv[k];
+    }
+    // coupling force of the free solid on this fluid particle, mid-point state
+    float4 pi = D.f_pos[i];
+    float4 vb = D.f_vs[i];
+    float vi[3] = {vb.x, vb.y, vb.z};
+    float p_i = D.f_p[i];
+    int cb = P.cell_begin;
+    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh2) {
+      int2 be = D.bc_se[cb + nl];
+      for (int k = be.x; k < be.y; ++k) {
+        float4 bn = D.b_nrm[k];
+        if (bn.w > 0.0f) continue;  // walls
+        float4 pb = D.b_pos[k];
+        float r[3] = {(pi.x - pb.x) - sh2[0], (pi.y - pb.y) - sh2[1], DIM == 3 ? (pi.z - pb.z) - sh2[2] : 0.0f};
+        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (r2 >= P.r2max_f) continue;
+        float f[3];
+        coupling_force<DIM>(P, pi.w, vb.w, p_i, vi, r, pb, D.b_vbar[k], bn, f);
+        for (int q = 0; q < DIM; ++q) acc[12 + q] += f[q];
+      }
+    });
+  }
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < P.s_count; l += stride) {
+    int a = P.s_begin + l;
+    double m = (double)P.rho0s * (double)P.Vs;
+    double H[9];
+    for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
+    for (int k = 0; k < DIM; ++k) {
+      double v = D.s_v[k * NS + a];
+      acc[3 + k] += m * v;
+      acc[7] += 0.5 * m * v * v;
+      acc[9 + k] += D.s_fF[k * NS + a];
+    }
+    // strain energy mu trE - mu lnJ + lambda/2 (lnJ)^2 in FP64
+    double trE = 0.0;
+    for (int i = 0; i < DIM; ++i) {
+      double cii = 2.0 * H[i * DIM + i];
+      for (int k = 0; k < DIM; ++k) cii += H[k * DIM + i] * H[k * DIM + i];
+      trE += 0.5 * cii;
+    }
+    double J;
+    if (DIM == 2) J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
+    else {
+      double F[9];
+      for (int k = 0; k < 9; ++k) F[k] = H[k] + ((k % 4 == 0) ? 1.0 : 0.0);
+      J = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+          F[2] * (F[3] * F[7] - F[4] * F[6]);
+    }
+    double lj = log(J);
+    acc[8] += (double)P.Vs * ((double)P.mu * trE - (double)P.mu * lj + 0.5 * (double)P.lam * lj * lj);
+  }
+  for (int k = 0; k < NRED; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < NRED; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NRED; ++k) D.red[(size_t)blockIdx.x * NRED + k] = sh[k][0];
+}
+
+__global__ void k_reduce_final(Dev D, int nblocks, double *out) {
+  if (threadIdx.x >= NRED) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += D.red[(size_t)b * NRED + threadIdx.x];
+  out[threadIdx.x] = s;
+}
+
+__global__ void k_set_rebuild(Dev D, int s) {
+  if (threadIdx.x == 0) D.st[s].need_rebuild = 1;
+}
+
+// ------------------------------------------------------------------ host-side launchers
+
+#define LAUNCH_DIM(dim, kern, grid, block, stream, ...)                          \
+  do {                                                                          \
+    if ((dim) == 2) hipLaunchKernelGGL(kern<2>, grid, block, 0, stream, __VA_ARGS__); \
+    else hipLaunchKernelGGL(kern<3>, grid, block, 0, stream, __VA_ARGS__);            \
+  } while (0)
+
+static inline int nblk(int n, int b) { return n > 0 ? (n + b - 1) / b : 1; }
+
+void launch_init_scene(const Dev &D, int s, const double *x_f, const double *v_f, int has_vf, double gabs,
+                       double hydroH, double dpd, int nf, hipStream_t st) {
+  LAUNCH_DIM(D.dim, k_init_fluid, dim3(nblk(nf, 256)), dim3(256), st, D, s, x_f, v_f, has_vf, gabs, hydroH, dpd);
+}
+
+void launch_init_walls(const Dev &D, int s, const double *x, const double *n, int nw, hipStream_t st) {
+  LAUNCH_DIM(D.dim, k_init_walls, dim3(nblk(nw, 256)), dim3(256), st, D, s, x, n);
+}
+
+void launch_init_solid(const Dev &D, int s, const double *x, const double *v, int has_v, int ns,
+                       hipStream_t st) {
+  LAUNCH_DIM(D.dim, k_init_solid, dim3(nblk(ns, 256)), dim3(256), st, D, s, x, v, has_v);
+}
+
+void launch_solid_reference(const Dev &D, int s, int ns_scene, hipStream_t st) {
+  LAUNCH_DIM(D.dim, k_solid_neighbours, dim3(nblk(ns_scene, 256)), dim3(256), st, D, s);
+}
+
+void launch_solid_B(const Dev &D, hipStream_t st) {
+  if (D.ns == 0) return;
+  LAUNCH_DIM(D.dim, k_solid_B, dim3(nblk(D.ns, 256)), dim3(256), st, D);
+}
+
+void launch_refresh_vmax(const Dev &D, hipStream_t st) {
+  hipLaunchKernelGGL(k_refresh_vmax, dim3(D.n_scenes), dim3(256), 0, st, D);
+}
+
+void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
+  hipLaunchKernelGGL(k_rebuild_begin, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
+  if (D.nf > 0) LAUNCH_DIM(D.dim, k_fluid_bin, dim3(nblk(D.nf, 256)), dim3(256), st, D);
+  if (D.nb > 0) LAUNCH_DIM(D.dim, k_bnd_bin, dim3(nblk(D.nb, 256)), dim3(256), st, D);
+  hipLaunchKernelGGL(k_scan_cells, dim3(D.n_scenes), dim3(1024), 0, st, D);
+  if (D.nf > 0) hipLaunchKernelGGL(k_fluid_scatter, dim3(nblk(D.nf, 256)), dim3(256), 0, st, D);
+  if (D.nb > 0) hipLaunchKernelGGL(k_bnd_scatter, dim3(nblk(D.nb, 256)), dim3(256), 0, st, D);
+  hipLaunchKernelGGL(k_cell_sort, dim3(nblk(D.ncell, 256)), dim3(256), 0, st, D);
+  if (D.nf > 0) hipLaunchKernelGGL(k_fluid_gather, dim3(nblk(D.nf, 256)), dim3(256), 0, st, D);
+  if (D.nb > 0) LAUNCH_DIM(D.dim, k_bnd_gather, dim3(nblk(D.nb, 256)), dim3(256), st, D);
+  if (D.nf > 0) LAUNCH_DIM(D.dim, k_reinit, dim3(nblk(D.nf, cfg.block_pair)), dim3(cfg.block_pair), st, D);
+}
+
+void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
+  if (D.nf > 0) LAUNCH_DIM(D.dim, k_fluid_force, dim3(nblk(D.nf, cfg.block_pair)), dim3(cfg.block_pair), st, D);
+}
+
+void launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
+  if (D.nf > 0)
+    LAUNCH_DIM(D.dim, k_fluid_continuity, dim3(nblk(D.nf, cfg.block_pair)), dim3(cfg.block_pair), st, D);
+}
+
+void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
+  if (D.ns > 0) LAUNCH_DIM(D.dim, k_couple, dim3(nblk(D.ns, cfg.block_couple)), dim3(cfg.block_couple), st, D);
+}
+
+void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
+  LAUNCH_DIM(D.dim, k_solid, dim3(D.n_scenes), dim3(cfg.block_solid), st, D);
+}
+
+void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t st) {
+  if (field < 10) LAUNCH_DIM(D.dim, k_read_fluid, dim3(nblk(n, 256)), dim3(256), st, D, s, field, out);
+  else LAUNCH_DIM(D.dim, k_read_solid, dim3(nblk(n, 256)), dim3(256), st, D, s, field, out);
+}
+
+void launch_write(const Dev &D, int s, int field, int n, const double *in, hipStream_t st) {
+  if (field < 10) LAUNCH_DIM(D.dim, k_write_fluid, dim3(nblk(n, 256)), dim3(256), st, D, s, field, in);
+  else LAUNCH_DIM(D.dim, k_write_solid, dim3(nblk(n, 256)), dim3(256), st, D, s, field, in);
+}
+
+void launch_reduce(const Dev &D, int s, int nblocks, double *out, hipStream_t st) {
+  LAUNCH_DIM(D.dim, k_reduce_partial, dim3(nblocks), dim3(256), st, D, s);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, st, D, nblocks, out);
+}
+
+void launch_set_rebuild(const Dev &D, int s, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_rebuild, dim3(1), dim3(64), 0, st, D, s);
+}
+
+}  // namespace mrsph

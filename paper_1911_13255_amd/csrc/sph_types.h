@@ -1,0 +1,115 @@
+// Device-side data layout of the multi-resolution SPH FSI library.
+//
+// Every array lives in the caller's arena.  Fluid particles of all scenes are
+// concatenated (scene s owns [f_begin, f_begin + f_count)) and, after each
+// rebuild, sorted by cell of the scene's grid in Morton order.  Positions are
+// stored as the integer cell of the last rebuild plus an offset from that
+// cell's origin: FP64 for the state that integrates and for the
+// number-density sum, an FP32 copy for the pair loops.  The fluid density is
+// stored as eps = rho / rho0 - 1 and the deformation gradient as H = F - I.
+// These keep FP32 sums accurate where the absolute values would cancel (pair
+// distances, pressure from density, stress from strain).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mrsph {
+
+struct ScenePar {
+  // particle ranges in the concatenated arrays
+  int f_begin, f_count;  // fluid
+  int w_begin, w_count;  // walls
+  int s_begin, s_count, s_nclamp;  // solid (clamp block last)
+  int b_begin, b_count;  // boundary sources: walls then free solid
+  int cell_begin, ncell_total;
+  int ncell[3];
+  int periodic[3];
+  float cs[3];         // cell size per axis (>= 2 h_F)
+  double lo[3], csd[3];  // FP64 copies for conversions
+  double len[3];       // box length per axis
+  // fluid
+  float hf, inv_hf, r2max_f, alpha_f;  // smoothing length, 1/h, (2h)^2, kernel normalisation
+  float rho0, c, eta, gamma;
+  float p_coef;       // rho0 c^2 / gamma
+  float gam_inv_rho0c2;  // gamma / (rho0 c^2)
+  float g[3];
+  float Vf;           // dp_f^d (wall volume, reference volume in the number density)
+  float psi0;         // number density of the unbounded lattice
+  double psi0d, dpf, dps;  // FP64 copies for the number-density sum
+  // solid
+  float hs, inv_hs, r2max_s, alpha_s;
+  float rho0s, mu, lam, c_s;
+  float Vs;           // dp_s^d
+  // time stepping
+  float cfl_ac, cfl_ad, cfl_s, u_ref;
+  double dt_visc;     // viscous bound of the advection step (0: none)
+  // inflow buffer
+  float in_U0, in_ts, in_H, in_len;
+  int riemann, reinit;
+};
+
+struct SceneState {
+  double t, dt_ac, dt_ad, dt_s, adv_accum;
+  int kappa, need_rebuild, rebuilding, err;
+  unsigned int vmax_prev, vmax_next;  // max fluid speed (float bits): step start / being reduced
+  unsigned int pad0, pad1;
+  unsigned long long n_ff, n_fw, n_fs, n_ss;  // pairs within support at the last rebuild
+  unsigned long long steps, rebuilds, substeps, interactions;
+};
+
+enum ErrBits { ERR_NAN_FLUID = 1, ERR_NAN_SOLID = 2, ERR_JACOBIAN = 4, ERR_CAPACITY = 8 };
+
+// Device pointers, passed by value to every kernel.
+struct Dev {
+  int n_scenes, dim;
+  ScenePar *par;
+  SceneState *st;
+  // fluid, sorted
+  int nf;
+  int *f_scene, *f_lin, *f_id;
+  float4 *f_pos;   // frozen offset at the last rebuild (xyz), mass (w)
+  double4 *f_off;  // current offset from the same cell origin (FP64: positions integrate here)
+  double4 *f_posd; // frozen offset in FP64 (read by the number-density sum)
+  float4 *f_va;    // (v, eps) at the step start
+  float4 *f_vb;    // (v^{n+1}, eps^{n+1/2}) written by the force kernel
+  float4 *f_vs;    // mid-point snapshot (v^n, eps^{n+1/2}) for the coupling on the solid
+  float4 *f_acc;   // acceleration of the last step
+  float *f_drho;   // d eps / dt kept for the next half step
+  float *f_p;      // mid-step pressure
+  int2 *f_nnb;     // fluid and boundary neighbours within 2 h_F at the last rebuild
+  // fluid rebuild scratch (indexed by the old sorted index)
+  int *fs_lin, *fs_slot, *fs_id, *f_perm;
+  double4 *fs_off;
+  float4 *fs_va;
+  float *fs_drho, *fs_m;
+  // cells
+  int ncell;
+  int *fc_count, *bc_count, *rank_to_lin, *cell_scene;
+  int2 *fc_se, *bc_se;  // [start, end) of each cell, indexed by scene-local linear index + cell_begin
+  // walls (static)
+  int nw;
+  int *w_lin, *w_scene;
+  double4 *w_off;
+  float4 *w_nrm;
+  // boundary particles seen by the fluid (walls + free solid), sorted by cell
+  int nb;
+  float4 *b_pos;   // frozen offset (xyz), volume (w)
+  float4 *b_vbar;  // averaged velocity (xyz), max(0, (abar - g).n) (w)
+  float4 *b_nrm;   // normal (xyz), +V_ref for walls / -V_ref for solid (w)
+  double4 *b_posd; // frozen offset in FP64
+  int *b_perm, *bs_lin, *bs_slot, *bs_scene;
+  double4 *bs_off;
+  // solid (per scene in original order), SoA with component stride ns
+  int ns, maxn;
+  int *s_scene, *s_lin0, *s_bslot, *s_blin, *s_cnt;
+  double *s_off0;  // reference offset from the reference cell, FP64
+  double *s_u, *s_v, *s_du, *s_dv;  // integration state in FP64 (displacement, velocity, step increments)
+  double *s_H, *s_dF, *s_B, *s_PB;  // H = F - I, dF/dt, B, P B in FP64 (d*d components)
+  float *s_a, *s_fF, *s_vbar, *s_abar, *s_n0, *s_n;
+  double *s_r0d;                   // reference positions, FP64 (3 per particle)
+  float4 *s_nbr;                   // [k * ns + a] = (V_b grad_a W_ab, b as int bits in w)
+  // staging and reductions
+  double *stage;
+  double *red;
+};
+
+}  // namespace mrsph

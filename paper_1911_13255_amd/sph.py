@@ -1,0 +1,254 @@
+"""Python binding of libmrsph (argument marshalling only).
+
+Every step of the method runs in the library's HIP kernels; PyTorch provides
+the device arena (one uint8 tensor) and the stream.  The entry points keep the
+C names: ``neighbor_build``, ``fluid_step``, ``couple``, ``solid_substeps``,
+``advance`` (sph_advance), ``read``/``write`` (sph_read/sph_write), ...
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmrsph.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "mrsph.h")
+
+SPH_OK, SPH_E_ARG, SPH_E_HIP, SPH_E_ORDER, SPH_E_CAPACITY, SPH_E_UNSTABLE = 0, -1, -2, -3, -4, -5
+F_X, F_V, F_RHO, F_DRHO, F_A, F_P, F_NNB = 0, 1, 2, 3, 4, 5, 6
+S_U, S_V, S_A, S_F, S_DF, S_FF, S_VBAR, S_ABAR, S_N, S_B, S_N0, S_X0 = range(10, 22)
+FLUID_FIELDS = {F_X, F_V, F_RHO, F_DRHO, F_A, F_P, F_NNB}
+VECTOR_FIELDS = {F_X, F_V, F_A, S_U, S_V, S_A, S_FF, S_VBAR, S_ABAR, S_N, S_N0, S_X0}
+TENSOR_FIELDS = {S_F, S_DF, S_B}
+
+_dp = C.POINTER(C.c_double)
+
+
+class SphError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mrsph error {code}: {msg}")
+        self.code = code
+
+
+class SphScene(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("n_fluid", C.c_int), ("n_wall", C.c_int), ("n_solid", C.c_int),
+        ("n_clamp", C.c_int),
+        ("dp_f", C.c_double), ("dp_s", C.c_double), ("h_ratio", C.c_double),
+        ("rho0_f", C.c_double), ("c_f", C.c_double), ("eta", C.c_double), ("gamma", C.c_double),
+        ("g", C.c_double * 3),
+        ("rho0_s", C.c_double), ("E", C.c_double), ("nu", C.c_double),
+        ("cfl_ac", C.c_double), ("cfl_ad", C.c_double), ("cfl_s", C.c_double), ("u_ref", C.c_double),
+        ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("periodic", C.c_int * 3),
+        ("hydro_H", C.c_double),
+        ("inflow_U0", C.c_double), ("inflow_ts", C.c_double), ("inflow_H", C.c_double),
+        ("inflow_len", C.c_double),
+        ("x_fluid", _dp), ("v_fluid", _dp), ("x_wall", _dp), ("nrm_wall", _dp),
+        ("x_solid", _dp), ("v_solid", _dp),
+    ]
+
+
+class SphOptions(C.Structure):
+    _fields_ = [("riemann", C.c_int), ("density_reinit", C.c_int), ("max_solid_nbr", C.c_int),
+                ("solid_block", C.c_int)]
+
+
+def exported_names():
+    """Function names declared in include/mrsph.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", txt)) - {"defined"})
+
+
+_lib = None
+
+
+def lib():
+    """Load libmrsph.so; fails loudly when the HIP library is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.sph_arena_bytes.restype = C.c_size_t
+        L.sph_arena_bytes.argtypes = [C.POINTER(SphScene), C.c_int, C.POINTER(SphOptions)]
+        L.sph_init.argtypes = [C.POINTER(SphScene), C.c_int, C.POINTER(SphOptions), vp, C.c_size_t, vp,
+                               C.POINTER(vp)]
+        for name in ("neighbor_build", "fluid_step", "couple", "solid_substeps", "sph_sync"):
+            getattr(L, name).argtypes = [vp]
+        L.sph_advance.argtypes = [vp, C.c_int]
+        L.sph_read.argtypes = [vp, C.c_int, C.c_int, _dp]
+        L.sph_write.argtypes = [vp, C.c_int, C.c_int, _dp]
+        L.sph_scalars.argtypes = [vp, C.c_int, _dp]
+        L.sph_set_scalars.argtypes = [vp, C.c_int, _dp]
+        L.sph_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
+        L.sph_reduce.argtypes = [vp, C.c_int, _dp]
+        L.sph_last_error.restype = C.c_char_p
+        L.sph_last_error.argtypes = [vp]
+        L.sph_destroy.argtypes = [vp]
+        L.sph_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def scene_struct(sc: dict):
+    """Marshal a scene dict (see scenes.py) into the C struct; returns (struct, keepalive)."""
+    keep = {}
+    for k in ("x_fluid", "v_fluid", "x_wall", "n_wall", "x_solid", "v_solid"):
+        a = sc.get(k)
+        keep[k] = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+    s = SphScene()
+    s.dim = int(sc["dim"])
+    s.n_fluid = len(keep["x_fluid"])
+    s.n_wall = len(keep["x_wall"])
+    s.n_solid = len(keep["x_solid"])
+    s.n_clamp = int(sc["n_clamp"])
+    for k in ("dp_f", "dp_s", "h_ratio", "rho0_f", "c_f", "eta", "gamma", "rho0_s", "E", "nu",
+              "cfl_ac", "cfl_ad", "cfl_s", "u_ref", "hydro_H", "inflow_U0", "inflow_ts",
+              "inflow_H", "inflow_len"):
+        setattr(s, k, float(sc[k]))
+    for k in range(3):
+        s.g[k] = float(sc["g"][k])
+        s.lo[k] = float(sc["lo"][k])
+        s.hi[k] = float(sc["hi"][k])
+        s.periodic[k] = int(sc["periodic"][k])
+    for k, a in keep.items():
+        setattr(s, "nrm_wall" if k == "n_wall" else k, _ptr(a))
+    return s, keep
+
+
+class Simulation:
+    """One or more scenes on one GPU, advanced by the library's kernels."""
+
+    def __init__(self, scenes, riemann: bool = True, density_reinit: int = 1,
+                 max_solid_nbr: int = 0, solid_block: int = 0, device: int = 0):
+        import torch
+
+        if isinstance(scenes, dict):
+            scenes = [scenes]
+        self.L = lib()
+        self.n_scenes = len(scenes)
+        self.dim = int(scenes[0]["dim"])
+        self.nf = [len(s["x_fluid"]) for s in scenes]
+        self.ns = [len(s["x_solid"]) for s in scenes]
+        arr = (SphScene * self.n_scenes)()
+        self._keep = []
+        for i, sc in enumerate(scenes):
+            st, keep = scene_struct(sc)
+            arr[i] = st
+            self._keep.append(keep)
+        self._scenes = arr
+        self.opt = SphOptions(int(riemann), int(density_reinit), int(max_solid_nbr), int(solid_block))
+        nbytes = self.L.sph_arena_bytes(arr, self.n_scenes, C.byref(self.opt))
+        if nbytes == 0:
+            raise SphError(SPH_E_ARG, "invalid scene description")
+        self.device = torch.device("cuda", device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.Stream(device=self.device)
+            self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self.arena_bytes = nbytes
+        ctx = C.c_void_p()
+        rc = self.L.sph_init(arr, self.n_scenes, C.byref(self.opt), C.c_void_p(self.arena.data_ptr()),
+                             nbytes + 256, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if rc != SPH_OK:
+            raise SphError(rc, "sph_init failed")
+        self.ctx = ctx
+
+    def _check(self, rc):
+        if rc != SPH_OK:
+            raise SphError(rc, self.L.sph_last_error(self.ctx).decode())
+        return rc
+
+    # --- Algorithm 1 entry points (enqueue only)
+    def neighbor_build(self):
+        self._check(self.L.neighbor_build(self.ctx))
+
+    def fluid_step(self):
+        self._check(self.L.fluid_step(self.ctx))
+
+    def couple(self):
+        self._check(self.L.couple(self.ctx))
+
+    def solid_substeps(self):
+        self._check(self.L.solid_substeps(self.ctx))
+
+    def step(self):
+        """One acoustic step through the four separate entry points."""
+        self.neighbor_build()
+        self.fluid_step()
+        self.couple()
+        self.solid_substeps()
+
+    def advance(self, n: int):
+        """n acoustic steps, replayed from a captured HIP graph."""
+        self._check(self.L.sph_advance(self.ctx, int(n)))
+
+    def sync(self):
+        return self._check(self.L.sph_sync(self.ctx))
+
+    # --- state I/O
+    def _shape(self, field, scene):
+        n = self.nf[scene] if field in FLUID_FIELDS else self.ns[scene]
+        if field in VECTOR_FIELDS:
+            return (n, self.dim)
+        if field in TENSOR_FIELDS:
+            return (n, self.dim, self.dim)
+        if field == F_NNB:
+            return (n, 2)
+        return (n,)
+
+    def read(self, field: int, scene: int = 0) -> np.ndarray:
+        out = np.zeros(self._shape(field, scene))
+        self._check(self.L.sph_read(self.ctx, int(field), int(scene), _ptr(out)))
+        return out
+
+    def write(self, field: int, value, scene: int = 0):
+        a = np.ascontiguousarray(np.broadcast_to(value, self._shape(field, scene)), dtype=np.float64)
+        self._check(self.L.sph_write(self.ctx, int(field), int(scene), _ptr(a)))
+
+    def scalars(self, scene: int = 0) -> dict:
+        out = np.zeros(8)
+        self._check(self.L.sph_scalars(self.ctx, int(scene), _ptr(out)))
+        keys = ("t", "dt_ac", "dt_ad", "dt_s", "adv_accum", "kappa", "need_rebuild", "vmax")
+        return dict(zip(keys, out.tolist()))
+
+    def set_scalars(self, scene: int = 0, **kw):
+        cur = self.scalars(scene)
+        cur.update(kw)
+        arr = np.array([cur["t"], 0.0, cur["dt_ad"], 0.0, cur["adv_accum"], 0.0,
+                        float(cur["need_rebuild"]), 0.0])
+        self._check(self.L.sph_set_scalars(self.ctx, int(scene), _ptr(arr)))
+
+    def counters(self, scene: int = -1) -> dict:
+        out = (C.c_ulonglong * 8)()
+        self._check(self.L.sph_counters(self.ctx, int(scene), out))
+        keys = ("n_ff", "n_fw", "n_fs", "n_ss", "steps", "rebuilds", "substeps", "interactions")
+        return dict(zip(keys, [int(x) for x in out]))
+
+    def reduce(self, scene: int = 0) -> dict:
+        out = np.zeros(15)
+        self._check(self.L.sph_reduce(self.ctx, int(scene), _ptr(out)))
+        return dict(mom_fluid=out[0:3].copy(), mom_solid=out[3:6].copy(), ke_fluid=out[6],
+                    ke_solid=out[7], strain_energy=out[8], sum_fF=out[9:12].copy(),
+                    sum_fS=out[12:15].copy())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.sph_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every symbol include/mrsph.h declares
+(no GPU calls), and host-side argument checks reject bad scenes."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from paper_1911_13255_amd import scenes, sph
+
+
+def _lib_or_skip():
+    if not os.path.exists(sph.LIB_PATH):
+        pytest.skip("libmrsph.so not built")
+    return sph.lib()
+
+
+def test_header_symbols_exported():
+    _lib_or_skip()
+    names = sph.exported_names()
+    for must in ("sph_init", "neighbor_build", "fluid_step", "couple", "solid_substeps", "sph_advance",
+                 "sph_read", "sph_write", "sph_reduce", "sph_counters", "sph_sync", "sph_destroy",
+                 "sph_arena_bytes", "sph_scalars", "sph_set_scalars", "sph_last_error"):
+        assert must in names
+    L = ctypes.CDLL(sph.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing
+
+
+def test_arena_bytes_and_argument_checks():
+    L = _lib_or_skip()
+    sc = scenes.dam_break_plate(seed=1)
+    st, keep = sph.scene_struct(sc)
+    arr = (sph.SphScene * 1)(st)
+    opt = sph.SphOptions(1, 1, 0, 0)
+    n1 = L.sph_arena_bytes(arr, 1, ctypes.byref(opt))
+    assert n1 > 0
+    # more scenes need more memory
+    arr2 = (sph.SphScene * 2)(st, st)
+    assert L.sph_arena_bytes(arr2, 2, ctypes.byref(opt)) > n1
+    # invalid descriptions give 0
+    bad = sph.SphScene.from_buffer_copy(st)
+    bad.dim = 4
+    assert L.sph_arena_bytes((sph.SphScene * 1)(bad), 1, ctypes.byref(opt)) == 0
+    bad = sph.SphScene.from_buffer_copy(st)
+    bad.n_clamp = bad.n_solid + 1
+    assert L.sph_arena_bytes((sph.SphScene * 1)(bad), 1, ctypes.byref(opt)) == 0
+    bad = sph.SphScene.from_buffer_copy(st)
+    bad.periodic[0] = 1
+    bad.hi[0] = bad.lo[0] + 0.02  # fewer than 3 cells of 2 h_F
+    assert L.sph_arena_bytes((sph.SphScene * 1)(bad), 1, ctypes.byref(opt)) == 0
+    mixed = sph.SphScene.from_buffer_copy(st)
+    mixed.dim = 3
+    assert L.sph_arena_bytes((sph.SphScene * 2)(st, mixed), 2, ctypes.byref(opt)) == 0
+    # init with no context pointer or a null arena fails without touching the GPU
+    out = ctypes.c_void_p()
+    assert L.sph_init(arr, 1, ctypes.byref(opt), None, 0, None, ctypes.byref(out)) == sph.SPH_E_ARG
+    assert L.sph_init(arr, 1, ctypes.byref(opt), None, 0, None, None) == sph.SPH_E_ARG
+
+
+def test_calls_without_context_are_order_errors():
+    L = _lib_or_skip()
+    for name in ("neighbor_build", "fluid_step", "couple", "solid_substeps", "sph_sync"):
+        assert getattr(L, name)(None) == sph.SPH_E_ORDER
+    assert L.sph_advance(None, 1) == sph.SPH_E_ORDER
+    buf = np.zeros(8)
+    assert L.sph_scalars(None, 0, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == sph.SPH_E_ORDER

@@ -1,0 +1,334 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances: per-field relative infinity-norm error <= 1e-4 per step (density,
+density rate, forces, solid state), pair sets identical particle by particle,
+the coupling momentum exchange exact to FP32 rounding (<= 1e-6 of the summed
+force magnitudes).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1911_13255_amd import scenes, sph
+
+pytestmark = pytest.mark.gpu
+
+STATE_FIELDS = (sph.F_X, sph.F_V, sph.F_RHO, sph.F_DRHO, sph.S_U, sph.S_V, sph.S_A, sph.S_F, sph.S_DF,
+                sph.S_VBAR, sph.S_ABAR)
+COMPARED = (sph.F_RHO, sph.F_DRHO, sph.F_A, sph.F_V, sph.S_FF, sph.S_U, sph.S_V, sph.S_F, sph.S_DF,
+            sph.S_VBAR, sph.S_ABAR, sph.S_A)
+NAMES = {sph.F_RHO: "rho", sph.F_DRHO: "drho", sph.F_A: "a_f", sph.F_V: "v_f", sph.S_FF: "fF",
+         sph.S_U: "u_s", sph.S_V: "v_s", sph.S_F: "F", sph.S_DF: "dF", sph.S_VBAR: "vbar",
+         sph.S_ABAR: "abar", sph.S_A: "a_s", sph.F_X: "x_f"}
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_inf(g, r):
+    den = np.abs(r).max() if r.size else 0.0
+    err = np.abs(g - r).max() if r.size else 0.0
+    return err / den if den > 0 else err
+
+
+def compare(sim, ora, fields=COMPARED, scene=0, tol=1e-4, skip_zero=True, label=""):
+    worst = {}
+    for f in fields:
+        if f >= 10 and ora.ns == 0:
+            continue
+        if f < 10 and ora.nf == 0:
+            continue
+        g, r = sim.read(f, scene), ora.get(f)
+        if f == sph.S_F:
+            g = g - np.eye(ora.dim)
+            r = r - np.eye(ora.dim)
+        if skip_zero and np.abs(r).max() == 0.0:
+            assert np.abs(g).max() <= 1e-30, (label, NAMES[f])
+            continue
+        worst[NAMES[f]] = rel_inf(g, r)
+        if worst[NAMES[f]] > tol:
+            d = np.abs(g - r).reshape(len(r), -1).max(1)
+            i = int(np.argmax(d))
+            note(f"  {label} {NAMES[f]}: worst particle {i} gpu {g[i]} oracle {r[i]} max|oracle| {np.abs(r).max():.3e}")
+    note(f"{label} errors: " + ", ".join(f"{k}={v:.2e}" for k, v in worst.items()))
+    for k, v in worst.items():
+        assert v <= tol, (label, k, v)
+    return worst
+
+
+def compare_positions(sim, ora, scene=0, tol=1e-6, label=""):
+    g, r = sim.read(sph.F_X, scene), ora.get(O.F_X)
+    d = g - r
+    # periodic axes: minimum image
+    err = np.abs(d).max() if d.size else 0.0
+    note(f"{label} position error {err:.2e} (h_f units {err / ora_hf(ora):.2e})")
+    assert err <= tol * max(1.0, np.abs(r).max())
+
+
+def ora_hf(ora):
+    return 1.3 * ora._s.dp_f
+
+
+def inject(sim, ora, scene=0):
+    """Teacher forcing at an advection-step start: the oracle state becomes the GPU's."""
+    for f in STATE_FIELDS:
+        if f >= 10 and ora.ns == 0:
+            continue
+        if f < 10 and ora.nf == 0:
+            continue
+        sim.write(f, ora.get(f), scene)
+    s = ora.scalars()
+    sim.set_scalars(scene, t=s["t"], adv_accum=0.0, dt_ad=s["dt_ad"], need_rebuild=1)
+
+
+def one_step(sim, ora):
+    sim.step()
+    ora.step(1)
+
+
+# ------------------------------------------------------------------ set-up
+
+def test_initial_state_and_reference_configuration(gpu):
+    sc = scenes.dam_break_plate(seed=1)
+    note("init dam_break_plate seed 1")
+    sim = sph.Simulation(sc)
+    o = O.Oracle(sc)
+    x = sim.read(sph.F_X)
+    assert np.abs(x - sc["x_fluid"]).max() < 1e-8
+    assert rel_inf(sim.read(sph.F_RHO), o.get(O.F_RHO)) < 1e-7
+    assert rel_inf(sim.read(sph.S_B), o.get(O.S_B)) < 1e-6
+    n0g, n0o = sim.read(sph.S_N0), o.get(O.S_N0)
+    assert np.abs(n0g - n0o).max() < 1e-6
+    assert np.array_equal(n0g == 0.0, n0o == 0.0)
+    assert np.abs(sim.read(sph.S_X0) - sc["x_solid"]).max() == 0.0
+    c = sim.counters(0)
+    assert c["n_ss"] == o.counters()["n_ss"]
+    sim.close()
+
+
+@pytest.mark.parametrize("name", ["dam_break_plate", "periodic_box", "plate_behind_cylinder"])
+def test_pair_sets_match_the_oracle(gpu, name):
+    sc = {"dam_break_plate": lambda: scenes.dam_break_plate(seed=3),
+          "periodic_box": lambda: scenes.periodic_box_with_solid(dim=2, n=16),
+          "plate_behind_cylinder": lambda: scenes.plate_behind_cylinder(dp_f=0.01)}[name]()
+    note(f"pairs {name}")
+    sim = sph.Simulation(sc)
+    o = O.Oracle(sc)
+    sim.neighbor_build()
+    o.rebuild()
+    nnb = sim.read(sph.F_NNB).astype(int)
+    sf, _ = o.pairs(0)
+    sb, _ = o.pairs(1)
+    assert np.array_equal(nnb[:, 0], np.diff(sf))
+    assert np.array_equal(nnb[:, 1], np.diff(sb))
+    c = sim.counters(0)
+    oc = o.counters()
+    assert c["n_ff"] == oc["n_ff"] and c["n_fw"] + c["n_fs"] == oc["n_fb"]
+    assert c["n_fs"] == oc["n_sf"]
+    sim.close()
+
+
+# ------------------------------------------------------------------ per-step parity
+
+@pytest.mark.parametrize("reinit", [1, 0, 2])
+def test_first_steps_dam_break(gpu, reinit):
+    sc = scenes.dam_break_plate(seed=1)
+    note(f"first steps dam_break_plate reinit {reinit}")
+    sim = sph.Simulation(sc, density_reinit=reinit)
+    o = O.Oracle(sc, density_reinit=reinit)
+    for k in range(12):
+        one_step(sim, o)
+        compare(sim, o, label=f"step {k + 1}")
+        compare_positions(sim, o, label=f"step {k + 1}")
+    s1, s2 = sim.scalars(), o.scalars()
+    assert abs(s1["t"] - s2["t"]) < 1e-6 * s2["t"]
+    assert s1["kappa"] == s2["kappa"]
+    assert sim.counters(0)["rebuilds"] == o.counters()["rebuilds"]
+    sim.sync()
+    sim.close()
+
+
+def test_teacher_forced_steps_dam_break(gpu):
+    # The oracle runs ahead; at several advection-step starts its state is
+    # written into the GPU, both take one step, the outputs are compared.
+    sc = scenes.dam_break_plate(seed=2)
+    o = O.Oracle(sc)
+    sim = sph.Simulation(sc)
+    checked = 0
+    for k in range(400):
+        if o.scalars()["need_rebuild"] and (k == 0 or k > 60) and checked < 8:
+            note(f"teacher-forced step at oracle step {k}")
+            inject(sim, o)
+            one_step(sim, o)
+            compare(sim, o, label=f"forced {k}")
+            compare_positions(sim, o, label=f"forced {k}")
+            checked += 1
+        else:
+            o.step(1)
+    assert checked >= 5
+    sim.sync()
+    sim.close()
+
+
+@pytest.mark.parametrize("dim,eta", [(2, 0.0), (2, 2.0), (3, 0.5)])
+def test_periodic_box_with_free_solid(gpu, dim, eta):
+    # Wetted free solid from the first step: coupling forces, kappa > 1.
+    sc = scenes.periodic_box_with_solid(dim=dim, n=16 if dim == 2 else 8, eta=eta, amp=0.3)
+    note(f"periodic box dim {dim} eta {eta}")
+    sim = sph.Simulation(sc)
+    o = O.Oracle(sc)
+    for k in range(6):
+        one_step(sim, o)
+        compare(sim, o, label=f"box{dim} step {k + 1}")
+    assert o.scalars()["kappa"] > 1
+    sim.sync()
+    sim.close()
+
+
+def test_channel_with_inflow(gpu):
+    # Periodic channel with the inflow buffer, cylinder walls and the plate.
+    sc = scenes.plate_behind_cylinder(dp_f=0.01)
+    note("channel dp_f 0.01")
+    sim = sph.Simulation(sc)
+    o = O.Oracle(sc)
+    for k in range(3):
+        one_step(sim, o)
+        compare(sim, o, label=f"channel step {k + 1}")
+    forced = 0
+    for k in range(200):
+        if o.scalars()["need_rebuild"] and k > 20:
+            inject(sim, o)
+            one_step(sim, o)
+            compare(sim, o, label=f"channel forced {k}")
+            forced += 1
+            if forced == 3:
+                break
+        else:
+            o.step(1)
+    assert forced == 3
+    sim.sync()
+    sim.close()
+
+
+def test_batched_scenes_match_separate_oracles(gpu):
+    scs = scenes.batched_dam_breaks(n_scenes=4)
+    note("batched 4 scenes " + str([len(s["x_fluid"]) for s in scs]))
+    sim = sph.Simulation(scs)
+    oras = [O.Oracle(s) for s in scs]
+    for k in range(3):
+        sim.step()
+        for o in oras:
+            o.step(1)
+        for i, o in enumerate(oras):
+            compare(sim, o, scene=i, label=f"scene {i} step {k + 1}")
+            assert sim.scalars(i)["kappa"] == o.scalars()["kappa"]
+    # teacher-forced step of each scene at its own next advection-step start
+    for i, o in enumerate(oras):
+        o.step(5)
+        while not o.scalars()["need_rebuild"]:
+            o.step(1)
+        inject(sim, o, scene=i)
+        sim.step()
+        o.step(1)
+        compare(sim, o, scene=i, label=f"scene {i} forced")
+    sim.sync()
+    sim.close()
+
+
+# ------------------------------------------------------------------ invariants in FP32
+
+def test_coupling_exchange_and_momentum(gpu):
+    sc = scenes.periodic_box_with_solid(dim=2, n=16, eta=1.0, amp=0.3)
+    note("momentum box")
+    sim = sph.Simulation(sc)
+    r0 = sim.reduce(0)
+    p0 = r0["mom_fluid"] + r0["mom_solid"]
+    mf_scale = None
+    for k in range(20):
+        sim.neighbor_build()
+        sim.fluid_step()
+        sim.couple()
+        red = sim.reduce(0)
+        fF = sim.read(sph.S_FF)
+        scale = np.abs(fF).sum()
+        resid = np.abs(red["sum_fS"][:2] + red["sum_fF"][:2]).max()
+        assert scale > 0
+        assert resid <= 1e-6 * scale, (k, resid, scale)
+        sim.solid_substeps()
+    red = sim.reduce(0)
+    p1 = red["mom_fluid"] + red["mom_solid"]
+    v = sim.read(sph.F_V)
+    mtot = sc["rho0_f"] * sc["dp_f"] ** 2 * len(v)
+    pscale = mtot * np.abs(v).max()
+    note(f"momentum drift {np.abs(p1 - p0).max():.3e} of {pscale:.3e}")
+    assert np.abs(p1 - p0).max() <= 1e-5 * pscale
+    sim.close()
+
+
+def test_graph_replay_matches_direct_calls(gpu):
+    sc = scenes.dam_break_plate(seed=4)
+    a = sph.Simulation(sc)
+    b = sph.Simulation(sc)
+    for rep in range(3):
+        for _ in range(7):
+            a.step()
+        b.advance(7)
+        for f in (sph.F_X, sph.F_V, sph.F_RHO, sph.S_U, sph.S_V, sph.S_VBAR):
+            assert np.array_equal(a.read(f), b.read(f)), (rep, f)
+        assert a.scalars() == b.scalars()
+    a.close()
+    b.close()
+
+
+def test_runs_are_bit_reproducible(gpu):
+    sc = scenes.periodic_box_with_solid(dim=2, n=16, eta=0.5, amp=0.3)
+    outs = []
+    for _ in range(2):
+        sim = sph.Simulation(sc)
+        sim.advance(25)
+        outs.append([sim.read(f) for f in (sph.F_X, sph.F_V, sph.F_RHO, sph.S_U, sph.S_FF)])
+        sim.close()
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------------ failure handling
+
+def test_nan_state_is_reported(gpu):
+    sc = scenes.dam_break_plate(seed=1)
+    sim = sph.Simulation(sc)
+    sim.advance(2)
+    assert sim.sync() == 0
+    v = sim.read(sph.F_V)
+    v[5, 0] = np.nan
+    sim.write(sph.F_V, v)
+    sim.advance(2)
+    with pytest.raises(sph.SphError) as e:
+        sim.sync()
+    assert e.value.code == sph.SPH_E_UNSTABLE
+    sim.close()
+
+
+def test_inverted_solid_is_reported(gpu):
+    sc = scenes.dam_break_plate(seed=1)
+    sim = sph.Simulation(sc)
+    F = sim.read(sph.S_F)
+    F[3] = np.diag([-1.0, 1.0])
+    sim.write(sph.S_F, F)
+    sim.advance(1)
+    with pytest.raises(sph.SphError) as e:
+        sim.sync()
+    assert e.value.code == sph.SPH_E_UNSTABLE
+    sim.close()
+
+
+def test_neighbour_capacity_overflow_is_reported(gpu):
+    sc = scenes.dam_break_plate(seed=1)
+    with pytest.raises(sph.SphError) as e:
+        sph.Simulation(sc, max_solid_nbr=4)
+    assert e.value.code == sph.SPH_E_CAPACITY
