@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of the plain multi-resolution SPH FSI path on one MI355X.
+
+Workload (default): the 2D flexible plate behind a rigid cylinder in a
+channel (11D x 4.1D, D = 0.1 m, Re = 100, rho_s/rho_f = 10, E* = 1.4e3,
+nu = 0.4, dp_f = D/20, dp_s = dp_f/2, periodic channel with an inflow
+buffer), synthetic seeded lattice.  A step is one fluid acoustic step of
+Algorithm 1: the rebuild when an advection step is due, the fluid force and
+continuity passes, the coupling force on the solid and kappa solid
+sub-steps, all replayed from one captured HIP graph with every decision on
+the device.
+
+Prints one JSON line: particle interactions per second (every within-support
+pair evaluated by every pair loop, counted on the device) and FSI steps per
+second, the roofline position of the dominant kernel, and the FP64 CPU
+oracle timed on the host on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-interactions/s; FSI steps/s plain vs surrogate at ≤1% tip error"
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed instructions: 256 CUs x 4 SIMD x 16 lanes
+# x 2 flops (FMA) x 2.4 GHz (the packed-FP32 figure of 157.3 TFLOP/s is not
+# reachable by code built without packed FP32 instructions).
+ALU_PEAK_TFLOPS = 78.6
+# Algorithmic cost of the fluid momentum pass per fluid particle and per
+# within-support pair (2D / 3D): bytes of the particle's own state read and
+# written once, flops of one pair evaluation.
+FORCE_BYTES_PER_PARTICLE = {2: 52.0, 3: 72.0}
+FORCE_FLOPS_PER_PAIR = 70.0
+SOLID_FLOPS_PER_PAIR = 33.0
+SOLID_FLOPS_PER_PARTICLE = 200.0
+SOLID_BYTES_PER_PARTICLE = {2: 160.0, 3: 300.0}
+
+
+def make_workload(name):
+    from paper_1911_13255_amd import scenes
+
+    if name == "plate_behind_cylinder":
+        return [scenes.plate_behind_cylinder(seed=1)]
+    if name == "dam_break_plate":
+        return [scenes.dam_break_plate(seed=1)]
+    if name == "dam_break_3d":
+        return [scenes.dam_break_plate_3d(seed=1)]
+    if name == "batched_dam_breaks":
+        return scenes.batched_dam_breaks(64)
+    raise ValueError(name)
+
+
+def cpu_baseline(scene, seconds=15.0):
+    """The FP64 oracle on the host cores on a bounded prefix of the same run."""
+    from oracle import oracle as ora
+
+    o = ora.Oracle(scene)
+    threads = ora.num_threads()
+    o.step(2)  # first rebuild outside the timing
+    c0 = o.counters()
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        o.step(10)
+        n += 10
+    dt = time.perf_counter() - t0
+    c1 = o.counters()
+    inter = c1["interactions"] - c0["interactions"]
+    return dict(value=inter / dt, unit="interactions/s", cores=threads, kind="oracle",
+                sample=f"{n} acoustic steps after the first two of the same scene and seed "
+                       f"({dt:.1f} s, FP64, OpenMP)",
+                steps_per_s=n / dt)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="plate_behind_cylinder",
+                    choices=["plate_behind_cylinder", "dam_break_plate", "dam_break_3d",
+                             "batched_dam_breaks"])
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1911_13255_amd import sph
+
+    scs = make_workload(args.workload)
+    dim = int(scs[0]["dim"])
+    print(f"[bench] workload {args.workload}: {len(scs)} scene(s), "
+          f"{sum(len(s['x_fluid']) for s in scs)} fluid, {sum(len(s['x_solid']) for s in scs)} solid, "
+          f"{sum(len(s['x_wall']) for s in scs)} wall particles", file=sys.stderr, flush=True)
+    sim = sph.Simulation(scs)
+    sim.advance(args.warmup)
+    torch.cuda.synchronize()
+    sim.sync()
+    c0 = sim.counters()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(sim.stream)
+    sim.advance(args.steps)
+    t_end.record(sim.stream)
+    t_end.synchronize()
+    torch.cuda.synchronize()
+    ms = t_start.elapsed_time(t_end)
+    sim.sync()
+    c1 = sim.counters()
+    inter = c1["interactions"] - c0["interactions"]
+    secs = ms / 1e3
+    value = inter / secs
+    steps_per_s = args.steps / secs
+    rebuilds = c1["rebuilds"] - c0["rebuilds"]
+    print(f"[bench] {args.steps} steps in {ms:.1f} ms, {rebuilds} rebuilds, "
+          f"{inter} interactions", file=sys.stderr, flush=True)
+
+    # per-kernel durations (HIP events on the library's stream), after the timed region
+    kt = {name: sim.time_kernel(k, args.kernel_reps) for name, k in
+          (("k_fluid_force", sph.K_FLUID_FORCE), ("k_fluid_continuity", sph.K_CONTINUITY),
+           ("k_couple", sph.K_COUPLE), ("k_solid", sph.K_SOLID))}
+    kt["rebuild_sequence"] = sim.time_kernel(sph.K_REBUILD, max(10, args.kernel_reps // 10))
+    per_step = dict(kt)
+    per_step["rebuild_sequence"] = kt["rebuild_sequence"] * rebuilds / args.steps
+    print(f"[bench] kernel ms per launch {json.dumps({k: round(v, 5) for k, v in kt.items()})}",
+          file=sys.stderr, flush=True)
+    nf = sum(len(s["x_fluid"]) for s in scs)
+    ns_free = sum(len(s["x_solid"]) - int(s["n_clamp"]) for s in scs)
+    pairs_f = c1["n_ff"] + c1["n_fw"] + c1["n_fs"]
+    dominant = max(("k_fluid_force", "k_solid"), key=lambda k: per_step[k])
+    if dominant == "k_fluid_force":
+        dur = kt["k_fluid_force"] * 1e-3
+        alg_bytes = FORCE_BYTES_PER_PARTICLE[dim] * nf
+        alg_flops = FORCE_FLOPS_PER_PAIR * pairs_f
+    else:
+        dur = kt["k_solid"] * 1e-3
+        kappa = (c1["substeps"] - c0["substeps"]) / max(1, c1["steps"] - c0["steps"])
+        alg_bytes = SOLID_BYTES_PER_PARTICLE[dim] * ns_free
+        alg_flops = kappa * (2 * SOLID_FLOPS_PER_PAIR * c1["n_ss"] + SOLID_FLOPS_PER_PARTICLE * ns_free)
+    gbs = alg_bytes / dur / 1e9
+    tflops = alg_flops / dur / 1e12
+    hbm_frac = gbs / HBM_PEAK_GBS
+    alu_frac = tflops / ALU_PEAK_TFLOPS
+    if alu_frac >= hbm_frac:
+        roof = dict(bound="alu", achieved=tflops, peak=ALU_PEAK_TFLOPS, unit="TFLOP/s", frac=alu_frac)
+    else:
+        roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm_frac)
+    roof.update(traffic=None, kernel=dominant, duration_us=dur * 1e6,
+                hbm_GBps=gbs, hbm_frac=hbm_frac, alu_TFLOPs=tflops, alu_frac=alu_frac,
+                algorithmic_bytes=alg_bytes, algorithmic_flops=alg_flops)
+
+    cpu = None
+    if not args.no_cpu_baseline and len(scs) == 1:
+        cpu = cpu_baseline(scs[0], args.cpu_seconds)
+    elif not args.no_cpu_baseline:
+        cpu = cpu_baseline(scs[0], args.cpu_seconds)
+        cpu["sample"] = "scene 0 of the batch only: " + cpu["sample"]
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "scenes": len(scs),
+            "n_fluid": nf,
+            "n_solid": sum(len(s["x_solid"]) for s in scs),
+            "n_wall": sum(len(s["x_wall"]) for s in scs),
+            "dim": dim,
+            "dp_f": scs[0]["dp_f"],
+            "dp_s": scs[0]["dp_s"],
+        },
+        "fsi_steps_per_s": steps_per_s,
+        "interactions_per_step": inter / args.steps,
+        "rebuilds": rebuilds,
+        "kernel_ms_per_step": {k: round(v, 6) for k, v in per_step.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -65,7 +65,10 @@ typedef struct {
   int riemann;        /* 1: low-dissipation Riemann solver (Section 2.2); 0: simple averages */
   int density_reinit; /* 0 off; 1 rho = rho0 max(1, psi/psi0); 2 rho = max(rho, rho0 psi/psi0) */
   int max_solid_nbr;  /* capacity of the solid reference neighbour table; 0 = default (40 in 2D, 128 in 3D) */
-  int solid_block;    /* threads per scene in the solid sub-step kernel; 0 = default */
+  int solid_block;    /* threads per scene in the solid sub-step kernel (power of two, 64..1024); 0 = default */
+  int lanes_per_particle; /* lanes sharing one particle in the fluid pair loops (1, 2, 4, 8, 16); 0 = chosen from the particle count */
+  int block_pair;     /* threads per block of the fluid pair loops (64, 128, 256); 0 = default */
+  int solid_lds;      /* 0: solid exchange fields in LDS when a scene fits; 1: always in global memory */
 } sph_options;
 
 /* Field ids for sph_read / sph_write (FP64, original particle order).
@@ -155,9 +158,10 @@ int sph_scalars(sph_ctx *ctx, int scene, double *out);
 int sph_set_scalars(sph_ctx *ctx, int scene, const double *in);
 
 /* Counters of one scene (scene = -1: sum over scenes): out[0..7] =
- * fluid-fluid pairs, fluid-wall pairs, fluid-solid pairs (at the last
- * rebuild), solid reference pairs, acoustic steps, rebuilds, solid sub-steps,
- * particle interactions evaluated.  Synchronises. */
+ * fluid-fluid pairs, fluid-wall pairs, fluid-solid pairs (of the last
+ * rebuild, totalled when the acoustic step that began with it ends), solid
+ * reference pairs, acoustic steps, rebuilds, solid sub-steps, particle
+ * interactions evaluated.  Synchronises. */
 int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out);
 
 /* FP64 reductions of one scene: out[0..2] fluid momentum, out[3..5] solid
@@ -167,6 +171,22 @@ int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out);
  * fluid step's mid-point state (valid between couple and solid_substeps).
  * Synchronises. */
 int sph_reduce(sph_ctx *ctx, int scene, double *out);
+
+/* Kernel ids for sph_time_kernel. */
+enum {
+  SPH_K_FLUID_FORCE = 0, /* momentum pass of fluid_step */
+  SPH_K_CONTINUITY = 1,  /* continuity pass of fluid_step */
+  SPH_K_COUPLE = 2,      /* couple */
+  SPH_K_SOLID = 3,       /* solid_substeps */
+  SPH_K_REBUILD = 4      /* neighbor_build with a rebuild forced in every scene */
+};
+
+/* Average duration in milliseconds of `reps` back-to-back launches of one
+ * kernel (or, for SPH_K_REBUILD, of the whole rebuild sequence) on the
+ * context's stream, from two HIP events around them.  For profiling: the
+ * launches advance the state like the entry point that owns the kernel.
+ * Synchronises. */
+int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms);
 
 /* Wait for the stream; return the first latched device error, if any. */
 int sph_sync(sph_ctx *ctx);

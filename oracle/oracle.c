@@ -16,6 +16,9 @@
  * check are marked "parity unpinned"; there are none at present.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1138,6 +1141,15 @@ void ora_fluid_side_coupling(const ora_ctx *c, double *out) {
       for (int q = 0; q < d; ++q) out[q] += f[q];
     }
   }
+}
+
+/* threads the oracle's parallel loops use */
+int ora_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 /* fluid masses (index order) */

@@ -254,6 +254,12 @@ def eos_inv(p, rho0, c, gam=7.0):
     return lib().ora_eos_inv(float(p), float(rho0), float(c), float(gam))
 
 
+def num_threads():
+    L = lib()
+    L.ora_num_threads.restype = C.c_int
+    return L.ora_num_threads()
+
+
 def psi0(d, h_ratio=1.3):
     return lib().ora_psi0(int(d), float(h_ratio))
 

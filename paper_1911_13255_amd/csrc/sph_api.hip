@@ -77,7 +77,7 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
     err = "dim must be 2 or 3";
     return false;
   }
-  sph_options o{1, 1, 0, 0};
+  sph_options o{1, 1, 0, 0, 0, 0, 0};
   if (opt) o = *opt;
   P.maxn = o.max_solid_nbr > 0 ? o.max_solid_nbr : (P.dim == 2 ? 40 : 128);
   int max_solid_scene = 0;
@@ -222,8 +222,28 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
     return false;
   }
   P.cfg.block_solid = bs;
-  P.cfg.block_pair = P.nf < 65536 ? 64 : 256;
+  // lanes per particle: enough lanes in flight to keep about eight waves per CU
+  auto pick_lpp = [](long long nparticles) {
+    const long long target = 256LL * 8 * 64;
+    int l = 1;
+    while (l < 16 && nparticles * l < target) l *= 2;
+    return l;
+  };
+  int lpp = o.lanes_per_particle;
+  if (lpp != 0 && lpp != 1 && lpp != 2 && lpp != 4 && lpp != 8 && lpp != 16) {
+    err = "lanes_per_particle must be 1, 2, 4, 8 or 16";
+    return false;
+  }
+  P.cfg.lpp_force = P.cfg.lpp_cont = P.cfg.lpp_reinit = lpp ? lpp : pick_lpp(P.nf);
+  P.cfg.lpp_couple = lpp ? lpp : pick_lpp(P.ns);
+  int bp = o.block_pair;
+  if (bp != 0 && bp != 64 && bp != 128 && bp != 256) {
+    err = "block_pair must be 64, 128 or 256";
+    return false;
+  }
+  P.cfg.block_pair = bp ? bp : 256;
   P.cfg.block_couple = 64;
+  P.cfg.solid_lds_n = o.solid_lds == 1 ? 0 : max_solid_scene;  // confirmed against the device in sph_init
   return true;
 }
 
@@ -252,6 +272,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.f_drho, nf);
   take(D.f_p, nf);
   take(D.f_nnb, nf);
+  take(D.f_speed, nf);
   take(D.fs_lin, nf);
   take(D.fs_slot, nf);
   take(D.fs_id, nf);
@@ -376,6 +397,20 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   ctx->cfg = P.cfg;
   ctx->graph = nullptr;
   ctx->graph_exec = nullptr;
+  {
+    // the solid exchange fields go to LDS when the largest scene fits
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      lds_max = 0;
+    size_t need_lds = (size_t)ctx->cfg.solid_lds_n * solid_lds_bytes_per_particle(P.dim);
+    // the kernel's own shared arrays take 8 KiB + a few bytes
+    if (ctx->cfg.solid_lds_n <= 0 || need_lds + 9 * 1024 > (size_t)lds_max ||
+        allow_solid_lds(P.dim, need_lds) != hipSuccess) {
+      ctx->cfg.solid_lds_n = 0;
+      (void)hipGetLastError();
+    }
+  }
   ctx->graph_failed = 0;
   ctx->err[0] = 0;
   size_t need = carve(nullptr, P, ctx->D);
@@ -661,6 +696,36 @@ int sph_sync(sph_ctx *ctx) {
     }
   }
   return SPH_OK;
+}
+
+int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms) {
+  if (!ctx) return SPH_E_ORDER;
+  if (reps <= 0 || !avg_ms || kernel < SPH_K_FLUID_FORCE || kernel > SPH_K_REBUILD) return SPH_E_ARG;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, ctx->stream));
+  for (int r = 0; r < reps; ++r) {
+    switch (kernel) {
+    case SPH_K_FLUID_FORCE: launch_fluid_force(ctx->D, ctx->cfg, ctx->stream); break;
+    case SPH_K_CONTINUITY: launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream); break;
+    case SPH_K_COUPLE: launch_couple(ctx->D, ctx->cfg, ctx->stream); break;
+    case SPH_K_SOLID: launch_solid(ctx->D, ctx->cfg, ctx->stream); break;
+    case SPH_K_REBUILD:
+      for (int s = 0; s < ctx->n_scenes; ++s) launch_set_rebuild(ctx->D, s, ctx->stream);
+      launch_rebuild(ctx->D, ctx->cfg, ctx->stream);
+      break;
+    }
+  }
+  HIPCHK(hipEventRecord(e1, ctx->stream));
+  int rc = check_launch(ctx, "sph_time_kernel");
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = (double)ms / reps;
+  return rc;
 }
 
 const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->err : "no context"; }

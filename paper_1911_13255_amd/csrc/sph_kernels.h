@@ -10,6 +10,8 @@ struct LaunchCfg {
   int block_pair;    // threads per block of the fluid pair kernels
   int block_couple;  // threads per block of the coupling kernel
   int block_solid;   // threads per scene of the solid sub-step kernel
+  int lpp_force, lpp_cont, lpp_couple, lpp_reinit;  // lanes per particle (1, 2, 4, 8, 16)
+  int solid_lds_n;   // solid particles per scene held in LDS (0: exchanged fields in global memory)
 };
 
 void launch_init_scene(const Dev &D, int s, const double *x_f, const double *v_f, int has_vf, double gabs,
@@ -29,5 +31,7 @@ void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t
 void launch_write(const Dev &D, int s, int field, int n, const double *in, hipStream_t st);
 void launch_reduce(const Dev &D, int s, int nblocks, double *out, hipStream_t st);
 void launch_set_rebuild(const Dev &D, int s, hipStream_t st);
+int solid_lds_bytes_per_particle(int dim);
+hipError_t allow_solid_lds(int dim, size_t bytes);
 
 }  // namespace mrsph

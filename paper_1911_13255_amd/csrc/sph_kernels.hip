@@ -161,6 +161,8 @@ __global__ void k_init_fluid(Dev D, int s, const double *x, const double *v, int
   if (has_v)
     for (int k = 0; k < DIM; ++k) vv[k] = (float)v[(size_t)DIM * i + k];
   D.f_va[gi] = make_float4(vv[0], vv[1], vv[2], (float)eps);
+  D.f_speed[gi] = sqrtf(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
+  D.f_nnb[gi] = make_int4(0, 0, 0, 0);
   D.f_vb[gi] = D.f_va[gi];
   D.f_acc[gi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   D.f_drho[gi] = 0.0f;
@@ -364,61 +366,46 @@ __global__ void k_refresh_vmax(Dev D) {
 }
 
 // ------------------------------------------------------------------ rebuild
+//
+// A rebuild runs for the scenes whose need_rebuild flag is set (set at the end
+// of the acoustic step that closes an advection step, or by a state write);
+// the five kernels below test the flag and exit at once otherwise, and the
+// solid kernel at the end of the step clears it.
 
-// Advection step start (Algorithm 1; Section 3.2, advection criterion):
-// dt_ad = cfl_ad min(h / max(|v|max, U_ref), h^2 rho0 / eta).
-__global__ void k_rebuild_begin(Dev D) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= D.n_scenes) return;
-  SceneState &S = D.st[s];
-  const ScenePar &P = D.par[s];
-  S.rebuilding = S.need_rebuild;
-  if (!S.need_rebuild) return;
-  double vm = fmax((double)__uint_as_float(S.vmax_prev), (double)P.u_ref);
-  double dt = (double)P.cfl_ad * (double)P.hf / vm;
-  if (P.dt_visc > 0.0) dt = fmin(dt, P.dt_visc);
-  S.dt_ad = dt;
-  S.adv_accum = 0.0;
-  S.need_rebuild = 0;
-  S.rebuilds += 1;
-  S.n_ff = S.n_fw = S.n_fs = 0;
-}
-
-// Bin the fluid of rebuilding scenes: new cell and offset from the current
-// position, slot within the cell, and a copy of the state by old index.
+// Bin the fluid and the boundary sources (walls, free solid) of rebuilding
+// scenes: new cell and offset from the current position, slot within the
+// cell, and a copy of the fluid state by old index.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_fluid_bin(Dev D) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= D.nf) return;
-  int s = D.f_scene[i];
-  if (!D.st[s].rebuilding) return;
-  const ScenePar &P = D.par[s];
-  int c[3];
-  decode_cell(P, D.f_lin[i], c);
-  double4 o = D.f_off[i];
-  double off[3] = {o.x, o.y, o.z};
-  if (!renormalise<DIM>(P, c, off)) atomicOr(&D.st[s].err, (int)ERR_NAN_FLUID);
-  int lin = encode_cell(P, c);
-  D.fs_lin[i] = lin;
-  D.fs_off[i] = make_double4(off[0], off[1], off[2], 0.0);
-  D.fs_slot[i] = atomicAdd(&D.fc_count[P.cell_begin + lin], 1);
-  D.fs_va[i] = D.f_va[i];
-  D.fs_drho[i] = D.f_drho[i];
-  D.fs_id[i] = D.f_id[i];
-  D.fs_m[i] = D.f_pos[i].w;
-}
-
-// Bin walls and free solid particles of rebuilding scenes into the fluid grid.
-template <int DIM>
-__global__ void __launch_bounds__(256) k_bnd_bin(Dev D) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_bin(Dev D) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < D.nf) {
+    int i = t;
+    int s = D.f_scene[i];
+    if (!D.st[s].need_rebuild) return;
+    const ScenePar &P = D.par[s];
+    int c[3];
+    decode_cell(P, D.f_lin[i], c);
+    double4 o = D.f_off[i];
+    double off[3] = {o.x, o.y, o.z};
+    if (!renormalise<DIM>(P, c, off)) atomicOr(&D.st[s].err, (int)ERR_NAN_FLUID);
+    int lin = encode_cell(P, c);
+    D.fs_lin[i] = lin;
+    D.fs_off[i] = make_double4(off[0], off[1], off[2], 0.0);
+    D.fs_slot[i] = atomicAdd(&D.fc_count[P.cell_begin + lin], 1);
+    D.fs_va[i] = D.f_va[i];
+    D.fs_drho[i] = D.f_drho[i];
+    D.fs_id[i] = D.f_id[i];
+    D.fs_m[i] = D.f_pos[i].w;
+    return;
+  }
+  int q = t - D.nf;
   if (q >= D.nb) return;
   int s = D.bs_scene[q];
-  if (!D.st[s].rebuilding) return;
+  if (!D.st[s].need_rebuild) return;
   const ScenePar &P = D.par[s];
   int local = q - P.b_begin;
   int c[3];
-  double off[3];
+  double off[3] = {0.0, 0.0, 0.0};
   int NS = D.ns;
   if (local < P.w_count) {
     int w = P.w_begin + local;
@@ -430,7 +417,6 @@ __global__ void __launch_bounds__(256) k_bnd_bin(Dev D) {
   } else {
     int a = P.s_begin + (local - P.w_count);
     decode_cell(P, D.s_lin0[a], c);
-    off[0] = off[1] = off[2] = 0.0;
     for (int k = 0; k < DIM; ++k) off[k] = D.s_off0[k * NS + a] + D.s_u[k * NS + a];
     if (!renormalise<DIM>(P, c, off)) atomicOr(&D.st[s].err, (int)ERR_NAN_SOLID);
   }
@@ -440,13 +426,25 @@ __global__ void __launch_bounds__(256) k_bnd_bin(Dev D) {
   D.bs_slot[q] = atomicAdd(&D.bc_count[P.cell_begin + lin], 1);
 }
 
-// Exclusive scan of the cell counts of one rebuilding scene in Morton order
-// (one block per scene), giving each cell's [start, end); counts are reset.
+// One block per rebuilding scene: advection time step (Section 3.2,
+// dt_ad = cfl_ad min(h / max(|v|max, U_ref), h^2 rho0 / eta)), then an
+// exclusive scan of the cell counts in Morton order giving each cell's
+// [start, end); counts are reset for the next rebuild.
 __global__ void __launch_bounds__(1024) k_scan_cells(Dev D) {
   __shared__ int sf[1024], sb[1024];
   int s = blockIdx.x;
-  if (!D.st[s].rebuilding) return;
+  SceneState &S = D.st[s];
+  if (!S.need_rebuild) return;
   const ScenePar &P = D.par[s];
+  if (threadIdx.x == 0) {
+    double vm = fmax((double)__uint_as_float(S.vmax_prev), (double)P.u_ref);
+    double dt = (double)P.cfl_ad * (double)P.hf / vm;
+    if (P.dt_visc > 0.0) dt = fmin(dt, P.dt_visc);
+    S.dt_ad = dt;
+    S.adv_accum = 0.0;
+    S.rebuilds += 1;
+    S.n_ff = S.n_fw = S.n_fs = 0;
+  }
   int n = P.ncell_total, cb = P.cell_begin;
   int T = blockDim.x, t = threadIdx.x;
   int chunk = (n + T - 1) / T;
@@ -482,82 +480,27 @@ __global__ void __launch_bounds__(1024) k_scan_cells(Dev D) {
   }
 }
 
-__global__ void k_fluid_scatter(Dev D) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= D.nf) return;
-  int s = D.f_scene[i];
-  if (!D.st[s].rebuilding) return;
-  const ScenePar &P = D.par[s];
-  D.f_perm[D.fc_se[P.cell_begin + D.fs_lin[i]].x + D.fs_slot[i]] = i;
-}
-
-__global__ void k_bnd_scatter(Dev D) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_scatter(Dev D) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < D.nf) {
+    int s = D.f_scene[t];
+    if (!D.st[s].need_rebuild) return;
+    D.f_perm[D.fc_se[D.par[s].cell_begin + D.fs_lin[t]].x + D.fs_slot[t]] = t;
+    return;
+  }
+  int q = t - D.nf;
   if (q >= D.nb) return;
   int s = D.bs_scene[q];
-  if (!D.st[s].rebuilding) return;
-  const ScenePar &P = D.par[s];
-  D.b_perm[D.bc_se[P.cell_begin + D.bs_lin[q]].x + D.bs_slot[q]] = q;
+  if (!D.st[s].need_rebuild) return;
+  D.b_perm[D.bc_se[D.par[s].cell_begin + D.bs_lin[q]].x + D.bs_slot[q]] = q;
 }
 
-// Deterministic order inside each cell: by original index (fluid) and by
-// source index (walls, then solid).  Insertion sort; cells hold a handful.
-__global__ void k_cell_sort(Dev D) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= D.ncell) return;
-  int s = D.cell_scene[c];
-  if (!D.st[s].rebuilding) return;
-  int2 se = D.fc_se[c];
-  for (int k = se.x + 1; k < se.y; ++k) {
-    int v = D.f_perm[k];
-    int key = D.fs_id[v];
-    int j = k - 1;
-    while (j >= se.x && D.fs_id[D.f_perm[j]] > key) {
-      D.f_perm[j + 1] = D.f_perm[j];
-      --j;
-    }
-    D.f_perm[j + 1] = v;
-  }
-  int2 be = D.bc_se[c];
-  for (int k = be.x + 1; k < be.y; ++k) {
-    int v = D.b_perm[k];
-    int j = k - 1;
-    while (j >= be.x && D.b_perm[j] > v) {
-      D.b_perm[j + 1] = D.b_perm[j];
-      --j;
-    }
-    D.b_perm[j + 1] = v;
-  }
-}
-
-__global__ void __launch_bounds__(256) k_fluid_gather(Dev D) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= D.nf) return;
-  int s = D.f_scene[k];
-  if (!D.st[s].rebuilding) return;
-  int o = D.f_perm[k];
-  double4 off = D.fs_off[o];
-  D.f_lin[k] = D.fs_lin[o];
-  D.f_id[k] = D.fs_id[o];
-  D.f_pos[k] = make_float4((float)off.x, (float)off.y, (float)off.z, D.fs_m[o]);
-  D.f_posd[k] = off;
-  D.f_off[k] = off;
-  D.f_va[k] = D.fs_va[o];
-  D.f_drho[k] = D.fs_drho[o];
-}
-
-// Boundary particles in cell order: frozen offset, volume, averaged velocity
+// Boundary particle in its cell slot: frozen offset, volume, averaged velocity
 // with the hydrostatic factor max(0, (abar - g).n), normal.  For the solid the
 // normal is updated from the deformation (n = normalise(F^-T n0)) and the
 // current volume is V0 det F.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_bnd_gather(Dev D) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= D.nb) return;
-  int s = D.bs_scene[k];
-  if (!D.st[s].rebuilding) return;
-  const ScenePar &P = D.par[s];
-  int q = D.b_perm[k];
+__device__ void gather_boundary(const Dev &D, const ScenePar &P, int k, int q) {
   int local = q - P.b_begin;
   double4 off = D.bs_off[q];
   int NS = D.ns;
@@ -572,25 +515,20 @@ __global__ void __launch_bounds__(256) k_bnd_gather(Dev D) {
     Vref = P.Vf;
   } else {
     int a = P.s_begin + (local - P.w_count);
-    float H[9], Fi[9];
-    for (int c = 0; c < DIM * DIM; ++c) H[c] = (float)D.s_H[c * NS + a];
-    float J;
+    double H[9], Fi[9];
+    for (int c = 0; c < DIM * DIM; ++c) H[c] = D.s_H[c * NS + a];
+    double J;
     if (DIM == 2) {
-      float f00 = 1.0f + H[0], f01 = H[1], f10 = H[2], f11 = 1.0f + H[3];
-      J = 1.0f + (H[0] + H[3] + (H[0] * H[3] - H[1] * H[2]));
-      // F^-T = (1/J) [[f11, -f10], [-f01, f00]]
-      Fi[0] = f11;
-      Fi[1] = -f10;
-      Fi[2] = -f01;
-      Fi[3] = f00;
+      // F^-T = (1/J) [[f11, -f10], [-f01, f00]]; the 1/J drops out of the normalisation
+      J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
+      Fi[0] = 1.0 + H[3];
+      Fi[1] = -H[2];
+      Fi[2] = -H[1];
+      Fi[3] = 1.0 + H[0];
     } else {
-      float F[9];
-      for (int c = 0; c < 9; ++c) F[c] = H[c] + ((c % 4 == 0) ? 1.0f : 0.0f);
-      float tr = H[0] + H[4] + H[8];
-      float m2 = (H[0] * H[4] - H[1] * H[3]) + (H[0] * H[8] - H[2] * H[6]) + (H[4] * H[8] - H[5] * H[7]);
-      float d3 = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
-                 H[2] * (H[3] * H[7] - H[4] * H[6]);
-      J = 1.0f + tr + m2 + d3;
+      double F[9];
+      for (int c = 0; c < 9; ++c) F[c] = H[c] + ((c % 4 == 0) ? 1.0 : 0.0);
+      J = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) + F[2] * (F[3] * F[7] - F[4] * F[6]);
       // cofactor matrix = J F^-T
       Fi[0] = F[4] * F[8] - F[5] * F[7];
       Fi[1] = F[5] * F[6] - F[3] * F[8];
@@ -602,23 +540,23 @@ __global__ void __launch_bounds__(256) k_bnd_gather(Dev D) {
       Fi[7] = F[2] * F[3] - F[0] * F[5];
       Fi[8] = F[0] * F[4] - F[1] * F[3];
     }
-    float n0[3] = {0.0f, 0.0f, 0.0f};
+    double n0[3] = {0.0, 0.0, 0.0}, nn[3] = {0.0, 0.0, 0.0};
     for (int c = 0; c < DIM; ++c) n0[c] = D.s_n0[c * NS + a];
-    float l2 = 0.0f;
+    double l2 = 0.0;
     for (int i = 0; i < DIM; ++i) {
-      float v = 0.0f;
+      double v = 0.0;
       for (int j = 0; j < DIM; ++j) v += Fi[i * DIM + j] * n0[j];
-      n[i] = v;
+      nn[i] = v;
       l2 += v * v;
     }
-    float inv = l2 > 0.0f ? rsqrtf(l2) : 0.0f;
+    double inv = l2 > 0.0 ? 1.0 / sqrt(l2) : 0.0;
     for (int i = 0; i < DIM; ++i) {
-      n[i] *= inv;
+      n[i] = (float)(nn[i] * inv);
       D.s_n[i * NS + a] = n[i];
       vb[i] = D.s_vbar[i * NS + a];
       ab[i] = D.s_abar[i * NS + a];
     }
-    V = P.Vs * J;
+    V = (float)(P.Vs * J);
     Vref = -P.Vs;
     D.s_bslot[a] = k;
     D.s_blin[a] = D.bs_lin[q];
@@ -632,33 +570,78 @@ __global__ void __launch_bounds__(256) k_bnd_gather(Dev D) {
   D.b_nrm[k] = make_float4(n[0], n[1], n[2], Vref);
 }
 
-// Wave-level add of a per-scene counter (lanes of one wave almost always
-// share the scene).
-__device__ __forceinline__ void scene_add_u64(unsigned long long *ctr, int s, unsigned long long v, bool active) {
-  int s0 = __shfl(s, 0);
-  bool uniform = __all(s == s0 || !active);
-  if (uniform) {
-    unsigned long long tot = active ? v : 0ull;
-    for (int off = 32; off > 0; off >>= 1) tot += __shfl_down(tot, off);
-    if (threadIdx.x % 64 == 0 && tot) atomicAdd(ctr + 0, tot);
-  } else if (active && v) {
-    atomicAdd(ctr, v);
+// One thread per cell of a rebuilding scene: order the cell's particles by
+// original index (fluid) and by source index (walls, then solid) so that the
+// layout does not depend on atomic arrival order, then gather their state.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_sort_gather(Dev D) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D.ncell) return;
+  int s = D.cell_scene[c];
+  if (!D.st[s].need_rebuild) return;
+  const ScenePar &P = D.par[s];
+  int2 se = D.fc_se[c];
+  for (int k = se.x + 1; k < se.y; ++k) {
+    int v = D.f_perm[k];
+    int key = D.fs_id[v];
+    int j = k - 1;
+    while (j >= se.x && D.fs_id[D.f_perm[j]] > key) {
+      D.f_perm[j + 1] = D.f_perm[j];
+      --j;
+    }
+    D.f_perm[j + 1] = v;
   }
+  for (int k = se.x; k < se.y; ++k) {
+    int o = D.f_perm[k];
+    double4 off = D.fs_off[o];
+    D.f_lin[k] = D.fs_lin[o];
+    D.f_id[k] = D.fs_id[o];
+    D.f_pos[k] = make_float4((float)off.x, (float)off.y, (float)off.z, D.fs_m[o]);
+    D.f_posd[k] = off;
+    D.f_off[k] = off;
+    D.f_va[k] = D.fs_va[o];
+    D.f_drho[k] = D.fs_drho[o];
+  }
+  int2 be = D.bc_se[c];
+  for (int k = be.x + 1; k < be.y; ++k) {
+    int v = D.b_perm[k];
+    int j = k - 1;
+    while (j >= be.x && D.b_perm[j] > v) {
+      D.b_perm[j + 1] = D.b_perm[j];
+      --j;
+    }
+    D.b_perm[j + 1] = v;
+  }
+  for (int k = be.x; k < be.y; ++k) gather_boundary<DIM>(D, P, k, D.b_perm[k]);
 }
+
+// Sum over a group of LPP consecutive lanes (a power of two dividing 64).
+template <int LPP, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  for (int m = 1; m < LPP; m <<= 1) v += __shfl_xor(v, m, LPP);
+  return v;
+}
+
+// Pair loops: LPP lanes share one particle; each lane takes every LPP-th
+// candidate of each neighbouring cell, and the partial sums are combined
+// with cross-lane shuffles.  More lanes per particle keep small scenes'
+// waves busy while their loads are in flight.
 
 // Density reinitialisation and pair counts at the start of an advection step
 // (Algorithm 1).  psi_i = sum_j V_ref,j W_ij over fluid (self included), walls
 // and free solid; mode 1: rho = rho0 max(1, psi/psi0); mode 2: rho =
 // max(rho, rho0 psi/psi0).  The pair counts feed the interaction counters.
 // The sum is an FP64 island: the pressure that follows is rho0 c^2 times the
-// relative excess of psi, so FP32 rounding of W would appear as pressure
-// noise; distances are formed in FP64 from the stored FP32 offsets.
-template <int DIM>
+// relative excess of psi, so FP32 rounding of W or of positions would appear
+// as pressure noise; distances come from the FP64 frozen offsets.
+template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_reinit(Dev D) {
-  int i = particle_index();
+  int g = particle_index();
+  int i = g / LPP, q = g % LPP;
   bool active = i < D.nf;
   int s = active ? D.f_scene[i] : 0;
-  if (active && !D.st[s].rebuilding) active = false;
+  if (active && !D.st[s].need_rebuild) active = false;
+  double psi = 0.0;
   unsigned long long nff = 0, nfw = 0, nfs = 0;
   if (active) {
     const ScenePar &P = D.par[s];
@@ -666,20 +649,20 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
     double4 qi = D.f_posd[i];
     const double h = P.hf, inv_h = 1.0 / h;
     const double alpha = DIM == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
-    const double Vf = DIM == 2 ? (double)P.dpf * P.dpf : (double)P.dpf * P.dpf * P.dpf;
-    const double Vs = DIM == 2 ? (double)P.dps * P.dps : (double)P.dps * P.dps * P.dps;
+    const double Vf = DIM == 2 ? P.dpf * P.dpf : P.dpf * P.dpf * P.dpf;
+    const double Vs = DIM == 2 ? P.dps * P.dps : P.dps * P.dps * P.dps;
     auto W64 = [&](double r) {
-      double q = r * inv_h, t = fmax(0.0, 1.0 - 0.5 * q);
-      return alpha * t * t * t * t * (1.0 + 2.0 * q);
+      double qq = r * inv_h, t = fmax(0.0, 1.0 - 0.5 * qq);
+      return alpha * t * t * t * t * (1.0 + 2.0 * qq);
     };
-    double psi = Vf * alpha;
+    if (q == 0) psi = Vf * alpha;
     int cb = P.cell_begin;
     visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh) {
       // the same cell offset in FP64 (sh is an exact multiple of the FP32 cell size)
       double shd[3];
       for (int k = 0; k < 3; ++k) shd[k] = (double)(sh[k] / P.cs[k]) * P.csd[k];
       int2 se = D.fc_se[cb + nl];
-      for (int j = se.x; j < se.y; ++j) {
+      for (int j = se.x + q; j < se.y; j += LPP) {
         if (j == i) continue;
         float4 pj = D.f_pos[j];
         // pair membership decided in FP32 exactly as in the force passes
@@ -694,7 +677,7 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         nff++;
       }
       int2 be = D.bc_se[cb + nl];
-      for (int k = be.x; k < be.y; ++k) {
+      for (int k = be.x + q; k < be.y; k += LPP) {
         float4 pb = D.b_pos[k];
         float rx = (pi.x - pb.x) - sh[0], ry = (pi.y - pb.y) - sh[1];
         float rz = DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f;
@@ -709,7 +692,15 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         else nfs++;
       }
     });
-    D.f_nnb[i] = make_int2((int)nff, (int)(nfw + nfs));
+  }
+  psi = group_sum<LPP>(psi);
+  nff = group_sum<LPP>(nff);
+  nfw = group_sum<LPP>(nfw);
+  nfs = group_sum<LPP>(nfs);
+  bool lead = active && q == 0;
+  if (lead) {
+    const ScenePar &P = D.par[s];
+    D.f_nnb[i] = make_int4((int)nff, (int)nfw, (int)nfs, 0);
     if (P.reinit) {
       float4 va = D.f_va[i];
       double e = psi / P.psi0d - 1.0;
@@ -717,10 +708,6 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
       D.f_va[i] = va;
     }
   }
-  SceneState *S = &D.st[s];
-  scene_add_u64(&S->n_ff, s, nff, active);
-  scene_add_u64(&S->n_fw, s, nfw, active);
-  scene_add_u64(&S->n_fs, s, nfs, active);
 }
 
 // ------------------------------------------------------------------ fluid step
@@ -729,18 +716,20 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
 // verlet-first-mediate; Section 3.1 momentum): half step of density (kept as
 // eps) and position, Riemann pressure and viscous forces from fluid
 // neighbours, coupling forces from walls and solid, gravity, full step of
-// velocity.  Writes (v^{n+1}, eps^{n+1/2}), the mid-point pressure and the
-// acceleration; v^n stays in f_va for the coupling and continuity passes.
-template <int DIM>
+// velocity.  Writes (v^{n+1}, eps^{n+1/2}), the mid-point snapshot
+// (v^n, eps^{n+1/2}), pressure and acceleration.
+template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
-  int i = particle_index();
-  if (i >= D.nf) return;
-  int s = D.f_scene[i];
+  int g = particle_index();
+  int i = g / LPP, q = g % LPP;
+  bool active = i < D.nf;
+  int ii = active ? i : 0;
+  int s = D.nf > 0 ? D.f_scene[ii] : 0;
   const ScenePar &P = D.par[s];
   float dt = (float)D.st[s].dt_ac;
-  float4 pi = D.f_pos[i];
-  float4 va = D.f_va[i];
-  float ehi = va.w + 0.5f * dt * D.f_drho[i];
+  float4 pi = D.f_pos[ii];
+  float4 va = D.f_va[ii];
+  float ehi = va.w + 0.5f * dt * D.f_drho[ii];
   float rhoi = P.rho0 * (1.0f + ehi);
   float p_i = eos_p(ehi, P);
   float mi = pi.w;
@@ -748,41 +737,45 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
   float vi[3] = {va.x, va.y, va.z};
   float fsum[3] = {0.0f, 0.0f, 0.0f};
   int cb = P.cell_begin;
-  visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh) {
-    int2 se = D.fc_se[cb + nl];
-    for (int j = se.x; j < se.y; ++j) {
-      if (j == i) continue;
-      float4 pj = D.f_pos[j];
-      float r[3] = {(pi.x - pj.x) - sh[0], (pi.y - pj.y) - sh[1], DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f};
-      float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-      if (r2 >= P.r2max_f) continue;
-      float4 vj4 = D.f_va[j];
-      float ehj = vj4.w + 0.5f * dt * D.f_drho[j];
-      float rhoj = P.rho0 * (1.0f + ehj);
-      float p_j = eos_p(ehj, P);
-      float Vj = pj.w / rhoj;
-      float rr = sqrtf(r2);
-      float inv_r = 1.0f / rr;
-      float e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
-      float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
-      float vj[3] = {vj4.x, vj4.y, vj4.z};
-      float Ps = riemann_pressure<DIM>(P, rhoi, rhoj, p_i, p_j, vi, vj, e);
-      float VV = Vi * Vj * dW;
-      float cpress = -2.0f * VV * Ps;
-      float cvisc = 2.0f * P.eta * VV * inv_r;
-      for (int k = 0; k < DIM; ++k) fsum[k] += cpress * e[k] + cvisc * (vi[k] - vj[k]);
-    }
-    int2 be = D.bc_se[cb + nl];
-    for (int k = be.x; k < be.y; ++k) {
-      float4 pb = D.b_pos[k];
-      float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
-      float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-      if (r2 >= P.r2max_f) continue;
-      float f[3];
-      coupling_force<DIM>(P, mi, ehi, p_i, vi, r, pb, D.b_vbar[k], D.b_nrm[k], f);
-      for (int q = 0; q < DIM; ++q) fsum[q] += f[q];
-    }
-  });
+  if (active) {
+    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh) {
+      int2 se = D.fc_se[cb + nl];
+      for (int j = se.x + q; j < se.y; j += LPP) {
+        if (j == i) continue;
+        float4 pj = D.f_pos[j];
+        float r[3] = {(pi.x - pj.x) - sh[0], (pi.y - pj.y) - sh[1], DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f};
+        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (r2 >= P.r2max_f) continue;
+        float4 vj4 = D.f_va[j];
+        float ehj = vj4.w + 0.5f * dt * D.f_drho[j];
+        float rhoj = P.rho0 * (1.0f + ehj);
+        float p_j = eos_p(ehj, P);
+        float Vj = pj.w / rhoj;
+        float rr = sqrtf(r2);
+        float inv_r = 1.0f / rr;
+        float e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
+        float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
+        float vj[3] = {vj4.x, vj4.y, vj4.z};
+        float Ps = riemann_pressure<DIM>(P, rhoi, rhoj, p_i, p_j, vi, vj, e);
+        float VV = Vi * Vj * dW;
+        float cpress = -2.0f * VV * Ps;
+        float cvisc = 2.0f * P.eta * VV * inv_r;
+        for (int k = 0; k < DIM; ++k) fsum[k] += cpress * e[k] + cvisc * (vi[k] - vj[k]);
+      }
+      int2 be = D.bc_se[cb + nl];
+      for (int k = be.x + q; k < be.y; k += LPP) {
+        float4 pb = D.b_pos[k];
+        float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
+        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (r2 >= P.r2max_f) continue;
+        float f[3];
+        coupling_force<DIM>(P, mi, ehi, p_i, vi, r, pb, D.b_vbar[k], D.b_nrm[k], f);
+        for (int c = 0; c < DIM; ++c) fsum[c] += f[c];
+      }
+    });
+  }
+  for (int k = 0; k < DIM; ++k) fsum[k] = group_sum<LPP>(fsum[k]);
+  if (!active || q != 0) return;
   float a[3] = {0.0f, 0.0f, 0.0f}, vn[3] = {vi[0], vi[1], vi[2]};
   for (int k = 0; k < DIM; ++k) {
     a[k] = fsum[k] / mi + P.g[k];
@@ -803,22 +796,24 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
 // Force of the fluid on each free solid particle (Section 2.2, F:p and F:v at
 // h_F): the exact negatives of the fluid-side pair terms, from the same
 // mid-point snapshot (v^n, eps^{n+1/2}, p^{n+1/2}) and the same frozen geometry.
-template <int DIM>
+template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_couple(Dev D) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= D.ns) return;
-  int s = D.s_scene[a];
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  int a = g / LPP, q = g % LPP;
+  bool active = a < D.ns;
+  int aa = active ? a : 0;
+  int s = D.ns > 0 ? D.s_scene[aa] : 0;
   const ScenePar &P = D.par[s];
   int NS = D.ns;
-  int local = a - P.s_begin;
+  int local = aa - P.s_begin;
   float fa[3] = {0.0f, 0.0f, 0.0f};
-  int k = D.s_bslot[a];
-  if (local < P.s_count - P.s_nclamp && k >= 0) {
+  int k = active ? D.s_bslot[aa] : -1;
+  if (active && local < P.s_count - P.s_nclamp && k >= 0) {
     float4 pb = D.b_pos[k], bv = D.b_vbar[k], bn = D.b_nrm[k];
     int cb = P.cell_begin;
     visit_cells<DIM>(P, D.s_blin[a], [&](int nl, const float *sh) {
       int2 se = D.fc_se[cb + nl];
-      for (int i = se.x; i < se.y; ++i) {
+      for (int i = se.x + q; i < se.y; i += LPP) {
         float4 pi = D.f_pos[i];
         // same rounding as the fluid side's (p_i - p_b) - shift
         float r[3] = {(pi.x - pb.x) + sh[0], (pi.y - pb.y) + sh[1], DIM == 3 ? (pi.z - pb.z) + sh[2] : 0.0f};
@@ -828,11 +823,13 @@ __global__ void __launch_bounds__(256) k_couple(Dev D) {
         float vi[3] = {vs.x, vs.y, vs.z};
         float f[3];
         coupling_force<DIM>(P, pi.w, vs.w, D.f_p[i], vi, r, pb, bv, bn, f);
-        for (int q = 0; q < DIM; ++q) fa[q] -= f[q];
+        for (int c = 0; c < DIM; ++c) fa[c] -= f[c];
       }
     });
   }
-  for (int q = 0; q < DIM; ++q) D.s_fF[q * NS + a] = fa[q];
+  for (int c = 0; c < DIM; ++c) fa[c] = group_sum<LPP>(fa[c]);
+  if (active && q == 0)
+    for (int c = 0; c < DIM; ++c) D.s_fF[c * NS + a] = fa[c];
 }
 
 // Fluid acoustic step, second part (Section 3.1 continuity with the Riemann
@@ -840,27 +837,27 @@ __global__ void __launch_bounds__(256) k_couple(Dev D) {
 // v^{n+1} at the mid-point density, plus rho_i sum_a V_a (v_i - vbar_a).grad W
 // for walls and solid; second half step of position and density; inflow
 // buffer; max speed for the next acoustic step.
-template <int DIM>
+template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
-  int i = particle_index();
+  int g = particle_index();
+  int i = g / LPP, q = g % LPP;
   bool active = i < D.nf;
-  int s = active ? D.f_scene[i] : 0;
-  float speed = 0.0f;
+  int ii = active ? i : 0;
+  int s = D.nf > 0 ? D.f_scene[ii] : 0;
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  float4 pi = D.f_pos[ii];
+  float4 vb = D.f_vb[ii];
+  float ehi = vb.w;
+  float rhoi = P.rho0 * (1.0f + ehi);
+  float p_i = D.f_p[ii];
+  float vi[3] = {vb.x, vb.y, vb.z};
+  float drho = 0.0f;
+  int cb = P.cell_begin;
   if (active) {
-    const ScenePar &P = D.par[s];
-    SceneState &S = D.st[s];
-    float dt = (float)S.dt_ac;
-    float4 pi = D.f_pos[i];
-    float4 vb = D.f_vb[i];
-    float ehi = vb.w;
-    float rhoi = P.rho0 * (1.0f + ehi);
-    float p_i = D.f_p[i];
-    float vi[3] = {vb.x, vb.y, vb.z};
-    float drho = 0.0f;
-    int cb = P.cell_begin;
     visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh) {
       int2 se = D.fc_se[cb + nl];
-      for (int j = se.x; j < se.y; ++j) {
+      for (int j = se.x + q; j < se.y; j += LPP) {
         if (j == i) continue;
         float4 pj = D.f_pos[j];
         float r[3] = {(pi.x - pj.x) - sh[0], (pi.y - pj.y) - sh[1], DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f};
@@ -878,7 +875,7 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
         drho += 2.0f * rhoi * Vj * riemann_dv_dot_e<DIM>(P, rhoi, rhoj, p_i, p_j, vi, vj, e) * dW;
       }
       int2 be = D.bc_se[cb + nl];
-      for (int k = be.x; k < be.y; ++k) {
+      for (int k = be.x + q; k < be.y; k += LPP) {
         float4 pb = D.b_pos[k];
         float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
         float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -891,6 +888,12 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
         drho += rhoi * pb.w * (dv / rr) * dW;
       }
     });
+  }
+  drho = group_sum<LPP>(drho);
+  bool lead = active && q == 0;
+  float speed = 0.0f;
+  if (lead) {
+    float dt = (float)S.dt_ac;
     float de = drho / P.rho0;
     float enew = ehi + 0.5f * dt * de;
     double4 off = D.f_off[i];
@@ -917,21 +920,14 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
     D.f_va[i] = make_float4(vi[0], vi[1], vi[2], enew);
     D.f_drho[i] = de;
     speed = sqrtf(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
+    D.f_speed[i] = speed;
     if (!(isfinite(speed) && isfinite(enew))) atomicOr(&S.err, (int)ERR_NAN_FLUID);
-  }
-  // per-scene max speed: one atomic per wave when the wave is in one scene
-  int s0 = __shfl(s, 0);
-  bool uniform = __all(s == s0 || !active);
-  if (uniform) {
-    float m = active ? speed : 0.0f;
-    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_down(m, off));
-    if (threadIdx.x % 64 == 0 && m > 0.0f) atomic_max_pos(&D.st[s0].vmax_next, m);
-  } else if (active) {
-    atomic_max_pos(&D.st[s].vmax_next, speed);
   }
 }
 
 // ------------------------------------------------------------------ solid sub-steps
+
+constexpr int KAPPA_MAX = 4096;
 
 // kappa solid sub-steps of the position-based Verlet scheme (Section 3.3,
 // Eqs. verlet-*-solid) for one scene per block, the fluid force held constant:
@@ -942,11 +938,14 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
 // floor(dt_ac / dt_S) + 1 equal sub-steps summing to dt_ac.  Afterwards the
 // averages vbar = du / dt_ac and abar = dv / dt_ac over the acoustic step
 // (Section 3.2) are handed to the boundary particles, and thread 0 closes the
-// acoustic step (time, advection accumulator, next dt_ac, counters).
-constexpr int KAPPA_MAX = 4096;
-
-template <int DIM>
-__global__ void __launch_bounds__(1024) k_solid(Dev D) {
+// acoustic step (time, advection accumulator, rebuild flag, next dt_ac,
+// counters).  The solid arithmetic is an FP64 island: the acceleration is a
+// second difference of the displacement and amplifies rounding noise at the
+// particle scale.  With LDS, the exchanged fields (v, P B) of the scene live
+// in shared memory for the whole launch.
+template <int DIM, bool LDS>
+__global__ void __launch_bounds__(1024) k_solid(Dev D, int lds_n) {
+  extern __shared__ double smem[];
   __shared__ float red[2][1024];
   __shared__ int kap_sh;
   __shared__ double del_sh;
@@ -956,6 +955,11 @@ __global__ void __launch_bounds__(1024) k_solid(Dev D) {
   const int NS = D.ns;
   const int base = P.s_begin, n = P.s_count, nfree = P.s_count - P.s_nclamp;
   const int T = blockDim.x, t = threadIdx.x;
+  // exchanged fields: in LDS indexed by scene-local index, else in global memory
+  double *PBx = LDS ? smem : D.s_PB;
+  double *Vx = LDS ? smem + DIM * DIM * lds_n : D.s_v;
+  const int xs = LDS ? lds_n : NS;
+  const int xo = LDS ? base : 0;
   double dt_ac = S.dt_ac;
   float vm = 0.0f, am = 0.0f;
   for (int l = t; l < nfree; l += T) {
@@ -1006,45 +1010,60 @@ __global__ void __launch_bounds__(1024) k_solid(Dev D) {
     for (int k = 0; k < DIM; ++k) {
       D.s_du[k * NS + a] = 0.0;
       D.s_dv[k * NS + a] = 0.0;
+      if (LDS) Vx[k * xs + (a - xo)] = D.s_v[k * NS + a];
     }
     if (l >= nfree)
-      for (int k = 0; k < DIM * DIM; ++k) D.s_PB[k * NS + a] = 0.0;
+      for (int k = 0; k < DIM * DIM; ++k) PBx[k * xs + (a - xo)] = 0.0;
   }
-  for (int sub = 0; sub < kap; ++sub) {
-    // first half: F, u; Neo-Hookean stress
-    for (int l = t; l < nfree; l += T) {
-      int a = base + l;
-      double H[9], B[9], PB[9];
-      for (int k = 0; k < DIM * DIM; ++k) {
-        H[k] = D.s_H[k * NS + a] + hd * D.s_dF[k * NS + a];
-        D.s_H[k * NS + a] = H[k];
-        B[k] = D.s_B[k * NS + a];
-      }
-      for (int k = 0; k < DIM; ++k) {
-        double inc = hd * D.s_v[k * NS + a];
-        D.s_u[k * NS + a] += inc;
-        D.s_du[k * NS + a] += inc;
-      }
-      double J;
-      nh_PB<DIM, double>(H, B, (double)P.mu, (double)P.lam, PB, J);
-      if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
-      for (int k = 0; k < DIM * DIM; ++k) D.s_PB[k * NS + a] = PB[k];
+  __syncthreads();
+  // Sub-step loop.  The first half-step and stress of sub-step k+1 run in the
+  // same pass as the deformation rate and second half of sub-step k (they touch
+  // only the particle's own state), so each sub-step has two barriers.
+  auto first_half = [&](int a, double *H, double *dF, double *u) {
+    double B[9], PB[9];
+    for (int k = 0; k < DIM * DIM; ++k) {
+      H[k] += hd * dF[k];
+      B[k] = D.s_B[k * NS + a];
     }
-    __syncthreads();
+    for (int k = 0; k < DIM; ++k) {
+      double inc = hd * Vx[k * xs + (a - xo)];
+      u[k] += inc;
+      D.s_du[k * NS + a] += inc;
+    }
+    double J;
+    nh_PB<DIM, double>(H, B, (double)P.mu, (double)P.lam, PB, J);
+    if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
+    for (int k = 0; k < DIM * DIM; ++k) PBx[k * xs + (a - xo)] = PB[k];
+  };
+  for (int l = t; l < nfree; l += T) {
+    int a = base + l;
+    double H[9], dF[9], u[3];
+    for (int k = 0; k < DIM * DIM; ++k) {
+      H[k] = D.s_H[k * NS + a];
+      dF[k] = D.s_dF[k * NS + a];
+    }
+    for (int k = 0; k < DIM; ++k) u[k] = D.s_u[k * NS + a];
+    first_half(a, H, dF, u);
+    for (int k = 0; k < DIM * DIM; ++k) D.s_H[k * NS + a] = H[k];
+    for (int k = 0; k < DIM; ++k) D.s_u[k * NS + a] = u[k];
+  }
+  __syncthreads();
+  for (int sub = 0; sub < kap; ++sub) {
     // momentum, velocity
     for (int l = t; l < nfree; l += T) {
       int a = base + l;
       double PBa[9];
-      for (int k = 0; k < DIM * DIM; ++k) PBa[k] = D.s_PB[k * NS + a];
+      for (int k = 0; k < DIM * DIM; ++k) PBa[k] = PBx[k * xs + (a - xo)];
       double acc[3] = {0.0, 0.0, 0.0};
       int cnt = D.s_cnt[a];
+#pragma unroll 4
       for (int q = 0; q < cnt; ++q) {
         float4 g = D.s_nbr[(size_t)q * NS + a];
-        int b = __float_as_int(g.w);
+        int b = __float_as_int(g.w) - xo;
         double gv[3] = {g.x, g.y, g.z};
         for (int i = 0; i < DIM; ++i) {
           double sum = 0.0;
-          for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + D.s_PB[(i * DIM + j) * NS + b]) * gv[j];
+          for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + PBx[(i * DIM + j) * xs + b]) * gv[j];
           acc[i] += sum;
         }
       }
@@ -1052,40 +1071,52 @@ __global__ void __launch_bounds__(1024) k_solid(Dev D) {
         double ak = ((double)P.Vs * acc[k] + (double)D.s_fF[k * NS + a]) * m_inv + (double)P.g[k];
         D.s_a[k * NS + a] = (float)ak;
         double dv = del * ak;
-        D.s_v[k * NS + a] += dv;
+        Vx[k * xs + (a - xo)] += dv;
         D.s_dv[k * NS + a] += dv;
       }
     }
     __syncthreads();
-    // deformation rate with the new velocity, second half
+    // deformation rate with the new velocity, second half; then the next
+    // sub-step's first half and stress
+    const bool more = sub + 1 < kap;
     for (int l = t; l < nfree; l += T) {
       int a = base + l;
       double va[3] = {0.0, 0.0, 0.0};
-      for (int k = 0; k < DIM; ++k) va[k] = D.s_v[k * NS + a];
+      for (int k = 0; k < DIM; ++k) va[k] = Vx[k * xs + (a - xo)];
       double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
       int cnt = D.s_cnt[a];
+#pragma unroll 4
       for (int q = 0; q < cnt; ++q) {
         float4 g = D.s_nbr[(size_t)q * NS + a];
-        int b = __float_as_int(g.w);
+        int b = __float_as_int(g.w) - xo;
         double gv[3] = {g.x, g.y, g.z};
         for (int i = 0; i < DIM; ++i) {
-          double dvi = D.s_v[i * NS + b] - va[i];
+          double dvi = Vx[i * xs + b] - va[i];
           for (int j = 0; j < DIM; ++j) G[i * DIM + j] += dvi * gv[j];
         }
       }
+      double H[9], dF[9], u[3];
+      for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
+      for (int k = 0; k < DIM; ++k) u[k] = D.s_u[k * NS + a];
       // (v_b - v_a) (x) (B grad W) summed = G B^T
       for (int i = 0; i < DIM; ++i)
         for (int j = 0; j < DIM; ++j) {
           double sum = 0.0;
           for (int k = 0; k < DIM; ++k) sum += G[i * DIM + k] * D.s_B[(j * DIM + k) * NS + a];
-          D.s_dF[(i * DIM + j) * NS + a] = sum;
-          D.s_H[(i * DIM + j) * NS + a] += hd * sum;
+          dF[i * DIM + j] = sum;
+          H[i * DIM + j] += hd * sum;
         }
       for (int k = 0; k < DIM; ++k) {
         double inc = hd * va[k];
-        D.s_u[k * NS + a] += inc;
+        u[k] += inc;
         D.s_du[k * NS + a] += inc;
       }
+      if (more) first_half(a, H, dF, u);
+      for (int k = 0; k < DIM * DIM; ++k) {
+        D.s_H[k * NS + a] = H[k];
+        D.s_dF[k * NS + a] = dF[k];
+      }
+      for (int k = 0; k < DIM; ++k) D.s_u[k * NS + a] = u[k];
     }
     __syncthreads();
   }
@@ -1093,6 +1124,8 @@ __global__ void __launch_bounds__(1024) k_solid(Dev D) {
   const double inv_dt = 1.0 / dt_ac;
   for (int l = t; l < nfree; l += T) {
     int a = base + l;
+    if (LDS)
+      for (int k = 0; k < DIM; ++k) D.s_v[k * NS + a] = Vx[k * xs + (a - xo)];
     float vbar[3] = {0.0f, 0.0f, 0.0f}, abar[3] = {0.0f, 0.0f, 0.0f}, nn[3] = {0.0f, 0.0f, 0.0f};
     bool bad = false;
     for (int k = 0; k < DIM; ++k) {
@@ -1121,16 +1154,60 @@ __global__ void __launch_bounds__(1024) k_solid(Dev D) {
       D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
     }
   }
+  // max fluid speed of the scene (next acoustic step) and, after a rebuild,
+  // the scene's pair counts, reduced from per-particle values
+  {
+    const bool rebuilt = S.need_rebuild != 0;
+    float m = 0.0f;
+    unsigned long long cff = 0, cfw = 0, cfs = 0;
+    for (int l = t; l < P.f_count; l += T) {
+      int i = P.f_begin + l;
+      m = fmaxf(m, D.f_speed[i]);
+      if (rebuilt) {
+        int4 c = D.f_nnb[i];
+        cff += c.x;
+        cfw += c.y;
+        cfs += c.z;
+      }
+    }
+    __syncthreads();
+    red[0][t] = m;
+    __syncthreads();
+    for (int w = T / 2; w > 0; w >>= 1) {
+      if (t < w) red[0][t] = fmaxf(red[0][t], red[0][t + w]);
+      __syncthreads();
+    }
+    if (rebuilt) {
+      // 64-bit sums through the LDS of the float buffer (reused as integers)
+      unsigned long long *ured = reinterpret_cast<unsigned long long *>(&red[1][0]);
+      for (int which = 0; which < 3; ++which) {
+        unsigned long long v = which == 0 ? cff : (which == 1 ? cfw : cfs);
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+        __syncthreads();
+        if ((t & 63) == 0) ured[t >> 6] = v;
+        __syncthreads();
+        if (t == 0) {
+          unsigned long long tot = 0;
+          for (int w = 0; w < (T + 63) / 64; ++w) tot += ured[w];
+          if (which == 0) S.n_ff = tot;
+          else if (which == 1) S.n_fw = tot;
+          else S.n_fs = tot;
+        }
+      }
+      __syncthreads();
+    }
+    if (t == 0) S.vmax_next = __float_as_uint(red[0][0]);
+  }
   if (t == 0) {
+    bool rebuilt = S.need_rebuild != 0;  // the rebuild kernels of this step ran
     unsigned long long inter = 2ull * (S.n_ff + S.n_fw + S.n_fs) + S.n_fs + 2ull * (unsigned long long)kap * S.n_ss;
-    if (S.rebuilding && P.reinit) inter += S.n_ff + S.n_fw + S.n_fs;
+    if (rebuilt && P.reinit) inter += S.n_ff + S.n_fw + S.n_fs;
     S.interactions += inter;
     S.substeps += kap;
     S.steps += 1;
     S.t += dt_ac;
     S.adv_accum += dt_ac;
-    if (S.adv_accum >= S.dt_ad) S.need_rebuild = 1;
-    S.rebuilding = 0;
+    S.need_rebuild = S.adv_accum >= S.dt_ad ? 1 : 0;
     float vmax = __uint_as_float(S.vmax_next);
     S.vmax_prev = S.vmax_next;
     S.vmax_next = 0u;
@@ -1164,9 +1241,9 @@ __global__ void k_read_fluid(Dev D, int s, int field, double *out) {
   } break;
   case 5: out[id] = D.f_p[i]; break;
   case 6: {
-    int2 c = D.f_nnb[i];
+    int4 c = D.f_nnb[i];
     out[2 * (size_t)id] = c.x;
-    out[2 * (size_t)id + 1] = c.y;
+    out[2 * (size_t)id + 1] = c.y + c.z;
   } break;
   }
 }
@@ -1198,6 +1275,7 @@ __global__ void k_write_fluid(Dev D, int s, int field, const double *in) {
     v.y = (float)in[(size_t)DIM * id + 1];
     if (DIM == 3) v.z = (float)in[(size_t)DIM * id + 2];
     D.f_va[i] = v;
+    D.f_speed[i] = sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
   } break;
   case 2: {
     float4 v = D.f_va[i];
@@ -1411,34 +1489,70 @@ void launch_refresh_vmax(const Dev &D, hipStream_t st) {
   hipLaunchKernelGGL(k_refresh_vmax, dim3(D.n_scenes), dim3(256), 0, st, D);
 }
 
+#define LAUNCH_LPP(kern, lpp, dim, grid, block, stream, ...)                                    \
+  do {                                                                                         \
+    switch (lpp) {                                                                             \
+    case 1: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 1>), grid, block, 0, stream, __VA_ARGS__);  \
+            else hipLaunchKernelGGL((kern<3, 1>), grid, block, 0, stream, __VA_ARGS__); break;       \
+    case 2: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 2>), grid, block, 0, stream, __VA_ARGS__);  \
+            else hipLaunchKernelGGL((kern<3, 2>), grid, block, 0, stream, __VA_ARGS__); break;       \
+    case 4: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 4>), grid, block, 0, stream, __VA_ARGS__);  \
+            else hipLaunchKernelGGL((kern<3, 4>), grid, block, 0, stream, __VA_ARGS__); break;       \
+    case 8: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 8>), grid, block, 0, stream, __VA_ARGS__);  \
+            else hipLaunchKernelGGL((kern<3, 8>), grid, block, 0, stream, __VA_ARGS__); break;       \
+    default: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 16>), grid, block, 0, stream, __VA_ARGS__); \
+            else hipLaunchKernelGGL((kern<3, 16>), grid, block, 0, stream, __VA_ARGS__); break;      \
+    }                                                                                          \
+  } while (0)
+
+static inline dim3 grid_for(long long threads, int block) {
+  return dim3((unsigned)std::max<long long>(1, (threads + block - 1) / block));
+}
+
 void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
-  hipLaunchKernelGGL(k_rebuild_begin, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
-  if (D.nf > 0) LAUNCH_DIM(D.dim, k_fluid_bin, dim3(nblk(D.nf, 256)), dim3(256), st, D);
-  if (D.nb > 0) LAUNCH_DIM(D.dim, k_bnd_bin, dim3(nblk(D.nb, 256)), dim3(256), st, D);
+  if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_bin, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
   hipLaunchKernelGGL(k_scan_cells, dim3(D.n_scenes), dim3(1024), 0, st, D);
-  if (D.nf > 0) hipLaunchKernelGGL(k_fluid_scatter, dim3(nblk(D.nf, 256)), dim3(256), 0, st, D);
-  if (D.nb > 0) hipLaunchKernelGGL(k_bnd_scatter, dim3(nblk(D.nb, 256)), dim3(256), 0, st, D);
-  hipLaunchKernelGGL(k_cell_sort, dim3(nblk(D.ncell, 256)), dim3(256), 0, st, D);
-  if (D.nf > 0) hipLaunchKernelGGL(k_fluid_gather, dim3(nblk(D.nf, 256)), dim3(256), 0, st, D);
-  if (D.nb > 0) LAUNCH_DIM(D.dim, k_bnd_gather, dim3(nblk(D.nb, 256)), dim3(256), st, D);
-  if (D.nf > 0) LAUNCH_DIM(D.dim, k_reinit, dim3(nblk(D.nf, cfg.block_pair)), dim3(cfg.block_pair), st, D);
+  if (D.nf + D.nb > 0) hipLaunchKernelGGL(k_scatter, grid_for(D.nf + D.nb, 256), dim3(256), 0, st, D);
+  LAUNCH_DIM(D.dim, k_sort_gather, grid_for(D.ncell, 256), dim3(256), st, D);
+  if (D.nf > 0)
+    LAUNCH_LPP(k_reinit, cfg.lpp_reinit, D.dim, grid_for((long long)D.nf * cfg.lpp_reinit, cfg.block_pair),
+               dim3(cfg.block_pair), st, D);
 }
 
 void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
-  if (D.nf > 0) LAUNCH_DIM(D.dim, k_fluid_force, dim3(nblk(D.nf, cfg.block_pair)), dim3(cfg.block_pair), st, D);
+  if (D.nf > 0)
+    LAUNCH_LPP(k_fluid_force, cfg.lpp_force, D.dim, grid_for((long long)D.nf * cfg.lpp_force, cfg.block_pair),
+               dim3(cfg.block_pair), st, D);
 }
 
 void launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   if (D.nf > 0)
-    LAUNCH_DIM(D.dim, k_fluid_continuity, dim3(nblk(D.nf, cfg.block_pair)), dim3(cfg.block_pair), st, D);
+    LAUNCH_LPP(k_fluid_continuity, cfg.lpp_cont, D.dim, grid_for((long long)D.nf * cfg.lpp_cont, cfg.block_pair),
+               dim3(cfg.block_pair), st, D);
 }
 
 void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
-  if (D.ns > 0) LAUNCH_DIM(D.dim, k_couple, dim3(nblk(D.ns, cfg.block_couple)), dim3(cfg.block_couple), st, D);
+  if (D.ns > 0)
+    LAUNCH_LPP(k_couple, cfg.lpp_couple, D.dim, grid_for((long long)D.ns * cfg.lpp_couple, cfg.block_couple),
+               dim3(cfg.block_couple), st, D);
 }
 
 void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
-  LAUNCH_DIM(D.dim, k_solid, dim3(D.n_scenes), dim3(cfg.block_solid), st, D);
+  if (cfg.solid_lds_n > 0) {
+    size_t bytes = (size_t)cfg.solid_lds_n * (D.dim * D.dim + D.dim) * sizeof(double);
+    if (D.dim == 2) hipLaunchKernelGGL((k_solid<2, true>), dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
+    else hipLaunchKernelGGL((k_solid<3, true>), dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
+  } else {
+    if (D.dim == 2) hipLaunchKernelGGL((k_solid<2, false>), dim3(D.n_scenes), dim3(cfg.block_solid), 0, st, D, 0);
+    else hipLaunchKernelGGL((k_solid<3, false>), dim3(D.n_scenes), dim3(cfg.block_solid), 0, st, D, 0);
+  }
+}
+
+int solid_lds_bytes_per_particle(int dim) { return (dim * dim + dim) * (int)sizeof(double); }
+
+hipError_t allow_solid_lds(int dim, size_t bytes) {
+  if (dim == 2) return hipFuncSetAttribute((const void *)k_solid<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return hipFuncSetAttribute((const void *)k_solid<3, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t st) {

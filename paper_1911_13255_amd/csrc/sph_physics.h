@@ -88,7 +88,7 @@ __device__ __forceinline__ float riemann_dv_dot_e(const ScenePar &P, float rho_i
 // The solid side calls the same function with the same arguments and takes
 // the negative; FP contraction is off so that both sides round identically.
 template <int DIM>
-__device__ __attribute__((noinline)) void coupling_force(const ScenePar &P, float m_i, float eh_i, float p_i,
+__device__ __forceinline__ void coupling_force(const ScenePar &P, float m_i, float eh_i, float p_i,
                                                         const float *v_i, const float *rv, float4 bpos,
                                                         float4 bvbar, float4 bnrm, float *f) {
 #pragma clang fp contract(off)

@@ -49,7 +49,7 @@ struct ScenePar {
 
 struct SceneState {
   double t, dt_ac, dt_ad, dt_s, adv_accum;
-  int kappa, need_rebuild, rebuilding, err;
+  int kappa, need_rebuild, pad2, err;
   unsigned int vmax_prev, vmax_next;  // max fluid speed (float bits): step start / being reduced
   unsigned int pad0, pad1;
   unsigned long long n_ff, n_fw, n_fs, n_ss;  // pairs within support at the last rebuild
@@ -75,7 +75,8 @@ struct Dev {
   float4 *f_acc;   // acceleration of the last step
   float *f_drho;   // d eps / dt kept for the next half step
   float *f_p;      // mid-step pressure
-  int2 *f_nnb;     // fluid and boundary neighbours within 2 h_F at the last rebuild
+  int4 *f_nnb;     // fluid, wall and solid neighbours within 2 h_F at the last rebuild
+  float *f_speed;  // |v| after the last continuity pass (reduced per scene by the solid kernel)
   // fluid rebuild scratch (indexed by the old sorted index)
   int *fs_lin, *fs_slot, *fs_id, *f_perm;
   double4 *fs_off;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libmrsph.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "mrsph.h")
 
 SPH_OK, SPH_E_ARG, SPH_E_HIP, SPH_E_ORDER, SPH_E_CAPACITY, SPH_E_UNSTABLE = 0, -1, -2, -3, -4, -5
+K_FLUID_FORCE, K_CONTINUITY, K_COUPLE, K_SOLID, K_REBUILD = 0, 1, 2, 3, 4
 F_X, F_V, F_RHO, F_DRHO, F_A, F_P, F_NNB = 0, 1, 2, 3, 4, 5, 6
 S_U, S_V, S_A, S_F, S_DF, S_FF, S_VBAR, S_ABAR, S_N, S_B, S_N0, S_X0 = range(10, 22)
 FLUID_FIELDS = {F_X, F_V, F_RHO, F_DRHO, F_A, F_P, F_NNB}
@@ -53,7 +54,8 @@ class SphScene(C.Structure):
 
 class SphOptions(C.Structure):
     _fields_ = [("riemann", C.c_int), ("density_reinit", C.c_int), ("max_solid_nbr", C.c_int),
-                ("solid_block", C.c_int)]
+                ("solid_block", C.c_int), ("lanes_per_particle", C.c_int), ("block_pair", C.c_int),
+                ("solid_lds", C.c_int)]
 
 
 def exported_names():
@@ -88,6 +90,7 @@ def lib():
         L.sph_set_scalars.argtypes = [vp, C.c_int, _dp]
         L.sph_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
         L.sph_reduce.argtypes = [vp, C.c_int, _dp]
+        L.sph_time_kernel.argtypes = [vp, C.c_int, C.c_int, _dp]
         L.sph_last_error.restype = C.c_char_p
         L.sph_last_error.argtypes = [vp]
         L.sph_destroy.argtypes = [vp]
@@ -130,7 +133,8 @@ class Simulation:
     """One or more scenes on one GPU, advanced by the library's kernels."""
 
     def __init__(self, scenes, riemann: bool = True, density_reinit: int = 1,
-                 max_solid_nbr: int = 0, solid_block: int = 0, device: int = 0):
+                 max_solid_nbr: int = 0, solid_block: int = 0, lanes_per_particle: int = 0,
+                 block_pair: int = 0, solid_lds: int = 0, device: int = 0):
         import torch
 
         if isinstance(scenes, dict):
@@ -147,7 +151,8 @@ class Simulation:
             arr[i] = st
             self._keep.append(keep)
         self._scenes = arr
-        self.opt = SphOptions(int(riemann), int(density_reinit), int(max_solid_nbr), int(solid_block))
+        self.opt = SphOptions(int(riemann), int(density_reinit), int(max_solid_nbr), int(solid_block),
+                              int(lanes_per_particle), int(block_pair), int(solid_lds))
         nbytes = self.L.sph_arena_bytes(arr, self.n_scenes, C.byref(self.opt))
         if nbytes == 0:
             raise SphError(SPH_E_ARG, "invalid scene description")
@@ -241,6 +246,12 @@ class Simulation:
         return dict(mom_fluid=out[0:3].copy(), mom_solid=out[3:6].copy(), ke_fluid=out[6],
                     ke_solid=out[7], strain_energy=out[8], sum_fF=out[9:12].copy(),
                     sum_fS=out[12:15].copy())
+
+    def time_kernel(self, kernel: int, reps: int = 100) -> float:
+        """Average milliseconds per launch of one kernel (HIP events on the stream)."""
+        out = C.c_double()
+        self._check(self.L.sph_time_kernel(self.ctx, int(kernel), int(reps), C.byref(out)))
+        return out.value
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -32,7 +32,7 @@ def test_arena_bytes_and_argument_checks():
     sc = scenes.dam_break_plate(seed=1)
     st, keep = sph.scene_struct(sc)
     arr = (sph.SphScene * 1)(st)
-    opt = sph.SphOptions(1, 1, 0, 0)
+    opt = sph.SphOptions(1, 1, 0, 0, 0, 0, 0)
     n1 = L.sph_arena_bytes(arr, 1, ctypes.byref(opt))
     assert n1 > 0
     # more scenes need more memory
