@@ -212,15 +212,30 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
     max_solid_scene = std::max(max_solid_scene, S.n_solid);
     P.par.push_back(p);
   }
+  int max_free_scene = 0;
+  for (int s = 0; s < n; ++s) max_free_scene = std::max(max_free_scene, sc[s].n_solid - sc[s].n_clamp);
   int bs = o.solid_block;
-  if (bs <= 0) {
-    bs = 64;
-    while (bs < max_solid_scene && bs < 1024) bs *= 2;
-  }
-  if (bs < 64 || bs > 1024 || (bs & (bs - 1))) {
+  if (bs != 0 && (bs < 64 || bs > 1024 || (bs & (bs - 1)))) {
     err = "solid_block must be a power of two in [64, 1024]";
     return false;
   }
+  // register-resident solid kernel (2D) when every scene's free solid fits
+  // 2048 particles (at most 2 per thread); otherwise the LDS or global variant
+  P.cfg.solid_ppt = 0;
+  if (o.solid_lds != 1 && P.dim == 2 && max_free_scene > 0 && max_free_scene <= 2048) {
+    // block limits of the register-resident kernel: 1024, 640, 512 threads
+    int ppt = max_free_scene <= 1024 ? 1 : (max_free_scene <= 1280 ? 2 : 4);
+    int limit = ppt == 1 ? 1024 : (ppt == 2 ? 640 : 512);
+    P.cfg.solid_ppt = ppt;
+    int need = (max_free_scene + ppt - 1) / ppt;
+    int want = std::max(64, (need + 63) / 64 * 64);
+    if (bs == 0 || bs > limit) bs = std::min(limit, want);
+  }
+  if (bs == 0) {
+    bs = 64;
+    while (bs < max_solid_scene && bs < 1024) bs *= 2;
+  }
+  if (P.cfg.solid_ppt && (long long)bs * P.cfg.solid_ppt < max_free_scene) P.cfg.solid_ppt = 0;
   P.cfg.block_solid = bs;
   // lanes per particle: enough lanes in flight to keep about eight waves per CU
   auto pick_lpp = [](long long nparticles) {
@@ -406,9 +421,16 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
     size_t need_lds = (size_t)ctx->cfg.solid_lds_n * solid_lds_bytes_per_particle(P.dim);
     // the kernel's own shared arrays take 8 KiB + a few bytes
     if (ctx->cfg.solid_lds_n <= 0 || need_lds + 9 * 1024 > (size_t)lds_max ||
-        allow_solid_lds(P.dim, need_lds) != hipSuccess) {
+        allow_solid_lds(P.dim, ctx->cfg.solid_ppt, need_lds) != hipSuccess) {
       ctx->cfg.solid_lds_n = 0;
+      ctx->cfg.solid_ppt = 0;
       (void)hipGetLastError();
+    }
+    // the global-memory variant needs a power-of-two block for its reductions
+    if (ctx->cfg.solid_ppt == 0) {
+      int bs = 64;
+      while (bs < ctx->cfg.block_solid) bs *= 2;
+      ctx->cfg.block_solid = std::min(bs, 1024);
     }
   }
   ctx->graph_failed = 0;

@@ -12,6 +12,7 @@ struct LaunchCfg {
   int block_solid;   // threads per scene of the solid sub-step kernel
   int lpp_force, lpp_cont, lpp_couple, lpp_reinit;  // lanes per particle (1, 2, 4, 8, 16)
   int solid_lds_n;   // solid particles per scene held in LDS (0: exchanged fields in global memory)
+  int solid_ppt;     // > 0: register-resident solid kernel with this many particles per thread
 };
 
 void launch_init_scene(const Dev &D, int s, const double *x_f, const double *v_f, int has_vf, double gabs,
@@ -32,6 +33,6 @@ void launch_write(const Dev &D, int s, int field, int n, const double *in, hipSt
 void launch_reduce(const Dev &D, int s, int nblocks, double *out, hipStream_t st);
 void launch_set_rebuild(const Dev &D, int s, hipStream_t st);
 int solid_lds_bytes_per_particle(int dim);
-hipError_t allow_solid_lds(int dim, size_t bytes);
+hipError_t allow_solid_lds(int dim, int ppt, size_t bytes);
 
 }  // namespace mrsph

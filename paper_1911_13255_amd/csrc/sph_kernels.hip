@@ -28,6 +28,13 @@ __device__ __forceinline__ int xcd_block() {
 
 __device__ __forceinline__ int particle_index() { return xcd_block() * blockDim.x + threadIdx.x; }
 
+// smallest power of two >= n (block-wide tree reductions over any block size)
+__device__ __forceinline__ int pow2_ceil(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
 __device__ __forceinline__ int wrapi(int n, int N) { return n < 0 ? n + N : (n >= N ? n - N : n); }
 
 __device__ __forceinline__ void decode_cell(const ScenePar &P, int lin, int *c) {
@@ -929,6 +936,74 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
 
 constexpr int KAPPA_MAX = 4096;
 
+// End of an acoustic step for one scene (whole block): max fluid speed for the
+// next acoustic step and, after a rebuild, the scene's pair counts, both
+// reduced from per-particle values; then thread 0 closes the step (time,
+// advection accumulator, rebuild flag, next dt_ac, counters).
+__device__ void solid_step_end(const Dev &D, const ScenePar &P, SceneState &S, float (*red)[1024], int kap,
+                               double dt_ac, int t, int T) {
+  // max fluid speed of the scene (next acoustic step) and, after a rebuild,
+  // the scene's pair counts, reduced from per-particle values
+  {
+    const bool rebuilt = S.need_rebuild != 0;
+    float m = 0.0f;
+    unsigned long long cff = 0, cfw = 0, cfs = 0;
+    for (int l = t; l < P.f_count; l += T) {
+      int i = P.f_begin + l;
+      m = fmaxf(m, D.f_speed[i]);
+      if (rebuilt) {
+        int4 c = D.f_nnb[i];
+        cff += c.x;
+        cfw += c.y;
+        cfs += c.z;
+      }
+    }
+    __syncthreads();
+    red[0][t] = m;
+    __syncthreads();
+    for (int w = pow2_ceil(T) / 2; w > 0; w >>= 1) {
+      if (t < w && t + w < T) red[0][t] = fmaxf(red[0][t], red[0][t + w]);
+      __syncthreads();
+    }
+    if (rebuilt) {
+      // 64-bit sums through the LDS of the float buffer (reused as integers)
+      unsigned long long *ured = reinterpret_cast<unsigned long long *>(&red[1][0]);
+      for (int which = 0; which < 3; ++which) {
+        unsigned long long v = which == 0 ? cff : (which == 1 ? cfw : cfs);
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+        __syncthreads();
+        if ((t & 63) == 0) ured[t >> 6] = v;
+        __syncthreads();
+        if (t == 0) {
+          unsigned long long tot = 0;
+          for (int w = 0; w < (T + 63) / 64; ++w) tot += ured[w];
+          if (which == 0) S.n_ff = tot;
+          else if (which == 1) S.n_fw = tot;
+          else S.n_fs = tot;
+        }
+      }
+      __syncthreads();
+    }
+    if (t == 0) S.vmax_next = __float_as_uint(red[0][0]);
+  }
+  if (t == 0) {
+    bool rebuilt = S.need_rebuild != 0;  // the rebuild kernels of this step ran
+    unsigned long long inter = 2ull * (S.n_ff + S.n_fw + S.n_fs) + S.n_fs + 2ull * (unsigned long long)kap * S.n_ss;
+    if (rebuilt && P.reinit) inter += S.n_ff + S.n_fw + S.n_fs;
+    S.interactions += inter;
+    S.substeps += kap;
+    S.steps += 1;
+    S.t += dt_ac;
+    S.adv_accum += dt_ac;
+    S.need_rebuild = S.adv_accum >= S.dt_ad ? 1 : 0;
+    float vmax = __uint_as_float(S.vmax_next);
+    S.vmax_prev = S.vmax_next;
+    S.vmax_next = 0u;
+    S.dt_ac = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)vmax);
+  }
+}
+
+
 // kappa solid sub-steps of the position-based Verlet scheme (Section 3.3,
 // Eqs. verlet-*-solid) for one scene per block, the fluid force held constant:
 //   F += dt/2 dF/dt;  u += dt/2 v;  P B from the Neo-Hookean stress;
@@ -976,8 +1051,8 @@ __global__ void __launch_bounds__(1024) k_solid(Dev D, int lds_n) {
   red[0][t] = vm;
   red[1][t] = am;
   __syncthreads();
-  for (int w = T / 2; w > 0; w >>= 1) {
-    if (t < w) {
+  for (int w = pow2_ceil(T) / 2; w > 0; w >>= 1) {
+    if (t < w && t + w < T) {
       red[0][t] = fmaxf(red[0][t], red[0][t + w]);
       red[1][t] = fmaxf(red[1][t], red[1][t + w]);
     }
@@ -1154,65 +1229,252 @@ __global__ void __launch_bounds__(1024) k_solid(Dev D, int lds_n) {
       D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
     }
   }
-  // max fluid speed of the scene (next acoustic step) and, after a rebuild,
-  // the scene's pair counts, reduced from per-particle values
-  {
-    const bool rebuilt = S.need_rebuild != 0;
-    float m = 0.0f;
-    unsigned long long cff = 0, cfw = 0, cfs = 0;
-    for (int l = t; l < P.f_count; l += T) {
-      int i = P.f_begin + l;
-      m = fmaxf(m, D.f_speed[i]);
-      if (rebuilt) {
-        int4 c = D.f_nnb[i];
-        cff += c.x;
-        cfw += c.y;
-        cfs += c.z;
-      }
+  solid_step_end(D, P, S, red, kap, dt_ac, t, T);
+}
+
+// The same sub-steps for 2D scenes whose free solid fits the block with at
+// most PPT particles per thread: each thread keeps its particles' own state
+// (H, dF/dt, u in FP64; B and the step increments in FP32) in registers for
+// the whole launch, v and P B of the scene live in LDS, and only the fixed
+// reference neighbour table is read from (L2-resident) global memory inside
+// the sub-step loop.
+// Block limits keep the register budget: 1024 threads for one particle per
+// thread, 640 for two, 512 for four.
+template <int DIM, int PPT>
+__global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_solid_reg(Dev D, int lds_n) {
+  extern __shared__ double smem[];
+  __shared__ float red[2][1024];
+  __shared__ int kap_sh;
+  __shared__ double del_sh;
+  constexpr int D2 = DIM * DIM;
+  int s = blockIdx.x;
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  const int NS = D.ns;
+  const int base = P.s_begin, n = P.s_count, nfree = P.s_count - P.s_nclamp;
+  const int T = blockDim.x, t = threadIdx.x;
+  double *PBx = smem;
+  double *Vx = smem + D2 * lds_n;
+  double dt_ac = S.dt_ac;
+  // own particles and their state
+  int la[PPT];
+  bool own[PPT];
+  double H[PPT][D2], dF[PPT][D2], u[PPT][DIM];
+  float B[PPT][D2], du[PPT][DIM], dv[PPT][DIM], fF[PPT][DIM], acc_last[PPT][DIM];
+  float vm = 0.0f, am = 0.0f;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    la[p] = t + p * T;
+    own[p] = la[p] < nfree;
+    int a = base + (own[p] ? la[p] : 0);
+    float v2 = 0.0f, a2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D2; ++k) {
+      H[p][k] = own[p] ? D.s_H[k * NS + a] : 0.0;
+      dF[p][k] = own[p] ? D.s_dF[k * NS + a] : 0.0;
+      B[p][k] = own[p] ? (float)D.s_B[k * NS + a] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      u[p][k] = own[p] ? D.s_u[k * NS + a] : 0.0;
+      du[p][k] = 0.0f;
+      dv[p][k] = 0.0f;
+      fF[p][k] = own[p] ? D.s_fF[k * NS + a] : 0.0f;
+      float vv = own[p] ? (float)D.s_v[k * NS + a] : 0.0f, q = own[p] ? D.s_a[k * NS + a] : 0.0f;
+      acc_last[p][k] = q;
+      v2 += vv * vv;
+      a2 += q * q;
+    }
+    vm = fmaxf(vm, sqrtf(v2));
+    am = fmaxf(am, sqrtf(a2));
+  }
+  red[0][t] = vm;
+  red[1][t] = am;
+  for (int l = t; l < n; l += T) {
+    int a = base + l;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) Vx[k * lds_n + l] = D.s_v[k * NS + a];
+    if (l >= nfree)
+#pragma unroll
+      for (int k = 0; k < D2; ++k) PBx[k * lds_n + l] = 0.0;
+  }
+  __syncthreads();
+  for (int w = pow2_ceil(T) / 2; w > 0; w >>= 1) {
+    if (t < w && t + w < T) {
+      red[0][t] = fmaxf(red[0][t], red[0][t + w]);
+      red[1][t] = fmaxf(red[1][t], red[1][t + w]);
     }
     __syncthreads();
-    red[0][t] = m;
-    __syncthreads();
-    for (int w = T / 2; w > 0; w >>= 1) {
-      if (t < w) red[0][t] = fmaxf(red[0][t], red[0][t + w]);
-      __syncthreads();
-    }
-    if (rebuilt) {
-      // 64-bit sums through the LDS of the float buffer (reused as integers)
-      unsigned long long *ured = reinterpret_cast<unsigned long long *>(&red[1][0]);
-      for (int which = 0; which < 3; ++which) {
-        unsigned long long v = which == 0 ? cff : (which == 1 ? cfw : cfs);
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
-        __syncthreads();
-        if ((t & 63) == 0) ured[t >> 6] = v;
-        __syncthreads();
-        if (t == 0) {
-          unsigned long long tot = 0;
-          for (int w = 0; w < (T + 63) / 64; ++w) tot += ured[w];
-          if (which == 0) S.n_ff = tot;
-          else if (which == 1) S.n_fw = tot;
-          else S.n_fs = tot;
-        }
-      }
-      __syncthreads();
-    }
-    if (t == 0) S.vmax_next = __float_as_uint(red[0][0]);
   }
   if (t == 0) {
-    bool rebuilt = S.need_rebuild != 0;  // the rebuild kernels of this step ran
-    unsigned long long inter = 2ull * (S.n_ff + S.n_fw + S.n_fs) + S.n_fs + 2ull * (unsigned long long)kap * S.n_ss;
-    if (rebuilt && P.reinit) inter += S.n_ff + S.n_fw + S.n_fs;
-    S.interactions += inter;
-    S.substeps += kap;
-    S.steps += 1;
-    S.t += dt_ac;
-    S.adv_accum += dt_ac;
-    S.need_rebuild = S.adv_accum >= S.dt_ad ? 1 : 0;
-    float vmax = __uint_as_float(S.vmax_next);
-    S.vmax_prev = S.vmax_next;
-    S.vmax_next = 0u;
-    S.dt_ac = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)vmax);
+    double dts = (double)P.cfl_s * (double)P.hs / ((double)P.c_s + (double)red[0][0]);
+    if (red[1][0] > 0.0f) dts = fmin(dts, (double)P.cfl_s * sqrt((double)P.hs / (double)red[1][0]));
+    double ratio = dt_ac / dts;
+    int kap;
+    if (!(ratio >= 0.0) || !(dt_ac > 0.0) || ratio > (double)(KAPPA_MAX - 1)) {
+      kap = (ratio >= 0.0 && dt_ac > 0.0) ? KAPPA_MAX : 1;
+      atomicOr(&S.err, (int)ERR_NAN_SOLID);
+    } else {
+      kap = (int)floor(ratio) + 1;
+    }
+    kap_sh = kap;
+    del_sh = dt_ac / kap;
+    S.dt_s = dts;
+    S.kappa = kap;
   }
+  __syncthreads();
+  const int kap = kap_sh;
+  const double del = del_sh;
+  const double hd = 0.5 * del;
+  const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
+  bool bad_J = false;
+  auto first_half = [&](int p) {
+    double PB[D2], Bd[D2];
+#pragma unroll
+    for (int k = 0; k < D2; ++k) {
+      H[p][k] += hd * dF[p][k];
+      Bd[k] = B[p][k];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      double inc = hd * Vx[k * lds_n + la[p]];
+      u[p][k] += inc;
+      du[p][k] += (float)inc;
+    }
+    double J;
+    nh_PB<DIM, double>(H[p], Bd, (double)P.mu, (double)P.lam, PB, J);
+    bad_J |= !(J > 0.0);
+#pragma unroll
+    for (int k = 0; k < D2; ++k) PBx[k * lds_n + la[p]] = PB[k];
+  };
+#pragma unroll
+  for (int p = 0; p < PPT; ++p)
+    if (own[p]) first_half(p);
+  __syncthreads();
+  for (int sub = 0; sub < kap; ++sub) {
+    // momentum, velocity
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      if (!own[p]) continue;
+      int l = la[p], a = base + l;
+      double PBa[D2];
+#pragma unroll
+      for (int k = 0; k < D2; ++k) PBa[k] = PBx[k * lds_n + l];
+      double acc[3] = {0.0, 0.0, 0.0};
+      int cnt = D.s_cnt[a];
+#pragma unroll 8
+      for (int q = 0; q < cnt; ++q) {
+        float4 g = D.s_nbr[(size_t)q * NS + a];
+        int b = __float_as_int(g.w) - base;
+        double gv[3] = {g.x, g.y, g.z};
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+          double sum = 0.0;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + PBx[(i * DIM + j) * lds_n + b]) * gv[j];
+          acc[i] += sum;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        double ak = ((double)P.Vs * acc[k] + (double)fF[p][k]) * m_inv + (double)P.g[k];
+        acc_last[p][k] = (float)ak;
+        double d_v = del * ak;
+        Vx[k * lds_n + l] += d_v;
+        dv[p][k] += (float)d_v;
+      }
+    }
+    __syncthreads();
+    // deformation rate with the new velocity, second half; then the next
+    // sub-step's first half and stress
+    const bool more = sub + 1 < kap;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      if (!own[p]) continue;
+      int l = la[p], a = base + l;
+      double va[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) va[k] = Vx[k * lds_n + l];
+      double G[D2];
+#pragma unroll
+      for (int k = 0; k < D2; ++k) G[k] = 0.0;
+      int cnt = D.s_cnt[a];
+#pragma unroll 8
+      for (int q = 0; q < cnt; ++q) {
+        float4 g = D.s_nbr[(size_t)q * NS + a];
+        int b = __float_as_int(g.w) - base;
+        double gv[3] = {g.x, g.y, g.z};
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+          double dvi = Vx[i * lds_n + b] - va[i];
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) G[i * DIM + j] += dvi * gv[j];
+        }
+      }
+      // (v_b - v_a) (x) (B grad W) summed = G B^T
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          double sum = 0.0;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) sum += G[i * DIM + k] * (double)B[p][j * DIM + k];
+          dF[p][i * DIM + j] = sum;
+          H[p][i * DIM + j] += hd * sum;
+        }
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        double inc = hd * va[k];
+        u[p][k] += inc;
+        du[p][k] += (float)inc;
+      }
+      if (more) first_half(p);
+    }
+    __syncthreads();
+  }
+  if (bad_J) atomicOr(&S.err, (int)ERR_JACOBIAN);
+  // write back, time averages, hand-over to the boundary particles
+  const double inv_dt = 1.0 / dt_ac;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    if (!own[p]) continue;
+    int l = la[p], a = base + l;
+    float vbar[3] = {0.0f, 0.0f, 0.0f}, abar[3] = {0.0f, 0.0f, 0.0f};
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < D2; ++k) {
+      D.s_H[k * NS + a] = H[p][k];
+      D.s_dF[k * NS + a] = dF[p][k];
+    }
+    float sa = 0.0f;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      D.s_u[k * NS + a] = u[p][k];
+      D.s_v[k * NS + a] = Vx[k * lds_n + l];
+      D.s_a[k * NS + a] = acc_last[p][k];
+      vbar[k] = (float)((double)du[p][k] * inv_dt);
+      abar[k] = (float)((double)dv[p][k] * inv_dt);
+      D.s_vbar[k * NS + a] = vbar[k];
+      D.s_abar[k * NS + a] = abar[k];
+      sa += (abar[k] - P.g[k]) * D.s_n[k * NS + a];
+      bad |= !isfinite(vbar[k]) || !isfinite(abar[k]);
+    }
+    if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
+    int kslot = D.s_bslot[a];
+    if (kslot >= 0) {
+      double J;
+      if (DIM == 2) J = (1.0 + H[p][0]) * (1.0 + H[p][3]) - H[p][1] * H[p][2];
+      else
+        J = (1.0 + H[p][0]) * ((1.0 + H[p][4]) * (1.0 + H[p][8]) - H[p][5] * H[p][7]) -
+            H[p][1] * (H[p][3] * (1.0 + H[p][8]) - H[p][5] * H[p][6]) +
+            H[p][2] * (H[p][3] * H[p][7] - (1.0 + H[p][4]) * H[p][6]);
+      float4 bp = D.b_pos[kslot];
+      bp.w = (float)(P.Vs * J);
+      D.b_pos[kslot] = bp;
+      D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
+    }
+  }
+  solid_step_end(D, P, S, red, kap, dt_ac, t, T);
 }
 
 // ------------------------------------------------------------------ state I/O
@@ -1537,8 +1799,18 @@ void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
                dim3(cfg.block_couple), st, D);
 }
 
+#define LAUNCH_SOLID_REG(ppt, ...)                                                        \
+  do {                                                                                    \
+    if ((ppt) == 1) hipLaunchKernelGGL((k_solid_reg<2, 1>), __VA_ARGS__);                 \
+    else if ((ppt) == 2) hipLaunchKernelGGL((k_solid_reg<2, 2>), __VA_ARGS__);            \
+    else hipLaunchKernelGGL((k_solid_reg<2, 4>), __VA_ARGS__);                            \
+  } while (0)
+
 void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
-  if (cfg.solid_lds_n > 0) {
+  if (cfg.solid_ppt > 0 && cfg.solid_lds_n > 0 && D.dim == 2) {
+    size_t bytes = (size_t)cfg.solid_lds_n * (D.dim * D.dim + D.dim) * sizeof(double);
+    LAUNCH_SOLID_REG(cfg.solid_ppt, dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
+  } else if (cfg.solid_lds_n > 0) {
     size_t bytes = (size_t)cfg.solid_lds_n * (D.dim * D.dim + D.dim) * sizeof(double);
     if (D.dim == 2) hipLaunchKernelGGL((k_solid<2, true>), dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
     else hipLaunchKernelGGL((k_solid<3, true>), dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
@@ -1550,9 +1822,12 @@ void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
 
 int solid_lds_bytes_per_particle(int dim) { return (dim * dim + dim) * (int)sizeof(double); }
 
-hipError_t allow_solid_lds(int dim, size_t bytes) {
-  if (dim == 2) return hipFuncSetAttribute((const void *)k_solid<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  return hipFuncSetAttribute((const void *)k_solid<3, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+hipError_t allow_solid_lds(int dim, int ppt, size_t bytes) {
+  const void *f;
+  if (ppt == 0 || dim != 2) f = dim == 2 ? (const void *)k_solid<2, true> : (const void *)k_solid<3, true>;
+  else f = ppt == 1 ? (const void *)k_solid_reg<2, 1>
+                     : (ppt == 2 ? (const void *)k_solid_reg<2, 2> : (const void *)k_solid_reg<2, 4>);
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t st) {

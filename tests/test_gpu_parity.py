@@ -179,12 +179,14 @@ def test_teacher_forced_steps_dam_break(gpu):
     sim.close()
 
 
-@pytest.mark.parametrize("dim,eta", [(2, 0.0), (2, 2.0), (3, 0.5)])
-def test_periodic_box_with_free_solid(gpu, dim, eta):
-    # Wetted free solid from the first step: coupling forces, kappa > 1.
+@pytest.mark.parametrize("dim,eta,solid_lds", [(2, 0.0, 0), (2, 2.0, 0), (2, 2.0, 1), (3, 0.5, 0),
+                                               (3, 0.5, 1)])
+def test_periodic_box_with_free_solid(gpu, dim, eta, solid_lds):
+    # Wetted free solid from the first step: coupling forces, kappa > 1; both
+    # the register/LDS-resident and the global-memory solid kernels.
     sc = scenes.periodic_box_with_solid(dim=dim, n=16 if dim == 2 else 8, eta=eta, amp=0.3)
-    note(f"periodic box dim {dim} eta {eta}")
-    sim = sph.Simulation(sc)
+    note(f"periodic box dim {dim} eta {eta} solid_lds {solid_lds}")
+    sim = sph.Simulation(sc, solid_lds=solid_lds)
     o = O.Oracle(sc)
     for k in range(6):
         one_step(sim, o)
