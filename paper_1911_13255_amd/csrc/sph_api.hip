@@ -25,6 +25,8 @@ struct sph_ctx {
   hipGraph_t graph;
   hipGraphExec_t graph_exec;
   int graph_failed;
+  hipStream_t side;  // second stream for the concurrent continuity pass (graph capture only)
+  hipEvent_t ev_fork, ev_join;
   size_t stage_doubles;
   char err[512];
 };
@@ -292,6 +294,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.fs_slot, nf);
   take(D.fs_id, nf);
   take(D.f_perm, nf);
+  take(D.f_pkey, nf);
   take(D.fs_off, nf);
   take(D.fs_va, nf);
   take(D.fs_drho, nf);
@@ -374,12 +377,28 @@ int read_states(sph_ctx *ctx, std::vector<SceneState> &st) {
   return SPH_OK;
 }
 
-int enqueue_step(sph_ctx *ctx) {
+// One acoustic step.  With a second stream the continuity pass (which no
+// later pass of the step reads until the step-end kernel) runs concurrently
+// with the coupling and solid passes.
+int enqueue_step(sph_ctx *ctx, bool fork) {
   launch_rebuild(ctx->D, ctx->cfg, ctx->stream);
   launch_fluid_force(ctx->D, ctx->cfg, ctx->stream);
-  launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream);
-  launch_couple(ctx->D, ctx->cfg, ctx->stream);
-  launch_solid(ctx->D, ctx->cfg, ctx->stream);
+  if (fork && ctx->side) {
+    if (hipEventRecord(ctx->ev_fork, ctx->stream) != hipSuccess ||
+        hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0) != hipSuccess)
+      return SPH_E_HIP;
+    launch_fluid_continuity(ctx->D, ctx->cfg, ctx->side);
+    launch_couple(ctx->D, ctx->cfg, ctx->stream);
+    launch_solid(ctx->D, ctx->cfg, ctx->stream);
+    if (hipEventRecord(ctx->ev_join, ctx->side) != hipSuccess ||
+        hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0) != hipSuccess)
+      return SPH_E_HIP;
+  } else {
+    launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream);
+    launch_couple(ctx->D, ctx->cfg, ctx->stream);
+    launch_solid(ctx->D, ctx->cfg, ctx->stream);
+  }
+  launch_step_end(ctx->D, ctx->stream);
   return check_launch(ctx, "acoustic step");
 }
 
@@ -412,6 +431,17 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   ctx->cfg = P.cfg;
   ctx->graph = nullptr;
   ctx->graph_exec = nullptr;
+  ctx->side = nullptr;
+  ctx->ev_fork = ctx->ev_join = nullptr;
+  if (ctx->stream) {
+    // default priority, like every stream here
+    if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+      ctx->side = nullptr;
+      (void)hipGetLastError();
+    }
+  }
   {
     // the solid exchange fields go to LDS when the largest scene fits
     int dev = 0, lds_max = 0;
@@ -561,6 +591,7 @@ int couple(sph_ctx *ctx) {
 int solid_substeps(sph_ctx *ctx) {
   if (!ctx) return SPH_E_ORDER;
   launch_solid(ctx->D, ctx->cfg, ctx->stream);
+  launch_step_end(ctx->D, ctx->stream);
   return check_launch(ctx, "solid_substeps");
 }
 
@@ -571,7 +602,7 @@ int sph_advance(sph_ctx *ctx, int n_steps) {
     // capture one acoustic step; every decision inside it is taken on the device
     hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      enqueue_step(ctx);
+      enqueue_step(ctx, true);
       hipGraph_t g = nullptr;
       e = hipStreamEndCapture(ctx->stream, &g);
       if (e == hipSuccess && g) {
@@ -594,7 +625,7 @@ int sph_advance(sph_ctx *ctx, int n_steps) {
     if (ctx->graph_exec) {
       HIPCHK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
     } else {
-      int rc = enqueue_step(ctx);
+      int rc = enqueue_step(ctx, false);
       if (rc != SPH_OK) return rc;
     }
   }
@@ -756,6 +787,9 @@ void sph_destroy(sph_ctx *ctx) {
   if (!ctx) return;
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   delete ctx;
 }
 

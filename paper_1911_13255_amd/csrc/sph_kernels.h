@@ -28,6 +28,7 @@ void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 void launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
+void launch_step_end(const Dev &D, hipStream_t st);
 void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t st);
 void launch_write(const Dev &D, int s, int field, int n, const double *in, hipStream_t st);
 void launch_reduce(const Dev &D, int s, int nblocks, double *out, hipStream_t st);

@@ -487,12 +487,16 @@ __global__ void __launch_bounds__(1024) k_scan_cells(Dev D) {
   }
 }
 
+// Counting-sort scatter into cell slots in arrival order, with the sort key
+// (original index; boundary: source index) beside each entry.
 __global__ void __launch_bounds__(256) k_scatter(Dev D) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < D.nf) {
     int s = D.f_scene[t];
     if (!D.st[s].need_rebuild) return;
-    D.f_perm[D.fc_se[D.par[s].cell_begin + D.fs_lin[t]].x + D.fs_slot[t]] = t;
+    int slot = D.fc_se[D.par[s].cell_begin + D.fs_lin[t]].x + D.fs_slot[t];
+    D.f_perm[slot] = t;
+    D.f_pkey[slot] = D.fs_id[t];
     return;
   }
   int q = t - D.nf;
@@ -577,49 +581,43 @@ __device__ void gather_boundary(const Dev &D, const ScenePar &P, int k, int q) {
   D.b_nrm[k] = make_float4(n[0], n[1], n[2], Vref);
 }
 
-// One thread per cell of a rebuilding scene: order the cell's particles by
-// original index (fluid) and by source index (walls, then solid) so that the
-// layout does not depend on atomic arrival order, then gather their state.
+// One thread per cell slot of a rebuilding scene: the entry's final place in
+// its cell is its rank by key among the cell's entries (fluid: original
+// index; boundary: source index), so the layout does not depend on atomic
+// arrival order; the particle's state moves straight to that place.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_sort_gather(Dev D) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= D.ncell) return;
-  int s = D.cell_scene[c];
-  if (!D.st[s].need_rebuild) return;
-  const ScenePar &P = D.par[s];
-  int2 se = D.fc_se[c];
-  for (int k = se.x + 1; k < se.y; ++k) {
-    int v = D.f_perm[k];
-    int key = D.fs_id[v];
-    int j = k - 1;
-    while (j >= se.x && D.fs_id[D.f_perm[j]] > key) {
-      D.f_perm[j + 1] = D.f_perm[j];
-      --j;
-    }
-    D.f_perm[j + 1] = v;
-  }
-  for (int k = se.x; k < se.y; ++k) {
-    int o = D.f_perm[k];
+__global__ void __launch_bounds__(256) k_rank_move(Dev D) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < D.nf) {
+    int s = D.f_scene[t];  // scenes own fixed index ranges
+    if (!D.st[s].need_rebuild) return;
+    const ScenePar &P = D.par[s];
+    int o = D.f_perm[t];
+    int key = D.f_pkey[t];
+    int2 se = D.fc_se[P.cell_begin + D.fs_lin[o]];
+    int rank = 0;
+    for (int j = se.x; j < se.y; ++j) rank += D.f_pkey[j] < key;
+    int k = se.x + rank;
     double4 off = D.fs_off[o];
     D.f_lin[k] = D.fs_lin[o];
-    D.f_id[k] = D.fs_id[o];
+    D.f_id[k] = key;
     D.f_pos[k] = make_float4((float)off.x, (float)off.y, (float)off.z, D.fs_m[o]);
     D.f_posd[k] = off;
     D.f_off[k] = off;
     D.f_va[k] = D.fs_va[o];
     D.f_drho[k] = D.fs_drho[o];
+    return;
   }
-  int2 be = D.bc_se[c];
-  for (int k = be.x + 1; k < be.y; ++k) {
-    int v = D.b_perm[k];
-    int j = k - 1;
-    while (j >= be.x && D.b_perm[j] > v) {
-      D.b_perm[j + 1] = D.b_perm[j];
-      --j;
-    }
-    D.b_perm[j + 1] = v;
-  }
-  for (int k = be.x; k < be.y; ++k) gather_boundary<DIM>(D, P, k, D.b_perm[k]);
+  int kb = t - D.nf;
+  if (kb >= D.nb) return;
+  int s = D.bs_scene[kb];  // the slot range of a scene equals its source range
+  if (!D.st[s].need_rebuild) return;
+  const ScenePar &P = D.par[s];
+  int q = D.b_perm[kb];
+  int2 be = D.bc_se[P.cell_begin + D.bs_lin[q]];
+  int rank = 0;
+  for (int j = be.x; j < be.y; ++j) rank += D.b_perm[j] < q;
+  gather_boundary<DIM>(D, P, be.x + rank, q);
 }
 
 // Sum over a group of LPP consecutive lanes (a power of two dividing 64).
@@ -1012,9 +1010,8 @@ __device__ void solid_step_end(const Dev &D, const ScenePar &P, SceneState &S, f
 // with dt_S = cfl_s min(h_S / (c_S + |v|max), sqrt(h_S / |a|max)) and kappa =
 // floor(dt_ac / dt_S) + 1 equal sub-steps summing to dt_ac.  Afterwards the
 // averages vbar = du / dt_ac and abar = dv / dt_ac over the acoustic step
-// (Section 3.2) are handed to the boundary particles, and thread 0 closes the
-// acoustic step (time, advection accumulator, rebuild flag, next dt_ac,
-// counters).  The solid arithmetic is an FP64 island: the acceleration is a
+// (Section 3.2) are stored for the step-end kernel.  The solid arithmetic is
+// an FP64 island: the acceleration is a
 // second difference of the displacement and amplifies rounding noise at the
 // particle scale.  With LDS, the exchanged fields (v, P B) of the scene live
 // in shared memory for the whole launch.
@@ -1212,24 +1209,7 @@ __global__ void __launch_bounds__(1024) k_solid(Dev D, int lds_n) {
       bad |= !isfinite(vbar[k]) || !isfinite(abar[k]);
     }
     if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
-    int kslot = D.s_bslot[a];
-    if (kslot >= 0) {
-      double H[9];
-      for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
-      double J;
-      if (DIM == 2) J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
-      else
-        J = (1.0 + H[0]) * ((1.0 + H[4]) * (1.0 + H[8]) - H[5] * H[7]) - H[1] * (H[3] * (1.0 + H[8]) - H[5] * H[6]) +
-            H[2] * (H[3] * H[7] - (1.0 + H[4]) * H[6]);
-      float sa = 0.0f;
-      for (int k = 0; k < DIM; ++k) sa += (abar[k] - P.g[k]) * nn[k];
-      float4 bp = D.b_pos[kslot];
-      bp.w = (float)(P.Vs * J);
-      D.b_pos[kslot] = bp;
-      D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
-    }
   }
-  solid_step_end(D, P, S, red, kap, dt_ac, t, T);
 }
 
 // The same sub-steps for 2D scenes whose free solid fits the block with at
@@ -1460,21 +1440,45 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
       bad |= !isfinite(vbar[k]) || !isfinite(abar[k]);
     }
     if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
-    int kslot = D.s_bslot[a];
-    if (kslot >= 0) {
-      double J;
-      if (DIM == 2) J = (1.0 + H[p][0]) * (1.0 + H[p][3]) - H[p][1] * H[p][2];
-      else
-        J = (1.0 + H[p][0]) * ((1.0 + H[p][4]) * (1.0 + H[p][8]) - H[p][5] * H[p][7]) -
-            H[p][1] * (H[p][3] * (1.0 + H[p][8]) - H[p][5] * H[p][6]) +
-            H[p][2] * (H[p][3] * H[p][7] - (1.0 + H[p][4]) * H[p][6]);
-      float4 bp = D.b_pos[kslot];
-      bp.w = (float)(P.Vs * J);
-      D.b_pos[kslot] = bp;
-      D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
-    }
   }
-  solid_step_end(D, P, S, red, kap, dt_ac, t, T);
+}
+
+// End of an acoustic step, one block per scene: the solid's averaged
+// velocity and acceleration and its current volume are handed to the
+// boundary particles seen by the fluid (with the hydrostatic factor
+// max(0, (abar - g).n)), then the scene's step is closed.  Kept apart from the
+// sub-step kernel so that the continuity pass, which reads the boundary
+// particles, can run concurrently with the coupling and solid passes.
+template <int DIM>
+__global__ void __launch_bounds__(1024) k_step_end(Dev D) {
+  __shared__ float red[2][1024];
+  int s = blockIdx.x;
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  const int NS = D.ns, T = blockDim.x, t = threadIdx.x;
+  const int nfree = P.s_count - P.s_nclamp;
+  for (int l = t; l < nfree; l += T) {
+    int a = P.s_begin + l;
+    int kslot = D.s_bslot[a];
+    if (kslot < 0) continue;
+    double H[9];
+    for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
+    double J;
+    if (DIM == 2) J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
+    else
+      J = (1.0 + H[0]) * ((1.0 + H[4]) * (1.0 + H[8]) - H[5] * H[7]) - H[1] * (H[3] * (1.0 + H[8]) - H[5] * H[6]) +
+          H[2] * (H[3] * H[7] - (1.0 + H[4]) * H[6]);
+    float vbar[3] = {0.0f, 0.0f, 0.0f}, sa = 0.0f;
+    for (int k = 0; k < DIM; ++k) {
+      vbar[k] = D.s_vbar[k * NS + a];
+      sa += (D.s_abar[k * NS + a] - P.g[k]) * D.s_n[k * NS + a];
+    }
+    float4 bp = D.b_pos[kslot];
+    bp.w = (float)(P.Vs * J);
+    D.b_pos[kslot] = bp;
+    D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
+  }
+  solid_step_end(D, P, S, red, S.kappa, S.dt_ac, t, T);
 }
 
 // ------------------------------------------------------------------ state I/O
@@ -1775,7 +1779,7 @@ void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_bin, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
   hipLaunchKernelGGL(k_scan_cells, dim3(D.n_scenes), dim3(1024), 0, st, D);
   if (D.nf + D.nb > 0) hipLaunchKernelGGL(k_scatter, grid_for(D.nf + D.nb, 256), dim3(256), 0, st, D);
-  LAUNCH_DIM(D.dim, k_sort_gather, grid_for(D.ncell, 256), dim3(256), st, D);
+  if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_rank_move, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
   if (D.nf > 0)
     LAUNCH_LPP(k_reinit, cfg.lpp_reinit, D.dim, grid_for((long long)D.nf * cfg.lpp_reinit, cfg.block_pair),
                dim3(cfg.block_pair), st, D);
@@ -1818,6 +1822,10 @@ void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
     if (D.dim == 2) hipLaunchKernelGGL((k_solid<2, false>), dim3(D.n_scenes), dim3(cfg.block_solid), 0, st, D, 0);
     else hipLaunchKernelGGL((k_solid<3, false>), dim3(D.n_scenes), dim3(cfg.block_solid), 0, st, D, 0);
   }
+}
+
+void launch_step_end(const Dev &D, hipStream_t st) {
+  LAUNCH_DIM(D.dim, k_step_end, dim3(D.n_scenes), dim3(1024), st, D);
 }
 
 int solid_lds_bytes_per_particle(int dim) { return (dim * dim + dim) * (int)sizeof(double); }

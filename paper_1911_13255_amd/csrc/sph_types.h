@@ -78,7 +78,7 @@ struct Dev {
   int4 *f_nnb;     // fluid, wall and solid neighbours within 2 h_F at the last rebuild
   float *f_speed;  // |v| after the last continuity pass (reduced per scene by the solid kernel)
   // fluid rebuild scratch (indexed by the old sorted index)
-  int *fs_lin, *fs_slot, *fs_id, *f_perm;
+  int *fs_lin, *fs_slot, *fs_id, *f_perm, *f_pkey;
   double4 *fs_off;
   float4 *fs_va;
   float *fs_drho, *fs_m;
