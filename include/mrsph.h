@@ -65,10 +65,12 @@ typedef struct {
   int riemann;        /* 1: low-dissipation Riemann solver (Section 2.2); 0: simple averages */
   int density_reinit; /* 0 off; 1 rho = rho0 max(1, psi/psi0); 2 rho = max(rho, rho0 psi/psi0) */
   int max_solid_nbr;  /* capacity of the solid reference neighbour table; 0 = default (40 in 2D, 128 in 3D) */
-  int solid_block;    /* threads per scene in the solid sub-step kernel (power of two, 64..1024); 0 = default */
+  int solid_block;    /* threads per scene of the register-resident solid kernel (power of two, 64..1024); 0 = default */
   int lanes_per_particle; /* lanes sharing one particle in the fluid pair loops (1, 2, 4, 8, 16); 0 = chosen from the particle count */
   int block_pair;     /* threads per block of the fluid pair loops (64, 128, 256); 0 = default */
-  int solid_lds;      /* 0: solid exchange fields in LDS when a scene fits; 1: always in global memory */
+  int solid_lds;      /* 0: 2D scenes whose free solid fits 2048 particles run one register-resident
+                         kernel per step (v and P B in LDS), other solids streamed passes;
+                         1: always the streamed passes */
 } sph_options;
 
 /* Field ids for sph_read / sph_write (FP64, original particle order).
@@ -132,12 +134,15 @@ int couple(sph_ctx *ctx);
  * force held constant (Section 3.3), Neo-Hookean stress (Section 2.1) and
  * the corrected total-Lagrangian momentum equation at h_S (Section 3.1);
  * then the time-averaged velocity and acceleration (Section 3.2) and the
- * end-of-step time bookkeeping.  Must follow couple.  Enqueue only. */
+ * end-of-step time bookkeeping.  Must follow couple.  Enqueue only, except
+ * for solids run as streamed passes (3D, large or solid_lds = 1): there
+ * kappa is read back to the host, which waits for the stream. */
 int solid_substeps(sph_ctx *ctx);
 
 /* n acoustic steps of Algorithm 1 (neighbor_build, fluid_step, couple,
  * solid_substeps); the first call captures one step into a HIP graph that
- * later calls replay.  Enqueue only. */
+ * later calls replay.  Enqueue only.  With streamed solid passes the steps
+ * are launched one by one without a graph and each waits for kappa. */
 int sph_advance(sph_ctx *ctx, int n_steps);
 
 /* Copy a field of one scene to host memory in original particle order

@@ -222,7 +222,7 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
     return false;
   }
   // register-resident solid kernel (2D) when every scene's free solid fits
-  // 2048 particles (at most 2 per thread); otherwise the LDS or global variant
+  // 2048 particles (at most 4 per thread); otherwise streamed passes
   P.cfg.solid_ppt = 0;
   if (o.solid_lds != 1 && P.dim == 2 && max_free_scene > 0 && max_free_scene <= 2048) {
     // block limits of the register-resident kernel: 1024, 640, 512 threads
@@ -260,7 +260,7 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
   }
   P.cfg.block_pair = bp ? bp : 256;
   P.cfg.block_couple = 64;
-  P.cfg.solid_lds_n = o.solid_lds == 1 ? 0 : max_solid_scene;  // confirmed against the device in sph_init
+  P.cfg.solid_lds_n = P.cfg.solid_ppt ? max_solid_scene : 0;  // confirmed against the device in sph_init
   return true;
 }
 
@@ -377,13 +377,40 @@ int read_states(sph_ctx *ctx, std::vector<SceneState> &st) {
   return SPH_OK;
 }
 
+// kappa solid sub-steps.  Small 2D solids: one
+// register-resident launch per step with kappa decided on the device.  Other
+// solids: streamed passes over all solid particles; kappa is read back to
+// the host to size the pass loop (this synchronises the stream).
+int enqueue_solid(sph_ctx *ctx) {
+  if (ctx->cfg.solid_ppt > 0) {
+    launch_solid(ctx->D, ctx->cfg, ctx->stream);
+  } else if (ctx->D.ns > 0) {
+    launch_solid_dt(ctx->D, ctx->stream);
+    std::vector<SceneState> st(ctx->n_scenes);
+    if (hipMemcpyAsync(st.data(), ctx->D.st, sizeof(SceneState) * ctx->n_scenes, hipMemcpyDeviceToHost,
+                       ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      std::snprintf(ctx->err, sizeof ctx->err, "solid_substeps: kappa read-back failed");
+      return SPH_E_HIP;
+    }
+    int kmax = 0;
+    for (const SceneState &x : st) kmax = std::max(kmax, x.kappa);
+    launch_solid_first(ctx->D, ctx->stream);
+    for (int sub = 0; sub < kmax; ++sub) launch_solid_pass(ctx->D, sub, ctx->stream);
+    launch_solid_average(ctx->D, ctx->stream);
+  } else {
+    launch_solid_dt(ctx->D, ctx->stream);
+  }
+  return SPH_OK;
+}
+
 // One acoustic step.  With a second stream the continuity pass (which no
 // later pass of the step reads until the step-end kernel) runs concurrently
 // with the coupling and solid passes.
 int enqueue_step(sph_ctx *ctx, bool fork) {
   launch_rebuild(ctx->D, ctx->cfg, ctx->stream);
   launch_fluid_force(ctx->D, ctx->cfg, ctx->stream);
-  if (fork && ctx->side) {
+  if (fork && ctx->side && ctx->cfg.solid_ppt > 0) {
     if (hipEventRecord(ctx->ev_fork, ctx->stream) != hipSuccess ||
         hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0) != hipSuccess)
       return SPH_E_HIP;
@@ -393,11 +420,13 @@ int enqueue_step(sph_ctx *ctx, bool fork) {
     if (hipEventRecord(ctx->ev_join, ctx->side) != hipSuccess ||
         hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0) != hipSuccess)
       return SPH_E_HIP;
-  } else {
-    launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream);
-    launch_couple(ctx->D, ctx->cfg, ctx->stream);
-    launch_solid(ctx->D, ctx->cfg, ctx->stream);
+    launch_step_end(ctx->D, ctx->stream);
+    return check_launch(ctx, "acoustic step");
   }
+  launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream);
+  launch_couple(ctx->D, ctx->cfg, ctx->stream);
+  int rc = enqueue_solid(ctx);
+  if (rc != SPH_OK) return rc;
   launch_step_end(ctx->D, ctx->stream);
   return check_launch(ctx, "acoustic step");
 }
@@ -443,7 +472,8 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
     }
   }
   {
-    // the solid exchange fields go to LDS when the largest scene fits
+    // the register-resident solid kernel holds v and P B of the largest
+    // scene in LDS; when they do not fit, the streamed passes are used
     int dev = 0, lds_max = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -456,12 +486,7 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
       ctx->cfg.solid_ppt = 0;
       (void)hipGetLastError();
     }
-    // the global-memory variant needs a power-of-two block for its reductions
-    if (ctx->cfg.solid_ppt == 0) {
-      int bs = 64;
-      while (bs < ctx->cfg.block_solid) bs *= 2;
-      ctx->cfg.block_solid = std::min(bs, 1024);
-    }
+
   }
   ctx->graph_failed = 0;
   ctx->err[0] = 0;
@@ -590,7 +615,8 @@ int couple(sph_ctx *ctx) {
 
 int solid_substeps(sph_ctx *ctx) {
   if (!ctx) return SPH_E_ORDER;
-  launch_solid(ctx->D, ctx->cfg, ctx->stream);
+  int rc = enqueue_solid(ctx);
+  if (rc != SPH_OK) return rc;
   launch_step_end(ctx->D, ctx->stream);
   return check_launch(ctx, "solid_substeps");
 }
@@ -598,7 +624,8 @@ int solid_substeps(sph_ctx *ctx) {
 int sph_advance(sph_ctx *ctx, int n_steps) {
   if (!ctx) return SPH_E_ORDER;
   if (n_steps < 0) return SPH_E_ARG;
-  if (!ctx->graph_exec && !ctx->graph_failed && ctx->stream) {
+  // the streamed solid path reads kappa back to the host: no graph then
+  if (!ctx->graph_exec && !ctx->graph_failed && ctx->stream && ctx->cfg.solid_ppt > 0) {
     // capture one acoustic step; every decision inside it is taken on the device
     hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
@@ -763,7 +790,14 @@ int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms) {
     case SPH_K_FLUID_FORCE: launch_fluid_force(ctx->D, ctx->cfg, ctx->stream); break;
     case SPH_K_CONTINUITY: launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream); break;
     case SPH_K_COUPLE: launch_couple(ctx->D, ctx->cfg, ctx->stream); break;
-    case SPH_K_SOLID: launch_solid(ctx->D, ctx->cfg, ctx->stream); break;
+    case SPH_K_SOLID:
+      // the streamed form synchronises once per repetition to read kappa
+      if (enqueue_solid(ctx) != SPH_OK) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return SPH_E_HIP;
+      }
+      break;
     case SPH_K_REBUILD:
       for (int s = 0; s < ctx->n_scenes; ++s) launch_set_rebuild(ctx->D, s, ctx->stream);
       launch_rebuild(ctx->D, ctx->cfg, ctx->stream);

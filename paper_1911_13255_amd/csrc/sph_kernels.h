@@ -11,8 +11,9 @@ struct LaunchCfg {
   int block_couple;  // threads per block of the coupling kernel
   int block_solid;   // threads per scene of the solid sub-step kernel
   int lpp_force, lpp_cont, lpp_couple, lpp_reinit;  // lanes per particle (1, 2, 4, 8, 16)
-  int solid_lds_n;   // solid particles per scene held in LDS (0: exchanged fields in global memory)
-  int solid_ppt;     // > 0: register-resident solid kernel with this many particles per thread
+  int solid_lds_n;   // solid particles per scene held in LDS by the register-resident kernel
+  int solid_ppt;     // > 0: register-resident solid kernel (2D) with this many particles per thread;
+                     // 0: streamed multi-block solid passes with kappa read back to the host
 };
 
 void launch_init_scene(const Dev &D, int s, const double *x_f, const double *v_f, int has_vf, double gabs,
@@ -29,6 +30,10 @@ void launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st)
 void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 void launch_step_end(const Dev &D, hipStream_t st);
+void launch_solid_dt(const Dev &D, hipStream_t st);
+void launch_solid_first(const Dev &D, hipStream_t st);
+void launch_solid_pass(const Dev &D, int sub, hipStream_t st);
+void launch_solid_average(const Dev &D, hipStream_t st);
 void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t st);
 void launch_write(const Dev &D, int s, int field, int n, const double *in, hipStream_t st);
 void launch_reduce(const Dev &D, int s, int nblocks, double *out, hipStream_t st);

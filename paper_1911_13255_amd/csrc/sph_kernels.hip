@@ -1003,7 +1003,7 @@ __device__ void solid_step_end(const Dev &D, const ScenePar &P, SceneState &S, f
 
 
 // kappa solid sub-steps of the position-based Verlet scheme (Section 3.3,
-// Eqs. verlet-*-solid) for one scene per block, the fluid force held constant:
+// Eqs. verlet-*-solid), the fluid force held constant:
 //   F += dt/2 dF/dt;  u += dt/2 v;  P B from the Neo-Hookean stress;
 //   a = [sum_b V_a V_b (P_a B_a + P_b B_b) grad0_a W_ab + f^F_a] / m_a + g;  v += dt a;
 //   dF/dt = sum_b V_b (v_b - v_a) (x) (B_a grad0_a W_ab);  F += dt/2 dF/dt;  u += dt/2 v;
@@ -1011,39 +1011,36 @@ __device__ void solid_step_end(const Dev &D, const ScenePar &P, SceneState &S, f
 // floor(dt_ac / dt_S) + 1 equal sub-steps summing to dt_ac.  Afterwards the
 // averages vbar = du / dt_ac and abar = dv / dt_ac over the acoustic step
 // (Section 3.2) are stored for the step-end kernel.  The solid arithmetic is
-// an FP64 island: the acceleration is a
-// second difference of the displacement and amplifies rounding noise at the
-// particle scale.  With LDS, the exchanged fields (v, P B) of the scene live
-// in shared memory for the whole launch.
-template <int DIM, bool LDS>
-__global__ void __launch_bounds__(1024) k_solid(Dev D, int lds_n) {
-  extern __shared__ double smem[];
+// an FP64 island: the acceleration is a second difference of the
+// displacement and amplifies rounding noise at the particle scale.
+//
+// Streamed form for solids of any size: one kernel per phase over all solid
+// particles of all scenes (a scene past its own kappa skips the pass).
+
+// Solid time step and kappa of each scene (one block per scene); the
+// step increments are cleared.
+__global__ void __launch_bounds__(1024) k_solid_dt(Dev D) {
   __shared__ float red[2][1024];
-  __shared__ int kap_sh;
-  __shared__ double del_sh;
   int s = blockIdx.x;
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
-  const int NS = D.ns;
-  const int base = P.s_begin, n = P.s_count, nfree = P.s_count - P.s_nclamp;
-  const int T = blockDim.x, t = threadIdx.x;
-  // exchanged fields: in LDS indexed by scene-local index, else in global memory
-  double *PBx = LDS ? smem : D.s_PB;
-  double *Vx = LDS ? smem + DIM * DIM * lds_n : D.s_v;
-  const int xs = LDS ? lds_n : NS;
-  const int xo = LDS ? base : 0;
-  double dt_ac = S.dt_ac;
+  const int NS = D.ns, T = blockDim.x, t = threadIdx.x, dim = D.dim;
+  const int nfree = P.s_count - P.s_nclamp;
   float vm = 0.0f, am = 0.0f;
-  for (int l = t; l < nfree; l += T) {
-    int a = base + l;
+  for (int l = t; l < P.s_count; l += T) {
+    int a = P.s_begin + l;
     float v2 = 0.0f, a2 = 0.0f;
-    for (int k = 0; k < DIM; ++k) {
+    for (int k = 0; k < dim; ++k) {
       float v = (float)D.s_v[k * NS + a], q = D.s_a[k * NS + a];
       v2 += v * v;
       a2 += q * q;
+      D.s_du[k * NS + a] = 0.0;
+      D.s_dv[k * NS + a] = 0.0;
     }
-    vm = fmaxf(vm, sqrtf(v2));
-    am = fmaxf(am, sqrtf(a2));
+    if (l < nfree) {
+      vm = fmaxf(vm, sqrtf(v2));
+      am = fmaxf(am, sqrtf(a2));
+    }
   }
   red[0][t] = vm;
   red[1][t] = am;
@@ -1056,6 +1053,7 @@ __global__ void __launch_bounds__(1024) k_solid(Dev D, int lds_n) {
     __syncthreads();
   }
   if (t == 0) {
+    double dt_ac = S.dt_ac;
     double dts = (double)P.cfl_s * (double)P.hs / ((double)P.c_s + (double)red[0][0]);
     if (red[1][0] > 0.0f) dts = fmin(dts, (double)P.cfl_s * sqrt((double)P.hs / (double)red[1][0]));
     // kappa is bounded: a collapsed solid step is reported, not iterated
@@ -1067,149 +1065,144 @@ __global__ void __launch_bounds__(1024) k_solid(Dev D, int lds_n) {
     } else {
       kap = (int)floor(ratio) + 1;
     }
-    kap_sh = kap;
-    del_sh = dt_ac / kap;
     S.dt_s = dts;
     S.kappa = kap;
   }
-  __syncthreads();
-  const int kap = kap_sh;
-  const double del = del_sh;
-  const double hd = 0.5 * del;
+}
+
+// First half of a sub-step for particle a (own state only), and its stress.
+template <int DIM>
+__device__ __forceinline__ void solid_first_half(const Dev &D, const ScenePar &P, SceneState &S, int a, double hd) {
+  const int NS = D.ns;
+  double H[9], B[9], PB[9];
+  for (int k = 0; k < DIM * DIM; ++k) {
+    H[k] = D.s_H[k * NS + a] + hd * D.s_dF[k * NS + a];
+    D.s_H[k * NS + a] = H[k];
+    B[k] = D.s_B[k * NS + a];
+  }
+  for (int k = 0; k < DIM; ++k) {
+    double inc = hd * D.s_v[k * NS + a];
+    D.s_u[k * NS + a] += inc;
+    D.s_du[k * NS + a] += inc;
+  }
+  double J;
+  nh_PB<DIM, double>(H, B, (double)P.mu, (double)P.lam, PB, J);
+  if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
+  for (int k = 0; k < DIM * DIM; ++k) D.s_PB[k * NS + a] = PB[k];
+}
+
+// First half of sub-step 0 (clamp particles: zero stress).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_solid_first(Dev D) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  int s = D.s_scene[a];
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  if (a - P.s_begin >= P.s_count - P.s_nclamp) {
+    for (int k = 0; k < DIM * DIM; ++k) D.s_PB[k * D.ns + a] = 0.0;
+    return;
+  }
+  solid_first_half<DIM>(D, P, S, a, 0.5 * S.dt_ac / S.kappa);
+}
+
+// Momentum and velocity of sub-step `sub`.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  int s = D.s_scene[a];
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  if (sub >= S.kappa || a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  const int NS = D.ns;
+  const double del = S.dt_ac / S.kappa;
+  double PBa[9];
+  for (int k = 0; k < DIM * DIM; ++k) PBa[k] = D.s_PB[k * NS + a];
+  double acc[3] = {0.0, 0.0, 0.0};
+  int cnt = D.s_cnt[a];
+#pragma unroll 4
+  for (int q = 0; q < cnt; ++q) {
+    float4 g = D.s_nbr[(size_t)q * NS + a];
+    int b = __float_as_int(g.w);
+    double gv[3] = {g.x, g.y, g.z};
+    for (int i = 0; i < DIM; ++i) {
+      double sum = 0.0;
+      for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + D.s_PB[(i * DIM + j) * NS + b]) * gv[j];
+      acc[i] += sum;
+    }
+  }
   const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
-  for (int l = t; l < n; l += T) {
-    int a = base + l;
-    for (int k = 0; k < DIM; ++k) {
-      D.s_du[k * NS + a] = 0.0;
-      D.s_dv[k * NS + a] = 0.0;
-      if (LDS) Vx[k * xs + (a - xo)] = D.s_v[k * NS + a];
-    }
-    if (l >= nfree)
-      for (int k = 0; k < DIM * DIM; ++k) PBx[k * xs + (a - xo)] = 0.0;
+  for (int k = 0; k < DIM; ++k) {
+    double ak = ((double)P.Vs * acc[k] + (double)D.s_fF[k * NS + a]) * m_inv + (double)P.g[k];
+    D.s_a[k * NS + a] = (float)ak;
+    double dv = del * ak;
+    D.s_v[k * NS + a] += dv;
+    D.s_dv[k * NS + a] += dv;
   }
-  __syncthreads();
-  // Sub-step loop.  The first half-step and stress of sub-step k+1 run in the
-  // same pass as the deformation rate and second half of sub-step k (they touch
-  // only the particle's own state), so each sub-step has two barriers.
-  auto first_half = [&](int a, double *H, double *dF, double *u) {
-    double B[9], PB[9];
-    for (int k = 0; k < DIM * DIM; ++k) {
-      H[k] += hd * dF[k];
-      B[k] = D.s_B[k * NS + a];
-    }
-    for (int k = 0; k < DIM; ++k) {
-      double inc = hd * Vx[k * xs + (a - xo)];
-      u[k] += inc;
-      D.s_du[k * NS + a] += inc;
-    }
-    double J;
-    nh_PB<DIM, double>(H, B, (double)P.mu, (double)P.lam, PB, J);
-    if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
-    for (int k = 0; k < DIM * DIM; ++k) PBx[k * xs + (a - xo)] = PB[k];
-  };
-  for (int l = t; l < nfree; l += T) {
-    int a = base + l;
-    double H[9], dF[9], u[3];
-    for (int k = 0; k < DIM * DIM; ++k) {
-      H[k] = D.s_H[k * NS + a];
-      dF[k] = D.s_dF[k * NS + a];
-    }
-    for (int k = 0; k < DIM; ++k) u[k] = D.s_u[k * NS + a];
-    first_half(a, H, dF, u);
-    for (int k = 0; k < DIM * DIM; ++k) D.s_H[k * NS + a] = H[k];
-    for (int k = 0; k < DIM; ++k) D.s_u[k * NS + a] = u[k];
-  }
-  __syncthreads();
-  for (int sub = 0; sub < kap; ++sub) {
-    // momentum, velocity
-    for (int l = t; l < nfree; l += T) {
-      int a = base + l;
-      double PBa[9];
-      for (int k = 0; k < DIM * DIM; ++k) PBa[k] = PBx[k * xs + (a - xo)];
-      double acc[3] = {0.0, 0.0, 0.0};
-      int cnt = D.s_cnt[a];
+}
+
+// Deformation rate with the new velocity and second half of sub-step `sub`;
+// then the first half and stress of the next sub-step.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  int s = D.s_scene[a];
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  if (sub >= S.kappa || a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  const int NS = D.ns;
+  const double hd = 0.5 * S.dt_ac / S.kappa;
+  double va[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < DIM; ++k) va[k] = D.s_v[k * NS + a];
+  double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int cnt = D.s_cnt[a];
 #pragma unroll 4
-      for (int q = 0; q < cnt; ++q) {
-        float4 g = D.s_nbr[(size_t)q * NS + a];
-        int b = __float_as_int(g.w) - xo;
-        double gv[3] = {g.x, g.y, g.z};
-        for (int i = 0; i < DIM; ++i) {
-          double sum = 0.0;
-          for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + PBx[(i * DIM + j) * xs + b]) * gv[j];
-          acc[i] += sum;
-        }
-      }
-      for (int k = 0; k < DIM; ++k) {
-        double ak = ((double)P.Vs * acc[k] + (double)D.s_fF[k * NS + a]) * m_inv + (double)P.g[k];
-        D.s_a[k * NS + a] = (float)ak;
-        double dv = del * ak;
-        Vx[k * xs + (a - xo)] += dv;
-        D.s_dv[k * NS + a] += dv;
-      }
+  for (int q = 0; q < cnt; ++q) {
+    float4 g = D.s_nbr[(size_t)q * NS + a];
+    int b = __float_as_int(g.w);
+    double gv[3] = {g.x, g.y, g.z};
+    for (int i = 0; i < DIM; ++i) {
+      double dvi = D.s_v[i * NS + b] - va[i];
+      for (int j = 0; j < DIM; ++j) G[i * DIM + j] += dvi * gv[j];
     }
-    __syncthreads();
-    // deformation rate with the new velocity, second half; then the next
-    // sub-step's first half and stress
-    const bool more = sub + 1 < kap;
-    for (int l = t; l < nfree; l += T) {
-      int a = base + l;
-      double va[3] = {0.0, 0.0, 0.0};
-      for (int k = 0; k < DIM; ++k) va[k] = Vx[k * xs + (a - xo)];
-      double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      int cnt = D.s_cnt[a];
-#pragma unroll 4
-      for (int q = 0; q < cnt; ++q) {
-        float4 g = D.s_nbr[(size_t)q * NS + a];
-        int b = __float_as_int(g.w) - xo;
-        double gv[3] = {g.x, g.y, g.z};
-        for (int i = 0; i < DIM; ++i) {
-          double dvi = Vx[i * xs + b] - va[i];
-          for (int j = 0; j < DIM; ++j) G[i * DIM + j] += dvi * gv[j];
-        }
-      }
-      double H[9], dF[9], u[3];
-      for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
-      for (int k = 0; k < DIM; ++k) u[k] = D.s_u[k * NS + a];
-      // (v_b - v_a) (x) (B grad W) summed = G B^T
-      for (int i = 0; i < DIM; ++i)
-        for (int j = 0; j < DIM; ++j) {
-          double sum = 0.0;
-          for (int k = 0; k < DIM; ++k) sum += G[i * DIM + k] * D.s_B[(j * DIM + k) * NS + a];
-          dF[i * DIM + j] = sum;
-          H[i * DIM + j] += hd * sum;
-        }
-      for (int k = 0; k < DIM; ++k) {
-        double inc = hd * va[k];
-        u[k] += inc;
-        D.s_du[k * NS + a] += inc;
-      }
-      if (more) first_half(a, H, dF, u);
-      for (int k = 0; k < DIM * DIM; ++k) {
-        D.s_H[k * NS + a] = H[k];
-        D.s_dF[k * NS + a] = dF[k];
-      }
-      for (int k = 0; k < DIM; ++k) D.s_u[k * NS + a] = u[k];
-    }
-    __syncthreads();
   }
-  // time averages over the acoustic step, handed to the boundary particles
-  const double inv_dt = 1.0 / dt_ac;
-  for (int l = t; l < nfree; l += T) {
-    int a = base + l;
-    if (LDS)
-      for (int k = 0; k < DIM; ++k) D.s_v[k * NS + a] = Vx[k * xs + (a - xo)];
-    float vbar[3] = {0.0f, 0.0f, 0.0f}, abar[3] = {0.0f, 0.0f, 0.0f}, nn[3] = {0.0f, 0.0f, 0.0f};
-    bool bad = false;
-    for (int k = 0; k < DIM; ++k) {
-      vbar[k] = (float)(D.s_du[k * NS + a] * inv_dt);
-      abar[k] = (float)(D.s_dv[k * NS + a] * inv_dt);
-      D.s_vbar[k * NS + a] = vbar[k];
-      D.s_abar[k * NS + a] = abar[k];
-      nn[k] = D.s_n[k * NS + a];
-      bad |= !isfinite(vbar[k]) || !isfinite(abar[k]);
+  // (v_b - v_a) (x) (B grad W) summed = G B^T
+  for (int i = 0; i < DIM; ++i)
+    for (int j = 0; j < DIM; ++j) {
+      double sum = 0.0;
+      for (int k = 0; k < DIM; ++k) sum += G[i * DIM + k] * D.s_B[(j * DIM + k) * NS + a];
+      D.s_dF[(i * DIM + j) * NS + a] = sum;
+      D.s_H[(i * DIM + j) * NS + a] += hd * sum;
     }
-    if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
+  for (int k = 0; k < DIM; ++k) {
+    double inc = hd * va[k];
+    D.s_u[k * NS + a] += inc;
+    D.s_du[k * NS + a] += inc;
   }
+  if (sub + 1 < S.kappa) solid_first_half<DIM>(D, P, S, a, hd);
+}
+
+// Time averages over the acoustic step.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_solid_average(Dev D) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  int s = D.s_scene[a];
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  if (a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  const int NS = D.ns;
+  const double inv_dt = 1.0 / S.dt_ac;
+  bool bad = false;
+  for (int k = 0; k < DIM; ++k) {
+    float vb = (float)(D.s_du[k * NS + a] * inv_dt), ab = (float)(D.s_dv[k * NS + a] * inv_dt);
+    D.s_vbar[k * NS + a] = vb;
+    D.s_abar[k * NS + a] = ab;
+    bad |= !isfinite(vb) || !isfinite(ab);
+  }
+  if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
 }
 
 // The same sub-steps for 2D scenes whose free solid fits the block with at
@@ -1811,17 +1804,26 @@ void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   } while (0)
 
 void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
-  if (cfg.solid_ppt > 0 && cfg.solid_lds_n > 0 && D.dim == 2) {
-    size_t bytes = (size_t)cfg.solid_lds_n * (D.dim * D.dim + D.dim) * sizeof(double);
-    LAUNCH_SOLID_REG(cfg.solid_ppt, dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
-  } else if (cfg.solid_lds_n > 0) {
-    size_t bytes = (size_t)cfg.solid_lds_n * (D.dim * D.dim + D.dim) * sizeof(double);
-    if (D.dim == 2) hipLaunchKernelGGL((k_solid<2, true>), dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
-    else hipLaunchKernelGGL((k_solid<3, true>), dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
-  } else {
-    if (D.dim == 2) hipLaunchKernelGGL((k_solid<2, false>), dim3(D.n_scenes), dim3(cfg.block_solid), 0, st, D, 0);
-    else hipLaunchKernelGGL((k_solid<3, false>), dim3(D.n_scenes), dim3(cfg.block_solid), 0, st, D, 0);
-  }
+  size_t bytes = (size_t)cfg.solid_lds_n * (D.dim * D.dim + D.dim) * sizeof(double);
+  LAUNCH_SOLID_REG(cfg.solid_ppt, dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
+}
+
+void launch_solid_dt(const Dev &D, hipStream_t st) {
+  hipLaunchKernelGGL(k_solid_dt, dim3(D.n_scenes), dim3(1024), 0, st, D);
+}
+
+void launch_solid_first(const Dev &D, hipStream_t st) {
+  if (D.ns > 0) LAUNCH_DIM(D.dim, k_solid_first, grid_for(D.ns, 256), dim3(256), st, D);
+}
+
+void launch_solid_pass(const Dev &D, int sub, hipStream_t st) {
+  if (D.ns == 0) return;
+  LAUNCH_DIM(D.dim, k_solid_momentum, grid_for(D.ns, 256), dim3(256), st, D, sub);
+  LAUNCH_DIM(D.dim, k_solid_rate, grid_for(D.ns, 256), dim3(256), st, D, sub);
+}
+
+void launch_solid_average(const Dev &D, hipStream_t st) {
+  if (D.ns > 0) LAUNCH_DIM(D.dim, k_solid_average, grid_for(D.ns, 256), dim3(256), st, D);
 }
 
 void launch_step_end(const Dev &D, hipStream_t st) {
@@ -1831,10 +1833,9 @@ void launch_step_end(const Dev &D, hipStream_t st) {
 int solid_lds_bytes_per_particle(int dim) { return (dim * dim + dim) * (int)sizeof(double); }
 
 hipError_t allow_solid_lds(int dim, int ppt, size_t bytes) {
-  const void *f;
-  if (ppt == 0 || dim != 2) f = dim == 2 ? (const void *)k_solid<2, true> : (const void *)k_solid<3, true>;
-  else f = ppt == 1 ? (const void *)k_solid_reg<2, 1>
-                     : (ppt == 2 ? (const void *)k_solid_reg<2, 2> : (const void *)k_solid_reg<2, 4>);
+  if (dim != 2 || ppt <= 0) return hipErrorInvalidValue;
+  const void *f = ppt == 1 ? (const void *)k_solid_reg<2, 1>
+                           : (ppt == 2 ? (const void *)k_solid_reg<2, 2> : (const void *)k_solid_reg<2, 4>);
   return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
