@@ -36,8 +36,8 @@ extern "C" {
 #define SPH_E_ARG (-1)      /* invalid argument or scene description */
 #define SPH_E_HIP (-2)      /* a HIP runtime call failed */
 #define SPH_E_ORDER (-3)    /* call out of sequence (e.g. before sph_init) */
-#define SPH_E_CAPACITY (-4) /* a fixed-capacity neighbour table overflowed */
-#define SPH_E_UNSTABLE (-5) /* NaN/Inf in the state or det F <= 0 */
+#define SPH_E_CAPACITY (-4) /* a fixed-capacity neighbour table or pair list overflowed */
+#define SPH_E_UNSTABLE (-5) /* NaN/Inf in the state or det F <= 0 (reported first when both hold) */
 
 typedef struct sph_ctx sph_ctx;
 
@@ -71,6 +71,10 @@ typedef struct {
   int solid_lds;      /* 0: 2D scenes whose free solid fits 2048 particles run one register-resident
                          kernel per step (v and P B in LDS), other solids streamed passes;
                          1: always the streamed passes */
+  int max_fluid_nbr;    /* capacity of each fluid particle's fluid pair list; 0 = default (twice the
+                           lattice count inside 2 h_F) */
+  int max_boundary_nbr; /* capacity of each fluid particle's wall and solid pair list; 0 = default
+                           (lattice count inside 2 h_F times 1 + (dp_F/dp_S)^d) */
 } sph_options;
 
 /* Field ids for sph_read / sph_write (FP64, original particle order).

@@ -39,6 +39,7 @@ struct Plan {
   int dim = 0, n_scenes = 0;
   int nf = 0, nw = 0, ns = 0, nb = 0, ncell = 0, maxn = 0;
   int max_count = 0;
+  int capf = 0, capb = 0, lw = 1;  // pair-list capacities per particle and chunk width
   std::vector<ScenePar> par;
   std::vector<int> rank_to_lin, cell_scene, bs_scene;
   LaunchCfg cfg{256, 256, 256};
@@ -261,6 +262,32 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
   P.cfg.block_pair = bp ? bp : 256;
   P.cfg.block_couple = 64;
   P.cfg.solid_lds_n = P.cfg.solid_ppt ? max_solid_scene : 0;  // confirmed against the device in sph_init
+  // pair-list capacities: particles of a lattice inside the support 2 h_F,
+  // with room for compression (fluid) and for the finer solid lattice
+  // (boundary: walls at dp_F plus solid at dp_S)
+  {
+    double hr = 0.0, ratio = 1.0;
+    for (int s = 0; s < n; ++s) {
+      hr = std::max(hr, sc[s].h_ratio);
+      if (sc[s].n_solid > 0) ratio = std::max(ratio, sc[s].dp_f / sc[s].dp_s);
+    }
+    double R = 2.0 * hr;
+    double ball = P.dim == 2 ? M_PI * R * R : 4.0 / 3.0 * M_PI * R * R * R;
+    auto up16 = [](double x) { return ((int)std::ceil(x) + 15) / 16 * 16; };
+    int cf = o.max_fluid_nbr, cbn = o.max_boundary_nbr;
+    if (cf < 0 || cbn < 0 || cf > 4096 || cbn > 4096) {
+      err = "max_fluid_nbr and max_boundary_nbr must lie in [0, 4096]";
+      return false;
+    }
+    P.capf = cf ? up16(cf) : up16(2.0 * ball + 8.0);
+    P.capb = cbn ? up16(cbn) : up16(ball * (1.0 + std::pow(ratio, P.dim)) + 16.0);
+    P.lw = P.cfg.lpp_force;
+    // neighbour indices share 27 bits of an entry with the relative cell id
+    if ((long long)P.nf + P.nb >= (1LL << 27)) {
+      err = "more than 2^27 fluid plus boundary particles";
+      return false;
+    }
+  }
   return true;
 }
 
@@ -289,6 +316,9 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.f_drho, nf);
   take(D.f_p, nf);
   take(D.f_nnb, nf);
+  take(D.f_nbl, nf * (size_t)P.capf);
+  take(D.f_bnl, nf * (size_t)P.capb);
+  take(D.f_rowlen, nf);
   take(D.f_speed, nf);
   take(D.fs_lin, nf);
   take(D.fs_slot, nf);
@@ -305,6 +335,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.cell_scene, nc);
   take(D.fc_se, nc);
   take(D.bc_se, nc);
+  take(D.cell_part, (nc + kCellTile - 1) / kCellTile + 1);
   take(D.w_lin, nw);
   take(D.w_scene, nw);
   take(D.w_off, nw);
@@ -507,6 +538,9 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   D.nb = P.nb;
   D.ncell = P.ncell;
   D.maxn = P.maxn;
+  D.capf = P.capf;
+  D.capb = P.capb;
+  D.lw = P.lw;
   ctx->stage_doubles = 9 * (size_t)std::max(P.max_count, 64) + 64;
   hipStream_t st = ctx->stream;
   int rc = SPH_OK;
@@ -772,7 +806,8 @@ int sph_sync(sph_ctx *ctx) {
       std::snprintf(ctx->err, sizeof ctx->err, "scene %d: %s%s%s%s", s, (e & ERR_NAN_FLUID) ? "non-finite fluid state " : "",
                     (e & ERR_NAN_SOLID) ? "non-finite solid state " : "", (e & ERR_JACOBIAN) ? "det F <= 0 " : "",
                     (e & ERR_CAPACITY) ? "neighbour table overflow" : "");
-      return (e & ERR_CAPACITY) ? SPH_E_CAPACITY : SPH_E_UNSTABLE;
+      // a state that blew up also crowds cells: instability takes precedence
+      return (e & (ERR_NAN_FLUID | ERR_NAN_SOLID | ERR_JACOBIAN)) ? SPH_E_UNSTABLE : SPH_E_CAPACITY;
     }
   }
   return SPH_OK;

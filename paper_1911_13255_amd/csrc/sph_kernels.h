@@ -6,6 +6,9 @@
 
 namespace mrsph {
 
+// cells per block of the multi-block cell scan
+constexpr int kCellTile = 4096;
+
 struct LaunchCfg {
   int block_pair;    // threads per block of the fluid pair kernels
   int block_couple;  // threads per block of the coupling kernel

@@ -49,7 +49,8 @@ __device__ __forceinline__ int encode_cell(const ScenePar &P, const int *c) {
 }
 
 // Visit the 3^d neighbouring cells of cell `lin`; fn(neighbour linear index,
-// geometric offset of its origin from this cell's origin).
+// geometric offset of its origin from this cell's origin) and the relative
+// cell id (dx+1) + 3 (dy+1) + 9 (dz+1), which cell_shift turns back into sh.
 template <int DIM, typename Fn>
 __device__ __forceinline__ void visit_cells(const ScenePar &P, int lin, Fn &&fn) {
   int c[3];
@@ -70,11 +71,24 @@ __device__ __forceinline__ void visit_cells(const ScenePar &P, int lin, Fn &&fn)
         if (P.periodic[0]) n0 = wrapi(n0, P.ncell[0]);
         else if (n0 < 0 || n0 >= P.ncell[0]) continue;
         float sh[3] = {(float)dx * P.cs[0], (float)dy * P.cs[1], (float)dz * P.cs[2]};
-        fn(n0 + P.ncell[0] * (n1 + P.ncell[1] * n2), sh);
+        fn(n0 + P.ncell[0] * (n1 + P.ncell[1] * n2), sh, (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
       }
     }
   }
 }
+
+template <int DIM>
+__device__ __forceinline__ void cell_shift(const ScenePar &P, int cid, float *sh) {
+  int dx = cid % 3 - 1, dy = (cid / 3) % 3 - 1, dz = cid / 9 - 1;
+  sh[0] = (float)dx * P.cs[0];
+  sh[1] = (float)dy * P.cs[1];
+  sh[2] = DIM == 3 ? (float)dz * P.cs[2] : 0.0f;
+}
+
+// Pair-list entries: neighbour index in the low 27 bits, relative cell id
+// (< 27) in the top 5.
+constexpr int kNbrBits = 27;
+constexpr unsigned kNbrMask = (1u << kNbrBits) - 1u;
 
 // Re-express (cell c, offset off) so that the offset lies in [0, cs) where the
 // grid allows: periodic axes wrap, other axes clamp to the edge cell and keep
@@ -134,6 +148,28 @@ __device__ __forceinline__ double absolute(const ScenePar &P, int lin, double of
 __device__ __forceinline__ float get4(float4 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
 __device__ __forceinline__ double get4(double4 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
 
+// Reduction over the whole block (blockDim a multiple of 64); the result is
+// returned to every thread.  sh holds one value per wavefront.
+template <typename T, typename Op>
+__device__ __forceinline__ T block_reduce(T v, Op op, T *sh) {
+  for (int m = 32; m > 0; m >>= 1) v = op(v, __shfl_xor(v, m));
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  T r = sh[0];
+  for (int k = 1; k < nw; ++k) r = op(r, sh[k]);
+  return r;
+}
+
+// True in every thread when all threads of the block pass the same key.
+__device__ __forceinline__ bool block_uniform(int key, int *sh) {
+  __syncthreads();
+  if (threadIdx.x == 0) *sh = key;
+  __syncthreads();
+  return __syncthreads_and(key == *sh) != 0;
+}
+
 // atomic max of a non-negative float through its bit pattern
 __device__ __forceinline__ void atomic_max_pos(unsigned int *addr, float v) {
   atomicMax(addr, __float_as_uint(v));
@@ -170,6 +206,7 @@ __global__ void k_init_fluid(Dev D, int s, const double *x, const double *v, int
   D.f_va[gi] = make_float4(vv[0], vv[1], vv[2], (float)eps);
   D.f_speed[gi] = sqrtf(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
   D.f_nnb[gi] = make_int4(0, 0, 0, 0);
+  D.f_rowlen[gi] = make_int2(0, 0);
   D.f_vb[gi] = D.f_va[gi];
   D.f_acc[gi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   D.f_drho[gi] = 0.0f;
@@ -376,8 +413,8 @@ __global__ void k_refresh_vmax(Dev D) {
 //
 // A rebuild runs for the scenes whose need_rebuild flag is set (set at the end
 // of the acoustic step that closes an advection step, or by a state write);
-// the five kernels below test the flag and exit at once otherwise, and the
-// solid kernel at the end of the step clears it.
+// the kernels below test the flag and exit at once otherwise, and the
+// step-close kernel at the end of the step clears it.
 
 // Bin the fluid and the boundary sources (walls, free solid) of rebuilding
 // scenes: new cell and offset from the current position, slot within the
@@ -433,57 +470,134 @@ __global__ void __launch_bounds__(256) k_bin(Dev D) {
   D.bs_slot[q] = atomicAdd(&D.bc_count[P.cell_begin + lin], 1);
 }
 
-// One block per rebuilding scene: advection time step (Section 3.2,
-// dt_ad = cfl_ad min(h / max(|v|max, U_ref), h^2 rho0 / eta)), then an
-// exclusive scan of the cell counts in Morton order giving each cell's
-// [start, end); counts are reset for the next rebuild.
-__global__ void __launch_bounds__(1024) k_scan_cells(Dev D) {
-  __shared__ int sf[1024], sb[1024];
-  int s = blockIdx.x;
-  SceneState &S = D.st[s];
-  if (!S.need_rebuild) return;
-  const ScenePar &P = D.par[s];
-  if (threadIdx.x == 0) {
-    double vm = fmax((double)__uint_as_float(S.vmax_prev), (double)P.u_ref);
-    double dt = (double)P.cfl_ad * (double)P.hf / vm;
-    if (P.dt_visc > 0.0) dt = fmin(dt, P.dt_visc);
-    S.dt_ad = dt;
-    S.adv_accum = 0.0;
-    S.rebuilds += 1;
-    S.n_ff = S.n_fw = S.n_fs = 0;
+// Cell scan of the rebuilding scenes: every cell's [start, end) in the sorted
+// fluid and boundary arrays, cells in Morton order within each scene.  The
+// cells of all scenes form one rank space (scene s owns [cell_begin,
+// cell_begin + ncell_total)); it is cut into tiles of kCellTile cells: tile
+// sums, an exclusive scan of the tile sums, then a scan inside each tile.
+// Scenes that do not rebuild hold zero counts, so a rebuilding scene's
+// entries start at its f_begin / b_begin plus the prefix from its first cell.
+
+// true when a tile holds cells of a rebuilding scene
+__device__ __forceinline__ bool tile_rebuilds(const Dev &D, int g0, int g1) {
+  int s0 = D.cell_scene[g0], s1 = D.cell_scene[g1 - 1];
+  for (int s = s0; s <= s1; ++s)
+    if (D.st[s].need_rebuild) return true;
+  return false;
+}
+
+__global__ void __launch_bounds__(1024) k_cell_sum(Dev D) {
+  __shared__ int shf[16], shb[16];
+  const int g0 = blockIdx.x * kCellTile, g1 = min(D.ncell, g0 + kCellTile);
+  if (!tile_rebuilds(D, g0, g1)) {
+    if (threadIdx.x == 0) D.cell_part[blockIdx.x] = make_int2(0, 0);
+    return;
   }
-  int n = P.ncell_total, cb = P.cell_begin;
-  int T = blockDim.x, t = threadIdx.x;
-  int chunk = (n + T - 1) / T;
-  int r0 = min(n, t * chunk), r1 = min(n, r0 + chunk);
   int lf = 0, lb = 0;
-  for (int r = r0; r < r1; ++r) {
-    int lin = D.rank_to_lin[cb + r];
-    lf += D.fc_count[cb + lin];
-    lb += D.bc_count[cb + lin];
+  for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+    int c = D.par[D.cell_scene[g]].cell_begin + D.rank_to_lin[g];
+    lf += D.fc_count[c];
+    lb += D.bc_count[c];
+  }
+  auto add = [](int a, int b) { return a + b; };
+  lf = block_reduce(lf, add, shf);
+  lb = block_reduce(lb, add, shb);
+  if (threadIdx.x == 0) D.cell_part[blockIdx.x] = make_int2(lf, lb);
+}
+
+// One block: per-scene bookkeeping of the rebuild (advection time step,
+// Section 3.2: dt_ad = cfl_ad min(h / max(|v|max, U_ref), h^2 rho0 / eta)),
+// the scan prefix at each scene's first cell, and the exclusive scan of the
+// tile sums.
+__global__ void __launch_bounds__(1024) k_cell_prefix(Dev D, int ntiles) {
+  __shared__ int sf[1024], sb[1024];
+  __shared__ int carry[2];
+  const int t = threadIdx.x, T = blockDim.x;
+  if (t == 0) {
+    int bf = 0, bb = 0;
+    for (int s = 0; s < D.n_scenes; ++s) {
+      SceneState &S = D.st[s];
+      const ScenePar &P = D.par[s];
+      S.base_f = bf;
+      S.base_b = bb;
+      if (!S.need_rebuild) continue;
+      bf += P.f_count;
+      bb += P.b_count;
+      double vm = fmax((double)__uint_as_float(S.vmax_prev), (double)P.u_ref);
+      double dt = (double)P.cfl_ad * (double)P.hf / vm;
+      if (P.dt_visc > 0.0) dt = fmin(dt, P.dt_visc);
+      S.dt_ad = dt;
+      S.adv_accum = 0.0;
+      S.rebuilds += 1;
+    }
+    carry[0] = carry[1] = 0;
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < ntiles; c0 += T) {
+    int k = c0 + t;
+    int2 v = k < ntiles ? D.cell_part[k] : make_int2(0, 0);
+    sf[t] = v.x;
+    sb[t] = v.y;
+    __syncthreads();
+    for (int w = 1; w < T; w <<= 1) {
+      int af = t >= w ? sf[t - w] : 0, ab = t >= w ? sb[t - w] : 0;
+      __syncthreads();
+      sf[t] += af;
+      sb[t] += ab;
+      __syncthreads();
+    }
+    if (k < ntiles) D.cell_part[k] = make_int2(carry[0] + sf[t] - v.x, carry[1] + sb[t] - v.y);
+    __syncthreads();
+    if (t == T - 1) {
+      carry[0] += sf[t];
+      carry[1] += sb[t];
+    }
+    __syncthreads();
+  }
+}
+
+// Each tile: scan of its cells (kCellTile / blockDim consecutive cells per
+// thread), [start, end) of every cell of a rebuilding scene; counts reset.
+__global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
+  __shared__ int sf[1024], sb[1024];
+  const int g0 = blockIdx.x * kCellTile, g1 = min(D.ncell, g0 + kCellTile);
+  if (!tile_rebuilds(D, g0, g1)) return;
+  const int t = threadIdx.x, T = blockDim.x;
+  const int per = kCellTile / T;
+  const int gs = g0 + t * per, ge = min(g1, gs + per);
+  int lf = 0, lb = 0;
+  for (int g = gs; g < ge; ++g) {
+    int c = D.par[D.cell_scene[g]].cell_begin + D.rank_to_lin[g];
+    lf += D.fc_count[c];
+    lb += D.bc_count[c];
   }
   sf[t] = lf;
   sb[t] = lb;
   __syncthreads();
-  // inclusive Hillis-Steele scan
   for (int w = 1; w < T; w <<= 1) {
-    int vf = t >= w ? sf[t - w] : 0;
-    int vb = t >= w ? sb[t - w] : 0;
+    int af = t >= w ? sf[t - w] : 0, ab = t >= w ? sb[t - w] : 0;
     __syncthreads();
-    sf[t] += vf;
-    sb[t] += vb;
+    sf[t] += af;
+    sb[t] += ab;
     __syncthreads();
   }
-  int pf = P.f_begin + sf[t] - lf, pb = P.b_begin + sb[t] - lb;
-  for (int r = r0; r < r1; ++r) {
-    int lin = D.rank_to_lin[cb + r];
-    int cf = D.fc_count[cb + lin], cbn = D.bc_count[cb + lin];
-    D.fc_se[cb + lin] = make_int2(pf, pf + cf);
-    D.bc_se[cb + lin] = make_int2(pb, pb + cbn);
+  int2 base = D.cell_part[blockIdx.x];
+  int pf = base.x + sf[t] - lf, pb = base.y + sb[t] - lb;
+  for (int g = gs; g < ge; ++g) {
+    int s = D.cell_scene[g];
+    const ScenePar &P = D.par[s];
+    const SceneState &S = D.st[s];
+    int c = P.cell_begin + D.rank_to_lin[g];
+    int cf = D.fc_count[c], cbn = D.bc_count[c];
+    if (S.need_rebuild) {
+      int f0 = P.f_begin + pf - S.base_f, b0 = P.b_begin + pb - S.base_b;
+      D.fc_se[c] = make_int2(f0, f0 + cf);
+      D.bc_se[c] = make_int2(b0, b0 + cbn);
+      D.fc_count[c] = 0;
+      D.bc_count[c] = 0;
+    }
     pf += cf;
     pb += cbn;
-    D.fc_count[cb + lin] = 0;
-    D.bc_count[cb + lin] = 0;
   }
 }
 
@@ -639,6 +753,11 @@ __device__ __forceinline__ T group_sum(T v) {
 // The sum is an FP64 island: the pressure that follows is rho0 c^2 times the
 // relative excess of psi, so FP32 rounding of W or of positions would appear
 // as pressure noise; distances come from the FP64 frozen offsets.
+// The same pass writes the pair lists that the force and continuity passes
+// walk until the next rebuild (pair geometry is frozen over an advection
+// step, Section 3.2).  The LPP lanes of a particle test LPP candidates at a
+// time and give their matches consecutive entries (a wavefront ballot ranks
+// them), so each row is dense in visiting order whatever LPP is.
 template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_reinit(Dev D) {
   int g = particle_index();
@@ -648,6 +767,18 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
   if (active && !D.st[s].need_rebuild) active = false;
   double psi = 0.0;
   unsigned long long nff = 0, nfw = 0, nfs = 0;
+  int lenf = 0, lenb = 0;  // the particle's row lengths so far (equal in its LPP lanes)
+  const size_t lstride = (size_t)D.nf * LPP;
+  unsigned *lf = D.f_nbl + (size_t)i * LPP, *lb = D.f_bnl + (size_t)i * LPP;
+  const int gsh = __lane_id() & ~(LPP - 1);  // first lane of this particle's group
+  const unsigned below = (1u << q) - 1u;
+  // rank of this lane's match among the group's matches of this round
+  auto rank_hits = [&](bool hit, int &len) {
+    unsigned grp = (unsigned)(__ballot(hit) >> gsh) & ((1u << LPP) - 1u);
+    int e = len + __popc(grp & below);
+    len += __popc(grp);
+    return e;
+  };
   if (active) {
     const ScenePar &P = D.par[s];
     float4 pi = D.f_pos[i];
@@ -662,39 +793,55 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
     };
     if (q == 0) psi = Vf * alpha;
     int cb = P.cell_begin;
-    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh) {
+    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh, int cid) {
+      const unsigned tag = (unsigned)cid << kNbrBits;
       // the same cell offset in FP64 (sh is an exact multiple of the FP32 cell size)
       double shd[3];
       for (int k = 0; k < 3; ++k) shd[k] = (double)(sh[k] / P.cs[k]) * P.csd[k];
       int2 se = D.fc_se[cb + nl];
-      for (int j = se.x + q; j < se.y; j += LPP) {
-        if (j == i) continue;
-        float4 pj = D.f_pos[j];
-        // pair membership decided in FP32 exactly as in the force passes
-        float rx = (pi.x - pj.x) - sh[0], ry = (pi.y - pj.y) - sh[1];
-        float rz = DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f;
-        float r2 = rx * rx + ry * ry + rz * rz;
-        if (r2 >= P.r2max_f) continue;
-        double4 qj = D.f_posd[j];
-        double dx = (qi.x - qj.x) - shd[0], dy = (qi.y - qj.y) - shd[1];
-        double dz = DIM == 3 ? (qi.z - qj.z) - shd[2] : 0.0;
-        psi += Vf * W64(sqrt(dx * dx + dy * dy + dz * dz));
-        nff++;
+      for (int j0 = se.x; j0 < se.y; j0 += LPP) {
+        int j = j0 + q;
+        bool hit = false;
+        if (j < se.y && j != i) {
+          float4 pj = D.f_pos[j];
+          // pair membership decided in FP32 exactly as in the force passes
+          float rx = (pi.x - pj.x) - sh[0], ry = (pi.y - pj.y) - sh[1];
+          float rz = DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f;
+          float r2 = rx * rx + ry * ry + rz * rz;
+          if (r2 < P.r2max_f) {
+            double4 qj = D.f_posd[j];
+            double dx = (qi.x - qj.x) - shd[0], dy = (qi.y - qj.y) - shd[1];
+            double dz = DIM == 3 ? (qi.z - qj.z) - shd[2] : 0.0;
+            psi += Vf * W64(sqrt(dx * dx + dy * dy + dz * dz));
+            nff++;
+            hit = true;
+          }
+        }
+        int e = rank_hits(hit, lenf);
+        if (hit && e < D.capf) lf[(size_t)(e / LPP) * lstride + e % LPP] = tag | (unsigned)j;
       }
       int2 be = D.bc_se[cb + nl];
-      for (int k = be.x + q; k < be.y; k += LPP) {
-        float4 pb = D.b_pos[k];
-        float rx = (pi.x - pb.x) - sh[0], ry = (pi.y - pb.y) - sh[1];
-        float rz = DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f;
-        float r2 = rx * rx + ry * ry + rz * rz;
-        if (r2 >= P.r2max_f) continue;
-        double4 qb = D.b_posd[k];
-        double dx = (qi.x - qb.x) - shd[0], dy = (qi.y - qb.y) - shd[1];
-        double dz = DIM == 3 ? (qi.z - qb.z) - shd[2] : 0.0;
-        bool wall = D.b_nrm[k].w > 0.0f;
-        psi += (wall ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy + dz * dz));
-        if (wall) nfw++;
-        else nfs++;
+      for (int k0 = be.x; k0 < be.y; k0 += LPP) {
+        int k = k0 + q;
+        bool hit = false;
+        if (k < be.y) {
+          float4 pb = D.b_pos[k];
+          float rx = (pi.x - pb.x) - sh[0], ry = (pi.y - pb.y) - sh[1];
+          float rz = DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f;
+          float r2 = rx * rx + ry * ry + rz * rz;
+          if (r2 < P.r2max_f) {
+            double4 qb = D.b_posd[k];
+            double dx = (qi.x - qb.x) - shd[0], dy = (qi.y - qb.y) - shd[1];
+            double dz = DIM == 3 ? (qi.z - qb.z) - shd[2] : 0.0;
+            bool wall = D.b_nrm[k].w > 0.0f;
+            psi += (wall ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy + dz * dz));
+            if (wall) nfw++;
+            else nfs++;
+            hit = true;
+          }
+        }
+        int e = rank_hits(hit, lenb);
+        if (hit && e < D.capb) lb[(size_t)(e / LPP) * lstride + e % LPP] = tag | (unsigned)k;
       }
     });
   }
@@ -706,6 +853,8 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
   if (lead) {
     const ScenePar &P = D.par[s];
     D.f_nnb[i] = make_int4((int)nff, (int)nfw, (int)nfs, 0);
+    D.f_rowlen[i] = make_int2(min(lenf, D.capf), min(lenb, D.capb));
+    if (lenf > D.capf || lenb > D.capb) atomicOr(&D.st[s].err, (int)ERR_CAPACITY);
     if (P.reinit) {
       float4 va = D.f_va[i];
       double e = psi / P.psi0d - 1.0;
@@ -741,16 +890,19 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
   float Vi = mi / rhoi;
   float vi[3] = {va.x, va.y, va.z};
   float fsum[3] = {0.0f, 0.0f, 0.0f};
-  int cb = P.cell_begin;
   if (active) {
-    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh) {
-      int2 se = D.fc_se[cb + nl];
-      for (int j = se.x + q; j < se.y; j += LPP) {
-        if (j == i) continue;
+    const int2 rl = D.f_rowlen[i];
+    const size_t lstride = (size_t)D.nf * LPP;
+    const unsigned *lp = D.f_nbl + (size_t)i * LPP + q;
+    for (int e = q; e < rl.x; e += LPP, lp += lstride) {
+      unsigned ent = *lp;
+      int j = (int)(ent & kNbrMask);
+      float sh[3];
+      cell_shift<DIM>(P, (int)(ent >> kNbrBits), sh);
+      {
         float4 pj = D.f_pos[j];
         float r[3] = {(pi.x - pj.x) - sh[0], (pi.y - pj.y) - sh[1], DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f};
         float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        if (r2 >= P.r2max_f) continue;
         float4 vj4 = D.f_va[j];
         float ehj = vj4.w + 0.5f * dt * D.f_drho[j];
         float rhoj = P.rho0 * (1.0f + ehj);
@@ -767,17 +919,19 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
         float cvisc = 2.0f * P.eta * VV * inv_r;
         for (int k = 0; k < DIM; ++k) fsum[k] += cpress * e[k] + cvisc * (vi[k] - vj[k]);
       }
-      int2 be = D.bc_se[cb + nl];
-      for (int k = be.x + q; k < be.y; k += LPP) {
-        float4 pb = D.b_pos[k];
-        float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
-        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        if (r2 >= P.r2max_f) continue;
-        float f[3];
-        coupling_force<DIM>(P, mi, ehi, p_i, vi, r, pb, D.b_vbar[k], D.b_nrm[k], f);
-        for (int c = 0; c < DIM; ++c) fsum[c] += f[c];
-      }
-    });
+    }
+    lp = D.f_bnl + (size_t)i * LPP + q;
+    for (int e = q; e < rl.y; e += LPP, lp += lstride) {
+      unsigned ent = *lp;
+      int k = (int)(ent & kNbrMask);
+      float sh[3];
+      cell_shift<DIM>(P, (int)(ent >> kNbrBits), sh);
+      float4 pb = D.b_pos[k];
+      float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
+      float f[3];
+      coupling_force<DIM>(P, mi, ehi, p_i, vi, r, pb, D.b_vbar[k], D.b_nrm[k], f);
+      for (int c = 0; c < DIM; ++c) fsum[c] += f[c];
+    }
   }
   for (int k = 0; k < DIM; ++k) fsum[k] = group_sum<LPP>(fsum[k]);
   if (!active || q != 0) return;
@@ -816,7 +970,7 @@ __global__ void __launch_bounds__(256) k_couple(Dev D) {
   if (active && local < P.s_count - P.s_nclamp && k >= 0) {
     float4 pb = D.b_pos[k], bv = D.b_vbar[k], bn = D.b_nrm[k];
     int cb = P.cell_begin;
-    visit_cells<DIM>(P, D.s_blin[a], [&](int nl, const float *sh) {
+    visit_cells<DIM>(P, D.s_blin[a], [&](int nl, const float *sh, int) {
       int2 se = D.fc_se[cb + nl];
       for (int i = se.x + q; i < se.y; i += LPP) {
         float4 pi = D.f_pos[i];
@@ -858,16 +1012,19 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
   float p_i = D.f_p[ii];
   float vi[3] = {vb.x, vb.y, vb.z};
   float drho = 0.0f;
-  int cb = P.cell_begin;
   if (active) {
-    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh) {
-      int2 se = D.fc_se[cb + nl];
-      for (int j = se.x + q; j < se.y; j += LPP) {
-        if (j == i) continue;
+    const int2 rl = D.f_rowlen[i];
+    const size_t lstride = (size_t)D.nf * LPP;
+    const unsigned *lp = D.f_nbl + (size_t)i * LPP + q;
+    for (int e = q; e < rl.x; e += LPP, lp += lstride) {
+      unsigned ent = *lp;
+      int j = (int)(ent & kNbrMask);
+      float sh[3];
+      cell_shift<DIM>(P, (int)(ent >> kNbrBits), sh);
+      {
         float4 pj = D.f_pos[j];
         float r[3] = {(pi.x - pj.x) - sh[0], (pi.y - pj.y) - sh[1], DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f};
         float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        if (r2 >= P.r2max_f) continue;
         float4 vj4 = D.f_vb[j];
         float rhoj = P.rho0 * (1.0f + vj4.w);
         float p_j = D.f_p[j];
@@ -879,12 +1036,17 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
         float vj[3] = {vj4.x, vj4.y, vj4.z};
         drho += 2.0f * rhoi * Vj * riemann_dv_dot_e<DIM>(P, rhoi, rhoj, p_i, p_j, vi, vj, e) * dW;
       }
-      int2 be = D.bc_se[cb + nl];
-      for (int k = be.x + q; k < be.y; k += LPP) {
+    }
+    lp = D.f_bnl + (size_t)i * LPP + q;
+    for (int e = q; e < rl.y; e += LPP, lp += lstride) {
+      unsigned ent = *lp;
+      int k = (int)(ent & kNbrMask);
+      float sh[3];
+      cell_shift<DIM>(P, (int)(ent >> kNbrBits), sh);
+      {
         float4 pb = D.b_pos[k];
         float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
         float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        if (r2 >= P.r2max_f) continue;
         float4 bv = D.b_vbar[k];
         float rr = sqrtf(r2);
         float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
@@ -892,7 +1054,7 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
         if (DIM == 3) dv += (vi[2] - bv.z) * r[2];
         drho += rhoi * pb.w * (dv / rr) * dW;
       }
-    });
+    }
   }
   drho = group_sum<LPP>(drho);
   bool lead = active && q == 0;
@@ -934,73 +1096,37 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
 
 constexpr int KAPPA_MAX = 4096;
 
-// End of an acoustic step for one scene (whole block): max fluid speed for the
-// next acoustic step and, after a rebuild, the scene's pair counts, both
-// reduced from per-particle values; then thread 0 closes the step (time,
-// advection accumulator, rebuild flag, next dt_ac, counters).
-__device__ void solid_step_end(const Dev &D, const ScenePar &P, SceneState &S, float (*red)[1024], int kap,
-                               double dt_ac, int t, int T) {
-  // max fluid speed of the scene (next acoustic step) and, after a rebuild,
-  // the scene's pair counts, reduced from per-particle values
-  {
-    const bool rebuilt = S.need_rebuild != 0;
-    float m = 0.0f;
-    unsigned long long cff = 0, cfw = 0, cfs = 0;
-    for (int l = t; l < P.f_count; l += T) {
-      int i = P.f_begin + l;
-      m = fmaxf(m, D.f_speed[i]);
-      if (rebuilt) {
-        int4 c = D.f_nnb[i];
-        cff += c.x;
-        cfw += c.y;
-        cfs += c.z;
-      }
-    }
-    __syncthreads();
-    red[0][t] = m;
-    __syncthreads();
-    for (int w = pow2_ceil(T) / 2; w > 0; w >>= 1) {
-      if (t < w && t + w < T) red[0][t] = fmaxf(red[0][t], red[0][t + w]);
-      __syncthreads();
-    }
-    if (rebuilt) {
-      // 64-bit sums through the LDS of the float buffer (reused as integers)
-      unsigned long long *ured = reinterpret_cast<unsigned long long *>(&red[1][0]);
-      for (int which = 0; which < 3; ++which) {
-        unsigned long long v = which == 0 ? cff : (which == 1 ? cfw : cfs);
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
-        __syncthreads();
-        if ((t & 63) == 0) ured[t >> 6] = v;
-        __syncthreads();
-        if (t == 0) {
-          unsigned long long tot = 0;
-          for (int w = 0; w < (T + 63) / 64; ++w) tot += ured[w];
-          if (which == 0) S.n_ff = tot;
-          else if (which == 1) S.n_fw = tot;
-          else S.n_fs = tot;
-        }
-      }
-      __syncthreads();
-    }
-    if (t == 0) S.vmax_next = __float_as_uint(red[0][0]);
+// Close of an acoustic step, one thread per scene (after k_step_reduce):
+// time, advection accumulator and rebuild flag, next acoustic time step from
+// the reduced max fluid speed (Section 3.2), pair counts after a rebuild and
+// the interaction counters.
+__global__ void k_step_close(Dev D) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= D.n_scenes) return;
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  const bool rebuilt = S.need_rebuild != 0;  // the rebuild kernels of this step ran
+  if (rebuilt) {
+    S.n_ff = S.acc_ff;
+    S.n_fw = S.acc_fw;
+    S.n_fs = S.acc_fs;
+    S.acc_ff = S.acc_fw = S.acc_fs = 0ull;
   }
-  if (t == 0) {
-    bool rebuilt = S.need_rebuild != 0;  // the rebuild kernels of this step ran
-    unsigned long long inter = 2ull * (S.n_ff + S.n_fw + S.n_fs) + S.n_fs + 2ull * (unsigned long long)kap * S.n_ss;
-    if (rebuilt && P.reinit) inter += S.n_ff + S.n_fw + S.n_fs;
-    S.interactions += inter;
-    S.substeps += kap;
-    S.steps += 1;
-    S.t += dt_ac;
-    S.adv_accum += dt_ac;
-    S.need_rebuild = S.adv_accum >= S.dt_ad ? 1 : 0;
-    float vmax = __uint_as_float(S.vmax_next);
-    S.vmax_prev = S.vmax_next;
-    S.vmax_next = 0u;
-    S.dt_ac = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)vmax);
-  }
+  const int kap = S.kappa;
+  const double dt_ac = S.dt_ac;
+  unsigned long long inter = 2ull * (S.n_ff + S.n_fw + S.n_fs) + S.n_fs + 2ull * (unsigned long long)kap * S.n_ss;
+  if (rebuilt && P.reinit) inter += S.n_ff + S.n_fw + S.n_fs;
+  S.interactions += inter;
+  S.substeps += kap;
+  S.steps += 1;
+  S.t += dt_ac;
+  S.adv_accum += dt_ac;
+  S.need_rebuild = S.adv_accum >= S.dt_ad ? 1 : 0;
+  float vmax = __uint_as_float(S.vmax_next);
+  S.vmax_prev = S.vmax_next;
+  S.vmax_next = 0u;
+  S.dt_ac = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)vmax);
 }
-
 
 // kappa solid sub-steps of the position-based Verlet scheme (Section 3.3,
 // Eqs. verlet-*-solid), the fluid force held constant:
@@ -1017,18 +1143,19 @@ __device__ void solid_step_end(const Dev &D, const ScenePar &P, SceneState &S, f
 // Streamed form for solids of any size: one kernel per phase over all solid
 // particles of all scenes (a scene past its own kappa skips the pass).
 
-// Solid time step and kappa of each scene (one block per scene); the
-// step increments are cleared.
-__global__ void __launch_bounds__(1024) k_solid_dt(Dev D) {
-  __shared__ float red[2][1024];
-  int s = blockIdx.x;
+// Solid time step and kappa of each scene: max |v| and |a| of the free solid
+// over all solid particles (one atomic per block and scene), the step
+// increments cleared; then k_solid_dt_close, one thread per scene.
+__global__ void __launch_bounds__(256) k_solid_dt_reduce(Dev D) {
+  __shared__ float shv[16], sha[16];
+  __shared__ int key;
+  const int dim = D.dim, NS = D.ns;
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  bool act = a < NS;
+  int s = D.s_scene[act ? a : blockIdx.x * blockDim.x];
   const ScenePar &P = D.par[s];
-  SceneState &S = D.st[s];
-  const int NS = D.ns, T = blockDim.x, t = threadIdx.x, dim = D.dim;
-  const int nfree = P.s_count - P.s_nclamp;
   float vm = 0.0f, am = 0.0f;
-  for (int l = t; l < P.s_count; l += T) {
-    int a = P.s_begin + l;
+  if (act) {
     float v2 = 0.0f, a2 = 0.0f;
     for (int k = 0; k < dim; ++k) {
       float v = (float)D.s_v[k * NS + a], q = D.s_a[k * NS + a];
@@ -1037,37 +1164,51 @@ __global__ void __launch_bounds__(1024) k_solid_dt(Dev D) {
       D.s_du[k * NS + a] = 0.0;
       D.s_dv[k * NS + a] = 0.0;
     }
-    if (l < nfree) {
-      vm = fmaxf(vm, sqrtf(v2));
-      am = fmaxf(am, sqrtf(a2));
+    if (a - P.s_begin < P.s_count - P.s_nclamp) {
+      vm = sqrtf(v2);
+      am = sqrtf(a2);
     }
   }
-  red[0][t] = vm;
-  red[1][t] = am;
-  __syncthreads();
-  for (int w = pow2_ceil(T) / 2; w > 0; w >>= 1) {
-    if (t < w && t + w < T) {
-      red[0][t] = fmaxf(red[0][t], red[0][t + w]);
-      red[1][t] = fmaxf(red[1][t], red[1][t + w]);
+  SceneState &S = D.st[s];
+  auto fmx = [](float x, float y) { return fmaxf(x, y); };
+  if (block_uniform(s, &key)) {
+    vm = block_reduce(vm, fmx, shv);
+    am = block_reduce(am, fmx, sha);
+    if (threadIdx.x == 0) {
+      atomic_max_pos(&S.smax_v, vm);
+      atomic_max_pos(&S.smax_a, am);
     }
-    __syncthreads();
+  } else if (act) {
+    atomic_max_pos(&S.smax_v, fmaxf(vm, 0.0f));
+    atomic_max_pos(&S.smax_a, fmaxf(am, 0.0f));
   }
-  if (t == 0) {
-    double dt_ac = S.dt_ac;
-    double dts = (double)P.cfl_s * (double)P.hs / ((double)P.c_s + (double)red[0][0]);
-    if (red[1][0] > 0.0f) dts = fmin(dts, (double)P.cfl_s * sqrt((double)P.hs / (double)red[1][0]));
-    // kappa is bounded: a collapsed solid step is reported, not iterated
-    double ratio = dt_ac / dts;
-    int kap;
-    if (!(ratio >= 0.0) || !(dt_ac > 0.0) || ratio > (double)(KAPPA_MAX - 1)) {
-      kap = (ratio >= 0.0 && dt_ac > 0.0) ? KAPPA_MAX : 1;
-      atomicOr(&S.err, (int)ERR_NAN_SOLID);
-    } else {
-      kap = (int)floor(ratio) + 1;
-    }
-    S.dt_s = dts;
-    S.kappa = kap;
+}
+
+// dt_S = cfl_s min(h_S / (c_S + |v|max), sqrt(h_S / |a|max)), kappa =
+// floor(dt_ac / dt_S) + 1 (bounded: a collapsed solid step is reported).
+__device__ __forceinline__ void solid_kappa(const ScenePar &P, SceneState &S, float vmax, float amax, double dt_ac,
+                                            int &kap, double &dts) {
+  dts = (double)P.cfl_s * (double)P.hs / ((double)P.c_s + (double)vmax);
+  if (amax > 0.0f) dts = fmin(dts, (double)P.cfl_s * sqrt((double)P.hs / (double)amax));
+  double ratio = dt_ac / dts;
+  if (!(ratio >= 0.0) || !(dt_ac > 0.0) || ratio > (double)(KAPPA_MAX - 1)) {
+    kap = (ratio >= 0.0 && dt_ac > 0.0) ? KAPPA_MAX : 1;
+    atomicOr(&S.err, (int)ERR_NAN_SOLID);
+  } else {
+    kap = (int)floor(ratio) + 1;
   }
+}
+
+__global__ void k_solid_dt_close(Dev D) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= D.n_scenes) return;
+  SceneState &S = D.st[s];
+  int kap;
+  double dts;
+  solid_kappa(D.par[s], S, __uint_as_float(S.smax_v), __uint_as_float(S.smax_a), S.dt_ac, kap, dts);
+  S.dt_s = dts;
+  S.kappa = kap;
+  S.smax_v = S.smax_a = 0u;
 }
 
 // First half of a sub-step for particle a (own state only), and its stress.
@@ -1280,16 +1421,9 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
     __syncthreads();
   }
   if (t == 0) {
-    double dts = (double)P.cfl_s * (double)P.hs / ((double)P.c_s + (double)red[0][0]);
-    if (red[1][0] > 0.0f) dts = fmin(dts, (double)P.cfl_s * sqrt((double)P.hs / (double)red[1][0]));
-    double ratio = dt_ac / dts;
     int kap;
-    if (!(ratio >= 0.0) || !(dt_ac > 0.0) || ratio > (double)(KAPPA_MAX - 1)) {
-      kap = (ratio >= 0.0 && dt_ac > 0.0) ? KAPPA_MAX : 1;
-      atomicOr(&S.err, (int)ERR_NAN_SOLID);
-    } else {
-      kap = (int)floor(ratio) + 1;
-    }
+    double dts;
+    solid_kappa(P, S, red[0][0], red[1][0], dt_ac, kap, dts);
     kap_sh = kap;
     del_sh = dt_ac / kap;
     S.dt_s = dts;
@@ -1436,42 +1570,80 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
   }
 }
 
-// End of an acoustic step, one block per scene: the solid's averaged
-// velocity and acceleration and its current volume are handed to the
-// boundary particles seen by the fluid (with the hydrostatic factor
-// max(0, (abar - g).n)), then the scene's step is closed.  Kept apart from the
-// sub-step kernel so that the continuity pass, which reads the boundary
-// particles, can run concurrently with the coupling and solid passes.
+// End of an acoustic step over all particles, before k_step_close.  Fluid
+// blocks: max fluid speed for the next acoustic step and, after a rebuild,
+// the pair counts, folded into the scene's accumulators with one atomic per
+// block (per thread where a block spans two scenes).  Solid blocks: the
+// solid's averaged velocity and acceleration and its current volume are
+// handed to the boundary particles seen by the fluid, with the hydrostatic
+// factor max(0, (abar - g).n).  Kept apart from the sub-step kernels so that
+// the continuity pass, which reads the boundary particles, can run
+// concurrently with the coupling and solid passes.
 template <int DIM>
-__global__ void __launch_bounds__(1024) k_step_end(Dev D) {
-  __shared__ float red[2][1024];
-  int s = blockIdx.x;
-  const ScenePar &P = D.par[s];
-  SceneState &S = D.st[s];
-  const int NS = D.ns, T = blockDim.x, t = threadIdx.x;
-  const int nfree = P.s_count - P.s_nclamp;
-  for (int l = t; l < nfree; l += T) {
-    int a = P.s_begin + l;
-    int kslot = D.s_bslot[a];
-    if (kslot < 0) continue;
-    double H[9];
-    for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
-    double J;
-    if (DIM == 2) J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
-    else
-      J = (1.0 + H[0]) * ((1.0 + H[4]) * (1.0 + H[8]) - H[5] * H[7]) - H[1] * (H[3] * (1.0 + H[8]) - H[5] * H[6]) +
-          H[2] * (H[3] * H[7] - (1.0 + H[4]) * H[6]);
-    float vbar[3] = {0.0f, 0.0f, 0.0f}, sa = 0.0f;
-    for (int k = 0; k < DIM; ++k) {
-      vbar[k] = D.s_vbar[k * NS + a];
-      sa += (D.s_abar[k * NS + a] - P.g[k]) * D.s_n[k * NS + a];
+__global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
+  __shared__ float shm[16];
+  __shared__ unsigned long long shc[3][16];
+  __shared__ int key;
+  if ((int)blockIdx.x < fluid_blocks) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool act = i < D.nf;
+    int s = D.f_scene[act ? i : blockIdx.x * blockDim.x];
+    SceneState &S = D.st[s];
+    const bool rebuilt = S.need_rebuild != 0;
+    float m = act ? D.f_speed[i] : 0.0f;
+    m = fmaxf(m, 0.0f);  // a NaN speed is flagged by the continuity pass
+    unsigned long long c[3] = {0ull, 0ull, 0ull};
+    if (act && rebuilt) {
+      int4 n = D.f_nnb[i];
+      c[0] = (unsigned long long)n.x;
+      c[1] = (unsigned long long)n.y;
+      c[2] = (unsigned long long)n.z;
     }
-    float4 bp = D.b_pos[kslot];
-    bp.w = (float)(P.Vs * J);
-    D.b_pos[kslot] = bp;
-    D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
+    if (block_uniform(s, &key)) {
+      m = block_reduce(m, [](float x, float y) { return fmaxf(x, y); }, shm);
+      if (threadIdx.x == 0) atomic_max_pos(&S.vmax_next, m);
+      if (rebuilt) {
+        auto add = [](unsigned long long x, unsigned long long y) { return x + y; };
+        for (int k = 0; k < 3; ++k) c[k] = block_reduce(c[k], add, shc[k]);
+        if (threadIdx.x == 0) {
+          atomicAdd(&S.acc_ff, c[0]);
+          atomicAdd(&S.acc_fw, c[1]);
+          atomicAdd(&S.acc_fs, c[2]);
+        }
+      }
+    } else if (act) {
+      atomic_max_pos(&S.vmax_next, m);
+      if (rebuilt) {
+        atomicAdd(&S.acc_ff, c[0]);
+        atomicAdd(&S.acc_fw, c[1]);
+        atomicAdd(&S.acc_fs, c[2]);
+      }
+    }
+    return;
   }
-  solid_step_end(D, P, S, red, S.kappa, S.dt_ac, t, T);
+  const int NS = D.ns;
+  int a = (blockIdx.x - fluid_blocks) * blockDim.x + threadIdx.x;
+  if (a >= NS) return;
+  const ScenePar &P = D.par[D.s_scene[a]];
+  if (a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  int kslot = D.s_bslot[a];
+  if (kslot < 0) return;
+  double H[9];
+  for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
+  double J;
+  if (DIM == 2) J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
+  else
+    J = (1.0 + H[0]) * ((1.0 + H[4]) * (1.0 + H[8]) - H[5] * H[7]) - H[1] * (H[3] * (1.0 + H[8]) - H[5] * H[6]) +
+        H[2] * (H[3] * H[7] - (1.0 + H[4]) * H[6]);
+  float vbar[3] = {0.0f, 0.0f, 0.0f}, sa = 0.0f;
+  for (int k = 0; k < DIM; ++k) {
+    vbar[k] = D.s_vbar[k * NS + a];
+    sa += (D.s_abar[k * NS + a] - P.g[k]) * D.s_n[k * NS + a];
+  }
+  float4 bp = D.b_pos[kslot];
+  bp.w = (float)(P.Vs * J);
+  D.b_pos[kslot] = bp;
+  D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
 }
 
 // ------------------------------------------------------------------ state I/O
@@ -1645,7 +1817,7 @@ __global__ void __launch_bounds__(256) k_reduce_partial(Dev D, int s) {
     float vi[3] = {vb.x, vb.y, vb.z};
     float p_i = D.f_p[i];
     int cb = P.cell_begin;
-    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh2) {
+    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh2, int) {
       int2 be = D.bc_se[cb + nl];
       for (int k = be.x; k < be.y; ++k) {
         float4 bn = D.b_nrm[k];
@@ -1770,7 +1942,10 @@ static inline dim3 grid_for(long long threads, int block) {
 
 void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_bin, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
-  hipLaunchKernelGGL(k_scan_cells, dim3(D.n_scenes), dim3(1024), 0, st, D);
+  const int ntiles = (D.ncell + kCellTile - 1) / kCellTile;
+  hipLaunchKernelGGL(k_cell_sum, dim3(ntiles), dim3(1024), 0, st, D);
+  hipLaunchKernelGGL(k_cell_prefix, dim3(1), dim3(1024), 0, st, D, ntiles);
+  hipLaunchKernelGGL(k_cell_apply, dim3(ntiles), dim3(1024), 0, st, D);
   if (D.nf + D.nb > 0) hipLaunchKernelGGL(k_scatter, grid_for(D.nf + D.nb, 256), dim3(256), 0, st, D);
   if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_rank_move, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
   if (D.nf > 0)
@@ -1809,7 +1984,8 @@ void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
 }
 
 void launch_solid_dt(const Dev &D, hipStream_t st) {
-  hipLaunchKernelGGL(k_solid_dt, dim3(D.n_scenes), dim3(1024), 0, st, D);
+  if (D.ns > 0) hipLaunchKernelGGL(k_solid_dt_reduce, grid_for(D.ns, 256), dim3(256), 0, st, D);
+  hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
 }
 
 void launch_solid_first(const Dev &D, hipStream_t st) {
@@ -1827,7 +2003,9 @@ void launch_solid_average(const Dev &D, hipStream_t st) {
 }
 
 void launch_step_end(const Dev &D, hipStream_t st) {
-  LAUNCH_DIM(D.dim, k_step_end, dim3(D.n_scenes), dim3(1024), st, D);
+  int fb = (D.nf + 255) / 256, sb = (D.ns + 255) / 256;
+  if (fb + sb > 0) LAUNCH_DIM(D.dim, k_step_reduce, dim3(fb + sb), dim3(256), st, D, fb);
+  hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
 }
 
 int solid_lds_bytes_per_particle(int dim) { return (dim * dim + dim) * (int)sizeof(double); }

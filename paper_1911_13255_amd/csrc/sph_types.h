@@ -51,9 +51,11 @@ struct SceneState {
   double t, dt_ac, dt_ad, dt_s, adv_accum;
   int kappa, need_rebuild, pad2, err;
   unsigned int vmax_prev, vmax_next;  // max fluid speed (float bits): step start / being reduced
-  unsigned int pad0, pad1;
+  unsigned int smax_v, smax_a;        // max solid speed and acceleration (float bits) being reduced
   unsigned long long n_ff, n_fw, n_fs, n_ss;  // pairs within support at the last rebuild
   unsigned long long steps, rebuilds, substeps, interactions;
+  unsigned long long acc_ff, acc_fw, acc_fs;  // pair counts being reduced after a rebuild
+  int base_f, base_b;  // cell-scan prefix at the scene's first cell (rebuild)
 };
 
 enum ErrBits { ERR_NAN_FLUID = 1, ERR_NAN_SOLID = 2, ERR_JACOBIAN = 4, ERR_CAPACITY = 8 };
@@ -76,6 +78,14 @@ struct Dev {
   float *f_drho;   // d eps / dt kept for the next half step
   float *f_p;      // mid-step pressure
   int4 *f_nnb;     // fluid, wall and solid neighbours within 2 h_F at the last rebuild
+  // Pair lists of the advection step (geometry is frozen between rebuilds):
+  // entry = neighbour index | (relative cell id 0..26) << 27; rows are dense.
+  // Entry e of particle i sits at ((e / lw) * nf + i) * lw + e % lw, so the
+  // lw lanes sharing a particle read lw consecutive entries.
+  int capf, capb, lw;
+  unsigned *f_nbl;  // fluid neighbours (capf entries per particle)
+  unsigned *f_bnl;  // boundary neighbours: walls and free solid (capb per particle)
+  int2 *f_rowlen;  // used length of each particle's two rows
   float *f_speed;  // |v| after the last continuity pass (reduced per scene by the solid kernel)
   // fluid rebuild scratch (indexed by the old sorted index)
   int *fs_lin, *fs_slot, *fs_id, *f_perm, *f_pkey;
@@ -85,6 +95,7 @@ struct Dev {
   // cells
   int ncell;
   int *fc_count, *bc_count, *rank_to_lin, *cell_scene;
+  int2 *cell_part;  // per-tile sums and then exclusive prefixes of the cell scan
   int2 *fc_se, *bc_se;  // [start, end) of each cell, indexed by scene-local linear index + cell_begin
   // walls (static)
   int nw;

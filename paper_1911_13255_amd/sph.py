@@ -55,7 +55,7 @@ class SphScene(C.Structure):
 class SphOptions(C.Structure):
     _fields_ = [("riemann", C.c_int), ("density_reinit", C.c_int), ("max_solid_nbr", C.c_int),
                 ("solid_block", C.c_int), ("lanes_per_particle", C.c_int), ("block_pair", C.c_int),
-                ("solid_lds", C.c_int)]
+                ("solid_lds", C.c_int), ("max_fluid_nbr", C.c_int), ("max_boundary_nbr", C.c_int)]
 
 
 def exported_names():
@@ -134,7 +134,8 @@ class Simulation:
 
     def __init__(self, scenes, riemann: bool = True, density_reinit: int = 1,
                  max_solid_nbr: int = 0, solid_block: int = 0, lanes_per_particle: int = 0,
-                 block_pair: int = 0, solid_lds: int = 0, device: int = 0):
+                 block_pair: int = 0, solid_lds: int = 0, max_fluid_nbr: int = 0,
+                 max_boundary_nbr: int = 0, device: int = 0):
         import torch
 
         if isinstance(scenes, dict):
@@ -152,7 +153,8 @@ class Simulation:
             self._keep.append(keep)
         self._scenes = arr
         self.opt = SphOptions(int(riemann), int(density_reinit), int(max_solid_nbr), int(solid_block),
-                              int(lanes_per_particle), int(block_pair), int(solid_lds))
+                              int(lanes_per_particle), int(block_pair), int(solid_lds),
+                              int(max_fluid_nbr), int(max_boundary_nbr))
         nbytes = self.L.sph_arena_bytes(arr, self.n_scenes, C.byref(self.opt))
         if nbytes == 0:
             raise SphError(SPH_E_ARG, "invalid scene description")

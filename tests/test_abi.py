@@ -32,7 +32,7 @@ def test_arena_bytes_and_argument_checks():
     sc = scenes.dam_break_plate(seed=1)
     st, keep = sph.scene_struct(sc)
     arr = (sph.SphScene * 1)(st)
-    opt = sph.SphOptions(1, 1, 0, 0, 0, 0, 0)
+    opt = sph.SphOptions(1, 1, 0, 0, 0, 0, 0, 0, 0)
     n1 = L.sph_arena_bytes(arr, 1, ctypes.byref(opt))
     assert n1 > 0
     # more scenes need more memory
@@ -49,6 +49,12 @@ def test_arena_bytes_and_argument_checks():
     bad.periodic[0] = 1
     bad.hi[0] = bad.lo[0] + 0.02  # fewer than 3 cells of 2 h_F
     assert L.sph_arena_bytes((sph.SphScene * 1)(bad), 1, ctypes.byref(opt)) == 0
+    # pair-list capacities beyond the limit are rejected
+    big = sph.SphOptions(1, 1, 0, 0, 0, 0, 0, 5000, 0)
+    assert L.sph_arena_bytes(arr, 1, ctypes.byref(big)) == 0
+    # larger capacities need more memory
+    roomy = sph.SphOptions(1, 1, 0, 0, 0, 0, 0, 256, 512)
+    assert L.sph_arena_bytes(arr, 1, ctypes.byref(roomy)) > n1
     mixed = sph.SphScene.from_buffer_copy(st)
     mixed.dim = 3
     assert L.sph_arena_bytes((sph.SphScene * 2)(st, mixed), 2, ctypes.byref(opt)) == 0
