@@ -31,14 +31,23 @@ HBM_PEAK_GBS = 8000.0
 # x 2 flops (FMA) x 2.4 GHz (the packed-FP32 figure of 157.3 TFLOP/s is not
 # reachable by code built without packed FP32 instructions).
 ALU_PEAK_TFLOPS = 78.6
-# Algorithmic cost of the fluid momentum pass per fluid particle and per
-# within-support pair (2D / 3D): bytes of the particle's own state read and
-# written once, flops of one pair evaluation.
-FORCE_BYTES_PER_PARTICLE = {2: 52.0, 3: 72.0}
+# Algorithmic cost per unit of work (derivations in the design notes):
+#  fluid force pass: own state read once and written once (164 B per fluid
+#  particle) plus one 4-byte pair-list entry per pair; 70 flops per pair.
+#  continuity pass: 140 B per fluid particle plus 4 B per pair; 40 flops per pair.
+#  solid sub-step kernel (2D, register resident): the solid state read and
+#  written once per launch (270 B per free particle) and the reference
+#  neighbour table once (16 B per solid pair); per sub-step 33 flops per
+#  solid pair and pass direction and 200 flops per particle.
+FORCE_BYTES_PER_PARTICLE = 164.0
+CONT_BYTES_PER_PARTICLE = 140.0
+LIST_BYTES_PER_PAIR = 4.0
 FORCE_FLOPS_PER_PAIR = 70.0
+CONT_FLOPS_PER_PAIR = 40.0
+SOLID_BYTES_PER_PARTICLE = 270.0
+SOLID_BYTES_PER_PAIR = 16.0
 SOLID_FLOPS_PER_PAIR = 33.0
 SOLID_FLOPS_PER_PARTICLE = 200.0
-SOLID_BYTES_PER_PARTICLE = {2: 160.0, 3: 300.0}
 
 
 def make_workload(name):
@@ -53,6 +62,25 @@ def make_workload(name):
     if name == "batched_dam_breaks":
         return scenes.batched_dam_breaks(64)
     raise ValueError(name)
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (profiles/hbm_traffic.json), or None when the kernel source changed since
+    the counters were taken or the pair was not profiled."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_1911_13255_amd", "csrc", "sph_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    ent = rec.get("workloads", {}).get(workload, {}).get(kernel)
+    return None if ent is None else float(ent["bytes_per_launch"])
 
 
 def cpu_baseline(scene, seconds=15.0):
@@ -141,6 +169,8 @@ def main():
           f"{inter} interactions", file=sys.stderr, flush=True)
 
     # per-kernel durations (HIP events on the library's stream), after the timed region
+    # (isolated launches on the library's stream; inside the timed graph the
+    # continuity pass overlaps the coupling and solid passes)
     kt = {name: sim.time_kernel(k, args.kernel_reps) for name, k in
           (("k_fluid_force", sph.K_FLUID_FORCE), ("k_fluid_continuity", sph.K_CONTINUITY),
            ("k_couple", sph.K_COUPLE), ("k_solid", sph.K_SOLID))}
@@ -152,16 +182,22 @@ def main():
     nf = sum(len(s["x_fluid"]) for s in scs)
     ns_free = sum(len(s["x_solid"]) - int(s["n_clamp"]) for s in scs)
     pairs_f = c1["n_ff"] + c1["n_fw"] + c1["n_fs"]
-    dominant = max(("k_fluid_force", "k_solid"), key=lambda k: per_step[k])
-    if dominant == "k_fluid_force":
-        dur = kt["k_fluid_force"] * 1e-3
-        alg_bytes = FORCE_BYTES_PER_PARTICLE[dim] * nf
-        alg_flops = FORCE_FLOPS_PER_PAIR * pairs_f
-    else:
-        dur = kt["k_solid"] * 1e-3
-        kappa = (c1["substeps"] - c0["substeps"]) / max(1, c1["steps"] - c0["steps"])
-        alg_bytes = SOLID_BYTES_PER_PARTICLE[dim] * ns_free
-        alg_flops = kappa * (2 * SOLID_FLOPS_PER_PAIR * c1["n_ss"] + SOLID_FLOPS_PER_PARTICLE * ns_free)
+    kappa = (c1["substeps"] - c0["substeps"]) / max(1, c1["steps"] - c0["steps"])
+    # single kernels and their algorithmic bytes and flops per launch; the
+    # streamed solid form (3D, large solids) is a sequence of kernels and is
+    # not a candidate
+    cand = {
+        "k_fluid_force": (kt["k_fluid_force"], FORCE_BYTES_PER_PARTICLE * nf + LIST_BYTES_PER_PAIR * pairs_f,
+                          FORCE_FLOPS_PER_PAIR * pairs_f),
+        "k_fluid_continuity": (kt["k_fluid_continuity"], CONT_BYTES_PER_PARTICLE * nf + LIST_BYTES_PER_PAIR * pairs_f,
+                               CONT_FLOPS_PER_PAIR * pairs_f),
+    }
+    if sim.solid_register_resident():
+        cand["k_solid_reg"] = (kt["k_solid"], SOLID_BYTES_PER_PARTICLE * ns_free + SOLID_BYTES_PER_PAIR * c1["n_ss"],
+                               kappa * (2 * SOLID_FLOPS_PER_PAIR * c1["n_ss"] + SOLID_FLOPS_PER_PARTICLE * ns_free))
+    dominant = max(cand, key=lambda k: cand[k][0])
+    dur_ms, alg_bytes, alg_flops = cand[dominant]
+    dur = dur_ms * 1e-3
     gbs = alg_bytes / dur / 1e9
     tflops = alg_flops / dur / 1e12
     hbm_frac = gbs / HBM_PEAK_GBS
@@ -170,9 +206,12 @@ def main():
         roof = dict(bound="alu", achieved=tflops, peak=ALU_PEAK_TFLOPS, unit="TFLOP/s", frac=alu_frac)
     else:
         roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm_frac)
-    roof.update(traffic=None, kernel=dominant, duration_us=dur * 1e6,
+    traffic = measured_traffic(args.workload, dominant)
+    roof.update(traffic=traffic, kernel=dominant, duration_us=dur * 1e6,
+                traffic_over_algorithmic=None if traffic is None else traffic / alg_bytes,
                 hbm_GBps=gbs, hbm_frac=hbm_frac, alu_TFLOPs=tflops, alu_frac=alu_frac,
-                algorithmic_bytes=alg_bytes, algorithmic_flops=alg_flops)
+                algorithmic_bytes=alg_bytes, algorithmic_flops=alg_flops,
+                workgroups_per_launch=len(scs) if dominant == "k_solid_reg" else None)
 
     cpu = None
     if not args.no_cpu_baseline and len(scs) == 1:
@@ -208,6 +247,7 @@ def main():
         "interactions_per_step": inter / args.steps,
         "rebuilds": rebuilds,
         "kernel_ms_per_step": {k: round(v, 6) for k, v in per_step.items()},
+        "launch": sim.launch_config(),
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -173,6 +173,15 @@ int sph_set_scalars(sph_ctx *ctx, int scene, const double *in);
  * interactions evaluated.  Synchronises. */
 int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out);
 
+/* Launch configuration chosen at sph_init (no GPU work): out[0..7] = lanes
+ * per fluid particle in the pair passes, lanes per solid particle in the
+ * coupling pass, threads per block of the pair passes, solid particles per
+ * thread of the register-resident solid kernel (0: streamed passes),
+ * threads per scene of that kernel, fluid and boundary pair-list capacity
+ * per particle, 1 when sph_advance replays a captured HIP graph (0 before
+ * the first sph_advance or without a graph). */
+int sph_launch_config(sph_ctx *ctx, int *out);
+
 /* FP64 reductions of one scene: out[0..2] fluid momentum, out[3..5] solid
  * momentum, out[6] fluid kinetic energy, out[7] solid kinetic energy,
  * out[8] solid strain energy, out[9..11] sum of the fluid force on the solid,

@@ -778,6 +778,16 @@ int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out) {
   return SPH_OK;
 }
 
+int sph_launch_config(sph_ctx *ctx, int *out) {
+  if (!ctx) return SPH_E_ORDER;
+  if (!out) return SPH_E_ARG;
+  const LaunchCfg &c = ctx->cfg;
+  int v[8] = {c.lpp_force, c.lpp_couple, c.block_pair, c.solid_ppt, c.block_solid, ctx->D.capf, ctx->D.capb,
+              ctx->graph_exec ? 1 : 0};
+  std::memcpy(out, v, sizeof v);
+  return SPH_OK;
+}
+
 int sph_reduce(sph_ctx *ctx, int scene, double *out) {
   if (!ctx) return SPH_E_ORDER;
   if (scene < 0 || scene >= ctx->n_scenes || !out) return SPH_E_ARG;

@@ -89,6 +89,7 @@ def lib():
         L.sph_scalars.argtypes = [vp, C.c_int, _dp]
         L.sph_set_scalars.argtypes = [vp, C.c_int, _dp]
         L.sph_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
+        L.sph_launch_config.argtypes = [vp, C.POINTER(C.c_int)]
         L.sph_reduce.argtypes = [vp, C.c_int, _dp]
         L.sph_time_kernel.argtypes = [vp, C.c_int, C.c_int, _dp]
         L.sph_last_error.restype = C.c_char_p
@@ -235,6 +236,16 @@ class Simulation:
         arr = np.array([cur["t"], 0.0, cur["dt_ad"], 0.0, cur["adv_accum"], 0.0,
                         float(cur["need_rebuild"]), 0.0])
         self._check(self.L.sph_set_scalars(self.ctx, int(scene), _ptr(arr)))
+
+    def launch_config(self) -> dict:
+        out = (C.c_int * 8)()
+        self._check(self.L.sph_launch_config(self.ctx, out))
+        keys = ("lpp_fluid", "lpp_couple", "block_pair", "solid_ppt", "block_solid", "cap_fluid_nbr",
+                "cap_boundary_nbr", "graph")
+        return dict(zip(keys, [int(x) for x in out]))
+
+    def solid_register_resident(self) -> bool:
+        return self.launch_config()["solid_ppt"] > 0
 
     def counters(self, scene: int = -1) -> dict:
         out = (C.c_ulonglong * 8)()

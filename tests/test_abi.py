@@ -69,5 +69,7 @@ def test_calls_without_context_are_order_errors():
     for name in ("neighbor_build", "fluid_step", "couple", "solid_substeps", "sph_sync"):
         assert getattr(L, name)(None) == sph.SPH_E_ORDER
     assert L.sph_advance(None, 1) == sph.SPH_E_ORDER
+    cfg = (ctypes.c_int * 8)()
+    assert L.sph_launch_config(None, cfg) == sph.SPH_E_ORDER
     buf = np.zeros(8)
     assert L.sph_scalars(None, 0, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == sph.SPH_E_ORDER
