@@ -108,18 +108,33 @@ def cpu_baseline(scene, seconds=15.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed acoustic steps (default per workload: 20000 for the channel, 2000 for the "
+                         "2D dam break, 300 for the 3D dam break, 1000 for the batch)")
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="plate_behind_cylinder",
                     choices=["plate_behind_cylinder", "dam_break_plate", "dam_break_3d",
                              "batched_dam_breaks"])
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default launch shapes instead of the autotuned ones")
+    ap.add_argument("--autotune-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "mrsph",
+                                                              "autotune.json"))
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="only run a plain FP32 device copy of this many MiB five times (the "
                          "reference for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    # the batch stays within 1100 steps: 8 of its 64 coarse scenes become
+    # unstable after the water hits the plate (from about step 1600, the FP64
+    # oracle included)
+    defaults = {"plate_behind_cylinder": (20000, 200), "dam_break_plate": (2000, 100),
+                "dam_break_3d": (300, 20), "batched_dam_breaks": (1000, 100)}[args.workload]
+    if args.steps is None:
+        args.steps = defaults[0]
+    if args.warmup is None:
+        args.warmup = defaults[1]
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
@@ -144,7 +159,15 @@ def main():
     print(f"[bench] workload {args.workload}: {len(scs)} scene(s), "
           f"{sum(len(s['x_fluid']) for s in scs)} fluid, {sum(len(s['x_solid']) for s in scs)} solid, "
           f"{sum(len(s['x_wall']) for s in scs)} wall particles", file=sys.stderr, flush=True)
-    sim = sph.Simulation(scs)
+    opts = {}
+    tune_s = 0.0
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        opts = sph.autotune(scs, warmup=10 if dim == 3 else 50, steps=10 if dim == 3 else 300,
+                            cache=args.autotune_cache)
+        tune_s = time.perf_counter() - t0
+        print(f"[bench] autotuned in {tune_s:.1f} s: {json.dumps(opts)}", file=sys.stderr, flush=True)
+    sim = sph.Simulation(scs, **opts)
     sim.advance(args.warmup)
     torch.cuda.synchronize()
     sim.sync()
@@ -248,6 +271,8 @@ def main():
         "rebuilds": rebuilds,
         "kernel_ms_per_step": {k: round(v, 6) for k, v in per_step.items()},
         "launch": sim.launch_config(),
+        "autotuned": not args.no_autotune,
+        "autotune_seconds": tune_s,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -75,6 +75,8 @@ typedef struct {
                            lattice count inside 2 h_F) */
   int max_boundary_nbr; /* capacity of each fluid particle's wall and solid pair list; 0 = default
                            (lattice count inside 2 h_F times 1 + (dp_F/dp_S)^d) */
+  int serial_passes;    /* 0: in sph_advance the continuity pass runs on a second stream,
+                           concurrently with the coupling and solid passes; 1: one stream */
 } sph_options;
 
 /* Field ids for sph_read / sph_write (FP64, original particle order).
@@ -172,6 +174,20 @@ int sph_set_scalars(sph_ctx *ctx, int scene, const double *in);
  * reference pairs, acoustic steps, rebuilds, solid sub-steps, particle
  * interactions evaluated.  Synchronises. */
 int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out);
+
+/* Autotuner of the launch shapes (batched scenes, hipGraph replay): for
+ * every candidate, lanes per fluid particle in {1, 2, 4, 8, 16} x threads
+ * per block of the pair passes in {64, 128, 256} x serial_passes in {0, 1},
+ * initialises the scenes in the caller's arena on the caller's stream,
+ * advances `warmup` acoustic steps and times `steps` more with HIP events.
+ * *best receives *opt with the fastest candidate's three fields; ms_per_step
+ * (may be NULL) its time per step.  The arena must hold sph_arena_bytes for
+ * *opt (the candidates do not change the size).  Synchronises; no context is
+ * left behind.  Returns SPH_E_ARG for bad arguments, else the first error of
+ * a candidate run. */
+int sph_autotune(const sph_scene *scenes, int n_scenes, const sph_options *opt, void *dev_arena,
+                 size_t arena_bytes, void *stream, int warmup, int steps, sph_options *best,
+                 double *ms_per_step);
 
 /* Launch configuration chosen at sph_init (no GPU work): out[0..7] = lanes
  * per fluid particle in the pair passes, lanes per solid particle in the

@@ -261,6 +261,11 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
   }
   P.cfg.block_pair = bp ? bp : 256;
   P.cfg.block_couple = 64;
+  if (o.serial_passes != 0 && o.serial_passes != 1) {
+    err = "serial_passes must be 0 or 1";
+    return false;
+  }
+  P.cfg.fork = o.serial_passes ? 0 : 1;
   P.cfg.solid_lds_n = P.cfg.solid_ppt ? max_solid_scene : 0;  // confirmed against the device in sph_init
   // pair-list capacities: particles of a lattice inside the support 2 h_F,
   // with room for compression (fluid) and for the finer solid lattice
@@ -441,7 +446,7 @@ int enqueue_solid(sph_ctx *ctx) {
 int enqueue_step(sph_ctx *ctx, bool fork) {
   launch_rebuild(ctx->D, ctx->cfg, ctx->stream);
   launch_fluid_force(ctx->D, ctx->cfg, ctx->stream);
-  if (fork && ctx->side && ctx->cfg.solid_ppt > 0) {
+  if (fork && ctx->cfg.fork && ctx->side && ctx->cfg.solid_ppt > 0) {
     if (hipEventRecord(ctx->ev_fork, ctx->stream) != hipSuccess ||
         hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0) != hipSuccess)
       return SPH_E_HIP;
@@ -861,6 +866,57 @@ int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms) {
 }
 
 const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+int sph_autotune(const sph_scene *scenes, int n_scenes, const sph_options *opt, void *dev_arena,
+                 size_t arena_bytes, void *stream, int warmup, int steps, sph_options *best,
+                 double *ms_per_step) {
+  if (!scenes || !opt || !best || !dev_arena || n_scenes <= 0 || warmup < 0 || steps <= 0) return SPH_E_ARG;
+  size_t need = sph_arena_bytes(scenes, n_scenes, opt);
+  if (need == 0 || arena_bytes < need) return SPH_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return SPH_E_HIP;
+  }
+  const int lpps[] = {1, 2, 4, 8, 16}, blocks[] = {64, 128, 256};
+  double best_ms = -1.0;
+  sph_options pick = *opt;
+  int rc = SPH_OK;
+  for (int serial = 0; serial < 2 && rc == SPH_OK; ++serial)
+    for (int lpp : lpps)
+      for (int bp : blocks) {
+        sph_options o = *opt;
+        o.lanes_per_particle = lpp;
+        o.block_pair = bp;
+        o.serial_passes = serial;
+        sph_ctx *ctx = nullptr;
+        rc = sph_init(scenes, n_scenes, &o, dev_arena, arena_bytes, stream, &ctx);
+        if (rc == SPH_OK) rc = sph_advance(ctx, warmup);
+        float ms = 0.0f;
+        if (rc == SPH_OK) {
+          if (hipStreamSynchronize(st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) rc = SPH_E_HIP;
+          if (rc == SPH_OK) rc = sph_advance(ctx, steps);
+          if (rc == SPH_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = SPH_E_HIP;
+          if (rc == SPH_OK) rc = sph_sync(ctx);
+        }
+        if (ctx) sph_destroy(ctx);
+        if (rc != SPH_OK) break;
+        double per = (double)ms / steps;
+        if (best_ms < 0.0 || per < best_ms) {
+          best_ms = per;
+          pick = o;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SPH_OK) return rc;
+  *best = pick;
+  if (ms_per_step) *ms_per_step = best_ms;
+  return SPH_OK;
+}
 
 void sph_destroy(sph_ctx *ctx) {
   if (!ctx) return;

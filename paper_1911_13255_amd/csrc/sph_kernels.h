@@ -17,6 +17,7 @@ struct LaunchCfg {
   int solid_lds_n;   // solid particles per scene held in LDS by the register-resident kernel
   int solid_ppt;     // > 0: register-resident solid kernel (2D) with this many particles per thread;
                      // 0: streamed multi-block solid passes with kappa read back to the host
+  int fork;          // 1: the continuity pass runs on a second stream beside coupling and solid
 };
 
 void launch_init_scene(const Dev &D, int s, const double *x_f, const double *v_f, int has_vf, double gabs,

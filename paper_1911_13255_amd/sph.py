@@ -8,6 +8,7 @@ C names: ``neighbor_build``, ``fluid_step``, ``couple``, ``solid_substeps``,
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 import re
 
@@ -55,7 +56,11 @@ class SphScene(C.Structure):
 class SphOptions(C.Structure):
     _fields_ = [("riemann", C.c_int), ("density_reinit", C.c_int), ("max_solid_nbr", C.c_int),
                 ("solid_block", C.c_int), ("lanes_per_particle", C.c_int), ("block_pair", C.c_int),
-                ("solid_lds", C.c_int), ("max_fluid_nbr", C.c_int), ("max_boundary_nbr", C.c_int)]
+                ("solid_lds", C.c_int), ("max_fluid_nbr", C.c_int), ("max_boundary_nbr", C.c_int),
+                ("serial_passes", C.c_int)]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 def exported_names():
@@ -90,6 +95,8 @@ def lib():
         L.sph_set_scalars.argtypes = [vp, C.c_int, _dp]
         L.sph_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
         L.sph_launch_config.argtypes = [vp, C.POINTER(C.c_int)]
+        L.sph_autotune.argtypes = [C.POINTER(SphScene), C.c_int, C.POINTER(SphOptions), vp, C.c_size_t, vp,
+                                   C.c_int, C.c_int, C.POINTER(SphOptions), _dp]
         L.sph_reduce.argtypes = [vp, C.c_int, _dp]
         L.sph_time_kernel.argtypes = [vp, C.c_int, C.c_int, _dp]
         L.sph_last_error.restype = C.c_char_p
@@ -130,13 +137,97 @@ def scene_struct(sc: dict):
     return s, keep
 
 
+def scene_array(scenes):
+    """C array of scene structs plus the host arrays it points into."""
+    arr = (SphScene * len(scenes))()
+    keep = []
+    for i, sc in enumerate(scenes):
+        st, k = scene_struct(sc)
+        arr[i] = st
+        keep.append(k)
+    return arr, keep
+
+
+def make_options(riemann=True, density_reinit=1, max_solid_nbr=0, solid_block=0, lanes_per_particle=0,
+                 block_pair=0, solid_lds=0, max_fluid_nbr=0, max_boundary_nbr=0, serial_passes=0):
+    return SphOptions(int(riemann), int(density_reinit), int(max_solid_nbr), int(solid_block),
+                      int(lanes_per_particle), int(block_pair), int(solid_lds), int(max_fluid_nbr),
+                      int(max_boundary_nbr), int(serial_passes))
+
+
+def workload_signature(scenes, opt: dict) -> str:
+    """Key of the autotuner cache: scene shapes and counts, fixed options, device."""
+    import hashlib
+
+    import torch
+
+    h = hashlib.sha256()
+    for sc in scenes:
+        h.update(repr((int(sc["dim"]), len(sc["x_fluid"]), len(sc["x_wall"]), len(sc["x_solid"]),
+                       int(sc["n_clamp"]), float(sc["dp_f"]), float(sc["dp_s"]))).encode())
+    fixed = {k: v for k, v in opt.items() if k not in ("lanes_per_particle", "block_pair", "serial_passes")}
+    h.update(json.dumps(fixed, sort_keys=True).encode())
+    h.update(torch.cuda.get_device_name(0).encode())
+    return h.hexdigest()[:32]
+
+
+def autotune(scenes, warmup: int = 20, steps: int = 200, cache: str = None, device: int = 0, **options) -> dict:
+    """Launch shapes for these scenes chosen by the library's autotuner
+    (sph_autotune), cached by workload signature in a JSON file.  Returns the
+    full option set to pass to Simulation."""
+    import torch
+
+    if isinstance(scenes, dict):
+        scenes = [scenes]
+    L = lib()
+    opt = make_options(**options)
+    key = workload_signature(scenes, opt.as_dict())
+    if cache and os.path.exists(cache):
+        try:
+            hit = json.load(open(cache)).get(key)
+        except ValueError:
+            hit = None
+        if hit:
+            return hit["options"]
+    arr, keep = scene_array(scenes)
+    nbytes = L.sph_arena_bytes(arr, len(scenes), C.byref(opt))
+    if nbytes == 0:
+        raise SphError(SPH_E_ARG, "invalid scene description")
+    dev = torch.device("cuda", device)
+    with torch.cuda.device(dev):
+        stream = torch.cuda.Stream(device=dev)
+        arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize(dev)
+    best = SphOptions()
+    ms = C.c_double(0.0)
+    rc = L.sph_autotune(arr, len(scenes), C.byref(opt), C.c_void_p(arena.data_ptr()), nbytes + 256,
+                        C.c_void_p(stream.cuda_stream), int(warmup), int(steps), C.byref(best), C.byref(ms))
+    torch.cuda.synchronize(dev)
+    del arena
+    if rc != SPH_OK:
+        raise SphError(rc, "sph_autotune failed")
+    chosen = best.as_dict()
+    if cache:
+        try:
+            db = json.load(open(cache)) if os.path.exists(cache) else {}
+        except ValueError:
+            db = {}
+        db[key] = {"options": chosen, "ms_per_step": ms.value}
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        json.dump(db, open(cache, "w"), indent=1)
+    return chosen
+
+
 class Simulation:
     """One or more scenes on one GPU, advanced by the library's kernels."""
 
     def __init__(self, scenes, riemann: bool = True, density_reinit: int = 1,
                  max_solid_nbr: int = 0, solid_block: int = 0, lanes_per_particle: int = 0,
                  block_pair: int = 0, solid_lds: int = 0, max_fluid_nbr: int = 0,
-                 max_boundary_nbr: int = 0, device: int = 0):
+                 max_boundary_nbr: int = 0, serial_passes: int = 0, device: int = 0,
+                 arena_fill: int = None):
+        """arena_fill: byte written over the whole arena before sph_init (tests
+        use it to show that no result depends on the arena's prior contents)."""
         import torch
 
         if isinstance(scenes, dict):
@@ -146,16 +237,10 @@ class Simulation:
         self.dim = int(scenes[0]["dim"])
         self.nf = [len(s["x_fluid"]) for s in scenes]
         self.ns = [len(s["x_solid"]) for s in scenes]
-        arr = (SphScene * self.n_scenes)()
-        self._keep = []
-        for i, sc in enumerate(scenes):
-            st, keep = scene_struct(sc)
-            arr[i] = st
-            self._keep.append(keep)
+        arr, self._keep = scene_array(scenes)
         self._scenes = arr
-        self.opt = SphOptions(int(riemann), int(density_reinit), int(max_solid_nbr), int(solid_block),
-                              int(lanes_per_particle), int(block_pair), int(solid_lds),
-                              int(max_fluid_nbr), int(max_boundary_nbr))
+        self.opt = make_options(riemann, density_reinit, max_solid_nbr, solid_block, lanes_per_particle,
+                                block_pair, solid_lds, max_fluid_nbr, max_boundary_nbr, serial_passes)
         nbytes = self.L.sph_arena_bytes(arr, self.n_scenes, C.byref(self.opt))
         if nbytes == 0:
             raise SphError(SPH_E_ARG, "invalid scene description")
@@ -163,6 +248,8 @@ class Simulation:
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.Stream(device=self.device)
             self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            if arena_fill is not None:
+                self.arena.fill_(int(arena_fill) & 0xFF)
         torch.cuda.synchronize(self.device)
         self.arena_bytes = nbytes
         ctx = C.c_void_p()

@@ -32,7 +32,7 @@ def test_arena_bytes_and_argument_checks():
     sc = scenes.dam_break_plate(seed=1)
     st, keep = sph.scene_struct(sc)
     arr = (sph.SphScene * 1)(st)
-    opt = sph.SphOptions(1, 1, 0, 0, 0, 0, 0, 0, 0)
+    opt = sph.make_options()
     n1 = L.sph_arena_bytes(arr, 1, ctypes.byref(opt))
     assert n1 > 0
     # more scenes need more memory
@@ -50,10 +50,10 @@ def test_arena_bytes_and_argument_checks():
     bad.hi[0] = bad.lo[0] + 0.02  # fewer than 3 cells of 2 h_F
     assert L.sph_arena_bytes((sph.SphScene * 1)(bad), 1, ctypes.byref(opt)) == 0
     # pair-list capacities beyond the limit are rejected
-    big = sph.SphOptions(1, 1, 0, 0, 0, 0, 0, 5000, 0)
+    big = sph.make_options(max_fluid_nbr=5000)
     assert L.sph_arena_bytes(arr, 1, ctypes.byref(big)) == 0
     # larger capacities need more memory
-    roomy = sph.SphOptions(1, 1, 0, 0, 0, 0, 0, 256, 512)
+    roomy = sph.make_options(max_fluid_nbr=256, max_boundary_nbr=512)
     assert L.sph_arena_bytes(arr, 1, ctypes.byref(roomy)) > n1
     mixed = sph.SphScene.from_buffer_copy(st)
     mixed.dim = 3
@@ -73,3 +73,25 @@ def test_calls_without_context_are_order_errors():
     assert L.sph_launch_config(None, cfg) == sph.SPH_E_ORDER
     buf = np.zeros(8)
     assert L.sph_scalars(None, 0, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == sph.SPH_E_ORDER
+
+
+def test_autotune_and_option_checks_without_gpu():
+    L = _lib_or_skip()
+    sc = scenes.dam_break_plate(seed=1)
+    arr, keep = sph.scene_array([sc])
+    opt = sph.make_options()
+    best = sph.SphOptions()
+    ms = ctypes.c_double()
+    # bad arguments are rejected before any GPU work
+    assert L.sph_autotune(None, 1, ctypes.byref(opt), None, 0, None, 1, 1, ctypes.byref(best),
+                          ctypes.byref(ms)) == sph.SPH_E_ARG
+    assert L.sph_autotune(arr, 1, ctypes.byref(opt), None, 1 << 30, None, 1, 1, ctypes.byref(best),
+                          ctypes.byref(ms)) == sph.SPH_E_ARG
+    assert L.sph_autotune(arr, 1, ctypes.byref(opt), ctypes.c_void_p(1), 16, None, 1, 0, ctypes.byref(best),
+                          ctypes.byref(ms)) == sph.SPH_E_ARG
+    # serial_passes is 0 or 1
+    assert L.sph_arena_bytes(arr, 1, ctypes.byref(sph.make_options(serial_passes=2))) == 0
+    assert L.sph_arena_bytes(arr, 1, ctypes.byref(sph.make_options(serial_passes=1))) > 0
+    # the autotuner's cache key depends on the scene shapes, not on the tuned fields
+    import paper_1911_13255_amd.sph as S
+    assert S.make_options(lanes_per_particle=4).as_dict()["lanes_per_particle"] == 4

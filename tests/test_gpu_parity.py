@@ -246,6 +246,120 @@ def test_batched_scenes_match_separate_oracles(gpu):
     sim.close()
 
 
+def test_autotuned_shapes_keep_parity_and_are_cached(gpu, tmp_path):
+    scs = scenes.batched_dam_breaks(n_scenes=4)
+    cache = str(tmp_path / "tune.json")
+    note("autotune batched 4 scenes")
+    opts = sph.autotune(scs, warmup=5, steps=20, cache=cache)
+    assert opts["lanes_per_particle"] in (1, 2, 4, 8, 16)
+    assert opts["block_pair"] in (64, 128, 256)
+    assert opts["serial_passes"] in (0, 1)
+    assert sph.autotune(scs, warmup=5, steps=20, cache=cache) == opts
+    sim = sph.Simulation(scs, **opts)
+    oras = [O.Oracle(s) for s in scs]
+    for k in range(3):
+        sim.advance(1)
+        for o in oras:
+            o.step(1)
+        for i, o in enumerate(oras):
+            compare(sim, o, scene=i, label=f"tuned scene {i} step {k + 1}")
+    sim.sync()
+    sim.close()
+
+
+@pytest.mark.parametrize("lpp,block", [(1, 64), (4, 128), (16, 256)])
+def test_launch_shapes_keep_parity(gpu, lpp, block):
+    sc = scenes.dam_break_plate(seed=2)
+    note(f"launch shape lpp {lpp} block {block}")
+    sim = sph.Simulation(sc, lanes_per_particle=lpp, block_pair=block)
+    o = O.Oracle(sc)
+    for k in range(4):
+        one_step(sim, o)
+        compare(sim, o, label=f"lpp {lpp} step {k + 1}")
+    sim.sync()
+    sim.close()
+
+
+@pytest.mark.parametrize("lpp", [0, 4])
+def test_results_do_not_depend_on_prior_arena_contents(gpu, lpp):
+    scs = scenes.batched_dam_breaks(n_scenes=4)
+    outs = []
+    for fill in (0x00, 0xFF, 0x5A):
+        note(f"arena fill {fill:#x} lpp {lpp}")
+        sim = sph.Simulation(scs, lanes_per_particle=lpp, serial_passes=1, arena_fill=fill)
+        sim.advance(60)
+        sim.sync()
+        outs.append([[sim.read(f, s) for f in (sph.F_X, sph.F_V, sph.F_RHO, sph.S_U, sph.S_FF)]
+                     for s in range(len(scs))])
+        assert sim.counters()["rebuilds"] > 4
+        sim.close()
+    for other in outs[1:]:
+        for a_s, b_s in zip(outs[0], other):
+            for x, y in zip(a_s, b_s):
+                assert np.array_equal(x, y)
+
+
+def test_serial_and_concurrent_passes_agree_bitwise(gpu):
+    sc = scenes.periodic_box_with_solid(dim=2, n=16, eta=0.5, amp=0.3)
+    a = sph.Simulation(sc, serial_passes=1)
+    b = sph.Simulation(sc, serial_passes=0)
+    a.advance(20)
+    b.advance(20)
+    assert b.launch_config()["graph"] == 1
+    for f in (sph.F_X, sph.F_V, sph.F_RHO, sph.S_U, sph.S_V, sph.S_FF):
+        assert np.array_equal(a.read(f), b.read(f)), f
+    a.close()
+    b.close()
+
+
+def _tip_history(run_steps, step, read_u, read_t, n_samples, every):
+    u, t = [], []
+    for _ in range(n_samples):
+        run_steps(every)
+        u.append(read_u())
+        t.append(read_t())
+    return np.array(u), np.array(t)
+
+
+def test_plate_tip_trajectory_within_one_percent(gpu):
+    # Extended 2D dam break: the surge reaches the plate after about 1500
+    # acoustic steps and bends it by centimetres by step 2000.  Tip error
+    # (free-end, mid-thickness particle) = max over time of |u_gpu(t) -
+    # u_oracle(t)| relative to max |u_oracle|, the GPU trajectory interpolated
+    # to the oracle's times (the adaptive step depends on the max fluid speed,
+    # so equal step counts are not equal times).  After the impact the
+    # trajectory is chaotic: the FP64 oracle itself moves by about 1.6% when
+    # the initial fluid positions change by one part in 1e7 (FP32 rounding).
+    # So the 1% bar is asserted through step 1800 and, over the whole run, the
+    # GPU error must stay within twice that intrinsic spread.
+    sc = scenes.dam_break_plate(seed=1)
+    tip = int(sc["tip_index"])
+    note("tip trajectory dam_break_plate seed 1, 2000 steps")
+    sim = sph.Simulation(sc)
+    o = O.Oracle(sc)
+    sc_p = dict(sc)
+    sc_p["x_fluid"] = sc["x_fluid"] * (1.0 + 1e-7)
+    op = O.Oracle(sc_p)
+    ug, tg = _tip_history(sim.advance, 5, lambda: sim.read(sph.S_U)[tip], lambda: sim.scalars()["t"], 400, 5)
+    uo, to = _tip_history(o.step, 5, lambda: o.get(O.S_U)[tip], lambda: o.scalars()["t"], 400, 5)
+    up, tp = _tip_history(op.step, 5, lambda: op.get(O.S_U)[tip], lambda: op.scalars()["t"], 400, 5)
+    umax = np.linalg.norm(uo, axis=1).max()
+
+    def err_to(ub, tb, upto):
+        keep = (to <= tb[-1]) & (np.arange(len(to)) < upto)
+        ui = np.stack([np.interp(to[keep], tb, ub[:, k]) for k in range(2)], axis=1)
+        return np.linalg.norm(ui - uo[keep], axis=1).max() / umax
+
+    e1800, eall, spread = err_to(ug, tg, 360), err_to(ug, tg, 400), err_to(up, tp, 400)
+    note(f"tip: max |u_oracle| {umax:.4e} m, error through step 1800 {e1800:.3e}, over 2000 steps {eall:.3e}, "
+         f"oracle spread under a 1e-7 perturbation {spread:.3e}, time drift {abs(tg[-1] - to[-1]) / to[-1]:.2e}")
+    assert umax > 1e-2  # the plate is loaded within the run
+    assert e1800 <= 0.01
+    assert eall <= max(0.01, 2.0 * spread)
+    sim.sync()
+    sim.close()
+
+
 # ------------------------------------------------------------------ invariants in FP32
 
 def test_coupling_exchange_and_momentum(gpu):
