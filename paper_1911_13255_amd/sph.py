@@ -64,10 +64,16 @@ class SphOptions(C.Structure):
 
 
 def exported_names():
-    """Function names declared in include/mrsph.h."""
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", txt)) - {"defined"})
+    """Function names declared in the headers under include/."""
+    inc = os.path.dirname(HEADER)
+    names = set()
+    for h in sorted(os.listdir(inc)):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(inc, h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", txt))
+    return sorted(names - {"defined"})
 
 
 _lib = None
