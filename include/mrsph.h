@@ -189,6 +189,44 @@ int sph_autotune(const sph_scene *scenes, int n_scenes, const sph_options *opt, 
                  size_t arena_bytes, void *stream, int warmup, int steps, sph_options *best,
                  double *ms_per_step);
 
+/* ---- learned sub-step surrogate (2D, register-resident solid kernel) ----
+ * A network of include/mrsph_mlp.h with 24 inputs and 4 outputs replaces
+ * the kappa solid sub-steps of an acoustic step where its prediction passes a
+ * residual check, scene by scene.  Features of a free solid particle, in
+ * order: F - I (4, row-major), v (2), a (2), the pressure and viscous parts
+ * of the coupling force (2 + 2), then the mean of these 12 over the
+ * particle's reference neighbours; outputs: vbar - v (2), abar - a (2), the
+ * changes of the time-averaged velocity and acceleration of Section 3.2.
+ * The prediction is advanced to the step end (u += dt vbar, v += dt abar,
+ * F from the corrected gradient of vbar) and accepted when
+ *   |abar - a(F_mid)|_2 / (|a(F_mid)|_2 + |g| sqrt(N)) <= threshold
+ * over the scene's N free particles, a(F_mid) being the solid momentum
+ * equation at the predicted mid-step deformation; otherwise the scene runs
+ * the plain sub-steps from its unchanged state. */
+struct mlp_ctx;
+
+/* Use `net` (kept by the caller, max_rows >= all solid particles) with the
+ * standardisation stats (host, 56 floats: feature mean[24], feature 1/std[24],
+ * output mean[4], output std[4]) and residual threshold; net = NULL or
+ * threshold <= 0 turns the surrogate off.  The next sph_advance captures a
+ * new graph.  SPH_E_ARG for 3D, streamed solids or mismatched sizes.
+ * Synchronises. */
+int sph_set_surrogate(sph_ctx *ctx, struct mlp_ctx *net, const float *stats, float threshold);
+
+/* Training data: features of every solid particle at the current state
+ * (rows in solid order, scene after scene, 24 floats each, clamp rows zero),
+ * standardised with stats_dev (device, 48 floats: mean, 1/std) or raw when it
+ * is NULL; call between couple and solid_substeps.  Enqueue only. */
+int sph_solid_features(sph_ctx *ctx, const float *stats_dev, float *x_dev);
+
+/* Targets after solid_substeps, from the raw features taken before it: rows
+ * of (vbar - v, abar - a), 4 floats each, clamp rows zero.  Enqueue only. */
+int sph_solid_targets(sph_ctx *ctx, const float *xraw_dev, float *t_dev);
+
+/* Surrogate steps of one scene (scene = -1: all): out[0] accepted, out[1]
+ * fell back to the sub-steps.  Synchronises. */
+int sph_surrogate_counters(sph_ctx *ctx, int scene, unsigned long long *out);
+
 /* Launch configuration chosen at sph_init (no GPU work): out[0..7] = lanes
  * per fluid particle in the pair passes, lanes per solid particle in the
  * coupling pass, threads per block of the pair passes, solid particles per

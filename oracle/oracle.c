@@ -59,6 +59,7 @@ typedef struct {
   double *xw, *wn;
   /* solid: 3 x 3 row-major tensors, 3-vectors */
   double *x0, *u, *vs, *as, *F, *dF, *B, *n0, *sn, *vbar, *abar, *fF, *xsr, *ms, *V0;
+  double *fFp; /* pressure part of the coupling force on the solid */
   int *clamp;
   int *s_start, *s_idx;
   double *s_grad; /* grad_a W(r0_ab, h_s) for each reference pair */
@@ -526,6 +527,7 @@ ora_ctx *ora_create(const ora_scene *sc) {
   c->vbar = zalloc(3 * (size_t)ns);
   c->abar = zalloc(3 * (size_t)ns);
   c->fF = zalloc(3 * (size_t)ns);
+  c->fFp = zalloc(3 * (size_t)ns);
   c->xsr = zalloc(3 * (size_t)ns);
   c->F = zalloc(9 * (size_t)ns);
   c->dF = zalloc(9 * (size_t)ns);
@@ -580,7 +582,7 @@ void ora_destroy(ora_ctx *c) {
   if (!c) return;
   double *bufs[] = {c->x, c->v, c->rho, c->drho, c->m, c->a, c->p, c->xr, c->sn_rho, c->sn_p,
                     c->sn_v, c->xw, c->wn, c->x0, c->u, c->vs, c->as, c->F, c->dF, c->B,
-                    c->n0, c->sn, c->vbar, c->abar, c->fF, c->xsr, c->ms, c->V0, c->s_grad};
+                    c->n0, c->sn, c->vbar, c->abar, c->fF, c->xsr, c->ms, c->V0, c->s_grad, c->fFp};
   for (size_t k = 0; k < sizeof bufs / sizeof bufs[0]; ++k) free(bufs[k]);
   int *ibufs[] = {c->clamp, c->s_start, c->s_idx, c->ff_start, c->ff_idx, c->fb_start,
                   c->fb_idx, c->sf_start, c->sf_idx};
@@ -624,7 +626,7 @@ static void bnd_state(const ora_ctx *c, int k, const double **xb, const double *
  * the printed sign does not give it for either orientation of n), and
  * v_d = 2 vbar_a - v_i (the printed 2 v_i - vbar_a would be anti-viscous). */
 static void coupling_pair(const ora_ctx *c, double rho_i, double p_i, const double *v_i,
-                          double V_i, const double *xi, int k, double *f) {
+                          double V_i, const double *xi, int k, double *f, double *fp) {
   const double *xb, *vb, *ab, *nb;
   double Va;
   bnd_state(c, k, &xb, &vb, &ab, &nb, &Va);
@@ -644,7 +646,9 @@ static void coupling_pair(const ora_ctx *c, double rho_i, double p_i, const doub
   for (int q = 0; q < 3; ++q) f[q] = 0.0;
   for (int q = 0; q < d; ++q) {
     double vd = 2.0 * vb[q] - v_i[q];
-    f[q] = -2.0 * V_i * Va * pf * dW * e[q] + 2.0 * c->eta * V_i * Va * (v_i[q] - vd) / (rr + 0.01 * c->hf) * dW;
+    double fpress = -2.0 * V_i * Va * pf * dW * e[q];
+    f[q] = fpress + 2.0 * c->eta * V_i * Va * (v_i[q] - vd) / (rr + 0.01 * c->hf) * dW;
+    if (fp) fp[q] = fpress;
   }
 }
 
@@ -787,7 +791,7 @@ void ora_fluid_step(ora_ctx *c) {
     }
     for (int t = c->fb_start[i]; t < c->fb_start[i + 1]; ++t) {
       double f[3];
-      coupling_pair(c, c->rho[i], c->p[i], c->v + 3 * i, Vi, c->xr + 3 * i, c->fb_idx[t], f);
+      coupling_pair(c, c->rho[i], c->p[i], c->v + 3 * i, Vi, c->xr + 3 * i, c->fb_idx[t], f, NULL);
       for (int q = 0; q < d; ++q) acc[q] += f[q] / c->m[i];
     }
     /* reading: body force enters as m_i g */
@@ -868,16 +872,22 @@ void ora_couple(ora_ctx *c) {
   int d = c->d, nfree = c->ns - c->nc;
 #pragma omp parallel for schedule(static)
   for (int a = 0; a < c->ns; ++a) {
-    double fa[3] = {0.0, 0.0, 0.0};
+    double fa[3] = {0.0, 0.0, 0.0}, fap[3] = {0.0, 0.0, 0.0};
     if (a < nfree)
       for (int t = c->sf_start[a]; t < c->sf_start[a + 1]; ++t) {
         int i = c->sf_idx[t];
         double Vi = c->m[i] / c->sn_rho[i];
-        double f[3];
-        coupling_pair(c, c->sn_rho[i], c->sn_p[i], c->sn_v + 3 * i, Vi, c->xr + 3 * i, c->nw + a, f);
-        for (int q = 0; q < d; ++q) fa[q] -= f[q];
+        double f[3], fp[3];
+        coupling_pair(c, c->sn_rho[i], c->sn_p[i], c->sn_v + 3 * i, Vi, c->xr + 3 * i, c->nw + a, f, fp);
+        for (int q = 0; q < d; ++q) {
+          fa[q] -= f[q];
+          fap[q] -= fp[q];
+        }
       }
-    for (int q = 0; q < 3; ++q) c->fF[3 * a + q] = fa[q];
+    for (int q = 0; q < 3; ++q) {
+      c->fF[3 * a + q] = fa[q];
+      c->fFp[3 * a + q] = fap[q];
+    }
   }
   c->interactions += c->n_sf;
 }
@@ -1006,7 +1016,7 @@ void ora_advance(ora_ctx *c, int n) {
 
 enum {
   F_X = 0, F_V, F_RHO, F_DRHO, F_A, F_P, /* fluid */
-  S_U = 10, S_V, S_A, S_F, S_DF, S_FF, S_VBAR, S_ABAR, S_N, S_B, S_N0, S_X0 /* solid */
+  S_U = 10, S_V, S_A, S_F, S_DF, S_FF, S_VBAR, S_ABAR, S_N, S_B, S_N0, S_X0, S_FFP /* solid */
 };
 
 static int field_shape(const ora_ctx *c, int f, double **buf, int *n, int *w, int *stride) {
@@ -1028,6 +1038,7 @@ static int field_shape(const ora_ctx *c, int f, double **buf, int *n, int *w, in
   case S_N: *buf = c->sn; *n = c->ns; *w = d; return 0;
   case S_N0: *buf = c->n0; *n = c->ns; *w = d; return 0;
   case S_X0: *buf = c->x0; *n = c->ns; *w = d; return 0;
+  case S_FFP: *buf = c->fFp; *n = c->ns; *w = d; return 0;
   case S_F: *buf = c->F; *n = c->ns; *w = -d; *stride = 9; return 0;
   case S_DF: *buf = c->dF; *n = c->ns; *w = -d; *stride = 9; return 0;
   case S_B: *buf = c->B; *n = c->ns; *w = -d; *stride = 9; return 0;
@@ -1137,7 +1148,7 @@ void ora_fluid_side_coupling(const ora_ctx *c, double *out) {
       int k = c->fb_idx[t];
       if (k < c->nw) continue;
       double f[3];
-      coupling_pair(c, c->sn_rho[i], c->sn_p[i], c->sn_v + 3 * i, Vi, c->xr + 3 * i, k, f);
+      coupling_pair(c, c->sn_rho[i], c->sn_p[i], c->sn_v + 3 * i, Vi, c->xr + 3 * i, k, f, NULL);
       for (int q = 0; q < d; ++q) out[q] += f[q];
     }
   }

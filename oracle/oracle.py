@@ -18,8 +18,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 # field ids (index order, FP64)
 F_X, F_V, F_RHO, F_DRHO, F_A, F_P = 0, 1, 2, 3, 4, 5
-S_U, S_V, S_A, S_F, S_DF, S_FF, S_VBAR, S_ABAR, S_N, S_B, S_N0, S_X0 = range(10, 22)
-VECTOR_FIELDS = {F_X, F_V, F_A, S_U, S_V, S_A, S_FF, S_VBAR, S_ABAR, S_N, S_N0, S_X0}
+S_U, S_V, S_A, S_F, S_DF, S_FF, S_VBAR, S_ABAR, S_N, S_B, S_N0, S_X0, S_FFP = range(10, 23)
+VECTOR_FIELDS = {F_X, F_V, F_A, S_U, S_V, S_A, S_FF, S_VBAR, S_ABAR, S_N, S_N0, S_X0, S_FFP}
 TENSOR_FIELDS = {S_F, S_DF, S_B}
 FLUID_FIELDS = {F_X, F_V, F_RHO, F_DRHO, F_A, F_P}
 

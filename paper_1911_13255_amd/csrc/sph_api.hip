@@ -11,7 +11,9 @@
 #include <string>
 #include <vector>
 
+#include "mlp_internal.h"
 #include "mrsph.h"
+#include "mrsph_mlp.h"
 #include "sph_kernels.h"
 
 using namespace mrsph;
@@ -28,6 +30,7 @@ struct sph_ctx {
   hipStream_t side;  // second stream for the concurrent continuity pass (graph capture only)
   hipEvent_t ev_fork, ev_join;
   size_t stage_doubles;
+  mlp_ctx *net;  // sub-step surrogate (nullptr: plain sub-steps only)
   char err[512];
 };
 
@@ -364,8 +367,14 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   for (double **p : dvec) take(*p, 3 * ns);
   double **dten[] = {&D.s_H, &D.s_dF, &D.s_B, &D.s_PB};
   for (double **p : dten) take(*p, 9 * ns);
-  float **vec[] = {&D.s_a, &D.s_fF, &D.s_vbar, &D.s_abar, &D.s_n0, &D.s_n};
+  float **vec[] = {&D.s_a, &D.s_fF, &D.s_vbar, &D.s_abar, &D.s_n0, &D.s_n, &D.s_fFp,
+                   &D.sur_vbar, &D.sur_abar, &D.sur_amid};
   for (float **p : vec) take(*p, 3 * ns);
+  take(D.sur_x, (size_t)kSurFeat * ns);
+  take(D.sur_y, (size_t)kSurOut * ns);
+  take(D.sur_stats, 2 * kSurFeat + 2 * kSurOut);
+  take(D.sur_H, 9 * ns);
+  take(D.sur_dF, 9 * ns);
   take(D.s_r0d, 3 * ns);
   take(D.s_nbr, (size_t)P.maxn * ns);
   take(D.stage, 9 * (size_t)std::max(P.max_count, 64) + 64);
@@ -417,9 +426,20 @@ int read_states(sph_ctx *ctx, std::vector<SceneState> &st) {
 // register-resident launch per step with kappa decided on the device.  Other
 // solids: streamed passes over all solid particles; kappa is read back to
 // the host to size the pass loop (this synchronises the stream).
+// Register-resident sub-steps, preceded by the learned step when a surrogate
+// is set (scenes it is accepted for skip the sub-steps).
+void enqueue_solid_reg(sph_ctx *ctx) {
+  if (ctx->net && ctx->D.sur_thr > 0.0f) {
+    launch_sur_features(ctx->D, ctx->D.sur_stats, ctx->D.sur_x, ctx->stream);
+    mlp_launch_forward(ctx->net->D, ctx->D.sur_x, ctx->D.sur_y, ctx->D.ns, false, ctx->stream);
+    launch_sur_predict(ctx->D, ctx->stream);
+  }
+  launch_solid(ctx->D, ctx->cfg, ctx->stream);
+}
+
 int enqueue_solid(sph_ctx *ctx) {
   if (ctx->cfg.solid_ppt > 0) {
-    launch_solid(ctx->D, ctx->cfg, ctx->stream);
+    enqueue_solid_reg(ctx);
   } else if (ctx->D.ns > 0) {
     launch_solid_dt(ctx->D, ctx->stream);
     std::vector<SceneState> st(ctx->n_scenes);
@@ -452,7 +472,7 @@ int enqueue_step(sph_ctx *ctx, bool fork) {
       return SPH_E_HIP;
     launch_fluid_continuity(ctx->D, ctx->cfg, ctx->side);
     launch_couple(ctx->D, ctx->cfg, ctx->stream);
-    launch_solid(ctx->D, ctx->cfg, ctx->stream);
+    enqueue_solid_reg(ctx);
     if (hipEventRecord(ctx->ev_join, ctx->side) != hipSuccess ||
         hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0) != hipSuccess)
       return SPH_E_HIP;
@@ -496,6 +516,7 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   ctx->cfg = P.cfg;
   ctx->graph = nullptr;
   ctx->graph_exec = nullptr;
+  ctx->net = nullptr;
   ctx->side = nullptr;
   ctx->ev_fork = ctx->ev_join = nullptr;
   if (ctx->stream) {
@@ -780,6 +801,59 @@ int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out) {
     for (int k = 0; k < 8; ++k) o[k] += v[k];
   }
   std::memcpy(out, o, sizeof o);
+  return SPH_OK;
+}
+
+int sph_set_surrogate(sph_ctx *ctx, mlp_ctx *net, const float *stats, float threshold) {
+  if (!ctx) return SPH_E_ORDER;
+  if (net == nullptr || !(threshold > 0.0f)) {
+    ctx->net = nullptr;
+    ctx->D.sur_thr = 0.0f;
+  } else {
+    if (!stats || ctx->dim != 2 || ctx->cfg.solid_ppt <= 0 || net->D.in_dim != kSurFeat ||
+        net->D.out_dim != kSurOut || net->D.max_rows < ctx->D.ns || ctx->D.ns == 0)
+      return SPH_E_ARG;
+    HIPCHK(hipMemcpyAsync(ctx->D.sur_stats, stats, sizeof(float) * (2 * kSurFeat + 2 * kSurOut),
+                          hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->net = net;
+    ctx->D.sur_thr = threshold;
+  }
+  // the captured step no longer matches: capture again at the next sph_advance
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->graph_exec = nullptr;
+  ctx->graph = nullptr;
+  ctx->graph_failed = 0;
+  return SPH_OK;
+}
+
+int sph_solid_features(sph_ctx *ctx, const float *stats_dev, float *x_dev) {
+  if (!ctx) return SPH_E_ORDER;
+  if (!x_dev || ctx->dim != 2) return SPH_E_ARG;
+  launch_sur_features(ctx->D, stats_dev, x_dev, ctx->stream);
+  return check_launch(ctx, "sph_solid_features");
+}
+
+int sph_solid_targets(sph_ctx *ctx, const float *xraw_dev, float *t_dev) {
+  if (!ctx) return SPH_E_ORDER;
+  if (!xraw_dev || !t_dev || ctx->dim != 2) return SPH_E_ARG;
+  launch_sur_targets(ctx->D, xraw_dev, t_dev, ctx->stream);
+  return check_launch(ctx, "sph_solid_targets");
+}
+
+int sph_surrogate_counters(sph_ctx *ctx, int scene, unsigned long long *out) {
+  if (!ctx) return SPH_E_ORDER;
+  if (scene < -1 || scene >= ctx->n_scenes || !out) return SPH_E_ARG;
+  std::vector<SceneState> st;
+  int rc = read_states(ctx, st);
+  if (rc != SPH_OK) return rc;
+  out[0] = out[1] = 0;
+  for (int s = 0; s < ctx->n_scenes; ++s) {
+    if (scene >= 0 && s != scene) continue;
+    out[0] += st[s].sur_ok;
+    out[1] += st[s].sur_fallback;
+  }
   return SPH_OK;
 }
 

@@ -8,6 +8,9 @@ namespace mrsph {
 
 // cells per block of the multi-block cell scan
 constexpr int kCellTile = 4096;
+// surrogate: features and outputs per solid particle (2D)
+constexpr int kSurFeat = 24;
+constexpr int kSurOut = 4;
 
 struct LaunchCfg {
   int block_pair;    // threads per block of the fluid pair kernels
@@ -34,6 +37,9 @@ void launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st)
 void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 void launch_step_end(const Dev &D, hipStream_t st);
+void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t st);
+void launch_sur_targets(const Dev &D, const float *xraw, float *t, hipStream_t st);
+void launch_sur_predict(const Dev &D, hipStream_t st);
 void launch_solid_dt(const Dev &D, hipStream_t st);
 void launch_solid_first(const Dev &D, hipStream_t st);
 void launch_solid_pass(const Dev &D, int sub, hipStream_t st);

@@ -250,6 +250,7 @@ __global__ void k_init_solid(Dev D, int s, const double *x, const double *v, int
     D.s_v[k * NS + a] = (has_v && !clamp) ? v[(size_t)DIM * i + k] : 0.0;
     D.s_a[k * NS + a] = 0.0f;
     D.s_fF[k * NS + a] = 0.0f;
+    D.s_fFp[k * NS + a] = 0.0f;
     D.s_vbar[k * NS + a] = 0.0f;
     D.s_abar[k * NS + a] = 0.0f;
     D.s_du[k * NS + a] = 0.0;
@@ -965,7 +966,7 @@ __global__ void __launch_bounds__(256) k_couple(Dev D) {
   const ScenePar &P = D.par[s];
   int NS = D.ns;
   int local = aa - P.s_begin;
-  float fa[3] = {0.0f, 0.0f, 0.0f};
+  float fa[3] = {0.0f, 0.0f, 0.0f}, fap[3] = {0.0f, 0.0f, 0.0f};
   int k = active ? D.s_bslot[aa] : -1;
   if (active && local < P.s_count - P.s_nclamp && k >= 0) {
     float4 pb = D.b_pos[k], bv = D.b_vbar[k], bn = D.b_nrm[k];
@@ -980,15 +981,24 @@ __global__ void __launch_bounds__(256) k_couple(Dev D) {
         if (r2 >= P.r2max_f) continue;
         float4 vs = D.f_vs[i];
         float vi[3] = {vs.x, vs.y, vs.z};
-        float f[3];
-        coupling_force<DIM>(P, pi.w, vs.w, D.f_p[i], vi, r, pb, bv, bn, f);
-        for (int c = 0; c < DIM; ++c) fa[c] -= f[c];
+        float f[3], fp[3];
+        coupling_force<DIM>(P, pi.w, vs.w, D.f_p[i], vi, r, pb, bv, bn, f, fp);
+        for (int c = 0; c < DIM; ++c) {
+          fa[c] -= f[c];
+          fap[c] -= fp[c];
+        }
       }
     });
   }
-  for (int c = 0; c < DIM; ++c) fa[c] = group_sum<LPP>(fa[c]);
+  for (int c = 0; c < DIM; ++c) {
+    fa[c] = group_sum<LPP>(fa[c]);
+    fap[c] = group_sum<LPP>(fap[c]);
+  }
   if (active && q == 0)
-    for (int c = 0; c < DIM; ++c) D.s_fF[c * NS + a] = fa[c];
+    for (int c = 0; c < DIM; ++c) {
+      D.s_fF[c * NS + a] = fa[c];
+      D.s_fFp[c * NS + a] = fap[c];
+    }
 }
 
 // Fluid acoustic step, second part (Section 3.1 continuity with the Riemann
@@ -1116,6 +1126,13 @@ __global__ void k_step_close(Dev D) {
   const double dt_ac = S.dt_ac;
   unsigned long long inter = 2ull * (S.n_ff + S.n_fw + S.n_fs) + S.n_fs + 2ull * (unsigned long long)kap * S.n_ss;
   if (rebuilt && P.reinit) inter += S.n_ff + S.n_fw + S.n_fs;
+  // surrogate step: feature means, rate and residual passes over the solid pairs
+  if (S.sur) {
+    inter += 3ull * S.n_ss;
+    if (S.sur == 1) S.sur_ok += 1;
+    else S.sur_fallback += 1;
+    S.sur = 0;
+  }
   S.interactions += inter;
   S.substeps += kap;
   S.steps += 1;
@@ -1369,6 +1386,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
   const int T = blockDim.x, t = threadIdx.x;
   double *PBx = smem;
   double *Vx = smem + D2 * lds_n;
+  if (S.sur == 1) return;  // the surrogate's step was accepted for this scene
   double dt_ac = S.dt_ac;
   // own particles and their state
   int la[PPT];
@@ -1644,6 +1662,203 @@ __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
   bp.w = (float)(P.Vs * J);
   D.b_pos[kslot] = bp;
   D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
+}
+
+// ------------------------------------------------------------------ surrogate
+//
+// Learned replacement of the kappa solid sub-steps of one acoustic step (2D):
+// per free solid particle, 24 features (F - I, v, a and the pressure and
+// viscous parts of the coupling force, then the mean of these 12 values over
+// the particle's reference neighbours) go through the network, which predicts
+// the change of the time-averaged velocity and acceleration over the step
+// (vbar - v, abar - a; Section 3.2 defines the averages).  The prediction is
+// advanced to the step end (u += dt vbar, v += dt abar, F from the corrected
+// gradient of vbar) and checked: the acceleration of the momentum equation at
+// the predicted mid-step deformation must match abar,
+//   |abar - a(F_mid)|_2 / (|a(F_mid)|_2 + |g| sqrt(N)) <= threshold
+// over the scene's free particles; otherwise the scene runs the plain
+// sub-steps from the untouched state.
+
+// Own features of solid particle a (2D).
+__device__ __forceinline__ void sur_own(const Dev &D, int a, float *f) {
+  const int NS = D.ns;
+  for (int k = 0; k < 4; ++k) f[k] = (float)D.s_H[k * NS + a];
+  for (int k = 0; k < 2; ++k) {
+    f[4 + k] = (float)D.s_v[k * NS + a];
+    f[6 + k] = D.s_a[k * NS + a];
+    float fp = D.s_fFp[k * NS + a];
+    f[8 + k] = fp;
+    f[10 + k] = D.s_fF[k * NS + a] - fp;
+  }
+}
+
+// Features of every solid particle, in solid order (clamp rows zero),
+// standardised by (mean, 1/std) when stats is given.
+__global__ void __launch_bounds__(256) k_sur_features(Dev D, const float *stats, float *x) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  const ScenePar &P = D.par[D.s_scene[a]];
+  float *row = x + (size_t)a * kSurFeat;
+  if (a - P.s_begin >= P.s_count - P.s_nclamp) {
+    for (int k = 0; k < kSurFeat; ++k) row[k] = 0.0f;
+    return;
+  }
+  float f[kSurFeat], m[12];
+  sur_own(D, a, f);
+  for (int k = 0; k < 12; ++k) m[k] = 0.0f;
+  int cnt = D.s_cnt[a];
+  for (int q = 0; q < cnt; ++q) {
+    int b = __float_as_int(D.s_nbr[(size_t)q * D.ns + a].w);
+    float fb[12];
+    sur_own(D, b, fb);
+    for (int k = 0; k < 12; ++k) m[k] += fb[k];
+  }
+  float inv = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
+  for (int k = 0; k < 12; ++k) f[12 + k] = m[k] * inv;
+  for (int k = 0; k < kSurFeat; ++k) row[k] = stats ? (f[k] - stats[k]) * stats[kSurFeat + k] : f[k];
+}
+
+// Training targets after a plain step, from the raw features of its start:
+// (vbar - v, abar - a) per free particle, zero rows for the clamp.
+__global__ void __launch_bounds__(256) k_sur_targets(Dev D, const float *xraw, float *t) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  const ScenePar &P = D.par[D.s_scene[a]];
+  const int NS = D.ns;
+  float *row = t + (size_t)a * kSurOut;
+  bool clamp = a - P.s_begin >= P.s_count - P.s_nclamp;
+  for (int k = 0; k < 2; ++k) {
+    row[k] = clamp ? 0.0f : D.s_vbar[k * NS + a] - xraw[(size_t)a * kSurFeat + 4 + k];
+    row[2 + k] = clamp ? 0.0f : D.s_abar[k * NS + a] - xraw[(size_t)a * kSurFeat + 6 + k];
+  }
+}
+
+// Predicted averages from the network output.
+__global__ void __launch_bounds__(256) k_sur_apply(Dev D) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  const ScenePar &P = D.par[D.s_scene[a]];
+  const int NS = D.ns;
+  bool clamp = a - P.s_begin >= P.s_count - P.s_nclamp;
+  const float *mo = D.sur_stats + 2 * kSurFeat, *so = mo + kSurOut;
+  const float *y = D.sur_y + (size_t)a * kSurOut;
+  for (int k = 0; k < 2; ++k) {
+    float vb = (float)D.s_v[k * NS + a] + (y[k] * so[k] + mo[k]);
+    float ab = D.s_a[k * NS + a] + (y[2 + k] * so[2 + k] + mo[2 + k]);
+    D.sur_vbar[k * NS + a] = clamp ? 0.0f : vb;
+    D.sur_abar[k * NS + a] = clamp ? 0.0f : ab;
+  }
+}
+
+// Deformation rate from the predicted averaged velocity (the corrected
+// gradient of Section 2.2), F at the step end and P B at the mid step.
+__global__ void __launch_bounds__(256) k_sur_rate(Dev D) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  const ScenePar &P = D.par[D.s_scene[a]];
+  const int NS = D.ns;
+  if (a - P.s_begin >= P.s_count - P.s_nclamp) {
+    for (int k = 0; k < 4; ++k) D.s_PB[k * NS + a] = 0.0;
+    return;
+  }
+  const double dt = D.st[D.s_scene[a]].dt_ac;
+  double va[2] = {D.sur_vbar[a], D.sur_vbar[NS + a]};
+  double G[4] = {0.0, 0.0, 0.0, 0.0};
+  int cnt = D.s_cnt[a];
+  for (int q = 0; q < cnt; ++q) {
+    float4 g = D.s_nbr[(size_t)q * NS + a];
+    int b = __float_as_int(g.w);
+    double gv[2] = {g.x, g.y};
+    for (int i = 0; i < 2; ++i) {
+      double dv = (double)D.sur_vbar[i * NS + b] - va[i];
+      for (int j = 0; j < 2; ++j) G[i * 2 + j] += dv * gv[j];
+    }
+  }
+  double H[4], Hm[4], B[4], PB[4], J;
+  for (int k = 0; k < 4; ++k) B[k] = D.s_B[k * NS + a];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double dF = G[i * 2] * B[j * 2] + G[i * 2 + 1] * B[j * 2 + 1];
+      double h = D.s_H[(i * 2 + j) * NS + a];
+      H[i * 2 + j] = h + dt * dF;
+      Hm[i * 2 + j] = h + 0.5 * dt * dF;
+      D.sur_dF[(i * 2 + j) * NS + a] = dF;
+    }
+  nh_PB<2, double>(Hm, B, (double)P.mu, (double)P.lam, PB, J);
+  for (int k = 0; k < 4; ++k) {
+    D.sur_H[k * NS + a] = H[k];
+    D.s_PB[k * NS + a] = PB[k];
+  }
+}
+
+// One block per scene: acceleration at the predicted mid state, the scene's
+// residual and the verdict (accepted scenes skip the sub-steps).
+__global__ void __launch_bounds__(1024) k_sur_residual(Dev D) {
+  __shared__ double red[2][16];
+  const int s = blockIdx.x, NS = D.ns;
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  const int nfree = P.s_count - P.s_nclamp;
+  const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
+  double r2 = 0.0, n2 = 0.0;
+  for (int l = threadIdx.x; l < nfree; l += blockDim.x) {
+    int a = P.s_begin + l;
+    double PBa[4];
+    for (int k = 0; k < 4; ++k) PBa[k] = D.s_PB[k * NS + a];
+    double acc[2] = {0.0, 0.0};
+    int cnt = D.s_cnt[a];
+    for (int q = 0; q < cnt; ++q) {
+      float4 g = D.s_nbr[(size_t)q * NS + a];
+      int b = __float_as_int(g.w);
+      double gv[2] = {g.x, g.y};
+      for (int i = 0; i < 2; ++i)
+        acc[i] += (PBa[i * 2] + D.s_PB[(i * 2) * NS + b]) * gv[0] + (PBa[i * 2 + 1] + D.s_PB[(i * 2 + 1) * NS + b]) * gv[1];
+    }
+    for (int k = 0; k < 2; ++k) {
+      double am = ((double)P.Vs * acc[k] + (double)D.s_fF[k * NS + a]) * m_inv + (double)P.g[k];
+      D.sur_amid[k * NS + a] = (float)am;
+      double d = (double)D.sur_abar[k * NS + a] - am;
+      r2 += d * d;
+      n2 += am * am;
+    }
+  }
+  auto add = [](double x, double y) { return x + y; };
+  r2 = block_reduce(r2, add, red[0]);
+  n2 = block_reduce(n2, add, red[1]);
+  if (threadIdx.x == 0) {
+    if (nfree == 0) {
+      S.sur = 0;
+    } else {
+      double gabs = sqrt((double)P.g[0] * P.g[0] + (double)P.g[1] * P.g[1]);
+      double res = sqrt(r2) / (sqrt(n2) + gabs * sqrt((double)nfree));
+      bool ok = res <= (double)D.sur_thr;  // false for NaN
+      S.sur = ok ? 1 : 2;
+      if (ok) S.kappa = 0;
+    }
+  }
+}
+
+// Accepted scenes take the predicted step-end state.
+__global__ void __launch_bounds__(256) k_sur_commit(Dev D) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  const int s = D.s_scene[a], NS = D.ns;
+  const ScenePar &P = D.par[s];
+  const SceneState &S = D.st[s];
+  if (S.sur != 1 || a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  const double dt = S.dt_ac;
+  for (int k = 0; k < 2; ++k) {
+    float vb = D.sur_vbar[k * NS + a], ab = D.sur_abar[k * NS + a];
+    D.s_u[k * NS + a] += dt * (double)vb;
+    D.s_v[k * NS + a] += dt * (double)ab;
+    D.s_a[k * NS + a] = D.sur_amid[k * NS + a];
+    D.s_vbar[k * NS + a] = vb;
+    D.s_abar[k * NS + a] = ab;
+  }
+  for (int k = 0; k < 4; ++k) {
+    D.s_H[k * NS + a] = D.sur_H[k * NS + a];
+    D.s_dF[k * NS + a] = D.sur_dF[k * NS + a];
+  }
 }
 
 // ------------------------------------------------------------------ state I/O
@@ -2000,6 +2215,22 @@ void launch_solid_pass(const Dev &D, int sub, hipStream_t st) {
 
 void launch_solid_average(const Dev &D, hipStream_t st) {
   if (D.ns > 0) LAUNCH_DIM(D.dim, k_solid_average, grid_for(D.ns, 256), dim3(256), st, D);
+}
+
+void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t st) {
+  if (D.ns > 0) hipLaunchKernelGGL(k_sur_features, grid_for(D.ns, 256), dim3(256), 0, st, D, stats, x);
+}
+
+void launch_sur_targets(const Dev &D, const float *xraw, float *t, hipStream_t st) {
+  if (D.ns > 0) hipLaunchKernelGGL(k_sur_targets, grid_for(D.ns, 256), dim3(256), 0, st, D, xraw, t);
+}
+
+void launch_sur_predict(const Dev &D, hipStream_t st) {
+  if (D.ns == 0) return;
+  hipLaunchKernelGGL(k_sur_apply, grid_for(D.ns, 256), dim3(256), 0, st, D);
+  hipLaunchKernelGGL(k_sur_rate, grid_for(D.ns, 256), dim3(256), 0, st, D);
+  hipLaunchKernelGGL(k_sur_residual, dim3(D.n_scenes), dim3(1024), 0, st, D);
+  hipLaunchKernelGGL(k_sur_commit, grid_for(D.ns, 256), dim3(256), 0, st, D);
 }
 
 void launch_step_end(const Dev &D, hipStream_t st) {

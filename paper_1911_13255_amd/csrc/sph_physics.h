@@ -90,7 +90,7 @@ __device__ __forceinline__ float riemann_dv_dot_e(const ScenePar &P, float rho_i
 template <int DIM>
 __device__ __forceinline__ void coupling_force(const ScenePar &P, float m_i, float eh_i, float p_i,
                                                         const float *v_i, const float *rv, float4 bpos,
-                                                        float4 bvbar, float4 bnrm, float *f) {
+                                                        float4 bvbar, float4 bnrm, float *f, float *fp = nullptr) {
 #pragma clang fp contract(off)
   float r2 = rv[0] * rv[0] + rv[1] * rv[1];
   if (DIM == 3) r2 += rv[2] * rv[2];
@@ -111,6 +111,7 @@ __device__ __forceinline__ void coupling_force(const ScenePar &P, float m_i, flo
     // v_i - v_d = 2 (v_i - vbar)
     float dv = 2.0f * (v_i[k] - vb[k]);
     f[k] = cp * rv[k] + cv * dv;
+    if (fp) fp[k] = cp * rv[k];  // pressure part alone
   }
 }
 

@@ -56,6 +56,8 @@ struct SceneState {
   unsigned long long steps, rebuilds, substeps, interactions;
   unsigned long long acc_ff, acc_fw, acc_fs;  // pair counts being reduced after a rebuild
   int base_f, base_b;  // cell-scan prefix at the scene's first cell (rebuild)
+  int sur, pad3;       // surrogate verdict of this step: 0 none, 1 accepted, 2 fell back to sub-steps
+  unsigned long long sur_ok, sur_fallback;  // surrogate steps accepted / rejected
 };
 
 enum ErrBits { ERR_NAN_FLUID = 1, ERR_NAN_SOLID = 2, ERR_JACOBIAN = 4, ERR_CAPACITY = 8 };
@@ -117,6 +119,13 @@ struct Dev {
   double *s_u, *s_v, *s_du, *s_dv;  // integration state in FP64 (displacement, velocity, step increments)
   double *s_H, *s_dF, *s_B, *s_PB;  // H = F - I, dF/dt, B, P B in FP64 (d*d components)
   float *s_a, *s_fF, *s_vbar, *s_abar, *s_n0, *s_n;
+  float *s_fFp;                    // pressure part of the coupling force
+  // sub-step surrogate (2D): features, network output, predicted state
+  float *sur_x, *sur_y;            // ns x 24 standardised features, ns x 4 standardised outputs
+  float *sur_stats;                // feature mean[24], 1/std[24], output mean[4], std[4]
+  float *sur_vbar, *sur_abar, *sur_amid;  // predicted averages, acceleration at the predicted mid state
+  double *sur_H, *sur_dF;          // predicted F - I and dF/dt at the step end
+  float sur_thr;                   // residual threshold (0: surrogate off)
   double *s_r0d;                   // reference positions, FP64 (3 per particle)
   float4 *s_nbr;                   // [k * ns + a] = (V_b grad_a W_ab, b as int bits in w)
   // staging and reductions

@@ -101,6 +101,10 @@ def lib():
         L.sph_set_scalars.argtypes = [vp, C.c_int, _dp]
         L.sph_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
         L.sph_launch_config.argtypes = [vp, C.POINTER(C.c_int)]
+        L.sph_set_surrogate.argtypes = [vp, vp, C.POINTER(C.c_float), C.c_float]
+        L.sph_solid_features.argtypes = [vp, vp, vp]
+        L.sph_solid_targets.argtypes = [vp, vp, vp]
+        L.sph_surrogate_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
         L.sph_autotune.argtypes = [C.POINTER(SphScene), C.c_int, C.POINTER(SphOptions), vp, C.c_size_t, vp,
                                    C.c_int, C.c_int, C.POINTER(SphOptions), _dp]
         L.sph_reduce.argtypes = [vp, C.c_int, _dp]
@@ -244,6 +248,7 @@ class Simulation:
         self.nf = [len(s["x_fluid"]) for s in scenes]
         self.ns = [len(s["x_solid"]) for s in scenes]
         arr, self._keep = scene_array(scenes)
+        self._scene_dicts = scenes
         self._scenes = arr
         self.opt = make_options(riemann, density_reinit, max_solid_nbr, solid_block, lanes_per_particle,
                                 block_pair, solid_lds, max_fluid_nbr, max_boundary_nbr, serial_passes)
@@ -329,6 +334,67 @@ class Simulation:
         arr = np.array([cur["t"], 0.0, cur["dt_ad"], 0.0, cur["adv_accum"], 0.0,
                         float(cur["need_rebuild"]), 0.0])
         self._check(self.L.sph_set_scalars(self.ctx, int(scene), _ptr(arr)))
+
+    # --- learned sub-step surrogate
+    def _enter(self):
+        import torch
+
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        import torch
+
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def solid_count(self) -> int:
+        return sum(self.ns)
+
+    def free_mask(self):
+        """Boolean mask of the free (not clamped) solid particles, rows in solid order."""
+        m = []
+        for sc in self._scene_dicts:
+            n, nc = len(sc["x_solid"]), int(sc["n_clamp"])
+            m.append(np.r_[np.ones(n - nc, bool), np.zeros(nc, bool)])
+        return np.concatenate(m) if m else np.zeros(0, bool)
+
+    def solid_features(self, stats_dev=None, out=None):
+        """(n_solid x 24) FP32 device tensor of the surrogate features now
+        (call between couple and solid_substeps)."""
+        import torch
+
+        x = out if out is not None else torch.empty((self.solid_count(), 24), dtype=torch.float32, device=self.device)
+        self._enter()
+        self._check(self.L.sph_solid_features(self.ctx, None if stats_dev is None else C.c_void_p(stats_dev.data_ptr()),
+                                              C.c_void_p(x.data_ptr())))
+        self._leave()
+        return x
+
+    def solid_targets(self, xraw, out=None):
+        import torch
+
+        t = out if out is not None else torch.empty((self.solid_count(), 4), dtype=torch.float32, device=self.device)
+        self._enter()
+        self._check(self.L.sph_solid_targets(self.ctx, C.c_void_p(xraw.data_ptr()), C.c_void_p(t.data_ptr())))
+        self._leave()
+        return t
+
+    def set_surrogate(self, net, stats, threshold: float):
+        """net: mlp.Network (24 -> 4) or None; stats: 56 floats (feature mean,
+        feature 1/std, output mean, output std)."""
+        if net is None:
+            self._check(self.L.sph_set_surrogate(self.ctx, None, None, 0.0))
+            self._net = None
+            return
+        st = np.ascontiguousarray(stats, dtype=np.float32)
+        assert st.size == 56
+        self._check(self.L.sph_set_surrogate(self.ctx, net.ctx, st.ctypes.data_as(C.POINTER(C.c_float)),
+                                             float(threshold)))
+        self._net = net  # keep the network alive while the context uses it
+
+    def surrogate_counters(self, scene: int = -1) -> dict:
+        out = (C.c_ulonglong * 2)()
+        self._check(self.L.sph_surrogate_counters(self.ctx, int(scene), out))
+        return {"accepted": int(out[0]), "fallback": int(out[1])}
 
     def launch_config(self) -> dict:
         out = (C.c_int * 8)()
