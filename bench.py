@@ -83,6 +83,30 @@ def measured_traffic(workload, kernel):
     return None if ent is None else float(ent["bytes_per_launch"])
 
 
+def surrogate_leg(workload, scene, seconds=30.0, threshold=1e-3, log=None):
+    """Learned sub-steps against the plain ones on one scene: a network trained
+    on the GPU (the library's own forward and error passes) on plain
+    trajectories of 16 batched dam-break scenes, then the surrogate run with
+    its residual check and fallback, timed beside the plain run; tip error of
+    the surrogate run against the plain one."""
+    from paper_1911_13255_amd import scenes, surrogate
+
+    t0 = time.perf_counter()
+    X, T = surrogate.collect(scenes.batched_dam_breaks(64)[:16], steps=1500, every=10, warmup=200)
+    t1 = time.perf_counter()
+    net, stats, hist = surrogate.fit(X, T, seconds=seconds)
+    t2 = time.perf_counter()
+    if log:
+        log(f"[bench] surrogate: {X.shape[0]} training rows collected in {t1 - t0:.1f} s, "
+            f"trained {t2 - t1:.1f} s, loss {hist[0][2]:.3e} -> {hist[-1][2]:.3e}")
+    res = surrogate.evaluate(scene, net, stats, threshold, steps=2000, every=10, timing_steps=2000)
+    res.update(workload=workload, training_rows=int(X.shape[0]), training_seconds=t2 - t1,
+               training_loss_first=hist[0][2], training_loss_last=hist[-1][2],
+               trained_on="plain trajectories of batched_dam_breaks scenes 0-15, steps 200-1500 every 10")
+    net.close()
+    return res
+
+
 def cpu_baseline(scene, seconds=15.0):
     """The FP64 oracle on the host cores on a bounded prefix of the same run."""
     from oracle import oracle as ora
@@ -122,6 +146,9 @@ def main():
                     help="use the library's default launch shapes instead of the autotuned ones")
     ap.add_argument("--autotune-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "mrsph",
                                                               "autotune.json"))
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the learned sub-step leg (2D single-scene workloads only)")
+    ap.add_argument("--surrogate-seconds", type=float, default=30.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="only run a plain FP32 device copy of this many MiB five times (the "
                          "reference for scaling HBM byte counters) and exit")
@@ -236,6 +263,12 @@ def main():
                 algorithmic_bytes=alg_bytes, algorithmic_flops=alg_flops,
                 workgroups_per_launch=len(scs) if dominant == "k_solid_reg" else None)
 
+    sur = None
+    if not args.no_surrogate and dim == 2 and len(scs) == 1 and sim.solid_register_resident():
+        sur = surrogate_leg(args.workload, scs[0], seconds=args.surrogate_seconds,
+                            log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(f"[bench] surrogate {json.dumps(sur)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline and len(scs) == 1:
         cpu = cpu_baseline(scs[0], args.cpu_seconds)
@@ -274,6 +307,7 @@ def main():
         "autotuned": not args.no_autotune,
         "autotune_seconds": tune_s,
         "roofline": roof,
+        "surrogate": sur,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
