@@ -8,6 +8,8 @@ namespace mrsph {
 
 // cells per block of the multi-block cell scan
 constexpr int kCellTile = 4096;
+// particles per thread in the grid-wide step-end reductions
+constexpr int kReduceItems = 8;
 // surrogate: features and outputs per solid particle (2D)
 constexpr int kSurFeat = 24;
 constexpr int kSurOut = 4;

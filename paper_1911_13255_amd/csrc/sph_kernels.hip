@@ -259,8 +259,9 @@ __global__ void k_init_solid(Dev D, int s, const double *x, const double *v, int
   for (int k = 0; k < DIM * DIM; ++k) {
     D.s_H[k * NS + a] = 0.0;
     D.s_dF[k * NS + a] = 0.0;
-    D.s_PB[k * NS + a] = 0.0;
   }
+  for (int k = 0; k < 9; ++k) D.s_PB[(size_t)a * 9 + k] = 0.0;
+  D.s_vaos[a] = make_double4(0.0, 0.0, 0.0, 0.0);
   D.s_bslot[a] = -1;
   D.s_blin[a] = 0;
 }
@@ -510,27 +511,31 @@ __global__ void __launch_bounds__(1024) k_cell_sum(Dev D) {
 // Section 3.2: dt_ad = cfl_ad min(h / max(|v|max, U_ref), h^2 rho0 / eta)),
 // the scan prefix at each scene's first cell, and the exclusive scan of the
 // tile sums.
+__device__ __forceinline__ void rebuild_bookkeeping(const Dev &D) {
+  int bf = 0, bb = 0;
+  for (int s = 0; s < D.n_scenes; ++s) {
+    SceneState &S = D.st[s];
+    const ScenePar &P = D.par[s];
+    S.base_f = bf;
+    S.base_b = bb;
+    if (!S.need_rebuild) continue;
+    bf += P.f_count;
+    bb += P.b_count;
+    double vm = fmax((double)__uint_as_float(S.vmax_prev), (double)P.u_ref);
+    double dt = (double)P.cfl_ad * (double)P.hf / vm;
+    if (P.dt_visc > 0.0) dt = fmin(dt, P.dt_visc);
+    S.dt_ad = dt;
+    S.adv_accum = 0.0;
+    S.rebuilds += 1;
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_cell_prefix(Dev D, int ntiles) {
   __shared__ int sf[1024], sb[1024];
   __shared__ int carry[2];
   const int t = threadIdx.x, T = blockDim.x;
   if (t == 0) {
-    int bf = 0, bb = 0;
-    for (int s = 0; s < D.n_scenes; ++s) {
-      SceneState &S = D.st[s];
-      const ScenePar &P = D.par[s];
-      S.base_f = bf;
-      S.base_b = bb;
-      if (!S.need_rebuild) continue;
-      bf += P.f_count;
-      bb += P.b_count;
-      double vm = fmax((double)__uint_as_float(S.vmax_prev), (double)P.u_ref);
-      double dt = (double)P.cfl_ad * (double)P.hf / vm;
-      if (P.dt_visc > 0.0) dt = fmin(dt, P.dt_visc);
-      S.dt_ad = dt;
-      S.adv_accum = 0.0;
-      S.rebuilds += 1;
-    }
+    rebuild_bookkeeping(D);
     carry[0] = carry[1] = 0;
   }
   __syncthreads();
@@ -559,10 +564,7 @@ __global__ void __launch_bounds__(1024) k_cell_prefix(Dev D, int ntiles) {
 
 // Each tile: scan of its cells (kCellTile / blockDim consecutive cells per
 // thread), [start, end) of every cell of a rebuilding scene; counts reset.
-__global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
-  __shared__ int sf[1024], sb[1024];
-  const int g0 = blockIdx.x * kCellTile, g1 = min(D.ncell, g0 + kCellTile);
-  if (!tile_rebuilds(D, g0, g1)) return;
+__device__ __forceinline__ void apply_tile(const Dev &D, int g0, int g1, int2 base, int *sf, int *sb) {
   const int t = threadIdx.x, T = blockDim.x;
   const int per = kCellTile / T;
   const int gs = g0 + t * per, ge = min(g1, gs + per);
@@ -582,7 +584,6 @@ __global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
     sb[t] += ab;
     __syncthreads();
   }
-  int2 base = D.cell_part[blockIdx.x];
   int pf = base.x + sf[t] - lf, pb = base.y + sb[t] - lb;
   for (int g = gs; g < ge; ++g) {
     int s = D.cell_scene[g];
@@ -600,6 +601,22 @@ __global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
     pf += cf;
     pb += cbn;
   }
+}
+
+__global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
+  __shared__ int sf[1024], sb[1024];
+  const int g0 = blockIdx.x * kCellTile, g1 = min(D.ncell, g0 + kCellTile);
+  if (!tile_rebuilds(D, g0, g1)) return;
+  apply_tile(D, g0, g1, D.cell_part[blockIdx.x], sf, sb);
+}
+
+// All cells in one tile: bookkeeping, scan and [start, end) in one block.
+__global__ void __launch_bounds__(1024) k_cell_one(Dev D) {
+  __shared__ int sf[1024], sb[1024];
+  if (!tile_rebuilds(D, 0, D.ncell)) return;
+  if (threadIdx.x == 0) rebuild_bookkeeping(D);
+  __syncthreads();
+  apply_tile(D, 0, D.ncell, make_int2(0, 0), sf, sb);
 }
 
 // Counting-sort scatter into cell slots in arrival order, with the sort key
@@ -1165,39 +1182,38 @@ __global__ void k_step_close(Dev D) {
 // increments cleared; then k_solid_dt_close, one thread per scene.
 __global__ void __launch_bounds__(256) k_solid_dt_reduce(Dev D) {
   __shared__ float shv[16], sha[16];
-  __shared__ int key;
   const int dim = D.dim, NS = D.ns;
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  bool act = a < NS;
-  int s = D.s_scene[act ? a : blockIdx.x * blockDim.x];
-  const ScenePar &P = D.par[s];
-  float vm = 0.0f, am = 0.0f;
-  if (act) {
-    float v2 = 0.0f, a2 = 0.0f;
+  const int span = blockDim.x * kReduceItems;
+  const int a0 = blockIdx.x * span, a1 = min(NS, a0 + span);
+  for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+    D.s_vaos[a] = make_double4(D.s_v[a], D.s_v[NS + a], dim == 3 ? D.s_v[2 * NS + a] : 0.0, 0.0);
     for (int k = 0; k < dim; ++k) {
-      float v = (float)D.s_v[k * NS + a], q = D.s_a[k * NS + a];
-      v2 += v * v;
-      a2 += q * q;
       D.s_du[k * NS + a] = 0.0;
       D.s_dv[k * NS + a] = 0.0;
     }
-    if (a - P.s_begin < P.s_count - P.s_nclamp) {
-      vm = sqrtf(v2);
-      am = sqrtf(a2);
-    }
   }
-  SceneState &S = D.st[s];
+  const int s0 = D.s_scene[a0], s1 = D.s_scene[a1 - 1];
   auto fmx = [](float x, float y) { return fmaxf(x, y); };
-  if (block_uniform(s, &key)) {
+  for (int s = s0; s <= s1; ++s) {
+    const ScenePar &P = D.par[s];
+    float vm = 0.0f, am = 0.0f;
+    for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+      if (D.s_scene[a] != s || a - P.s_begin >= P.s_count - P.s_nclamp) continue;
+      float v2 = 0.0f, a2 = 0.0f;
+      for (int k = 0; k < dim; ++k) {
+        float v = (float)D.s_v[k * NS + a], q = D.s_a[k * NS + a];
+        v2 += v * v;
+        a2 += q * q;
+      }
+      vm = fmaxf(vm, sqrtf(v2));
+      am = fmaxf(am, sqrtf(a2));
+    }
     vm = block_reduce(vm, fmx, shv);
     am = block_reduce(am, fmx, sha);
     if (threadIdx.x == 0) {
-      atomic_max_pos(&S.smax_v, vm);
-      atomic_max_pos(&S.smax_a, am);
+      atomic_max_pos(&D.st[s].smax_v, vm);
+      atomic_max_pos(&D.st[s].smax_a, am);
     }
-  } else if (act) {
-    atomic_max_pos(&S.smax_v, fmaxf(vm, 0.0f));
-    atomic_max_pos(&S.smax_a, fmaxf(am, 0.0f));
   }
 }
 
@@ -1246,7 +1262,7 @@ __device__ __forceinline__ void solid_first_half(const Dev &D, const ScenePar &P
   double J;
   nh_PB<DIM, double>(H, B, (double)P.mu, (double)P.lam, PB, J);
   if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
-  for (int k = 0; k < DIM * DIM; ++k) D.s_PB[k * NS + a] = PB[k];
+  for (int k = 0; k < DIM * DIM; ++k) D.s_PB[(size_t)a * 9 + k] = PB[k];
 }
 
 // First half of sub-step 0 (clamp particles: zero stress).
@@ -1258,7 +1274,7 @@ __global__ void __launch_bounds__(256) k_solid_first(Dev D) {
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
   if (a - P.s_begin >= P.s_count - P.s_nclamp) {
-    for (int k = 0; k < DIM * DIM; ++k) D.s_PB[k * D.ns + a] = 0.0;
+    for (int k = 0; k < DIM * DIM; ++k) D.s_PB[(size_t)a * 9 + k] = 0.0;
     return;
   }
   solid_first_half<DIM>(D, P, S, a, 0.5 * S.dt_ac / S.kappa);
@@ -1276,7 +1292,7 @@ __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
   const int NS = D.ns;
   const double del = S.dt_ac / S.kappa;
   double PBa[9];
-  for (int k = 0; k < DIM * DIM; ++k) PBa[k] = D.s_PB[k * NS + a];
+  for (int k = 0; k < DIM * DIM; ++k) PBa[k] = D.s_PB[(size_t)a * 9 + k];
   double acc[3] = {0.0, 0.0, 0.0};
   int cnt = D.s_cnt[a];
 #pragma unroll 4
@@ -1284,20 +1300,26 @@ __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
     float4 g = D.s_nbr[(size_t)q * NS + a];
     int b = __float_as_int(g.w);
     double gv[3] = {g.x, g.y, g.z};
+    const double *pb = D.s_PB + (size_t)b * 9;  // one record per neighbour
+    double PBb[9];
+    for (int k = 0; k < DIM * DIM; ++k) PBb[k] = pb[k];
     for (int i = 0; i < DIM; ++i) {
       double sum = 0.0;
-      for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + D.s_PB[(i * DIM + j) * NS + b]) * gv[j];
+      for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + PBb[i * DIM + j]) * gv[j];
       acc[i] += sum;
     }
   }
   const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
+  double vn[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < DIM; ++k) {
     double ak = ((double)P.Vs * acc[k] + (double)D.s_fF[k * NS + a]) * m_inv + (double)P.g[k];
     D.s_a[k * NS + a] = (float)ak;
     double dv = del * ak;
-    D.s_v[k * NS + a] += dv;
+    vn[k] = D.s_v[k * NS + a] + dv;
+    D.s_v[k * NS + a] = vn[k];
     D.s_dv[k * NS + a] += dv;
   }
+  D.s_vaos[a] = make_double4(vn[0], vn[1], vn[2], 0.0);
 }
 
 // Deformation rate with the new velocity and second half of sub-step `sub`;
@@ -1321,8 +1343,10 @@ __global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
     float4 g = D.s_nbr[(size_t)q * NS + a];
     int b = __float_as_int(g.w);
     double gv[3] = {g.x, g.y, g.z};
+    double4 vb = D.s_vaos[b];
+    double vbv[3] = {vb.x, vb.y, vb.z};
     for (int i = 0; i < DIM; ++i) {
-      double dvi = D.s_v[i * NS + b] - va[i];
+      double dvi = vbv[i] - va[i];
       for (int j = 0; j < DIM; ++j) G[i * DIM + j] += dvi * gv[j];
     }
   }
@@ -1601,40 +1625,38 @@ template <int DIM>
 __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
   __shared__ float shm[16];
   __shared__ unsigned long long shc[3][16];
-  __shared__ int key;
   if ((int)blockIdx.x < fluid_blocks) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool act = i < D.nf;
-    int s = D.f_scene[act ? i : blockIdx.x * blockDim.x];
-    SceneState &S = D.st[s];
-    const bool rebuilt = S.need_rebuild != 0;
-    float m = act ? D.f_speed[i] : 0.0f;
-    m = fmaxf(m, 0.0f);  // a NaN speed is flagged by the continuity pass
-    unsigned long long c[3] = {0ull, 0ull, 0ull};
-    if (act && rebuilt) {
-      int4 n = D.f_nnb[i];
-      c[0] = (unsigned long long)n.x;
-      c[1] = (unsigned long long)n.y;
-      c[2] = (unsigned long long)n.z;
-    }
-    if (block_uniform(s, &key)) {
-      m = block_reduce(m, [](float x, float y) { return fmaxf(x, y); }, shm);
+    // kReduceItems particles per thread; one reduction and atomic per scene
+    // present in the block (scenes own contiguous ranges)
+    const int span = blockDim.x * kReduceItems;
+    const int i0 = blockIdx.x * span, i1 = min(D.nf, i0 + span);
+    const int s0 = D.f_scene[i0], s1 = D.f_scene[i1 - 1];
+    auto fmx = [](float x, float y) { return fmaxf(x, y); };
+    auto add = [](unsigned long long x, unsigned long long y) { return x + y; };
+    for (int s = s0; s <= s1; ++s) {
+      SceneState &S = D.st[s];
+      const bool rebuilt = S.need_rebuild != 0;
+      float m = 0.0f;  // fmaxf drops a NaN speed; the continuity pass flags it
+      unsigned long long c[3] = {0ull, 0ull, 0ull};
+      for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        if (D.f_scene[i] != s) continue;
+        m = fmaxf(m, D.f_speed[i]);
+        if (rebuilt) {
+          int4 n = D.f_nnb[i];
+          c[0] += (unsigned long long)n.x;
+          c[1] += (unsigned long long)n.y;
+          c[2] += (unsigned long long)n.z;
+        }
+      }
+      m = block_reduce(m, fmx, shm);
       if (threadIdx.x == 0) atomic_max_pos(&S.vmax_next, m);
       if (rebuilt) {
-        auto add = [](unsigned long long x, unsigned long long y) { return x + y; };
         for (int k = 0; k < 3; ++k) c[k] = block_reduce(c[k], add, shc[k]);
         if (threadIdx.x == 0) {
           atomicAdd(&S.acc_ff, c[0]);
           atomicAdd(&S.acc_fw, c[1]);
           atomicAdd(&S.acc_fs, c[2]);
         }
-      }
-    } else if (act) {
-      atomic_max_pos(&S.vmax_next, m);
-      if (rebuilt) {
-        atomicAdd(&S.acc_ff, c[0]);
-        atomicAdd(&S.acc_fw, c[1]);
-        atomicAdd(&S.acc_fs, c[2]);
       }
     }
     return;
@@ -1758,7 +1780,7 @@ __global__ void __launch_bounds__(256) k_sur_rate(Dev D) {
   const ScenePar &P = D.par[D.s_scene[a]];
   const int NS = D.ns;
   if (a - P.s_begin >= P.s_count - P.s_nclamp) {
-    for (int k = 0; k < 4; ++k) D.s_PB[k * NS + a] = 0.0;
+    for (int k = 0; k < 4; ++k) D.s_PB[(size_t)a * 9 + k] = 0.0;
     return;
   }
   const double dt = D.st[D.s_scene[a]].dt_ac;
@@ -1787,7 +1809,7 @@ __global__ void __launch_bounds__(256) k_sur_rate(Dev D) {
   nh_PB<2, double>(Hm, B, (double)P.mu, (double)P.lam, PB, J);
   for (int k = 0; k < 4; ++k) {
     D.sur_H[k * NS + a] = H[k];
-    D.s_PB[k * NS + a] = PB[k];
+    D.s_PB[(size_t)a * 9 + k] = PB[k];
   }
 }
 
@@ -1804,7 +1826,7 @@ __global__ void __launch_bounds__(1024) k_sur_residual(Dev D) {
   for (int l = threadIdx.x; l < nfree; l += blockDim.x) {
     int a = P.s_begin + l;
     double PBa[4];
-    for (int k = 0; k < 4; ++k) PBa[k] = D.s_PB[k * NS + a];
+    for (int k = 0; k < 4; ++k) PBa[k] = D.s_PB[(size_t)a * 9 + k];
     double acc[2] = {0.0, 0.0};
     int cnt = D.s_cnt[a];
     for (int q = 0; q < cnt; ++q) {
@@ -1812,7 +1834,8 @@ __global__ void __launch_bounds__(1024) k_sur_residual(Dev D) {
       int b = __float_as_int(g.w);
       double gv[2] = {g.x, g.y};
       for (int i = 0; i < 2; ++i)
-        acc[i] += (PBa[i * 2] + D.s_PB[(i * 2) * NS + b]) * gv[0] + (PBa[i * 2 + 1] + D.s_PB[(i * 2 + 1) * NS + b]) * gv[1];
+        acc[i] += (PBa[i * 2] + D.s_PB[(size_t)b * 9 + i * 2]) * gv[0] +
+                  (PBa[i * 2 + 1] + D.s_PB[(size_t)b * 9 + i * 2 + 1]) * gv[1];
     }
     for (int k = 0; k < 2; ++k) {
       double am = ((double)P.Vs * acc[k] + (double)D.s_fF[k * NS + a]) * m_inv + (double)P.g[k];
@@ -2158,9 +2181,13 @@ static inline dim3 grid_for(long long threads, int block) {
 void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_bin, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
   const int ntiles = (D.ncell + kCellTile - 1) / kCellTile;
-  hipLaunchKernelGGL(k_cell_sum, dim3(ntiles), dim3(1024), 0, st, D);
-  hipLaunchKernelGGL(k_cell_prefix, dim3(1), dim3(1024), 0, st, D, ntiles);
-  hipLaunchKernelGGL(k_cell_apply, dim3(ntiles), dim3(1024), 0, st, D);
+  if (ntiles == 1) {
+    hipLaunchKernelGGL(k_cell_one, dim3(1), dim3(1024), 0, st, D);
+  } else {
+    hipLaunchKernelGGL(k_cell_sum, dim3(ntiles), dim3(1024), 0, st, D);
+    hipLaunchKernelGGL(k_cell_prefix, dim3(1), dim3(1024), 0, st, D, ntiles);
+    hipLaunchKernelGGL(k_cell_apply, dim3(ntiles), dim3(1024), 0, st, D);
+  }
   if (D.nf + D.nb > 0) hipLaunchKernelGGL(k_scatter, grid_for(D.nf + D.nb, 256), dim3(256), 0, st, D);
   if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_rank_move, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
   if (D.nf > 0)
@@ -2199,7 +2226,9 @@ void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
 }
 
 void launch_solid_dt(const Dev &D, hipStream_t st) {
-  if (D.ns > 0) hipLaunchKernelGGL(k_solid_dt_reduce, grid_for(D.ns, 256), dim3(256), 0, st, D);
+  if (D.ns > 0)
+    hipLaunchKernelGGL(k_solid_dt_reduce, dim3((D.ns + 256 * kReduceItems - 1) / (256 * kReduceItems)), dim3(256), 0,
+                       st, D);
   hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
 }
 
@@ -2234,7 +2263,7 @@ void launch_sur_predict(const Dev &D, hipStream_t st) {
 }
 
 void launch_step_end(const Dev &D, hipStream_t st) {
-  int fb = (D.nf + 255) / 256, sb = (D.ns + 255) / 256;
+  int fb = (D.nf + 256 * kReduceItems - 1) / (256 * kReduceItems), sb = (D.ns + 255) / 256;
   if (fb + sb > 0) LAUNCH_DIM(D.dim, k_step_reduce, dim3(fb + sb), dim3(256), st, D, fb);
   hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
 }
