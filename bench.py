@@ -32,14 +32,16 @@ HBM_PEAK_GBS = 8000.0
 # reachable by code built without packed FP32 instructions).
 ALU_PEAK_TFLOPS = 78.6
 # Algorithmic cost per unit of work (derivations in the design notes):
-#  fluid force pass: own state read once and written once (164 B per fluid
-#  particle) plus one 4-byte pair-list entry per pair; 70 flops per pair.
+#  fluid force pass: own state read once and written once (144 B per fluid
+#  particle: reads position 16, mid-point snapshot 16, FP64 offset 32, row
+#  lengths 8, scene 4; writes offset 32, v 16, p 4, a 16) plus one 4-byte
+#  pair-list entry per pair; 70 flops per pair.
 #  continuity pass: 140 B per fluid particle plus 4 B per pair; 40 flops per pair.
 #  solid sub-step kernel (2D, register resident): the solid state read and
 #  written once per launch (270 B per free particle) and the reference
 #  neighbour table once (16 B per solid pair); per sub-step 33 flops per
 #  solid pair and pass direction and 200 flops per particle.
-FORCE_BYTES_PER_PARTICLE = 164.0
+FORCE_BYTES_PER_PARTICLE = 144.0
 CONT_BYTES_PER_PARTICLE = 140.0
 LIST_BYTES_PER_PAIR = 4.0
 FORCE_FLOPS_PER_PAIR = 70.0

@@ -566,6 +566,7 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   D.ncell = P.ncell;
   D.maxn = P.maxn;
   D.capf = P.capf;
+  D.fluid_prep = P.nf >= 100000 ? 1 : 0;
   D.capb = P.capb;
   D.lw = P.lw;
   ctx->stage_doubles = 9 * (size_t)std::max(P.max_count, 64) + 64;

@@ -8,6 +8,8 @@
 // cell origin.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sph_kernels.h"
 #include "sph_physics.h"
 
@@ -884,12 +886,25 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
 
 // ------------------------------------------------------------------ fluid step
 
+// Mid-point snapshot (v^n, eps^{n+1/2}) of every fluid particle for the
+// force pass and the coupling on the solid (half step of the density,
+// Section 3.3); one record per particle so that the force pass gathers a
+// neighbour's state in one read.  Used for large particle counts, where the
+// saved gathers outweigh one more launch.
+__global__ void __launch_bounds__(256) k_fluid_prep(Dev D) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.nf) return;
+  float dt = (float)D.st[D.f_scene[i]].dt_ac;
+  float4 va = D.f_va[i];
+  D.f_vs[i] = make_float4(va.x, va.y, va.z, va.w + 0.5f * dt * D.f_drho[i]);
+}
+
 // Fluid acoustic step, first part (Section 3.3, Eqs. verlet-first-half and
 // verlet-first-mediate; Section 3.1 momentum): half step of density (kept as
 // eps) and position, Riemann pressure and viscous forces from fluid
 // neighbours, coupling forces from walls and solid, gravity, full step of
-// velocity.  Writes (v^{n+1}, eps^{n+1/2}), the mid-point snapshot
-// (v^n, eps^{n+1/2}), pressure and acceleration.
+// velocity.  Reads the mid-point snapshot (v^n, eps^{n+1/2}) of k_fluid_prep;
+// writes (v^{n+1}, eps^{n+1/2}), pressure and acceleration.
 template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
   int g = particle_index();
@@ -897,13 +912,16 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
   bool active = i < D.nf;
   int ii = active ? i : 0;
   int s = D.nf > 0 ? D.f_scene[ii] : 0;
-  const ScenePar &P = D.par[s];
+  const ScenePar P = D.par[s];  // by value: the pair loop keeps its fields in registers
   float dt = (float)D.st[s].dt_ac;
   float4 pi = D.f_pos[ii];
-  float4 va = D.f_va[ii];
-  float ehi = va.w + 0.5f * dt * D.f_drho[ii];
+  // (v^n, eps^{n+1/2}): from k_fluid_prep for large particle counts, else formed here
+  const bool prep = D.fluid_prep != 0;
+  float4 va = prep ? D.f_vs[ii] : D.f_va[ii];
+  float ehi = prep ? va.w : va.w + 0.5f * dt * D.f_drho[ii];
   float rhoi = P.rho0 * (1.0f + ehi);
   float p_i = eos_p(ehi, P);
+  const bool tait7 = __all(P.gamma == 7.0f) != 0;  // before any divergence: uniform
   float mi = pi.w;
   float Vi = mi / rhoi;
   float vi[3] = {va.x, va.y, va.z};
@@ -912,6 +930,9 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
     const int2 rl = D.f_rowlen[i];
     const size_t lstride = (size_t)D.nf * LPP;
     const unsigned *lp = D.f_nbl + (size_t)i * LPP + q;
+    // the loop is written once and instantiated for both snapshot sources
+    auto fluid_pairs = [&](auto prep_tag) {
+      constexpr bool PREP = decltype(prep_tag)::value;
     for (int e = q; e < rl.x; e += LPP, lp += lstride) {
       unsigned ent = *lp;
       int j = (int)(ent & kNbrMask);
@@ -921,13 +942,20 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
         float4 pj = D.f_pos[j];
         float r[3] = {(pi.x - pj.x) - sh[0], (pi.y - pj.y) - sh[1], DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f};
         float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        float4 vj4 = D.f_va[j];
-        float ehj = vj4.w + 0.5f * dt * D.f_drho[j];
+        float4 vj4;
+        float ehj;
+        if (PREP) {
+          vj4 = D.f_vs[j];
+          ehj = vj4.w;
+        } else {
+          vj4 = D.f_va[j];
+          ehj = vj4.w + 0.5f * dt * D.f_drho[j];
+        }
         float rhoj = P.rho0 * (1.0f + ehj);
-        float p_j = eos_p(ehj, P);
-        float Vj = pj.w / rhoj;
-        float rr = sqrtf(r2);
-        float inv_r = 1.0f / rr;
+        float p_j = eos_p_pair(ehj, P, tait7);
+        float Vj = pj.w * fast_rcp(rhoj);
+        float rr = fast_sqrt(r2);
+        float inv_r = fast_rcp(rr);
         float e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
         float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
         float vj[3] = {vj4.x, vj4.y, vj4.z};
@@ -938,6 +966,9 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
         for (int k = 0; k < DIM; ++k) fsum[k] += cpress * e[k] + cvisc * (vi[k] - vj[k]);
       }
     }
+    };
+    if (prep) fluid_pairs(std::true_type{});
+    else fluid_pairs(std::false_type{});
     lp = D.f_bnl + (size_t)i * LPP + q;
     for (int e = q; e < rl.y; e += LPP, lp += lstride) {
       unsigned ent = *lp;
@@ -965,7 +996,7 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
   if (DIM == 3) off.z += hdt * vi[2];
   D.f_off[i] = off;
   D.f_vb[i] = make_float4(vn[0], vn[1], vn[2], ehi);
-  D.f_vs[i] = make_float4(vi[0], vi[1], vi[2], ehi);
+  if (!prep) D.f_vs[i] = make_float4(vi[0], vi[1], vi[2], ehi);
   D.f_p[i] = p_i;
   D.f_acc[i] = make_float4(a[0], a[1], a[2], 0.0f);
 }
@@ -1030,7 +1061,7 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
   bool active = i < D.nf;
   int ii = active ? i : 0;
   int s = D.nf > 0 ? D.f_scene[ii] : 0;
-  const ScenePar &P = D.par[s];
+  const ScenePar P = D.par[s];  // by value: the pair loop keeps its fields in registers
   SceneState &S = D.st[s];
   float4 pi = D.f_pos[ii];
   float4 vb = D.f_vb[ii];
@@ -1055,9 +1086,9 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
         float4 vj4 = D.f_vb[j];
         float rhoj = P.rho0 * (1.0f + vj4.w);
         float p_j = D.f_p[j];
-        float Vj = pj.w / rhoj;
-        float rr = sqrtf(r2);
-        float inv_r = 1.0f / rr;
+        float Vj = pj.w * fast_rcp(rhoj);
+        float rr = fast_sqrt(r2);
+        float inv_r = fast_rcp(rr);
         float e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
         float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
         float vj[3] = {vj4.x, vj4.y, vj4.z};
@@ -1075,7 +1106,7 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
         float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
         float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         float4 bv = D.b_vbar[k];
-        float rr = sqrtf(r2);
+        float rr = fast_sqrt(r2);
         float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
         float dv = (vi[0] - bv.x) * r[0] + (vi[1] - bv.y) * r[1];
         if (DIM == 3) dv += (vi[2] - bv.z) * r[2];
@@ -1390,14 +1421,15 @@ __global__ void __launch_bounds__(256) k_solid_average(Dev D) {
 // The same sub-steps for 2D scenes whose free solid fits the block with at
 // most PPT particles per thread: each thread keeps its particles' own state
 // (H, dF/dt, u in FP64; B and the step increments in FP32) in registers for
-// the whole launch, v and P B of the scene live in LDS, and only the fixed
+// the whole launch, v and P B of the scene live in LDS (one record per
+// particle, so a neighbour's values arrive in wide reads), and only the fixed
 // reference neighbour table is read from (L2-resident) global memory inside
 // the sub-step loop.
 // Block limits keep the register budget: 1024 threads for one particle per
 // thread, 640 for two, 512 for four.
 template <int DIM, int PPT>
 __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_solid_reg(Dev D, int lds_n) {
-  extern __shared__ double smem[];
+  extern __shared__ __align__(16) double smem[];
   __shared__ float red[2][1024];
   __shared__ int kap_sh;
   __shared__ double del_sh;
@@ -1449,10 +1481,10 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
   for (int l = t; l < n; l += T) {
     int a = base + l;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) Vx[k * lds_n + l] = D.s_v[k * NS + a];
+    for (int k = 0; k < DIM; ++k) Vx[l * DIM + k] = D.s_v[k * NS + a];
     if (l >= nfree)
 #pragma unroll
-      for (int k = 0; k < D2; ++k) PBx[k * lds_n + l] = 0.0;
+      for (int k = 0; k < D2; ++k) PBx[l * D2 + k] = 0.0;
   }
   __syncthreads();
   for (int w = pow2_ceil(T) / 2; w > 0; w >>= 1) {
@@ -1486,7 +1518,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
     }
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      double inc = hd * Vx[k * lds_n + la[p]];
+      double inc = hd * Vx[la[p] * DIM + k];
       u[p][k] += inc;
       du[p][k] += (float)inc;
     }
@@ -1494,7 +1526,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
     nh_PB<DIM, double>(H[p], Bd, (double)P.mu, (double)P.lam, PB, J);
     bad_J |= !(J > 0.0);
 #pragma unroll
-    for (int k = 0; k < D2; ++k) PBx[k * lds_n + la[p]] = PB[k];
+    for (int k = 0; k < D2; ++k) PBx[la[p] * D2 + k] = PB[k];
   };
 #pragma unroll
   for (int p = 0; p < PPT; ++p)
@@ -1508,7 +1540,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
       int l = la[p], a = base + l;
       double PBa[D2];
 #pragma unroll
-      for (int k = 0; k < D2; ++k) PBa[k] = PBx[k * lds_n + l];
+      for (int k = 0; k < D2; ++k) PBa[k] = PBx[l * D2 + k];
       double acc[3] = {0.0, 0.0, 0.0};
       int cnt = D.s_cnt[a];
 #pragma unroll 8
@@ -1520,7 +1552,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
         for (int i = 0; i < DIM; ++i) {
           double sum = 0.0;
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + PBx[(i * DIM + j) * lds_n + b]) * gv[j];
+          for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + PBx[b * D2 + i * DIM + j]) * gv[j];
           acc[i] += sum;
         }
       }
@@ -1529,7 +1561,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
         double ak = ((double)P.Vs * acc[k] + (double)fF[p][k]) * m_inv + (double)P.g[k];
         acc_last[p][k] = (float)ak;
         double d_v = del * ak;
-        Vx[k * lds_n + l] += d_v;
+        Vx[l * DIM + k] += d_v;
         dv[p][k] += (float)d_v;
       }
     }
@@ -1543,7 +1575,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
       int l = la[p], a = base + l;
       double va[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) va[k] = Vx[k * lds_n + l];
+      for (int k = 0; k < DIM; ++k) va[k] = Vx[l * DIM + k];
       double G[D2];
 #pragma unroll
       for (int k = 0; k < D2; ++k) G[k] = 0.0;
@@ -1555,7 +1587,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
         double gv[3] = {g.x, g.y, g.z};
 #pragma unroll
         for (int i = 0; i < DIM; ++i) {
-          double dvi = Vx[i * lds_n + b] - va[i];
+          double dvi = Vx[b * DIM + i] - va[i];
 #pragma unroll
           for (int j = 0; j < DIM; ++j) G[i * DIM + j] += dvi * gv[j];
         }
@@ -1599,7 +1631,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       D.s_u[k * NS + a] = u[p][k];
-      D.s_v[k * NS + a] = Vx[k * lds_n + l];
+      D.s_v[k * NS + a] = Vx[l * DIM + k];
       D.s_a[k * NS + a] = acc_last[p][k];
       vbar[k] = (float)((double)du[p][k] * inv_dt);
       abar[k] = (float)((double)dv[p][k] * inv_dt);
@@ -2196,6 +2228,7 @@ void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
 }
 
 void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
+  if (D.nf > 0 && D.fluid_prep) hipLaunchKernelGGL(k_fluid_prep, grid_for(D.nf, 256), dim3(256), 0, st, D);
   if (D.nf > 0)
     LAUNCH_LPP(k_fluid_force, cfg.lpp_force, D.dim, grid_for((long long)D.nf * cfg.lpp_force, cfg.block_pair),
                dim3(cfg.block_pair), st, D);

@@ -34,6 +34,23 @@ __device__ __forceinline__ float eos_p(float eps, const ScenePar &P) {
   return P.p_coef * expm1f(P.gamma * log1pf(eps));
 }
 
+// The same inside pair loops: `tait7` is true when every lane of the
+// wavefront belongs to a gamma = 7 scene (a uniform branch, so the general
+// power is not evaluated beside the polynomial).
+__device__ __forceinline__ float eos_p_pair(float eps, const ScenePar &P, bool tait7) {
+  if (tait7) {
+    float poly = 7.0f + eps * (21.0f + eps * (35.0f + eps * (35.0f + eps * (21.0f + eps * (7.0f + eps)))));
+    return P.p_coef * eps * poly;
+  }
+  return eos_p(eps, P);
+}
+
+// Reciprocal with the hardware approximation (1 ulp); for pair-loop
+// quotients that do not have to round like the coupling force's.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Square root with the hardware approximation (1 ulp), same use.
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Inverse: eps of the density at pressure p, with the bracket
 // 1 + gamma p / (rho0 c^2) clipped at 0 (zero density under extreme tension).
 __device__ __forceinline__ float eos_eps(float p, const ScenePar &P) {
@@ -76,7 +93,7 @@ __device__ __forceinline__ float riemann_dv_dot_e(const ScenePar &P, float rho_i
   // v_i - v* = (v_i - v_j)/2 + (U* - (U_L+U_R)/2) e, and e.e = 1
   float half = 0.5f * (dotv<DIM>(vi, e) - dotv<DIM>(vj, e));
   if (!P.riemann) return half;
-  return half + (p_i - p_j) / (2.0f * (0.5f * (rho_i + rho_j)) * P.c);
+  return half + (p_i - p_j) * fast_rcp((rho_i + rho_j) * P.c);  // / (2 rho_bar c)
 }
 
 // Force on fluid particle i from one wall or solid particle a, at h_F

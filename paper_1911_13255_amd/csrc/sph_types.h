@@ -75,7 +75,7 @@ struct Dev {
   double4 *f_posd; // frozen offset in FP64 (read by the number-density sum)
   float4 *f_va;    // (v, eps) at the step start
   float4 *f_vb;    // (v^{n+1}, eps^{n+1/2}) written by the force kernel
-  float4 *f_vs;    // mid-point snapshot (v^n, eps^{n+1/2}) for the coupling on the solid
+  float4 *f_vs;    // mid-point snapshot (v^n, eps^{n+1/2}): force pass and coupling on the solid
   float4 *f_acc;   // acceleration of the last step
   float *f_drho;   // d eps / dt kept for the next half step
   float *f_p;      // mid-step pressure
@@ -85,6 +85,7 @@ struct Dev {
   // Entry e of particle i sits at ((e / lw) * nf + i) * lw + e % lw, so the
   // lw lanes sharing a particle read lw consecutive entries.
   int capf, capb, lw;
+  int fluid_prep;  // 1: k_fluid_prep forms the mid-point snapshot before the force pass
   unsigned *f_nbl;  // fluid neighbours (capf entries per particle)
   unsigned *f_bnl;  // boundary neighbours: walls and free solid (capb per particle)
   int2 *f_rowlen;  // used length of each particle's two rows
