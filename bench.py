@@ -192,7 +192,7 @@ def main():
     tune_s = 0.0
     if not args.no_autotune:
         t0 = time.perf_counter()
-        opts = sph.autotune(scs, warmup=10 if dim == 3 else 50, steps=10 if dim == 3 else 300,
+        opts = sph.autotune(scs, warmup=10 if dim == 3 else 100, steps=10 if dim == 3 else 1000,
                             cache=args.autotune_cache)
         tune_s = time.perf_counter() - t0
         print(f"[bench] autotuned in {tune_s:.1f} s: {json.dumps(opts)}", file=sys.stderr, flush=True)

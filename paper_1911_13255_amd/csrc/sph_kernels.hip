@@ -1068,6 +1068,7 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
   float ehi = vb.w;
   float rhoi = P.rho0 * (1.0f + ehi);
   float p_i = D.f_p[ii];
+  const bool tait7 = __all(P.gamma == 7.0f) != 0;  // before any divergence: uniform
   float vi[3] = {vb.x, vb.y, vb.z};
   float drho = 0.0f;
   if (active) {
@@ -1085,7 +1086,11 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
         float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         float4 vj4 = D.f_vb[j];
         float rhoj = P.rho0 * (1.0f + vj4.w);
-        float p_j = D.f_p[j];
+        // the force pass's pressure: recomputed from eps for gamma = 7 (the same
+        // expression, so the same bits) instead of a second gather
+        float p_j;
+        if (tait7) p_j = eos_p_pair(vj4.w, P, true);
+        else p_j = D.f_p[j];
         float Vj = pj.w * fast_rcp(rhoj);
         float rr = fast_sqrt(r2);
         float inv_r = fast_rcp(rr);
@@ -1110,7 +1115,7 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
         float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
         float dv = (vi[0] - bv.x) * r[0] + (vi[1] - bv.y) * r[1];
         if (DIM == 3) dv += (vi[2] - bv.z) * r[2];
-        drho += rhoi * pb.w * (dv / rr) * dW;
+        drho += rhoi * pb.w * (dv * fast_rcp(rr)) * dW;
       }
     }
   }
