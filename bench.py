@@ -165,8 +165,8 @@ def main():
     if args.warmup is None:
         args.warmup = defaults[1]
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the hot path runs on one GPU only (asked for --gpus {args.gpus}); "
+              "run one process per GPU on its own share of the scenes instead", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -13,7 +13,8 @@ SOURCES = ["sph_kernels.hip", "sph_api.hip", "mlp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # no packed FP32 instructions (build)
+    # no packed FP32 instructions: some of their forms have given wrong
+    # results on this hardware without an error
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -228,7 +229,9 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
   // register-resident solid kernel (2D) when every scene's free solid fits
   // 2048 particles (at most 4 per thread); otherwise streamed passes
   P.cfg.solid_ppt = 0;
-  if (o.solid_lds != 1 && P.dim == 2 && max_free_scene > 0 && max_free_scene <= 2048) {
+  // (and its reference table fits the 31-bit range of a buffer resource)
+  const bool table_fits = (size_t)(P.maxn + kSolidBatch) * P.ns * sizeof(float4) < (size_t)INT_MAX;
+  if (o.solid_lds != 1 && P.dim == 2 && max_free_scene > 0 && max_free_scene <= 2048 && table_fits) {
     // block limits of the register-resident kernel: 1024, 640, 512 threads
     int ppt = max_free_scene <= 1024 ? 1 : (max_free_scene <= 1280 ? 2 : 4);
     int limit = ppt == 1 ? 1024 : (ppt == 2 ? 640 : 512);
@@ -377,7 +380,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.sur_H, 9 * ns);
   take(D.sur_dF, 9 * ns);
   take(D.s_r0d, 3 * ns);
-  take(D.s_nbr, (size_t)P.maxn * ns);
+  take(D.s_nbr, (size_t)(P.maxn + kSolidBatch) * ns);
   take(D.stage, 9 * (size_t)std::max(P.max_count, 64) + 64);
   take(D.red, 16 * 1024);
   return off + kAlign;
@@ -565,6 +568,11 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   D.nb = P.nb;
   D.ncell = P.ncell;
   D.maxn = P.maxn;
+  D.nbr_rows = P.maxn + kSolidBatch;
+  {
+    size_t tb = (size_t)D.nbr_rows * P.ns * sizeof(float4);
+    D.nbr_bytes = tb < (size_t)INT_MAX ? (int)tb : 0;
+  }
   D.capf = P.capf;
   D.fluid_prep = P.nf >= 100000 ? 1 : 0;
   D.capb = P.capb;

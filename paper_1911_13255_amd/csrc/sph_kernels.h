@@ -10,6 +10,12 @@ namespace mrsph {
 constexpr int kCellTile = 4096;
 // particles per thread in the grid-wide step-end reductions
 constexpr int kReduceItems = 8;
+// reference-table rows each lane loads ahead in the block-resident solid
+// kernel; the table carries this many null rows beyond the capacity
+#ifndef MRSPH_SOLID_BATCH
+#define MRSPH_SOLID_BATCH 2
+#endif
+constexpr int kSolidBatch = MRSPH_SOLID_BATCH;
 // surrogate: features and outputs per solid particle (2D)
 constexpr int kSurFeat = 24;
 constexpr int kSurOut = 4;

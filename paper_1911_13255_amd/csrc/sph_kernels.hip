@@ -89,6 +89,13 @@ __device__ __forceinline__ void cell_shift(const ScenePar &P, int cid, float *sh
 
 // Pair-list entries: neighbour index in the low 27 bits, relative cell id
 // (< 27) in the top 5.
+// four dwords as returned by a 128-bit buffer load (components by index in
+// unrolled loops; floats are reinterpreted per element with __int_as_float)
+typedef int i4v __attribute__((ext_vector_type(4)));
+// word 3 of a buffer resource on this architecture family: 32-bit data
+// format, raw byte addressing (stride 0), so loads past the range read zero
+constexpr int kBufferWord3 = 0x00020000;
+
 constexpr int kNbrBits = 27;
 constexpr unsigned kNbrMask = (1u << kNbrBits) - 1u;
 
@@ -319,6 +326,10 @@ __global__ void __launch_bounds__(256) k_solid_neighbours(Dev D, int s) {
   if (active) {
     D.s_cnt[a] = cnt < D.maxn ? cnt : D.maxn;
     if (cnt > D.maxn) atomicOr(&D.st[s].err, (int)ERR_CAPACITY);
+    // null entries (zero gradient, the particle itself) fill the rest of the
+    // list, so kernels may walk any row count up to nbr_rows
+    for (int q = min(cnt, D.maxn); q < D.nbr_rows; ++q)
+      D.s_nbr[(size_t)q * NS + a] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(a));
   }
 }
 
@@ -1447,6 +1458,9 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
   const int T = blockDim.x, t = threadIdx.x;
   double *PBx = smem;
   double *Vx = smem + D2 * lds_n;
+  // one LDS record per particle: a neighbour's P B (or v) arrives in wide reads
+  auto PI = [&](int l, int k) { return l * D2 + k; };
+  auto VI = [&](int l, int k) { return l * DIM + k; };
   if (S.sur == 1) return;  // the surrogate's step was accepted for this scene
   double dt_ac = S.dt_ac;
   // own particles and their state
@@ -1486,10 +1500,10 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
   for (int l = t; l < n; l += T) {
     int a = base + l;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) Vx[l * DIM + k] = D.s_v[k * NS + a];
+    for (int k = 0; k < DIM; ++k) Vx[VI(l, k)] = D.s_v[k * NS + a];
     if (l >= nfree)
 #pragma unroll
-      for (int k = 0; k < D2; ++k) PBx[l * D2 + k] = 0.0;
+      for (int k = 0; k < D2; ++k) PBx[PI(l, k)] = 0.0;
   }
   __syncthreads();
   for (int w = pow2_ceil(T) / 2; w > 0; w >>= 1) {
@@ -1523,7 +1537,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
     }
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      double inc = hd * Vx[la[p] * DIM + k];
+      double inc = hd * Vx[VI(la[p], k)];
       u[p][k] += inc;
       du[p][k] += (float)inc;
     }
@@ -1531,90 +1545,152 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
     nh_PB<DIM, double>(H[p], Bd, (double)P.mu, (double)P.lam, PB, J);
     bad_J |= !(J > 0.0);
 #pragma unroll
-    for (int k = 0; k < D2; ++k) PBx[la[p] * D2 + k] = PB[k];
+    for (int k = 0; k < D2; ++k) PBx[PI(la[p], k)] = PB[k];
   };
 #pragma unroll
   for (int p = 0; p < PPT; ++p)
     if (own[p]) first_half(p);
   __syncthreads();
-  for (int sub = 0; sub < kap; ++sub) {
-    // momentum, velocity
+  // Reference-table rows of the own particles.  Every row is padded past
+  // its count with null entries (zero gradient, the particle itself), so the
+  // lanes of a wave walk their rows in lockstep up to the wave's longest row
+  // without masking; a lane without a particle in slot p walks the first
+  // particle's row and discards the sums.  Entries arrive by buffer loads
+  // whose vector offset is the lane's particle and whose scalar offset is
+  // the row, so addressing costs no vector instructions.
+  const __amdgpu_buffer_rsrc_t tab =
+      __builtin_amdgcn_make_buffer_rsrc((void *)D.s_nbr, 0, D.nbr_bytes, kBufferWord3);
+  const int row_bytes = NS * (int)sizeof(float4);
+  unsigned voff[PPT];
+  int cnt_max = 0;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    int lo = own[p] ? la[p] : 0;
+    voff[p] = (unsigned)(base + lo) * (unsigned)sizeof(float4);
+    if (own[p]) cnt_max = max(cnt_max, D.s_cnt[base + lo]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt_max = max(cnt_max, __shfl_xor(cnt_max, o));
+  const int wrows = __builtin_amdgcn_readfirstlane(cnt_max);
+  auto entry = [&](int p, int q) {
+    return (i4v)__builtin_amdgcn_raw_buffer_load_b128(tab, voff[p], q * row_bytes, 0);
+  };
+  // sum_b g_ab of each own particle, fixed for the launch:
+  // sum_b (P_a B_a + P_b B_b) g_ab = P_a B_a sum_b g_ab + sum_b P_b B_b g_ab and
+  // sum_b (v_b - v_a) (x) g_ab = sum_b v_b (x) g_ab - v_a (x) sum_b g_ab
+  double gs[PPT][DIM];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p)
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) gs[p][k] = 0.0;
+  for (int q = 0; q < wrows; ++q)
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-      if (!own[p]) continue;
-      int l = la[p], a = base + l;
-      double PBa[D2];
+      i4v g = entry(p, q);
 #pragma unroll
-      for (int k = 0; k < D2; ++k) PBa[k] = PBx[l * D2 + k];
-      double acc[3] = {0.0, 0.0, 0.0};
-      int cnt = D.s_cnt[a];
-#pragma unroll 8
-      for (int q = 0; q < cnt; ++q) {
-        float4 g = D.s_nbr[(size_t)q * NS + a];
-        int b = __float_as_int(g.w) - base;
-        double gv[3] = {g.x, g.y, g.z};
+      for (int k = 0; k < DIM; ++k) gs[p][k] += (double)__int_as_float(g[k]);
+    }
+  for (int sub = 0; sub < kap; ++sub) {
+    // momentum, velocity
+    {
+      double acc[PPT][DIM];
 #pragma unroll
-        for (int i = 0; i < DIM; ++i) {
-          double sum = 0.0;
+      for (int p = 0; p < PPT; ++p)
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + PBx[b * D2 + i * DIM + j]) * gv[j];
-          acc[i] += sum;
-        }
+        for (int k = 0; k < DIM; ++k) acc[p][k] = 0.0;
+      for (int q0 = 0; q0 < wrows; q0 += kSolidBatch) {
+        i4v g[kSolidBatch][PPT];
+#pragma unroll
+        for (int r = 0; r < kSolidBatch; ++r)
+#pragma unroll
+          for (int p = 0; p < PPT; ++p) g[r][p] = entry(p, q0 + r);
+#pragma unroll
+        for (int r = 0; r < kSolidBatch; ++r)
+#pragma unroll
+          for (int p = 0; p < PPT; ++p) {
+            int b = g[r][p][3] - base;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+#pragma unroll
+              for (int j = 0; j < DIM; ++j) acc[p][i] += PBx[PI(b, i * DIM + j)] * (double)__int_as_float(g[r][p][j]);
+          }
       }
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) {
-        double ak = ((double)P.Vs * acc[k] + (double)fF[p][k]) * m_inv + (double)P.g[k];
-        acc_last[p][k] = (float)ak;
-        double d_v = del * ak;
-        Vx[l * DIM + k] += d_v;
-        dv[p][k] += (float)d_v;
+      for (int p = 0; p < PPT; ++p) {
+        if (!own[p]) continue;
+        int l = la[p];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          double own_term = 0.0;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) own_term += PBx[PI(l, k * DIM + j)] * gs[p][j];
+          double ak = ((double)P.Vs * (acc[p][k] + own_term) + (double)fF[p][k]) * m_inv + (double)P.g[k];
+          acc_last[p][k] = (float)ak;
+          double d_v = del * ak;
+          Vx[VI(l, k)] += d_v;
+          dv[p][k] += (float)d_v;
+        }
       }
     }
     __syncthreads();
     // deformation rate with the new velocity, second half; then the next
     // sub-step's first half and stress
     const bool more = sub + 1 < kap;
+    {
+      double G[PPT][D2];
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      if (!own[p]) continue;
-      int l = la[p], a = base + l;
-      double va[3] = {0.0, 0.0, 0.0};
+      for (int p = 0; p < PPT; ++p)
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) va[k] = Vx[l * DIM + k];
-      double G[D2];
+        for (int k = 0; k < D2; ++k) G[p][k] = 0.0;
+      for (int q0 = 0; q0 < wrows; q0 += kSolidBatch) {
+        i4v g[kSolidBatch][PPT];
 #pragma unroll
-      for (int k = 0; k < D2; ++k) G[k] = 0.0;
-      int cnt = D.s_cnt[a];
-#pragma unroll 8
-      for (int q = 0; q < cnt; ++q) {
-        float4 g = D.s_nbr[(size_t)q * NS + a];
-        int b = __float_as_int(g.w) - base;
-        double gv[3] = {g.x, g.y, g.z};
+        for (int r = 0; r < kSolidBatch; ++r)
 #pragma unroll
-        for (int i = 0; i < DIM; ++i) {
-          double dvi = Vx[b * DIM + i] - va[i];
+          for (int p = 0; p < PPT; ++p) g[r][p] = entry(p, q0 + r);
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) G[i * DIM + j] += dvi * gv[j];
-        }
+        for (int r = 0; r < kSolidBatch; ++r)
+#pragma unroll
+          for (int p = 0; p < PPT; ++p) {
+            int b = g[r][p][3] - base;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+              double vb = Vx[VI(b, i)];
+#pragma unroll
+              for (int j = 0; j < DIM; ++j) G[p][i * DIM + j] += vb * (double)__int_as_float(g[r][p][j]);
+            }
+          }
       }
-      // (v_b - v_a) (x) (B grad W) summed = G B^T
 #pragma unroll
-      for (int i = 0; i < DIM; ++i)
+      for (int p = 0; p < PPT; ++p) {
+        if (!own[p]) continue;
+        int l = la[p];
+        double va[DIM];
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-          double sum = 0.0;
+        for (int k = 0; k < DIM; ++k) va[k] = Vx[VI(l, k)];
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) sum += G[i * DIM + k] * (double)B[p][j * DIM + k];
-          dF[p][i * DIM + j] = sum;
-          H[p][i * DIM + j] += hd * sum;
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) G[p][i * DIM + j] -= va[i] * gs[p][j];
+        // (v_b - v_a) (x) (B grad W) summed = G B^T
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) {
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) sum += G[p][i * DIM + k] * (double)B[p][j * DIM + k];
+            dF[p][i * DIM + j] = sum;
+            H[p][i * DIM + j] += hd * sum;
+          }
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          double inc = hd * va[k];
+          u[p][k] += inc;
+          du[p][k] += (float)inc;
         }
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) {
-        double inc = hd * va[k];
-        u[p][k] += inc;
-        du[p][k] += (float)inc;
+        if (more) first_half(p);
       }
-      if (more) first_half(p);
     }
     __syncthreads();
   }
@@ -1636,7 +1712,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       D.s_u[k * NS + a] = u[p][k];
-      D.s_v[k * NS + a] = Vx[l * DIM + k];
+      D.s_v[k * NS + a] = Vx[VI(l, k)];
       D.s_a[k * NS + a] = acc_last[p][k];
       vbar[k] = (float)((double)du[p][k] * inv_dt);
       abar[k] = (float)((double)dv[p][k] * inv_dt);
