@@ -16,6 +16,10 @@ constexpr int kReduceItems = 8;
 #define MRSPH_SOLID_BATCH 2
 #endif
 constexpr int kSolidBatch = MRSPH_SOLID_BATCH;
+// doubles per P B record in LDS of the block-resident solid kernel: the four
+// 2D components padded to 48 bytes, a stride at which eight consecutive
+// records start on distinct LDS banks
+constexpr int solid_pb_record(int dim) { return dim == 2 ? 6 : dim * dim; }
 // surrogate: features and outputs per solid particle (2D)
 constexpr int kSurFeat = 24;
 constexpr int kSurOut = 4;

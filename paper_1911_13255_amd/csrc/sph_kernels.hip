@@ -92,6 +92,7 @@ __device__ __forceinline__ void cell_shift(const ScenePar &P, int cid, float *sh
 // four dwords as returned by a 128-bit buffer load (components by index in
 // unrolled loops; floats are reinterpreted per element with __int_as_float)
 typedef int i4v __attribute__((ext_vector_type(4)));
+typedef int i3v __attribute__((ext_vector_type(3)));
 // word 3 of a buffer resource on this architecture family: 32-bit data
 // format, raw byte addressing (stride 0), so loads past the range read zero
 constexpr int kBufferWord3 = 0x00020000;
@@ -318,7 +319,9 @@ __global__ void __launch_bounds__(256) k_solid_neighbours(Dev D, int s) {
         double Vb = P.Vs;
         float g[3] = {0.0f, 0.0f, 0.0f};
         for (int k = 0; k < DIM; ++k) g[k] = (float)(Vb * r[k] / rr * dW);
-        D.s_nbr[(size_t)cnt * NS + a] = make_float4(g[0], g[1], g[2], __int_as_float(P.s_begin + ib));
+        // (in 2D z holds the neighbour's index within the scene)
+        D.s_nbr[(size_t)cnt * NS + a] =
+            make_float4(g[0], g[1], DIM == 2 ? __int_as_float(ib) : g[2], __int_as_float(P.s_begin + ib));
       }
       cnt++;
     }
@@ -329,7 +332,7 @@ __global__ void __launch_bounds__(256) k_solid_neighbours(Dev D, int s) {
     // null entries (zero gradient, the particle itself) fill the rest of the
     // list, so kernels may walk any row count up to nbr_rows
     for (int q = min(cnt, D.maxn); q < D.nbr_rows; ++q)
-      D.s_nbr[(size_t)q * NS + a] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(a));
+      D.s_nbr[(size_t)q * NS + a] = make_float4(0.0f, 0.0f, DIM == 2 ? __int_as_float(i) : 0.0f, __int_as_float(a));
   }
 }
 
@@ -1456,10 +1459,11 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
   const int NS = D.ns;
   const int base = P.s_begin, n = P.s_count, nfree = P.s_count - P.s_nclamp;
   const int T = blockDim.x, t = threadIdx.x;
+  constexpr int PR = solid_pb_record(DIM);
   double *PBx = smem;
-  double *Vx = smem + D2 * lds_n;
+  double *Vx = smem + PR * lds_n;
   // one LDS record per particle: a neighbour's P B (or v) arrives in wide reads
-  auto PI = [&](int l, int k) { return l * D2 + k; };
+  auto PI = [&](int l, int k) { return (int)__umul24((unsigned)l, (unsigned)PR) + k; };
   auto VI = [&](int l, int k) { return l * DIM + k; };
   if (S.sur == 1) return;  // the surrogate's step was accepted for this scene
   double dt_ac = S.dt_ac;
@@ -1572,8 +1576,14 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) cnt_max = max(cnt_max, __shfl_xor(cnt_max, o));
   const int wrows = __builtin_amdgcn_readfirstlane(cnt_max);
-  auto entry = [&](int p, int q) {
-    return (i4v)__builtin_amdgcn_raw_buffer_load_b128(tab, voff[p], q * row_bytes, 0);
+  // in 2D z holds the index within the scene: one 12-byte load per entry
+  auto entry = [&](int p, int q) -> i4v {
+    if constexpr (DIM == 2) {
+      i3v e = (i3v)__builtin_amdgcn_raw_buffer_load_b96(tab, voff[p], q * row_bytes, 0);
+      return i4v{e[0], e[1], 0, e[2]};
+    } else {
+      return (i4v)__builtin_amdgcn_raw_buffer_load_b128(tab, voff[p], q * row_bytes, 0);
+    }
   };
   // sum_b g_ab of each own particle, fixed for the launch:
   // sum_b (P_a B_a + P_b B_b) g_ab = P_a B_a sum_b g_ab + sum_b P_b B_b g_ab and
@@ -1608,7 +1618,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
         for (int r = 0; r < kSolidBatch; ++r)
 #pragma unroll
           for (int p = 0; p < PPT; ++p) {
-            int b = g[r][p][3] - base;
+            const int b = DIM == 2 ? g[r][p][3] : g[r][p][3] - base;
 #pragma unroll
             for (int i = 0; i < DIM; ++i)
 #pragma unroll
@@ -1652,7 +1662,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
         for (int r = 0; r < kSolidBatch; ++r)
 #pragma unroll
           for (int p = 0; p < PPT; ++p) {
-            int b = g[r][p][3] - base;
+            const int b = DIM == 2 ? g[r][p][3] : g[r][p][3] - base;
 #pragma unroll
             for (int i = 0; i < DIM; ++i) {
               double vb = Vx[VI(b, i)];
@@ -2335,7 +2345,7 @@ void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   } while (0)
 
 void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
-  size_t bytes = (size_t)cfg.solid_lds_n * (D.dim * D.dim + D.dim) * sizeof(double);
+  size_t bytes = (size_t)cfg.solid_lds_n * solid_lds_bytes_per_particle(D.dim);
   LAUNCH_SOLID_REG(cfg.solid_ppt, dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
 }
 
@@ -2382,7 +2392,7 @@ void launch_step_end(const Dev &D, hipStream_t st) {
   hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
 }
 
-int solid_lds_bytes_per_particle(int dim) { return (dim * dim + dim) * (int)sizeof(double); }
+int solid_lds_bytes_per_particle(int dim) { return (solid_pb_record(dim) + dim) * (int)sizeof(double); }
 
 hipError_t allow_solid_lds(int dim, int ppt, size_t bytes) {
   if (dim != 2 || ppt <= 0) return hipErrorInvalidValue;
