@@ -380,6 +380,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.sur_H, 9 * ns);
   take(D.sur_dF, 9 * ns);
   take(D.s_r0d, 3 * ns);
+  take(D.s_gsum, 3 * ns);
   take(D.s_nbr, (size_t)(P.maxn + kSolidBatch) * ns);
   take(D.stage, 9 * (size_t)std::max(P.max_count, 64) + 64);
   take(D.red, 16 * 1024);
@@ -540,8 +541,8 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
       lds_max = 0;
     size_t need_lds = (size_t)ctx->cfg.solid_lds_n * solid_lds_bytes_per_particle(P.dim);
-    // the kernel's own shared arrays take 8 KiB + a few bytes
-    if (ctx->cfg.solid_lds_n <= 0 || need_lds + 9 * 1024 > (size_t)lds_max ||
+    // the kernel's own shared arrays take under 1 KiB
+    if (ctx->cfg.solid_lds_n <= 0 || need_lds + 1024 > (size_t)lds_max ||
         allow_solid_lds(P.dim, ctx->cfg.solid_ppt, need_lds) != hipSuccess) {
       ctx->cfg.solid_lds_n = 0;
       ctx->cfg.solid_ppt = 0;

@@ -294,6 +294,7 @@ __global__ void __launch_bounds__(256) k_solid_neighbours(Dev D, int s) {
   double alpha = DIM == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
   int cnt = 0;
   int NS = D.ns;
+  double gsum[3] = {0.0, 0.0, 0.0};
   for (int t0 = 0; t0 < P.s_count; t0 += 256) {
     __syncthreads();
     int tb = t0 + threadIdx.x;
@@ -318,7 +319,10 @@ __global__ void __launch_bounds__(256) k_solid_neighbours(Dev D, int s) {
         double dW = -5.0 * alpha * qq * t * t * t / h;
         double Vb = P.Vs;
         float g[3] = {0.0f, 0.0f, 0.0f};
-        for (int k = 0; k < DIM; ++k) g[k] = (float)(Vb * r[k] / rr * dW);
+        for (int k = 0; k < DIM; ++k) {
+          g[k] = (float)(Vb * r[k] / rr * dW);
+          gsum[k] += (double)g[k];  // of the stored values, in slot order
+        }
         // (in 2D z holds the neighbour's index within the scene)
         D.s_nbr[(size_t)cnt * NS + a] =
             make_float4(g[0], g[1], DIM == 2 ? __int_as_float(ib) : g[2], __int_as_float(P.s_begin + ib));
@@ -333,6 +337,7 @@ __global__ void __launch_bounds__(256) k_solid_neighbours(Dev D, int s) {
     // list, so kernels may walk any row count up to nbr_rows
     for (int q = min(cnt, D.maxn); q < D.nbr_rows; ++q)
       D.s_nbr[(size_t)q * NS + a] = make_float4(0.0f, 0.0f, DIM == 2 ? __int_as_float(i) : 0.0f, __int_as_float(a));
+    for (int k = 0; k < 3; ++k) D.s_gsum[k * NS + a] = gsum[k];
   }
 }
 
@@ -1449,7 +1454,7 @@ __global__ void __launch_bounds__(256) k_solid_average(Dev D) {
 template <int DIM, int PPT>
 __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_solid_reg(Dev D, int lds_n) {
   extern __shared__ __align__(16) double smem[];
-  __shared__ float red[2][1024];
+  __shared__ float red[2][16];
   __shared__ int kap_sh;
   __shared__ double del_sh;
   constexpr int D2 = DIM * DIM;
@@ -1499,8 +1504,16 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
     vm = fmaxf(vm, sqrtf(v2));
     am = fmaxf(am, sqrtf(a2));
   }
-  red[0][t] = vm;
-  red[1][t] = am;
+  // block maxima of |v| and |a|: wave shuffles, then one value per wave
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    vm = fmaxf(vm, __shfl_xor(vm, o));
+    am = fmaxf(am, __shfl_xor(am, o));
+  }
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = vm;
+    red[1][t >> 6] = am;
+  }
   for (int l = t; l < n; l += T) {
     int a = base + l;
 #pragma unroll
@@ -1510,14 +1523,11 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
       for (int k = 0; k < D2; ++k) PBx[PI(l, k)] = 0.0;
   }
   __syncthreads();
-  for (int w = pow2_ceil(T) / 2; w > 0; w >>= 1) {
-    if (t < w && t + w < T) {
-      red[0][t] = fmaxf(red[0][t], red[0][t + w]);
-      red[1][t] = fmaxf(red[1][t], red[1][t + w]);
-    }
-    __syncthreads();
-  }
   if (t == 0) {
+    for (int w = 1; w < (T + 63) / 64; ++w) {
+      red[0][0] = fmaxf(red[0][0], red[0][w]);
+      red[1][0] = fmaxf(red[1][0], red[1][w]);
+    }
     int kap;
     double dts;
     solid_kappa(P, S, red[0][0], red[1][0], dt_ac, kap, dts);
@@ -1585,21 +1595,14 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
       return (i4v)__builtin_amdgcn_raw_buffer_load_b128(tab, voff[p], q * row_bytes, 0);
     }
   };
-  // sum_b g_ab of each own particle, fixed for the launch:
+  // sum_b g_ab of each own particle (stored with the table):
   // sum_b (P_a B_a + P_b B_b) g_ab = P_a B_a sum_b g_ab + sum_b P_b B_b g_ab and
   // sum_b (v_b - v_a) (x) g_ab = sum_b v_b (x) g_ab - v_a (x) sum_b g_ab
   double gs[PPT][DIM];
 #pragma unroll
   for (int p = 0; p < PPT; ++p)
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) gs[p][k] = 0.0;
-  for (int q = 0; q < wrows; ++q)
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      i4v g = entry(p, q);
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) gs[p][k] += (double)__int_as_float(g[k]);
-    }
+    for (int k = 0; k < DIM; ++k) gs[p][k] = own[p] ? D.s_gsum[k * NS + base + la[p]] : 0.0;
   for (int sub = 0; sub < kap; ++sub) {
     // momentum, velocity
     {

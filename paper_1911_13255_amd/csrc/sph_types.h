@@ -130,6 +130,7 @@ struct Dev {
   double *sur_H, *sur_dF;          // predicted F - I and dF/dt at the step end
   float sur_thr;                   // residual threshold (0: surrogate off)
   double *s_r0d;                   // reference positions, FP64 (3 per particle)
+  double *s_gsum;                  // sum over the reference neighbours of the stored V_b grad_a W_ab, FP64 (SoA)
   float4 *s_nbr;                   // [k * ns + a] = (V_b grad_a W_ab, b as int bits in w; in 2D z holds b - scene start)
   int nbr_rows;                    // rows of s_nbr: maxn plus the null rows that pad every particle's list
   int nbr_bytes;                   // bytes of s_nbr (0 when it would not fit a 31-bit buffer range)
