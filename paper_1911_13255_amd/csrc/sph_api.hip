@@ -384,6 +384,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.s_nbr, (size_t)(P.maxn + kSolidBatch) * ns);
   take(D.stage, 9 * (size_t)std::max(P.max_count, 64) + 64);
   take(D.red, 16 * 1024);
+  take(D.rebuild_any, 1);
   return off + kAlign;
 }
 
@@ -598,6 +599,8 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   std::memset(s0.data(), 0, sizeof(SceneState) * n_scenes);
   for (auto &x : s0) x.need_rebuild = 1;
   HIPCHK_INIT(hipMemcpyAsync(D.st, s0.data(), sizeof(SceneState) * n_scenes, hipMemcpyHostToDevice, st));
+  static const int kOne = 1;
+  HIPCHK_INIT(hipMemcpyAsync(D.rebuild_any, &kOne, sizeof(int), hipMemcpyHostToDevice, st));
   if (P.ncell) {
     HIPCHK_INIT(hipMemcpyAsync(D.rank_to_lin, P.rank_to_lin.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
     HIPCHK_INIT(hipMemcpyAsync(D.cell_scene, P.cell_scene.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
@@ -795,6 +798,8 @@ int sph_set_scalars(sph_ctx *ctx, int scene, const double *in) {
   S.adv_accum = in[4];
   S.need_rebuild = in[6] != 0.0;
   HIPCHK(hipMemcpy(ctx->D.st + scene, &S, sizeof(SceneState), hipMemcpyHostToDevice));
+  const int one = 1;  // conservative: the rebuild kernels check the scenes' own flags
+  HIPCHK(hipMemcpy(ctx->D.rebuild_any, &one, sizeof(int), hipMemcpyHostToDevice));
   return SPH_OK;
 }
 

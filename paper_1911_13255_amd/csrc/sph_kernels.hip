@@ -87,8 +87,6 @@ __device__ __forceinline__ void cell_shift(const ScenePar &P, int cid, float *sh
   sh[2] = DIM == 3 ? (float)dz * P.cs[2] : 0.0f;
 }
 
-// Pair-list entries: neighbour index in the low 27 bits, relative cell id
-// (< 27) in the top 5.
 // four dwords as returned by a 128-bit buffer load (components by index in
 // unrolled loops; floats are reinterpreted per element with __int_as_float)
 typedef int i4v __attribute__((ext_vector_type(4)));
@@ -97,6 +95,8 @@ typedef int i3v __attribute__((ext_vector_type(3)));
 // format, raw byte addressing (stride 0), so loads past the range read zero
 constexpr int kBufferWord3 = 0x00020000;
 
+// Pair-list entries: neighbour index in the low 27 bits, relative cell id
+// (< 27) in the top 5.
 constexpr int kNbrBits = 27;
 constexpr unsigned kNbrMask = (1u << kNbrBits) - 1u;
 
@@ -444,6 +444,7 @@ __global__ void k_refresh_vmax(Dev D) {
 // cell, and a copy of the fluid state by old index.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_bin(Dev D) {
+  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < D.nf) {
     int i = t;
@@ -511,6 +512,7 @@ __device__ __forceinline__ bool tile_rebuilds(const Dev &D, int g0, int g1) {
 
 __global__ void __launch_bounds__(1024) k_cell_sum(Dev D) {
   __shared__ int shf[16], shb[16];
+  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
   const int g0 = blockIdx.x * kCellTile, g1 = min(D.ncell, g0 + kCellTile);
   if (!tile_rebuilds(D, g0, g1)) {
     if (threadIdx.x == 0) D.cell_part[blockIdx.x] = make_int2(0, 0);
@@ -554,6 +556,7 @@ __device__ __forceinline__ void rebuild_bookkeeping(const Dev &D) {
 __global__ void __launch_bounds__(1024) k_cell_prefix(Dev D, int ntiles) {
   __shared__ int sf[1024], sb[1024];
   __shared__ int carry[2];
+  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
   const int t = threadIdx.x, T = blockDim.x;
   if (t == 0) {
     rebuild_bookkeeping(D);
@@ -626,6 +629,7 @@ __device__ __forceinline__ void apply_tile(const Dev &D, int g0, int g1, int2 ba
 
 __global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
   __shared__ int sf[1024], sb[1024];
+  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
   const int g0 = blockIdx.x * kCellTile, g1 = min(D.ncell, g0 + kCellTile);
   if (!tile_rebuilds(D, g0, g1)) return;
   apply_tile(D, g0, g1, D.cell_part[blockIdx.x], sf, sb);
@@ -634,6 +638,7 @@ __global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
 // All cells in one tile: bookkeeping, scan and [start, end) in one block.
 __global__ void __launch_bounds__(1024) k_cell_one(Dev D) {
   __shared__ int sf[1024], sb[1024];
+  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
   if (!tile_rebuilds(D, 0, D.ncell)) return;
   if (threadIdx.x == 0) rebuild_bookkeeping(D);
   __syncthreads();
@@ -643,6 +648,7 @@ __global__ void __launch_bounds__(1024) k_cell_one(Dev D) {
 // Counting-sort scatter into cell slots in arrival order, with the sort key
 // (original index; boundary: source index) beside each entry.
 __global__ void __launch_bounds__(256) k_scatter(Dev D) {
+  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < D.nf) {
     int s = D.f_scene[t];
@@ -740,6 +746,7 @@ __device__ void gather_boundary(const Dev &D, const ScenePar &P, int k, int q) {
 // arrival order; the particle's state moves straight to that place.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_rank_move(Dev D) {
+  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < D.nf) {
     int s = D.f_scene[t];  // scenes own fixed index ranges
@@ -799,6 +806,7 @@ __device__ __forceinline__ T group_sum(T v) {
 // them), so each row is dense in visiting order whatever LPP is.
 template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_reinit(Dev D) {
+  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
   int g = particle_index();
   int i = g / LPP, q = g % LPP;
   bool active = i < D.nf;
@@ -1211,6 +1219,7 @@ __global__ void k_step_close(Dev D) {
   S.t += dt_ac;
   S.adv_accum += dt_ac;
   S.need_rebuild = S.adv_accum >= S.dt_ad ? 1 : 0;
+  if (S.need_rebuild) *D.rebuild_any = 1;  // cleared by k_step_reduce of the next step
   float vmax = __uint_as_float(S.vmax_next);
   S.vmax_prev = S.vmax_next;
   S.vmax_next = 0u;
@@ -1751,6 +1760,9 @@ template <int DIM>
 __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
   __shared__ float shm[16];
   __shared__ unsigned long long shc[3][16];
+  // this step's rebuild kernels are done; k_step_close sets the flag again
+  // for the scenes that close an advection step
+  if (blockIdx.x == 0 && threadIdx.x == 0) *D.rebuild_any = 0;
   if ((int)blockIdx.x < fluid_blocks) {
     // kReduceItems particles per thread; one reduction and atomic per scene
     // present in the block (scenes own contiguous ranges)
@@ -2244,7 +2256,10 @@ __global__ void k_reduce_final(Dev D, int nblocks, double *out) {
 }
 
 __global__ void k_set_rebuild(Dev D, int s) {
-  if (threadIdx.x == 0) D.st[s].need_rebuild = 1;
+  if (threadIdx.x == 0) {
+    D.st[s].need_rebuild = 1;
+    *D.rebuild_any = 1;
+  }
 }
 
 // ------------------------------------------------------------------ host-side launchers
