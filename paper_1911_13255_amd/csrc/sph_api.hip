@@ -385,7 +385,6 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.stage, 9 * (size_t)std::max(P.max_count, 64) + 64);
   take(D.red, 16 * 1024);
   take(D.rebuild_any, 1);
-  take(D.step_done, 1);
   return off + kAlign;
 }
 
@@ -602,7 +601,6 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   HIPCHK_INIT(hipMemcpyAsync(D.st, s0.data(), sizeof(SceneState) * n_scenes, hipMemcpyHostToDevice, st));
   static const int kOne = 1;
   HIPCHK_INIT(hipMemcpyAsync(D.rebuild_any, &kOne, sizeof(int), hipMemcpyHostToDevice, st));
-  HIPCHK_INIT(hipMemsetAsync(D.step_done, 0, sizeof(unsigned), st));
   if (P.ncell) {
     HIPCHK_INIT(hipMemcpyAsync(D.rank_to_lin, P.rank_to_lin.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
     HIPCHK_INIT(hipMemcpyAsync(D.cell_scene, P.cell_scene.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));

@@ -1186,11 +1186,13 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
 
 constexpr int KAPPA_MAX = 4096;
 
-// Close of an acoustic step for scene s (after the step-end reductions):
+// Close of an acoustic step, one thread per scene (after k_step_reduce):
 // time, advection accumulator and rebuild flag, next acoustic time step from
 // the reduced max fluid speed (Section 3.2), pair counts after a rebuild and
 // the interaction counters.
-__device__ void close_scene(const Dev &D, int s) {
+__global__ void k_step_close(Dev D) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= D.n_scenes) return;
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
   const bool rebuilt = S.need_rebuild != 0;  // the rebuild kernels of this step ran
@@ -1217,18 +1219,11 @@ __device__ void close_scene(const Dev &D, int s) {
   S.t += dt_ac;
   S.adv_accum += dt_ac;
   S.need_rebuild = S.adv_accum >= S.dt_ad ? 1 : 0;
-  if (S.need_rebuild) *D.rebuild_any = 1;  // cleared before the next step's close
+  if (S.need_rebuild) *D.rebuild_any = 1;  // cleared by k_step_reduce of the next step
   float vmax = __uint_as_float(S.vmax_next);
   S.vmax_prev = S.vmax_next;
   S.vmax_next = 0u;
   S.dt_ac = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)vmax);
-}
-
-// Stand-alone close (one block), for launches without particles to reduce.
-__global__ void k_step_close(Dev D) {
-  if (threadIdx.x == 0) *D.rebuild_any = 0;
-  __syncthreads();
-  for (int s = threadIdx.x; s < D.n_scenes; s += blockDim.x) close_scene(D, s);
 }
 
 // kappa solid sub-steps of the position-based Verlet scheme (Section 3.3,
@@ -1752,35 +1747,8 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
   }
 }
 
-// Hand-over of solid particle a's step results to its boundary particle.
-template <int DIM>
-__device__ void hand_over(const Dev &D, int a) {
-  const int NS = D.ns;
-  if (a >= NS) return;
-  const ScenePar &P = D.par[D.s_scene[a]];
-  if (a - P.s_begin >= P.s_count - P.s_nclamp) return;
-  int kslot = D.s_bslot[a];
-  if (kslot < 0) return;
-  double H[9];
-  for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
-  double J;
-  if (DIM == 2) J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
-  else
-    J = (1.0 + H[0]) * ((1.0 + H[4]) * (1.0 + H[8]) - H[5] * H[7]) - H[1] * (H[3] * (1.0 + H[8]) - H[5] * H[6]) +
-        H[2] * (H[3] * H[7] - (1.0 + H[4]) * H[6]);
-  float vbar[3] = {0.0f, 0.0f, 0.0f}, sa = 0.0f;
-  for (int k = 0; k < DIM; ++k) {
-    vbar[k] = D.s_vbar[k * NS + a];
-    sa += (D.s_abar[k * NS + a] - P.g[k]) * D.s_n[k * NS + a];
-  }
-  float4 bp = D.b_pos[kslot];
-  bp.w = (float)(P.Vs * J);
-  D.b_pos[kslot] = bp;
-  D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
-}
-
-// End of an acoustic step over all particles; its last block to finish
-// closes the step of every scene (close_scene).  Fluid blocks: max fluid speed for the next acoustic step and, after a rebuild,
+// End of an acoustic step over all particles, before k_step_close.  Fluid
+// blocks: max fluid speed for the next acoustic step and, after a rebuild,
 // the pair counts, folded into the scene's accumulators with one atomic per
 // block (per thread where a block spans two scenes).  Solid blocks: the
 // solid's averaged velocity and acceleration and its current volume are
@@ -1792,7 +1760,9 @@ template <int DIM>
 __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
   __shared__ float shm[16];
   __shared__ unsigned long long shc[3][16];
-  __shared__ bool last;
+  // this step's rebuild kernels are done; k_step_close sets the flag again
+  // for the scenes that close an advection step
+  if (blockIdx.x == 0 && threadIdx.x == 0) *D.rebuild_any = 0;
   if ((int)blockIdx.x < fluid_blocks) {
     // kReduceItems particles per thread; one reduction and atomic per scene
     // present in the block (scenes own contiguous ranges)
@@ -1827,22 +1797,31 @@ __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
         }
       }
     }
-  } else {
-    hand_over<DIM>(D, (blockIdx.x - fluid_blocks) * blockDim.x + threadIdx.x);
+    return;
   }
-  // the last block to finish closes the step of every scene: each block
-  // publishes its results before counting itself done, the last one
-  // acquires them before reading (no block waits for another)
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(D.step_done, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (threadIdx.x == 0) *D.rebuild_any = 0;  // the rebuild kernels of this step are done
-  __syncthreads();
-  for (int s = threadIdx.x; s < D.n_scenes; s += blockDim.x) close_scene(D, s);
-  if (threadIdx.x == 0) *D.step_done = 0u;
+  const int NS = D.ns;
+  int a = (blockIdx.x - fluid_blocks) * blockDim.x + threadIdx.x;
+  if (a >= NS) return;
+  const ScenePar &P = D.par[D.s_scene[a]];
+  if (a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  int kslot = D.s_bslot[a];
+  if (kslot < 0) return;
+  double H[9];
+  for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
+  double J;
+  if (DIM == 2) J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
+  else
+    J = (1.0 + H[0]) * ((1.0 + H[4]) * (1.0 + H[8]) - H[5] * H[7]) - H[1] * (H[3] * (1.0 + H[8]) - H[5] * H[6]) +
+        H[2] * (H[3] * H[7] - (1.0 + H[4]) * H[6]);
+  float vbar[3] = {0.0f, 0.0f, 0.0f}, sa = 0.0f;
+  for (int k = 0; k < DIM; ++k) {
+    vbar[k] = D.s_vbar[k * NS + a];
+    sa += (D.s_abar[k * NS + a] - P.g[k]) * D.s_n[k * NS + a];
+  }
+  float4 bp = D.b_pos[kslot];
+  bp.w = (float)(P.Vs * J);
+  D.b_pos[kslot] = bp;
+  D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
 }
 
 // ------------------------------------------------------------------ surrogate
@@ -2428,7 +2407,7 @@ void launch_sur_predict(const Dev &D, hipStream_t st) {
 void launch_step_end(const Dev &D, hipStream_t st) {
   int fb = (D.nf + 256 * kReduceItems - 1) / (256 * kReduceItems), sb = (D.ns + 255) / 256;
   if (fb + sb > 0) LAUNCH_DIM(D.dim, k_step_reduce, dim3(fb + sb), dim3(256), st, D, fb);
-  else hipLaunchKernelGGL(k_step_close, dim3(1), dim3(1024), 0, st, D);
+  hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
 }
 
 int solid_lds_bytes_per_particle(int dim) { return (solid_pb_record(dim) + dim) * (int)sizeof(double); }

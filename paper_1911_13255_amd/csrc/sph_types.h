@@ -137,7 +137,6 @@ struct Dev {
   // 0 only when no scene rebuilds at the next step start (the rebuild
   // kernels then exit after one load); 1 when some scene may
   int *rebuild_any;
-  unsigned *step_done;  // blocks of the step-end kernel done so far (0 between launches)
   // staging and reductions
   double *stage;
   double *red;
