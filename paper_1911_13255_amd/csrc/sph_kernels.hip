@@ -30,6 +30,10 @@ __device__ __forceinline__ int xcd_block() {
 
 __device__ __forceinline__ int particle_index() { return xcd_block() * blockDim.x + threadIdx.x; }
 
+// Component k of particle a's P B (component-major: the lanes of a wave
+// gather consecutive neighbours' component k from a few cache lines).
+__device__ __forceinline__ size_t pb_at(const Dev &D, int a, int k) { return (size_t)k * D.ns + a; }
+
 // smallest power of two >= n (block-wide tree reductions over any block size)
 __device__ __forceinline__ int pow2_ceil(int n) {
   int p = 1;
@@ -270,8 +274,7 @@ __global__ void k_init_solid(Dev D, int s, const double *x, const double *v, int
     D.s_H[k * NS + a] = 0.0;
     D.s_dF[k * NS + a] = 0.0;
   }
-  for (int k = 0; k < 9; ++k) D.s_PB[(size_t)a * 9 + k] = 0.0;
-  D.s_vaos[a] = make_double4(0.0, 0.0, 0.0, 0.0);
+  for (int k = 0; k < 9; ++k) D.s_PB[pb_at(D, a, k)] = 0.0;
   D.s_bslot[a] = -1;
   D.s_blin[a] = 0;
 }
@@ -1250,7 +1253,6 @@ __global__ void __launch_bounds__(256) k_solid_dt_reduce(Dev D) {
   const int span = blockDim.x * kReduceItems;
   const int a0 = blockIdx.x * span, a1 = min(NS, a0 + span);
   for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
-    D.s_vaos[a] = make_double4(D.s_v[a], D.s_v[NS + a], dim == 3 ? D.s_v[2 * NS + a] : 0.0, 0.0);
     for (int k = 0; k < dim; ++k) {
       D.s_du[k * NS + a] = 0.0;
       D.s_dv[k * NS + a] = 0.0;
@@ -1326,7 +1328,7 @@ __device__ __forceinline__ void solid_first_half(const Dev &D, const ScenePar &P
   double J;
   nh_PB<DIM, double>(H, B, (double)P.mu, (double)P.lam, PB, J);
   if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
-  for (int k = 0; k < DIM * DIM; ++k) D.s_PB[(size_t)a * 9 + k] = PB[k];
+  for (int k = 0; k < DIM * DIM; ++k) D.s_PB[pb_at(D, a, k)] = PB[k];
 }
 
 // First half of sub-step 0 (clamp particles: zero stress).
@@ -1338,7 +1340,7 @@ __global__ void __launch_bounds__(256) k_solid_first(Dev D) {
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
   if (a - P.s_begin >= P.s_count - P.s_nclamp) {
-    for (int k = 0; k < DIM * DIM; ++k) D.s_PB[(size_t)a * 9 + k] = 0.0;
+    for (int k = 0; k < DIM * DIM; ++k) D.s_PB[pb_at(D, a, k)] = 0.0;
     return;
   }
   solid_first_half<DIM>(D, P, S, a, 0.5 * S.dt_ac / S.kappa);
@@ -1356,7 +1358,7 @@ __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
   const int NS = D.ns;
   const double del = S.dt_ac / S.kappa;
   double PBa[9];
-  for (int k = 0; k < DIM * DIM; ++k) PBa[k] = D.s_PB[(size_t)a * 9 + k];
+  for (int k = 0; k < DIM * DIM; ++k) PBa[k] = D.s_PB[pb_at(D, a, k)];
   double acc[3] = {0.0, 0.0, 0.0};
   int cnt = D.s_cnt[a];
 #pragma unroll 4
@@ -1364,9 +1366,8 @@ __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
     float4 g = D.s_nbr[(size_t)q * NS + a];
     int b = __float_as_int(g.w);
     double gv[3] = {g.x, g.y, g.z};
-    const double *pb = D.s_PB + (size_t)b * 9;  // one record per neighbour
     double PBb[9];
-    for (int k = 0; k < DIM * DIM; ++k) PBb[k] = pb[k];
+    for (int k = 0; k < DIM * DIM; ++k) PBb[k] = D.s_PB[pb_at(D, b, k)];
     for (int i = 0; i < DIM; ++i) {
       double sum = 0.0;
       for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + PBb[i * DIM + j]) * gv[j];
@@ -1383,7 +1384,6 @@ __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
     D.s_v[k * NS + a] = vn[k];
     D.s_dv[k * NS + a] += dv;
   }
-  D.s_vaos[a] = make_double4(vn[0], vn[1], vn[2], 0.0);
 }
 
 // Deformation rate with the new velocity and second half of sub-step `sub`;
@@ -1407,8 +1407,7 @@ __global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
     float4 g = D.s_nbr[(size_t)q * NS + a];
     int b = __float_as_int(g.w);
     double gv[3] = {g.x, g.y, g.z};
-    double4 vb = D.s_vaos[b];
-    double vbv[3] = {vb.x, vb.y, vb.z};
+    double vbv[3] = {D.s_v[b], D.s_v[NS + b], DIM == 3 ? D.s_v[2 * NS + b] : 0.0};
     for (int i = 0; i < DIM; ++i) {
       double dvi = vbv[i] - va[i];
       for (int j = 0; j < DIM; ++j) G[i * DIM + j] += dvi * gv[j];
@@ -1918,7 +1917,7 @@ __global__ void __launch_bounds__(256) k_sur_rate(Dev D) {
   const ScenePar &P = D.par[D.s_scene[a]];
   const int NS = D.ns;
   if (a - P.s_begin >= P.s_count - P.s_nclamp) {
-    for (int k = 0; k < 4; ++k) D.s_PB[(size_t)a * 9 + k] = 0.0;
+    for (int k = 0; k < 4; ++k) D.s_PB[pb_at(D, a, k)] = 0.0;
     return;
   }
   const double dt = D.st[D.s_scene[a]].dt_ac;
@@ -1947,7 +1946,7 @@ __global__ void __launch_bounds__(256) k_sur_rate(Dev D) {
   nh_PB<2, double>(Hm, B, (double)P.mu, (double)P.lam, PB, J);
   for (int k = 0; k < 4; ++k) {
     D.sur_H[k * NS + a] = H[k];
-    D.s_PB[(size_t)a * 9 + k] = PB[k];
+    D.s_PB[pb_at(D, a, k)] = PB[k];
   }
 }
 
@@ -1964,7 +1963,7 @@ __global__ void __launch_bounds__(1024) k_sur_residual(Dev D) {
   for (int l = threadIdx.x; l < nfree; l += blockDim.x) {
     int a = P.s_begin + l;
     double PBa[4];
-    for (int k = 0; k < 4; ++k) PBa[k] = D.s_PB[(size_t)a * 9 + k];
+    for (int k = 0; k < 4; ++k) PBa[k] = D.s_PB[pb_at(D, a, k)];
     double acc[2] = {0.0, 0.0};
     int cnt = D.s_cnt[a];
     for (int q = 0; q < cnt; ++q) {
@@ -1972,8 +1971,8 @@ __global__ void __launch_bounds__(1024) k_sur_residual(Dev D) {
       int b = __float_as_int(g.w);
       double gv[2] = {g.x, g.y};
       for (int i = 0; i < 2; ++i)
-        acc[i] += (PBa[i * 2] + D.s_PB[(size_t)b * 9 + i * 2]) * gv[0] +
-                  (PBa[i * 2 + 1] + D.s_PB[(size_t)b * 9 + i * 2 + 1]) * gv[1];
+        acc[i] += (PBa[i * 2] + D.s_PB[pb_at(D, b, i * 2)]) * gv[0] +
+                  (PBa[i * 2 + 1] + D.s_PB[pb_at(D, b, i * 2 + 1)]) * gv[1];
     }
     for (int k = 0; k < 2; ++k) {
       double am = ((double)P.Vs * acc[k] + (double)D.s_fF[k * NS + a]) * m_inv + (double)P.g[k];

@@ -119,8 +119,7 @@ struct Dev {
   double *s_off0;  // reference offset from the reference cell, FP64
   double *s_u, *s_v, *s_du, *s_dv;  // integration state in FP64 (displacement, velocity, step increments)
   double *s_H, *s_dF, *s_B;        // H = F - I, dF/dt, B in FP64 (d*d components)
-  double *s_PB;                    // P B in FP64, one 9-double record per particle (neighbour gathers)
-  double4 *s_vaos;                 // velocity, one record per particle (neighbour gathers)
+  double *s_PB;                    // P B in FP64, component-major [k * ns + a] (9 components allocated)
   float *s_a, *s_fF, *s_vbar, *s_abar, *s_n0, *s_n;
   float *s_fFp;                    // pressure part of the coupling force
   // sub-step surrogate (2D): features, network output, predicted state
