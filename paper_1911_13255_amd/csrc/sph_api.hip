@@ -356,6 +356,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.b_nrm, nb);
   take(D.b_posd, nb);
   take(D.b_perm, nb);
+  take(D.b_solid, nb);
   take(D.bs_lin, nb);
   take(D.bs_slot, nb);
   take(D.bs_scene, nb);
@@ -381,6 +382,8 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.s_r0d, 3 * ns);
   take(D.s_gsum, 3 * ns);
   take(D.s_nbr, (size_t)(P.maxn + kSolidBatch) * ns);
+  take(D.s_cpl_cnt, ns);
+  take(D.s_cpl, (size_t)P.capf * ns);
   take(D.stage, 9 * (size_t)std::max(P.max_count, 64) + 64);
   take(D.red, 16 * 1024);
   take(D.rebuild_any, 1);
@@ -600,6 +603,7 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   HIPCHK_INIT(hipMemcpyAsync(D.st, s0.data(), sizeof(SceneState) * n_scenes, hipMemcpyHostToDevice, st));
   static const int kOne = 1;
   HIPCHK_INIT(hipMemcpyAsync(D.rebuild_any, &kOne, sizeof(int), hipMemcpyHostToDevice, st));
+  if (P.ns) HIPCHK_INIT(hipMemsetAsync(D.s_cpl_cnt, 0, sizeof(int) * P.ns, st));
   if (P.ncell) {
     HIPCHK_INIT(hipMemcpyAsync(D.rank_to_lin, P.rank_to_lin.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
     HIPCHK_INIT(hipMemcpyAsync(D.cell_scene, P.cell_scene.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));

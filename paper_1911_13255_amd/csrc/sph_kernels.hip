@@ -680,6 +680,7 @@ __device__ void gather_boundary(const Dev &D, const ScenePar &P, int k, int q) {
   float n[3] = {0.0f, 0.0f, 0.0f}, vb[3] = {0.0f, 0.0f, 0.0f}, ab[3] = {0.0f, 0.0f, 0.0f};
   float V, Vref;
   if (local < P.w_count) {
+    D.b_solid[k] = -1;
     float4 wn = D.w_nrm[P.w_begin + local];
     n[0] = wn.x;
     n[1] = wn.y;
@@ -733,6 +734,8 @@ __device__ void gather_boundary(const Dev &D, const ScenePar &P, int k, int q) {
     Vref = -P.Vs;
     D.s_bslot[a] = k;
     D.s_blin[a] = D.bs_lin[q];
+    D.b_solid[k] = a;
+    D.s_cpl_cnt[a] = 0;  // the fluid side fills the coupling list in k_reinit
   }
   float sa = 0.0f;
   for (int i = 0; i < DIM; ++i) sa += (ab[i] - P.g[i]) * n[i];
@@ -885,8 +888,16 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
             double dz = DIM == 3 ? (qi.z - qb.z) - shd[2] : 0.0;
             bool wall = D.b_nrm[k].w > 0.0f;
             psi += (wall ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy + dz * dz));
-            if (wall) nfw++;
-            else nfs++;
+            if (wall) {
+              nfw++;
+            } else {
+              nfs++;
+              // the transposed entry for the solid particle's coupling list,
+              // with the cell offset seen from its side (26 - cid)
+              const int a = D.b_solid[k];
+              const int e = atomicAdd(&D.s_cpl_cnt[a], 1);
+              if (e < D.capf) D.s_cpl[(size_t)e * D.ns + a] = ((unsigned)(26 - cid) << kNbrBits) | (unsigned)i;
+            }
             hit = true;
           }
         }
@@ -911,6 +922,33 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
       va.w = P.reinit == 2 ? fmaxf(va.w, (float)e) : (float)fmax(0.0, e);
       D.f_va[i] = va;
     }
+  }
+}
+
+// Coupling lists of the free solid particles of rebuilding scenes, put in
+// ascending entry order (their entries arrive by atomics in any order), so
+// the coupling sums do not depend on arrival order.  One 64-lane block per
+// solid particle: the list is staged in LDS and every entry goes to its rank
+// (entries are distinct: a fluid particle appears once per list).
+__global__ void __launch_bounds__(64) k_cpl_sort(Dev D) {
+  extern __shared__ unsigned ent[];
+  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
+  const int a = blockIdx.x;
+  const int s = D.s_scene[a];
+  if (!D.st[s].need_rebuild || D.s_bslot[a] < 0) return;
+  const int NS = D.ns;
+  const int c = D.s_cpl_cnt[a];
+  if (c > D.capf && threadIdx.x == 0) atomicOr(&D.st[s].err, (int)ERR_CAPACITY);
+  const int n = min(c, D.capf);
+  if (n < 2) return;
+  unsigned *l = D.s_cpl + a;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) ent[e] = l[(size_t)e * NS];
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const unsigned v = ent[e];
+    int rank = 0;
+    for (int f = 0; f < n; ++f) rank += ent[f] < v;
+    l[(size_t)rank * NS] = v;
   }
 }
 
@@ -1048,25 +1086,27 @@ __global__ void __launch_bounds__(256) k_couple(Dev D) {
   int k = active ? D.s_bslot[aa] : -1;
   if (active && local < P.s_count - P.s_nclamp && k >= 0) {
     float4 pb = D.b_pos[k], bv = D.b_vbar[k], bn = D.b_nrm[k];
-    int cb = P.cell_begin;
-    visit_cells<DIM>(P, D.s_blin[a], [&](int nl, const float *sh, int) {
-      int2 se = D.fc_se[cb + nl];
-      for (int i = se.x + q; i < se.y; i += LPP) {
-        float4 pi = D.f_pos[i];
-        // same rounding as the fluid side's (p_i - p_b) - shift
-        float r[3] = {(pi.x - pb.x) + sh[0], (pi.y - pb.y) + sh[1], DIM == 3 ? (pi.z - pb.z) + sh[2] : 0.0f};
-        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        if (r2 >= P.r2max_f) continue;
-        float4 vs = D.f_vs[i];
-        float vi[3] = {vs.x, vs.y, vs.z};
-        float f[3], fp[3];
-        coupling_force<DIM>(P, pi.w, vs.w, D.f_p[i], vi, r, pb, bv, bn, f, fp);
-        for (int c = 0; c < DIM; ++c) {
-          fa[c] -= f[c];
-          fap[c] -= fp[c];
-        }
+    // the fluid neighbours listed for this particle at the last rebuild
+    const int n = min(D.s_cpl_cnt[a], D.capf);
+    for (int e = q; e < n; e += LPP) {
+      const unsigned ent = D.s_cpl[(size_t)e * NS + a];
+      const int i = (int)(ent & kNbrMask);
+      float sh[3];
+      cell_shift<DIM>(P, (int)(ent >> kNbrBits), sh);
+      float4 pi = D.f_pos[i];
+      // same rounding as the fluid side's (p_i - p_b) - shift
+      float r[3] = {(pi.x - pb.x) + sh[0], (pi.y - pb.y) + sh[1], DIM == 3 ? (pi.z - pb.z) + sh[2] : 0.0f};
+      float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      if (r2 >= P.r2max_f) continue;  // listed pairs passed this same test
+      float4 vs = D.f_vs[i];
+      float vi[3] = {vs.x, vs.y, vs.z};
+      float f[3], fp[3];
+      coupling_force<DIM>(P, pi.w, vs.w, D.f_p[i], vi, r, pb, bv, bn, f, fp);
+      for (int c = 0; c < DIM; ++c) {
+        fa[c] -= f[c];
+        fap[c] -= fp[c];
       }
-    });
+    }
   }
   for (int c = 0; c < DIM; ++c) {
     fa[c] = group_sum<LPP>(fa[c]);
@@ -2333,6 +2373,7 @@ void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   if (D.nf > 0)
     LAUNCH_LPP(k_reinit, cfg.lpp_reinit, D.dim, grid_for((long long)D.nf * cfg.lpp_reinit, cfg.block_pair),
                dim3(cfg.block_pair), st, D);
+  if (D.ns > 0) hipLaunchKernelGGL(k_cpl_sort, dim3(D.ns), dim3(64), D.capf * sizeof(unsigned), st, D);
 }
 
 void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {

@@ -112,6 +112,7 @@ struct Dev {
   float4 *b_nrm;   // normal (xyz), +V_ref for walls / -V_ref for solid (w)
   double4 *b_posd; // frozen offset in FP64
   int *b_perm, *bs_lin, *bs_slot, *bs_scene;
+  int *b_solid;  // per boundary slot: its solid particle, or -1 for a wall
   double4 *bs_off;
   // solid (per scene in original order), SoA with component stride ns
   int ns, maxn;
@@ -122,6 +123,8 @@ struct Dev {
   double *s_PB;                    // P B in FP64, component-major [k * ns + a] (9 components allocated)
   float *s_a, *s_fF, *s_vbar, *s_abar, *s_n0, *s_n;
   float *s_fFp;                    // pressure part of the coupling force
+  int *s_cpl_cnt;                  // fluid neighbours of each free solid particle (set at rebuilds)
+  unsigned *s_cpl;                 // [e * ns + a]: fluid index | (cell offset id << kNbrBits), ascending
   // sub-step surrogate (2D): features, network output, predicted state
   float *sur_x, *sur_y;            // ns x 24 standardised features, ns x 4 standardised outputs
   float *sur_stats;                // feature mean[24], 1/std[24], output mean[4], std[4]
