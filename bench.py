@@ -31,25 +31,31 @@ HBM_PEAK_GBS = 8000.0
 # x 2 flops (FMA) x 2.4 GHz (the packed-FP32 figure of 157.3 TFLOP/s is not
 # reachable by code built without packed FP32 instructions).
 ALU_PEAK_TFLOPS = 78.6
-# Algorithmic cost per unit of work (derivations in the design notes):
+# Algorithmic cost per unit of work:
 #  fluid force pass: own state read once and written once (144 B per fluid
 #  particle: reads position 16, mid-point snapshot 16, FP64 offset 32, row
 #  lengths 8, scene 4; writes offset 32, v 16, p 4, a 16) plus one 4-byte
 #  pair-list entry per pair; 70 flops per pair.
 #  continuity pass: 140 B per fluid particle plus 4 B per pair; 40 flops per pair.
-#  solid sub-step kernel (2D, register resident): the solid state read and
-#  written once per launch (270 B per free particle) and the reference
-#  neighbour table once (16 B per solid pair); per sub-step 33 flops per
-#  solid pair and pass direction and 200 flops per particle.
+#  solid sub-step kernel (2D, block resident): the solid state read and
+#  written once per launch (300 B per free particle: reads H, dF/dt, B 32 each,
+#  u and v 16 each, v again for the shared copy 16, a and f^F 8 each, the
+#  gradient sum 16, the neighbour count 4; writes H, dF/dt 32 each, u, v 16
+#  each, a, vbar, abar 8 each) and the reference neighbour table once (12 B
+#  per solid pair); per sub-step 22 flops per solid pair (momentum 12: the
+#  stress sum 4, its product with the gradient 6, the accumulation 2; rate 10:
+#  the velocity difference 2, its outer product with the gradient 4, the
+#  accumulation 4) and about 130 flops per particle (Neo-Hookean stress and
+#  P B about 80, G B^T 12, the integration updates about 40).
 FORCE_BYTES_PER_PARTICLE = 144.0
 CONT_BYTES_PER_PARTICLE = 140.0
 LIST_BYTES_PER_PAIR = 4.0
 FORCE_FLOPS_PER_PAIR = 70.0
 CONT_FLOPS_PER_PAIR = 40.0
-SOLID_BYTES_PER_PARTICLE = 270.0
-SOLID_BYTES_PER_PAIR = 16.0
-SOLID_FLOPS_PER_PAIR = 33.0
-SOLID_FLOPS_PER_PARTICLE = 200.0
+SOLID_BYTES_PER_PARTICLE = 300.0
+SOLID_BYTES_PER_PAIR = 12.0
+SOLID_FLOPS_PER_PAIR_SUBSTEP = 22.0
+SOLID_FLOPS_PER_PARTICLE_SUBSTEP = 130.0
 
 
 def make_workload(name):
@@ -246,7 +252,8 @@ def main():
     }
     if sim.solid_register_resident():
         cand["k_solid_reg"] = (kt["k_solid"], SOLID_BYTES_PER_PARTICLE * ns_free + SOLID_BYTES_PER_PAIR * c1["n_ss"],
-                               kappa * (2 * SOLID_FLOPS_PER_PAIR * c1["n_ss"] + SOLID_FLOPS_PER_PARTICLE * ns_free))
+                               kappa * (SOLID_FLOPS_PER_PAIR_SUBSTEP * c1["n_ss"] +
+                                        SOLID_FLOPS_PER_PARTICLE_SUBSTEP * ns_free))
     dominant = max(cand, key=lambda k: cand[k][0])
     dur_ms, alg_bytes, alg_flops = cand[dominant]
     dur = dur_ms * 1e-3
