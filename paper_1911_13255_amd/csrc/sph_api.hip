@@ -386,7 +386,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.s_cpl, (size_t)P.capf * ns);
   take(D.stage, 9 * (size_t)std::max(P.max_count, 64) + 64);
   take(D.red, 16 * 1024);
-  take(D.rebuild_any, 1);
+  take(D.rebuild_count, 1);
   return off + kAlign;
 }
 
@@ -601,8 +601,8 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   std::memset(s0.data(), 0, sizeof(SceneState) * n_scenes);
   for (auto &x : s0) x.need_rebuild = 1;
   HIPCHK_INIT(hipMemcpyAsync(D.st, s0.data(), sizeof(SceneState) * n_scenes, hipMemcpyHostToDevice, st));
-  static const int kOne = 1;
-  HIPCHK_INIT(hipMemcpyAsync(D.rebuild_any, &kOne, sizeof(int), hipMemcpyHostToDevice, st));
+  // every scene starts with its flag set
+  HIPCHK_INIT(hipMemcpy(D.rebuild_count, &n_scenes, sizeof(int), hipMemcpyHostToDevice));
   if (P.ns) HIPCHK_INIT(hipMemsetAsync(D.s_cpl_cnt, 0, sizeof(int) * P.ns, st));
   if (P.ncell) {
     HIPCHK_INIT(hipMemcpyAsync(D.rank_to_lin, P.rank_to_lin.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
@@ -799,10 +799,15 @@ int sph_set_scalars(sph_ctx *ctx, int scene, const double *in) {
   S.t = in[0];
   S.dt_ad = in[2];
   S.adv_accum = in[4];
+  const int was = S.need_rebuild;
   S.need_rebuild = in[6] != 0.0;
   HIPCHK(hipMemcpy(ctx->D.st + scene, &S, sizeof(SceneState), hipMemcpyHostToDevice));
-  const int one = 1;  // conservative: the rebuild kernels check the scenes' own flags
-  HIPCHK(hipMemcpy(ctx->D.rebuild_any, &one, sizeof(int), hipMemcpyHostToDevice));
+  if (S.need_rebuild != was) {  // keep the count of set flags (the stream is idle here)
+    int cnt = 0;
+    HIPCHK(hipMemcpy(&cnt, ctx->D.rebuild_count, sizeof(int), hipMemcpyDeviceToHost));
+    cnt += S.need_rebuild - was;
+    HIPCHK(hipMemcpy(ctx->D.rebuild_count, &cnt, sizeof(int), hipMemcpyHostToDevice));
+  }
   return SPH_OK;
 }
 

@@ -447,7 +447,7 @@ __global__ void k_refresh_vmax(Dev D) {
 // cell, and a copy of the fluid state by old index.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_bin(Dev D) {
-  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < D.nf) {
     int i = t;
@@ -515,7 +515,7 @@ __device__ __forceinline__ bool tile_rebuilds(const Dev &D, int g0, int g1) {
 
 __global__ void __launch_bounds__(1024) k_cell_sum(Dev D) {
   __shared__ int shf[16], shb[16];
-  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   const int g0 = blockIdx.x * kCellTile, g1 = min(D.ncell, g0 + kCellTile);
   if (!tile_rebuilds(D, g0, g1)) {
     if (threadIdx.x == 0) D.cell_part[blockIdx.x] = make_int2(0, 0);
@@ -559,7 +559,7 @@ __device__ __forceinline__ void rebuild_bookkeeping(const Dev &D) {
 __global__ void __launch_bounds__(1024) k_cell_prefix(Dev D, int ntiles) {
   __shared__ int sf[1024], sb[1024];
   __shared__ int carry[2];
-  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   const int t = threadIdx.x, T = blockDim.x;
   if (t == 0) {
     rebuild_bookkeeping(D);
@@ -632,7 +632,7 @@ __device__ __forceinline__ void apply_tile(const Dev &D, int g0, int g1, int2 ba
 
 __global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
   __shared__ int sf[1024], sb[1024];
-  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   const int g0 = blockIdx.x * kCellTile, g1 = min(D.ncell, g0 + kCellTile);
   if (!tile_rebuilds(D, g0, g1)) return;
   apply_tile(D, g0, g1, D.cell_part[blockIdx.x], sf, sb);
@@ -641,7 +641,7 @@ __global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
 // All cells in one tile: bookkeeping, scan and [start, end) in one block.
 __global__ void __launch_bounds__(1024) k_cell_one(Dev D) {
   __shared__ int sf[1024], sb[1024];
-  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   if (!tile_rebuilds(D, 0, D.ncell)) return;
   if (threadIdx.x == 0) rebuild_bookkeeping(D);
   __syncthreads();
@@ -651,7 +651,7 @@ __global__ void __launch_bounds__(1024) k_cell_one(Dev D) {
 // Counting-sort scatter into cell slots in arrival order, with the sort key
 // (original index; boundary: source index) beside each entry.
 __global__ void __launch_bounds__(256) k_scatter(Dev D) {
-  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < D.nf) {
     int s = D.f_scene[t];
@@ -752,7 +752,7 @@ __device__ void gather_boundary(const Dev &D, const ScenePar &P, int k, int q) {
 // arrival order; the particle's state moves straight to that place.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_rank_move(Dev D) {
-  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < D.nf) {
     int s = D.f_scene[t];  // scenes own fixed index ranges
@@ -812,7 +812,7 @@ __device__ __forceinline__ T group_sum(T v) {
 // them), so each row is dense in visiting order whatever LPP is.
 template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_reinit(Dev D) {
-  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   int g = particle_index();
   int i = g / LPP, q = g % LPP;
   bool active = i < D.nf;
@@ -932,7 +932,7 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
 // (entries are distinct: a fluid particle appears once per list).
 __global__ void __launch_bounds__(64) k_cpl_sort(Dev D) {
   extern __shared__ unsigned ent[];
-  if (*D.rebuild_any == 0) return;  // no scene rebuilds this step
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   const int a = blockIdx.x;
   const int s = D.s_scene[a];
   if (!D.st[s].need_rebuild || D.s_bslot[a] < 0) return;
@@ -1229,20 +1229,20 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
 
 constexpr int KAPPA_MAX = 4096;
 
-// Close of an acoustic step, one thread per scene (after k_step_reduce):
+// Close of an acoustic step of scene s (after the step-end reductions):
 // time, advection accumulator and rebuild flag, next acoustic time step from
 // the reduced max fluid speed (Section 3.2), pair counts after a rebuild and
 // the interaction counters.
-__global__ void k_step_close(Dev D) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= D.n_scenes) return;
+// vmax: the step's max fluid speed (float bits); counts: the pair counts
+// after a rebuild (null: take the accumulators the reduction kernel filled).
+__device__ void close_scene(const Dev &D, int s, unsigned vmax_bits, const unsigned long long *counts) {
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
   const bool rebuilt = S.need_rebuild != 0;  // the rebuild kernels of this step ran
   if (rebuilt) {
-    S.n_ff = S.acc_ff;
-    S.n_fw = S.acc_fw;
-    S.n_fs = S.acc_fs;
+    S.n_ff = counts ? counts[0] : S.acc_ff;
+    S.n_fw = counts ? counts[1] : S.acc_fw;
+    S.n_fs = counts ? counts[2] : S.acc_fs;
     S.acc_ff = S.acc_fw = S.acc_fs = 0ull;
   }
   const int kap = S.kappa;
@@ -1261,12 +1261,19 @@ __global__ void k_step_close(Dev D) {
   S.steps += 1;
   S.t += dt_ac;
   S.adv_accum += dt_ac;
-  S.need_rebuild = S.adv_accum >= S.dt_ad ? 1 : 0;
-  if (S.need_rebuild) *D.rebuild_any = 1;  // cleared by k_step_reduce of the next step
-  float vmax = __uint_as_float(S.vmax_next);
-  S.vmax_prev = S.vmax_next;
+  const int was = S.need_rebuild, now = S.adv_accum >= S.dt_ad ? 1 : 0;
+  S.need_rebuild = now;
+  if (now != was) atomicAdd(D.rebuild_count, now - was);
+  float vmax = __uint_as_float(vmax_bits);
+  S.vmax_prev = vmax_bits;
   S.vmax_next = 0u;
   S.dt_ac = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)vmax);
+}
+
+__global__ void k_step_close(Dev D) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= D.n_scenes) return;
+  close_scene(D, s, D.st[s].vmax_next, nullptr);
 }
 
 // kappa solid sub-steps of the position-based Verlet scheme (Section 3.3,
@@ -1488,6 +1495,47 @@ __global__ void __launch_bounds__(256) k_solid_average(Dev D) {
     bad |= !isfinite(vb) || !isfinite(ab);
   }
   if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
+}
+
+// Hand-over of free solid particle a's step results to its boundary particle
+// seen by the fluid: current volume V0 det F, averaged velocity and the
+// hydrostatic factor max(0, (abar - g).n).
+template <int DIM>
+__device__ __forceinline__ void hand_over_values(const Dev &D, const ScenePar &P, int a, double J, const float *vbar,
+                                                 const float *abar) {
+  const int NS = D.ns;
+  const int kslot = D.s_bslot[a];
+  if (kslot < 0) return;
+  float sa = 0.0f;
+  for (int k = 0; k < DIM; ++k) sa += (abar[k] - P.g[k]) * D.s_n[k * NS + a];
+  float4 bp = D.b_pos[kslot];
+  bp.w = (float)(P.Vs * J);
+  D.b_pos[kslot] = bp;
+  D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], DIM == 3 ? vbar[2] : 0.0f, fmaxf(0.0f, sa));
+}
+
+template <int DIM>
+__device__ __forceinline__ double det_F(const double *H) {
+  if (DIM == 2) return (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
+  return (1.0 + H[0]) * ((1.0 + H[4]) * (1.0 + H[8]) - H[5] * H[7]) - H[1] * (H[3] * (1.0 + H[8]) - H[5] * H[6]) +
+         H[2] * (H[3] * H[7] - (1.0 + H[4]) * H[6]);
+}
+
+// The same from the stored state (solid index a, any free particle).
+template <int DIM>
+__device__ void hand_over(const Dev &D, int a) {
+  const int NS = D.ns;
+  if (a >= NS) return;
+  const ScenePar &P = D.par[D.s_scene[a]];
+  if (a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  double H[9];
+  for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
+  float vbar[3] = {0.0f, 0.0f, 0.0f}, abar[3] = {0.0f, 0.0f, 0.0f};
+  for (int k = 0; k < DIM; ++k) {
+    vbar[k] = D.s_vbar[k * NS + a];
+    abar[k] = D.s_abar[k * NS + a];
+  }
+  hand_over_values<DIM>(D, P, a, det_F<DIM>(H), vbar, abar);
 }
 
 // The same sub-steps for 2D scenes whose free solid fits the block with at
@@ -1779,7 +1827,6 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_so
       abar[k] = (float)((double)dv[p][k] * inv_dt);
       D.s_vbar[k * NS + a] = vbar[k];
       D.s_abar[k * NS + a] = abar[k];
-      sa += (abar[k] - P.g[k]) * D.s_n[k * NS + a];
       bad |= !isfinite(vbar[k]) || !isfinite(abar[k]);
     }
     if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
@@ -1799,9 +1846,6 @@ template <int DIM>
 __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
   __shared__ float shm[16];
   __shared__ unsigned long long shc[3][16];
-  // this step's rebuild kernels are done; k_step_close sets the flag again
-  // for the scenes that close an advection step
-  if (blockIdx.x == 0 && threadIdx.x == 0) *D.rebuild_any = 0;
   if ((int)blockIdx.x < fluid_blocks) {
     // kReduceItems particles per thread; one reduction and atomic per scene
     // present in the block (scenes own contiguous ranges)
@@ -1838,29 +1882,7 @@ __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
     }
     return;
   }
-  const int NS = D.ns;
-  int a = (blockIdx.x - fluid_blocks) * blockDim.x + threadIdx.x;
-  if (a >= NS) return;
-  const ScenePar &P = D.par[D.s_scene[a]];
-  if (a - P.s_begin >= P.s_count - P.s_nclamp) return;
-  int kslot = D.s_bslot[a];
-  if (kslot < 0) return;
-  double H[9];
-  for (int k = 0; k < DIM * DIM; ++k) H[k] = D.s_H[k * NS + a];
-  double J;
-  if (DIM == 2) J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];
-  else
-    J = (1.0 + H[0]) * ((1.0 + H[4]) * (1.0 + H[8]) - H[5] * H[7]) - H[1] * (H[3] * (1.0 + H[8]) - H[5] * H[6]) +
-        H[2] * (H[3] * H[7] - (1.0 + H[4]) * H[6]);
-  float vbar[3] = {0.0f, 0.0f, 0.0f}, sa = 0.0f;
-  for (int k = 0; k < DIM; ++k) {
-    vbar[k] = D.s_vbar[k * NS + a];
-    sa += (D.s_abar[k * NS + a] - P.g[k]) * D.s_n[k * NS + a];
-  }
-  float4 bp = D.b_pos[kslot];
-  bp.w = (float)(P.Vs * J);
-  D.b_pos[kslot] = bp;
-  D.b_vbar[kslot] = make_float4(vbar[0], vbar[1], vbar[2], fmaxf(0.0f, sa));
+  hand_over<DIM>(D, (blockIdx.x - fluid_blocks) * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------------ surrogate
@@ -2295,9 +2317,9 @@ __global__ void k_reduce_final(Dev D, int nblocks, double *out) {
 }
 
 __global__ void k_set_rebuild(Dev D, int s) {
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && !D.st[s].need_rebuild) {
     D.st[s].need_rebuild = 1;
-    *D.rebuild_any = 1;
+    atomicAdd(D.rebuild_count, 1);
   }
 }
 

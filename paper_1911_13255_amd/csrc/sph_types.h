@@ -136,9 +136,9 @@ struct Dev {
   float4 *s_nbr;                   // [k * ns + a] = (V_b grad_a W_ab, b as int bits in w; in 2D z holds b - scene start)
   int nbr_rows;                    // rows of s_nbr: maxn plus the null rows that pad every particle's list
   int nbr_bytes;                   // bytes of s_nbr (0 when it would not fit a 31-bit buffer range)
-  // 0 only when no scene rebuilds at the next step start (the rebuild
-  // kernels then exit after one load); 1 when some scene may
-  int *rebuild_any;
+  // number of scenes whose need_rebuild flag is set (every writer of a flag
+  // adjusts it); the rebuild kernels exit after this one load when it is 0
+  int *rebuild_count;
   // staging and reductions
   double *stage;
   double *red;
