@@ -45,7 +45,7 @@ struct Plan {
   int max_count = 0;
   int capf = 0, capb = 0, lw = 1;  // pair-list capacities per particle and chunk width
   std::vector<ScenePar> par;
-  std::vector<int> rank_to_lin, cell_scene, bs_scene;
+  std::vector<int> rank_to_cell, cell_scene, bs_scene;
   LaunchCfg cfg{256, 256, 256};
 };
 
@@ -206,7 +206,7 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
     }
     std::sort(codes.begin(), codes.end());
     for (int r = 0; r < nc; ++r) {
-      P.rank_to_lin.push_back(codes[r].second);
+      P.rank_to_cell.push_back(p.cell_begin + codes[r].second);
       P.cell_scene.push_back(s);
     }
     for (int q = 0; q < p.b_count; ++q) P.bs_scene.push_back(s);
@@ -342,7 +342,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.fs_m, nf);
   take(D.fc_count, nc);
   take(D.bc_count, nc);
-  take(D.rank_to_lin, nc);
+  take(D.rank_to_cell, nc);
   take(D.cell_scene, nc);
   take(D.fc_se, nc);
   take(D.bc_se, nc);
@@ -605,7 +605,7 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   HIPCHK_INIT(hipMemcpy(D.rebuild_count, &n_scenes, sizeof(int), hipMemcpyHostToDevice));
   if (P.ns) HIPCHK_INIT(hipMemsetAsync(D.s_cpl_cnt, 0, sizeof(int) * P.ns, st));
   if (P.ncell) {
-    HIPCHK_INIT(hipMemcpyAsync(D.rank_to_lin, P.rank_to_lin.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
+    HIPCHK_INIT(hipMemcpyAsync(D.rank_to_cell, P.rank_to_cell.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
     HIPCHK_INIT(hipMemcpyAsync(D.cell_scene, P.cell_scene.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
     HIPCHK_INIT(hipMemsetAsync(D.fc_count, 0, sizeof(int) * P.ncell, st));
     HIPCHK_INIT(hipMemsetAsync(D.bc_count, 0, sizeof(int) * P.ncell, st));

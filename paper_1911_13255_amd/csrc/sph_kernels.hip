@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(1024) k_cell_sum(Dev D) {
   }
   int lf = 0, lb = 0;
   for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-    int c = D.par[D.cell_scene[g]].cell_begin + D.rank_to_lin[g];
+    int c = D.rank_to_cell[g];
     lf += D.fc_count[c];
     lb += D.bc_count[c];
   }
@@ -591,61 +591,98 @@ __global__ void __launch_bounds__(1024) k_cell_prefix(Dev D, int ntiles) {
 
 // Each tile: scan of its cells (kCellTile / blockDim consecutive cells per
 // thread), [start, end) of every cell of a rebuilding scene; counts reset.
-__device__ __forceinline__ void apply_tile(const Dev &D, int g0, int g1, int2 base, int *sf, int *sb) {
-  const int t = threadIdx.x, T = blockDim.x;
-  const int per = kCellTile / T;
-  const int gs = g0 + t * per, ge = min(g1, gs + per);
+// LDS of one tile of the cell scan: the cells of the tile, then per cell its
+// fluid and boundary counts, turned into exclusive prefixes in place.
+struct TileLds {
+  int cell[kCellTile], pf[kCellTile], pb[kCellTile];
+  int wf[16], wb[16];
+};
+
+// Scan of one tile (at most kCellTile cells, 1024 threads): counts staged in
+// LDS by coalesced loads, per-thread sums of kCellTile / 1024 consecutive
+// cells, a block scan by wavefront shuffles, then [start, end) and the count
+// reset written cell by cell in coalesced order.
+__device__ __forceinline__ void apply_tile(const Dev &D, int g0, int g1, int2 base, TileLds &L) {
+  const int t = threadIdx.x, T = blockDim.x, lane = t & 63, w = t >> 6;
+  const int ng = g1 - g0, per = kCellTile / T;
+  for (int g = t; g < ng; g += T) {
+    const int c = D.rank_to_cell[g0 + g];
+    L.cell[g] = c;
+    L.pf[g] = D.fc_count[c];
+    L.pb[g] = D.bc_count[c];
+  }
+  __syncthreads();
+  const int gs = t * per, ge = min(ng, gs + per);
   int lf = 0, lb = 0;
   for (int g = gs; g < ge; ++g) {
-    int c = D.par[D.cell_scene[g]].cell_begin + D.rank_to_lin[g];
-    lf += D.fc_count[c];
-    lb += D.bc_count[c];
+    lf += L.pf[g];
+    lb += L.pb[g];
   }
-  sf[t] = lf;
-  sb[t] = lb;
-  __syncthreads();
-  for (int w = 1; w < T; w <<= 1) {
-    int af = t >= w ? sf[t - w] : 0, ab = t >= w ? sb[t - w] : 0;
-    __syncthreads();
-    sf[t] += af;
-    sb[t] += ab;
-    __syncthreads();
-  }
-  int pf = base.x + sf[t] - lf, pb = base.y + sb[t] - lb;
-  for (int g = gs; g < ge; ++g) {
-    int s = D.cell_scene[g];
-    const ScenePar &P = D.par[s];
-    const SceneState &S = D.st[s];
-    int c = P.cell_begin + D.rank_to_lin[g];
-    int cf = D.fc_count[c], cbn = D.bc_count[c];
-    if (S.need_rebuild) {
-      int f0 = P.f_begin + pf - S.base_f, b0 = P.b_begin + pb - S.base_b;
-      D.fc_se[c] = make_int2(f0, f0 + cf);
-      D.bc_se[c] = make_int2(b0, b0 + cbn);
-      D.fc_count[c] = 0;
-      D.bc_count[c] = 0;
+  // inclusive block scan of (lf, lb)
+  int xf = lf, xb = lb;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int yf = __shfl_up(xf, o), yb = __shfl_up(xb, o);
+    if (lane >= o) {
+      xf += yf;
+      xb += yb;
     }
+  }
+  if (lane == 63) {
+    L.wf[w] = xf;
+    L.wb[w] = xb;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int af = 0, ab = 0;
+    for (int k = 0; k < (T + 63) / 64; ++k) {
+      const int vf = L.wf[k], vb = L.wb[k];
+      L.wf[k] = af;
+      L.wb[k] = ab;
+      af += vf;
+      ab += vb;
+    }
+  }
+  __syncthreads();
+  int pf = base.x + L.wf[w] + xf - lf, pb = base.y + L.wb[w] + xb - lb;
+  for (int g = gs; g < ge; ++g) {
+    const int cf = L.pf[g], cb = L.pb[g];
+    L.pf[g] = pf;
+    L.pb[g] = pb;
     pf += cf;
-    pb += cbn;
+    pb += cb;
+  }
+  __syncthreads();
+  for (int g = t; g < ng; g += T) {
+    const int s = D.cell_scene[g0 + g];
+    const SceneState &S = D.st[s];
+    if (!S.need_rebuild) continue;
+    const ScenePar &P = D.par[s];
+    const int c = L.cell[g];
+    const int f0 = P.f_begin + L.pf[g] - S.base_f, b0 = P.b_begin + L.pb[g] - S.base_b;
+    D.fc_se[c] = make_int2(f0, f0 + D.fc_count[c]);
+    D.bc_se[c] = make_int2(b0, b0 + D.bc_count[c]);
+    D.fc_count[c] = 0;
+    D.bc_count[c] = 0;
   }
 }
 
 __global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
-  __shared__ int sf[1024], sb[1024];
+  __shared__ TileLds L;
   if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   const int g0 = blockIdx.x * kCellTile, g1 = min(D.ncell, g0 + kCellTile);
   if (!tile_rebuilds(D, g0, g1)) return;
-  apply_tile(D, g0, g1, D.cell_part[blockIdx.x], sf, sb);
+  apply_tile(D, g0, g1, D.cell_part[blockIdx.x], L);
 }
 
 // All cells in one tile: bookkeeping, scan and [start, end) in one block.
 __global__ void __launch_bounds__(1024) k_cell_one(Dev D) {
-  __shared__ int sf[1024], sb[1024];
+  __shared__ TileLds L;
   if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   if (!tile_rebuilds(D, 0, D.ncell)) return;
   if (threadIdx.x == 0) rebuild_bookkeeping(D);
   __syncthreads();
-  apply_tile(D, 0, D.ncell, make_int2(0, 0), sf, sb);
+  apply_tile(D, 0, D.ncell, make_int2(0, 0), L);
 }
 
 // Counting-sort scatter into cell slots in arrival order, with the sort key
@@ -846,23 +883,24 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
     };
     if (q == 0) psi = Vf * alpha;
     int cb = P.cell_begin;
-    visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh, int cid) {
+    // one neighbouring cell: its fluid candidates, then its boundary ones;
+    // a candidate's FP64 position is requested with its FP32 one
+    auto cell_body = [&](int nl, const float *sh, int cid, int2 se, int2 be) {
       const unsigned tag = (unsigned)cid << kNbrBits;
       // the same cell offset in FP64 (sh is an exact multiple of the FP32 cell size)
       double shd[3];
       for (int k = 0; k < 3; ++k) shd[k] = (double)(sh[k] / P.cs[k]) * P.csd[k];
-      int2 se = D.fc_se[cb + nl];
       for (int j0 = se.x; j0 < se.y; j0 += LPP) {
         int j = j0 + q;
         bool hit = false;
         if (j < se.y && j != i) {
           float4 pj = D.f_pos[j];
+          double4 qj = D.f_posd[j];
           // pair membership decided in FP32 exactly as in the force passes
           float rx = (pi.x - pj.x) - sh[0], ry = (pi.y - pj.y) - sh[1];
           float rz = DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f;
           float r2 = rx * rx + ry * ry + rz * rz;
           if (r2 < P.r2max_f) {
-            double4 qj = D.f_posd[j];
             double dx = (qi.x - qj.x) - shd[0], dy = (qi.y - qj.y) - shd[1];
             double dz = DIM == 3 ? (qi.z - qj.z) - shd[2] : 0.0;
             psi += Vf * W64(sqrt(dx * dx + dy * dy + dz * dz));
@@ -873,20 +911,20 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         int e = rank_hits(hit, lenf);
         if (hit && e < D.capf) lf[(size_t)(e / LPP) * lstride + e % LPP] = tag | (unsigned)j;
       }
-      int2 be = D.bc_se[cb + nl];
       for (int k0 = be.x; k0 < be.y; k0 += LPP) {
         int k = k0 + q;
         bool hit = false;
         if (k < be.y) {
           float4 pb = D.b_pos[k];
+          double4 qb = D.b_posd[k];
+          const float nw = D.b_nrm[k].w;
           float rx = (pi.x - pb.x) - sh[0], ry = (pi.y - pb.y) - sh[1];
           float rz = DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f;
           float r2 = rx * rx + ry * ry + rz * rz;
           if (r2 < P.r2max_f) {
-            double4 qb = D.b_posd[k];
             double dx = (qi.x - qb.x) - shd[0], dy = (qi.y - qb.y) - shd[1];
             double dz = DIM == 3 ? (qi.z - qb.z) - shd[2] : 0.0;
-            bool wall = D.b_nrm[k].w > 0.0f;
+            bool wall = nw > 0.0f;
             psi += (wall ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy + dz * dz));
             if (wall) {
               nfw++;
@@ -904,7 +942,38 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         int e = rank_hits(hit, lenb);
         if (hit && e < D.capb) lb[(size_t)(e / LPP) * lstride + e % LPP] = tag | (unsigned)k;
       }
-    });
+    };
+    if constexpr (DIM == 2) {
+      // the 3 x 3 cells' ranges are requested together, then the cells are
+      // walked in the same order as visit_cells (so the rows are the same)
+      int c[3];
+      decode_cell(P, D.f_lin[i], c);
+      int nlv[9];
+      int2 sev[9], bev[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        int n0 = c[0] + k % 3 - 1, n1 = c[1] + k / 3 - 1;
+        bool ok = true;
+        if (P.periodic[0]) n0 = wrapi(n0, P.ncell[0]);
+        else ok &= n0 >= 0 && n0 < P.ncell[0];
+        if (P.periodic[1]) n1 = wrapi(n1, P.ncell[1]);
+        else ok &= n1 >= 0 && n1 < P.ncell[1];
+        nlv[k] = ok ? n0 + P.ncell[0] * n1 : -1;
+        const int2 fr = D.fc_se[cb + (ok ? nlv[k] : 0)], br = D.bc_se[cb + (ok ? nlv[k] : 0)];
+        sev[k] = ok ? fr : make_int2(0, 0);
+        bev[k] = ok ? br : make_int2(0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        if (nlv[k] < 0) continue;
+        const float sh[3] = {(float)(k % 3 - 1) * P.cs[0], (float)(k / 3 - 1) * P.cs[1], 0.0f};
+        cell_body(nlv[k], sh, k + 9, sev[k], bev[k]);
+      }
+    } else {
+      visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh, int cid) {
+        cell_body(nl, sh, cid, D.fc_se[cb + nl], D.bc_se[cb + nl]);
+      });
+    }
   }
   psi = group_sum<LPP>(psi);
   nff = group_sum<LPP>(nff);

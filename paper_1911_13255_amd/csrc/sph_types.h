@@ -97,7 +97,8 @@ struct Dev {
   float *fs_drho, *fs_m;
   // cells
   int ncell;
-  int *fc_count, *bc_count, *rank_to_lin, *cell_scene;
+  int *fc_count, *bc_count, *cell_scene;
+  int *rank_to_cell;  // cell of each Morton rank (the scene's cell_begin + its linear index)
   int2 *cell_part;  // per-tile sums and then exclusive prefixes of the cell scan
   int2 *fc_se, *bc_se;  // [start, end) of each cell, indexed by scene-local linear index + cell_begin
   // walls (static)
