@@ -31,6 +31,9 @@ HBM_PEAK_GBS = 8000.0
 # x 2 flops (FMA) x 2.4 GHz (the packed-FP32 figure of 157.3 TFLOP/s is not
 # reachable by code built without packed FP32 instructions).
 ALU_PEAK_TFLOPS = 78.6
+# FP64 vector peak (the same lane rate as FP32 without packed instructions)
+FP64_PEAK_TFLOPS = 78.6
+NUM_CUS = 256
 # Algorithmic cost per unit of work:
 #  fluid force pass: own state read once and written once (144 B per fluid
 #  particle: reads position 16, mid-point snapshot 16, FP64 offset 32, row
@@ -261,7 +264,14 @@ def main():
     tflops = alg_flops / dur / 1e12
     hbm_frac = gbs / HBM_PEAK_GBS
     alu_frac = tflops / ALU_PEAK_TFLOPS
-    if alu_frac >= hbm_frac:
+    if dominant == "k_solid_reg":
+        # FP64 arithmetic of one workgroup per scene (LDS gathers, table loads
+        # and FP64 FMAs bound it together): the FP64 vector peak, with the
+        # fraction of the CUs the launch occupies beside it
+        roof = dict(bound="alu", achieved=tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=tflops / FP64_PEAK_TFLOPS, cus_used=len(scs),
+                    frac_of_cus_used=tflops / (FP64_PEAK_TFLOPS * len(scs) / NUM_CUS))
+    elif alu_frac >= hbm_frac:
         roof = dict(bound="alu", achieved=tflops, peak=ALU_PEAK_TFLOPS, unit="TFLOP/s", frac=alu_frac)
     else:
         roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm_frac)

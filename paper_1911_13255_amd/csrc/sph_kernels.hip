@@ -883,69 +883,62 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
     };
     if (q == 0) psi = Vf * alpha;
     int cb = P.cell_begin;
-    // one neighbouring cell: its fluid candidates, then its boundary ones;
-    // a candidate's FP64 position is requested with its FP32 one
-    auto cell_body = [&](int nl, const float *sh, int cid, int2 se, int2 be) {
-      const unsigned tag = (unsigned)cid << kNbrBits;
-      // the same cell offset in FP64 (sh is an exact multiple of the FP32 cell size)
-      double shd[3];
-      for (int k = 0; k < 3; ++k) shd[k] = (double)(sh[k] / P.cs[k]) * P.csd[k];
-      for (int j0 = se.x; j0 < se.y; j0 += LPP) {
-        int j = j0 + q;
-        bool hit = false;
-        if (j < se.y && j != i) {
-          float4 pj = D.f_pos[j];
-          double4 qj = D.f_posd[j];
-          // pair membership decided in FP32 exactly as in the force passes
-          float rx = (pi.x - pj.x) - sh[0], ry = (pi.y - pj.y) - sh[1];
-          float rz = DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f;
-          float r2 = rx * rx + ry * ry + rz * rz;
-          if (r2 < P.r2max_f) {
-            double dx = (qi.x - qj.x) - shd[0], dy = (qi.y - qj.y) - shd[1];
-            double dz = DIM == 3 ? (qi.z - qj.z) - shd[2] : 0.0;
-            psi += Vf * W64(sqrt(dx * dx + dy * dy + dz * dz));
-            nff++;
-            hit = true;
-          }
+    // One candidate of each lane of the group (all lanes take part: the
+    // matches are ranked by a ballot in candidate order).  sh / shd: the
+    // neighbour cell's offset in FP32 and FP64; tag: its cell id in the entry.
+    auto fluid_candidate = [&](bool valid, int j, float4 pj, double4 qj, const float *sh, const double *shd,
+                               unsigned tag) {
+      bool hit = false;
+      if (valid) {
+        // pair membership decided in FP32 exactly as in the force passes
+        float rx = (pi.x - pj.x) - sh[0], ry = (pi.y - pj.y) - sh[1];
+        float rz = DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f;
+        float r2 = rx * rx + ry * ry + rz * rz;
+        if (r2 < P.r2max_f) {
+          double dx = (qi.x - qj.x) - shd[0], dy = (qi.y - qj.y) - shd[1];
+          double dz = DIM == 3 ? (qi.z - qj.z) - shd[2] : 0.0;
+          psi += Vf * W64(sqrt(dx * dx + dy * dy + dz * dz));
+          nff++;
+          hit = true;
         }
-        int e = rank_hits(hit, lenf);
-        if (hit && e < D.capf) lf[(size_t)(e / LPP) * lstride + e % LPP] = tag | (unsigned)j;
       }
-      for (int k0 = be.x; k0 < be.y; k0 += LPP) {
-        int k = k0 + q;
-        bool hit = false;
-        if (k < be.y) {
-          float4 pb = D.b_pos[k];
-          double4 qb = D.b_posd[k];
-          const float nw = D.b_nrm[k].w;
-          float rx = (pi.x - pb.x) - sh[0], ry = (pi.y - pb.y) - sh[1];
-          float rz = DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f;
-          float r2 = rx * rx + ry * ry + rz * rz;
-          if (r2 < P.r2max_f) {
-            double dx = (qi.x - qb.x) - shd[0], dy = (qi.y - qb.y) - shd[1];
-            double dz = DIM == 3 ? (qi.z - qb.z) - shd[2] : 0.0;
-            bool wall = nw > 0.0f;
-            psi += (wall ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy + dz * dz));
-            if (wall) {
-              nfw++;
-            } else {
-              nfs++;
-              // the transposed entry for the solid particle's coupling list,
-              // with the cell offset seen from its side (26 - cid)
-              const int a = D.b_solid[k];
-              const int e = atomicAdd(&D.s_cpl_cnt[a], 1);
-              if (e < D.capf) D.s_cpl[(size_t)e * D.ns + a] = ((unsigned)(26 - cid) << kNbrBits) | (unsigned)i;
-            }
-            hit = true;
+      int e = rank_hits(hit, lenf);
+      if (hit && e < D.capf) lf[(size_t)(e / LPP) * lstride + e % LPP] = tag | (unsigned)j;
+    };
+    auto boundary_candidate = [&](bool valid, int k, float4 pb, double4 qb, float nw, const float *sh,
+                                  const double *shd, unsigned tag, int cid) {
+      bool hit = false;
+      if (valid) {
+        float rx = (pi.x - pb.x) - sh[0], ry = (pi.y - pb.y) - sh[1];
+        float rz = DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f;
+        float r2 = rx * rx + ry * ry + rz * rz;
+        if (r2 < P.r2max_f) {
+          double dx = (qi.x - qb.x) - shd[0], dy = (qi.y - qb.y) - shd[1];
+          double dz = DIM == 3 ? (qi.z - qb.z) - shd[2] : 0.0;
+          bool wall = nw > 0.0f;
+          psi += (wall ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy + dz * dz));
+          if (wall) {
+            nfw++;
+          } else {
+            nfs++;
+            // the transposed entry for the solid particle's coupling list,
+            // with the cell offset seen from its side (26 - cid)
+            const int a = D.b_solid[k];
+            const int e = atomicAdd(&D.s_cpl_cnt[a], 1);
+            if (e < D.capf) D.s_cpl[(size_t)e * D.ns + a] = ((unsigned)(26 - cid) << kNbrBits) | (unsigned)i;
           }
+          hit = true;
         }
-        int e = rank_hits(hit, lenb);
-        if (hit && e < D.capb) lb[(size_t)(e / LPP) * lstride + e % LPP] = tag | (unsigned)k;
       }
+      int e = rank_hits(hit, lenb);
+      if (hit && e < D.capb) lb[(size_t)(e / LPP) * lstride + e % LPP] = tag | (unsigned)k;
     };
     if constexpr (DIM == 2) {
-      // the 3 x 3 cells' ranges are requested together, then the cells are
-      // walked in the same order as visit_cells (so the rows are the same)
+      // The 3 x 3 cells' ranges are requested together; their candidates are
+      // then taken in one enumeration (cell by cell in visit_cells' order,
+      // then by index, so the rows are the same as a cell-by-cell walk), the
+      // loads of kRounds rounds issued before any is used.
+      constexpr int kRounds = 2;
       int c[3];
       decode_cell(P, D.f_lin[i], c);
       int nlv[9];
@@ -963,15 +956,119 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         sev[k] = ok ? fr : make_int2(0, 0);
         bev[k] = ok ? br : make_int2(0, 0);
       }
+      int pf[10], pb[10];  // prefix counts of the candidates over the cells
+      pf[0] = pb[0] = 0;
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        if (nlv[k] < 0) continue;
-        const float sh[3] = {(float)(k % 3 - 1) * P.cs[0], (float)(k / 3 - 1) * P.cs[1], 0.0f};
-        cell_body(nlv[k], sh, k + 9, sev[k], bev[k]);
+        pf[k + 1] = pf[k] + (sev[k].y - sev[k].x);
+        pb[k + 1] = pb[k] + (bev[k].y - bev[k].x);
+      }
+      // cell k of enumeration position e and the index offset of its range
+      // (a select chain over constant indices: the arrays stay in registers)
+      auto locate = [](int e, const int *pre, const int2 *rng, int &k, int &off) {
+        k = 0;
+        off = rng[0].x;
+#pragma unroll
+        for (int m = 1; m < 9; ++m)
+          if (e >= pre[m]) {
+            k = m;
+            off = rng[m].x - pre[m];
+          }
+      };
+      auto offsets = [&](int k, float *sh, double *shd) {
+        const int dx = k % 3 - 1, dy = k / 3 - 1;
+        sh[0] = (float)dx * P.cs[0];
+        sh[1] = (float)dy * P.cs[1];
+        sh[2] = 0.0f;
+        shd[0] = (double)dx * P.csd[0];
+        shd[1] = (double)dy * P.csd[1];
+        shd[2] = 0.0;
+      };
+      for (int e0 = 0; e0 < pf[9]; e0 += kRounds * LPP) {
+        float4 pj[kRounds];
+        double4 qj[kRounds];
+        int jr[kRounds], kr[kRounds];
+        bool vr[kRounds];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+          const int e = e0 + r * LPP + q;
+          int off;
+          locate(e, pf, sev, kr[r], off);
+          jr[r] = off + e;
+          vr[r] = e < pf[9] && jr[r] != i;
+          if (vr[r]) {
+            pj[r] = D.f_pos[jr[r]];
+            qj[r] = D.f_posd[jr[r]];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+          float sh[3];
+          double shd[3];
+          offsets(kr[r], sh, shd);
+          fluid_candidate(vr[r], jr[r], pj[r], qj[r], sh, shd, (unsigned)(kr[r] + 9) << kNbrBits);
+        }
+      }
+      for (int e0 = 0; e0 < pb[9]; e0 += kRounds * LPP) {
+        float4 pq[kRounds];
+        double4 qq[kRounds];
+        float nw[kRounds];
+        int kb[kRounds], kr[kRounds];
+        bool vr[kRounds];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+          const int e = e0 + r * LPP + q;
+          int off;
+          locate(e, pb, bev, kr[r], off);
+          kb[r] = off + e;
+          vr[r] = e < pb[9];
+          if (vr[r]) {
+            pq[r] = D.b_pos[kb[r]];
+            qq[r] = D.b_posd[kb[r]];
+            nw[r] = D.b_nrm[kb[r]].w;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+          float sh[3];
+          double shd[3];
+          offsets(kr[r], sh, shd);
+          boundary_candidate(vr[r], kb[r], pq[r], qq[r], nw[r], sh, shd, (unsigned)(kr[r] + 9) << kNbrBits,
+                             kr[r] + 9);
+        }
       }
     } else {
       visit_cells<DIM>(P, D.f_lin[i], [&](int nl, const float *sh, int cid) {
-        cell_body(nl, sh, cid, D.fc_se[cb + nl], D.bc_se[cb + nl]);
+        const unsigned tag = (unsigned)cid << kNbrBits;
+        // the same cell offset in FP64 (sh is an exact multiple of the FP32 cell size)
+        double shd[3];
+        for (int k = 0; k < 3; ++k) shd[k] = (double)(sh[k] / P.cs[k]) * P.csd[k];
+        const int2 se = D.fc_se[cb + nl];
+        for (int j0 = se.x; j0 < se.y; j0 += LPP) {
+          const int j = j0 + q;
+          const bool valid = j < se.y && j != i;
+          float4 pj;
+          double4 qj;
+          if (valid) {
+            pj = D.f_pos[j];
+            qj = D.f_posd[j];
+          }
+          fluid_candidate(valid, j, pj, qj, sh, shd, tag);
+        }
+        const int2 be = D.bc_se[cb + nl];
+        for (int k0 = be.x; k0 < be.y; k0 += LPP) {
+          const int k = k0 + q;
+          const bool valid = k < be.y;
+          float4 pb;
+          double4 qb;
+          float nw = 0.0f;
+          if (valid) {
+            pb = D.b_pos[k];
+            qb = D.b_posd[k];
+            nw = D.b_nrm[k].w;
+          }
+          boundary_candidate(valid, k, pb, qb, nw, sh, shd, tag, cid);
+        }
       });
     }
   }
