@@ -178,9 +178,10 @@ int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out);
 /* Autotuner of the launch shapes (batched scenes, hipGraph replay): for
  * every candidate, lanes per fluid particle in {1, 2, 4, 8, 16} x threads
  * per block of the pair passes in {64, 128, 256} x serial_passes in {0, 1},
- * initialises the scenes in the caller's arena on the caller's stream,
- * advances `warmup` acoustic steps and times `steps` more with HIP events,
- * twice, keeping the faster repetition.
+ * twice: initialises the scenes in the caller's arena on the caller's
+ * stream, advances `warmup` acoustic steps and times `steps` more with HIP
+ * events; the faster repetition counts (a trial never runs the scenes past
+ * warmup + steps steps).
  * *best receives *opt with the fastest candidate's three fields; ms_per_step
  * (may be NULL) its time per step.  The arena must hold sph_arena_bytes for
  * *opt (the candidates do not change the size).  Synchronises; no context is

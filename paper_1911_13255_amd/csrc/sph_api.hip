@@ -232,9 +232,9 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
   // (and its reference table fits the 31-bit range of a buffer resource)
   const bool table_fits = (size_t)(P.maxn + kSolidBatch) * P.ns * sizeof(float4) < (size_t)INT_MAX;
   if (o.solid_lds != 1 && P.dim == 2 && max_free_scene > 0 && max_free_scene <= 2048 && table_fits) {
-    // block limits of the register-resident kernel: 1024, 640, 512 threads
-    int ppt = max_free_scene <= 1024 ? 1 : (max_free_scene <= 1280 ? 2 : 4);
-    int limit = ppt == 1 ? 1024 : (ppt == 2 ? 640 : 512);
+    // block limits of the register-resident kernel: 1024, 768, 512 threads
+    int ppt = max_free_scene <= 1024 ? 1 : (max_free_scene <= 1536 ? 2 : 4);
+    int limit = ppt == 1 ? 1024 : (ppt == 2 ? 768 : 512);
     P.cfg.solid_ppt = ppt;
     int need = (max_free_scene + ppt - 1) / ppt;
     int want = std::max(64, (need + 63) / 64 * 64);
@@ -988,22 +988,25 @@ int sph_autotune(const sph_scene *scenes, int n_scenes, const sph_options *opt, 
         o.lanes_per_particle = lpp;
         o.block_pair = bp;
         o.serial_passes = serial;
-        sph_ctx *ctx = nullptr;
-        rc = sph_init(scenes, n_scenes, &o, dev_arena, arena_bytes, stream, &ctx);
-        if (rc == SPH_OK) rc = sph_advance(ctx, warmup);
-        // two timed repetitions, the faster one counts (short runs are noisy)
+        // two timed repetitions, the faster one counts (short runs are
+        // noisy); each starts from a fresh context, so a trial never runs
+        // more than warmup + steps steps of the scenes
         float ms = 0.0f;
         for (int rep = 0; rep < 2 && rc == SPH_OK; ++rep) {
+          sph_ctx *ctx = nullptr;
           float m = 0.0f;
-          if (hipStreamSynchronize(st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) rc = SPH_E_HIP;
+          rc = sph_init(scenes, n_scenes, &o, dev_arena, arena_bytes, stream, &ctx);
+          if (rc == SPH_OK) rc = sph_advance(ctx, warmup);
+          if (rc == SPH_OK && (hipStreamSynchronize(st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess))
+            rc = SPH_E_HIP;
           if (rc == SPH_OK) rc = sph_advance(ctx, steps);
           if (rc == SPH_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                                hipEventElapsedTime(&m, e0, e1) != hipSuccess))
             rc = SPH_E_HIP;
+          if (rc == SPH_OK) rc = sph_sync(ctx);
+          if (ctx) sph_destroy(ctx);
           if (rc == SPH_OK) ms = rep == 0 ? m : std::min(ms, m);
         }
-        if (rc == SPH_OK) rc = sph_sync(ctx);
-        if (ctx) sph_destroy(ctx);
         if (rc != SPH_OK) break;
         double per = (double)ms / steps;
         if (best_ms < 0.0 || per < best_ms) {

@@ -1712,9 +1712,9 @@ __device__ void hand_over(const Dev &D, int a) {
 // reference neighbour table is read from (L2-resident) global memory inside
 // the sub-step loop.
 // Block limits keep the register budget: 1024 threads for one particle per
-// thread, 640 for two, 512 for four.
+// thread (4 waves per SIMD), 768 for two (3 waves per SIMD), 512 for four.
 template <int DIM, int PPT>
-__global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 640 : 512)) k_solid_reg(Dev D, int lds_n) {
+__global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_solid_reg(Dev D, int lds_n) {
   extern __shared__ __align__(16) double smem[];
   __shared__ float red[2][16];
   __shared__ int kap_sh;
