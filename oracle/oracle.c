@@ -39,6 +39,8 @@ typedef struct {
   double inflow_U0, inflow_ts, inflow_H, inflow_len;
   const double *x_fluid, *v_fluid, *x_wall, *nrm_wall, *x_solid, *v_solid;
   int riemann, density_reinit;
+  int material;    /* 0 Neo-Hookean, 1 linear elastic (Saint Venant-Kirchhoff) */
+  int single_step; /* 1: the solid step is the one step of fluid and solid (kappa = 1) */
 } ora_scene;
 
 typedef struct {
@@ -50,7 +52,7 @@ typedef struct {
   double lo[3], hi[3], L[3];
   int per[3];
   double hydroH, inU0, ints, inH, inlen;
-  int riemann, reinit;
+  int riemann, reinit, material, single;
   double psi0;
   /* fluid, n x 3 vectors */
   double *x, *v, *rho, *drho, *m, *a, *p, *xr;
@@ -224,6 +226,39 @@ double ora_nh_energy(int d, const double *F, double mu, double lam) {
   for (int i = 0; i < d; ++i) trE += 0.5 * (C[4 * i] - 1.0);
   double lj = log(mat_det(d, F));
   return mu * trE - mu * lj + 0.5 * lam * lj * lj;
+}
+
+/* ------------------------------------------ linear elastic (Kirchhoff) material
+ * Isotropic linear elasticity in the Green-Lagrange strain (Section 2.1):
+ *   E = (F^T F - I)/2,  S = lambda tr(E) I + 2 mu E,  P = F S,
+ * with strain energy W = lambda/2 tr(E)^2 + mu E:E.  Plane strain in 2D. */
+void ora_svk_stress(int d, const double *F, double mu, double lam, double *P) {
+  double Ft[9], C[9], E[9], S[9];
+  mat_transpose(d, F, Ft);
+  mat_mul(d, Ft, F, C);
+  memset(E, 0, sizeof E);
+  memset(S, 0, sizeof S);
+  double trE = 0.0;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) E[3 * i + j] = 0.5 * (C[3 * i + j] - (i == j ? 1.0 : 0.0));
+  for (int i = 0; i < d; ++i) trE += E[4 * i];
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) S[3 * i + j] = 2.0 * mu * E[3 * i + j] + (i == j ? lam * trE : 0.0);
+  mat_mul(d, F, S, P);
+}
+
+double ora_svk_energy(int d, const double *F, double mu, double lam) {
+  double Ft[9], C[9];
+  mat_transpose(d, F, Ft);
+  mat_mul(d, Ft, F, C);
+  double trE = 0.0, EE = 0.0;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      double e = 0.5 * (C[3 * i + j] - (i == j ? 1.0 : 0.0));
+      EE += e * e;
+      if (i == j) trE += e;
+    }
+  return 0.5 * lam * trE * trE + mu * EE;
 }
 
 /* ----------------------------------------------------- particle number density
@@ -487,6 +522,8 @@ ora_ctx *ora_create(const ora_scene *sc) {
   c->inlen = sc->inflow_len;
   c->riemann = sc->riemann;
   c->reinit = sc->density_reinit;
+  c->material = sc->material;
+  c->single = sc->single_step;
   c->psi0 = ora_psi0(d, sc->h_ratio);
 
   int nf = c->nf, nw = c->nw, ns = c->ns;
@@ -749,11 +786,16 @@ static double inflow_speed(const ora_ctx *c, double y, double t) {
   return 6.0 * Ub * y * (c->inH - y) / (c->inH * c->inH);
 }
 
+static double solid_dt(const ora_ctx *c);
+
 /* One fluid acoustic step with the position-based Verlet scheme (Section 3.3). */
 void ora_fluid_step(ora_ctx *c) {
   int d = c->d, nf = c->nf;
   /* Acoustic criterion (Section 3.2) with the scene's CFL number. */
   c->dt_ac = c->cfl_ac * c->hf / (c->c + vmax_fluid(c));
+  /* The contrast to the multiple time steps (Section 3.2): the solid step,
+   * when smaller, is the single step of both fluid and structure. */
+  if (c->single && c->ns > c->nc) c->dt_ac = fmin(c->dt_ac, solid_dt(c));
   double dt = c->dt_ac;
   /* first half: density and position to the mid-point */
   for (int i = 0; i < nf; ++i) {
@@ -894,24 +936,31 @@ void ora_couple(ora_ctx *c) {
 
 /* ------------------------------------------------------------ O9 solid sub-steps */
 
-/* kappa solid steps with the position-based Verlet scheme (Section 3.3), the
- * fluid force held constant; then the time averages of Section 3.2. */
-void ora_solid_substeps(ora_ctx *c) {
-  int d = c->d, ns = c->ns;
-  /* Solid time step (Section 3.2) over free particles at the step start;
-   * the acceleration bound is dropped while |a|max = 0. */
+/* Solid time step (Section 3.2) over free particles at the step start;
+ * the acceleration bound is dropped while |a|max = 0. */
+static double solid_dt(const ora_ctx *c) {
+  int d = c->d;
   double vm = 0.0, am = 0.0;
-  for (int a = 0; a < ns; ++a)
+  for (int a = 0; a < c->ns; ++a)
     if (!c->clamp[a]) {
       vm = fmax(vm, norm(d, c->vs + 3 * a));
       am = fmax(am, norm(d, c->as + 3 * a));
     }
   double dts = c->cfl_s * c->hs / (c->cs + vm);
   if (am > 0.0) dts = fmin(dts, c->cfl_s * sqrt(c->hs / am));
+  return dts;
+}
+
+/* kappa solid steps with the position-based Verlet scheme (Section 3.3), the
+ * fluid force held constant; then the time averages of Section 3.2. */
+void ora_solid_substeps(ora_ctx *c) {
+  int d = c->d, ns = c->ns;
+  double dts = solid_dt(c);
   c->dt_s = dts;
   /* Reading: kappa = floor(dt_ac / dt_s) + 1 equal sub-steps of dt_ac / kappa,
-   * so that they sum to dt_ac exactly. */
-  c->kappa = (int)floor(c->dt_ac / dts) + 1;
+   * so that they sum to dt_ac exactly.  With one shared step (the contrast of
+   * Section 3.2) dt_ac <= dt_s already and the solid takes one step. */
+  c->kappa = c->single ? 1 : (int)floor(c->dt_ac / dts) + 1;
   double del = c->dt_ac / c->kappa;
   double *u0 = zalloc(3 * (size_t)ns), *v0 = zalloc(3 * (size_t)ns);
   memcpy(u0, c->u, sizeof(double) * 3 * (size_t)ns);
@@ -927,7 +976,8 @@ void ora_solid_substeps(ora_ctx *c) {
 #pragma omp parallel for schedule(static)
     for (int a = 0; a < ns; ++a) {
       double P[9];
-      ora_nh_stress(d, c->F + 9 * a, c->mu, c->lam, P);
+      if (c->material == 1) ora_svk_stress(d, c->F + 9 * a, c->mu, c->lam, P);
+      else ora_nh_stress(d, c->F + 9 * a, c->mu, c->lam, P);
       mat_mul(d, P, c->B + 9 * a, PB + 9 * a);
     }
     /* Momentum (Section 2.2, corrected total-Lagrangian form at h_S):
@@ -1132,7 +1182,8 @@ void ora_totals(const ora_ctx *c, double *out) {
       out[9 + k] += c->fF[3 * a + k];
     }
     out[7] += 0.5 * c->ms[a] * dot(d, c->vs + 3 * a, c->vs + 3 * a);
-    out[8] += c->V0[a] * ora_nh_energy(d, c->F + 9 * a, c->mu, c->lam);
+    out[8] += c->V0[a] * (c->material == 1 ? ora_svk_energy(d, c->F + 9 * a, c->mu, c->lam)
+                                           : ora_nh_energy(d, c->F + 9 * a, c->mu, c->lam));
   }
 }
 

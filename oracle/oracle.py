@@ -42,6 +42,7 @@ class OraScene(C.Structure):
         ("x_fluid", _dp), ("v_fluid", _dp), ("x_wall", _dp), ("nrm_wall", _dp),
         ("x_solid", _dp), ("v_solid", _dp),
         ("riemann", C.c_int), ("density_reinit", C.c_int),
+        ("material", C.c_int), ("single_step", C.c_int),
     ]
 
 
@@ -95,6 +96,9 @@ def lib():
         L.ora_nh_stress.argtypes = [C.c_int, _dp, C.c_double, C.c_double, _dp]
         L.ora_nh_energy.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
         L.ora_nh_energy.restype = C.c_double
+        L.ora_svk_stress.argtypes = [C.c_int, _dp, C.c_double, C.c_double, _dp]
+        L.ora_svk_energy.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
+        L.ora_svk_energy.restype = C.c_double
         for name in ("ora_brute_pairs", "ora_grid_pairs"):
             getattr(L, name).argtypes = [C.POINTER(OraScene), _dp, C.c_int, C.c_double,
                                          C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -132,6 +136,8 @@ def make_scene_struct(sc: dict, riemann: int = 1, density_reinit: int = 1):
         setattr(s, "nrm_wall" if k == "n_wall" else k, _ptr(a))
     s.riemann = int(riemann)
     s.density_reinit = int(density_reinit)
+    s.material = int(sc.get("material", 0))
+    s.single_step = int(sc.get("single_step", 0))
     return s, keep
 
 
@@ -294,6 +300,25 @@ def nh_energy(F, mu, lam):
     F3 = np.eye(3)
     F3[:d, :d] = F
     return lib().ora_nh_energy(d, _ptr(np.ascontiguousarray(F3)), float(mu), float(lam))
+
+
+def svk_stress(F, mu, lam):
+    """First Piola-Kirchhoff stress of the linear elastic (Kirchhoff) law."""
+    F = np.asarray(F, float)
+    d = F.shape[0]
+    F3 = np.eye(3)
+    F3[:d, :d] = F
+    P3 = np.zeros((3, 3))
+    lib().ora_svk_stress(d, _ptr(np.ascontiguousarray(F3)), float(mu), float(lam), _ptr(P3))
+    return P3[:d, :d]
+
+
+def svk_energy(F, mu, lam):
+    F = np.asarray(F, float)
+    d = F.shape[0]
+    F3 = np.eye(3)
+    F3[:d, :d] = F
+    return lib().ora_svk_energy(d, _ptr(np.ascontiguousarray(F3)), float(mu), float(lam))
 
 
 def neighbour_lists(sc: dict, x: np.ndarray, radius: float, brute: bool):

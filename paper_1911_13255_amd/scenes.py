@@ -75,7 +75,7 @@ def _base(dim: int) -> dict:
         hydro_H=0.0, inflow_U0=0.0, inflow_ts=0.0, inflow_H=0.0, inflow_len=0.0,
         x_fluid=np.zeros((0, dim)), v_fluid=None, x_wall=np.zeros((0, dim)),
         n_wall=np.zeros((0, dim)), x_solid=np.zeros((0, dim)), v_solid=None,
-        n_clamp=0, tip_index=-1, name="",
+        n_clamp=0, tip_index=-1, name="", material=0, single_step=0,
     )
 
 
