@@ -59,6 +59,12 @@ typedef struct {
   const double *x_fluid, *v_fluid;       /* (n_fluid, dim); v_fluid may be NULL */
   const double *x_wall, *nrm_wall;       /* (n_wall, dim): wall positions and unit normals into the fluid */
   const double *x_solid, *v_solid;       /* (n_solid, dim); v_solid may be NULL */
+  int material;    /* solid law (Section 2.1): 0 Neo-Hookean, 1 linear elastic in the
+                      Green-Lagrange strain, S = lambda tr(E) I + 2 mu E (Kirchhoff) */
+  int single_step; /* 0: multiple time steps, kappa = floor(dt_ac / dt_S) + 1 solid
+                      sub-steps per acoustic step (Section 3.2); 1: the contrast the
+                      same section names, dt_S (when smaller) as the one step of fluid
+                      and structure, kappa = 1 */
 } sph_scene;
 
 typedef struct {

@@ -107,6 +107,10 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
       err = "invalid material or resolution parameters";
       return false;
     }
+    if ((S.material != 0 && S.material != 1) || (S.single_step != 0 && S.single_step != 1)) {
+      err = "material must be 0 or 1 and single_step 0 or 1";
+      return false;
+    }
     ScenePar p;
     std::memset(&p, 0, sizeof p);
     double hf = S.h_ratio * S.dp_f, hs = S.h_ratio * S.dp_s;
@@ -198,6 +202,8 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
     p.in_len = (float)S.inflow_len;
     p.riemann = o.riemann ? 1 : 0;
     p.reinit = o.density_reinit;
+    p.material = S.material;
+    p.single_step = S.single_step;
     // Morton order of the scene's cells
     std::vector<std::pair<uint64_t, int>> codes(nc);
     for (int lin = 0; lin < nc; ++lin) {
@@ -579,6 +585,8 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   }
   D.capf = P.capf;
   D.fluid_prep = P.nf >= 100000 ? 1 : 0;
+  D.any_single = 0;
+  for (int s = 0; s < n_scenes; ++s) D.any_single |= P.par[s].single_step;
   D.capb = P.capb;
   D.lw = P.lw;
   ctx->stage_doubles = 9 * (size_t)std::max(P.max_count, 64) + 64;
@@ -768,7 +776,8 @@ int sph_write(sph_ctx *ctx, int field, int scene, const double *host) {
   HIPCHK(hipMemcpyAsync(ctx->D.stage, host, sizeof(double) * w * (size_t)n, hipMemcpyHostToDevice, ctx->stream));
   launch_write(ctx->D, scene, field, n, ctx->D.stage, ctx->stream);
   if (field != SPH_F_RHO && field != SPH_F_DRHO) launch_set_rebuild(ctx->D, scene, ctx->stream);
-  if (field == SPH_F_V) launch_refresh_vmax(ctx->D, ctx->stream);
+  if (field == SPH_F_V || (ctx->D.any_single && (field == SPH_S_V || field == SPH_S_A)))
+    launch_refresh_vmax(ctx->D, ctx->stream);
   int rc = check_launch(ctx, "sph_write");
   if (rc != SPH_OK) return rc;
   HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -410,8 +410,17 @@ __global__ void k_solid_B(Dev D) {
   }
 }
 
+// Solid time step (Section 3.2): dt_S = cfl_s min(h_S / (c_S + |v|max),
+// sqrt(h_S / |a|max)), the acceleration bound dropped while |a|max = 0.
+__device__ __forceinline__ double solid_dt(const ScenePar &P, float vmax, float amax) {
+  double dts = (double)P.cfl_s * (double)P.hs / ((double)P.c_s + (double)vmax);
+  if (amax > 0.0f) dts = fmin(dts, (double)P.cfl_s * sqrt((double)P.hs / (double)amax));
+  return dts;
+}
+
 // Max fluid speed of each scene and the acoustic time step that follows
-// (Section 3.2, acoustic criterion); one block per scene.
+// (Section 3.2, acoustic criterion); one block per scene.  A scene
+// that takes one shared step also takes the solid step of its free solid.
 __global__ void k_refresh_vmax(Dev D) {
   __shared__ float red[256];
   int s = blockIdx.x;
@@ -427,11 +436,36 @@ __global__ void k_refresh_vmax(Dev D) {
     if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
+  const float vmax = red[0];
+  double dt = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)vmax);
+  if (P.single_step && P.s_count > P.s_nclamp) {
+    // one shared step: the solid step of the current free-solid state
+    __syncthreads();
+    float sv = 0.0f, sa = 0.0f;
+    const int NS = D.ns;
+    for (int l = threadIdx.x; l < P.s_count - P.s_nclamp; l += blockDim.x) {
+      const int a = P.s_begin + l;
+      float v2 = 0.0f, a2 = 0.0f;
+      for (int k = 0; k < D.dim; ++k) {
+        float v = (float)D.s_v[k * NS + a], q = D.s_a[k * NS + a];
+        v2 += v * v;
+        a2 += q * q;
+      }
+      sv = fmaxf(sv, sqrtf(v2));
+      sa = fmaxf(sa, sqrtf(a2));
+    }
+    auto fmx = [](float x, float y) { return fmaxf(x, y); };
+    __shared__ float shv[16], sha[16];
+    sv = block_reduce(sv, fmx, shv);
+    sa = block_reduce(sa, fmx, sha);
+    dt = fmin(dt, solid_dt(P, sv, sa));
+  }
   if (threadIdx.x == 0) {
     SceneState &S = D.st[s];
-    S.vmax_prev = __float_as_uint(red[0]);
+    S.vmax_prev = __float_as_uint(vmax);
     S.vmax_next = 0u;
-    S.dt_ac = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)red[0]);
+    S.send_v = S.send_a = 0u;
+    S.dt_ac = dt;
   }
 }
 
@@ -1433,7 +1467,12 @@ __device__ void close_scene(const Dev &D, int s, unsigned vmax_bits, const unsig
   float vmax = __uint_as_float(vmax_bits);
   S.vmax_prev = vmax_bits;
   S.vmax_next = 0u;
-  S.dt_ac = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)vmax);
+  double dt = (double)P.cfl_ac * (double)P.hf / ((double)P.c + (double)vmax);
+  // one shared step: the solid step of the state the next step starts from
+  if (P.single_step && P.s_count > P.s_nclamp)
+    dt = fmin(dt, solid_dt(P, __uint_as_float(S.send_v), __uint_as_float(S.send_a)));
+  S.send_v = S.send_a = 0u;
+  S.dt_ac = dt;
 }
 
 __global__ void k_step_close(Dev D) {
@@ -1500,14 +1539,14 @@ __global__ void __launch_bounds__(256) k_solid_dt_reduce(Dev D) {
 // floor(dt_ac / dt_S) + 1 (bounded: a collapsed solid step is reported).
 __device__ __forceinline__ void solid_kappa(const ScenePar &P, SceneState &S, float vmax, float amax, double dt_ac,
                                             int &kap, double &dts) {
-  dts = (double)P.cfl_s * (double)P.hs / ((double)P.c_s + (double)vmax);
-  if (amax > 0.0f) dts = fmin(dts, (double)P.cfl_s * sqrt((double)P.hs / (double)amax));
+  dts = solid_dt(P, vmax, amax);
   double ratio = dt_ac / dts;
   if (!(ratio >= 0.0) || !(dt_ac > 0.0) || ratio > (double)(KAPPA_MAX - 1)) {
     kap = (ratio >= 0.0 && dt_ac > 0.0) ? KAPPA_MAX : 1;
     atomicOr(&S.err, (int)ERR_NAN_SOLID);
   } else {
-    kap = (int)floor(ratio) + 1;
+    // one shared step: dt_ac <= dt_S was chosen at the step start
+    kap = P.single_step ? 1 : (int)floor(ratio) + 1;
   }
 }
 
@@ -1539,7 +1578,7 @@ __device__ __forceinline__ void solid_first_half(const Dev &D, const ScenePar &P
     D.s_du[k * NS + a] += inc;
   }
   double J;
-  nh_PB<DIM, double>(H, B, (double)P.mu, (double)P.lam, PB, J);
+  solid_PB<DIM, double>(P.material, H, B, (double)P.mu, (double)P.lam, PB, J);
   if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
   for (int k = 0; k < DIM * DIM; ++k) D.s_PB[pb_at(D, a, k)] = PB[k];
 }
@@ -1818,7 +1857,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
       du[p][k] += (float)inc;
     }
     double J;
-    nh_PB<DIM, double>(H[p], Bd, (double)P.mu, (double)P.lam, PB, J);
+    solid_PB<DIM, double>(P.material, H[p], Bd, (double)P.mu, (double)P.lam, PB, J);
     bad_J |= !(J > 0.0);
 #pragma unroll
     for (int k = 0; k < D2; ++k) PBx[PI(la[p], k)] = PB[k];
@@ -1999,6 +2038,49 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   }
 }
 
+// Max |v| and |a| of the free solid at the end of a step, for scenes that
+// take one shared step (their next step size needs the solid step).  A wave
+// whose lanes share one scene reduces first; lanes of a wave that straddles
+// scenes each post their own maximum.
+template <int DIM>
+__device__ void single_step_maxima(const Dev &D, int a) {
+  const int NS = D.ns;
+  int s = -1;
+  float vm = 0.0f, am = 0.0f;
+  if (a < NS) {
+    s = D.s_scene[a];
+    const ScenePar &P = D.par[s];
+    if (!P.single_step || a - P.s_begin >= P.s_count - P.s_nclamp) {
+      s = -1;
+    } else {
+      float v2 = 0.0f, a2 = 0.0f;
+      for (int k = 0; k < DIM; ++k) {
+        float v = (float)D.s_v[k * NS + a], q = D.s_a[k * NS + a];
+        v2 += v * v;
+        a2 += q * q;
+      }
+      vm = sqrtf(v2);
+      am = sqrtf(a2);
+    }
+  }
+  const int s0 = __shfl(s, 0);
+  if (__all(s == s0)) {
+    if (s0 < 0) return;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      vm = fmaxf(vm, __shfl_xor(vm, o));
+      am = fmaxf(am, __shfl_xor(am, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomic_max_pos(&D.st[s0].send_v, vm);
+      atomic_max_pos(&D.st[s0].send_a, am);
+    }
+  } else if (s >= 0) {
+    atomic_max_pos(&D.st[s].send_v, vm);
+    atomic_max_pos(&D.st[s].send_a, am);
+  }
+}
+
 // End of an acoustic step over all particles, before k_step_close.  Fluid
 // blocks: max fluid speed for the next acoustic step and, after a rebuild,
 // the pair counts, folded into the scene's accumulators with one atomic per
@@ -2048,7 +2130,9 @@ __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
     }
     return;
   }
-  hand_over<DIM>(D, (blockIdx.x - fluid_blocks) * blockDim.x + threadIdx.x);
+  const int a = (blockIdx.x - fluid_blocks) * blockDim.x + threadIdx.x;
+  hand_over<DIM>(D, a);
+  if (D.any_single) single_step_maxima<DIM>(D, a);
 }
 
 // ------------------------------------------------------------------ surrogate
@@ -2171,7 +2255,7 @@ __global__ void __launch_bounds__(256) k_sur_rate(Dev D) {
       Hm[i * 2 + j] = h + 0.5 * dt * dF;
       D.sur_dF[(i * 2 + j) * NS + a] = dF;
     }
-  nh_PB<2, double>(Hm, B, (double)P.mu, (double)P.lam, PB, J);
+  solid_PB<2, double>(P.material, Hm, B, (double)P.mu, (double)P.lam, PB, J);
   for (int k = 0; k < 4; ++k) {
     D.sur_H[k * NS + a] = H[k];
     D.s_PB[pb_at(D, a, k)] = PB[k];
@@ -2446,12 +2530,20 @@ __global__ void __launch_bounds__(256) k_reduce_partial(Dev D, int s) {
       acc[7] += 0.5 * m * v * v;
       acc[9 + k] += D.s_fF[k * NS + a];
     }
-    // strain energy mu trE - mu lnJ + lambda/2 (lnJ)^2 in FP64
-    double trE = 0.0;
-    for (int i = 0; i < DIM; ++i) {
-      double cii = 2.0 * H[i * DIM + i];
-      for (int k = 0; k < DIM; ++k) cii += H[k * DIM + i] * H[k * DIM + i];
-      trE += 0.5 * cii;
+    // strain energy in FP64: Neo-Hookean mu trE - mu lnJ + lambda/2 (lnJ)^2,
+    // linear elastic lambda/2 (trE)^2 + mu E:E
+    double trE = 0.0, EE = 0.0;
+    for (int i = 0; i < DIM; ++i)
+      for (int j = 0; j < DIM; ++j) {
+        double e = H[i * DIM + j] + H[j * DIM + i];
+        for (int k = 0; k < DIM; ++k) e += H[k * DIM + i] * H[k * DIM + j];
+        e *= 0.5;
+        EE += e * e;
+        if (i == j) trE += e;
+      }
+    if (P.material == 1) {
+      acc[8] += (double)P.Vs * (0.5 * (double)P.lam * trE * trE + (double)P.mu * EE);
+      continue;
     }
     double J;
     if (DIM == 2) J = (1.0 + H[0]) * (1.0 + H[3]) - H[1] * H[2];

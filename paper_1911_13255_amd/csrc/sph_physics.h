@@ -134,10 +134,14 @@ __device__ __forceinline__ void coupling_force(const ScenePar &P, float m_i, flo
 
 // ---------------------------------------------------------------- solid
 
-// Neo-Hookean material (Section 2.1): S = dW/dE = mu (I - C^-1) + lambda ln J C^-1,
-// evaluated as S = C^-1 (mu (C - I) + lambda ln J I) with C - I = H + H^T + H^T H,
-// so that small strains keep their relative precision.  Returns P B = (I + H) S B
-// and J = det(I + H).  T is float or double.
+// Solid stress (Section 2.1) as P B, from H = F - I, with
+// C - I = H + H^T + H^T H and M = mu (C - I) + lambda q I:
+//   material 0, Neo-Hookean: S = dW/dE = mu (I - C^-1) + lambda ln J C^-1,
+//     evaluated as S = C^-1 M with q = ln J;
+//   material 1, linear elastic in the Green-Lagrange strain (Kirchhoff):
+//     S = lambda tr(E) I + 2 mu E = M with q = tr(E) = tr(C - I) / 2.
+// Both forms keep the relative precision of small strains.  Returns
+// P B = (I + H) S B and J = det(I + H).  T is float or double.
 template <typename T>
 __device__ __forceinline__ T log1p_t(T x);
 template <>
@@ -146,7 +150,7 @@ template <>
 __device__ __forceinline__ double log1p_t<double>(double x) { return log1p(x); }
 
 template <int DIM, typename T>
-__device__ __forceinline__ void nh_PB(const T *H, const T *B, T mu, T lam, T *PB, T &J) {
+__device__ __forceinline__ void solid_PB(int material, const T *H, const T *B, T mu, T lam, T *PB, T &J) {
   T CmI[9];
   for (int i = 0; i < DIM; ++i)
     for (int j = 0; j < DIM; ++j) {
@@ -165,15 +169,27 @@ __device__ __forceinline__ void nh_PB(const T *H, const T *B, T mu, T lam, T *PB
     Jm1 = tr + m2 + d3;
   }
   J = T(1) + Jm1;
-  T lnJ = log1p_t<T>(Jm1);
+  const bool nh = material != 1;
+  T q;
+  if (nh) {
+    q = log1p_t<T>(Jm1);
+  } else {
+    q = T(0);
+    for (int i = 0; i < DIM; ++i) q += CmI[i * DIM + i];
+    q *= T(0.5);
+  }
+  T M[9];
+  for (int i = 0; i < DIM; ++i)
+    for (int j = 0; j < DIM; ++j) M[i * DIM + j] = mu * CmI[i * DIM + j] + (i == j ? lam * q : T(0));
+  // C^-1 (Neo-Hookean) or the identity (linear elastic)
   T Ci[9];
   T inv = T(1) / (J * J);  // det C = J^2
   if (DIM == 2) {
     T c00 = T(1) + CmI[0], c11 = T(1) + CmI[3], c01 = CmI[1];
-    Ci[0] = c11 * inv;
-    Ci[1] = -c01 * inv;
-    Ci[2] = -c01 * inv;
-    Ci[3] = c00 * inv;
+    Ci[0] = nh ? c11 * inv : T(1);
+    Ci[1] = nh ? -c01 * inv : T(0);
+    Ci[2] = nh ? -c01 * inv : T(0);
+    Ci[3] = nh ? c00 * inv : T(1);
   } else {
     T C[9];
     for (int k = 0; k < 9; ++k) C[k] = CmI[k];
@@ -189,10 +205,9 @@ __device__ __forceinline__ void nh_PB(const T *H, const T *B, T mu, T lam, T *PB
     Ci[6] = (C[3] * C[7] - C[4] * C[6]) * inv;
     Ci[7] = (C[1] * C[6] - C[0] * C[7]) * inv;
     Ci[8] = (C[0] * C[4] - C[1] * C[3]) * inv;
+    if (!nh)
+      for (int k = 0; k < 9; ++k) Ci[k] = (k % 4 == 0) ? T(1) : T(0);
   }
-  T M[9];
-  for (int i = 0; i < DIM; ++i)
-    for (int j = 0; j < DIM; ++j) M[i * DIM + j] = mu * CmI[i * DIM + j] + (i == j ? lam * lnJ : T(0));
   T S[9];
   for (int i = 0; i < DIM; ++i)
     for (int j = 0; j < DIM; ++j) {

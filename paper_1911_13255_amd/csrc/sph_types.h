@@ -45,6 +45,8 @@ struct ScenePar {
   // inflow buffer
   float in_U0, in_ts, in_H, in_len;
   int riemann, reinit;
+  int material;     // 0 Neo-Hookean, 1 linear elastic (Kirchhoff)
+  int single_step;  // 1: the solid step is the one step of fluid and solid (kappa = 1)
 };
 
 struct SceneState {
@@ -52,6 +54,7 @@ struct SceneState {
   int kappa, need_rebuild, pad2, err;
   unsigned int vmax_prev, vmax_next;  // max fluid speed (float bits): step start / being reduced
   unsigned int smax_v, smax_a;        // max solid speed and acceleration (float bits) being reduced
+  unsigned int send_v, send_a;        // single step: the same at the step end, for the next step's size
   unsigned long long n_ff, n_fw, n_fs, n_ss;  // pairs within support at the last rebuild
   unsigned long long steps, rebuilds, substeps, interactions;
   unsigned long long acc_ff, acc_fw, acc_fs;  // pair counts being reduced after a rebuild
@@ -86,6 +89,7 @@ struct Dev {
   // lw lanes sharing a particle read lw consecutive entries.
   int capf, capb, lw;
   int fluid_prep;  // 1: k_fluid_prep forms the mid-point snapshot before the force pass
+  int any_single;  // 1: some scene takes one shared step (step-end solid maxima needed)
   unsigned *f_nbl;  // fluid neighbours (capf entries per particle)
   unsigned *f_bnl;  // boundary neighbours: walls and free solid (capb per particle)
   int2 *f_rowlen;  // used length of each particle's two rows

@@ -50,6 +50,7 @@ class SphScene(C.Structure):
         ("inflow_len", C.c_double),
         ("x_fluid", _dp), ("v_fluid", _dp), ("x_wall", _dp), ("nrm_wall", _dp),
         ("x_solid", _dp), ("v_solid", _dp),
+        ("material", C.c_int), ("single_step", C.c_int),
     ]
 
 
@@ -144,6 +145,8 @@ def scene_struct(sc: dict):
         s.periodic[k] = int(sc["periodic"][k])
     for k, a in keep.items():
         setattr(s, "nrm_wall" if k == "n_wall" else k, _ptr(a))
+    s.material = int(sc.get("material", 0))
+    s.single_step = int(sc.get("single_step", 0))
     return s, keep
 
 
