@@ -118,6 +118,65 @@ def surrogate_leg(workload, scene, seconds=30.0, threshold=1e-3, log=None):
     return res
 
 
+# The paper's flow-induced-vibration cases (Section 4.1, its Table 2) on the
+# channel geometry, with the linear elastic law its benchmark uses; bh = 0.2 D
+# is the plate thickness.
+PAPER_CASES = (
+    ("I", dict(dp_f=0.005, dp_ratio=1.0), 0, "dp_F = dp_S = bh/4, multiple time steps"),
+    ("II", dict(dp_f=0.0025, dp_ratio=1.0), 0, "dp_F = dp_S = bh/8, multiple time steps"),
+    ("III", dict(dp_f=0.01, dp_ratio=2.0), 0, "dp_F = 2 dp_S, dp_S = bh/4, multiple time steps"),
+    ("IV", dict(dp_f=0.01, dp_ratio=2.0), 1, "dp_F = 2 dp_S, dp_S = bh/4, one shared time step"),
+)
+# CPU wall-clock seconds the paper reports for these cases up to t* = 200
+# (Xeon L5520 2.27 GHz, shared-memory parallel), for the ratios only.
+PAPER_CASE_SECONDS = {"I": 1297.7, "II": 10926.7, "III": 249.5, "IV": 451.4}
+
+
+def paper_cases(steps=3000, warmup=300, log=None):
+    """The four cases on the GPU: simulated time advanced per wall second and
+    the speed-ups the paper draws from them (multi-resolution: III over I;
+    multiple time steps: III over IV), beside the paper's own CPU ratios."""
+    import torch
+    from paper_1911_13255_amd import scenes, sph
+
+    out = {}
+    for name, geo, single, desc in PAPER_CASES:
+        sc = scenes.plate_behind_cylinder(seed=1, **geo)
+        sc["material"] = 1
+        sc["single_step"] = single
+        sim = sph.Simulation([sc])
+        sim.advance(warmup)
+        sim.sync()
+        t0, c0 = sim.scalars()["t"], sim.counters()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(sim.stream)
+        sim.advance(steps)
+        ev1.record(sim.stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        sim.sync()
+        t1, c1 = sim.scalars()["t"], sim.counters()
+        secs = ms / 1e3
+        out[name] = dict(description=desc, dp_f=sc["dp_f"], dp_s=sc["dp_s"], single_step=single,
+                         n_fluid=len(sc["x_fluid"]), n_solid=len(sc["x_solid"]),
+                         kappa_mean=(c1["substeps"] - c0["substeps"]) / steps, steps=steps,
+                         ms_per_step=ms / steps, fsi_steps_per_s=steps / secs,
+                         interactions_per_s=(c1["interactions"] - c0["interactions"]) / secs,
+                         simulated_s_per_wall_s=(t1 - t0) / secs)
+        sim.close()
+        if log:
+            log(f"[bench] case {name}: {json.dumps(out[name])}")
+    rate = {k: v["simulated_s_per_wall_s"] for k, v in out.items()}
+    paper = PAPER_CASE_SECONDS
+    return dict(cases=out, material="linear elastic (Kirchhoff)", launch="library default shapes",
+                multi_resolution_speedup_III_over_I=rate["III"] / rate["I"],
+                multi_step_speedup_III_over_IV=rate["III"] / rate["IV"],
+                resolution_cost_II_over_I=rate["I"] / rate["II"],
+                paper_cpu_ratios=dict(III_over_I=paper["I"] / paper["III"], III_over_IV=paper["IV"] / paper["III"],
+                                      II_over_I=paper["II"] / paper["I"],
+                                      hardware="Xeon L5520 2.27 GHz CPU, wall-clock to t* = 200"))
+
+
 def cpu_baseline(scene, seconds=15.0):
     """The FP64 oracle on the host cores on a bounded prefix of the same run."""
     from oracle import oracle as ora
@@ -160,6 +219,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned sub-step leg (2D single-scene workloads only)")
     ap.add_argument("--surrogate-seconds", type=float, default=30.0)
+    ap.add_argument("--no-cases", action="store_true",
+                    help="skip the paper's four flow-induced-vibration cases (channel workload only)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="only run a plain FP32 device copy of this many MiB five times (the "
                          "reference for scaling HBM byte counters) and exit")
@@ -288,6 +349,10 @@ def main():
                             log=lambda m: print(m, file=sys.stderr, flush=True))
         print(f"[bench] surrogate {json.dumps(sur)}", file=sys.stderr, flush=True)
 
+    cases = None
+    if not args.no_cases and args.workload == "plate_behind_cylinder":
+        cases = paper_cases(log=lambda m: print(m, file=sys.stderr, flush=True))
+
     cpu = None
     if not args.no_cpu_baseline and len(scs) == 1:
         cpu = cpu_baseline(scs[0], args.cpu_seconds)
@@ -327,6 +392,7 @@ def main():
         "autotune_seconds": tune_s,
         "roofline": roof,
         "surrogate": sur,
+        "paper_cases": cases,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

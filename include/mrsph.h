@@ -263,9 +263,11 @@ enum {
 
 /* Average duration in milliseconds of `reps` back-to-back launches of one
  * kernel (or, for SPH_K_REBUILD, of the whole rebuild sequence) on the
- * context's stream, from two HIP events around them.  For profiling: the
- * launches advance the state like the entry point that owns the kernel.
- * Synchronises. */
+ * context's stream, from two HIP events around them.  The launches are
+ * captured into a HIP graph that is replayed twice, the first time untimed
+ * (on the null stream, and for the streamed solid form, which reads kappa
+ * back, they are launched directly).  For profiling: every launch advances
+ * the state like the entry point that owns the kernel.  Synchronises. */
 int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms);
 
 /* Wait for the stream; return the first latched device error, if any. */

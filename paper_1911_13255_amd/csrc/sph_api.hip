@@ -938,36 +938,58 @@ int sph_sync(sph_ctx *ctx) {
 int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms) {
   if (!ctx) return SPH_E_ORDER;
   if (reps <= 0 || !avg_ms || kernel < SPH_K_FLUID_FORCE || kernel > SPH_K_REBUILD) return SPH_E_ARG;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventRecord(e0, ctx->stream));
-  for (int r = 0; r < reps; ++r) {
+  hipStream_t st = ctx->stream;
+  auto enqueue_one = [&]() -> int {
     switch (kernel) {
-    case SPH_K_FLUID_FORCE: launch_fluid_force(ctx->D, ctx->cfg, ctx->stream); break;
-    case SPH_K_CONTINUITY: launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream); break;
-    case SPH_K_COUPLE: launch_couple(ctx->D, ctx->cfg, ctx->stream); break;
-    case SPH_K_SOLID:
-      // the streamed form synchronises once per repetition to read kappa
-      if (enqueue_solid(ctx) != SPH_OK) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return SPH_E_HIP;
-      }
-      break;
+    case SPH_K_FLUID_FORCE: launch_fluid_force(ctx->D, ctx->cfg, st); break;
+    case SPH_K_CONTINUITY: launch_fluid_continuity(ctx->D, ctx->cfg, st); break;
+    case SPH_K_COUPLE: launch_couple(ctx->D, ctx->cfg, st); break;
+    case SPH_K_SOLID: return enqueue_solid(ctx);
     case SPH_K_REBUILD:
-      for (int s = 0; s < ctx->n_scenes; ++s) launch_set_rebuild(ctx->D, s, ctx->stream);
-      launch_rebuild(ctx->D, ctx->cfg, ctx->stream);
+      for (int s = 0; s < ctx->n_scenes; ++s) launch_set_rebuild(ctx->D, s, st);
+      launch_rebuild(ctx->D, ctx->cfg, st);
       break;
     }
+    return SPH_OK;
+  };
+  // The repetitions are captured into a graph and replayed twice, the first
+  // replay untimed, so that the timed launches follow each other on the
+  // device instead of at the host's launch rate.  The streamed solid form
+  // reads kappa back once per repetition and is launched directly.
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  if (st && !(kernel == SPH_K_SOLID && ctx->cfg.solid_ppt == 0)) {
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      for (int r = 0; r < reps; ++r) (void)enqueue_one();
+      if (hipStreamEndCapture(st, &g) == hipSuccess && g &&
+          hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess)
+        ge = nullptr;
+    }
+    if (!ge) (void)hipGetLastError();
   }
-  HIPCHK(hipEventRecord(e1, ctx->stream));
-  int rc = check_launch(ctx, "sph_time_kernel");
-  HIPCHK(hipEventSynchronize(e1));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = SPH_OK;
   float ms = 0.0f;
-  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = SPH_E_HIP;
+  } else if (ge) {
+    if (hipGraphLaunch(ge, st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess ||
+        hipGraphLaunch(ge, st) != hipSuccess || hipEventRecord(e1, st) != hipSuccess)
+      rc = SPH_E_HIP;
+  } else if (hipEventRecord(e0, st) != hipSuccess) {
+    rc = SPH_E_HIP;
+  } else {
+    for (int r = 0; r < reps && rc == SPH_OK; ++r) rc = enqueue_one();
+    if (rc == SPH_OK && hipEventRecord(e1, st) != hipSuccess) rc = SPH_E_HIP;
+  }
+  if (rc == SPH_OK) rc = check_launch(ctx, "sph_time_kernel");
+  if (rc == SPH_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = SPH_E_HIP;
+  if (rc == SPH_E_HIP && !ctx->err[0]) std::snprintf(ctx->err, sizeof ctx->err, "sph_time_kernel: HIP call failed");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (ge) (void)hipGraphExecDestroy(ge);
+  if (g) (void)hipGraphDestroy(g);
   *avg_ms = (double)ms / reps;
   return rc;
 }

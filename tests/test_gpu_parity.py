@@ -417,6 +417,26 @@ def test_runs_are_bit_reproducible(gpu):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("solid_lds", [0, 1])
+def test_kernel_timing_replays_every_kernel(gpu, solid_lds):
+    # Graph-replayed (block-resident solid) and directly launched (streamed
+    # solid) timing: positive durations, a time per launch independent of the
+    # repetition count, and a state the repetitions leave valid.
+    sc = scenes.periodic_box_with_solid(dim=2, n=16, eta=0.5, amp=0.3)
+    note(f"kernel timing solid_lds {solid_lds}")
+    sim = sph.Simulation(sc, solid_lds=solid_lds)
+    sim.advance(5)
+    for k in (sph.K_FLUID_FORCE, sph.K_CONTINUITY, sph.K_COUPLE, sph.K_SOLID, sph.K_REBUILD):
+        t10, t40 = sim.time_kernel(k, 10), sim.time_kernel(k, 40)
+        note(f"  kernel {k}: {t10 * 1e3:.2f} us (10 reps), {t40 * 1e3:.2f} us (40 reps)")
+        assert 0.0 < t10 < 50.0 and 0.0 < t40 < 50.0
+        assert t40 < 3.0 * t10 and t10 < 3.0 * t40
+    sim.sync()
+    for f in (sph.F_V, sph.S_V, sph.S_F):
+        assert np.all(np.isfinite(sim.read(f)))
+    sim.close()
+
+
 # ------------------------------------------------------------------ failure handling
 
 def test_nan_state_is_reported(gpu):
