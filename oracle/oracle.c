@@ -41,6 +41,7 @@ typedef struct {
   int riemann, density_reinit;
   int material;    /* 0 Neo-Hookean, 1 linear elastic (Saint Venant-Kirchhoff) */
   int single_step; /* 1: the solid step is the one step of fluid and solid (kappa = 1) */
+  int velocity_verlet; /* test contrast: 1 velocity-based Verlet instead of position-based */
 } ora_scene;
 
 typedef struct {
@@ -52,7 +53,7 @@ typedef struct {
   double lo[3], hi[3], L[3];
   int per[3];
   double hydroH, inU0, ints, inH, inlen;
-  int riemann, reinit, material, single;
+  int riemann, reinit, material, single, vv;
   double psi0;
   /* fluid, n x 3 vectors */
   double *x, *v, *rho, *drho, *m, *a, *p, *xr;
@@ -524,6 +525,7 @@ ora_ctx *ora_create(const ora_scene *sc) {
   c->reinit = sc->density_reinit;
   c->material = sc->material;
   c->single = sc->single_step;
+  c->vv = sc->velocity_verlet;
   c->psi0 = ora_psi0(d, sc->h_ratio);
 
   int nf = c->nf, nw = c->nw, ns = c->ns;
@@ -788,28 +790,22 @@ static double inflow_speed(const ora_ctx *c, double y, double t) {
 
 static double solid_dt(const ora_ctx *c);
 
-/* One fluid acoustic step with the position-based Verlet scheme (Section 3.3). */
-void ora_fluid_step(ora_ctx *c) {
-  int d = c->d, nf = c->nf;
-  /* Acoustic criterion (Section 3.2) with the scene's CFL number. */
-  c->dt_ac = c->cfl_ac * c->hf / (c->c + vmax_fluid(c));
-  /* The contrast to the multiple time steps (Section 3.2): the solid step,
-   * when smaller, is the single step of both fluid and structure. */
-  if (c->single && c->ns > c->nc) c->dt_ac = fmin(c->dt_ac, solid_dt(c));
-  double dt = c->dt_ac;
-  /* first half: density and position to the mid-point */
-  for (int i = 0; i < nf; ++i) {
-    c->rho[i] += 0.5 * dt * c->drho[i];
-    for (int k = 0; k < d; ++k) c->x[3 * i + k] += 0.5 * dt * c->v[3 * i + k];
-  }
-  for (int i = 0; i < nf; ++i) {
+/* Pressure from the density and the snapshot the coupling on the solid reads
+ * (the state at which the fluid forces are evaluated). */
+static void fluid_snapshot(ora_ctx *c) {
+  for (int i = 0; i < c->nf; ++i) {
     c->p[i] = ora_eos(c->rho[i], c->rho0, c->c, c->gam);
     c->sn_rho[i] = c->rho[i];
     c->sn_p[i] = c->p[i];
     for (int k = 0; k < 3; ++k) c->sn_v[3 * i + k] = c->v[3 * i + k];
   }
-  /* Momentum equation at the mid-point (Section 3.1): Riemann pressure,
-   * viscous term, coupling forces from walls and solid, gravity. */
+}
+
+/* Momentum equation (Section 3.1) at the current density, pressure and
+ * velocity: Riemann pressure, viscous term, coupling forces from walls and
+ * solid, gravity. */
+static void fluid_accel(ora_ctx *c) {
+  int d = c->d, nf = c->nf;
 #pragma omp parallel for schedule(static)
   for (int i = 0; i < nf; ++i) {
     double acc[3] = {0.0, 0.0, 0.0};
@@ -839,12 +835,12 @@ void ora_fluid_step(ora_ctx *c) {
     /* reading: body force enters as m_i g */
     for (int q = 0; q < d; ++q) c->a[3 * i + q] = acc[q] + c->g[q];
   }
-  /* velocity: full step */
-  for (int i = 0; i < nf; ++i)
-    for (int k = 0; k < d; ++k) c->v[3 * i + k] += dt * c->a[3 * i + k];
-  /* Continuity (Section 3.1) with the new velocity at the mid-point density.
-   * Reading: walls and solid add rho_i sum_a V_a (v_i - vbar_a).grad_i W_ia. */
-  double *drho = zalloc(nf);
+}
+
+/* Continuity (Section 3.1) at the current density and velocity.
+ * Reading: walls and solid add rho_i sum_a V_a (v_i - vbar_a).grad_i W_ia. */
+static void fluid_drho(const ora_ctx *c, double *drho) {
+  int d = c->d, nf = c->nf;
 #pragma omp parallel for schedule(static)
   for (int i = 0; i < nf; ++i) {
     double s = 0.0;
@@ -881,17 +877,13 @@ void ora_fluid_step(ora_ctx *c) {
     }
     drho[i] = s;
   }
-  /* second half: position with the new velocity, density with the new rate */
-  for (int i = 0; i < nf; ++i) {
-    c->drho[i] = drho[i];
-    c->rho[i] += 0.5 * dt * drho[i];
-    for (int k = 0; k < d; ++k) c->x[3 * i + k] += 0.5 * dt * c->v[3 * i + k];
-  }
-  free(drho);
-  /* periodic wrap and inflow buffer (Section 4.1; reading: periodic channel
-   * whose first inflow_len of length is reset to the inflow profile) */
-  double tn = c->t + dt;
-  for (int i = 0; i < nf; ++i) {
+}
+
+/* periodic wrap and inflow buffer (Section 4.1; reading: periodic channel
+ * whose first inflow_len of length is reset to the inflow profile) */
+static void fluid_wrap_inflow(ora_ctx *c, double tn) {
+  int d = c->d;
+  for (int i = 0; i < c->nf; ++i) {
     for (int k = 0; k < d; ++k)
       if (c->per[k]) {
         double s = c->x[3 * i + k] - c->lo[k];
@@ -902,6 +894,64 @@ void ora_fluid_step(ora_ctx *c) {
       for (int k = 1; k < d; ++k) c->v[3 * i + k] = 0.0;
     }
   }
+}
+
+/* The velocity-based Verlet scheme that Section 3.3 contrasts with its own
+ * (test contrast only): half a step of velocity with the acceleration of the
+ * last evaluation, a full step of position and density, the forces and the
+ * density rate evaluated at the new state, another half step of velocity.
+ * The accelerations and rates start at zero before the first evaluation. */
+static void fluid_step_velocity_verlet(ora_ctx *c, double dt) {
+  int d = c->d, nf = c->nf;
+  for (int i = 0; i < nf; ++i) {
+    for (int k = 0; k < d; ++k) c->v[3 * i + k] += 0.5 * dt * c->a[3 * i + k];
+    c->rho[i] += dt * c->drho[i];
+    for (int k = 0; k < d; ++k) c->x[3 * i + k] += dt * c->v[3 * i + k];
+  }
+  fluid_snapshot(c);
+  fluid_accel(c);
+  fluid_drho(c, c->drho);
+  for (int i = 0; i < nf; ++i)
+    for (int k = 0; k < d; ++k) c->v[3 * i + k] += 0.5 * dt * c->a[3 * i + k];
+  fluid_wrap_inflow(c, c->t + dt);
+  c->interactions += 2 * (c->n_ff + c->n_fb);
+}
+
+/* One fluid acoustic step with the position-based Verlet scheme (Section 3.3). */
+void ora_fluid_step(ora_ctx *c) {
+  int d = c->d, nf = c->nf;
+  /* Acoustic criterion (Section 3.2) with the scene's CFL number. */
+  c->dt_ac = c->cfl_ac * c->hf / (c->c + vmax_fluid(c));
+  /* The contrast to the multiple time steps (Section 3.2): the solid step,
+   * when smaller, is the single step of both fluid and structure. */
+  if (c->single && c->ns > c->nc) c->dt_ac = fmin(c->dt_ac, solid_dt(c));
+  double dt = c->dt_ac;
+  if (c->vv) {
+    fluid_step_velocity_verlet(c, dt);
+    return;
+  }
+  /* first half: density and position to the mid-point */
+  for (int i = 0; i < nf; ++i) {
+    c->rho[i] += 0.5 * dt * c->drho[i];
+    for (int k = 0; k < d; ++k) c->x[3 * i + k] += 0.5 * dt * c->v[3 * i + k];
+  }
+  /* forces at the mid-point */
+  fluid_snapshot(c);
+  fluid_accel(c);
+  /* velocity: full step */
+  for (int i = 0; i < nf; ++i)
+    for (int k = 0; k < d; ++k) c->v[3 * i + k] += dt * c->a[3 * i + k];
+  /* continuity with the new velocity at the mid-point density */
+  double *drho = zalloc(nf);
+  fluid_drho(c, drho);
+  /* second half: position with the new velocity, density with the new rate */
+  for (int i = 0; i < nf; ++i) {
+    c->drho[i] = drho[i];
+    c->rho[i] += 0.5 * dt * drho[i];
+    for (int k = 0; k < d; ++k) c->x[3 * i + k] += 0.5 * dt * c->v[3 * i + k];
+  }
+  free(drho);
+  fluid_wrap_inflow(c, c->t + dt);
   c->interactions += 2 * (c->n_ff + c->n_fb);
 }
 
@@ -951,6 +1001,66 @@ static double solid_dt(const ora_ctx *c) {
   return dts;
 }
 
+/* P B of every solid particle at its current deformation gradient. */
+static void solid_PB(const ora_ctx *c, double *PB) {
+  int d = c->d;
+#pragma omp parallel for schedule(static)
+  for (int a = 0; a < c->ns; ++a) {
+    double P[9];
+    if (c->material == 1) ora_svk_stress(d, c->F + 9 * a, c->mu, c->lam, P);
+    else ora_nh_stress(d, c->F + 9 * a, c->mu, c->lam, P);
+    mat_mul(d, P, c->B + 9 * a, PB + 9 * a);
+  }
+}
+
+/* Momentum (Section 2.2, corrected total-Lagrangian form at h_S):
+ *   m_a dv/dt = sum_b V_a V_b (P_a B_a + P_b B_b) grad0_a W_ab + f^F_a + m_a g. */
+static void solid_accel(ora_ctx *c, const double *PB) {
+  int d = c->d;
+#pragma omp parallel for schedule(static)
+  for (int a = 0; a < c->ns; ++a) {
+    if (c->clamp[a]) continue;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int t = c->s_start[a]; t < c->s_start[a + 1]; ++t) {
+      int b = c->s_idx[t];
+      for (int i = 0; i < d; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < d; ++j) s += (PB[9 * a + 3 * i + j] + PB[9 * b + 3 * i + j]) * c->s_grad[3 * t + j];
+        acc[i] += c->V0[a] * c->V0[b] * s;
+      }
+    }
+    for (int q = 0; q < d; ++q) c->as[3 * a + q] = (acc[q] + c->fF[3 * a + q]) / c->ms[a] + c->g[q];
+  }
+}
+
+/* Reading: dF/dt = sum_b V_b (v_b - v_a) (x) (B_a grad0_a W_ab), the
+ * corrected gradient of the velocity. */
+static void solid_rate(ora_ctx *c) {
+  int d = c->d;
+#pragma omp parallel for schedule(static)
+  for (int a = 0; a < c->ns; ++a) {
+    double G[9] = {0};
+    if (!c->clamp[a])
+      for (int t = c->s_start[a]; t < c->s_start[a + 1]; ++t) {
+        int b = c->s_idx[t];
+        double bg[3] = {0};
+        for (int i = 0; i < d; ++i)
+          for (int j = 0; j < d; ++j) bg[i] += c->B[9 * a + 3 * i + j] * c->s_grad[3 * t + j];
+        for (int i = 0; i < d; ++i)
+          for (int j = 0; j < d; ++j)
+            G[3 * i + j] += c->V0[b] * (c->vs[3 * b + i] - c->vs[3 * a + i]) * bg[j];
+      }
+    memcpy(c->dF + 9 * a, G, sizeof G);
+  }
+}
+
+/* Reading: the clamp block is held at u = 0, v = 0, F = I. */
+static void solid_hold_clamp(ora_ctx *c, int a) {
+  for (int q = 0; q < 3; ++q) c->u[3 * a + q] = c->vs[3 * a + q] = c->as[3 * a + q] = 0.0;
+  mat_eye(c->F + 9 * a);
+  memset(c->dF + 9 * a, 0, 9 * sizeof(double));
+}
+
 /* kappa solid steps with the position-based Verlet scheme (Section 3.3), the
  * fluid force held constant; then the time averages of Section 3.2. */
 void ora_solid_substeps(ora_ctx *c) {
@@ -967,63 +1077,51 @@ void ora_solid_substeps(ora_ctx *c) {
   memcpy(v0, c->vs, sizeof(double) * 3 * (size_t)ns);
   double *PB = zalloc(9 * (size_t)ns);
   for (int sub = 0; sub < c->kappa; ++sub) {
+    if (c->vv) {
+      /* velocity-based contrast: half kick with the last evaluation, full
+       * step of F (rate from the half-kicked velocity) and position, the
+       * stress and acceleration at the new state, second half kick */
+      for (int a = 0; a < ns; ++a) {
+        if (c->clamp[a]) continue;
+        for (int q = 0; q < d; ++q) c->vs[3 * a + q] += 0.5 * del * c->as[3 * a + q];
+      }
+      solid_rate(c);
+      for (int a = 0; a < ns; ++a) {
+        if (c->clamp[a]) continue;
+        for (int q = 0; q < 9; ++q) c->F[9 * a + q] += del * c->dF[9 * a + q];
+        for (int q = 0; q < d; ++q) c->u[3 * a + q] += del * c->vs[3 * a + q];
+      }
+      solid_PB(c, PB);
+      solid_accel(c, PB);
+      for (int a = 0; a < ns; ++a) {
+        if (c->clamp[a]) {
+          solid_hold_clamp(c, a);
+          continue;
+        }
+        for (int q = 0; q < d; ++q) c->vs[3 * a + q] += 0.5 * del * c->as[3 * a + q];
+      }
+      c->interactions += 2 * c->n_ss;
+      c->substeps++;
+      continue;
+    }
     /* first half: deformation gradient, density (rho0 / J), position */
     for (int a = 0; a < ns; ++a) {
       if (c->clamp[a]) continue;
       for (int q = 0; q < 9; ++q) c->F[9 * a + q] += 0.5 * del * c->dF[9 * a + q];
       for (int q = 0; q < d; ++q) c->u[3 * a + q] += 0.5 * del * c->vs[3 * a + q];
     }
-#pragma omp parallel for schedule(static)
-    for (int a = 0; a < ns; ++a) {
-      double P[9];
-      if (c->material == 1) ora_svk_stress(d, c->F + 9 * a, c->mu, c->lam, P);
-      else ora_nh_stress(d, c->F + 9 * a, c->mu, c->lam, P);
-      mat_mul(d, P, c->B + 9 * a, PB + 9 * a);
-    }
-    /* Momentum (Section 2.2, corrected total-Lagrangian form at h_S):
-     *   m_a dv/dt = sum_b V_a V_b (P_a B_a + P_b B_b) grad0_a W_ab + f^F_a + m_a g. */
-#pragma omp parallel for schedule(static)
-    for (int a = 0; a < ns; ++a) {
-      if (c->clamp[a]) continue;
-      double acc[3] = {0.0, 0.0, 0.0};
-      for (int t = c->s_start[a]; t < c->s_start[a + 1]; ++t) {
-        int b = c->s_idx[t];
-        for (int i = 0; i < d; ++i) {
-          double s = 0.0;
-          for (int j = 0; j < d; ++j) s += (PB[9 * a + 3 * i + j] + PB[9 * b + 3 * i + j]) * c->s_grad[3 * t + j];
-          acc[i] += c->V0[a] * c->V0[b] * s;
-        }
-      }
-      for (int q = 0; q < d; ++q) c->as[3 * a + q] = (acc[q] + c->fF[3 * a + q]) / c->ms[a] + c->g[q];
-    }
+    solid_PB(c, PB);
+    solid_accel(c, PB);
     for (int a = 0; a < ns; ++a) {
       if (c->clamp[a]) continue;
       for (int q = 0; q < d; ++q) c->vs[3 * a + q] += del * c->as[3 * a + q];
     }
-    /* Reading: dF/dt = sum_b V_b (v_b - v_a) (x) (B_a grad0_a W_ab), the
-     * corrected gradient of the velocity, with the new velocity. */
-#pragma omp parallel for schedule(static)
-    for (int a = 0; a < ns; ++a) {
-      double G[9] = {0};
-      if (!c->clamp[a])
-        for (int t = c->s_start[a]; t < c->s_start[a + 1]; ++t) {
-          int b = c->s_idx[t];
-          double bg[3] = {0};
-          for (int i = 0; i < d; ++i)
-            for (int j = 0; j < d; ++j) bg[i] += c->B[9 * a + 3 * i + j] * c->s_grad[3 * t + j];
-          for (int i = 0; i < d; ++i)
-            for (int j = 0; j < d; ++j)
-              G[3 * i + j] += c->V0[b] * (c->vs[3 * b + i] - c->vs[3 * a + i]) * bg[j];
-        }
-      memcpy(c->dF + 9 * a, G, sizeof G);
-    }
+    /* deformation rate with the new velocity */
+    solid_rate(c);
     /* second half: deformation gradient and position */
     for (int a = 0; a < ns; ++a) {
       if (c->clamp[a]) {
-        /* Reading: the clamp block is held at u = 0, v = 0, F = I. */
-        for (int q = 0; q < 3; ++q) c->u[3 * a + q] = c->vs[3 * a + q] = c->as[3 * a + q] = 0.0;
-        mat_eye(c->F + 9 * a);
-        memset(c->dF + 9 * a, 0, 9 * sizeof(double));
+        solid_hold_clamp(c, a);
         continue;
       }
       for (int q = 0; q < 9; ++q) c->F[9 * a + q] += 0.5 * del * c->dF[9 * a + q];

@@ -42,7 +42,7 @@ class OraScene(C.Structure):
         ("x_fluid", _dp), ("v_fluid", _dp), ("x_wall", _dp), ("nrm_wall", _dp),
         ("x_solid", _dp), ("v_solid", _dp),
         ("riemann", C.c_int), ("density_reinit", C.c_int),
-        ("material", C.c_int), ("single_step", C.c_int),
+        ("material", C.c_int), ("single_step", C.c_int), ("velocity_verlet", C.c_int),
     ]
 
 
@@ -138,6 +138,7 @@ def make_scene_struct(sc: dict, riemann: int = 1, density_reinit: int = 1):
     s.density_reinit = int(density_reinit)
     s.material = int(sc.get("material", 0))
     s.single_step = int(sc.get("single_step", 0))
+    s.velocity_verlet = int(sc.get("velocity_verlet", 0))
     return s, keep
 
 

@@ -197,3 +197,50 @@ def test_single_step_conserves_momentum():
         dts.append(s["dt_ac"] / s["dt_s"])
     assert max(dts) == 1.0  # the solid step set the shared step
     assert np.abs(total() - p0).max() < 1e-12 * scale
+
+
+# ---------------------------------------------------------------- velocity-based Verlet
+
+def test_velocity_verlet_drift_is_the_marching_interval_mismatch():
+    # Section 3.3: with multiple time steps the velocity-based scheme does not
+    # conserve momentum, because the fluid applies the coupling force of an
+    # evaluation over half of each neighbouring acoustic step while the solid
+    # applies it over its own sub-steps.  The force of evaluation n reaches
+    # the fluid with weight (dt_n + dt_{n+1})/2 and the solid with weight
+    # dt_n - delta_n/2 + delta_{n+1}/2 (delta = dt / kappa); every other force
+    # cancels in pairs.  The observed drift must be exactly that mismatch,
+    # while the position-based scheme keeps the total to round-off.
+    sc = scenes.periodic_box_with_solid(dim=2, n=12, amp=0.3)
+    sc["velocity_verlet"] = 1
+    o = O.Oracle(sc)
+    mf, ms = o.masses()
+
+    def total():
+        return mf @ o.get(O.F_V) + ms @ o.get(O.S_V)
+
+    scale = mf @ np.abs(o.get(O.F_V)).sum(1) + ms @ np.abs(o.get(O.S_V)).sum(1)
+    p0 = total()
+    forces, dts, kaps = [], [], []
+    for _ in range(30):
+        if o.scalars()["need_rebuild"]:
+            o.rebuild()
+        o.fluid_step()
+        o.couple()
+        pair = o.fluid_side_coupling()[:2] + o.totals()["sum_fF"][:2]
+        assert np.abs(pair).max() <= 1e-13 * np.abs(o.get(O.S_FF)).sum()
+        forces.append(o.totals()["sum_fF"][:2].copy())
+        o.solid_substeps()
+        s = o.scalars()
+        dts.append(s["dt_ac"])
+        kaps.append(s["kappa"])
+    assert max(kaps) > 1 and len(set(dts)) > 1
+    n = len(dts)
+    pred = np.zeros(2)
+    for k in range(n):
+        last = k == n - 1
+        w_solid = dts[k] - 0.5 * dts[k] / kaps[k] + (0.0 if last else 0.5 * dts[k + 1] / kaps[k + 1])
+        w_fluid = 0.5 * dts[k] + (0.0 if last else 0.5 * dts[k + 1])
+        pred += (w_solid - w_fluid) * forces[k]
+    drift = total() - p0
+    assert np.abs(drift).max() > 1e3 * 1e-13 * scale  # a real drift
+    assert np.abs(drift - pred).max() <= 1e-12 * scale
