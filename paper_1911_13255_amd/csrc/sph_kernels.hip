@@ -20,13 +20,14 @@ namespace mrsph {
 // Blocks are handed to the 8 XCDs round-robin; remap so that each XCD works
 // on one contiguous range of (Morton-sorted) particles and its own L2 holds
 // their neighbours.
-__device__ __forceinline__ int xcd_block() {
-  int nb = gridDim.x, b = blockIdx.x;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
   int full = (nb / 8) * 8;
   if (b >= full) return b;
   int per = full / 8;
   return (b % 8) * per + b / 8;
 }
+
+__device__ __forceinline__ int xcd_block() { return xcd_block(blockIdx.x, gridDim.x); }
 
 __device__ __forceinline__ int particle_index() { return xcd_block() * blockDim.x + threadIdx.x; }
 
@@ -1127,28 +1128,43 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
 
 // Coupling lists of the free solid particles of rebuilding scenes, put in
 // ascending entry order (their entries arrive by atomics in any order), so
-// the coupling sums do not depend on arrival order.  One 64-lane block per
-// solid particle: the list is staged in LDS and every entry goes to its rank
-// (entries are distinct: a fluid particle appears once per list).
-__global__ void __launch_bounds__(64) k_cpl_sort(Dev D) {
-  extern __shared__ unsigned ent[];
-  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
-  const int a = blockIdx.x;
-  const int s = D.s_scene[a];
-  if (!D.st[s].need_rebuild || D.s_bslot[a] < 0) return;
+// the coupling sums do not depend on arrival order.  Run by the leading
+// blocks of the fluid force launch (the lists are read by the coupling pass
+// that follows it): each wave takes one list at a time, stages it in LDS
+// and sends every entry to its rank (entries are distinct: a fluid particle
+// appears once per list).  Every thread of a block runs the same number of
+// rounds, so the barriers are uniform.
+__device__ void sort_coupling_lists(const Dev &D, int nsort) {
+  extern __shared__ unsigned cpl_stage[];
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step (uniform)
+  const int waves = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned *ent = cpl_stage + w * D.capf;
   const int NS = D.ns;
-  const int c = D.s_cpl_cnt[a];
-  if (c > D.capf && threadIdx.x == 0) atomicOr(&D.st[s].err, (int)ERR_CAPACITY);
-  const int n = min(c, D.capf);
-  if (n < 2) return;
-  unsigned *l = D.s_cpl + a;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) ent[e] = l[(size_t)e * NS];
-  __syncthreads();
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const unsigned v = ent[e];
-    int rank = 0;
-    for (int f = 0; f < n; ++f) rank += ent[f] < v;
-    l[(size_t)rank * NS] = v;
+  const int stride = nsort * waves;
+  const int rounds = (NS + stride - 1) / stride;
+  for (int it = 0; it < rounds; ++it) {
+    const int a = it * stride + (int)blockIdx.x * waves + w;
+    int n = 0;
+    if (a < NS) {
+      const int s = D.s_scene[a];
+      if (D.st[s].need_rebuild && D.s_bslot[a] >= 0) {
+        const int c = D.s_cpl_cnt[a];
+        if (c > D.capf && lane == 0) atomicOr(&D.st[s].err, (int)ERR_CAPACITY);
+        n = min(c, D.capf);
+      }
+    }
+    unsigned *l = D.s_cpl + (a < NS ? a : 0);
+    if (n >= 2)
+      for (int e = lane; e < n; e += 64) ent[e] = l[(size_t)e * NS];
+    __syncthreads();
+    if (n >= 2)
+      for (int e = lane; e < n; e += 64) {
+        const unsigned v = ent[e];
+        int rank = 0;
+        for (int f = 0; f < n; ++f) rank += ent[f] < v;
+        l[(size_t)rank * NS] = v;
+      }
+    __syncthreads();
   }
 }
 
@@ -1175,7 +1191,13 @@ __global__ void __launch_bounds__(256) k_fluid_prep(Dev D) {
 // writes (v^{n+1}, eps^{n+1/2}), pressure and acceleration.
 template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
-  int g = particle_index();
+  if ((int)blockIdx.x < D.sort_blocks) {
+    sort_coupling_lists(D, D.sort_blocks);
+    return;
+  }
+  // the leading blocks are a multiple of 8: the XCD of a force block is
+  // still its index modulo 8
+  int g = xcd_block(blockIdx.x - D.sort_blocks, gridDim.x - D.sort_blocks) * blockDim.x + threadIdx.x;
   int i = g / LPP, q = g % LPP;
   bool active = i < D.nf;
   int ii = active ? i : 0;
@@ -1805,6 +1827,45 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
     vm = fmaxf(vm, sqrtf(v2));
     am = fmaxf(am, sqrtf(a2));
   }
+  // (Issued before the first barrier so that these loads overlap the state
+  // loads above.)  Reference-table rows of the own particles.  Every row is padded past
+  // its count with null entries (zero gradient, the particle itself), so the
+  // lanes of a wave walk their rows in lockstep up to the wave's longest row
+  // without masking; a lane without a particle in slot p walks the first
+  // particle's row and discards the sums.  Entries arrive by buffer loads
+  // whose vector offset is the lane's particle and whose scalar offset is
+  // the row, so addressing costs no vector instructions.
+  const __amdgpu_buffer_rsrc_t tab =
+      __builtin_amdgcn_make_buffer_rsrc((void *)D.s_nbr, 0, D.nbr_bytes, kBufferWord3);
+  const int row_bytes = NS * (int)sizeof(float4);
+  unsigned voff[PPT];
+  int cnt_max = 0;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    int lo = own[p] ? la[p] : 0;
+    voff[p] = (unsigned)(base + lo) * (unsigned)sizeof(float4);
+    if (own[p]) cnt_max = max(cnt_max, D.s_cnt[base + lo]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt_max = max(cnt_max, __shfl_xor(cnt_max, o));
+  const int wrows = __builtin_amdgcn_readfirstlane(cnt_max);
+  // in 2D z holds the index within the scene: one 12-byte load per entry
+  auto entry = [&](int p, int q) -> i4v {
+    if constexpr (DIM == 2) {
+      i3v e = (i3v)__builtin_amdgcn_raw_buffer_load_b96(tab, voff[p], q * row_bytes, 0);
+      return i4v{e[0], e[1], 0, e[2]};
+    } else {
+      return (i4v)__builtin_amdgcn_raw_buffer_load_b128(tab, voff[p], q * row_bytes, 0);
+    }
+  };
+  // sum_b g_ab of each own particle (stored with the table):
+  // sum_b (P_a B_a + P_b B_b) g_ab = P_a B_a sum_b g_ab + sum_b P_b B_b g_ab and
+  // sum_b (v_b - v_a) (x) g_ab = sum_b v_b (x) g_ab - v_a (x) sum_b g_ab
+  double gs[PPT][DIM];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p)
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) gs[p][k] = own[p] ? D.s_gsum[k * NS + base + la[p]] : 0.0;
   // block maxima of |v| and |a|: wave shuffles, then one value per wave
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -1866,44 +1927,6 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   for (int p = 0; p < PPT; ++p)
     if (own[p]) first_half(p);
   __syncthreads();
-  // Reference-table rows of the own particles.  Every row is padded past
-  // its count with null entries (zero gradient, the particle itself), so the
-  // lanes of a wave walk their rows in lockstep up to the wave's longest row
-  // without masking; a lane without a particle in slot p walks the first
-  // particle's row and discards the sums.  Entries arrive by buffer loads
-  // whose vector offset is the lane's particle and whose scalar offset is
-  // the row, so addressing costs no vector instructions.
-  const __amdgpu_buffer_rsrc_t tab =
-      __builtin_amdgcn_make_buffer_rsrc((void *)D.s_nbr, 0, D.nbr_bytes, kBufferWord3);
-  const int row_bytes = NS * (int)sizeof(float4);
-  unsigned voff[PPT];
-  int cnt_max = 0;
-#pragma unroll
-  for (int p = 0; p < PPT; ++p) {
-    int lo = own[p] ? la[p] : 0;
-    voff[p] = (unsigned)(base + lo) * (unsigned)sizeof(float4);
-    if (own[p]) cnt_max = max(cnt_max, D.s_cnt[base + lo]);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) cnt_max = max(cnt_max, __shfl_xor(cnt_max, o));
-  const int wrows = __builtin_amdgcn_readfirstlane(cnt_max);
-  // in 2D z holds the index within the scene: one 12-byte load per entry
-  auto entry = [&](int p, int q) -> i4v {
-    if constexpr (DIM == 2) {
-      i3v e = (i3v)__builtin_amdgcn_raw_buffer_load_b96(tab, voff[p], q * row_bytes, 0);
-      return i4v{e[0], e[1], 0, e[2]};
-    } else {
-      return (i4v)__builtin_amdgcn_raw_buffer_load_b128(tab, voff[p], q * row_bytes, 0);
-    }
-  };
-  // sum_b g_ab of each own particle (stored with the table):
-  // sum_b (P_a B_a + P_b B_b) g_ab = P_a B_a sum_b g_ab + sum_b P_b B_b g_ab and
-  // sum_b (v_b - v_a) (x) g_ab = sum_b v_b (x) g_ab - v_a (x) sum_b g_ab
-  double gs[PPT][DIM];
-#pragma unroll
-  for (int p = 0; p < PPT; ++p)
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) gs[p][k] = own[p] ? D.s_gsum[k * NS + base + la[p]] : 0.0;
   for (int sub = 0; sub < kap; ++sub) {
     // momentum, velocity
     {
@@ -2618,19 +2641,19 @@ void launch_refresh_vmax(const Dev &D, hipStream_t st) {
   hipLaunchKernelGGL(k_refresh_vmax, dim3(D.n_scenes), dim3(256), 0, st, D);
 }
 
-#define LAUNCH_LPP(kern, lpp, dim, grid, block, stream, ...)                                    \
+#define LAUNCH_LPP(kern, lpp, dim, grid, block, shm, stream, ...)                                    \
   do {                                                                                         \
     switch (lpp) {                                                                             \
-    case 1: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 1>), grid, block, 0, stream, __VA_ARGS__);  \
-            else hipLaunchKernelGGL((kern<3, 1>), grid, block, 0, stream, __VA_ARGS__); break;       \
-    case 2: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 2>), grid, block, 0, stream, __VA_ARGS__);  \
-            else hipLaunchKernelGGL((kern<3, 2>), grid, block, 0, stream, __VA_ARGS__); break;       \
-    case 4: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 4>), grid, block, 0, stream, __VA_ARGS__);  \
-            else hipLaunchKernelGGL((kern<3, 4>), grid, block, 0, stream, __VA_ARGS__); break;       \
-    case 8: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 8>), grid, block, 0, stream, __VA_ARGS__);  \
-            else hipLaunchKernelGGL((kern<3, 8>), grid, block, 0, stream, __VA_ARGS__); break;       \
-    default: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 16>), grid, block, 0, stream, __VA_ARGS__); \
-            else hipLaunchKernelGGL((kern<3, 16>), grid, block, 0, stream, __VA_ARGS__); break;      \
+    case 1: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 1>), grid, block, shm, stream, __VA_ARGS__);  \
+            else hipLaunchKernelGGL((kern<3, 1>), grid, block, shm, stream, __VA_ARGS__); break;       \
+    case 2: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 2>), grid, block, shm, stream, __VA_ARGS__);  \
+            else hipLaunchKernelGGL((kern<3, 2>), grid, block, shm, stream, __VA_ARGS__); break;       \
+    case 4: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 4>), grid, block, shm, stream, __VA_ARGS__);  \
+            else hipLaunchKernelGGL((kern<3, 4>), grid, block, shm, stream, __VA_ARGS__); break;       \
+    case 8: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 8>), grid, block, shm, stream, __VA_ARGS__);  \
+            else hipLaunchKernelGGL((kern<3, 8>), grid, block, shm, stream, __VA_ARGS__); break;       \
+    default: if ((dim) == 2) hipLaunchKernelGGL((kern<2, 16>), grid, block, shm, stream, __VA_ARGS__); \
+            else hipLaunchKernelGGL((kern<3, 16>), grid, block, shm, stream, __VA_ARGS__); break;      \
     }                                                                                          \
   } while (0)
 
@@ -2652,27 +2675,42 @@ void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_rank_move, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
   if (D.nf > 0)
     LAUNCH_LPP(k_reinit, cfg.lpp_reinit, D.dim, grid_for((long long)D.nf * cfg.lpp_reinit, cfg.block_pair),
-               dim3(cfg.block_pair), st, D);
-  if (D.ns > 0) hipLaunchKernelGGL(k_cpl_sort, dim3(D.ns), dim3(64), D.capf * sizeof(unsigned), st, D);
+               dim3(cfg.block_pair), 0, st, D);
 }
+
+// coupling lists ordered by each wave of the force launch's leading blocks
+constexpr int kListsPerWave = 2;
 
 void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   if (D.nf > 0 && D.fluid_prep) hipLaunchKernelGGL(k_fluid_prep, grid_for(D.nf, 256), dim3(256), 0, st, D);
-  if (D.nf > 0)
-    LAUNCH_LPP(k_fluid_force, cfg.lpp_force, D.dim, grid_for((long long)D.nf * cfg.lpp_force, cfg.block_pair),
-               dim3(cfg.block_pair), st, D);
+  if (D.nf > 0) {
+    // leading blocks order the coupling lists after a rebuild: kListsPerWave
+    // lists per wave, more where that would need over 2048 blocks (each
+    // block that only finds no rebuild still costs a dispatch), a multiple
+    // of 8 blocks
+    Dev Df = D;
+    const int waves = cfg.block_pair / 64;
+    const int per = std::max(kListsPerWave, (D.ns + waves * 2048 - 1) / (waves * 2048));
+    int nsort = D.ns > 0 ? (D.ns + per * waves - 1) / (per * waves) : 0;
+    nsort = (nsort + 7) / 8 * 8;
+    Df.sort_blocks = nsort;
+    dim3 grid = grid_for((long long)D.nf * cfg.lpp_force, cfg.block_pair);
+    grid.x += nsort;
+    const size_t shm = nsort ? (size_t)waves * D.capf * sizeof(unsigned) : 0;
+    LAUNCH_LPP(k_fluid_force, cfg.lpp_force, D.dim, grid, dim3(cfg.block_pair), shm, st, Df);
+  }
 }
 
 void launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   if (D.nf > 0)
     LAUNCH_LPP(k_fluid_continuity, cfg.lpp_cont, D.dim, grid_for((long long)D.nf * cfg.lpp_cont, cfg.block_pair),
-               dim3(cfg.block_pair), st, D);
+               dim3(cfg.block_pair), 0, st, D);
 }
 
 void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   if (D.ns > 0)
     LAUNCH_LPP(k_couple, cfg.lpp_couple, D.dim, grid_for((long long)D.ns * cfg.lpp_couple, cfg.block_couple),
-               dim3(cfg.block_couple), st, D);
+               dim3(cfg.block_couple), 0, st, D);
 }
 
 #define LAUNCH_SOLID_REG(ppt, ...)                                                        \
