@@ -28,6 +28,7 @@ struct sph_ctx {
   hipGraph_t graph;
   hipGraphExec_t graph_exec;
   int graph_failed;
+  int prebin;        // a rebuild set from the host may await binning (sph_advance bins it first)
   hipStream_t side;  // second stream for the concurrent continuity pass (graph capture only)
   hipEvent_t ev_fork, ev_join;
   size_t stage_doubles;
@@ -478,7 +479,7 @@ int enqueue_solid(sph_ctx *ctx) {
 // later pass of the step reads until the step-end kernel) runs concurrently
 // with the coupling and solid passes.
 int enqueue_step(sph_ctx *ctx, bool fork) {
-  launch_rebuild(ctx->D, ctx->cfg, ctx->stream);
+  launch_rebuild(ctx->D, ctx->cfg, ctx->stream, false);
   launch_fluid_force(ctx->D, ctx->cfg, ctx->stream);
   if (fork && ctx->cfg.fork && ctx->side && ctx->cfg.solid_ppt > 0) {
     if (hipEventRecord(ctx->ev_fork, ctx->stream) != hipSuccess ||
@@ -675,13 +676,14 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
     HIPCHK_INIT(hipMemcpy(D.st, stv.data(), sizeof(SceneState) * n_scenes, hipMemcpyHostToDevice));
   }
 #undef HIPCHK_INIT
+  ctx->prebin = 1;  // every scene starts with a rebuild
   *out = ctx;
   return SPH_OK;
 }
 
 int neighbor_build(sph_ctx *ctx) {
   if (!ctx) return SPH_E_ORDER;
-  launch_rebuild(ctx->D, ctx->cfg, ctx->stream);
+  launch_rebuild(ctx->D, ctx->cfg, ctx->stream, true);
   return check_launch(ctx, "neighbor_build");
 }
 
@@ -733,6 +735,12 @@ int sph_advance(sph_ctx *ctx, int n_steps) {
       (void)hipGetLastError();
     }
   }
+  // rebuilds set from the host are binned here; the steps bin the rebuilds
+  // they decide themselves at their end
+  if (ctx->prebin && n_steps > 0) {
+    launch_bin(ctx->D, ctx->stream);
+    ctx->prebin = 0;
+  }
   for (int k = 0; k < n_steps; ++k) {
     if (ctx->graph_exec) {
       HIPCHK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
@@ -775,7 +783,11 @@ int sph_write(sph_ctx *ctx, int field, int scene, const double *host) {
   HIPCHK(hipStreamSynchronize(ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->D.stage, host, sizeof(double) * w * (size_t)n, hipMemcpyHostToDevice, ctx->stream));
   launch_write(ctx->D, scene, field, n, ctx->D.stage, ctx->stream);
+  // the step-end binning copied the fluid state: a scene binned before this
+  // write is binned again when its rebuild starts
   if (field != SPH_F_RHO && field != SPH_F_DRHO) launch_set_rebuild(ctx->D, scene, ctx->stream);
+  else launch_unbin(ctx->D, scene, ctx->stream);
+  ctx->prebin = 1;
   if (field == SPH_F_V || (ctx->D.any_single && (field == SPH_S_V || field == SPH_S_A)))
     launch_refresh_vmax(ctx->D, ctx->stream);
   int rc = check_launch(ctx, "sph_write");
@@ -810,6 +822,12 @@ int sph_set_scalars(sph_ctx *ctx, int scene, const double *in) {
   S.adv_accum = in[4];
   const int was = S.need_rebuild;
   S.need_rebuild = in[6] != 0.0;
+  if (S.binned && !S.need_rebuild) {  // a withdrawn rebuild gives back its binning
+    launch_unbin(ctx->D, scene, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    S.binned = 0;
+  }
+  if (S.need_rebuild && !was) ctx->prebin = 1;
   HIPCHK(hipMemcpy(ctx->D.st + scene, &S, sizeof(SceneState), hipMemcpyHostToDevice));
   if (S.need_rebuild != was) {  // keep the count of set flags (the stream is idle here)
     int cnt = 0;
@@ -947,7 +965,7 @@ int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms) {
     case SPH_K_SOLID: return enqueue_solid(ctx);
     case SPH_K_REBUILD:
       for (int s = 0; s < ctx->n_scenes; ++s) launch_set_rebuild(ctx->D, s, st);
-      launch_rebuild(ctx->D, ctx->cfg, st);
+      launch_rebuild(ctx->D, ctx->cfg, st, true);
       break;
     }
     return SPH_OK;
@@ -990,6 +1008,8 @@ int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms) {
   if (e1) (void)hipEventDestroy(e1);
   if (ge) (void)hipGraphExecDestroy(ge);
   if (g) (void)hipGraphDestroy(g);
+  // the forced rebuilds consumed their binning: the next steps bin again
+  if (kernel == SPH_K_REBUILD) ctx->prebin = 1;
   *avg_ms = (double)ms / reps;
   return rc;
 }

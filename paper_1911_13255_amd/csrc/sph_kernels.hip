@@ -477,17 +477,25 @@ __global__ void k_refresh_vmax(Dev D) {
 // the kernels below test the flag and exit at once otherwise, and the
 // step-close kernel at the end of the step clears it.
 
-// Bin the fluid and the boundary sources (walls, free solid) of rebuilding
-// scenes: new cell and offset from the current position, slot within the
-// cell, and a copy of the fluid state by old index.
+// The advection step ends with the acoustic step that is closing: the same
+// test, on the same values, as close_scene's.
+__device__ __forceinline__ bool rebuilds_next(const SceneState &S) { return S.adv_accum + S.dt_ac >= S.dt_ad; }
+
+// Bin entry t (fluid, then walls and free solid) of a rebuilding scene: new
+// cell and offset from the current position, slot within the cell, and a
+// copy of the fluid state by old index.  at_step_end: binned by the step-end
+// kernel for the rebuild that the closing step is about to set; otherwise at
+// the start of a step for a rebuild set from the host (scenes not binned yet).
 template <int DIM>
-__global__ void __launch_bounds__(256) k_bin(Dev D) {
-  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void bin_entry(const Dev &D, int t, bool at_step_end) {
+  auto due = [&](int s) {
+    const SceneState &S = D.st[s];
+    return at_step_end ? rebuilds_next(S) : (S.need_rebuild && !S.binned);
+  };
   if (t < D.nf) {
     int i = t;
     int s = D.f_scene[i];
-    if (!D.st[s].need_rebuild) return;
+    if (!due(s)) return;
     const ScenePar &P = D.par[s];
     int c[3];
     decode_cell(P, D.f_lin[i], c);
@@ -507,7 +515,7 @@ __global__ void __launch_bounds__(256) k_bin(Dev D) {
   int q = t - D.nf;
   if (q >= D.nb) return;
   int s = D.bs_scene[q];
-  if (!D.st[s].need_rebuild) return;
+  if (!due(s)) return;
   const ScenePar &P = D.par[s];
   int local = q - P.b_begin;
   int c[3];
@@ -530,6 +538,15 @@ __global__ void __launch_bounds__(256) k_bin(Dev D) {
   D.bs_lin[q] = lin;
   D.bs_off[q] = make_double4(off[0], off[1], off[2], 0.0);
   D.bs_slot[q] = atomicAdd(&D.bc_count[P.cell_begin + lin], 1);
+}
+
+// Binning at the start of a step, for rebuilds set from the host (state
+// writes, initialisation, a forced rebuild); the rebuilds the method itself
+// decides are binned by the step-end kernel of the step before.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_bin(Dev D) {
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
+  bin_entry<DIM>(D, blockIdx.x * blockDim.x + threadIdx.x, false);
 }
 
 // Cell scan of the rebuilding scenes: every cell's [start, end) in the sorted
@@ -1485,6 +1502,7 @@ __device__ void close_scene(const Dev &D, int s, unsigned vmax_bits, const unsig
   S.adv_accum += dt_ac;
   const int was = S.need_rebuild, now = S.adv_accum >= S.dt_ad ? 1 : 0;
   S.need_rebuild = now;
+  S.binned = now;  // the step-end kernel binned exactly these scenes
   if (now != was) atomicAdd(D.rebuild_count, now - was);
   float vmax = __uint_as_float(vmax_bits);
   S.vmax_prev = vmax_bits;
@@ -2114,14 +2132,21 @@ __device__ void single_step_maxima(const Dev &D, int a) {
 // the continuity pass, which reads the boundary particles, can run
 // concurrently with the coupling and solid passes.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
+__global__ void __launch_bounds__(256) k_step_reduce(Dev D, int bin_blocks, int fluid_blocks) {
   __shared__ float shm[16];
   __shared__ unsigned long long shc[3][16];
-  if ((int)blockIdx.x < fluid_blocks) {
+  if ((int)blockIdx.x < bin_blocks) {
+    // the particles of scenes whose advection step ends with this step are
+    // binned for the rebuild that opens the next one
+    bin_entry<DIM>(D, blockIdx.x * blockDim.x + threadIdx.x, true);
+    return;
+  }
+  const int blk = blockIdx.x - bin_blocks;
+  if (blk < fluid_blocks) {
     // kReduceItems particles per thread; one reduction and atomic per scene
     // present in the block (scenes own contiguous ranges)
     const int span = blockDim.x * kReduceItems;
-    const int i0 = blockIdx.x * span, i1 = min(D.nf, i0 + span);
+    const int i0 = blk * span, i1 = min(D.nf, i0 + span);
     const int s0 = D.f_scene[i0], s1 = D.f_scene[i1 - 1];
     auto fmx = [](float x, float y) { return fmaxf(x, y); };
     auto add = [](unsigned long long x, unsigned long long y) { return x + y; };
@@ -2153,7 +2178,7 @@ __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int fluid_blocks) {
     }
     return;
   }
-  const int a = (blockIdx.x - fluid_blocks) * blockDim.x + threadIdx.x;
+  const int a = (blk - fluid_blocks) * blockDim.x + threadIdx.x;
   hand_over<DIM>(D, a);
   if (D.any_single) single_step_maxima<DIM>(D, a);
 }
@@ -2597,12 +2622,33 @@ __global__ void k_reduce_final(Dev D, int nblocks, double *out) {
   out[threadIdx.x] = s;
 }
 
-__global__ void k_set_rebuild(Dev D, int s) {
+// Drops the binning done at the end of the last step for scene s (the state
+// has changed since, or the rebuild is withdrawn): its cell counts return to
+// zero and the scene is binned again when its rebuild starts.
+__device__ void unbin_scene(const Dev &D, int s) {
+  SceneState &S = D.st[s];
+  const int binned = S.binned;  // uniform: read before any thread writes it
+  __syncthreads();
+  if (binned) {
+    const ScenePar &P = D.par[s];
+    for (int c = threadIdx.x; c < P.ncell_total; c += blockDim.x) {
+      D.fc_count[P.cell_begin + c] = 0;
+      D.bc_count[P.cell_begin + c] = 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) S.binned = 0;
+}
+
+__global__ void __launch_bounds__(256) k_set_rebuild(Dev D, int s) {
+  unbin_scene(D, s);
   if (threadIdx.x == 0 && !D.st[s].need_rebuild) {
     D.st[s].need_rebuild = 1;
     atomicAdd(D.rebuild_count, 1);
   }
 }
+
+__global__ void __launch_bounds__(256) k_unbin(Dev D, int s) { unbin_scene(D, s); }
 
 // ------------------------------------------------------------------ host-side launchers
 
@@ -2661,8 +2707,8 @@ static inline dim3 grid_for(long long threads, int block) {
   return dim3((unsigned)std::max<long long>(1, (threads + block - 1) / block));
 }
 
-void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
-  if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_bin, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
+void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool with_bin) {
+  if (with_bin) launch_bin(D, st);
   const int ntiles = (D.ncell + kCellTile - 1) / kCellTile;
   if (ntiles == 1) {
     hipLaunchKernelGGL(k_cell_one, dim3(1), dim3(1024), 0, st, D);
@@ -2764,7 +2810,8 @@ void launch_sur_predict(const Dev &D, hipStream_t st) {
 
 void launch_step_end(const Dev &D, hipStream_t st) {
   int fb = (D.nf + 256 * kReduceItems - 1) / (256 * kReduceItems), sb = (D.ns + 255) / 256;
-  if (fb + sb > 0) LAUNCH_DIM(D.dim, k_step_reduce, dim3(fb + sb), dim3(256), st, D, fb);
+  int bb = (D.nf + D.nb + 255) / 256;
+  if (bb + fb + sb > 0) LAUNCH_DIM(D.dim, k_step_reduce, dim3(bb + fb + sb), dim3(256), st, D, bb, fb);
   hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
 }
 
@@ -2793,7 +2840,15 @@ void launch_reduce(const Dev &D, int s, int nblocks, double *out, hipStream_t st
 }
 
 void launch_set_rebuild(const Dev &D, int s, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_rebuild, dim3(1), dim3(64), 0, st, D, s);
+  hipLaunchKernelGGL(k_set_rebuild, dim3(1), dim3(256), 0, st, D, s);
+}
+
+void launch_unbin(const Dev &D, int s, hipStream_t st) {
+  hipLaunchKernelGGL(k_unbin, dim3(1), dim3(256), 0, st, D, s);
+}
+
+void launch_bin(const Dev &D, hipStream_t st) {
+  if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_bin, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
 }
 
 }  // namespace mrsph
