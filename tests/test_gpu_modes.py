@@ -130,3 +130,25 @@ def test_single_step_graph_replay_matches_direct_calls(gpu):
     assert a.counters(0)["substeps"] == 39
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("case", ["I", "II", "III", "IV"])
+def test_paper_cases_full_size(gpu, case):
+    # The four flow-induced-vibration cases the benchmark times, at their full
+    # sizes (up to 70k fluid particles), linear elastic plate: three steps
+    # against the whole oracle.
+    import bench
+
+    name, geo, single, _ = [c for c in bench.PAPER_CASES if c[0] == case][0]
+    sc = scenes.plate_behind_cylinder(seed=1, **geo)
+    sc["material"] = 1
+    sc["single_step"] = single
+    note(f"paper case {name}: {len(sc['x_fluid'])} fluid, {len(sc['x_solid'])} solid, single step {single}")
+    sim = sph.Simulation(sc)
+    o = O.Oracle(sc)
+    for k in range(3):
+        one_step(sim, o)
+        compare(sim, o, label=f"case {name} step {k + 1}")
+        assert sim.scalars()["kappa"] == o.scalars()["kappa"]
+    sim.sync()
+    sim.close()
