@@ -193,10 +193,24 @@ def cpu_baseline(scene, seconds=15.0):
     dt = time.perf_counter() - t0
     c1 = o.counters()
     inter = c1["interactions"] - c0["interactions"]
+    # the same oracle on one thread, on a shorter sample continuing the run
+    ora.set_threads(1)
+    c2 = o.counters()
+    t1 = time.perf_counter()
+    n1 = 0
+    while time.perf_counter() - t1 < seconds / 3.0:
+        o.step(2)
+        n1 += 2
+    dt1 = time.perf_counter() - t1
+    c3 = o.counters()
+    ora.set_threads(threads)
     return dict(value=inter / dt, unit="interactions/s", cores=threads, kind="oracle",
                 sample=f"{n} acoustic steps after the first two of the same scene and seed "
                        f"({dt:.1f} s, FP64, OpenMP)",
-                steps_per_s=n / dt)
+                steps_per_s=n / dt,
+                single_thread=dict(value=(c3["interactions"] - c2["interactions"]) / dt1, cores=1,
+                                   sample=f"the next {n1} acoustic steps ({dt1:.1f} s)",
+                                   steps_per_s=n1 / dt1))
 
 
 def main():

@@ -1312,6 +1312,15 @@ int ora_num_threads(void) {
 #endif
 }
 
+/* threads of the following parallel loops (timing only) */
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* fluid masses (index order) */
 void ora_masses(const ora_ctx *c, double *mf, double *ms) {
   if (mf) memcpy(mf, c->m, sizeof(double) * (size_t)c->nf);

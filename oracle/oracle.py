@@ -267,6 +267,14 @@ def num_threads():
     return L.ora_num_threads()
 
 
+def set_threads(n: int):
+    """OpenMP threads of the oracle's parallel loops from now on (timing only)."""
+    L = lib()
+    L.ora_set_threads.argtypes = [C.c_int]
+    L.ora_set_threads.restype = None
+    L.ora_set_threads(int(n))
+
+
 def psi0(d, h_ratio=1.3):
     return lib().ora_psi0(int(d), float(h_ratio))
 
