@@ -179,6 +179,55 @@ def test_teacher_forced_steps_dam_break(gpu):
     sim.close()
 
 
+@pytest.mark.parametrize("path", ["calls", "graph"])
+def test_host_writes_after_a_step_end_binning(gpu, path):
+    # A step whose close sets a rebuild has already binned the scene's
+    # particles.  A later density write must reach the rebuilt state, and a
+    # rebuild withdrawn from the host must leave the next rebuild intact; both
+    # through the separate entry points and through graph replays.
+    sc = scenes.dam_break_plate(seed=3)
+    sim = sph.Simulation(sc)
+    o = O.Oracle(sc)
+    gstep = sim.step if path == "calls" else (lambda: sim.advance(1))
+
+    def step():
+        gstep()
+        o.step(1)
+
+    def until_rebuild_due():
+        for _ in range(200):
+            step()
+            if o.scalars()["need_rebuild"]:
+                assert sim.scalars()["need_rebuild"] == 1
+                return
+        raise AssertionError("no rebuild within 200 steps")
+
+    step()
+    until_rebuild_due()
+    rho = o.get(O.F_RHO) * (1.0 + 1e-3 * np.sin(np.arange(ora_nf(o))))
+    o.set(O.F_RHO, rho)
+    sim.write(sph.F_RHO, rho)
+    note(f"{path}: density written after a step-end binning")
+    step()
+    compare(sim, o, label=f"{path} density write")
+    until_rebuild_due()
+    o.set_scalars({"need_rebuild": 0})
+    sim.set_scalars(0, need_rebuild=0)
+    note(f"{path}: rebuild withdrawn after a step-end binning")
+    step()
+    assert sim.counters(0)["rebuilds"] == o.counters()["rebuilds"]
+    for k in range(12):
+        step()
+    compare(sim, o, label=f"{path} after the withdrawn rebuild")
+    assert sim.counters(0)["rebuilds"] == o.counters()["rebuilds"]
+    sim.sync()
+    sim.close()
+
+
+def ora_nf(o):
+    return len(o.get(O.F_RHO))
+
+
 @pytest.mark.parametrize("dim,eta,solid_lds", [(2, 0.0, 0), (2, 2.0, 0), (2, 2.0, 1), (3, 0.5, 0),
                                                (3, 0.5, 1)])
 def test_periodic_box_with_free_solid(gpu, dim, eta, solid_lds):
