@@ -735,10 +735,10 @@ int sph_advance(sph_ctx *ctx, int n_steps) {
       (void)hipGetLastError();
     }
   }
-  // rebuilds set from the host are binned here; the steps bin the rebuilds
-  // they decide themselves at their end
+  // rebuilds set from the host are binned (and scanned) here; the steps do
+  // that at their end for the rebuilds they decide themselves
   if (ctx->prebin && n_steps > 0) {
-    launch_bin(ctx->D, ctx->stream);
+    launch_prebin(ctx->D, ctx->stream);
     ctx->prebin = 0;
   }
   for (int k = 0; k < n_steps; ++k) {

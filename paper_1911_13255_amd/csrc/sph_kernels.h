@@ -43,11 +43,13 @@ void launch_init_solid(const Dev &D, int s, const double *x, const double *v, in
 void launch_solid_reference(const Dev &D, int s, int ns_scene, hipStream_t st);
 void launch_solid_B(const Dev &D, hipStream_t st);
 void launch_refresh_vmax(const Dev &D, hipStream_t st);
-// with_bin: bin the scenes whose rebuild was set from the host; graph steps
-// leave it to a launch_bin ahead of the replays (the method's own rebuilds
-// are binned by the step-end kernel)
+// with_bin: bin (and scan) the scenes whose rebuild was set from the host;
+// graph steps leave that to a launch_prebin ahead of the replays (the
+// method's own rebuilds are binned by the step-end reduction and, where the
+// cells form one tile, scanned by the step close)
 void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool with_bin);
 void launch_bin(const Dev &D, hipStream_t st);
+void launch_prebin(const Dev &D, hipStream_t st);
 void launch_unbin(const Dev &D, int s, hipStream_t st);
 void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 void launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st);

@@ -557,11 +557,15 @@ __global__ void __launch_bounds__(256) k_bin(Dev D) {
 // Scenes that do not rebuild hold zero counts, so a rebuilding scene's
 // entries start at its f_begin / b_begin plus the prefix from its first cell.
 
-// true when a tile holds cells of a rebuilding scene
+// a rebuilding scene whose cells are not scanned yet (binned == 2: scanned
+// by the close of the step that set the rebuild)
+__device__ __forceinline__ bool scan_due(const SceneState &S) { return S.need_rebuild && S.binned != 2; }
+
+// true when a tile holds cells of a scene due for its scan
 __device__ __forceinline__ bool tile_rebuilds(const Dev &D, int g0, int g1) {
   int s0 = D.cell_scene[g0], s1 = D.cell_scene[g1 - 1];
   for (int s = s0; s <= s1; ++s)
-    if (D.st[s].need_rebuild) return true;
+    if (scan_due(D.st[s])) return true;
   return false;
 }
 
@@ -585,20 +589,27 @@ __global__ void __launch_bounds__(1024) k_cell_sum(Dev D) {
   if (threadIdx.x == 0) D.cell_part[blockIdx.x] = make_int2(lf, lb);
 }
 
-// One block: per-scene bookkeeping of the rebuild (advection time step,
-// Section 3.2: dt_ad = cfl_ad min(h / max(|v|max, U_ref), h^2 rho0 / eta)),
-// the scan prefix at each scene's first cell, and the exclusive scan of the
-// tile sums.
-__device__ __forceinline__ void rebuild_bookkeeping(const Dev &D) {
+// The scan prefix at the first cell of each scene due for its scan.
+__device__ __forceinline__ void scan_bases(const Dev &D) {
   int bf = 0, bb = 0;
   for (int s = 0; s < D.n_scenes; ++s) {
     SceneState &S = D.st[s];
     const ScenePar &P = D.par[s];
     S.base_f = bf;
     S.base_b = bb;
-    if (!S.need_rebuild) continue;
+    if (!scan_due(S)) continue;
     bf += P.f_count;
     bb += P.b_count;
+  }
+}
+
+// Per-scene bookkeeping when the rebuild runs (advection time step, Section
+// 3.2: dt_ad = cfl_ad min(h / max(|v|max, U_ref), h^2 rho0 / eta)).
+__device__ __forceinline__ void rebuild_bookkeeping(const Dev &D) {
+  for (int s = 0; s < D.n_scenes; ++s) {
+    SceneState &S = D.st[s];
+    const ScenePar &P = D.par[s];
+    if (!S.need_rebuild) continue;
     double vm = fmax((double)__uint_as_float(S.vmax_prev), (double)P.u_ref);
     double dt = (double)P.cfl_ad * (double)P.hf / vm;
     if (P.dt_visc > 0.0) dt = fmin(dt, P.dt_visc);
@@ -608,13 +619,19 @@ __device__ __forceinline__ void rebuild_bookkeeping(const Dev &D) {
   }
 }
 
+// The scenes whose cells were just scanned (after the last use of scan_due).
+__device__ __forceinline__ void mark_scanned(const Dev &D) {
+  for (int s = 0; s < D.n_scenes; ++s)
+    if (scan_due(D.st[s])) D.st[s].binned = 2;
+}
+
 __global__ void __launch_bounds__(1024) k_cell_prefix(Dev D, int ntiles) {
   __shared__ int sf[1024], sb[1024];
   __shared__ int carry[2];
   if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   const int t = threadIdx.x, T = blockDim.x;
   if (t == 0) {
-    rebuild_bookkeeping(D);
+    scan_bases(D);
     carry[0] = carry[1] = 0;
   }
   __syncthreads();
@@ -708,7 +725,7 @@ __device__ __forceinline__ void apply_tile(const Dev &D, int g0, int g1, int2 ba
   for (int g = t; g < ng; g += T) {
     const int s = D.cell_scene[g0 + g];
     const SceneState &S = D.st[s];
-    if (!S.need_rebuild) continue;
+    if (!scan_due(S)) continue;
     const ScenePar &P = D.par[s];
     const int c = L.cell[g];
     const int f0 = P.f_begin + L.pf[g] - S.base_f, b0 = P.b_begin + L.pb[g] - S.base_b;
@@ -727,14 +744,20 @@ __global__ void __launch_bounds__(1024) k_cell_apply(Dev D) {
   apply_tile(D, g0, g1, D.cell_part[blockIdx.x], L);
 }
 
-// All cells in one tile: bookkeeping, scan and [start, end) in one block.
+// All cells in one tile: scene bases, scan and [start, end) in one block.
+__device__ void scan_one_tile(const Dev &D, TileLds &L) {
+  if (!tile_rebuilds(D, 0, D.ncell)) return;  // the same answer in every thread
+  if (threadIdx.x == 0) scan_bases(D);
+  __syncthreads();
+  apply_tile(D, 0, D.ncell, make_int2(0, 0), L);
+  __syncthreads();
+  if (threadIdx.x == 0) mark_scanned(D);
+}
+
 __global__ void __launch_bounds__(1024) k_cell_one(Dev D) {
   __shared__ TileLds L;
   if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
-  if (!tile_rebuilds(D, 0, D.ncell)) return;
-  if (threadIdx.x == 0) rebuild_bookkeeping(D);
-  __syncthreads();
-  apply_tile(D, 0, D.ncell, make_int2(0, 0), L);
+  scan_one_tile(D, L);
 }
 
 // Counting-sort scatter into cell slots in arrival order, with the sort key
@@ -742,6 +765,7 @@ __global__ void __launch_bounds__(1024) k_cell_one(Dev D) {
 __global__ void __launch_bounds__(256) k_scatter(Dev D) {
   if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
   int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) rebuild_bookkeeping(D);  // read by no kernel before the step close
   if (t < D.nf) {
     int s = D.f_scene[t];
     if (!D.st[s].need_rebuild) return;
@@ -1519,6 +1543,17 @@ __global__ void k_step_close(Dev D) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= D.n_scenes) return;
   close_scene(D, s, D.st[s].vmax_next, nullptr);
+}
+
+// The same close, one thread per scene, then (all cells in one tile) the
+// cell scan of the rebuilds it has just set, whose particles the step-end
+// reduction binned: the next step starts with the scatter.
+__global__ void __launch_bounds__(1024) k_step_close_scan(Dev D) {
+  __shared__ TileLds L;
+  const int s = threadIdx.x;
+  if (s < D.n_scenes) close_scene(D, s, D.st[s].vmax_next, nullptr);
+  __syncthreads();
+  scan_one_tile(D, L);
 }
 
 // kappa solid sub-steps of the position-based Verlet scheme (Section 3.3,
@@ -2707,11 +2742,15 @@ static inline dim3 grid_for(long long threads, int block) {
   return dim3((unsigned)std::max<long long>(1, (threads + block - 1) / block));
 }
 
+// all cells in one tile and at most one close thread per scene in a block:
+// the step close also scans the cells of the rebuilds it sets
+static inline bool step_end_scan(const Dev &D) { return D.ncell <= kCellTile && D.n_scenes <= 1024; }
+
 void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool with_bin) {
   if (with_bin) launch_bin(D, st);
   const int ntiles = (D.ncell + kCellTile - 1) / kCellTile;
   if (ntiles == 1) {
-    hipLaunchKernelGGL(k_cell_one, dim3(1), dim3(1024), 0, st, D);
+    if (with_bin || !step_end_scan(D)) hipLaunchKernelGGL(k_cell_one, dim3(1), dim3(1024), 0, st, D);
   } else {
     hipLaunchKernelGGL(k_cell_sum, dim3(ntiles), dim3(1024), 0, st, D);
     hipLaunchKernelGGL(k_cell_prefix, dim3(1), dim3(1024), 0, st, D, ntiles);
@@ -2812,7 +2851,8 @@ void launch_step_end(const Dev &D, hipStream_t st) {
   int fb = (D.nf + 256 * kReduceItems - 1) / (256 * kReduceItems), sb = (D.ns + 255) / 256;
   int bb = (D.nf + D.nb + 255) / 256;
   if (bb + fb + sb > 0) LAUNCH_DIM(D.dim, k_step_reduce, dim3(bb + fb + sb), dim3(256), st, D, bb, fb);
-  hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
+  if (step_end_scan(D)) hipLaunchKernelGGL(k_step_close_scan, dim3(1), dim3(1024), 0, st, D);
+  else hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
 }
 
 int solid_lds_bytes_per_particle(int dim) { return (solid_pb_record(dim) + dim) * (int)sizeof(double); }
@@ -2849,6 +2889,11 @@ void launch_unbin(const Dev &D, int s, hipStream_t st) {
 
 void launch_bin(const Dev &D, hipStream_t st) {
   if (D.nf + D.nb > 0) LAUNCH_DIM(D.dim, k_bin, grid_for(D.nf + D.nb, 256), dim3(256), st, D);
+}
+
+void launch_prebin(const Dev &D, hipStream_t st) {
+  launch_bin(D, st);
+  if (step_end_scan(D)) hipLaunchKernelGGL(k_cell_one, dim3(1), dim3(1024), 0, st, D);
 }
 
 }  // namespace mrsph

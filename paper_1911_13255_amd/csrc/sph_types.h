@@ -52,7 +52,7 @@ struct ScenePar {
 struct SceneState {
   double t, dt_ac, dt_ad, dt_s, adv_accum;
   int kappa, need_rebuild, err;
-  int binned;  // 1: the pending rebuild's particles were binned at the end of the last step
+  int binned;  // pending rebuild prepared at the end of the last step: 1 particles binned, 2 cells scanned too
   unsigned int vmax_prev, vmax_next;  // max fluid speed (float bits): step start / being reduced
   unsigned int smax_v, smax_a;        // max solid speed and acceleration (float bits) being reduced
   unsigned int send_v, send_a;        // single step: the same at the step end, for the next step's size
