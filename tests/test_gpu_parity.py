@@ -220,6 +220,17 @@ def test_host_writes_after_a_step_end_binning(gpu, path):
         step()
     compare(sim, o, label=f"{path} after the withdrawn rebuild")
     assert sim.counters(0)["rebuilds"] == o.counters()["rebuilds"]
+    # a velocity write (a forced rebuild of its own) on a scene whose cells
+    # the step close has already scanned
+    until_rebuild_due()
+    v = o.get(O.F_V) * 0.9
+    o.set(O.F_V, v)
+    sim.write(sph.F_V, v)
+    note(f"{path}: velocity written after a step-end scan")
+    for k in range(3):
+        step()
+    compare(sim, o, label=f"{path} velocity write")
+    assert sim.counters(0)["rebuilds"] == o.counters()["rebuilds"]
     sim.sync()
     sim.close()
 
