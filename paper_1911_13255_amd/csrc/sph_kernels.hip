@@ -275,7 +275,10 @@ __global__ void k_init_solid(Dev D, int s, const double *x, const double *v, int
     D.s_H[k * NS + a] = 0.0;
     D.s_dF[k * NS + a] = 0.0;
   }
-  for (int k = 0; k < 9; ++k) D.s_PB[pb_at(D, a, k)] = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    D.s_PB[pb_at(D, a, k)] = 0.0;
+    D.s_PBf[pb_at(D, a, k)] = 0.0f;
+  }
   D.s_bslot[a] = -1;
   D.s_blin[a] = 0;
 }
@@ -1655,7 +1658,10 @@ __device__ __forceinline__ void solid_first_half(const Dev &D, const ScenePar &P
   double J;
   solid_PB<DIM, double>(P.material, H, B, (double)P.mu, (double)P.lam, PB, J);
   if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
-  for (int k = 0; k < DIM * DIM; ++k) D.s_PB[pb_at(D, a, k)] = PB[k];
+  for (int k = 0; k < DIM * DIM; ++k) {
+    D.s_PB[pb_at(D, a, k)] = PB[k];
+    D.s_PBf[pb_at(D, a, k)] = (float)PB[k];
+  }
 }
 
 // First half of sub-step 0 (clamp particles: zero stress).
@@ -1667,7 +1673,10 @@ __global__ void __launch_bounds__(256) k_solid_first(Dev D) {
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
   if (a - P.s_begin >= P.s_count - P.s_nclamp) {
-    for (int k = 0; k < DIM * DIM; ++k) D.s_PB[pb_at(D, a, k)] = 0.0;
+    for (int k = 0; k < DIM * DIM; ++k) {
+      D.s_PB[pb_at(D, a, k)] = 0.0;
+      D.s_PBf[pb_at(D, a, k)] = 0.0f;
+    }
     return;
   }
   solid_first_half<DIM>(D, P, S, a, 0.5 * S.dt_ac / S.kappa);
@@ -1684,23 +1693,26 @@ __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
   if (sub >= S.kappa || a - P.s_begin >= P.s_count - P.s_nclamp) return;
   const int NS = D.ns;
   const double del = S.dt_ac / S.kappa;
-  double PBa[9];
-  for (int k = 0; k < DIM * DIM; ++k) PBa[k] = D.s_PB[pb_at(D, a, k)];
+  // sum_b (P_a B_a + P_b B_b) g_ab = P_a B_a sum_b g_ab + sum_b P_b B_b g_ab:
+  // the own term in FP64, the neighbours' P B gathered in FP32 (the gathers
+  // bound this pass; their rounding reaches the acceleration scaled by about
+  // the ratio of the stress length scale to h)
   double acc[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < DIM; ++i)
+    for (int j = 0; j < DIM; ++j) acc[i] += D.s_PB[pb_at(D, a, i * DIM + j)] * D.s_gsum[j * NS + a];
+  float accn[3] = {0.0f, 0.0f, 0.0f};
   int cnt = D.s_cnt[a];
 #pragma unroll 4
   for (int q = 0; q < cnt; ++q) {
     float4 g = D.s_nbr[(size_t)q * NS + a];
     int b = __float_as_int(g.w);
-    double gv[3] = {g.x, g.y, g.z};
-    double PBb[9];
-    for (int k = 0; k < DIM * DIM; ++k) PBb[k] = D.s_PB[pb_at(D, b, k)];
-    for (int i = 0; i < DIM; ++i) {
-      double sum = 0.0;
-      for (int j = 0; j < DIM; ++j) sum += (PBa[i * DIM + j] + PBb[i * DIM + j]) * gv[j];
-      acc[i] += sum;
-    }
+    float gv[3] = {g.x, g.y, g.z};
+    float PBb[9];
+    for (int k = 0; k < DIM * DIM; ++k) PBb[k] = D.s_PBf[pb_at(D, b, k)];
+    for (int i = 0; i < DIM; ++i)
+      for (int j = 0; j < DIM; ++j) accn[i] += PBb[i * DIM + j] * gv[j];
   }
+  for (int i = 0; i < DIM; ++i) acc[i] += (double)accn[i];
   const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
   double vn[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < DIM; ++k) {

@@ -128,6 +128,7 @@ struct Dev {
   double *s_u, *s_v, *s_du, *s_dv;  // integration state in FP64 (displacement, velocity, step increments)
   double *s_H, *s_dF, *s_B;        // H = F - I, dF/dt, B in FP64 (d*d components)
   double *s_PB;                    // P B in FP64, component-major [k * ns + a] (9 components allocated)
+  float *s_PBf;                    // the same rounded to FP32: what the streamed momentum pass gathers
   float *s_a, *s_fF, *s_vbar, *s_abar, *s_n0, *s_n;
   float *s_fFp;                    // pressure part of the coupling force
   int *s_cpl_cnt;                  // fluid neighbours of each free solid particle (set at rebuilds)
