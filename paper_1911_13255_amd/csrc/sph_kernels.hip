@@ -478,7 +478,10 @@ __global__ void k_refresh_vmax(Dev D) {
 // A rebuild runs for the scenes whose need_rebuild flag is set (set at the end
 // of the acoustic step that closes an advection step, or by a state write);
 // the kernels below test the flag and exit at once otherwise, and the
-// step-close kernel at the end of the step clears it.
+// step-close kernel at the end of the step clears it.  Stages of a rebuild the
+// method decides run ahead, in kernels that run anyway: the binning in the
+// step-end reduction and, where the cells form one tile, the cell scan in the
+// step close; the coupling lists are put in order by the force launch.
 
 // The advection step ends with the acoustic step that is closing: the same
 // test, on the same values, as close_scene's.
