@@ -486,7 +486,7 @@ int enqueue_step(sph_ctx *ctx, bool fork) {
     if (hipEventRecord(ctx->ev_fork, ctx->stream) != hipSuccess ||
         hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0) != hipSuccess)
       return SPH_E_HIP;
-    launch_fluid_continuity(ctx->D, ctx->cfg, ctx->side);
+    launch_fluid_continuity(ctx->D, ctx->cfg, ctx->side, false);
     launch_couple(ctx->D, ctx->cfg, ctx->stream);
     enqueue_solid_reg(ctx);
     if (hipEventRecord(ctx->ev_join, ctx->side) != hipSuccess ||
@@ -495,8 +495,7 @@ int enqueue_step(sph_ctx *ctx, bool fork) {
     launch_step_end(ctx->D, ctx->stream);
     return check_launch(ctx, "acoustic step");
   }
-  launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream);
-  launch_couple(ctx->D, ctx->cfg, ctx->stream);
+  if (!launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream, true)) launch_couple(ctx->D, ctx->cfg, ctx->stream);
   int rc = enqueue_solid(ctx);
   if (rc != SPH_OK) return rc;
   launch_step_end(ctx->D, ctx->stream);
@@ -691,7 +690,7 @@ int neighbor_build(sph_ctx *ctx) {
 int fluid_step(sph_ctx *ctx) {
   if (!ctx) return SPH_E_ORDER;
   launch_fluid_force(ctx->D, ctx->cfg, ctx->stream);
-  launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream);
+  launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream, false);
   return check_launch(ctx, "fluid_step");
 }
 
@@ -961,7 +960,7 @@ int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms) {
   auto enqueue_one = [&]() -> int {
     switch (kernel) {
     case SPH_K_FLUID_FORCE: launch_fluid_force(ctx->D, ctx->cfg, st); break;
-    case SPH_K_CONTINUITY: launch_fluid_continuity(ctx->D, ctx->cfg, st); break;
+    case SPH_K_CONTINUITY: launch_fluid_continuity(ctx->D, ctx->cfg, st, false); break;
     case SPH_K_COUPLE: launch_couple(ctx->D, ctx->cfg, st); break;
     case SPH_K_SOLID: return enqueue_solid(ctx);
     case SPH_K_REBUILD:

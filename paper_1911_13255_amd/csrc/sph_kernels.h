@@ -52,7 +52,9 @@ void launch_bin(const Dev &D, hipStream_t st);
 void launch_prebin(const Dev &D, hipStream_t st);
 void launch_unbin(const Dev &D, int s, hipStream_t st);
 void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
-void launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
+// with_couple: the coupling on the solid runs in leading blocks of the same
+// launch where the shapes allow; returns true when it did
+bool launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool with_couple);
 void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 void launch_step_end(const Dev &D, hipStream_t st);

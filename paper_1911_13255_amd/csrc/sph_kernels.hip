@@ -1342,8 +1342,7 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
 // h_F): the exact negatives of the fluid-side pair terms, from the same
 // mid-point snapshot (v^n, eps^{n+1/2}, p^{n+1/2}) and the same frozen geometry.
 template <int DIM, int LPP>
-__global__ void __launch_bounds__(256) k_couple(Dev D) {
-  int g = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void couple_entry(const Dev &D, int g) {
   int a = g / LPP, q = g % LPP;
   bool active = a < D.ns;
   int aa = active ? a : 0;
@@ -1388,6 +1387,11 @@ __global__ void __launch_bounds__(256) k_couple(Dev D) {
     }
 }
 
+template <int DIM, int LPP>
+__global__ void __launch_bounds__(256) k_couple(Dev D) {
+  couple_entry<DIM, LPP>(D, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Fluid acoustic step, second part (Section 3.1 continuity with the Riemann
 // interface velocity; Section 3.3, Eq. verlet-first-final): density rate with
 // v^{n+1} at the mid-point density, plus rho_i sum_a V_a (v_i - vbar_a).grad W
@@ -1395,7 +1399,14 @@ __global__ void __launch_bounds__(256) k_couple(Dev D) {
 // buffer; max speed for the next acoustic step.
 template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
-  int g = particle_index();
+  // in a graph step the coupling on the solid, which reads only the force
+  // pass's snapshot, runs in the leading blocks (a multiple of 8, so the XCD
+  // of a continuity block is still its index modulo 8)
+  if ((int)blockIdx.x < D.couple_blocks) {
+    couple_entry<DIM, LPP>(D, blockIdx.x * blockDim.x + threadIdx.x);
+    return;
+  }
+  int g = xcd_block(blockIdx.x - D.couple_blocks, gridDim.x - D.couple_blocks) * blockDim.x + threadIdx.x;
   int i = g / LPP, q = g % LPP;
   bool active = i < D.nf;
   int ii = active ? i : 0;
@@ -2801,10 +2812,18 @@ void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
   }
 }
 
-void launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
-  if (D.nf > 0)
-    LAUNCH_LPP(k_fluid_continuity, cfg.lpp_cont, D.dim, grid_for((long long)D.nf * cfg.lpp_cont, cfg.block_pair),
-               dim3(cfg.block_pair), 0, st, D);
+bool launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool with_couple) {
+  if (D.nf == 0) return false;
+  Dev Dc = D;
+  Dc.couple_blocks = 0;
+  if (with_couple && D.ns > 0 && cfg.lpp_couple == cfg.lpp_cont) {
+    const long long threads = (long long)D.ns * cfg.lpp_cont;
+    Dc.couple_blocks = (int)((threads + cfg.block_pair - 1) / cfg.block_pair + 7) / 8 * 8;
+  }
+  dim3 grid = grid_for((long long)D.nf * cfg.lpp_cont, cfg.block_pair);
+  grid.x += Dc.couple_blocks;
+  LAUNCH_LPP(k_fluid_continuity, cfg.lpp_cont, D.dim, grid, dim3(cfg.block_pair), 0, st, Dc);
+  return Dc.couple_blocks > 0;
 }
 
 void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {

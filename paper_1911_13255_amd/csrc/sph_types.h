@@ -92,6 +92,7 @@ struct Dev {
   int fluid_prep;  // 1: k_fluid_prep forms the mid-point snapshot before the force pass
   int any_single;  // 1: some scene takes one shared step (step-end solid maxima needed)
   int sort_blocks; // leading blocks of the force launch that order the coupling lists
+  int couple_blocks; // leading blocks of the continuity launch that run the coupling on the solid
   unsigned *f_nbl;  // fluid neighbours (capf entries per particle)
   unsigned *f_bnl;  // boundary neighbours: walls and free solid (capb per particle)
   int2 *f_rowlen;  // used length of each particle's two rows
