@@ -444,18 +444,21 @@ int read_states(sph_ctx *ctx, std::vector<SceneState> &st) {
 // the host to size the pass loop (this synchronises the stream).
 // Register-resident sub-steps, preceded by the learned step when a surrogate
 // is set (scenes it is accepted for skip the sub-steps).
-void enqueue_solid_reg(sph_ctx *ctx) {
+// step_end: the solid launch also does the step-end reduction's work
+void enqueue_solid_reg(sph_ctx *ctx, bool step_end) {
   if (ctx->net && ctx->D.sur_thr > 0.0f) {
     launch_sur_features(ctx->D, ctx->D.sur_stats, ctx->D.sur_x, ctx->stream);
     mlp_launch_forward(ctx->net->D, ctx->D.sur_x, ctx->D.sur_y, ctx->D.ns, false, ctx->stream);
     launch_sur_predict(ctx->D, ctx->stream);
   }
-  launch_solid(ctx->D, ctx->cfg, ctx->stream);
+  launch_solid(ctx->D, ctx->cfg, ctx->stream, step_end);
 }
 
-int enqueue_solid(sph_ctx *ctx) {
+// step_end as above; it applies to the register-resident form only (the
+// streamed passes leave the step end to its own launch)
+int enqueue_solid(sph_ctx *ctx, bool step_end) {
   if (ctx->cfg.solid_ppt > 0) {
-    enqueue_solid_reg(ctx);
+    enqueue_solid_reg(ctx, step_end);
   } else if (ctx->D.ns > 0) {
     launch_solid_dt(ctx->D, ctx->stream);
     std::vector<SceneState> st(ctx->n_scenes);
@@ -488,17 +491,17 @@ int enqueue_step(sph_ctx *ctx, bool fork) {
       return SPH_E_HIP;
     launch_fluid_continuity(ctx->D, ctx->cfg, ctx->side, false);
     launch_couple(ctx->D, ctx->cfg, ctx->stream);
-    enqueue_solid_reg(ctx);
+    enqueue_solid_reg(ctx, false);
     if (hipEventRecord(ctx->ev_join, ctx->side) != hipSuccess ||
         hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0) != hipSuccess)
       return SPH_E_HIP;
-    launch_step_end(ctx->D, ctx->stream);
+    launch_step_end(ctx->D, ctx->stream, false);
     return check_launch(ctx, "acoustic step");
   }
   if (!launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream, true)) launch_couple(ctx->D, ctx->cfg, ctx->stream);
-  int rc = enqueue_solid(ctx);
+  int rc = enqueue_solid(ctx, true);
   if (rc != SPH_OK) return rc;
-  launch_step_end(ctx->D, ctx->stream);
+  launch_step_end(ctx->D, ctx->stream, ctx->cfg.solid_ppt > 0);
   return check_launch(ctx, "acoustic step");
 }
 
@@ -702,9 +705,9 @@ int couple(sph_ctx *ctx) {
 
 int solid_substeps(sph_ctx *ctx) {
   if (!ctx) return SPH_E_ORDER;
-  int rc = enqueue_solid(ctx);
+  int rc = enqueue_solid(ctx, true);
   if (rc != SPH_OK) return rc;
-  launch_step_end(ctx->D, ctx->stream);
+  launch_step_end(ctx->D, ctx->stream, ctx->cfg.solid_ppt > 0);
   return check_launch(ctx, "solid_substeps");
 }
 
@@ -962,7 +965,7 @@ int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms) {
     case SPH_K_FLUID_FORCE: launch_fluid_force(ctx->D, ctx->cfg, st); break;
     case SPH_K_CONTINUITY: launch_fluid_continuity(ctx->D, ctx->cfg, st, false); break;
     case SPH_K_COUPLE: launch_couple(ctx->D, ctx->cfg, st); break;
-    case SPH_K_SOLID: return enqueue_solid(ctx);
+    case SPH_K_SOLID: return enqueue_solid(ctx, false);
     case SPH_K_REBUILD:
       for (int s = 0; s < ctx->n_scenes; ++s) launch_set_rebuild(ctx->D, s, st);
       launch_rebuild(ctx->D, ctx->cfg, st, true);

@@ -56,8 +56,10 @@ void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 // launch where the shapes allow; returns true when it did
 bool launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool with_couple);
 void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
-void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
-void launch_step_end(const Dev &D, hipStream_t st);
+// step_end: the launch also does the step-end reduction's work (serial steps)
+void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_end);
+// reduced: the solid launch already did the step-end reduction's work
+void launch_step_end(const Dev &D, hipStream_t st, bool reduced);
 void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t st);
 void launch_sur_targets(const Dev &D, const float *xraw, float *t, hipStream_t st);
 void launch_sur_predict(const Dev &D, hipStream_t st);

@@ -492,13 +492,17 @@ __device__ __forceinline__ bool rebuilds_next(const SceneState &S) { return S.ad
 // copy of the fluid state by old index.  at_step_end: binned by the step-end
 // kernel for the rebuild that the closing step is about to set; otherwise at
 // the start of a step for a rebuild set from the host (scenes not binned yet).
+// which entries a bin_entry call takes
+enum { kBinFluid = 1, kBinWalls = 2, kBinSolid = 4, kBinAll = 7 };
+
 template <int DIM>
-__device__ void bin_entry(const Dev &D, int t, bool at_step_end) {
+__device__ void bin_entry(const Dev &D, int t, bool at_step_end, int which = kBinAll) {
   auto due = [&](int s) {
     const SceneState &S = D.st[s];
     return at_step_end ? rebuilds_next(S) : (S.need_rebuild && !S.binned);
   };
   if (t < D.nf) {
+    if (!(which & kBinFluid)) return;
     int i = t;
     int s = D.f_scene[i];
     if (!due(s)) return;
@@ -524,6 +528,7 @@ __device__ void bin_entry(const Dev &D, int t, bool at_step_end) {
   if (!due(s)) return;
   const ScenePar &P = D.par[s];
   int local = q - P.b_begin;
+  if (!(which & (local < P.w_count ? kBinWalls : kBinSolid))) return;
   int c[3];
   double off[3] = {0.0, 0.0, 0.0};
   int NS = D.ns;
@@ -1844,6 +1849,8 @@ __device__ void hand_over(const Dev &D, int a) {
   hand_over_values<DIM>(D, P, a, det_F<DIM>(H), vbar, abar);
 }
 
+__device__ void fluid_step_end(const Dev &D, int blk, float *shm, unsigned long long (*shc)[16]);
+
 // The same sub-steps for 2D scenes whose free solid fits the block with at
 // most PPT particles per thread: each thread keeps its particles' own state
 // (H, dF/dt, u in FP64; B and the step increments in FP32) in registers for
@@ -1859,7 +1866,17 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   __shared__ float red[2][16];
   __shared__ int kap_sh;
   __shared__ double del_sh;
+  __shared__ unsigned long long end_c[3][16];
   constexpr int D2 = DIM * DIM;
+  if ((int)blockIdx.x >= D.n_scenes) {
+    // blocks beside the scenes' solid blocks end the step of the fluid: its
+    // speed and pair-count reductions, and the binning of fluid and walls for
+    // a rebuild that the closing step sets
+    const int b = blockIdx.x - D.n_scenes;
+    if (b < D.end_fluid_blocks) fluid_step_end(D, b, red[0], end_c);
+    else bin_entry<DIM>(D, (b - D.end_fluid_blocks) * blockDim.x + threadIdx.x, true, kBinFluid | kBinWalls);
+    return;
+  }
   int s = blockIdx.x;
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
@@ -1872,7 +1889,37 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   // one LDS record per particle: a neighbour's P B (or v) arrives in wide reads
   auto PI = [&](int l, int k) { return (int)__umul24((unsigned)l, (unsigned)PR) + k; };
   auto VI = [&](int l, int k) { return l * DIM + k; };
-  if (S.sur == 1) return;  // the surrogate's step was accepted for this scene
+  if (S.sur == 1) {
+    // the surrogate's step was accepted for this scene: only the step end of
+    // its solid remains, from the stored state
+    if (D.solid_step_end) {
+      const bool rb = rebuilds_next(S);
+      float sv = 0.0f, sa = 0.0f;
+      for (int l = t; l < nfree; l += T) {
+        const int a = base + l;
+        hand_over<DIM>(D, a);
+        if (rb) bin_entry<DIM>(D, D.nf + P.b_begin + P.w_count + l, true, kBinSolid);
+        float v2 = 0.0f, a2 = 0.0f;
+        for (int k = 0; k < DIM; ++k) {
+          const float v = (float)D.s_v[k * NS + a], q = D.s_a[k * NS + a];
+          v2 += v * v;
+          a2 += q * q;
+        }
+        sv = fmaxf(sv, sqrtf(v2));
+        sa = fmaxf(sa, sqrtf(a2));
+      }
+      if (P.single_step) {
+        auto fmx = [](float x, float y) { return fmaxf(x, y); };
+        sv = block_reduce(sv, fmx, red[0]);
+        sa = block_reduce(sa, fmx, red[1]);
+        if (t == 0) {
+          S.send_v = __float_as_uint(sv);
+          S.send_a = __float_as_uint(sa);
+        }
+      }
+    }
+    return;
+  }
   double dt_ac = S.dt_ac;
   // own particles and their state
   int la[PPT];
@@ -2111,8 +2158,12 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
     __syncthreads();
   }
   if (bad_J) atomicOr(&S.err, (int)ERR_JACOBIAN);
-  // write back, time averages, hand-over to the boundary particles
+  // write back, time averages; where this launch ends the step, the
+  // hand-over to the boundary particles, the binning of the solid for a
+  // rebuild the closing step sets and the single-step maxima
   const double inv_dt = 1.0 / dt_ac;
+  const bool step_end = D.solid_step_end != 0, rb = step_end && rebuilds_next(S);
+  float end_v = 0.0f, end_a = 0.0f;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     if (!own[p]) continue;
@@ -2137,6 +2188,28 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
       bad |= !isfinite(vbar[k]) || !isfinite(abar[k]);
     }
     if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
+    if (step_end) {
+      hand_over_values<DIM>(D, P, a, det_F<DIM>(H[p]), vbar, abar);
+      if (rb) bin_entry<DIM>(D, D.nf + P.b_begin + P.w_count + l, true, kBinSolid);
+      float v2 = 0.0f, a2 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const float v = (float)Vx[VI(l, k)];
+        v2 += v * v;
+        a2 += acc_last[p][k] * acc_last[p][k];
+      }
+      end_v = fmaxf(end_v, sqrtf(v2));
+      end_a = fmaxf(end_a, sqrtf(a2));
+    }
+  }
+  if (step_end && P.single_step) {
+    auto fmx = [](float x, float y) { return fmaxf(x, y); };
+    end_v = block_reduce(end_v, fmx, red[0]);
+    end_a = block_reduce(end_a, fmx, red[1]);
+    if (t == 0) {
+      S.send_v = __float_as_uint(end_v);
+      S.send_a = __float_as_uint(end_a);
+    }
   }
 }
 
@@ -2183,6 +2256,45 @@ __device__ void single_step_maxima(const Dev &D, int a) {
   }
 }
 
+// Step end of the fluid, block blk of the fluid range: max speed for the
+// next acoustic step and, after a rebuild, the pair counts, kReduceItems
+// particles per thread and one reduction and atomic per scene present in the
+// block (scenes own contiguous ranges).  Any block size that is a multiple of
+// 64 (at most 1024).
+__device__ void fluid_step_end(const Dev &D, int blk, float *shm, unsigned long long (*shc)[16]) {
+  const int span = blockDim.x * kReduceItems;
+  const int i0 = blk * span, i1 = min(D.nf, i0 + span);
+  const int s0 = D.f_scene[i0], s1 = D.f_scene[i1 - 1];
+  auto fmx = [](float x, float y) { return fmaxf(x, y); };
+  auto add = [](unsigned long long x, unsigned long long y) { return x + y; };
+  for (int s = s0; s <= s1; ++s) {
+    SceneState &S = D.st[s];
+    const bool rebuilt = S.need_rebuild != 0;
+    float m = 0.0f;  // fmaxf drops a NaN speed; the continuity pass flags it
+    unsigned long long c[3] = {0ull, 0ull, 0ull};
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      if (D.f_scene[i] != s) continue;
+      m = fmaxf(m, D.f_speed[i]);
+      if (rebuilt) {
+        int4 n = D.f_nnb[i];
+        c[0] += (unsigned long long)n.x;
+        c[1] += (unsigned long long)n.y;
+        c[2] += (unsigned long long)n.z;
+      }
+    }
+    m = block_reduce(m, fmx, shm);
+    if (threadIdx.x == 0) atomic_max_pos(&S.vmax_next, m);
+    if (rebuilt) {
+      for (int k = 0; k < 3; ++k) c[k] = block_reduce(c[k], add, shc[k]);
+      if (threadIdx.x == 0) {
+        atomicAdd(&S.acc_ff, c[0]);
+        atomicAdd(&S.acc_fw, c[1]);
+        atomicAdd(&S.acc_fs, c[2]);
+      }
+    }
+  }
+}
+
 // End of an acoustic step over all particles, before k_step_close.  Fluid
 // blocks: max fluid speed for the next acoustic step and, after a rebuild,
 // the pair counts, folded into the scene's accumulators with one atomic per
@@ -2204,45 +2316,14 @@ __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int bin_blocks, int 
   }
   const int blk = blockIdx.x - bin_blocks;
   if (blk < fluid_blocks) {
-    // kReduceItems particles per thread; one reduction and atomic per scene
-    // present in the block (scenes own contiguous ranges)
-    const int span = blockDim.x * kReduceItems;
-    const int i0 = blk * span, i1 = min(D.nf, i0 + span);
-    const int s0 = D.f_scene[i0], s1 = D.f_scene[i1 - 1];
-    auto fmx = [](float x, float y) { return fmaxf(x, y); };
-    auto add = [](unsigned long long x, unsigned long long y) { return x + y; };
-    for (int s = s0; s <= s1; ++s) {
-      SceneState &S = D.st[s];
-      const bool rebuilt = S.need_rebuild != 0;
-      float m = 0.0f;  // fmaxf drops a NaN speed; the continuity pass flags it
-      unsigned long long c[3] = {0ull, 0ull, 0ull};
-      for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        if (D.f_scene[i] != s) continue;
-        m = fmaxf(m, D.f_speed[i]);
-        if (rebuilt) {
-          int4 n = D.f_nnb[i];
-          c[0] += (unsigned long long)n.x;
-          c[1] += (unsigned long long)n.y;
-          c[2] += (unsigned long long)n.z;
-        }
-      }
-      m = block_reduce(m, fmx, shm);
-      if (threadIdx.x == 0) atomic_max_pos(&S.vmax_next, m);
-      if (rebuilt) {
-        for (int k = 0; k < 3; ++k) c[k] = block_reduce(c[k], add, shc[k]);
-        if (threadIdx.x == 0) {
-          atomicAdd(&S.acc_ff, c[0]);
-          atomicAdd(&S.acc_fw, c[1]);
-          atomicAdd(&S.acc_fs, c[2]);
-        }
-      }
-    }
+    fluid_step_end(D, blk, shm, shc);
     return;
   }
   const int a = (blk - fluid_blocks) * blockDim.x + threadIdx.x;
   hand_over<DIM>(D, a);
   if (D.any_single) single_step_maxima<DIM>(D, a);
 }
+
 
 // ------------------------------------------------------------------ surrogate
 //
@@ -2839,9 +2920,18 @@ void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
     else hipLaunchKernelGGL((k_solid_reg<2, 4>), __VA_ARGS__);                            \
   } while (0)
 
-void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
+void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_end) {
   size_t bytes = (size_t)cfg.solid_lds_n * solid_lds_bytes_per_particle(D.dim);
-  LAUNCH_SOLID_REG(cfg.solid_ppt, dim3(D.n_scenes), dim3(cfg.block_solid), bytes, st, D, cfg.solid_lds_n);
+  Dev Ds = D;
+  Ds.solid_step_end = step_end ? 1 : 0;
+  Ds.end_fluid_blocks = 0;
+  int extra = 0;
+  if (step_end) {
+    const int T = cfg.block_solid;
+    Ds.end_fluid_blocks = D.nf > 0 ? (D.nf + T * kReduceItems - 1) / (T * kReduceItems) : 0;
+    extra = Ds.end_fluid_blocks + (D.nf + D.nb + T - 1) / T;
+  }
+  LAUNCH_SOLID_REG(cfg.solid_ppt, dim3(D.n_scenes + extra), dim3(cfg.block_solid), bytes, st, Ds, cfg.solid_lds_n);
 }
 
 void launch_solid_dt(const Dev &D, hipStream_t st) {
@@ -2881,10 +2971,10 @@ void launch_sur_predict(const Dev &D, hipStream_t st) {
   hipLaunchKernelGGL(k_sur_commit, grid_for(D.ns, 256), dim3(256), 0, st, D);
 }
 
-void launch_step_end(const Dev &D, hipStream_t st) {
+void launch_step_end(const Dev &D, hipStream_t st, bool reduced) {
   int fb = (D.nf + 256 * kReduceItems - 1) / (256 * kReduceItems), sb = (D.ns + 255) / 256;
   int bb = (D.nf + D.nb + 255) / 256;
-  if (bb + fb + sb > 0) LAUNCH_DIM(D.dim, k_step_reduce, dim3(bb + fb + sb), dim3(256), st, D, bb, fb);
+  if (!reduced && bb + fb + sb > 0) LAUNCH_DIM(D.dim, k_step_reduce, dim3(bb + fb + sb), dim3(256), st, D, bb, fb);
   if (step_end_scan(D)) hipLaunchKernelGGL(k_step_close_scan, dim3(1), dim3(1024), 0, st, D);
   else hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
 }

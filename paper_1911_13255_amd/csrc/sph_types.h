@@ -93,6 +93,8 @@ struct Dev {
   int any_single;  // 1: some scene takes one shared step (step-end solid maxima needed)
   int sort_blocks; // leading blocks of the force launch that order the coupling lists
   int couple_blocks; // leading blocks of the continuity launch that run the coupling on the solid
+  int solid_step_end;    // 1: the block-resident solid launch also ends the step (hand-over, binning, reductions)
+  int end_fluid_blocks;  // its blocks beside the scenes' that reduce the fluid's step end
   unsigned *f_nbl;  // fluid neighbours (capf entries per particle)
   unsigned *f_bnl;  // boundary neighbours: walls and free solid (capb per particle)
   int2 *f_rowlen;  // used length of each particle's two rows
