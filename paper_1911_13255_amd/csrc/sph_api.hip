@@ -379,6 +379,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   double **dten[] = {&D.s_H, &D.s_dF, &D.s_B, &D.s_PB};
   for (double **p : dten) take(*p, 9 * ns);
   take(D.s_PBf, 9 * ns);
+  take(D.s_vf, ns);
   float **vec[] = {&D.s_a, &D.s_fF, &D.s_vbar, &D.s_abar, &D.s_n0, &D.s_n, &D.s_fFp,
                    &D.sur_vbar, &D.sur_abar, &D.sur_amid};
   for (float **p : vec) take(*p, 3 * ns);

@@ -1696,6 +1696,8 @@ __global__ void __launch_bounds__(256) k_solid_first(Dev D) {
       D.s_PB[pb_at(D, a, k)] = 0.0;
       D.s_PBf[pb_at(D, a, k)] = 0.0f;
     }
+    const int NS = D.ns;
+    D.s_vf[a] = make_float4((float)D.s_v[a], (float)D.s_v[NS + a], DIM == 3 ? (float)D.s_v[2 * NS + a] : 0.0f, 0.0f);
     return;
   }
   solid_first_half<DIM>(D, P, S, a, 0.5 * S.dt_ac / S.kappa);
@@ -1742,6 +1744,7 @@ __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
     D.s_v[k * NS + a] = vn[k];
     D.s_dv[k * NS + a] += dv;
   }
+  D.s_vf[a] = make_float4((float)vn[0], (float)vn[1], (float)vn[2], 0.0f);
 }
 
 // Deformation rate with the new velocity and second half of sub-step `sub`;
@@ -1758,19 +1761,27 @@ __global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
   const double hd = 0.5 * S.dt_ac / S.kappa;
   double va[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < DIM; ++k) va[k] = D.s_v[k * NS + a];
-  double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // the neighbours' v gathered as one FP32 record each (the gathers bound
+  // this pass); the differences v_b - v_a are taken between FP32-rounded
+  // values, so a rigid translation still gives exactly zero, and summed in
+  // FP32
+  float vaf[3] = {(float)va[0], (float)va[1], (float)va[2]};
+  float Gn[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   int cnt = D.s_cnt[a];
 #pragma unroll 4
   for (int q = 0; q < cnt; ++q) {
     float4 g = D.s_nbr[(size_t)q * NS + a];
     int b = __float_as_int(g.w);
-    double gv[3] = {g.x, g.y, g.z};
-    double vbv[3] = {D.s_v[b], D.s_v[NS + b], DIM == 3 ? D.s_v[2 * NS + b] : 0.0};
+    float gv[3] = {g.x, g.y, g.z};
+    float4 vb = D.s_vf[b];
+    float vbv[3] = {vb.x, vb.y, vb.z};
     for (int i = 0; i < DIM; ++i) {
-      double dvi = vbv[i] - va[i];
-      for (int j = 0; j < DIM; ++j) G[i * DIM + j] += dvi * gv[j];
+      float dvi = vbv[i] - vaf[i];
+      for (int j = 0; j < DIM; ++j) Gn[i * DIM + j] += dvi * gv[j];
     }
   }
+  double G[9];
+  for (int k = 0; k < DIM * DIM; ++k) G[k] = (double)Gn[k];
   // (v_b - v_a) (x) (B grad W) summed = G B^T
   for (int i = 0; i < DIM; ++i)
     for (int j = 0; j < DIM; ++j) {

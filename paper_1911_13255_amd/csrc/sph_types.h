@@ -132,6 +132,9 @@ struct Dev {
   double *s_H, *s_dF, *s_B;        // H = F - I, dF/dt, B in FP64 (d*d components)
   double *s_PB;                    // P B in FP64, component-major [k * ns + a] (9 components allocated)
   float *s_PBf;                    // the same rounded to FP32: what the streamed momentum pass gathers
+  float4 *s_vf;                    // v rounded to FP32, one 16-byte record per particle: what the streamed
+                                   // rate pass gathers (free particles: written by the momentum pass of the
+                                   // same sub-step; clamped ones: by the first pass of the step)
   float *s_a, *s_fF, *s_vbar, *s_abar, *s_n0, *s_n;
   float *s_fFp;                    // pressure part of the coupling force
   int *s_cpl_cnt;                  // fluid neighbours of each free solid particle (set at rebuilds)
