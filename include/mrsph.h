@@ -244,6 +244,18 @@ int sph_surrogate_counters(sph_ctx *ctx, int scene, unsigned long long *out);
  * the first sph_advance or without a graph). */
 int sph_launch_config(sph_ctx *ctx, int *out);
 
+/* Reference neighbour table of the solid (Section 2.2: the gradients
+ * V_b grad_a W(X_a - X_b) are fixed in the reference configuration), as set
+ * up by sph_init (no GPU work): out[0] = 1 when the 3D streamed sub-step
+ * passes walk the compact table (every scene's solid is a lattice of one
+ * spacing, smoothing length and volume, so a pair's gradient depends only on
+ * its lattice offset: 4 bytes per pair, the neighbour's index and the
+ * offset's class), 0 for the full table (16 bytes per pair: the FP32
+ * gradient and the index); out[1] = pair capacity per solid particle;
+ * out[2] = bytes per pair that the sub-step passes read.  SPH_E_ORDER
+ * without a context, SPH_E_ARG for a null out. */
+int sph_solid_table(sph_ctx *ctx, int *out);
+
 /* FP64 reductions of one scene: out[0..2] fluid momentum, out[3..5] solid
  * momentum, out[6] fluid kinetic energy, out[7] solid kinetic energy,
  * out[8] solid strain energy, out[9..11] sum of the fluid force on the solid,

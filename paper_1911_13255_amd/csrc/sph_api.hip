@@ -380,6 +380,9 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   for (double **p : dten) take(*p, 9 * ns);
   take(D.s_PBf, 9 * ns);
   take(D.s_vf, ns);
+  take(D.s_nbc, P.dim == 3 ? (size_t)P.maxn * ns : 1);
+  take(D.s_gcls, kNbrClasses);
+  take(D.nbc_ok, 1);
   float **vec[] = {&D.s_a, &D.s_fF, &D.s_vbar, &D.s_abar, &D.s_n0, &D.s_n, &D.s_fFp,
                    &D.sur_vbar, &D.sur_abar, &D.sur_amid};
   for (float **p : vec) take(*p, 3 * ns);
@@ -679,6 +682,34 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
     }
     HIPCHK_INIT(hipMemcpy(D.st, stv.data(), sizeof(SceneState) * n_scenes, hipMemcpyHostToDevice));
   }
+  // compact reference table (3D): where every scene's solid is a lattice of
+  // one spacing, smoothing length and volume, and every pair matches its
+  // offset class
+  D.nbr_compact = 0;
+  if (P.dim == 3 && P.ns > 0 && (size_t)P.ns < ((size_t)1 << 25)) {
+    int s0 = -1;
+    bool same = true;
+    for (int s = 0; s < n_scenes; ++s) {
+      const ScenePar &q = P.par[s];
+      if (q.s_count == 0) continue;
+      if (s0 < 0) s0 = s;
+      else same = same && q.dps == P.par[s0].dps && q.hs == P.par[s0].hs && q.Vs == P.par[s0].Vs;
+    }
+    if (same && s0 >= 0) {
+      int flag = 1;
+      HIPCHK_INIT(hipMemcpy(D.nbc_ok, &flag, sizeof(int), hipMemcpyHostToDevice));
+      launch_solid_classes(D, s0, st);
+      for (int s = 0; s < n_scenes; ++s) launch_solid_compact(D, s, P.par[s].s_count, st);
+      HIPCHK_INIT(hipStreamSynchronize(st));
+      HIPCHK_INIT(hipMemcpy(&flag, D.nbc_ok, sizeof(int), hipMemcpyDeviceToHost));
+      if (flag) {
+        launch_solid_gsum_classes(D, st);
+        HIPCHK_INIT(hipStreamSynchronize(st));
+        D.nbr_compact = 1;
+      }
+      if ((rc = check_launch(ctx, "compact reference table")) != SPH_OK) return fail(rc);
+    }
+  }
 #undef HIPCHK_INIT
   ctx->prebin = 1;  // every scene starts with a rebuild
   *out = ctx;
@@ -918,6 +949,15 @@ int sph_launch_config(sph_ctx *ctx, int *out) {
   const LaunchCfg &c = ctx->cfg;
   int v[8] = {c.lpp_force, c.lpp_couple, c.block_pair, c.solid_ppt, c.block_solid, ctx->D.capf, ctx->D.capb,
               ctx->graph_exec ? 1 : 0};
+  std::memcpy(out, v, sizeof v);
+  return SPH_OK;
+}
+
+int sph_solid_table(sph_ctx *ctx, int *out) {
+  if (!ctx) return SPH_E_ORDER;
+  if (!out) return SPH_E_ARG;
+  const int compact = ctx->D.nbr_compact;
+  int v[3] = {compact, ctx->D.maxn, compact ? (int)sizeof(unsigned) : (int)sizeof(float4)};
   std::memcpy(out, v, sizeof v);
   return SPH_OK;
 }

@@ -8,6 +8,9 @@ namespace mrsph {
 
 // cells per block of the multi-block cell scan
 constexpr int kCellTile = 4096;
+// offset classes of the compact reference table (3D): offsets of -2..2
+// lattice spacings per axis, 125 of them
+constexpr int kNbrClasses = 128;
 // particles per thread in the grid-wide step-end reductions
 constexpr int kReduceItems = 8;
 // reference-table rows each lane loads ahead in the block-resident solid
@@ -42,6 +45,12 @@ void launch_init_solid(const Dev &D, int s, const double *x, const double *v, in
                        hipStream_t st);
 void launch_solid_reference(const Dev &D, int s, int ns_scene, hipStream_t st);
 void launch_solid_B(const Dev &D, hipStream_t st);
+// compact reference table: class gradients from scene s, then every scene's
+// pairs checked against their class (D.nbc_ok cleared on a mismatch)
+void launch_solid_classes(const Dev &D, int s, hipStream_t st);
+void launch_solid_compact(const Dev &D, int s, int ns_scene, hipStream_t st);
+// gradient sums of the compact table's entries (once it is in use)
+void launch_solid_gsum_classes(const Dev &D, hipStream_t st);
 void launch_refresh_vmax(const Dev &D, hipStream_t st);
 // with_bin: bin (and scan) the scenes whose rebuild was set from the host;
 // graph steps leave that to a launch_prebin ahead of the replays (the

@@ -283,6 +283,19 @@ __global__ void k_init_solid(Dev D, int s, const double *x, const double *v, int
   D.s_blin[a] = 0;
 }
 
+// Reference-table gradient of one pair: V_b grad_a W(r) for r = X_a - X_b
+// with r2 = |r|^2 inside the support, rounded to FP32 per component.
+template <int DIM>
+__device__ __forceinline__ void ref_gradient(const ScenePar &P, const double *r, double r2, float *g) {
+  double h = P.hs;
+  double alpha = DIM == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+  double rr = sqrt(r2);
+  double qq = rr / h, t = 1.0 - 0.5 * qq;
+  double dW = -5.0 * alpha * qq * t * t * t / h;
+  double Vb = P.Vs;
+  for (int k = 0; k < DIM; ++k) g[k] = (float)(Vb * r[k] / rr * dW);
+}
+
 // Reference neighbour table of the solid (Section 2.2, corrected
 // configuration), by exhaustive search over the scene's solid in FP64 with
 // ascending neighbour index: b != a with |r0_a - r0_b| < 2 h_S, stored as
@@ -298,7 +311,6 @@ __global__ void __launch_bounds__(256) k_solid_neighbours(Dev D, int s) {
   if (active)
     for (int k = 0; k < 3; ++k) xa[k] = D.s_r0d[3 * (size_t)a + k];
   double h = P.hs, r2max = 4.0 * h * h;
-  double alpha = DIM == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
   int cnt = 0;
   int NS = D.ns;
   double gsum[3] = {0.0, 0.0, 0.0};
@@ -321,15 +333,9 @@ __global__ void __launch_bounds__(256) k_solid_neighbours(Dev D, int s) {
       }
       if (r2 >= r2max) continue;
       if (cnt < D.maxn) {
-        double rr = sqrt(r2);
-        double qq = rr / h, t = 1.0 - 0.5 * qq;
-        double dW = -5.0 * alpha * qq * t * t * t / h;
-        double Vb = P.Vs;
         float g[3] = {0.0f, 0.0f, 0.0f};
-        for (int k = 0; k < DIM; ++k) {
-          g[k] = (float)(Vb * r[k] / rr * dW);
-          gsum[k] += (double)g[k];  // of the stored values, in slot order
-        }
+        ref_gradient<DIM>(P, r, r2, g);
+        for (int k = 0; k < DIM; ++k) gsum[k] += (double)g[k];  // of the stored values, in slot order
         // (in 2D z holds the neighbour's index within the scene)
         D.s_nbr[(size_t)cnt * NS + a] =
             make_float4(g[0], g[1], DIM == 2 ? __int_as_float(ib) : g[2], __int_as_float(P.s_begin + ib));
@@ -346,6 +352,76 @@ __global__ void __launch_bounds__(256) k_solid_neighbours(Dev D, int s) {
       D.s_nbr[(size_t)q * NS + a] = make_float4(0.0f, 0.0f, DIM == 2 ? __int_as_float(i) : 0.0f, __int_as_float(a));
     for (int k = 0; k < 3; ++k) D.s_gsum[k * NS + a] = gsum[k];
   }
+}
+
+// Compact reference table (3D).  Where the reference configuration is a
+// lattice of spacing dp_S, the offset X_b - X_a of a pair is o dp_S for an
+// integer o with |o_k| <= 2 inside the support 2 h_S < 3 dp_S, and the pair's
+// gradient depends on o alone: a table entry shrinks to the neighbour's index
+// and o's class c = 25 (o_x + 2) + 5 (o_y + 2) + (o_z + 2), 4 bytes instead of
+// 16, and the class gradients sit in LDS of the passes that walk the table.
+
+// the class gradient of class c (zero for the centre and offsets outside the support)
+__global__ void k_solid_classes(Dev D, int s) {
+  const int c = threadIdx.x;
+  if (c >= kNbrClasses) return;
+  const ScenePar &P = D.par[s];
+  const int o[3] = {c / 25 - 2, (c / 5) % 5 - 2, c % 5 - 2};
+  double r[3], r2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    r[k] = -(double)o[k] * P.dps;
+    r2 += r[k] * r[k];
+  }
+  float g[3] = {0.0f, 0.0f, 0.0f};
+  const double h = P.hs;
+  if (c < 125 && r2 > 0.0 && r2 < 4.0 * h * h) ref_gradient<3>(P, r, r2, g);
+  D.s_gcls[c] = make_float4(g[0], g[1], g[2], 0.0f);
+}
+
+// every pair of scene s: its lattice offset, the class entry, and a check that
+// the stored gradient equals the class gradient to FP32 rounding
+__global__ void __launch_bounds__(256) k_solid_compact(Dev D, int s) {
+  const ScenePar &P = D.par[s];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.s_count) return;
+  const int a = P.s_begin + i, NS = D.ns;
+  double xa[3];
+  for (int k = 0; k < 3; ++k) xa[k] = D.s_r0d[3 * (size_t)a + k];
+  const int cnt = D.s_cnt[a];
+  bool ok = true;
+  for (int q = 0; q < cnt && ok; ++q) {
+    const float4 g = D.s_nbr[(size_t)q * NS + a];
+    const int b = __float_as_int(g.w);
+    int o[3];
+    for (int k = 0; k < 3; ++k) {
+      const double d = (D.s_r0d[3 * (size_t)b + k] - xa[k]) / P.dps;
+      o[k] = (int)rint(d);
+      ok &= fabs(d - (double)o[k]) <= 1e-6 && abs(o[k]) <= 2;
+    }
+    if (!ok) break;
+    const int c = 25 * (o[0] + 2) + 5 * (o[1] + 2) + (o[2] + 2);
+    const float4 e = D.s_gcls[c];
+    const float tol = 1e-6f * (fabsf(e.x) + fabsf(e.y) + fabsf(e.z));
+    ok &= tol > 0.0f && fabsf(g.x - e.x) <= tol && fabsf(g.y - e.y) <= tol && fabsf(g.z - e.z) <= tol;
+    D.s_nbc[(size_t)q * NS + a] = ((unsigned)b << 7) | (unsigned)c;
+  }
+  if (!ok) atomicAnd(D.nbc_ok, 0);
+}
+
+// gradient sums of the compact entries, in slot order (the own term of the
+// momentum sum then uses the same gradients as the neighbour terms)
+__global__ void __launch_bounds__(256) k_solid_gsum_classes(Dev D) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  const int NS = D.ns, cnt = D.s_cnt[a];
+  double gs[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < cnt; ++q) {
+    const float4 e = D.s_gcls[D.s_nbc[(size_t)q * NS + a] & 127u];
+    gs[0] += (double)e.x;
+    gs[1] += (double)e.y;
+    gs[2] += (double)e.z;
+  }
+  for (int k = 0; k < 3; ++k) D.s_gsum[k * NS + a] = gs[k];
 }
 
 // Correction matrix B_a = (sum_b V_b (r0_b - r0_a) (x) grad_a W_ab)^-1 in FP64
@@ -1706,6 +1782,12 @@ __global__ void __launch_bounds__(256) k_solid_first(Dev D) {
 // Momentum and velocity of sub-step `sub`.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
+  __shared__ float4 gcl[kNbrClasses];
+  const bool compact = DIM == 3 && D.nbr_compact;
+  if (compact) {
+    if (threadIdx.x < kNbrClasses) gcl[threadIdx.x] = D.s_gcls[threadIdx.x];
+    __syncthreads();
+  }
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= D.ns) return;
   int s = D.s_scene[a];
@@ -1723,15 +1805,25 @@ __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
     for (int j = 0; j < DIM; ++j) acc[i] += D.s_PB[pb_at(D, a, i * DIM + j)] * D.s_gsum[j * NS + a];
   float accn[3] = {0.0f, 0.0f, 0.0f};
   int cnt = D.s_cnt[a];
-#pragma unroll 4
-  for (int q = 0; q < cnt; ++q) {
-    float4 g = D.s_nbr[(size_t)q * NS + a];
-    int b = __float_as_int(g.w);
+  auto pair = [&](int b, const float4 &g) {
     float gv[3] = {g.x, g.y, g.z};
     float PBb[9];
     for (int k = 0; k < DIM * DIM; ++k) PBb[k] = D.s_PBf[pb_at(D, b, k)];
     for (int i = 0; i < DIM; ++i)
       for (int j = 0; j < DIM; ++j) accn[i] += PBb[i * DIM + j] * gv[j];
+  };
+  if (compact) {
+#pragma unroll 4
+    for (int q = 0; q < cnt; ++q) {
+      const unsigned e = D.s_nbc[(size_t)q * NS + a];
+      pair((int)(e >> 7), gcl[e & 127u]);
+    }
+  } else {
+#pragma unroll 4
+    for (int q = 0; q < cnt; ++q) {
+      const float4 g = D.s_nbr[(size_t)q * NS + a];
+      pair(__float_as_int(g.w), g);
+    }
   }
   for (int i = 0; i < DIM; ++i) acc[i] += (double)accn[i];
   const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
@@ -1751,6 +1843,12 @@ __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
 // then the first half and stress of the next sub-step.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
+  __shared__ float4 gcl[kNbrClasses];
+  const bool compact = DIM == 3 && D.nbr_compact;
+  if (compact) {
+    if (threadIdx.x < kNbrClasses) gcl[threadIdx.x] = D.s_gcls[threadIdx.x];
+    __syncthreads();
+  }
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= D.ns) return;
   int s = D.s_scene[a];
@@ -1768,16 +1866,26 @@ __global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
   float vaf[3] = {(float)va[0], (float)va[1], (float)va[2]};
   float Gn[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   int cnt = D.s_cnt[a];
-#pragma unroll 4
-  for (int q = 0; q < cnt; ++q) {
-    float4 g = D.s_nbr[(size_t)q * NS + a];
-    int b = __float_as_int(g.w);
+  auto pair = [&](int b, const float4 &g) {
     float gv[3] = {g.x, g.y, g.z};
     float4 vb = D.s_vf[b];
     float vbv[3] = {vb.x, vb.y, vb.z};
     for (int i = 0; i < DIM; ++i) {
       float dvi = vbv[i] - vaf[i];
       for (int j = 0; j < DIM; ++j) Gn[i * DIM + j] += dvi * gv[j];
+    }
+  };
+  if (compact) {
+#pragma unroll 4
+    for (int q = 0; q < cnt; ++q) {
+      const unsigned e = D.s_nbc[(size_t)q * NS + a];
+      pair((int)(e >> 7), gcl[e & 127u]);
+    }
+  } else {
+#pragma unroll 4
+    for (int q = 0; q < cnt; ++q) {
+      const float4 g = D.s_nbr[(size_t)q * NS + a];
+      pair(__float_as_int(g.w), g);
     }
   }
   double G[9];
@@ -2834,6 +2942,18 @@ void launch_solid_reference(const Dev &D, int s, int ns_scene, hipStream_t st) {
 void launch_solid_B(const Dev &D, hipStream_t st) {
   if (D.ns == 0) return;
   LAUNCH_DIM(D.dim, k_solid_B, dim3(nblk(D.ns, 256)), dim3(256), st, D);
+}
+
+void launch_solid_classes(const Dev &D, int s, hipStream_t st) {
+  hipLaunchKernelGGL(k_solid_classes, dim3(1), dim3(kNbrClasses), 0, st, D, s);
+}
+
+void launch_solid_compact(const Dev &D, int s, int ns_scene, hipStream_t st) {
+  if (ns_scene > 0) hipLaunchKernelGGL(k_solid_compact, dim3(nblk(ns_scene, 256)), dim3(256), 0, st, D, s);
+}
+
+void launch_solid_gsum_classes(const Dev &D, hipStream_t st) {
+  if (D.ns > 0) hipLaunchKernelGGL(k_solid_gsum_classes, dim3(nblk(D.ns, 256)), dim3(256), 0, st, D);
 }
 
 void launch_refresh_vmax(const Dev &D, hipStream_t st) {

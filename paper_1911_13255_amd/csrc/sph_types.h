@@ -132,6 +132,13 @@ struct Dev {
   double *s_H, *s_dF, *s_B;        // H = F - I, dF/dt, B in FP64 (d*d components)
   double *s_PB;                    // P B in FP64, component-major [k * ns + a] (9 components allocated)
   float *s_PBf;                    // the same rounded to FP32: what the streamed momentum pass gathers
+  // compact reference table of lattice reference configurations (3D): per
+  // pair the neighbour's index << 7 | its offset class, [q * ns + a]; the
+  // classes' gradients in s_gcls (one table for the context)
+  unsigned *s_nbc;
+  float4 *s_gcls;
+  int *nbc_ok;                     // set-up: stays 1 while every pair matches its class
+  int nbr_compact;                 // 1: the streamed solid passes walk s_nbc
   float4 *s_vf;                    // v rounded to FP32, one 16-byte record per particle: what the streamed
                                    // rate pass gathers (free particles: written by the momentum pass of the
                                    // same sub-step; clamped ones: by the first pass of the step)

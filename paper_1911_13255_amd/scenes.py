@@ -102,14 +102,16 @@ def _tank_walls(extent, dp, layers=3, open_top=True):
     return pts, nrm
 
 
-def _finish(sc: dict, seed: int) -> dict:
+def _finish(sc: dict, seed: int, solid_lattice: bool = False) -> dict:
+    """Seeded jitter of 1e-4 dp on the fluid and (unless ``solid_lattice``)
+    on the free solid particles, then contiguous FP64 arrays."""
     dim = sc["dim"]
     nf = len(sc["x_fluid"])
     ns = len(sc["x_solid"])
     nfree = ns - sc["n_clamp"]
     if seed is not None:
         sc["x_fluid"] = sc["x_fluid"] + _jitter(seed, 0, nf, dim, sc["dp_f"])
-        if nfree > 0:
+        if nfree > 0 and not solid_lattice:
             xs = sc["x_solid"].copy()
             xs[:nfree] += _jitter(seed, 4 * nf, nfree, dim, sc["dp_s"])
             sc["x_solid"] = xs
@@ -234,8 +236,12 @@ def plate_behind_cylinder(seed: int = 1, D: float = 0.1, dp_f: float = None,
 def dam_break_plate_3d(seed: int = 1, dp_f: float = 0.006, dp_ratio: float = 2.0,
                        water=(0.6, 0.6, 1.2), tank=(1.6, 0.6, 1.2),
                        plate=(0.04, 0.6, 0.4), plate_x=0.8, E=5e6, nu=0.45,
-                       rho_s=1100.0, cfl_ac=0.25) -> dict:
-    """3D dam break on an elastic plate clamped at its base (z is vertical)."""
+                       rho_s=1100.0, cfl_ac=0.25, solid_lattice: bool = True) -> dict:
+    """3D dam break on an elastic plate clamped at its base (z is vertical).
+
+    The plate's reference configuration is its exact lattice unless
+    ``solid_lattice`` is False (then it is jittered like the fluid).
+    """
     sc = _base(3)
     g = 9.81
     H = water[2]
@@ -261,7 +267,7 @@ def dam_break_plate_3d(seed: int = 1, dp_f: float = 0.006, dp_ratio: float = 2.0
     m = 3 * dp_f + 0.02
     sc["lo"] = np.array([-m, -m, -m])
     sc["hi"] = np.array([tank[0] + m, tank[1] + m, tank[2] + 0.2])
-    return _finish(sc, seed)
+    return _finish(sc, seed, solid_lattice)
 
 
 def batched_dam_breaks(n_scenes: int = 64, master_seed: int = 2026) -> list:
@@ -314,7 +320,8 @@ def hydrostatic_column(seed: int = 3, dp: float = 0.01, width: float = 0.2,
 
 
 def periodic_box_with_solid(seed: int = 5, dim: int = 2, n: int = 16, dp: float = 0.01,
-                            solid=True, amp: float = 0.05, eta: float = 0.0) -> dict:
+                            solid=True, amp: float = 0.05, eta: float = 0.0,
+                            solid_lattice: bool = False) -> dict:
     """Fully periodic fluid box with a free (unclamped) elastic block, g = 0.
 
     Velocities are a seeded random field of amplitude ``amp`` (times the fluid
@@ -349,7 +356,7 @@ def periodic_box_with_solid(seed: int = 5, dim: int = 2, n: int = 16, dp: float 
     sc["lo"][:dim] = 0.0
     sc["hi"][:dim] = Lb
     sc["periodic"] = np.array([1 if k < dim else 0 for k in range(3)], dtype=np.int32)
-    return _finish(sc, seed)
+    return _finish(sc, seed, solid_lattice)
 
 
 def shear_layer(seed: int = 7, dp: float = 0.01, n_x: int = 16, n_y: int = 8,

@@ -102,6 +102,7 @@ def lib():
         L.sph_set_scalars.argtypes = [vp, C.c_int, _dp]
         L.sph_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
         L.sph_launch_config.argtypes = [vp, C.POINTER(C.c_int)]
+        L.sph_solid_table.argtypes = [vp, C.POINTER(C.c_int)]
         L.sph_set_surrogate.argtypes = [vp, vp, C.POINTER(C.c_float), C.c_float]
         L.sph_solid_features.argtypes = [vp, vp, vp]
         L.sph_solid_targets.argtypes = [vp, vp, vp]
@@ -405,6 +406,11 @@ class Simulation:
         keys = ("lpp_fluid", "lpp_couple", "block_pair", "solid_ppt", "block_solid", "cap_fluid_nbr",
                 "cap_boundary_nbr", "graph")
         return dict(zip(keys, [int(x) for x in out]))
+
+    def solid_table(self) -> dict:
+        out = (C.c_int * 3)()
+        self._check(self.L.sph_solid_table(self.ctx, out))
+        return {"compact": int(out[0]), "capacity": int(out[1]), "bytes_per_pair": int(out[2])}
 
     def solid_register_resident(self) -> bool:
         return self.launch_config()["solid_ppt"] > 0

@@ -95,6 +95,9 @@ def test_dam_break_3d_sampled_first_step(gpu):
     nf = len(sc["x_fluid"])
     note(f"3D dam break full size: {nf} fluid, {len(sc['x_solid'])} solid")
     sim = sph.Simulation(sc)
+    # the plate's reference configuration is its lattice: the streamed solid
+    # passes walk the compact table
+    assert sim.solid_table()["compact"] == 1
     sim.step()
     a_gpu = sim.read(sph.F_A)
     rho_gpu = sim.read(sph.F_RHO)

@@ -299,6 +299,28 @@ def test_periodic_box_with_free_solid(gpu, dim, eta, solid_lds):
     sim.close()
 
 
+@pytest.mark.parametrize("solid_lattice", [True, False])
+def test_compact_reference_table_3d(gpu, solid_lattice):
+    # A solid whose reference configuration is an exact lattice lets the
+    # streamed 3D passes walk the 4-byte table of lattice-offset classes; the
+    # default jittered one (1e-4 dp_S) keeps the full 16-byte table. Both
+    # follow the oracle.
+    # n = 12: a 6^3 block, whose inner particles hold every lattice offset class
+    sc = scenes.periodic_box_with_solid(dim=3, n=12, eta=0.5, amp=0.3, solid_lattice=solid_lattice)
+    note(f"compact table solid_lattice {solid_lattice}")
+    sim = sph.Simulation(sc, solid_lds=0)
+    tab = sim.solid_table()
+    assert tab["compact"] == (1 if solid_lattice else 0), tab
+    assert tab["bytes_per_pair"] == (4 if solid_lattice else 16), tab
+    o = O.Oracle(sc)
+    for k in range(6):
+        one_step(sim, o)
+        compare(sim, o, label=f"box3 lattice {solid_lattice} step {k + 1}")
+    assert o.scalars()["kappa"] > 1
+    sim.sync()
+    sim.close()
+
+
 def test_channel_with_inflow(gpu):
     # Periodic channel with the inflow buffer, cylinder walls and the plate.
     sc = scenes.plate_behind_cylinder(dp_f=0.01)
