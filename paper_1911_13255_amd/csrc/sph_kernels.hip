@@ -1890,20 +1890,40 @@ __global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
   }
   double G[9];
   for (int k = 0; k < DIM * DIM; ++k) G[k] = (double)Gn[k];
-  // (v_b - v_a) (x) (B grad W) summed = G B^T
+  // (v_b - v_a) (x) (B grad W) summed = G B^T; then, for a following
+  // sub-step, its first half on the values still in registers (the same
+  // arithmetic as solid_first_half, without reading back what was just
+  // written)
+  const bool more = sub + 1 < S.kappa;
+  double H[9], B[9];
+  for (int k = 0; k < DIM * DIM; ++k) {
+    B[k] = D.s_B[k * NS + a];
+    H[k] = D.s_H[k * NS + a];
+  }
   for (int i = 0; i < DIM; ++i)
     for (int j = 0; j < DIM; ++j) {
       double sum = 0.0;
-      for (int k = 0; k < DIM; ++k) sum += G[i * DIM + k] * D.s_B[(j * DIM + k) * NS + a];
+      for (int k = 0; k < DIM; ++k) sum += G[i * DIM + k] * B[j * DIM + k];
       D.s_dF[(i * DIM + j) * NS + a] = sum;
-      D.s_H[(i * DIM + j) * NS + a] += hd * sum;
+      const double h1 = H[i * DIM + j] + hd * sum;
+      H[i * DIM + j] = more ? h1 + hd * sum : h1;
+      D.s_H[(i * DIM + j) * NS + a] = H[i * DIM + j];
     }
   for (int k = 0; k < DIM; ++k) {
-    double inc = hd * va[k];
-    D.s_u[k * NS + a] += inc;
-    D.s_du[k * NS + a] += inc;
+    const double inc = hd * va[k];
+    const double u1 = D.s_u[k * NS + a] + inc, du1 = D.s_du[k * NS + a] + inc;
+    D.s_u[k * NS + a] = more ? u1 + inc : u1;
+    D.s_du[k * NS + a] = more ? du1 + inc : du1;
   }
-  if (sub + 1 < S.kappa) solid_first_half<DIM>(D, P, S, a, hd);
+  if (more) {
+    double PB[9], J;
+    solid_PB<DIM, double>(P.material, H, B, (double)P.mu, (double)P.lam, PB, J);
+    if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
+    for (int k = 0; k < DIM * DIM; ++k) {
+      D.s_PB[pb_at(D, a, k)] = PB[k];
+      D.s_PBf[pb_at(D, a, k)] = (float)PB[k];
+    }
+  }
 }
 
 // Time averages over the acoustic step.
