@@ -17,7 +17,9 @@
  *    reported by sph_sync and by sph_read/sph_scalars, which synchronise.
  *  - Memory: all device memory is one caller-owned arena of sph_arena_bytes()
  *    bytes (e.g. a uint8 tensor).  The library never allocates or frees device
- *    memory; it frees only the host context it allocated in sph_init.
+ *    memory; sph_init allocates the host context and a small pinned host
+ *    buffer (the scene states, read back asynchronously by the streamed
+ *    solid passes), and sph_destroy frees both.
  *  - Host arrays passed in are read during the call only.
  *  - Threading: one context per stream; calls on one context are not
  *    thread-safe.  Contexts are independent.

@@ -31,6 +31,13 @@ struct sph_ctx {
   int prebin;        // a rebuild set from the host may await binning (sph_advance bins it first)
   hipStream_t side;  // second stream for the concurrent continuity pass (graph capture only)
   hipEvent_t ev_fork, ev_join;
+  // streamed solid: the scene states copied to pinned host memory at the end
+  // of each step, after the next step's kappa is computed (kappa_next); the
+  // next step waits on ev_kappa while its fluid passes run, instead of
+  // stopping the stream to read kappa at its solid phase
+  SceneState *st_host;
+  hipEvent_t ev_kappa;
+  int kappa_ready;  // 1: st_host's kappa_next belongs to the step about to be enqueued
   size_t stage_doubles;
   mlp_ctx *net;  // sub-step surrogate (nullptr: plain sub-steps only)
   char err[512];
@@ -444,8 +451,10 @@ int read_states(sph_ctx *ctx, std::vector<SceneState> &st) {
 
 // kappa solid sub-steps.  Small 2D solids: one
 // register-resident launch per step with kappa decided on the device.  Other
-// solids: streamed passes over all solid particles; kappa is read back to
-// the host to size the pass loop (this synchronises the stream).
+// solids: streamed passes over all solid particles; kappa sizes the host's
+// pass loop: inside sph_advance it was copied to pinned memory at the end of
+// the step before (the host waits on that copy only), otherwise it is read
+// back here (this synchronises the stream).
 // Register-resident sub-steps, preceded by the learned step when a surrogate
 // is set (scenes it is accepted for skip the sub-steps).
 // step_end: the solid launch also does the step-end reduction's work
@@ -465,18 +474,29 @@ int enqueue_solid(sph_ctx *ctx, bool step_end) {
     enqueue_solid_reg(ctx, step_end);
   } else if (ctx->D.ns > 0) {
     launch_solid_dt(ctx->D, ctx->stream);
-    std::vector<SceneState> st(ctx->n_scenes);
-    if (hipMemcpyAsync(st.data(), ctx->D.st, sizeof(SceneState) * ctx->n_scenes, hipMemcpyDeviceToHost,
-                       ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess) {
-      std::snprintf(ctx->err, sizeof ctx->err, "solid_substeps: kappa read-back failed");
-      return SPH_E_HIP;
-    }
     int kmax = 0;
-    for (const SceneState &x : st) kmax = std::max(kmax, x.kappa);
+    if (ctx->kappa_ready) {
+      // kappa as the end of the step before computed it from the same state
+      // (the averaging pass flags a scene whose kappa exceeds the passes)
+      ctx->kappa_ready = 0;
+      if (hipEventSynchronize(ctx->ev_kappa) != hipSuccess) {
+        std::snprintf(ctx->err, sizeof ctx->err, "solid_substeps: kappa read-back failed");
+        return SPH_E_HIP;
+      }
+      for (int s = 0; s < ctx->n_scenes; ++s) kmax = std::max(kmax, ctx->st_host[s].kappa_next);
+    } else {
+      std::vector<SceneState> st(ctx->n_scenes);
+      if (hipMemcpyAsync(st.data(), ctx->D.st, sizeof(SceneState) * ctx->n_scenes, hipMemcpyDeviceToHost,
+                         ctx->stream) != hipSuccess ||
+          hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        std::snprintf(ctx->err, sizeof ctx->err, "solid_substeps: kappa read-back failed");
+        return SPH_E_HIP;
+      }
+      for (const SceneState &x : st) kmax = std::max(kmax, x.kappa);
+    }
     launch_solid_first(ctx->D, ctx->stream);
     for (int sub = 0; sub < kmax; ++sub) launch_solid_pass(ctx->D, sub, ctx->stream);
-    launch_solid_average(ctx->D, ctx->stream);
+    launch_solid_average(ctx->D, kmax, ctx->stream);
   } else {
     launch_solid_dt(ctx->D, ctx->stream);
   }
@@ -506,6 +526,15 @@ int enqueue_step(sph_ctx *ctx, bool fork) {
   int rc = enqueue_solid(ctx, true);
   if (rc != SPH_OK) return rc;
   launch_step_end(ctx->D, ctx->stream, ctx->cfg.solid_ppt > 0);
+  if (ctx->cfg.solid_ppt == 0 && ctx->D.ns > 0 && ctx->st_host) {
+    // the next step's kappa depends only on the state this close leaves
+    launch_solid_dt_next(ctx->D, ctx->stream);
+    if (hipMemcpyAsync(ctx->st_host, ctx->D.st, sizeof(SceneState) * ctx->n_scenes, hipMemcpyDeviceToHost,
+                       ctx->stream) != hipSuccess ||
+        hipEventRecord(ctx->ev_kappa, ctx->stream) != hipSuccess)
+      return SPH_E_HIP;
+    ctx->kappa_ready = 1;
+  }
   return check_launch(ctx, "acoustic step");
 }
 
@@ -541,6 +570,16 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   ctx->net = nullptr;
   ctx->side = nullptr;
   ctx->ev_fork = ctx->ev_join = nullptr;
+  ctx->st_host = nullptr;
+  ctx->ev_kappa = nullptr;
+  ctx->kappa_ready = 0;
+  if (hipHostMalloc((void **)&ctx->st_host, sizeof(SceneState) * n_scenes, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_kappa, hipEventDisableTiming) != hipSuccess) {
+    if (ctx->st_host) (void)hipHostFree(ctx->st_host);
+    ctx->st_host = nullptr;
+    ctx->ev_kappa = nullptr;
+    (void)hipGetLastError();
+  }
   if (ctx->stream) {
     // default priority, like every stream here
     if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
@@ -805,6 +844,7 @@ int sph_read(sph_ctx *ctx, int field, int scene, double *host) {
 
 int sph_write(sph_ctx *ctx, int field, int scene, const double *host) {
   if (!ctx) return SPH_E_ORDER;
+  ctx->kappa_ready = 0;  // the state may change: the next step reads kappa at its solid phase
   if (scene < 0 || scene >= ctx->n_scenes || !host) return SPH_E_ARG;
   static const int writable[] = {SPH_F_X, SPH_F_V, SPH_F_RHO, SPH_F_DRHO, SPH_S_U, SPH_S_V,
                                  SPH_S_A, SPH_S_F, SPH_S_DF, SPH_S_VBAR, SPH_S_ABAR};
@@ -847,6 +887,7 @@ int sph_scalars(sph_ctx *ctx, int scene, double *out) {
 
 int sph_set_scalars(sph_ctx *ctx, int scene, const double *in) {
   if (!ctx) return SPH_E_ORDER;
+  ctx->kappa_ready = 0;  // the state may change: the next step reads kappa at its solid phase
   if (scene < 0 || scene >= ctx->n_scenes || !in) return SPH_E_ARG;
   std::vector<SceneState> st;
   int rc = read_states(ctx, st);
@@ -892,6 +933,7 @@ int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out) {
 
 int sph_set_surrogate(sph_ctx *ctx, mlp_ctx *net, const float *stats, float threshold) {
   if (!ctx) return SPH_E_ORDER;
+  ctx->kappa_ready = 0;  // the state may change: the next step reads kappa at its solid phase
   if (net == nullptr || !(threshold > 0.0f)) {
     ctx->net = nullptr;
     ctx->D.sur_thr = 0.0f;
@@ -987,11 +1029,14 @@ int sph_sync(sph_ctx *ctx) {
   for (int s = 0; s < ctx->n_scenes; ++s) {
     int e = st[s].err;
     if (e) {
-      std::snprintf(ctx->err, sizeof ctx->err, "scene %d: %s%s%s%s", s, (e & ERR_NAN_FLUID) ? "non-finite fluid state " : "",
+      std::snprintf(ctx->err, sizeof ctx->err, "scene %d: %s%s%s%s%s", s,
+                    (e & ERR_NAN_FLUID) ? "non-finite fluid state " : "",
                     (e & ERR_NAN_SOLID) ? "non-finite solid state " : "", (e & ERR_JACOBIAN) ? "det F <= 0 " : "",
-                    (e & ERR_CAPACITY) ? "neighbour table overflow" : "");
+                    (e & ERR_CAPACITY) ? "neighbour table overflow " : "",
+                    (e & ERR_KAPPA) ? "fewer solid sub-step passes than kappa" : "");
       // a state that blew up also crowds cells: instability takes precedence
-      return (e & (ERR_NAN_FLUID | ERR_NAN_SOLID | ERR_JACOBIAN)) ? SPH_E_UNSTABLE : SPH_E_CAPACITY;
+      if (e & (ERR_NAN_FLUID | ERR_NAN_SOLID | ERR_JACOBIAN)) return SPH_E_UNSTABLE;
+      return (e & ERR_CAPACITY) ? SPH_E_CAPACITY : SPH_E_ORDER;
     }
   }
   return SPH_OK;
@@ -999,6 +1044,7 @@ int sph_sync(sph_ctx *ctx) {
 
 int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms) {
   if (!ctx) return SPH_E_ORDER;
+  ctx->kappa_ready = 0;  // the state may change: the next step reads kappa at its solid phase
   if (reps <= 0 || !avg_ms || kernel < SPH_K_FLUID_FORCE || kernel > SPH_K_REBUILD) return SPH_E_ARG;
   hipStream_t st = ctx->stream;
   auto enqueue_one = [&]() -> int {
@@ -1124,6 +1170,11 @@ void sph_destroy(sph_ctx *ctx) {
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->ev_kappa) {
+    (void)hipEventSynchronize(ctx->ev_kappa);  // any copy into st_host has landed
+    (void)hipEventDestroy(ctx->ev_kappa);
+  }
+  if (ctx->st_host) (void)hipHostFree(ctx->st_host);
   delete ctx;
 }
 

@@ -73,9 +73,13 @@ void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t
 void launch_sur_targets(const Dev &D, const float *xraw, float *t, hipStream_t st);
 void launch_sur_predict(const Dev &D, hipStream_t st);
 void launch_solid_dt(const Dev &D, hipStream_t st);
+// the same reduction at a step's end, after its close, into kappa_next only
+// (the step increments and kappa stay untouched)
+void launch_solid_dt_next(const Dev &D, hipStream_t st);
 void launch_solid_first(const Dev &D, hipStream_t st);
 void launch_solid_pass(const Dev &D, int sub, hipStream_t st);
-void launch_solid_average(const Dev &D, hipStream_t st);
+// launched: sub-step passes launched this step (scenes with a larger kappa are flagged)
+void launch_solid_average(const Dev &D, int launched, hipStream_t st);
 void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t st);
 void launch_write(const Dev &D, int s, int field, int n, const double *in, hipStream_t st);
 void launch_reduce(const Dev &D, int s, int nblocks, double *out, hipStream_t st);

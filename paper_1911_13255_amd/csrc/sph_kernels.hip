@@ -1672,12 +1672,12 @@ __global__ void __launch_bounds__(1024) k_step_close_scan(Dev D) {
 // Solid time step and kappa of each scene: max |v| and |a| of the free solid
 // over all solid particles (one atomic per block and scene), the step
 // increments cleared; then k_solid_dt_close, one thread per scene.
-__global__ void __launch_bounds__(256) k_solid_dt_reduce(Dev D) {
+__global__ void __launch_bounds__(256) k_solid_dt_reduce(Dev D, int next) {
   __shared__ float shv[16], sha[16];
   const int dim = D.dim, NS = D.ns;
   const int span = blockDim.x * kReduceItems;
   const int a0 = blockIdx.x * span, a1 = min(NS, a0 + span);
-  for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+  for (int a = a0 + threadIdx.x; a < a1 && !next; a += blockDim.x) {
     for (int k = 0; k < dim; ++k) {
       D.s_du[k * NS + a] = 0.0;
       D.s_dv[k * NS + a] = 0.0;
@@ -1723,15 +1723,23 @@ __device__ __forceinline__ void solid_kappa(const ScenePar &P, SceneState &S, fl
   }
 }
 
-__global__ void k_solid_dt_close(Dev D) {
+__global__ void k_solid_dt_close(Dev D, int next) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= D.n_scenes) return;
   SceneState &S = D.st[s];
   int kap;
   double dts;
-  solid_kappa(D.par[s], S, __uint_as_float(S.smax_v), __uint_as_float(S.smax_a), S.dt_ac, kap, dts);
-  S.dt_s = dts;
-  S.kappa = kap;
+  if (next) {
+    // the error bits of a step-start evaluation are left to that one
+    const int err = S.err;
+    solid_kappa(D.par[s], S, __uint_as_float(S.smax_v), __uint_as_float(S.smax_a), S.dt_ac, kap, dts);
+    S.err = err;
+    S.kappa_next = kap;
+  } else {
+    solid_kappa(D.par[s], S, __uint_as_float(S.smax_v), __uint_as_float(S.smax_a), S.dt_ac, kap, dts);
+    S.dt_s = dts;
+    S.kappa = kap;
+  }
   S.smax_v = S.smax_a = 0u;
 }
 
@@ -1928,12 +1936,13 @@ __global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
 
 // Time averages over the acoustic step.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_solid_average(Dev D) {
+__global__ void __launch_bounds__(256) k_solid_average(Dev D, int launched) {
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= D.ns) return;
   int s = D.s_scene[a];
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
+  if (a == P.s_begin && S.kappa > launched) atomicOr(&S.err, (int)ERR_KAPPA);
   if (a - P.s_begin >= P.s_count - P.s_nclamp) return;
   const int NS = D.ns;
   const double inv_dt = 1.0 / S.dt_ac;
@@ -3088,8 +3097,15 @@ void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_
 void launch_solid_dt(const Dev &D, hipStream_t st) {
   if (D.ns > 0)
     hipLaunchKernelGGL(k_solid_dt_reduce, dim3((D.ns + 256 * kReduceItems - 1) / (256 * kReduceItems)), dim3(256), 0,
-                       st, D);
-  hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
+                       st, D, 0);
+  hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D, 0);
+}
+
+void launch_solid_dt_next(const Dev &D, hipStream_t st) {
+  if (D.ns > 0)
+    hipLaunchKernelGGL(k_solid_dt_reduce, dim3((D.ns + 256 * kReduceItems - 1) / (256 * kReduceItems)), dim3(256), 0,
+                       st, D, 1);
+  hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D, 1);
 }
 
 void launch_solid_first(const Dev &D, hipStream_t st) {
@@ -3102,8 +3118,8 @@ void launch_solid_pass(const Dev &D, int sub, hipStream_t st) {
   LAUNCH_DIM(D.dim, k_solid_rate, grid_for(D.ns, 256), dim3(256), st, D, sub);
 }
 
-void launch_solid_average(const Dev &D, hipStream_t st) {
-  if (D.ns > 0) LAUNCH_DIM(D.dim, k_solid_average, grid_for(D.ns, 256), dim3(256), st, D);
+void launch_solid_average(const Dev &D, int launched, hipStream_t st) {
+  if (D.ns > 0) LAUNCH_DIM(D.dim, k_solid_average, grid_for(D.ns, 256), dim3(256), st, D, launched);
 }
 
 void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t st) {

@@ -52,6 +52,8 @@ struct ScenePar {
 struct SceneState {
   double t, dt_ac, dt_ad, dt_s, adv_accum;
   int kappa, need_rebuild, err;
+  int kappa_next;  // streamed solid: kappa of the next step, computed at this step's end for the host
+  int pad_kn;
   int binned;  // pending rebuild prepared at the end of the last step: 1 particles binned, 2 cells scanned too
   unsigned int vmax_prev, vmax_next;  // max fluid speed (float bits): step start / being reduced
   unsigned int smax_v, smax_a;        // max solid speed and acceleration (float bits) being reduced
@@ -64,7 +66,9 @@ struct SceneState {
   unsigned long long sur_ok, sur_fallback;  // surrogate steps accepted / rejected
 };
 
-enum ErrBits { ERR_NAN_FLUID = 1, ERR_NAN_SOLID = 2, ERR_JACOBIAN = 4, ERR_CAPACITY = 8 };
+// ERR_KAPPA: the streamed solid passes were launched fewer times than the
+// scene's kappa (an inconsistency of the host's sub-step count)
+enum ErrBits { ERR_NAN_FLUID = 1, ERR_NAN_SOLID = 2, ERR_JACOBIAN = 4, ERR_CAPACITY = 8, ERR_KAPPA = 16 };
 
 // Device pointers, passed by value to every kernel.
 struct Dev {
