@@ -13,7 +13,11 @@
  *
  * Readings of the paper where it is silent or garbled (numbered R1-R34 in the
  * design notes) are marked "reading" below.  Functions with no independent
- * check are marked "parity unpinned"; there are none at present.
+ * check are marked "parity unpinned"; there are none at present: besides the
+ * invariants (rigid motions, momentum exchange, hydrostatics), the magnitude
+ * of every pair sum (continuity, pressure and viscous terms, the wall and
+ * solid coupling terms, the solid stress divergence) is pinned to a closed
+ * form on a lattice by the tests.
  */
 #include <math.h>
 #ifdef _OPENMP
