@@ -23,6 +23,15 @@
  *  - Host arrays passed in are read during the call only.
  *  - Threading: one context per stream; calls on one context are not
  *    thread-safe.  Contexts are independent.
+ *  - Order (Algorithm 1): one acoustic step is neighbor_build, fluid_step,
+ *    couple, solid_substeps, in this order (neighbor_build rebuilds only the
+ *    scenes whose advection step is due, and may be repeated).  A context
+ *    starts at a step boundary; sph_advance, sph_write, sph_set_scalars,
+ *    sph_set_surrogate, sph_solid_targets and sph_time_kernel run only
+ *    there; sph_solid_features only between couple and solid_substeps.  A
+ *    call out of this sequence returns SPH_E_ORDER, enqueues nothing and
+ *    leaves the state and the sequence as they were.  Read-only calls
+ *    (sph_read, sph_reduce, sph_pairs, counters, scalars) run anywhere in it.
  *  - Units are SI; positions are row-major (n, dim) float64.
  */
 #ifndef MRSPH_H
@@ -40,6 +49,8 @@ extern "C" {
 #define SPH_E_ORDER (-3)    /* call out of sequence (e.g. before sph_init) */
 #define SPH_E_CAPACITY (-4) /* a fixed-capacity neighbour table or pair list overflowed */
 #define SPH_E_UNSTABLE (-5) /* NaN/Inf in the state or det F <= 0 (reported first when both hold) */
+#define SPH_FALLBACK 1      /* info (sph_sync): a learned sub-step fell back to the plain sub-steps
+                               since the previous sph_sync */
 
 typedef struct sph_ctx sph_ctx;
 
@@ -136,19 +147,22 @@ int neighbor_build(sph_ctx *ctx);
 /* One fluid acoustic step of the position-based Verlet scheme (Section 3.3):
  * half step in density and position, momentum with the Riemann pressure,
  * viscous and coupling forces at h_F (Section 3.1), full step in velocity,
- * continuity with the new velocity, second half step.  Enqueue only. */
+ * continuity with the new velocity, second half step.  Must follow
+ * neighbor_build (else SPH_E_ORDER).  Enqueue only. */
 int fluid_step(sph_ctx *ctx);
 
 /* Pressure and viscous forces of the fluid on the solid (Section 2.2,
  * Eqs. F:p and F:v at h_F), as exact negatives of the fluid-side pair terms
- * of the same step.  Must follow fluid_step.  Enqueue only. */
+ * of the same step.  Must follow fluid_step (else SPH_E_ORDER).  Enqueue
+ * only. */
 int couple(sph_ctx *ctx);
 
 /* kappa solid sub-steps of the position-based Verlet scheme with the fluid
  * force held constant (Section 3.3), Neo-Hookean stress (Section 2.1) and
  * the corrected total-Lagrangian momentum equation at h_S (Section 3.1);
  * then the time-averaged velocity and acceleration (Section 3.2) and the
- * end-of-step time bookkeeping.  Must follow couple.  Enqueue only, except
+ * end-of-step time bookkeeping.  Must follow couple (else SPH_E_ORDER).
+ * Enqueue only, except
  * for solids run as streamed passes (3D, large or solid_lds = 1): there
  * kappa is read back to the host, which waits for the stream. */
 int solid_substeps(sph_ctx *ctx);
@@ -284,7 +298,26 @@ enum {
  * the state like the entry point that owns the kernel.  Synchronises. */
 int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms);
 
-/* Wait for the stream; return the first latched device error, if any. */
+/* Neighbour lists of one scene at the last rebuild, for checking the cell
+ * search against a brute-force search (Algorithm 1, rebuild at the start of
+ * each advection step; the solid's reference lists of Section 2.2).  Rows are
+ * in original particle order and each row is sorted ascending (a list is a
+ * set: the kernels' own order is the cell walk's).
+ *   which 0: fluid -> fluid neighbours within 2 h_F (original fluid index);
+ *   which 1: fluid -> boundary neighbours within 2 h_F, boundary index =
+ *            wall index for walls, n_wall + free solid index for the solid;
+ *   which 2: free solid -> fluid neighbours within 2 h_F (the coupling list);
+ *   which 3: solid -> solid reference neighbours within 2 h_S (solid index).
+ * start (host, rows + 1 ints; rows = n_fluid, n_fluid, free solid, solid) is
+ * always filled; idx (host, as many ints as the return value) is filled when
+ * not NULL, so a first call with idx = NULL sizes the second.  Returns the
+ * number of entries (>= 0) or an error.  Synchronises; for tests and
+ * diagnostics (it copies the scene's lists to the host). */
+int sph_pairs(sph_ctx *ctx, int which, int scene, int *start, int *idx);
+
+/* Wait for the stream; return the first latched device error, if any, else
+ * SPH_FALLBACK when a learned step fell back since the last call, else
+ * SPH_OK. */
 int sph_sync(sph_ctx *ctx);
 
 /* Text of the last error of this context (static storage of the context). */

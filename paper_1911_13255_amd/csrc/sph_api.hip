@@ -40,6 +40,11 @@ struct sph_ctx {
   int kappa_ready;  // 1: st_host's kappa_next belongs to the step about to be enqueued
   size_t stage_doubles;
   mlp_ctx *net;  // sub-step surrogate (nullptr: plain sub-steps only)
+  // position in Algorithm 1's sequence of one acoustic step: 0 at a step
+  // boundary, 1 after neighbor_build, 2 after fluid_step, 3 after couple
+  // (solid_substeps returns it to 0)
+  int phase;
+  unsigned long long fallback_seen;  // surrogate fall-backs already reported by sph_sync
   char err[512];
 };
 
@@ -371,6 +376,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.b_posd, nb);
   take(D.b_perm, nb);
   take(D.b_solid, nb);
+  take(D.b_src, nb);
   take(D.bs_lin, nb);
   take(D.bs_slot, nb);
   take(D.bs_scene, nb);
@@ -440,6 +446,17 @@ int field_width(int dim, int field) {
     return dim * dim;
   }
   return 0;
+}
+
+// Call-order check of the step sequence (Algorithm 1): `need` is the phase the
+// call requires.
+int check_phase(sph_ctx *ctx, const char *call, int need) {
+  if (ctx->phase == need) return SPH_OK;
+  static const char *where[] = {"at a step boundary (after sph_init or solid_substeps)", "after neighbor_build",
+                                "after fluid_step", "after couple"};
+  std::snprintf(ctx->err, sizeof ctx->err, "%s called out of sequence: it runs %s, the context is %s", call,
+                where[need], where[ctx->phase]);
+  return SPH_E_ORDER;
 }
 
 int read_states(sph_ctx *ctx, std::vector<SceneState> &st) {
@@ -608,6 +625,8 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   }
   ctx->graph_failed = 0;
   ctx->err[0] = 0;
+  ctx->phase = 0;
+  ctx->fallback_seen = 0;
   size_t need = carve(nullptr, P, ctx->D);
   if (!dev_arena || arena_bytes < need) {
     std::snprintf(ctx->err, sizeof ctx->err, "arena too small: %zu < %zu", arena_bytes, need);
@@ -757,34 +776,52 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
 
 int neighbor_build(sph_ctx *ctx) {
   if (!ctx) return SPH_E_ORDER;
+  // at a step boundary, or again after itself (a no-op then: nothing is due)
+  int rc = ctx->phase == 1 ? SPH_OK : check_phase(ctx, "neighbor_build", 0);
+  if (rc != SPH_OK) return rc;
   launch_rebuild(ctx->D, ctx->cfg, ctx->stream, true);
-  return check_launch(ctx, "neighbor_build");
+  rc = check_launch(ctx, "neighbor_build");
+  if (rc == SPH_OK) ctx->phase = 1;
+  return rc;
 }
 
 int fluid_step(sph_ctx *ctx) {
   if (!ctx) return SPH_E_ORDER;
+  int rc = check_phase(ctx, "fluid_step", 1);
+  if (rc != SPH_OK) return rc;
   launch_fluid_force(ctx->D, ctx->cfg, ctx->stream);
   launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream, false);
-  return check_launch(ctx, "fluid_step");
+  rc = check_launch(ctx, "fluid_step");
+  if (rc == SPH_OK) ctx->phase = 2;
+  return rc;
 }
 
 int couple(sph_ctx *ctx) {
   if (!ctx) return SPH_E_ORDER;
+  int rc = check_phase(ctx, "couple", 2);
+  if (rc != SPH_OK) return rc;
   launch_couple(ctx->D, ctx->cfg, ctx->stream);
-  return check_launch(ctx, "couple");
+  rc = check_launch(ctx, "couple");
+  if (rc == SPH_OK) ctx->phase = 3;
+  return rc;
 }
 
 int solid_substeps(sph_ctx *ctx) {
   if (!ctx) return SPH_E_ORDER;
-  int rc = enqueue_solid(ctx, true);
+  int rc = check_phase(ctx, "solid_substeps", 3);
+  if (rc != SPH_OK) return rc;
+  rc = enqueue_solid(ctx, true);
   if (rc != SPH_OK) return rc;
   launch_step_end(ctx->D, ctx->stream, ctx->cfg.solid_ppt > 0);
-  return check_launch(ctx, "solid_substeps");
+  rc = check_launch(ctx, "solid_substeps");
+  if (rc == SPH_OK) ctx->phase = 0;
+  return rc;
 }
 
 int sph_advance(sph_ctx *ctx, int n_steps) {
   if (!ctx) return SPH_E_ORDER;
   if (n_steps < 0) return SPH_E_ARG;
+  if (check_phase(ctx, "sph_advance", 0) != SPH_OK) return SPH_E_ORDER;
   // the streamed solid path reads kappa back to the host: no graph then
   if (!ctx->graph_exec && !ctx->graph_failed && ctx->stream && ctx->cfg.solid_ppt > 0) {
     // capture one acoustic step; every decision inside it is taken on the device
@@ -844,6 +881,7 @@ int sph_read(sph_ctx *ctx, int field, int scene, double *host) {
 
 int sph_write(sph_ctx *ctx, int field, int scene, const double *host) {
   if (!ctx) return SPH_E_ORDER;
+  if (check_phase(ctx, "sph_write", 0) != SPH_OK) return SPH_E_ORDER;
   ctx->kappa_ready = 0;  // the state may change: the next step reads kappa at its solid phase
   if (scene < 0 || scene >= ctx->n_scenes || !host) return SPH_E_ARG;
   static const int writable[] = {SPH_F_X, SPH_F_V, SPH_F_RHO, SPH_F_DRHO, SPH_S_U, SPH_S_V,
@@ -887,6 +925,7 @@ int sph_scalars(sph_ctx *ctx, int scene, double *out) {
 
 int sph_set_scalars(sph_ctx *ctx, int scene, const double *in) {
   if (!ctx) return SPH_E_ORDER;
+  if (check_phase(ctx, "sph_set_scalars", 0) != SPH_OK) return SPH_E_ORDER;
   ctx->kappa_ready = 0;  // the state may change: the next step reads kappa at its solid phase
   if (scene < 0 || scene >= ctx->n_scenes || !in) return SPH_E_ARG;
   std::vector<SceneState> st;
@@ -933,6 +972,7 @@ int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out) {
 
 int sph_set_surrogate(sph_ctx *ctx, mlp_ctx *net, const float *stats, float threshold) {
   if (!ctx) return SPH_E_ORDER;
+  if (check_phase(ctx, "sph_set_surrogate", 0) != SPH_OK) return SPH_E_ORDER;
   ctx->kappa_ready = 0;  // the state may change: the next step reads kappa at its solid phase
   if (net == nullptr || !(threshold > 0.0f)) {
     ctx->net = nullptr;
@@ -958,6 +998,7 @@ int sph_set_surrogate(sph_ctx *ctx, mlp_ctx *net, const float *stats, float thre
 
 int sph_solid_features(sph_ctx *ctx, const float *stats_dev, float *x_dev) {
   if (!ctx) return SPH_E_ORDER;
+  if (check_phase(ctx, "sph_solid_features", 3) != SPH_OK) return SPH_E_ORDER;
   if (!x_dev || ctx->dim != 2) return SPH_E_ARG;
   launch_sur_features(ctx->D, stats_dev, x_dev, ctx->stream);
   return check_launch(ctx, "sph_solid_features");
@@ -965,6 +1006,7 @@ int sph_solid_features(sph_ctx *ctx, const float *stats_dev, float *x_dev) {
 
 int sph_solid_targets(sph_ctx *ctx, const float *xraw_dev, float *t_dev) {
   if (!ctx) return SPH_E_ORDER;
+  if (check_phase(ctx, "sph_solid_targets", 0) != SPH_OK) return SPH_E_ORDER;
   if (!xraw_dev || !t_dev || ctx->dim != 2) return SPH_E_ARG;
   launch_sur_targets(ctx->D, xraw_dev, t_dev, ctx->stream);
   return check_launch(ctx, "sph_solid_targets");
@@ -1021,6 +1063,78 @@ int sph_reduce(sph_ctx *ctx, int scene, double *out) {
   return SPH_OK;
 }
 
+int sph_pairs(sph_ctx *ctx, int which, int scene, int *start, int *idx) {
+  if (!ctx) return SPH_E_ORDER;
+  if (scene < 0 || scene >= ctx->n_scenes || !start || which < 0 || which > 3) return SPH_E_ARG;
+  const ScenePar &p = ctx->par[scene];
+  const Dev &D = ctx->D;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  // sorted fluid index (within the scene) -> original index
+  std::vector<int> fid(p.f_count);
+  if (p.f_count && which != 3)
+    HIPCHK(hipMemcpy(fid.data(), D.f_id + p.f_begin, sizeof(int) * p.f_count, hipMemcpyDeviceToHost));
+  std::vector<std::vector<int>> rows;
+  if (which <= 1) {
+    const int n = p.f_count, lw = D.lw, cap = which == 0 ? D.capf : D.capb;
+    const unsigned *list = which == 0 ? D.f_nbl : D.f_bnl;
+    rows.resize(n);
+    std::vector<int2> len(n);
+    std::vector<unsigned> ent((size_t)n * cap);
+    std::vector<int> bsrc(which == 1 ? p.b_count : 0);
+    if (n) {
+      HIPCHK(hipMemcpy(len.data(), D.f_rowlen + p.f_begin, sizeof(int2) * n, hipMemcpyDeviceToHost));
+      // the scene's entries of chunk c (lw entries per particle) are contiguous
+      for (int c = 0; c < cap / lw; ++c)
+        HIPCHK(hipMemcpy(ent.data() + (size_t)c * n * lw, list + ((size_t)c * D.nf + p.f_begin) * lw,
+                         sizeof(unsigned) * (size_t)n * lw, hipMemcpyDeviceToHost));
+    }
+    if (!bsrc.empty())
+      HIPCHK(hipMemcpy(bsrc.data(), D.b_src + p.b_begin, sizeof(int) * p.b_count, hipMemcpyDeviceToHost));
+    for (int k = 0; k < n; ++k) {
+      int L = std::min(which == 0 ? len[k].x : len[k].y, cap);
+      std::vector<int> &r = rows[fid[k]];
+      for (int e = 0; e < L; ++e) {
+        int j = (int)(ent[((size_t)(e / lw) * n + k) * lw + e % lw] & ((1u << 27) - 1u));
+        r.push_back(which == 0 ? fid[j - p.f_begin] : bsrc[j - p.b_begin]);
+      }
+    }
+  } else {
+    const int n = which == 2 ? p.s_count - p.s_nclamp : p.s_count;
+    rows.resize(n);
+    if (n) {
+      std::vector<int> cnt(n);
+      HIPCHK(hipMemcpy(cnt.data(), which == 2 ? D.s_cpl_cnt + p.s_begin : D.s_cnt + p.s_begin, sizeof(int) * n,
+                       hipMemcpyDeviceToHost));
+      int cap = which == 2 ? D.capf : D.maxn, used = 0;
+      for (int a = 0; a < n; ++a) used = std::max(used, std::min(cnt[a], cap));
+      for (int q = 0; q < used; ++q) {
+        std::vector<int> col(n);
+        if (which == 2) {
+          HIPCHK(hipMemcpy(col.data(), D.s_cpl + (size_t)q * D.ns + p.s_begin, sizeof(int) * n,
+                           hipMemcpyDeviceToHost));
+        } else {
+          std::vector<float4> g(n);
+          HIPCHK(hipMemcpy(g.data(), D.s_nbr + (size_t)q * D.ns + p.s_begin, sizeof(float4) * n,
+                           hipMemcpyDeviceToHost));
+          for (int a = 0; a < n; ++a) std::memcpy(&col[a], &g[a].w, sizeof(int));
+        }
+        for (int a = 0; a < n; ++a)
+          if (q < std::min(cnt[a], cap))
+            rows[a].push_back(which == 2 ? fid[(col[a] & ((1 << 27) - 1)) - p.f_begin] : col[a] - p.s_begin);
+      }
+    }
+  }
+  int total = 0;
+  start[0] = 0;
+  for (size_t a = 0; a < rows.size(); ++a) {
+    std::sort(rows[a].begin(), rows[a].end());
+    if (idx) std::memcpy(idx + total, rows[a].data(), sizeof(int) * rows[a].size());
+    total += (int)rows[a].size();
+    start[a + 1] = total;
+  }
+  return total;
+}
+
 int sph_sync(sph_ctx *ctx) {
   if (!ctx) return SPH_E_ORDER;
   std::vector<SceneState> st;
@@ -1039,11 +1153,19 @@ int sph_sync(sph_ctx *ctx) {
       return (e & ERR_CAPACITY) ? SPH_E_CAPACITY : SPH_E_ORDER;
     }
   }
+  // info: a learned step fell back to the plain sub-steps since the last sync
+  unsigned long long fb = 0;
+  for (int s = 0; s < ctx->n_scenes; ++s) fb += st[s].sur_fallback;
+  if (fb > ctx->fallback_seen) {
+    ctx->fallback_seen = fb;
+    return SPH_FALLBACK;
+  }
   return SPH_OK;
 }
 
 int sph_time_kernel(sph_ctx *ctx, int kernel, int reps, double *avg_ms) {
   if (!ctx) return SPH_E_ORDER;
+  if (check_phase(ctx, "sph_time_kernel", 0) != SPH_OK) return SPH_E_ORDER;
   ctx->kappa_ready = 0;  // the state may change: the next step reads kappa at its solid phase
   if (reps <= 0 || !avg_ms || kernel < SPH_K_FLUID_FORCE || kernel > SPH_K_REBUILD) return SPH_E_ARG;
   hipStream_t st = ctx->stream;

@@ -940,6 +940,7 @@ __device__ void gather_boundary(const Dev &D, const ScenePar &P, int k, int q) {
   float sa = 0.0f;
   for (int i = 0; i < DIM; ++i) sa += (ab[i] - P.g[i]) * n[i];
   sa = fmaxf(0.0f, sa);
+  D.b_src[k] = local;
   D.b_pos[k] = make_float4((float)off.x, (float)off.y, (float)off.z, V);
   D.b_posd[k] = off;
   D.b_vbar[k] = make_float4(vb[0], vb[1], vb[2], sa);

@@ -127,6 +127,7 @@ struct Dev {
   double4 *b_posd; // frozen offset in FP64
   int *b_perm, *bs_lin, *bs_slot, *bs_scene;
   int *b_solid;  // per boundary slot: its solid particle, or -1 for a wall
+  int *b_src;    // per boundary slot: its source index within the scene (walls first, then free solid)
   double4 *bs_off;
   // solid (per scene in original order), SoA with component stride ns
   int ns, maxn;

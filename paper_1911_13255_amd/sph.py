@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(PKG, "libmrsph.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "mrsph.h")
 
 SPH_OK, SPH_E_ARG, SPH_E_HIP, SPH_E_ORDER, SPH_E_CAPACITY, SPH_E_UNSTABLE = 0, -1, -2, -3, -4, -5
+SPH_FALLBACK = 1  # info code of sph_sync
 K_FLUID_FORCE, K_CONTINUITY, K_COUPLE, K_SOLID, K_REBUILD = 0, 1, 2, 3, 4
 F_X, F_V, F_RHO, F_DRHO, F_A, F_P, F_NNB = 0, 1, 2, 3, 4, 5, 6
 S_U, S_V, S_A, S_F, S_DF, S_FF, S_VBAR, S_ABAR, S_N, S_B, S_N0, S_X0 = range(10, 22)
@@ -111,6 +112,7 @@ def lib():
                                    C.c_int, C.c_int, C.POINTER(SphOptions), _dp]
         L.sph_reduce.argtypes = [vp, C.c_int, _dp]
         L.sph_time_kernel.argtypes = [vp, C.c_int, C.c_int, _dp]
+        L.sph_pairs.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.sph_last_error.restype = C.c_char_p
         L.sph_last_error.argtypes = [vp]
         L.sph_destroy.argtypes = [vp]
@@ -275,7 +277,8 @@ class Simulation:
         self.ctx = ctx
 
     def _check(self, rc):
-        if rc != SPH_OK:
+        """Raise on an error code; positive info codes are returned."""
+        if rc < SPH_OK:
             raise SphError(rc, self.L.sph_last_error(self.ctx).decode())
         return rc
 
@@ -427,6 +430,22 @@ class Simulation:
         return dict(mom_fluid=out[0:3].copy(), mom_solid=out[3:6].copy(), ke_fluid=out[6],
                     ke_solid=out[7], strain_energy=out[8], sum_fF=out[9:12].copy(),
                     sum_fS=out[12:15].copy())
+
+    def pairs(self, which: int, scene: int = 0):
+        """(start, idx) CSR neighbour lists at the last rebuild in original
+        order, rows sorted (see sph_pairs): which 0 fluid-fluid, 1 fluid-boundary
+        (walls, then n_wall + free solid index), 2 free solid-fluid,
+        3 solid-solid reference."""
+        sc = self._scene_dicts[scene]
+        n = {0: self.nf[scene], 1: self.nf[scene], 2: self.ns[scene] - int(sc["n_clamp"]),
+             3: self.ns[scene]}[which]
+        start = np.zeros(n + 1, dtype=np.int32)
+        ip = C.POINTER(C.c_int)
+        cnt = self._check(self.L.sph_pairs(self.ctx, int(which), int(scene), start.ctypes.data_as(ip), None))
+        idx = np.zeros(max(cnt, 1), dtype=np.int32)
+        self._check(self.L.sph_pairs(self.ctx, int(which), int(scene), start.ctypes.data_as(ip),
+                                     idx.ctypes.data_as(ip)))
+        return start, idx[:cnt]
 
     def time_kernel(self, kernel: int, reps: int = 100) -> float:
         """Average milliseconds per launch of one kernel (HIP events on the stream)."""

@@ -7,6 +7,16 @@ depends only on particles within 4 h_F of it (its neighbours within 2 h_F and
 their own neighbourhoods through the density reinitialisation), so the oracle
 runs a crop of radius 4 h_F + dp_F around each sample and must give that
 particle the same acceleration as the full GPU run.
+
+The plate of the 3D dam break (354k solid particles, the streamed sub-step
+passes over 173 blocks) is checked the same way: within one acoustic step a
+solid particle's state depends on the solid within 4 h_S per sub-step (its
+neighbours' stress, which depends on their neighbours' velocities), so after
+kappa sub-steps on the solid within (4 kappa + 2) h_S, and on correct
+correction matrices there, 2 h_S further.  The step's kappa depends on the
+largest solid speed of the whole plate: a written velocity bump puts that
+maximum on one particle deep in the plate's index range, and every crop also
+holds that particle, so each crop takes the same kappa as the full run.
 """
 import numpy as np
 import pytest
@@ -69,13 +79,17 @@ def test_all_64_batched_scenes(gpu):
     sim.close()
 
 
-def crop(sc, center, radius):
-    """The scene restricted to the particles within `radius` of `center`
-    (order kept, so the clamp block stays last)."""
+def crop(sc, center, radius, extra=()):
+    """The scene restricted to the particles within `radius` of `center`, and
+    within each (center, radius) of `extra` (order kept, so the clamp block
+    stays last)."""
     out = dict(sc)
 
     def within(x):
-        return np.where(np.linalg.norm(x - center, axis=1) <= radius)[0]
+        keep = np.linalg.norm(x - center, axis=1) <= radius
+        for c, r in extra:
+            keep |= np.linalg.norm(x - c, axis=1) <= r
+        return np.where(keep)[0]
 
     fi = within(sc["x_fluid"])
     wi = within(sc["x_wall"])
@@ -87,22 +101,50 @@ def crop(sc, center, radius):
     out["x_solid"] = sc["x_solid"][si] if len(si) else np.zeros((0, sc["dim"]))
     out["n_clamp"] = int(np.sum(si >= n_s - int(sc["n_clamp"])))
     out["tip_index"] = 0
+    out["_solid_index"] = si
     return out, fi
+
+
+SOLID_FIELDS = ((sph.S_U, "u_s"), (sph.S_V, "v_s"), (sph.S_F, "F"), (sph.S_DF, "dF"), (sph.S_VBAR, "vbar"),
+                (sph.S_ABAR, "abar"), (sph.S_A, "a_s"))
+
+
+def plate_bump(sc):
+    """Velocity bump of 1 m/s on the free plate (Gaussian, 15 mm), its unique
+    maximum on the free particle nearest (0.8345, 0.45, 0.2), deep in the plate's
+    index range (the last blocks of the solid reductions)."""
+    xs = sc["x_solid"]
+    nfree = len(xs) - int(sc["n_clamp"])
+    p = int(np.argmin(np.linalg.norm(xs[:nfree] - np.array([0.8345, 0.45, 0.2]), axis=1)))
+    dirv = np.array([1.0, 0.3, -0.5])
+    dirv /= np.linalg.norm(dirv)
+    w = np.exp(-np.sum((xs - xs[p]) ** 2, axis=1) / 0.015 ** 2)
+    v = w[:, None] * dirv[None, :]
+    v[nfree:] = 0.0
+    return v, p
 
 
 def test_dam_break_3d_sampled_first_step(gpu):
     sc = scenes.dam_break_plate_3d(seed=1)
     nf = len(sc["x_fluid"])
-    note(f"3D dam break full size: {nf} fluid, {len(sc['x_solid'])} solid")
+    ns = len(sc["x_solid"])
+    note(f"3D dam break full size: {nf} fluid, {ns} solid")
     sim = sph.Simulation(sc)
     # the plate's reference configuration is its lattice: the streamed solid
     # passes walk the compact table
     assert sim.solid_table()["compact"] == 1
+    assert not sim.solid_register_resident()
+    vs, pstar = plate_bump(sc)
+    assert pstar > 0.7 * ns
+    sim.write(sph.S_V, vs)
     sim.step()
     a_gpu = sim.read(sph.F_A)
     rho_gpu = sim.read(sph.F_RHO)
+    solid_gpu = {f: sim.read(f) for f, _ in SOLID_FIELDS}
+    kappa_gpu = sim.scalars()["kappa"]
     sim.sync()
     sim.close()
+    note(f"3D dam break: GPU step done, kappa {kappa_gpu:.0f}")
     x = sc["x_fluid"]
     rng = np.random.default_rng(2024)
     hf, dpf = sc["h_ratio"] * sc["dp_f"], sc["dp_f"]
@@ -128,3 +170,41 @@ def test_dam_break_3d_sampled_first_step(gpu):
     note(f"3D sampled first step: {len(samples)} samples, acceleration error {err_a:.2e}, density error {err_rho:.2e}")
     assert err_a <= 1e-4
     assert err_rho <= 1e-6
+    # the plate: samples at the bump, beside it, at the clamp, the free top
+    # edge, a side edge and inside
+    xs = sc["x_solid"]
+    nfree = ns - int(sc["n_clamp"])
+    hs, dps = sc["h_ratio"] * sc["dp_s"], sc["dp_s"]
+
+    def nearest(p):
+        return int(np.argmin(np.linalg.norm(xs[:nfree] - np.asarray(p), axis=1)))
+
+    ssamples = [pstar, nearest(xs[pstar] + [0.0, 0.02, 0.01]), nearest([0.8015, 0.3, 0.0015]),
+                nearest([0.8385, 0.05, 0.0045]), nearest([0.82, 0.2, 0.3985]), nearest([0.8015, 0.0015, 0.2]),
+                int(rng.integers(0, nfree))]
+    kap = int(round(kappa_gpu))
+    R = (4 * kap + 4) * hs + dps
+    ref = {name: [] for _, name in SOLID_FIELDS}
+    smp = {name: [] for _, name in SOLID_FIELDS}
+    for a in ssamples:
+        sub, _ = crop(sc, xs[a], R, extra=((xs[pstar], 1.5 * dps),))
+        si = sub.pop("_solid_index")
+        o = O.Oracle(sub)
+        o.set(O.S_V, vs[si])
+        o.step(1)
+        assert int(o.scalars()["kappa"]) == kap, (a, o.scalars()["kappa"], kap)
+        k = int(np.where(si == a)[0][0])
+        for f, name in SOLID_FIELDS:
+            r, g = o.get(f)[k], solid_gpu[f][a]
+            if f == sph.S_F:
+                r, g = r - np.eye(3), g - np.eye(3)
+            ref[name].append(r)
+            smp[name].append(g)
+    errs = {}
+    for name in ref:
+        r, g = np.array(ref[name]), np.array(smp[name])
+        errs[name] = np.abs(g - r).max() / np.abs(r).max()
+    note(f"3D plate: {len(ssamples)} samples, kappa {kap}, crop radius {R:.4f} m, errors " +
+         ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for name, e in errs.items():
+        assert e <= 1e-4, (name, e)

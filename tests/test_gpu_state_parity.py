@@ -1,0 +1,214 @@
+"""Parity of the parts the per-step comparisons leave out: the updated surface
+normals, the FP64 reductions, the streamed solid passes on solids that span
+several blocks, and the plate-tip trajectory of the channel.
+
+- Normals (reading of Section 3.2: n = normalise(F^-T n0), updated at each
+  advection-step start): a rotated and stretched F is written on both sides.
+- Reductions (Section 3.3, the momentum argument; the energies): sph_reduce
+  against the oracle's totals on the same written state.
+- Streamed solid (Section 3.3, kappa position-based Verlet sub-steps;
+  Algorithm 1's solid loop): periodic boxes whose solid holds several blocks
+  of the step-end and time-step reductions, over separate calls and several
+  sph_advance calls (the next step's kappa is reduced at each step's end).
+- Channel tip (Section 4.1 geometry): the tip displacement against the
+  oracle's over 6,000 acoustic steps.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1911_13255_amd import scenes, sph
+
+pytestmark = pytest.mark.gpu
+
+STATE_FIELDS = (sph.F_X, sph.F_V, sph.F_RHO, sph.F_DRHO, sph.S_U, sph.S_V, sph.S_A, sph.S_F, sph.S_DF,
+                sph.S_VBAR, sph.S_ABAR)
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_inf(g, r):
+    den = np.abs(r).max() if r.size else 0.0
+    err = np.abs(g - r).max() if r.size else 0.0
+    return err / den if den > 0 else err
+
+
+def inject(sim, ora, scene=0):
+    for f in STATE_FIELDS:
+        if f >= 10 and ora.ns == 0:
+            continue
+        sim.write(f, ora.get(f), scene)
+    s = ora.scalars()
+    sim.set_scalars(scene, t=s["t"], adv_accum=0.0, dt_ad=s["dt_ad"], need_rebuild=1)
+
+
+def rotation(d, th):
+    if d == 2:
+        return np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    ax = np.array([1.0, -2.0, 0.5])
+    ax /= np.linalg.norm(ax)
+    K = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+    return np.eye(3) + math.sin(th) * K + (1 - math.cos(th)) * K @ K
+
+
+@pytest.mark.parametrize("name", ["dam_break_plate", "box3d"])
+def test_updated_normals(gpu, name):
+    sc = scenes.dam_break_plate(seed=1) if name == "dam_break_plate" else \
+        scenes.periodic_box_with_solid(dim=3, n=12, amp=0.0)
+    d = int(sc["dim"])
+    note(f"normals {name}")
+    sim = sph.Simulation(sc)
+    o = O.Oracle(sc)
+    ns = len(sc["x_solid"])
+    nfree = ns - int(sc["n_clamp"])
+    rng = np.random.default_rng(8)
+    F = np.empty((ns, d, d))
+    for a in range(ns):
+        S = rng.standard_normal((d, d))
+        F[a] = rotation(d, rng.uniform(-0.6, 0.6)) @ (np.eye(d) + 0.15 * 0.5 * (S + S.T))
+    sim.write(sph.S_F, F)
+    o.set(O.S_F, F)
+    sim.neighbor_build()
+    o.rebuild()
+    ng, no = sim.read(sph.S_N)[:nfree], o.get(O.S_N)[:nfree]
+    n0 = o.get(O.S_N0)[:nfree]
+    has = np.linalg.norm(n0, axis=1) > 0
+    assert has.sum() > 10
+    # the update really turns the normals
+    assert np.abs(no[has] - n0[has]).max() > 0.1
+    err = np.abs(ng - no).max()
+    note(f"{name}: normal error {err:.2e} over {has.sum()} surface particles")
+    assert err <= 1e-5
+    assert np.all(ng[~has] == 0.0)
+    sim.fluid_step()
+    sim.couple()
+    sim.solid_substeps()
+    sim.sync()
+    sim.close()
+
+
+@pytest.mark.parametrize("dim,material", [(2, 0), (2, 1), (3, 0)])
+def test_reductions_match_the_oracle_totals(gpu, dim, material):
+    sc = scenes.periodic_box_with_solid(dim=dim, n=16 if dim == 2 else 8, eta=0.5, amp=0.3)
+    sc["material"] = material
+    note(f"reductions dim {dim} material {material}")
+    o = O.Oracle(sc)
+    o.step(15)
+    while not o.scalars()["need_rebuild"]:
+        o.step(1)
+    sim = sph.Simulation(sc)
+    inject(sim, o)
+    red, tot = sim.reduce(0), o.totals()
+    assert tot["strain_energy"] > 0 and tot["ke_solid"] > 0
+    for k in ("mom_fluid", "mom_solid"):
+        scale = np.abs(red[k]).max() + 1e-300
+        err = np.abs(red[k][:dim] - tot[k][:dim]).max()
+        note(f"  {k}: gpu {red[k][:dim]} oracle {tot[k][:dim]}")
+        # momenta are sums of terms of both signs: compare against the sum of |m v|
+        mv = sim.read(sph.F_V) if k == "mom_fluid" else sim.read(sph.S_V)
+        m = (sc["rho0_f"] * sc["dp_f"] ** dim) if k == "mom_fluid" else (sc["rho0_s"] * sc["dp_s"] ** dim)
+        assert err <= 1e-6 * m * np.abs(mv).sum(), (k, err, scale)
+    for k in ("ke_fluid", "ke_solid", "strain_energy"):
+        e = abs(red[k] - tot[k]) / abs(tot[k])
+        note(f"  {k}: gpu {red[k]:.9e} oracle {tot[k]:.9e} rel {e:.2e}")
+        assert e <= 1e-6, k
+    # one step later, from the same state: the summed coupling force
+    sim.step()
+    o.step(1)
+    red, tot = sim.reduce(0), o.totals()
+    fF = o.get(O.S_FF)
+    e = np.abs(red["sum_fF"][:dim] - tot["sum_fF"][:dim]).max() / np.abs(fF).sum()
+    note(f"  sum fF: gpu {red['sum_fF'][:dim]} oracle {tot['sum_fF'][:dim]} rel {e:.2e}")
+    assert e <= 1e-5
+    for k in ("ke_fluid", "ke_solid", "strain_energy"):
+        assert abs(red[k] - tot[k]) <= 1e-4 * abs(tot[k]), k
+    sim.sync()
+    sim.close()
+
+
+COMPARED = ((sph.F_RHO, "rho"), (sph.F_DRHO, "drho"), (sph.F_A, "a_f"), (sph.S_FF, "fF"), (sph.S_U, "u_s"),
+            (sph.S_V, "v_s"), (sph.S_F, "F"), (sph.S_DF, "dF"), (sph.S_VBAR, "vbar"), (sph.S_ABAR, "abar"),
+            (sph.S_A, "a_s"))
+
+
+def compare(sim, o, label, tol=1e-4):
+    worst = {}
+    for f, name in COMPARED:
+        g, r = sim.read(f), o.get(f)
+        if f == sph.S_F:
+            g, r = g - np.eye(o.dim), r - np.eye(o.dim)
+        if np.abs(r).max() == 0.0:
+            continue
+        worst[name] = rel_inf(g, r)
+    note(f"{label}: " + ", ".join(f"{k}={v:.2e}" for k, v in worst.items()))
+    for k, v in worst.items():
+        assert v <= tol, (label, k, v)
+
+
+@pytest.mark.parametrize("dim,n,lattice", [(2, 160, False), (3, 38, True), (3, 38, False)])
+def test_streamed_solid_over_several_blocks(gpu, dim, n, lattice):
+    # (n/2)^dim solid particles: 6,400 in 2D, 6,859 in 3D, over the 2,048
+    # particles of a block of the step-end and time-step reductions
+    sc = scenes.periodic_box_with_solid(dim=dim, n=n, eta=0.5, amp=0.3, solid_lattice=lattice)
+    ns = len(sc["x_solid"])
+    note(f"streamed solid dim {dim}: {len(sc['x_fluid'])} fluid, {ns} solid, lattice {lattice}")
+    assert ns > 3 * 2048
+    sim = sph.Simulation(sc, solid_lds=1)
+    assert not sim.solid_register_resident()
+    assert sim.solid_table()["compact"] == (1 if (lattice and dim == 3) else 0)
+    o = O.Oracle(sc)
+    for k in range(2):
+        sim.step()
+        o.step(1)
+        compare(sim, o, f"dim {dim} call step {k + 1}")
+        assert sim.scalars()["kappa"] == o.scalars()["kappa"]
+    for k in range(3):
+        sim.advance(2)
+        o.step(2)
+        compare(sim, o, f"dim {dim} advance {2 * k + 4}")
+        assert sim.scalars()["kappa"] == o.scalars()["kappa"]
+    assert o.scalars()["kappa"] > 1
+    assert sim.counters(0)["substeps"] == o.counters()["substeps"]
+    sim.sync()
+    sim.close()
+
+
+def test_channel_tip_trajectory_within_one_percent(gpu):
+    # The plate behind the cylinder (config of Section 4.1's shape, 17,444 fluid
+    # particles): tip = free-end, mid-thickness particle; error = max over the
+    # run of |u_gpu(t) - u_oracle(t)| / max |u_oracle|, the GPU trajectory
+    # interpolated to the oracle's times.  6,000 steps reach t = 2.1 s, with
+    # the tip moving by up to about 2 mm across the channel.
+    sc = scenes.plate_behind_cylinder(seed=1)
+    tip = int(sc["tip_index"])
+    steps, every = 6000, 20
+    note(f"channel tip trajectory, {steps} steps")
+    sim = sph.Simulation(sc)
+    o = O.Oracle(sc)
+    ug, tg, uo, to = [], [], [], []
+    for _ in range(steps // every):
+        sim.advance(every)
+        o.step(every)
+        ug.append(sim.read(sph.S_U)[tip])
+        tg.append(sim.scalars()["t"])
+        uo.append(o.get(O.S_U)[tip])
+        to.append(o.scalars()["t"])
+    ug, tg, uo, to = map(np.array, (ug, tg, uo, to))
+    umax = np.linalg.norm(uo, axis=1).max()
+    keep = to <= tg[-1]
+    ui = np.stack([np.interp(to[keep], tg, ug[:, k]) for k in range(2)], axis=1)
+    err = np.linalg.norm(ui - uo[keep], axis=1)
+    e = err.max() / umax
+    worst = int(np.argmax(err))
+    note(f"channel tip: max |u_oracle| {umax:.4e} m, error {e:.3e} (worst at step {(worst + 1) * every}), "
+         f"time drift {abs(tg[-1] - to[-1]) / to[-1]:.2e}")
+    assert umax > 1e-3
+    assert e <= 0.01
+    sim.sync()
+    sim.close()
