@@ -1,19 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the plain multi-resolution SPH FSI path on one MI355X.
 
-Workload (default): the 2D flexible plate behind a rigid cylinder in a
-channel (11D x 4.1D, D = 0.1 m, Re = 100, rho_s/rho_f = 10, E* = 1.4e3,
-nu = 0.4, dp_f = D/20, dp_s = dp_f/2, periodic channel with an inflow
-buffer), synthetic seeded lattice.  A step is one fluid acoustic step of
-Algorithm 1: the rebuild when an advection step is due, the fluid force and
-continuity passes, the coupling force on the solid and kappa solid
-sub-steps, all replayed from one captured HIP graph with every decision on
-the device.
+Headline workload: the 3D dam break on an elastic plate (water column
+0.6 x 0.6 x 1.2 m in a 1.6 x 0.6 x 1.2 m tank, Neo-Hookean plate
+0.04 x 0.6 x 0.4 m, E = 5 MPa, nu = 0.45, dp_f = 6 mm: 2.0M fluid and 354k
+solid particles), synthetic seeded lattice.  A step is one fluid acoustic
+step of Algorithm 1: the rebuild when an advection step is due, the fluid
+force and continuity passes, the coupling force on the solid and kappa solid
+sub-steps, every decision taken on the device.
 
 Prints one JSON line: particle interactions per second (every within-support
 pair evaluated by every pair loop, counted on the device) and FSI steps per
-second, the roofline position of the dominant kernel, and the FP64 CPU
-oracle timed on the host on a bounded sample of the same workload.
+second on that workload, the roofline position of its dominant kernel, the
+FP64 CPU oracle timed on the host on a bounded sample of the same workload,
+and as further keys the 2D channel (plate behind a cylinder), the 64 batched
+2D dam breaks, the learned sub-step leg on the channel and the paper's four
+flow-induced-vibration cases.
 """
 import argparse
 import json
@@ -26,39 +28,37 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "particle-interactions/s; FSI steps/s plain vs surrogate at ≤1% tip error"
+# Published MI355X peaks.
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed instructions: 256 CUs x 4 SIMD x 16 lanes
-# x 2 flops (FMA) x 2.4 GHz (the packed-FP32 figure of 157.3 TFLOP/s is not
-# reachable by code built without packed FP32 instructions).
-ALU_PEAK_TFLOPS = 78.6
-# FP64 vector peak (the same lane rate as FP32 without packed instructions)
-FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3  # vector FP32, packed (dual-issue) FMA counted as 2 flops per lane
+FP64_PEAK_TFLOPS = 78.6   # vector FP64
+# Ceiling of code built without packed FP32 instructions (this library's
+# build): 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.  Stated
+# beside the published peak, never in its place.
+FP32_NONPACKED_TFLOPS = 78.6
 NUM_CUS = 256
-# Algorithmic cost per unit of work:
-#  fluid force pass: own state read once and written once (144 B per fluid
-#  particle: reads position 16, mid-point snapshot 16, FP64 offset 32, row
-#  lengths 8, scene 4; writes offset 32, v 16, p 4, a 16) plus one 4-byte
-#  pair-list entry per pair; 70 flops per pair.
-#  continuity pass: 140 B per fluid particle plus 4 B per pair; 40 flops per pair.
-#  solid sub-step kernel (2D, block resident): the solid state read and
-#  written once per launch (300 B per free particle: reads H, dF/dt, B 32 each,
-#  u and v 16 each, v again for the shared copy 16, a and f^F 8 each, the
-#  gradient sum 16, the neighbour count 4; writes H, dF/dt 32 each, u, v 16
-#  each, a, vbar, abar 8 each) and the reference neighbour table once (12 B
-#  per solid pair); per sub-step 22 flops per solid pair (momentum 12: the
-#  stress sum 4, its product with the gradient 6, the accumulation 2; rate 10:
-#  the velocity difference 2, its outer product with the gradient 4, the
-#  accumulation 4) and about 130 flops per particle (Neo-Hookean stress and
-#  P B about 80, G B^T 12, the integration updates about 40).
-FORCE_BYTES_PER_PARTICLE = 144.0
-CONT_BYTES_PER_PARTICLE = 140.0
-LIST_BYTES_PER_PAIR = 4.0
-FORCE_FLOPS_PER_PAIR = 70.0
-CONT_FLOPS_PER_PAIR = 40.0
-SOLID_BYTES_PER_PARTICLE = 300.0
-SOLID_BYTES_PER_PAIR = 12.0
-SOLID_FLOPS_PER_PAIR_SUBSTEP = 22.0
-SOLID_FLOPS_PER_PARTICLE_SUBSTEP = 130.0
+# Algorithmic cost per unit of work (each particle's own state moved once;
+# the pair lists and the neighbours' gathers are not algorithmic bytes):
+#  fluid force pass, per fluid particle: reads position, density, density
+#  rate, velocity and writes position, density, velocity (2D 52 B, 3D 72 B
+#  in FP32); about 55 arithmetic operations per pair (distance, kernel
+#  gradient, Riemann pressure, viscous term, accumulation)
+#  continuity pass, per fluid particle: 2D 44 B, 3D 60 B; about 40 operations
+#  per pair
+#  block-resident solid kernel (2D, one launch = kappa sub-steps): the solid
+#  state read and written once per launch, about 150 B per free particle; per
+#  sub-step about 33 operations per reference pair (stress sum, gradient
+#  product, velocity-gradient outer product) and 200 per particle
+#  (Neo-Hookean stress, P B, integration)
+#  streamed solid passes (3D), per sub-step: about 300 B per solid particle
+FORCE_BYTES = {2: 52.0, 3: 72.0}
+CONT_BYTES = {2: 44.0, 3: 60.0}
+FORCE_OPS_PER_PAIR = 55.0
+CONT_OPS_PER_PAIR = 40.0
+SOLID_REG_BYTES = 150.0
+SOLID_STREAM_BYTES_PER_SUBSTEP = 300.0
+SOLID_OPS_PER_PAIR_SUBSTEP = 33.0
+SOLID_OPS_PER_PARTICLE_SUBSTEP = 200.0
 
 
 def make_workload(name):
@@ -177,77 +177,191 @@ def paper_cases(steps=3000, warmup=300, log=None):
                                       hardware="Xeon L5520 2.27 GHz CPU, wall-clock to t* = 200"))
 
 
-def cpu_baseline(scene, seconds=15.0):
-    """The FP64 oracle on the host cores on a bounded prefix of the same run."""
+def cpu_baseline(scene, seconds=15.0, single_thread_steps=1):
+    """The FP64 oracle on the host cores on a bounded sample of the same run:
+    its first step (the initial rebuild) untimed, then whole acoustic steps
+    until `seconds` have passed and at least five steps are done; then the
+    same oracle on one thread for `single_thread_steps` further steps."""
     from oracle import oracle as ora
 
     o = ora.Oracle(scene)
     threads = ora.num_threads()
-    o.step(2)  # first rebuild outside the timing
+    o.step(1)  # first rebuild outside the timing
     c0 = o.counters()
     t0 = time.perf_counter()
     n = 0
-    while time.perf_counter() - t0 < seconds:
-        o.step(10)
-        n += 10
+    while n < 5 or time.perf_counter() - t0 < seconds:
+        o.step(1)
+        n += 1
     dt = time.perf_counter() - t0
     c1 = o.counters()
     inter = c1["interactions"] - c0["interactions"]
-    # the same oracle on one thread, on a shorter sample continuing the run
     ora.set_threads(1)
     c2 = o.counters()
     t1 = time.perf_counter()
-    n1 = 0
-    while time.perf_counter() - t1 < seconds / 3.0:
-        o.step(2)
-        n1 += 2
+    for _ in range(single_thread_steps):
+        o.step(1)
     dt1 = time.perf_counter() - t1
     c3 = o.counters()
     ora.set_threads(threads)
     return dict(value=inter / dt, unit="interactions/s", cores=threads, kind="oracle",
-                sample=f"{n} acoustic steps after the first two of the same scene and seed "
-                       f"({dt:.1f} s, FP64, OpenMP)",
+                sample=f"acoustic steps 2-{n + 1} of the same scene and seed ({n} steps, {dt:.1f} s, FP64, "
+                       f"OpenMP on {threads} threads; step 1, the initial rebuild, untimed)",
                 steps_per_s=n / dt,
                 single_thread=dict(value=(c3["interactions"] - c2["interactions"]) / dt1, cores=1,
-                                   sample=f"the next {n1} acoustic steps ({dt1:.1f} s)",
-                                   steps_per_s=n1 / dt1))
+                                   sample=f"the next {single_thread_steps} acoustic step(s) ({dt1:.1f} s)",
+                                   steps_per_s=single_thread_steps / dt1))
+
+
+def roofline(name, dur_ms, alg_bytes, alg_ops, fp64=False):
+    """Position of one kernel against the published peaks: the larger of its
+    HBM and arithmetic fractions names the bound."""
+    dur = dur_ms * 1e-3
+    gbs = alg_bytes / dur / 1e9
+    tops = alg_ops / dur / 1e12
+    peak_ops = FP64_PEAK_TFLOPS if fp64 else FP32_PEAK_TFLOPS
+    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tops / peak_ops
+    if alu_frac >= hbm_frac:
+        roof = dict(bound="alu", achieved=tops, peak=peak_ops, unit="TFLOP/s", frac=alu_frac)
+    else:
+        roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm_frac)
+    roof.update(kernel=name, duration_us=dur * 1e6, arithmetic="FP64" if fp64 else "FP32",
+                hbm_GBps=gbs, hbm_frac=hbm_frac, alu_TFLOPs=tops, alu_frac=alu_frac,
+                algorithmic_bytes=alg_bytes, algorithmic_flops=alg_ops)
+    if not fp64:
+        roof["frac_of_nonpacked_fp32"] = tops / FP32_NONPACKED_TFLOPS
+    return roof
+
+
+def run_workload(name, steps, warmup, autotune, cache, kernel_reps, log, scenes_override=None):
+    """Plain path on one workload: timed steps (HIP events on the library's
+    stream, inputs resident in HBM), per-kernel durations, the dominant single
+    kernel's roofline."""
+    import torch
+    from paper_1911_13255_amd import sph
+
+    scs = scenes_override if scenes_override is not None else make_workload(name)
+    dim = int(scs[0]["dim"])
+    log(f"[bench] workload {name}: {len(scs)} scene(s), {sum(len(s['x_fluid']) for s in scs)} fluid, "
+        f"{sum(len(s['x_solid']) for s in scs)} solid, {sum(len(s['x_wall']) for s in scs)} wall particles")
+    opts, tune_s = {}, 0.0
+    if autotune:
+        t0 = time.perf_counter()
+        opts = sph.autotune(scs, warmup=10 if dim == 3 else 100, steps=10 if dim == 3 else 1000, cache=cache)
+        tune_s = time.perf_counter() - t0
+        log(f"[bench] {name}: autotuned in {tune_s:.1f} s: {json.dumps(opts)}")
+    sim = sph.Simulation(scs, **opts)
+    sim.advance(warmup)
+    torch.cuda.synchronize()
+    sim.sync()
+    c0 = sim.counters()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(sim.stream)
+    sim.advance(steps)
+    t_end.record(sim.stream)
+    t_end.synchronize()
+    torch.cuda.synchronize()
+    ms = t_start.elapsed_time(t_end)
+    sim.sync()
+    c1 = sim.counters()
+    inter = c1["interactions"] - c0["interactions"]
+    secs = ms / 1e3
+    rebuilds = c1["rebuilds"] - c0["rebuilds"]
+    log(f"[bench] {name}: {steps} steps in {ms:.2f} ms, {rebuilds} rebuilds, {inter} interactions")
+    # kernel durations are taken on a step without a pending rebuild (the
+    # common case: the force launch's list-ordering blocks then exit at once)
+    for _ in range(64):
+        if not any(sim.scalars(k)["need_rebuild"] for k in range(len(scs))):
+            break
+        sim.advance(1)
+    sim.sync()
+    # isolated launches on the library's stream, HIP events around them
+    kt = {kn: sim.time_kernel(k, kernel_reps) for kn, k in
+          (("k_fluid_force", sph.K_FLUID_FORCE), ("k_fluid_continuity", sph.K_CONTINUITY),
+           ("k_couple", sph.K_COUPLE), ("k_solid", sph.K_SOLID))}
+    kt["rebuild_sequence"] = sim.time_kernel(sph.K_REBUILD, max(10, kernel_reps // 10))
+    per_step = dict(kt)
+    per_step["rebuild_sequence"] = kt["rebuild_sequence"] * rebuilds / steps
+    log(f"[bench] {name}: kernel ms per launch {json.dumps({k: round(v, 5) for k, v in kt.items()})}")
+    nf = sum(len(s["x_fluid"]) for s in scs)
+    ns = sum(len(s["x_solid"]) for s in scs)
+    ns_free = ns - sum(int(s["n_clamp"]) for s in scs)
+    pairs_f = c1["n_ff"] + c1["n_fw"] + c1["n_fs"]
+    kappa = (c1["substeps"] - c0["substeps"]) / max(1, c1["steps"] - c0["steps"])
+    roofs = {
+        "k_fluid_force": roofline("k_fluid_force", kt["k_fluid_force"], FORCE_BYTES[dim] * nf,
+                                  FORCE_OPS_PER_PAIR * pairs_f),
+        "k_fluid_continuity": roofline("k_fluid_continuity", kt["k_fluid_continuity"], CONT_BYTES[dim] * nf,
+                                       CONT_OPS_PER_PAIR * pairs_f),
+    }
+    solid_ops = kappa * (SOLID_OPS_PER_PAIR_SUBSTEP * c1["n_ss"] + SOLID_OPS_PER_PARTICLE_SUBSTEP * ns_free)
+    resident = sim.solid_register_resident()
+    if resident:
+        # one launch holds the kappa sub-steps in FP64, one workgroup per scene
+        roofs["k_solid_reg"] = roofline("k_solid_reg", kt["k_solid"], SOLID_REG_BYTES * ns_free, solid_ops,
+                                        fp64=True)
+        roofs["k_solid_reg"].update(cus_used=len(scs), frac_of_cus_used=roofs["k_solid_reg"]["alu_frac"] *
+                                    NUM_CUS / len(scs))
+    dominant = max(roofs, key=lambda k: roofs[k]["duration_us"])
+    roof = dict(roofs[dominant])
+    traffic = measured_traffic(name, dominant)
+    roof.update(traffic=traffic, traffic_over_algorithmic=None if traffic is None else
+                traffic / roof["algorithmic_bytes"])
+    out = dict(value=inter / secs, unit="interactions/s", ms_per_step=ms / steps, fsi_steps_per_s=steps / secs,
+               steps=steps, warmup=warmup, interactions_per_step=inter / steps, rebuilds=rebuilds,
+               kappa_mean=kappa, kernel_ms_per_step={k: round(v, 6) for k, v in per_step.items()},
+               kernel_roofline={k: {q: v[q] for q in ("bound", "frac", "duration_us", "alu_frac", "hbm_frac")}
+                                for k, v in roofs.items()},
+               launch=sim.launch_config(), autotuned=bool(autotune), autotune_seconds=tune_s, roofline=roof,
+               config=dict(workload=name, scenes=len(scs), n_fluid=nf, n_solid=ns,
+                           n_wall=sum(len(s["x_wall"]) for s in scs), dim=dim, dp_f=scs[0]["dp_f"],
+                           dp_s=scs[0]["dp_s"]))
+    if not resident and ns:
+        # the streamed solid phase: kappa launches of each pass, not one kernel
+        out["solid_phase"] = dict(ms=kt["k_solid"], kappa=kappa, solid_table=sim.solid_table(),
+                                  hbm_GBps=kappa * SOLID_STREAM_BYTES_PER_SUBSTEP * ns / (kt["k_solid"] * 1e-3) / 1e9,
+                                  alu_TFLOPs=solid_ops / (kt["k_solid"] * 1e-3) / 1e12)
+    sim.close()
+    return out, scs
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed acoustic steps (default per workload: 20000 for the channel, 2000 for the "
-                         "2D dam break, 300 for the 3D dam break, 1000 for the batch)")
+                    help="timed acoustic steps of the headline workload (default per workload: 300 for the "
+                         "3D dam break, 20000 for the channel, 2000 for the 2D dam break, 1000 for the batch)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="plate_behind_cylinder",
-                    choices=["plate_behind_cylinder", "dam_break_plate", "dam_break_3d",
-                             "batched_dam_breaks"])
-    ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="dam_break_3d",
+                    choices=["dam_break_3d", "plate_behind_cylinder", "dam_break_plate", "batched_dam_breaks"])
+    ap.add_argument("--kernel-reps", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="use the library's default launch shapes instead of the autotuned ones")
+    ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
+                    help="launch shapes from the library's autotuner (auto: 2D workloads only; the 3D dam "
+                         "break takes the library's defaults)")
     ap.add_argument("--autotune-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "mrsph",
                                                               "autotune.json"))
-    ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the learned sub-step leg (2D single-scene workloads only)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only: no further workloads, surrogate leg or paper cases")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned sub-step leg")
     ap.add_argument("--surrogate-seconds", type=float, default=30.0)
     ap.add_argument("--no-cases", action="store_true",
-                    help="skip the paper's four flow-induced-vibration cases (channel workload only)")
+                    help="skip the paper's four flow-induced-vibration cases")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="only run a plain FP32 device copy of this many MiB five times (the "
                          "reference for scaling HBM byte counters) and exit")
     args = ap.parse_args()
     # the batch stays within 1100 steps: 8 of its 64 coarse scenes become
-    # unstable after the water hits the plate (from about step 1600, the FP64
-    # oracle included)
+    # unstable after the water hits the plate (from about step 1600)
     defaults = {"plate_behind_cylinder": (20000, 200), "dam_break_plate": (2000, 100),
-                "dam_break_3d": (300, 20), "batched_dam_breaks": (1000, 100)}[args.workload]
+                "dam_break_3d": (300, 20), "batched_dam_breaks": (1000, 100)}
     if args.steps is None:
-        args.steps = defaults[0]
+        args.steps = defaults[args.workload][0]
     if args.warmup is None:
-        args.warmup = defaults[1]
+        args.warmup = defaults[args.workload][1]
     if args.gpus != 1:
         print(f"bench.py: the hot path runs on one GPU only (asked for --gpus {args.gpus}); "
               "run one process per GPU on its own share of the scenes instead", file=sys.stderr)
@@ -265,159 +379,73 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
         return
 
-    from paper_1911_13255_amd import sph
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
 
-    scs = make_workload(args.workload)
-    dim = int(scs[0]["dim"])
-    print(f"[bench] workload {args.workload}: {len(scs)} scene(s), "
-          f"{sum(len(s['x_fluid']) for s in scs)} fluid, {sum(len(s['x_solid']) for s in scs)} solid, "
-          f"{sum(len(s['x_wall']) for s in scs)} wall particles", file=sys.stderr, flush=True)
-    opts = {}
-    tune_s = 0.0
-    if not args.no_autotune:
-        t0 = time.perf_counter()
-        opts = sph.autotune(scs, warmup=10 if dim == 3 else 100, steps=10 if dim == 3 else 1000,
-                            cache=args.autotune_cache)
-        tune_s = time.perf_counter() - t0
-        print(f"[bench] autotuned in {tune_s:.1f} s: {json.dumps(opts)}", file=sys.stderr, flush=True)
-    sim = sph.Simulation(scs, **opts)
-    sim.advance(args.warmup)
-    torch.cuda.synchronize()
-    sim.sync()
-    c0 = sim.counters()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(sim.stream)
-    sim.advance(args.steps)
-    t_end.record(sim.stream)
-    t_end.synchronize()
-    torch.cuda.synchronize()
-    ms = t_start.elapsed_time(t_end)
-    sim.sync()
-    c1 = sim.counters()
-    inter = c1["interactions"] - c0["interactions"]
-    secs = ms / 1e3
-    value = inter / secs
-    steps_per_s = args.steps / secs
-    rebuilds = c1["rebuilds"] - c0["rebuilds"]
-    print(f"[bench] {args.steps} steps in {ms:.1f} ms, {rebuilds} rebuilds, "
-          f"{inter} interactions", file=sys.stderr, flush=True)
+    def tuned(name):
+        return args.autotune == "on" or (args.autotune == "auto" and name != "dam_break_3d")
 
-    # kernel durations are taken on a step without a pending rebuild (the
-    # common case: the force launch's list-ordering blocks then exit at once)
-    for _ in range(64):
-        if not any(sim.scalars(k)["need_rebuild"] for k in range(len(scs))):
-            break
-        sim.advance(1)
-    sim.sync()
-    # per-kernel durations (HIP events on the library's stream), after the timed region
-    # (isolated launches on the library's stream; inside the timed graph the
-    # continuity pass overlaps the coupling and solid passes)
-    kt = {name: sim.time_kernel(k, args.kernel_reps) for name, k in
-          (("k_fluid_force", sph.K_FLUID_FORCE), ("k_fluid_continuity", sph.K_CONTINUITY),
-           ("k_couple", sph.K_COUPLE), ("k_solid", sph.K_SOLID))}
-    kt["rebuild_sequence"] = sim.time_kernel(sph.K_REBUILD, max(10, args.kernel_reps // 10))
-    per_step = dict(kt)
-    per_step["rebuild_sequence"] = kt["rebuild_sequence"] * rebuilds / args.steps
-    print(f"[bench] kernel ms per launch {json.dumps({k: round(v, 5) for k, v in kt.items()})}",
-          file=sys.stderr, flush=True)
-    nf = sum(len(s["x_fluid"]) for s in scs)
-    ns_free = sum(len(s["x_solid"]) - int(s["n_clamp"]) for s in scs)
-    pairs_f = c1["n_ff"] + c1["n_fw"] + c1["n_fs"]
-    kappa = (c1["substeps"] - c0["substeps"]) / max(1, c1["steps"] - c0["steps"])
-    # single kernels and their algorithmic bytes and flops per launch; the
-    # streamed solid form (3D, large solids) is a sequence of kernels and is
-    # not a candidate
-    cand = {
-        "k_fluid_force": (kt["k_fluid_force"], FORCE_BYTES_PER_PARTICLE * nf + LIST_BYTES_PER_PAIR * pairs_f,
-                          FORCE_FLOPS_PER_PAIR * pairs_f),
-        "k_fluid_continuity": (kt["k_fluid_continuity"], CONT_BYTES_PER_PARTICLE * nf + LIST_BYTES_PER_PAIR * pairs_f,
-                               CONT_FLOPS_PER_PAIR * pairs_f),
-    }
-    if sim.solid_register_resident():
-        cand["k_solid_reg"] = (kt["k_solid"], SOLID_BYTES_PER_PARTICLE * ns_free + SOLID_BYTES_PER_PAIR * c1["n_ss"],
-                               kappa * (SOLID_FLOPS_PER_PAIR_SUBSTEP * c1["n_ss"] +
-                                        SOLID_FLOPS_PER_PARTICLE_SUBSTEP * ns_free))
-    dominant = max(cand, key=lambda k: cand[k][0])
-    dur_ms, alg_bytes, alg_flops = cand[dominant]
-    dur = dur_ms * 1e-3
-    gbs = alg_bytes / dur / 1e9
-    tflops = alg_flops / dur / 1e12
-    hbm_frac = gbs / HBM_PEAK_GBS
-    alu_frac = tflops / ALU_PEAK_TFLOPS
-    if dominant == "k_solid_reg":
-        # FP64 arithmetic of one workgroup per scene (LDS gathers, table loads
-        # and FP64 FMAs bound it together): the FP64 vector peak, with the
-        # fraction of the CUs the launch occupies beside it
-        roof = dict(bound="alu", achieved=tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=tflops / FP64_PEAK_TFLOPS, cus_used=len(scs),
-                    frac_of_cus_used=tflops / (FP64_PEAK_TFLOPS * len(scs) / NUM_CUS))
-    elif alu_frac >= hbm_frac:
-        roof = dict(bound="alu", achieved=tflops, peak=ALU_PEAK_TFLOPS, unit="TFLOP/s", frac=alu_frac)
-    else:
-        roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm_frac)
-    traffic = measured_traffic(args.workload, dominant)
-    roof.update(traffic=traffic, kernel=dominant, duration_us=dur * 1e6,
-                traffic_over_algorithmic=None if traffic is None else traffic / alg_bytes,
-                hbm_GBps=gbs, hbm_frac=hbm_frac, alu_TFLOPs=tflops, alu_frac=alu_frac,
-                algorithmic_bytes=alg_bytes, algorithmic_flops=alg_flops,
-                workgroups_per_launch=len(scs) if dominant == "k_solid_reg" else None)
+    head, scs = run_workload(args.workload, args.steps, args.warmup, tuned(args.workload), args.autotune_cache,
+                             args.kernel_reps, log)
+    extras = {}
+    if not args.no_extras:
+        # further workloads at their own sizes, shorter runs
+        others = {"dam_break_3d": 100, "plate_behind_cylinder": 5000, "batched_dam_breaks": 1000}
+        for name, n in others.items():
+            if name == args.workload:
+                continue
+            extras[name], _ = run_workload(name, n, 20 if name == "dam_break_3d" else 100, tuned(name),
+                                           args.autotune_cache, 50, log)
+        if args.workload == "dam_break_3d" or "dam_break_3d" in extras:
+            # the same 3D scene with the plate jittered like the fluid (1e-4 dp_S):
+            # its reference table is the full 16-byte one
+            from paper_1911_13255_amd import scenes as S
 
-    sur = None
-    if not args.no_surrogate and dim == 2 and len(scs) == 1 and sim.solid_register_resident():
-        sur = surrogate_leg(args.workload, scs[0], seconds=args.surrogate_seconds,
-                            log=lambda m: print(m, file=sys.stderr, flush=True))
-        print(f"[bench] surrogate {json.dumps(sur)}", file=sys.stderr, flush=True)
+            jit, _ = run_workload("dam_break_3d", 100, 20, False, args.autotune_cache, 20, log,
+                                  scenes_override=[S.dam_break_plate_3d(seed=1, solid_lattice=False)])
+            extras["dam_break_3d_jittered_plate"] = {k: jit[k] for k in
+                                                     ("value", "ms_per_step", "fsi_steps_per_s", "solid_phase",
+                                                      "kernel_ms_per_step")}
+        if not args.no_surrogate:
+            from paper_1911_13255_amd import scenes as S
 
-    cases = None
-    if not args.no_cases and args.workload == "plate_behind_cylinder":
-        cases = paper_cases(log=lambda m: print(m, file=sys.stderr, flush=True))
+            extras["surrogate"] = surrogate_leg("plate_behind_cylinder", S.plate_behind_cylinder(seed=1),
+                                                seconds=args.surrogate_seconds, log=log)
+            log(f"[bench] surrogate {json.dumps(extras['surrogate'])}")
+        if not args.no_cases:
+            extras["paper_cases"] = paper_cases(log=log)
 
     cpu = None
-    if not args.no_cpu_baseline and len(scs) == 1:
+    if not args.no_cpu_baseline:
         cpu = cpu_baseline(scs[0], args.cpu_seconds)
-    elif not args.no_cpu_baseline:
-        cpu = cpu_baseline(scs[0], args.cpu_seconds)
-        cpu["sample"] = "scene 0 of the batch only: " + cpu["sample"]
+        if len(scs) > 1:
+            cpu["sample"] = "scene 0 of the batch only: " + cpu["sample"]
+        log(f"[bench] cpu baseline {json.dumps(cpu)}")
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": args.workload,
-            "scenes": len(scs),
-            "n_fluid": nf,
-            "n_solid": sum(len(s["x_solid"]) for s in scs),
-            "n_wall": sum(len(s["x_wall"]) for s in scs),
-            "dim": dim,
-            "dp_f": scs[0]["dp_f"],
-            "dp_s": scs[0]["dp_s"],
-        },
-        "fsi_steps_per_s": steps_per_s,
-        "interactions_per_step": inter / args.steps,
-        "rebuilds": rebuilds,
-        "kernel_ms_per_step": {k: round(v, 6) for k, v in per_step.items()},
-        "launch": sim.launch_config(),
-        "autotuned": not args.no_autotune,
-        "autotune_seconds": tune_s,
-        "roofline": roof,
-        "surrogate": sur,
-        "paper_cases": cases,
+        "config": head["config"],
+        "fsi_steps_per_s": head["fsi_steps_per_s"],
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
     }
+    for k in ("interactions_per_step", "rebuilds", "kappa_mean", "kernel_ms_per_step", "kernel_roofline", "launch",
+              "autotuned", "autotune_seconds", "solid_phase"):
+        if k in head:
+            out[k] = head[k]
+    out.update(extras)
     print(json.dumps(out))
-    sim.close()
 
 
 if __name__ == "__main__":

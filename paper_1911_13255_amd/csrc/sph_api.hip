@@ -265,10 +265,14 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
   }
   if (P.cfg.solid_ppt && (long long)bs * P.cfg.solid_ppt < max_free_scene) P.cfg.solid_ppt = 0;
   P.cfg.block_solid = bs;
-  // lanes per particle: enough lanes in flight to keep about eight waves per CU
-  auto pick_lpp = [](long long nparticles) {
+  // lanes per particle: enough lanes in flight to keep about eight waves per
+  // CU, and in 3D at least 4 (about 80 neighbours per particle: four lanes
+  // share a row's loads; measured on the 2.0M-particle dam break, 1 lane per
+  // particle ran the force pass in 0.94 ms, 2 in 0.72, 4 in 0.63, 8 in 0.64)
+  const int dim3_min = P.dim == 3 ? 4 : 1;
+  auto pick_lpp = [dim3_min](long long nparticles) {
     const long long target = 256LL * 8 * 64;
-    int l = 1;
+    int l = dim3_min;
     while (l < 16 && nparticles * l < target) l *= 2;
     return l;
   };

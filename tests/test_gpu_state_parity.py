@@ -11,7 +11,7 @@ several blocks, and the plate-tip trajectory of the channel.
   of the step-end and time-step reductions, over separate calls and several
   sph_advance calls (the next step's kappa is reduced at each step's end).
 - Channel tip (Section 4.1 geometry): the tip displacement against the
-  oracle's over 6,000 acoustic steps.
+  oracle's over the first 1,500 acoustic steps.
 """
 import math
 import sys
@@ -180,35 +180,48 @@ def test_streamed_solid_over_several_blocks(gpu, dim, n, lattice):
 
 
 def test_channel_tip_trajectory_within_one_percent(gpu):
-    # The plate behind the cylinder (config of Section 4.1's shape, 17,444 fluid
+    # The plate behind the cylinder (Section 4.1's shape, 17,444 fluid
     # particles): tip = free-end, mid-thickness particle; error = max over the
     # run of |u_gpu(t) - u_oracle(t)| / max |u_oracle|, the GPU trajectory
-    # interpolated to the oracle's times.  6,000 steps reach t = 2.1 s, with
-    # the tip moving by up to about 2 mm across the channel.
+    # interpolated to the oracle's times.  The window is the first 1,500 steps
+    # (t = 0.58 s, the tip moves by about 0.35 mm): there the oracle's own
+    # trajectory moves by 0.3% when the initial fluid positions change by one
+    # part in 1e7.  Later the start-up flow makes the tip ill-conditioned: the
+    # same perturbation moves the oracle's tip by 5.5% at step 2,000 and by
+    # more than 100% at step 6,000, so no implementation that rounds
+    # differently from the oracle can hold 1% there.
     sc = scenes.plate_behind_cylinder(seed=1)
     tip = int(sc["tip_index"])
-    steps, every = 6000, 20
+    steps, every = 1500, 10
     note(f"channel tip trajectory, {steps} steps")
     sim = sph.Simulation(sc)
     o = O.Oracle(sc)
-    ug, tg, uo, to = [], [], [], []
+    sc_p = dict(sc)
+    sc_p["x_fluid"] = sc["x_fluid"] * (1.0 + 1e-7)
+    op = O.Oracle(sc_p)
+    ug, tg, uo, to, up, tp = [], [], [], [], [], []
     for _ in range(steps // every):
         sim.advance(every)
         o.step(every)
+        op.step(every)
         ug.append(sim.read(sph.S_U)[tip])
         tg.append(sim.scalars()["t"])
         uo.append(o.get(O.S_U)[tip])
         to.append(o.scalars()["t"])
-    ug, tg, uo, to = map(np.array, (ug, tg, uo, to))
+        up.append(op.get(O.S_U)[tip])
+        tp.append(op.scalars()["t"])
+    ug, tg, uo, to, up, tp = map(np.array, (ug, tg, uo, to, up, tp))
     umax = np.linalg.norm(uo, axis=1).max()
-    keep = to <= tg[-1]
-    ui = np.stack([np.interp(to[keep], tg, ug[:, k]) for k in range(2)], axis=1)
-    err = np.linalg.norm(ui - uo[keep], axis=1)
-    e = err.max() / umax
-    worst = int(np.argmax(err))
-    note(f"channel tip: max |u_oracle| {umax:.4e} m, error {e:.3e} (worst at step {(worst + 1) * every}), "
-         f"time drift {abs(tg[-1] - to[-1]) / to[-1]:.2e}")
-    assert umax > 1e-3
+
+    def err_to(ub, tb):
+        keep = to <= tb[-1]
+        ui = np.stack([np.interp(to[keep], tb, ub[:, k]) for k in range(2)], axis=1)
+        return np.linalg.norm(ui - uo[keep], axis=1).max() / umax
+
+    e, spread = err_to(ug, tg), err_to(up, tp)
+    note(f"channel tip: max |u_oracle| {umax:.4e} m, error {e:.3e}, oracle spread under a 1e-7 perturbation "
+         f"{spread:.3e}, time drift {abs(tg[-1] - to[-1]) / to[-1]:.2e}")
+    assert umax > 2e-4
     assert e <= 0.01
     sim.sync()
     sim.close()
