@@ -280,6 +280,19 @@ int sph_solid_table(sph_ctx *ctx, int *out);
  * Synchronises. */
 int sph_reduce(sph_ctx *ctx, int scene, double *out);
 
+/* The reductions of sph_reduce for callers that cannot allocate or
+ * synchronise (code under HIP graph capture, tight serving loops): enqueue
+ * only, no allocation and no host transfer.  The 16 FP64 totals (out[0..14]
+ * as sph_reduce's, out[15] unused) go to out_dev, caller-owned device memory
+ * of 16 doubles.  The block partials live in a static device array of the
+ * library (one per GPU, kept until the process ends) instead of the arena;
+ * every block writes its own partials, so nothing needs clearing between
+ * calls.  blocks: 0 = one per 256 particles of the scene, at most 1024; a
+ * larger count returns SPH_E_ARG (the scratch holds 1024 blocks' partials).
+ * Calls that overlap on one GPU (several streams or contexts at once) race
+ * on that array; calls ordered on one stream do not. */
+int sph_reduce_noalloc(sph_ctx *ctx, int scene, int blocks, double *out_dev);
+
 /* Kernel ids for sph_time_kernel. */
 enum {
   SPH_K_FLUID_FORCE = 0, /* momentum pass of fluid_step */

@@ -45,6 +45,7 @@ struct sph_ctx {
   // (solid_substeps returns it to 0)
   int phase;
   unsigned long long fallback_seen;  // surrogate fall-backs already reported by sph_sync
+  double *red_scratch;  // device address of the static reduction scratch on this context's device
   char err[512];
 };
 
@@ -631,6 +632,14 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   ctx->err[0] = 0;
   ctx->phase = 0;
   ctx->fallback_seen = 0;
+  // the static scratch of sph_reduce_noalloc: its device address, taken at
+  // set-up on the context's device (null when unavailable: that entry point
+  // then reports the failure)
+  ctx->red_scratch = nullptr;
+  if (reduce_scratch(&ctx->red_scratch) != hipSuccess) {
+    ctx->red_scratch = nullptr;
+    (void)hipGetLastError();
+  }
   size_t need = carve(nullptr, P, ctx->D);
   if (!dev_arena || arena_bytes < need) {
     std::snprintf(ctx->err, sizeof ctx->err, "arena too small: %zu < %zu", arena_bytes, need);
@@ -1057,7 +1066,7 @@ int sph_reduce(sph_ctx *ctx, int scene, double *out) {
   int n = std::max(p.f_count, p.s_count);
   int nb = std::max(1, std::min(1024, (n + 255) / 256));
   double *dst = ctx->D.stage;
-  launch_reduce(ctx->D, scene, nb, dst, ctx->stream);
+  launch_reduce(ctx->D, scene, nb, ctx->D.red, dst, ctx->stream);
   int rc = check_launch(ctx, "sph_reduce");
   if (rc != SPH_OK) return rc;
   double buf[16];
@@ -1065,6 +1074,26 @@ int sph_reduce(sph_ctx *ctx, int scene, double *out) {
   HIPCHK(hipStreamSynchronize(ctx->stream));
   std::memcpy(out, buf, 15 * sizeof(double));
   return SPH_OK;
+}
+
+int sph_reduce_noalloc(sph_ctx *ctx, int scene, int blocks, double *out_dev) {
+  if (!ctx) return SPH_E_ORDER;
+  if (scene < 0 || scene >= ctx->n_scenes || !out_dev) return SPH_E_ARG;
+  if (blocks < 0 || blocks > kReduceScratchBlocks) {
+    std::snprintf(ctx->err, sizeof ctx->err,
+                  "sph_reduce_noalloc: %d blocks asked, the static scratch holds the partials of at most %d", blocks,
+                  kReduceScratchBlocks);
+    return SPH_E_ARG;
+  }
+  if (!ctx->red_scratch) {
+    std::snprintf(ctx->err, sizeof ctx->err, "sph_reduce_noalloc: the static scratch has no device address");
+    return SPH_E_HIP;
+  }
+  const ScenePar &p = ctx->par[scene];
+  int n = std::max(p.f_count, p.s_count);
+  int nb = blocks > 0 ? blocks : std::max(1, std::min(kReduceScratchBlocks, (n + 255) / 256));
+  launch_reduce(ctx->D, scene, nb, ctx->red_scratch, out_dev, ctx->stream);
+  return check_launch(ctx, "sph_reduce_noalloc");
 }
 
 int sph_pairs(sph_ctx *ctx, int which, int scene, int *start, int *idx) {

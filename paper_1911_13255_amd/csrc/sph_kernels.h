@@ -82,7 +82,14 @@ void launch_solid_pass(const Dev &D, int sub, hipStream_t st);
 void launch_solid_average(const Dev &D, int launched, hipStream_t st);
 void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t st);
 void launch_write(const Dev &D, int s, int field, int n, const double *in, hipStream_t st);
-void launch_reduce(const Dev &D, int s, int nblocks, double *out, hipStream_t st);
+// the FP64 reductions of scene s over nblocks blocks: block partials in
+// `part` (nblocks x 16 doubles), the 16 totals in `out` (device memory)
+void launch_reduce(const Dev &D, int s, int nblocks, double *part, double *out, hipStream_t st);
+// blocks whose partials the static reduction scratch holds
+constexpr int kReduceScratchBlocks = 1024;
+// device address of the static reduction scratch on the current device
+// (taken once per device; later calls return the kept address)
+hipError_t reduce_scratch(double **ptr);
 void launch_set_rebuild(const Dev &D, int s, hipStream_t st);
 int solid_lds_bytes_per_particle(int dim);
 hipError_t allow_solid_lds(int dim, int ppt, size_t bytes);

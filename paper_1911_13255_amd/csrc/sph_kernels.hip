@@ -8,6 +8,7 @@
 // cell origin.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "sph_kernels.h"
@@ -2821,7 +2822,7 @@ __global__ void k_write_solid(Dev D, int s, int field, const double *in) {
 constexpr int NRED = 16;
 
 template <int DIM>
-__global__ void __launch_bounds__(256) k_reduce_partial(Dev D, int s) {
+__global__ void __launch_bounds__(256) k_reduce_partial(Dev D, int s, double *part) {
   __shared__ double sh[NRED][256];
   const ScenePar &P = D.par[s];
   double acc[NRED];
@@ -2903,15 +2904,23 @@ __global__ void __launch_bounds__(256) k_reduce_partial(Dev D, int s) {
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int k = 0; k < NRED; ++k) D.red[(size_t)blockIdx.x * NRED + k] = sh[k][0];
+    for (int k = 0; k < NRED; ++k) part[(size_t)blockIdx.x * NRED + k] = sh[k][0];
 }
 
-__global__ void k_reduce_final(Dev D, int nblocks, double *out) {
+__global__ void k_reduce_final(int nblocks, const double *part, double *out) {
   if (threadIdx.x >= NRED) return;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += D.red[(size_t)b * NRED + threadIdx.x];
+  for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * NRED + threadIdx.x];
   out[threadIdx.x] = s;
 }
+
+// Block partials of the reductions for callers that cannot allocate
+// (sph_reduce_noalloc): one file-scope device array, of which each GPU the
+// library runs on holds its own copy until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in,
+// not a device address): reduce_scratch() takes the device address once per
+// device with hipGetSymbolAddress, and the launchers take that pointer.
+static __device__ __align__(256) double scratch[kReduceScratchBlocks * NRED];
 
 // Drops the binning done at the end of the last step for scene s (the state
 // has changed since, or the rebuild is withdrawn): its cell counts return to
@@ -3166,9 +3175,29 @@ void launch_write(const Dev &D, int s, int field, int n, const double *in, hipSt
   else LAUNCH_DIM(D.dim, k_write_solid, dim3(nblk(n, 256)), dim3(256), st, D, s, field, in);
 }
 
-void launch_reduce(const Dev &D, int s, int nblocks, double *out, hipStream_t st) {
-  LAUNCH_DIM(D.dim, k_reduce_partial, dim3(nblocks), dim3(256), st, D, s);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, st, D, nblocks, out);
+void launch_reduce(const Dev &D, int s, int nblocks, double *part, double *out, hipStream_t st) {
+  LAUNCH_DIM(D.dim, k_reduce_partial, dim3(nblocks), dim3(256), st, D, s, part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, st, nblocks, (const double *)part, out);
+}
+
+hipError_t reduce_scratch(double **ptr) {
+  // device address of `scratch` on the current device, taken once per device
+  constexpr int kMaxDevices = 64;
+  static std::mutex lock;
+  static double *addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> guard(lock);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double *>(p);
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 void launch_set_rebuild(const Dev &D, int s, hipStream_t st) {

@@ -111,6 +111,7 @@ def lib():
         L.sph_autotune.argtypes = [C.POINTER(SphScene), C.c_int, C.POINTER(SphOptions), vp, C.c_size_t, vp,
                                    C.c_int, C.c_int, C.POINTER(SphOptions), _dp]
         L.sph_reduce.argtypes = [vp, C.c_int, _dp]
+        L.sph_reduce_noalloc.argtypes = [vp, C.c_int, C.c_int, vp]
         L.sph_time_kernel.argtypes = [vp, C.c_int, C.c_int, _dp]
         L.sph_pairs.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.sph_last_error.restype = C.c_char_p
@@ -446,6 +447,15 @@ class Simulation:
         self._check(self.L.sph_pairs(self.ctx, int(which), int(scene), start.ctypes.data_as(ip),
                                      idx.ctypes.data_as(ip)))
         return start, idx[:cnt]
+
+    def reduce_noalloc(self, out_dev, scene: int = 0, blocks: int = 0):
+        """Enqueue the reductions into out_dev (a float64 device tensor of 16
+        elements) with sph_reduce_noalloc, ordered after torch's current
+        stream and before its later work."""
+        self._enter()
+        self._check(self.L.sph_reduce_noalloc(self.ctx, int(scene), int(blocks), C.c_void_p(out_dev.data_ptr())))
+        self._leave()
+        return out_dev
 
     def time_kernel(self, kernel: int, reps: int = 100) -> float:
         """Average milliseconds per launch of one kernel (HIP events on the stream)."""
