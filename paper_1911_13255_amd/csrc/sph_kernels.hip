@@ -1050,8 +1050,10 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
     int cb = P.cell_begin;
     // One candidate of each lane of the group (all lanes take part: the
     // matches are ranked by a ballot in candidate order).  sh / shd: the
-    // neighbour cell's offset in FP32 and FP64; tag: its cell id in the entry.
-    auto fluid_candidate = [&](bool valid, int j, float4 pj, double4 qj, const float *sh, const double *shd,
+    // neighbour cell's offset in FP32 and FP64; tag: its cell id in the entry;
+    // qload(): the candidate's FP64 offset (taken only for a match where the
+    // caller has not loaded it ahead).
+    auto fluid_candidate = [&](bool valid, int j, float4 pj, auto qload, const float *sh, const double *shd,
                                unsigned tag) {
       bool hit = false;
       if (valid) {
@@ -1060,6 +1062,7 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         float rz = DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f;
         float r2 = rx * rx + ry * ry + rz * rz;
         if (r2 < P.r2max_f) {
+          const double4 qj = qload();
           double dx = (qi.x - qj.x) - shd[0], dy = (qi.y - qj.y) - shd[1];
           double dz = DIM == 3 ? (qi.z - qj.z) - shd[2] : 0.0;
           psi += Vf * W64(sqrt(dx * dx + dy * dy + dz * dz));
@@ -1070,7 +1073,9 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
       int e = rank_hits(hit, lenf);
       if (hit && e < D.capf) lf[(size_t)(e / LPP) * lstride + e % LPP] = tag | (unsigned)j;
     };
-    auto boundary_candidate = [&](bool valid, int k, float4 pb, double4 qb, float nw, const float *sh,
+    // qload(), nwload(): the boundary candidate's FP64 offset and the sign of
+    // its reference volume (walls positive), for a match
+    auto boundary_candidate = [&](bool valid, int k, float4 pb, auto qload, auto nwload, const float *sh,
                                   const double *shd, unsigned tag, int cid) {
       bool hit = false;
       if (valid) {
@@ -1078,9 +1083,10 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         float rz = DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f;
         float r2 = rx * rx + ry * ry + rz * rz;
         if (r2 < P.r2max_f) {
+          const double4 qb = qload();
           double dx = (qi.x - qb.x) - shd[0], dy = (qi.y - qb.y) - shd[1];
           double dz = DIM == 3 ? (qi.z - qb.z) - shd[2] : 0.0;
-          bool wall = nw > 0.0f;
+          bool wall = nwload() > 0.0f;
           psi += (wall ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy + dz * dz));
           if (wall) {
             nfw++;
@@ -1171,7 +1177,7 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
           float sh[3];
           double shd[3];
           offsets(kr[r], sh, shd);
-          fluid_candidate(vr[r], jr[r], pj[r], qj[r], sh, shd, (unsigned)(kr[r] + 9) << kNbrBits);
+          fluid_candidate(vr[r], jr[r], pj[r], [&] { return qj[r]; }, sh, shd, (unsigned)(kr[r] + 9) << kNbrBits);
         }
       }
       for (int e0 = 0; e0 < pb[9]; e0 += kRounds * LPP) {
@@ -1198,8 +1204,8 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
           float sh[3];
           double shd[3];
           offsets(kr[r], sh, shd);
-          boundary_candidate(vr[r], kb[r], pq[r], qq[r], nw[r], sh, shd, (unsigned)(kr[r] + 9) << kNbrBits,
-                             kr[r] + 9);
+          boundary_candidate(vr[r], kb[r], pq[r], [&] { return qq[r]; }, [&] { return nw[r]; }, sh, shd,
+                             (unsigned)(kr[r] + 9) << kNbrBits, kr[r] + 9);
         }
       }
     } else {
@@ -1208,6 +1214,8 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         // the same cell offset in FP64 (sh is an exact multiple of the FP32 cell size)
         double shd[3];
         for (int k = 0; k < 3; ++k) shd[k] = (double)(sh[k] / P.cs[k]) * P.csd[k];
+        // the candidates' FP64 offsets are loaded with their FP32 ones (reading
+        // them only for a match, one candidate in six, measured no faster)
         const int2 se = D.fc_se[cb + nl];
         for (int j0 = se.x; j0 < se.y; j0 += LPP) {
           const int j = j0 + q;
@@ -1218,7 +1226,7 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
             pj = D.f_pos[j];
             qj = D.f_posd[j];
           }
-          fluid_candidate(valid, j, pj, qj, sh, shd, tag);
+          fluid_candidate(valid, j, pj, [&] { return qj; }, sh, shd, tag);
         }
         const int2 be = D.bc_se[cb + nl];
         for (int k0 = be.x; k0 < be.y; k0 += LPP) {
@@ -1232,7 +1240,7 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
             qb = D.b_posd[k];
             nw = D.b_nrm[k].w;
           }
-          boundary_candidate(valid, k, pb, qb, nw, sh, shd, tag, cid);
+          boundary_candidate(valid, k, pb, [&] { return qb; }, [&] { return nw; }, sh, shd, tag, cid);
         }
       });
     }
@@ -1304,7 +1312,10 @@ __device__ void sort_coupling_lists(const Dev &D, int nsort) {
 // force pass and the coupling on the solid (half step of the density,
 // Section 3.3); one record per particle so that the force pass gathers a
 // neighbour's state in one read.  Used for large particle counts, where the
-// saved gathers outweigh one more launch.
+// saved gathers outweigh one more launch.  (A third per-particle record of
+// pressure and volume, saving their evaluation per pair, was measured
+// slower: the pair loops are bound by their gathers as much as by their
+// arithmetic.)
 __global__ void __launch_bounds__(256) k_fluid_prep(Dev D) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= D.nf) return;
@@ -1313,14 +1324,49 @@ __global__ void __launch_bounds__(256) k_fluid_prep(Dev D) {
   D.f_vs[i] = make_float4(va.x, va.y, va.z, va.w + 0.5f * dt * D.f_drho[i]);
 }
 
+// Geometric shifts of the 27 neighbour cells, by relative cell id
+// (dx+1) + 3 (dy+1) + 9 (dz+1), staged in LDS for the scene of the block's
+// first particle: a pair's shift is one LDS read instead of a base-3 decode.
+// Returns whether the calling lane's particle belongs to that scene (other
+// lanes, in blocks that straddle scenes, decode the id themselves).  Every
+// thread of the block must call it.
+template <int DIM>
+__device__ __forceinline__ bool stage_shifts(const Dev &D, int s, float4 *tab) {
+  __shared__ int s0;
+  if (threadIdx.x == 0) s0 = s;
+  __syncthreads();
+  const int sb = s0;
+  if (threadIdx.x < 27) {
+    float sh[3];
+    cell_shift<DIM>(D.par[sb], (int)threadIdx.x, sh);
+    tab[threadIdx.x] = make_float4(sh[0], sh[1], sh[2], 0.0f);
+  }
+  __syncthreads();
+  return s == sb;
+}
+
+template <int DIM>
+__device__ __forceinline__ float4 pair_shift(const ScenePar &P, bool tab_ok, const float4 *tab, unsigned ent) {
+  const int cid = (int)(ent >> kNbrBits);
+  if (tab_ok) return tab[cid];
+  float sh[3];
+  cell_shift<DIM>(P, cid, sh);
+  return make_float4(sh[0], sh[1], sh[2], 0.0f);
+}
+
 // Fluid acoustic step, first part (Section 3.3, Eqs. verlet-first-half and
 // verlet-first-mediate; Section 3.1 momentum): half step of density (kept as
 // eps) and position, Riemann pressure and viscous forces from fluid
 // neighbours, coupling forces from walls and solid, gravity, full step of
 // velocity.  Reads the mid-point snapshot (v^n, eps^{n+1/2}) of k_fluid_prep;
 // writes (v^{n+1}, eps^{n+1/2}), pressure and acceleration.
+//
+// Per fluid pair (e = r/|r|, du = U_L - U_R = -(v_i - v_j).e):
+//   P* = (p_i + p_j)/2 + (rho_i + rho_j)/4 clamp(3 du, 0, c) du,
+//   f_i += -2 V_i V_j P* dW e + 2 eta V_i V_j dW / |r| (v_i - v_j).
 template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
+  __shared__ float4 shift_tab[27];
   if ((int)blockIdx.x < D.sort_blocks) {
     sort_coupling_lists(D, D.sort_blocks);
     return;
@@ -1332,6 +1378,7 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
   bool active = i < D.nf;
   int ii = active ? i : 0;
   int s = D.nf > 0 ? D.f_scene[ii] : 0;
+  const bool tab_ok = stage_shifts<DIM>(D, s, shift_tab);
   const ScenePar P = D.par[s];  // by value: the pair loop keeps its fields in registers
   float dt = (float)D.st[s].dt_ac;
   float4 pi = D.f_pos[ii];
@@ -1346,6 +1393,14 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
   float Vi = mi / rhoi;
   float vi[3] = {va.x, va.y, va.z};
   float fsum[3] = {0.0f, 0.0f, 0.0f};
+  // loop invariants of the pair terms
+  const float half_pi = 0.5f * p_i;
+  const float qrho_i = 0.25f * rhoi;            // (rho_i + rho_j)/4 = qrho_i + qrho0 (1 + eps_j)
+  const float qrho0 = 0.25f * P.rho0;
+  const float cm = P.riemann ? P.c : 0.0f;     // clamp bound of 3 du (0: simple averages)
+  const float kdw = -5.0f * P.alpha_f * P.inv_hf * P.inv_hf;  // dW = kdw r t^3, t = 1 - r/(2h)
+  const float kt = -0.5f * P.inv_hf;
+  const float m2Vi = -2.0f * Vi, e2Vi = 2.0f * P.eta * Vi;
   if (active) {
     const int2 rl = D.f_rowlen[i];
     const size_t lstride = (size_t)D.nf * LPP;
@@ -1353,39 +1408,39 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
     // the loop is written once and instantiated for both snapshot sources
     auto fluid_pairs = [&](auto prep_tag) {
       constexpr bool PREP = decltype(prep_tag)::value;
-    for (int e = q; e < rl.x; e += LPP, lp += lstride) {
-      unsigned ent = *lp;
-      int j = (int)(ent & kNbrMask);
-      float sh[3];
-      cell_shift<DIM>(P, (int)(ent >> kNbrBits), sh);
-      {
-        float4 pj = D.f_pos[j];
-        float r[3] = {(pi.x - pj.x) - sh[0], (pi.y - pj.y) - sh[1], DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f};
-        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      for (int e = q; e < rl.x; e += LPP, lp += lstride) {
+        const unsigned ent = *lp;
+        const int j = (int)(ent & kNbrMask);
+        const float4 sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
+        const float4 pj = D.f_pos[j];
         float4 vj4;
-        float ehj;
         if (PREP) {
           vj4 = D.f_vs[j];
-          ehj = vj4.w;
         } else {
           vj4 = D.f_va[j];
-          ehj = vj4.w + 0.5f * dt * D.f_drho[j];
+          vj4.w += 0.5f * dt * D.f_drho[j];
         }
-        float rhoj = P.rho0 * (1.0f + ehj);
-        float p_j = eos_p_pair(ehj, P, tait7);
-        float Vj = pj.w * fast_rcp(rhoj);
-        float rr = fast_sqrt(r2);
-        float inv_r = fast_rcp(rr);
-        float e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
-        float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
-        float vj[3] = {vj4.x, vj4.y, vj4.z};
-        float Ps = riemann_pressure<DIM>(P, rhoi, rhoj, p_i, p_j, vi, vj, e);
-        float VV = Vi * Vj * dW;
-        float cpress = -2.0f * VV * Ps;
-        float cvisc = 2.0f * P.eta * VV * inv_r;
-        for (int k = 0; k < DIM; ++k) fsum[k] += cpress * e[k] + cvisc * (vi[k] - vj[k]);
+        const float p_j = eos_p_pair(vj4.w, P, tait7);
+        const float Vj = pj.w * fast_rcp(P.rho0 * (1.0f + vj4.w));
+        float r[3] = {(pi.x - pj.x) - sh.x, (pi.y - pj.y) - sh.y, DIM == 3 ? (pi.z - pj.z) - sh.z : 0.0f};
+        float r2 = r[0] * r[0] + r[1] * r[1];
+        if (DIM == 3) r2 += r[2] * r[2];
+        const float inv_r = __builtin_amdgcn_rsqf(r2);
+        const float rr = r2 * inv_r;
+        const float t = 1.0f + kt * rr;
+        const float dW = (kdw * rr) * (t * t * t);
+        const float dv[3] = {vi[0] - vj4.x, vi[1] - vj4.y, DIM == 3 ? vi[2] - vj4.z : 0.0f};
+        float w = dv[0] * r[0] + dv[1] * r[1];
+        if (DIM == 3) w += dv[2] * r[2];
+        w *= inv_r;  // (v_i - v_j).e = -du
+        const float beta = __builtin_amdgcn_fmed3f(-3.0f * w, 0.0f, cm);
+        const float qrho = qrho_i + qrho0 * (1.0f + vj4.w);
+        const float Ps = (half_pi + 0.5f * p_j) - (qrho * beta) * w;
+        const float VdW = Vj * dW;
+        const float cpress = (m2Vi * VdW) * Ps * inv_r;  // times r: the unit vector's 1/|r| folded in
+        const float cvisc = (e2Vi * VdW) * inv_r;
+        for (int k = 0; k < DIM; ++k) fsum[k] += cpress * r[k] + cvisc * dv[k];
       }
-    }
     };
     if (prep) fluid_pairs(std::true_type{});
     else fluid_pairs(std::false_type{});
@@ -1393,10 +1448,9 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
     for (int e = q; e < rl.y; e += LPP, lp += lstride) {
       unsigned ent = *lp;
       int k = (int)(ent & kNbrMask);
-      float sh[3];
-      cell_shift<DIM>(P, (int)(ent >> kNbrBits), sh);
+      const float4 sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
       float4 pb = D.b_pos[k];
-      float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
+      float r[3] = {(pi.x - pb.x) - sh.x, (pi.y - pb.y) - sh.y, DIM == 3 ? (pi.z - pb.z) - sh.z : 0.0f};
       float f[3];
       coupling_force<DIM>(P, mi, ehi, p_i, vi, r, pb, D.b_vbar[k], D.b_nrm[k], f);
       for (int c = 0; c < DIM; ++c) fsum[c] += f[c];
@@ -1482,6 +1536,7 @@ __global__ void __launch_bounds__(256) k_couple(Dev D) {
 // buffer; max speed for the next acoustic step.
 template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
+  __shared__ float4 shift_tab[27];
   // in a graph step the coupling on the solid, which reads only the force
   // pass's snapshot, runs in the leading blocks (a multiple of 8, so the XCD
   // of a continuity block is still its index modulo 8)
@@ -1494,6 +1549,7 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
   bool active = i < D.nf;
   int ii = active ? i : 0;
   int s = D.nf > 0 ? D.f_scene[ii] : 0;
+  const bool tab_ok = stage_shifts<DIM>(D, s, shift_tab);
   const ScenePar P = D.par[s];  // by value: the pair loop keeps its fields in registers
   SceneState &S = D.st[s];
   float4 pi = D.f_pos[ii];
@@ -1504,51 +1560,59 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
   const bool tait7 = __all(P.gamma == 7.0f) != 0;  // before any divergence: uniform
   float vi[3] = {vb.x, vb.y, vb.z};
   float drho = 0.0f;
+  // Per fluid pair, with v* the Riemann interface velocity:
+  //   (v_i - v*).e = (v_i - v_j).e / 2 + (p_i - p_j) / ((rho_i + rho_j) c),
+  //   drho_i += 2 rho_i V_j (v_i - v*).e dW.
+  const float rc = P.riemann ? P.c : 0.0f;
+  const float kdw = -5.0f * P.alpha_f * P.inv_hf * P.inv_hf;
+  const float kt = -0.5f * P.inv_hf;
   if (active) {
     const int2 rl = D.f_rowlen[i];
     const size_t lstride = (size_t)D.nf * LPP;
     const unsigned *lp = D.f_nbl + (size_t)i * LPP + q;
-    for (int e = q; e < rl.x; e += LPP, lp += lstride) {
-      unsigned ent = *lp;
-      int j = (int)(ent & kNbrMask);
-      float sh[3];
-      cell_shift<DIM>(P, (int)(ent >> kNbrBits), sh);
-      {
-        float4 pj = D.f_pos[j];
-        float r[3] = {(pi.x - pj.x) - sh[0], (pi.y - pj.y) - sh[1], DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f};
-        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        float4 vj4 = D.f_vb[j];
-        float rhoj = P.rho0 * (1.0f + vj4.w);
-        // the force pass's pressure: recomputed from eps for gamma = 7 (the same
-        // expression, so the same bits) instead of a second gather
-        float p_j;
-        if (tait7) p_j = eos_p_pair(vj4.w, P, true);
-        else p_j = D.f_p[j];
-        float Vj = pj.w * fast_rcp(rhoj);
-        float rr = fast_sqrt(r2);
-        float inv_r = fast_rcp(rr);
-        float e[3] = {r[0] * inv_r, r[1] * inv_r, r[2] * inv_r};
-        float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
-        float vj[3] = {vj4.x, vj4.y, vj4.z};
-        drho += 2.0f * rhoi * Vj * riemann_dv_dot_e<DIM>(P, rhoi, rhoj, p_i, p_j, vi, vj, e) * dW;
+    {
+      for (int e = q; e < rl.x; e += LPP, lp += lstride) {
+        const unsigned ent = *lp;
+        const int j = (int)(ent & kNbrMask);
+        const float4 sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
+        const float4 pj = D.f_pos[j];
+        const float4 vj4 = D.f_vb[j];
+        // the force pass's pressure: recomputed from eps for gamma = 7 (the
+        // same expression, so the same bits) instead of a second gather
+        const float p_j = tait7 ? eos_p_pair(vj4.w, P, true) : D.f_p[j];
+        const float Vj = pj.w * fast_rcp(P.rho0 * (1.0f + vj4.w));
+        float r[3] = {(pi.x - pj.x) - sh.x, (pi.y - pj.y) - sh.y, DIM == 3 ? (pi.z - pj.z) - sh.z : 0.0f};
+        float r2 = r[0] * r[0] + r[1] * r[1];
+        if (DIM == 3) r2 += r[2] * r[2];
+        const float inv_r = __builtin_amdgcn_rsqf(r2);
+        const float rr = r2 * inv_r;
+        const float t = 1.0f + kt * rr;
+        const float dW = (kdw * rr) * (t * t * t);
+        float w = (vi[0] - vj4.x) * r[0] + (vi[1] - vj4.y) * r[1];
+        if (DIM == 3) w += (vi[2] - vj4.z) * r[2];
+        const float rhoj = P.rho0 * (1.0f + vj4.w);
+        const float dvs = 0.5f * (w * inv_r) + (p_i - p_j) * fast_rcp((rhoi + rhoj) * rc);
+        drho += (2.0f * rhoi) * (Vj * dW) * (rc > 0.0f ? dvs : 0.5f * (w * inv_r));
       }
     }
     lp = D.f_bnl + (size_t)i * LPP + q;
     for (int e = q; e < rl.y; e += LPP, lp += lstride) {
       unsigned ent = *lp;
       int k = (int)(ent & kNbrMask);
-      float sh[3];
-      cell_shift<DIM>(P, (int)(ent >> kNbrBits), sh);
+      const float4 sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
       {
         float4 pb = D.b_pos[k];
-        float r[3] = {(pi.x - pb.x) - sh[0], (pi.y - pb.y) - sh[1], DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f};
-        float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        float r[3] = {(pi.x - pb.x) - sh.x, (pi.y - pb.y) - sh.y, DIM == 3 ? (pi.z - pb.z) - sh.z : 0.0f};
+        float r2 = r[0] * r[0] + r[1] * r[1];
+        if (DIM == 3) r2 += r[2] * r[2];
         float4 bv = D.b_vbar[k];
-        float rr = fast_sqrt(r2);
-        float dW = wendland_dW(rr, P.inv_hf, P.alpha_f);
+        const float inv_r = __builtin_amdgcn_rsqf(r2);
+        const float rr = r2 * inv_r;
+        const float t = 1.0f + kt * rr;
+        const float dW = (kdw * rr) * (t * t * t);
         float dv = (vi[0] - bv.x) * r[0] + (vi[1] - bv.y) * r[1];
         if (DIM == 3) dv += (vi[2] - bv.z) * r[2];
-        drho += rhoi * pb.w * (dv * fast_rcp(rr)) * dW;
+        drho += rhoi * pb.w * (dv * inv_r) * dW;
       }
     }
   }
