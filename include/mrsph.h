@@ -215,27 +215,36 @@ int sph_autotune(const sph_scene *scenes, int n_scenes, const sph_options *opt, 
 
 /* ---- learned sub-step surrogate (2D, register-resident solid kernel) ----
  * A network of include/mrsph_mlp.h with 24 inputs and 4 outputs replaces
- * the kappa solid sub-steps of an acoustic step where its prediction passes a
- * residual check, scene by scene.  Features of a free solid particle, in
- * order: F - I (4, row-major), v (2), a (2), the pressure and viscous parts
- * of the coupling force (2 + 2), then the mean of these 12 over the
- * particle's reference neighbours; outputs: vbar - v (2), abar - a (2), the
- * changes of the time-averaged velocity and acceleration of Section 3.2.
- * The prediction is advanced to the step end (u += dt vbar, v += dt abar,
- * F from the corrected gradient of vbar) and accepted when
- *   |abar - a(F_mid)|_2 / (|a(F_mid)|_2 + |g| sqrt(N)) <= threshold
- * over the scene's N free particles, a(F_mid) being the solid momentum
- * equation at the predicted mid-step deformation; otherwise the scene runs
- * the plain sub-steps from its unchanged state. */
+ * the kappa solid sub-steps of acoustic steps, scene by scene, while the
+ * plain sub-steps judge it.  Features of a free solid particle, in order:
+ * F - I (4, row-major), v (2), a (2), the pressure and viscous parts of the
+ * coupling force (2 + 2), then the mean of these 12 over the particle's
+ * reference neighbours; outputs: vbar - v (2), abar - a (2), the changes of
+ * the time-averaged velocity and acceleration of Section 3.2.  Per scene,
+ * each acoustic step is one of:
+ *   judge step: the plain sub-steps run and stand; the network's averages
+ *     are compared with theirs over the N free particles,
+ *       R = max(|vbar_net - vbar|_2 / (|vbar|_2 + |g| dt sqrt(N)),
+ *               |abar_net - abar|_2 / (|abar|_2 + |g| sqrt(N))),
+ *     and R <= threshold opens a window of every - 1 learned steps, while
+ *     R > threshold is followed by every - 1 plain steps;
+ *   learned step: the sub-steps are skipped and the predicted averages
+ *     advance the solid (u += dt vbar, v += dt abar, F from the corrected
+ *     gradient of vbar, the stored acceleration := abar);
+ *   plain step: the plain sub-steps, no network.
+ * The first step after sph_set_surrogate is a judge step.  Exact averages
+ * give R = 0, so they pass any threshold; a non-finite R fails every one,
+ * and threshold = +infinity passes every judge whose R is finite. */
 struct mlp_ctx;
 
 /* Use `net` (kept by the caller, max_rows >= all solid particles) with the
  * standardisation stats (host, 56 floats: feature mean[24], feature 1/std[24],
- * output mean[4], output std[4]) and residual threshold; net = NULL or
+ * output mean[4], output std[4]), the judge threshold and the judge interval
+ * `every` (>= 1; 1 judges every step, so no step is learned); net = NULL or
  * threshold <= 0 turns the surrogate off.  The next sph_advance captures a
- * new graph.  SPH_E_ARG for 3D, streamed solids or mismatched sizes.
- * Synchronises. */
-int sph_set_surrogate(sph_ctx *ctx, struct mlp_ctx *net, const float *stats, float threshold);
+ * new graph.  SPH_E_ARG for 3D, streamed solids, mismatched sizes or every
+ * outside [1, 2^20].  Synchronises. */
+int sph_set_surrogate(sph_ctx *ctx, struct mlp_ctx *net, const float *stats, float threshold, int every);
 
 /* Training data: features of every solid particle at the current state
  * (rows in solid order, scene after scene, 24 floats each, clamp rows zero),
@@ -247,8 +256,10 @@ int sph_solid_features(sph_ctx *ctx, const float *stats_dev, float *x_dev);
  * of (vbar - v, abar - a), 4 floats each, clamp rows zero.  Enqueue only. */
 int sph_solid_targets(sph_ctx *ctx, const float *xraw_dev, float *t_dev);
 
-/* Surrogate steps of one scene (scene = -1: all): out[0] accepted, out[1]
- * fell back to the sub-steps.  Synchronises. */
+/* Surrogate steps of one scene (scene = -1: all) since sph_init: out[0]
+ * acoustic steps the network took (learned steps), out[1] steps the plain
+ * sub-steps took while a network was set (judge and plain steps), out[2]
+ * judge steps passed, out[3] judge steps failed.  Synchronises. */
 int sph_surrogate_counters(sph_ctx *ctx, int scene, unsigned long long *out);
 
 /* Launch configuration chosen at sph_init (no GPU work): out[0..7] = lanes

@@ -12,12 +12,14 @@ quantities involved):
   values over its reference neighbours (|r0_ab| < 2 h_S, b != a);
   the network output y (standardised) gives vbar = v + y_v std + mean and
   abar = a + y_a std + mean;
-  dF/dt = sum_b (vbar_b - vbar_a) (x) (B_a V_b grad0 W_ab), F_end = F + dt dF/dt,
-  F_mid = F + dt/2 dF/dt;
-  a(F_mid) = [V sum_b (P_a B_a + P_b B_b) V_b grad0 W_ab + f^F] / m + g with the
-  Neo-Hookean P = F S(F) of Section 2.1 at F_mid;
-  residual = |abar - a(F_mid)|_2 / (|a(F_mid)|_2 + |g| sqrt(N)) over the N free
-  particles; accepted steps end at u + dt vbar, v + dt abar, F_end.
+  a learned step: dF/dt = sum_b (vbar_b - vbar_a) (x) (B_a V_b grad0 W_ab),
+  F_end = F + dt dF/dt, u_end = u + dt vbar, v_end = v + dt abar, and the
+  stored acceleration becomes abar;
+  a judge step compares the predicted averages with those of the plain
+  sub-steps over the N free particles,
+    R = max(|vbar_pred - vbar|_2 / (|vbar|_2 + |g| dt sqrt(N)),
+            |abar_pred - abar|_2 / (|abar|_2 + |g| sqrt(N))),
+  and passes when R <= threshold.
 """
 import numpy as np
 
@@ -71,41 +73,50 @@ def features(sc, o, pairs):
     return X
 
 
-def surrogate_step(sc, o, pairs, y, out_mean, out_std):
-    """Predicted step from standardised network outputs y (n_solid x 4)."""
-    k = scene_constants(sc)
-    dt = o.scalars()["dt_ac"]
-    F0, v0, a0 = o.get(O.S_F), o.get(O.S_V), o.get(O.S_A)
-    u0, fF, B = o.get(O.S_U), o.get(O.S_FF), o.get(O.S_B)
-    ns = len(F0)
-    nfree = ns - k["nclamp"]
+def predicted_averages(sc, o, y, out_mean, out_std):
+    """(vbar, abar) from standardised network outputs y (n_solid x 4), clamp
+    rows zero."""
+    nfree = len(y) - int(sc["n_clamp"])
+    v0, a0 = o.get(O.S_V), o.get(O.S_A)
     d = y * out_std + out_mean
-    vbar = np.zeros((ns, 2))
-    abar = np.zeros((ns, 2))
+    vbar = np.zeros((len(y), 2))
+    abar = np.zeros((len(y), 2))
     vbar[:nfree] = v0[:nfree] + d[:nfree, 0:2]
     abar[:nfree] = a0[:nfree] + d[:nfree, 2:4]
+    return vbar, abar
+
+
+def learned_step(sc, o, pairs, y, out_mean, out_std):
+    """The state a learned step ends at, from standardised outputs y."""
+    k = scene_constants(sc)
+    dt = o.scalars()["dt_ac"]
+    F0, u0, v0, B = o.get(O.S_F), o.get(O.S_U), o.get(O.S_V), o.get(O.S_B)
+    ns = len(F0)
+    nfree = ns - k["nclamp"]
+    vbar, abar = predicted_averages(sc, o, y, out_mean, out_std)
     Fend = F0.copy()
-    PB = np.zeros((ns, 2, 2))
+    dFs = np.zeros_like(F0)
     for a in range(nfree):
         nb, gr = pairs[a]
         G = np.zeros((2, 2))
         for b, gg in zip(nb, gr):
             G += np.outer(vbar[b] - vbar[a], gg)
-        dF = G @ B[a].T
-        Fend[a] = F0[a] + dt * dF
-        PB[a] = O.nh_stress(F0[a] + 0.5 * dt * dF, k["mu"], k["lam"]) @ B[a]
-    amid = np.zeros((ns, 2))
-    for a in range(nfree):
-        nb, gr = pairs[a]
-        acc = np.zeros(2)
-        for b, gg in zip(nb, gr):
-            acc += (PB[a] + PB[b]) @ gg
-        amid[a] = (k["Vs"] * acc + fF[a]) / (k["rho0s"] * k["Vs"]) + k["g"]
-    r2 = np.sum((abar[:nfree] - amid[:nfree]) ** 2)
-    n2 = np.sum(amid[:nfree] ** 2)
-    res = np.sqrt(r2) / (np.sqrt(n2) + np.linalg.norm(k["g"]) * np.sqrt(nfree))
-    u = u0.copy()
-    v = v0.copy()
+        dFs[a] = G @ B[a].T
+        Fend[a] = F0[a] + dt * dFs[a]
+    u, v = u0.copy(), v0.copy()
     u[:nfree] += dt * vbar[:nfree]
     v[:nfree] += dt * abar[:nfree]
-    return dict(vbar=vbar, abar=abar, F=Fend, a=amid, u=u, v=v, residual=res)
+    a = o.get(O.S_A).copy()
+    a[:nfree] = abar[:nfree]
+    return dict(vbar=vbar, abar=abar, F=Fend, dF=dFs, u=u, v=v, a=a)
+
+
+def judge_residual(sc, vbar_pred, abar_pred, vbar, abar, dt):
+    """R of a judge step over the free particles (see the module docstring)."""
+    k = scene_constants(sc)
+    nfree = len(vbar) - k["nclamp"]
+    g = np.linalg.norm(k["g"])
+    rn = np.sqrt(max(nfree, 1))
+    rv = np.linalg.norm(vbar_pred[:nfree] - vbar[:nfree]) / (np.linalg.norm(vbar[:nfree]) + g * dt * rn + 1e-300)
+    ra = np.linalg.norm(abar_pred[:nfree] - abar[:nfree]) / (np.linalg.norm(abar[:nfree]) + g * rn + 1e-300)
+    return max(rv, ra)

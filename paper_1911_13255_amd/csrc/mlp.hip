@@ -1,13 +1,16 @@
 // Sub-step surrogate network on the gfx950 matrix cores: a per-particle
 // multilayer perceptron in_dim -> 128 -> 128 -> 128 -> out_dim (SiLU hidden
 // activations), bfloat16 operands with FP32 accumulation
-// (v_mfma_f32_16x16x16_bf16), FP32 master weights trained with Adam.
+// (v_mfma_f32_16x16x32_bf16, gfx950's 32-deep BF16 matrix-core form), FP32
+// master weights trained with Adam.
 //
-// Matrix-core operand layout (16x16x16, wave64), checked on the device:
-//   A (16 x 16, rows x k):  lane l holds A[l % 16][4 (l / 16) + j], j = 0..3
-//   B (16 x 16, k x cols):  lane l holds B[4 (l / 16) + j][l % 16]
+// Matrix-core operand layout (16x16x32, wave64):
+//   A (16 x 32, rows x k):  lane l holds A[l % 16][8 (l / 16) + j], j = 0..7
+//   B (32 x 16, k x cols):  lane l holds B[8 (l / 16) + j][l % 16]
 //   D (16 x 16):            lane l holds D[4 (l / 16) + j][l % 16]
-// Every operand fragment is 4 consecutive bfloat16 in an LDS row (one 8-byte
+// (the error pass through the 16-wide output layer uses the 16-deep form,
+// v_mfma_f32_16x16x16_bf16, with 4 of k per lane: A[l % 16][4 (l / 16) + j]).
+// Every operand fragment is 8 consecutive bfloat16 in an LDS row (one 16-byte
 // read): the forward pass keeps W transposed (N x K), the error pass keeps W
 // (K x N), the weight-gradient pass transposes its tiles while staging them.
 #include <hip/hip_runtime.h>
@@ -24,7 +27,15 @@
 namespace mrsph {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+// D += A B over one 16 x 16 x 32 tile (operands as 8 raw bfloat16 per lane)
+__device__ __forceinline__ f4 mfma_bf16(s8 a, s8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
+                                                 0);
+}
 
 // bfloat16 of an FP32 value, nearest with ties to even (NaN stays NaN)
 __device__ __forceinline__ unsigned short f2bf(float x) {
@@ -42,13 +53,13 @@ __device__ __forceinline__ float silu_grad(float z) {
 }
 
 // LDS row pitch in bfloat16 elements: 8 extra elements shift consecutive rows
-// by four banks and keep 8-byte alignment.
+// by four banks and keep the 16-byte alignment of the operand reads.
 constexpr int pitch(int k) { return k + 8; }
 
 constexpr int kParamsPadded = kMlpIn * kMlpHid + kMlpHid + 2 * (kMlpHid * kMlpHid + kMlpHid) + kMlpHid * kMlpOut +
                               kMlpOut;
 
-__device__ __forceinline__ s4 lds4(const unsigned short *p) { return *reinterpret_cast<const s4 *>(p); }
+__device__ __forceinline__ s8 lds8(const unsigned short *p) { return *reinterpret_cast<const s8 *>(p); }
 
 // Copy a K-wide row-major bfloat16 matrix of `rows` rows into LDS rows of pitch(K).
 __device__ __forceinline__ void stage_rows(const unsigned short *src, unsigned short *dst, int rows, int K) {
@@ -64,16 +75,16 @@ __device__ __forceinline__ void stage_rows(const unsigned short *src, unsigned s
 template <int K, int N>
 __device__ __forceinline__ void wave_gemm_fwd(const unsigned short *Hin, const unsigned short *WT, int r0, f4 *acc) {
   constexpr int NT = N / 16;
-  const int l = threadIdx.x & 63, kq = (l >> 4) * 4;
+  const int l = threadIdx.x & 63, kq = (l >> 4) * 8;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) acc[nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    s4 a = lds4(Hin + (r0 + (l & 15)) * pitch(K) + k0 + kq);
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    s8 a = lds8(Hin + (r0 + (l & 15)) * pitch(K) + k0 + kq);
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      s4 b = lds4(WT + (nt * 16 + (l & 15)) * pitch(K) + k0 + kq);
-      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+      s8 b = lds8(WT + (nt * 16 + (l & 15)) * pitch(K) + k0 + kq);
+      acc[nt] = mfma_bf16(a, b, acc[nt]);
     }
   }
 }
@@ -100,10 +111,13 @@ __device__ __forceinline__ void hidden_epilogue(const f4 *acc, const float *bias
 }
 
 // Forward pass over tiles of kMlpTile rows: all weights in LDS, each wave owns
-// 16 rows through all four layers.
+// 16 rows through all four layers.  tile_active (may be null): per tile, 0
+// when none of its rows is wanted (the tile is skipped, its outputs untouched).
 template <bool TRAIN>
-__global__ void __launch_bounds__(256) k_mlp_forward(MlpDev M, const float *x, float *yout, int rows) {
+__global__ void __launch_bounds__(256) k_mlp_forward(MlpDev M, const float *x, float *yout, int rows,
+                                                     const int *tile_active) {
   extern __shared__ __align__(16) unsigned short lds[];
+  if (tile_active && tile_active[blockIdx.x] == 0) return;  // uniform per block
   unsigned short *WT0 = lds;                              // 128 x pitch(32)
   unsigned short *WT1 = WT0 + kMlpHid * pitch(kMlpIn);    // 128 x pitch(128)
   unsigned short *WT2 = WT1 + kMlpHid * pitch(kMlpHid);   // 128 x pitch(128)
@@ -191,7 +205,7 @@ __global__ void __launch_bounds__(256) k_mlp_back_err(const unsigned short *Wbf,
   extern __shared__ __align__(16) unsigned short lds[];
   unsigned short *Ws = lds;                 // K x pitch(N)
   unsigned short *Dt = Ws + K * pitch(N);   // 64 x pitch(N)
-  const int t = threadIdx.x, w = t >> 6, l = t & 63, kq = (l >> 4) * 4;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, kq = (l >> 4) * 8;
   const int row0 = blockIdx.x * kMlpTile;
   stage_rows(Wbf, Ws, K, N);
   for (int i = t; i < kMlpTile * N; i += blockDim.x) {
@@ -204,12 +218,24 @@ __global__ void __launch_bounds__(256) k_mlp_back_err(const unsigned short *Wbf,
 #pragma unroll
   for (int kt = 0; kt < KT; ++kt) acc[kt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   const int r0 = w * 16;
+  if constexpr (N % 32 == 0) {
 #pragma unroll
-  for (int n0 = 0; n0 < N; n0 += 16) {
-    s4 a = lds4(Dt + (r0 + (l & 15)) * pitch(N) + n0 + kq);
+    for (int n0 = 0; n0 < N; n0 += 32) {
+      s8 a = lds8(Dt + (r0 + (l & 15)) * pitch(N) + n0 + kq);
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        s8 b = lds8(Ws + (kt * 16 + (l & 15)) * pitch(N) + n0 + kq);
+        acc[kt] = mfma_bf16(a, b, acc[kt]);
+      }
+    }
+  } else {
+    // the output layer's 16 columns: one 16-deep product (lanes hold 4 of k)
+    static_assert(N == 16, "error pass over 16 output columns");
+    const int kq4 = (l >> 4) * 4;
+    s4 a = *reinterpret_cast<const s4 *>(Dt + (r0 + (l & 15)) * pitch(N) + kq4);
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
-      s4 b = lds4(Ws + (kt * 16 + (l & 15)) * pitch(N) + n0 + kq);
+      s4 b = *reinterpret_cast<const s4 *>(Ws + (kt * 16 + (l & 15)) * pitch(N) + kq4);
       acc[kt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[kt], 0, 0, 0);
     }
   }
@@ -233,7 +259,7 @@ __global__ void __launch_bounds__(256) k_mlp_back_weight(const unsigned short *h
   extern __shared__ __align__(16) unsigned short lds[];
   unsigned short *Ht = lds;                         // K x pitch(kMlpChunk)
   unsigned short *Dt = Ht + K * pitch(kMlpChunk);   // N x pitch(kMlpChunk)
-  const int t = threadIdx.x, w = t >> 6, l = t & 63, kq = (l >> 4) * 4;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, kq = (l >> 4) * 8;
   const int row0 = blockIdx.x * kMlpChunk;
   for (int i = t; i < kMlpChunk * K; i += blockDim.x) {
     int m = i / K, k = i % K;
@@ -254,13 +280,13 @@ __global__ void __launch_bounds__(256) k_mlp_back_weight(const unsigned short *h
 #pragma unroll
   for (int i = 0; i < TPW; ++i) acc[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int m0 = 0; m0 < kMlpChunk; m0 += 16) {
+  for (int m0 = 0; m0 < kMlpChunk; m0 += 32) {
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       int tile = w + 4 * i, kt = tile / NT, nt = tile % NT;
-      s4 a = lds4(Ht + (kt * 16 + (l & 15)) * pitch(kMlpChunk) + m0 + kq);
-      s4 b = lds4(Dt + (nt * 16 + (l & 15)) * pitch(kMlpChunk) + m0 + kq);
-      acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i], 0, 0, 0);
+      s8 a = lds8(Ht + (kt * 16 + (l & 15)) * pitch(kMlpChunk) + m0 + kq);
+      s8 b = lds8(Dt + (nt * 16 + (l & 15)) * pitch(kMlpChunk) + m0 + kq);
+      acc[i] = mfma_bf16(a, b, acc[i]);
     }
   }
   float *P = partW + (size_t)blockIdx.x * K * N;
@@ -325,10 +351,11 @@ constexpr size_t wgt_lds_bytes() {
   return sizeof(unsigned short) * (size_t)((K + N) * pitch(kMlpChunk));
 }
 
-void mlp_launch_forward(const MlpDev &M, const float *x, float *y, int rows, bool train, hipStream_t st) {
+void mlp_launch_forward(const MlpDev &M, const float *x, float *y, int rows, bool train, hipStream_t st,
+                        const int *tile_active) {
   dim3 grid((rows + kMlpTile - 1) / kMlpTile);
-  if (train) hipLaunchKernelGGL(k_mlp_forward<true>, grid, dim3(256), fwd_lds_bytes(), st, M, x, y, rows);
-  else hipLaunchKernelGGL(k_mlp_forward<false>, grid, dim3(256), fwd_lds_bytes(), st, M, x, y, rows);
+  if (train) hipLaunchKernelGGL(k_mlp_forward<true>, grid, dim3(256), fwd_lds_bytes(), st, M, x, y, rows, tile_active);
+  else hipLaunchKernelGGL(k_mlp_forward<false>, grid, dim3(256), fwd_lds_bytes(), st, M, x, y, rows, tile_active);
 }
 
 static hipError_t allow_lds() {
@@ -534,7 +561,7 @@ int mlp_get_grads(mlp_ctx *m, float *host, size_t n) { return copy_block(m, m ? 
 int mlp_forward(mlp_ctx *m, const float *x_dev, float *y_dev, int rows) {
   if (!m) return SPH_E_ORDER;
   if (!x_dev || !y_dev || rows < 1 || rows > m->D.max_rows) return SPH_E_ARG;
-  mlp_launch_forward(m->D, x_dev, y_dev, rows, false, m->stream);
+  mlp_launch_forward(m->D, x_dev, y_dev, rows, false, m->stream, nullptr);
   return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_HIP;
 }
 
@@ -543,7 +570,7 @@ int mlp_backward(mlp_ctx *m, const float *x_dev, const float *t_dev, int rows, d
   if (!x_dev || !t_dev || rows < 1 || rows > m->D.max_rows) return SPH_E_ARG;
   const MlpDev &D = m->D;
   hipStream_t st = m->stream;
-  mlp_launch_forward(D, x_dev, nullptr, rows, true, st);
+  mlp_launch_forward(D, x_dev, nullptr, rows, true, st, nullptr);
   int nparts = (rows * kMlpOut + 255) / 256;
   hipLaunchKernelGGL(k_mlp_out_err, dim3(nparts), dim3(256), 0, st, D, t_dev, rows);
   hipLaunchKernelGGL(k_mlp_loss_final, dim3(1), dim3(64), 0, st, D, nparts, rows);

@@ -405,6 +405,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
                    &D.sur_vbar, &D.sur_abar, &D.sur_amid};
   for (float **p : vec) take(*p, 3 * ns);
   take(D.sur_x, (size_t)kSurFeat * ns);
+  take(D.sur_blk, (ns + 63) / 64);
   take(D.sur_y, (size_t)kSurOut * ns);
   take(D.sur_stats, 2 * kSurFeat + 2 * kSurOut);
   take(D.sur_H, 9 * ns);
@@ -481,12 +482,14 @@ int read_states(sph_ctx *ctx, std::vector<SceneState> &st) {
 // is set (scenes it is accepted for skip the sub-steps).
 // step_end: the solid launch also does the step-end reduction's work
 void enqueue_solid_reg(sph_ctx *ctx, bool step_end) {
-  if (ctx->net && ctx->D.sur_thr > 0.0f) {
-    launch_sur_features(ctx->D, ctx->D.sur_stats, ctx->D.sur_x, ctx->stream);
-    mlp_launch_forward(ctx->net->D, ctx->D.sur_x, ctx->D.sur_y, ctx->D.ns, false, ctx->stream);
-    launch_sur_predict(ctx->D, ctx->stream);
+  const bool sur = ctx->net && ctx->D.sur_thr > 0.0f;
+  if (sur) {
+    launch_sur_step(ctx->D, ctx->stream);
+    mlp_launch_forward(ctx->net->D, ctx->D.sur_x, ctx->D.sur_y, ctx->D.ns, false, ctx->stream, ctx->D.sur_blk);
+    launch_sur_update(ctx->D, ctx->stream);
   }
   launch_solid(ctx->D, ctx->cfg, ctx->stream, step_end);
+  if (sur) launch_sur_judge(ctx->D, ctx->stream);
 }
 
 // step_end as above; it applies to the register-resident form only (the
@@ -983,7 +986,7 @@ int sph_counters(sph_ctx *ctx, int scene, unsigned long long *out) {
   return SPH_OK;
 }
 
-int sph_set_surrogate(sph_ctx *ctx, mlp_ctx *net, const float *stats, float threshold) {
+int sph_set_surrogate(sph_ctx *ctx, mlp_ctx *net, const float *stats, float threshold, int every) {
   if (!ctx) return SPH_E_ORDER;
   if (check_phase(ctx, "sph_set_surrogate", 0) != SPH_OK) return SPH_E_ORDER;
   ctx->kappa_ready = 0;  // the state may change: the next step reads kappa at its solid phase
@@ -992,13 +995,25 @@ int sph_set_surrogate(sph_ctx *ctx, mlp_ctx *net, const float *stats, float thre
     ctx->D.sur_thr = 0.0f;
   } else {
     if (!stats || ctx->dim != 2 || ctx->cfg.solid_ppt <= 0 || net->D.in_dim != kSurFeat ||
-        net->D.out_dim != kSurOut || net->D.max_rows < ctx->D.ns || ctx->D.ns == 0)
+        net->D.out_dim != kSurOut || net->D.max_rows < ctx->D.ns || ctx->D.ns == 0 || every < 1 ||
+        every > (1 << 20))
       return SPH_E_ARG;
     HIPCHK(hipMemcpyAsync(ctx->D.sur_stats, stats, sizeof(float) * (2 * kSurFeat + 2 * kSurOut),
                           hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->net = net;
     ctx->D.sur_thr = threshold;
+    ctx->D.sur_every = every;
+    // the first step with the network is a judge step
+    std::vector<SceneState> st;
+    int rc = read_states(ctx, st);
+    if (rc != SPH_OK) return rc;
+    for (SceneState &x : st) {
+      x.sur = 0;
+      x.sur_window = 0;
+      x.sur_countdown = 0;
+    }
+    HIPCHK(hipMemcpy(ctx->D.st, st.data(), sizeof(SceneState) * ctx->n_scenes, hipMemcpyHostToDevice));
   }
   // the captured step no longer matches: capture again at the next sph_advance
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -1031,11 +1046,13 @@ int sph_surrogate_counters(sph_ctx *ctx, int scene, unsigned long long *out) {
   std::vector<SceneState> st;
   int rc = read_states(ctx, st);
   if (rc != SPH_OK) return rc;
-  out[0] = out[1] = 0;
+  out[0] = out[1] = out[2] = out[3] = 0;
   for (int s = 0; s < ctx->n_scenes; ++s) {
     if (scene >= 0 && s != scene) continue;
     out[0] += st[s].sur_ok;
     out[1] += st[s].sur_fallback;
+    out[2] += st[s].sur_judge_ok;
+    out[3] += st[s].sur_judge_fail;
   }
   return SPH_OK;
 }
@@ -1186,9 +1203,9 @@ int sph_sync(sph_ctx *ctx) {
       return (e & ERR_CAPACITY) ? SPH_E_CAPACITY : SPH_E_ORDER;
     }
   }
-  // info: a learned step fell back to the plain sub-steps since the last sync
+  // info: a judge step rejected the network since the last sync
   unsigned long long fb = 0;
-  for (int s = 0; s < ctx->n_scenes; ++s) fb += st[s].sur_fallback;
+  for (int s = 0; s < ctx->n_scenes; ++s) fb += st[s].sur_judge_fail;
   if (fb > ctx->fallback_seen) {
     ctx->fallback_seen = fb;
     return SPH_FALLBACK;

@@ -71,7 +71,12 @@ void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_
 void launch_step_end(const Dev &D, hipStream_t st, bool reduced);
 void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t st);
 void launch_sur_targets(const Dev &D, const float *xraw, float *t, hipStream_t st);
-void launch_sur_predict(const Dev &D, hipStream_t st);
+// learned sub-step: the step's mode per scene and the network's features
+// (before the forward pass), the predicted averages and a learned step's
+// solid update (after it), the judge and the schedule (after the solid phase)
+void launch_sur_step(const Dev &D, hipStream_t st);
+void launch_sur_update(const Dev &D, hipStream_t st);
+void launch_sur_judge(const Dev &D, hipStream_t st);
 void launch_solid_dt(const Dev &D, hipStream_t st);
 // the same reduction at a step's end, after its close, into kappa_next only
 // (the step increments and kappa stay untouched)

@@ -1676,11 +1676,16 @@ __device__ void close_scene(const Dev &D, int s, unsigned vmax_bits, const unsig
   const double dt_ac = S.dt_ac;
   unsigned long long inter = 2ull * (S.n_ff + S.n_fw + S.n_fs) + S.n_fs + 2ull * (unsigned long long)kap * S.n_ss;
   if (rebuilt && P.reinit) inter += S.n_ff + S.n_fw + S.n_fs;
-  // surrogate step: feature means, rate and residual passes over the solid pairs
+  // surrogate steps: the feature means over the solid pairs (learned and
+  // judge steps) and the rate pass of a learned step
   if (S.sur) {
-    inter += 3ull * S.n_ss;
-    if (S.sur == 1) S.sur_ok += 1;
-    else S.sur_fallback += 1;
+    if (S.sur == kSurLearned) {
+      inter += 2ull * S.n_ss;
+      S.sur_ok += 1;
+    } else {
+      if (S.sur == kSurJudge) inter += S.n_ss;
+      S.sur_fallback += 1;
+    }
     S.sur = 0;
   }
   S.interactions += inter;
@@ -2103,9 +2108,9 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   // one LDS record per particle: a neighbour's P B (or v) arrives in wide reads
   auto PI = [&](int l, int k) { return (int)__umul24((unsigned)l, (unsigned)PR) + k; };
   auto VI = [&](int l, int k) { return l * DIM + k; };
-  if (S.sur == 1) {
-    // the surrogate's step was accepted for this scene: only the step end of
-    // its solid remains, from the stored state
+  if (S.sur == kSurLearned) {
+    // a learned step advanced this scene's solid: only the step end remains,
+    // from the stored state
     if (D.solid_step_end) {
       const bool rb = rebuilds_next(S);
       float sv = 0.0f, sa = 0.0f;
@@ -2546,13 +2551,26 @@ __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int bin_blocks, int 
 // viscous parts of the coupling force, then the mean of these 12 values over
 // the particle's reference neighbours) go through the network, which predicts
 // the change of the time-averaged velocity and acceleration over the step
-// (vbar - v, abar - a; Section 3.2 defines the averages).  The prediction is
-// advanced to the step end (u += dt vbar, v += dt abar, F from the corrected
-// gradient of vbar) and checked: the acceleration of the momentum equation at
-// the predicted mid-step deformation must match abar,
-//   |abar - a(F_mid)|_2 / (|a(F_mid)|_2 + |g| sqrt(N)) <= threshold
-// over the scene's free particles; otherwise the scene runs the plain
-// sub-steps from the untouched state.
+// (vbar - v, abar - a; Section 3.2 defines the averages).
+//
+// The plain sub-steps judge the network.  Per scene and step the mode is:
+//   judge step: the plain sub-steps run, and the network's averages are
+//     compared with theirs, R = max(|dvbar|_2 / (|vbar|_2 + |g| dt sqrt(N)),
+//     |dabar|_2 / (|abar|_2 + |g| sqrt(N))) over the N free particles; the
+//     plain result stands.  R <= threshold opens a window of every - 1
+//     learned steps, else every - 1 plain steps follow;
+//   learned step: the predicted averages advance the solid (u += dt vbar,
+//     v += dt abar, F from the corrected gradient of vbar, a = abar) and the
+//     sub-steps are skipped;
+//   plain step: the plain sub-steps, no network.
+// The first step after the network is set is a judge step.  Exact averages
+// give R = 0 and pass any threshold.
+
+// mode of scene S's current step from the schedule its last judge set
+__device__ __forceinline__ int sur_mode(const SceneState &S) {
+  if (S.sur_window > 0) return kSurLearned;
+  return S.sur_countdown <= 0 ? kSurJudge : kSurPlain;
+}
 
 // Own features of solid particle a (2D).
 __device__ __forceinline__ void sur_own(const Dev &D, int a, float *f) {
@@ -2567,17 +2585,9 @@ __device__ __forceinline__ void sur_own(const Dev &D, int a, float *f) {
   }
 }
 
-// Features of every solid particle, in solid order (clamp rows zero),
-// standardised by (mean, 1/std) when stats is given.
-__global__ void __launch_bounds__(256) k_sur_features(Dev D, const float *stats, float *x) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= D.ns) return;
-  const ScenePar &P = D.par[D.s_scene[a]];
-  float *row = x + (size_t)a * kSurFeat;
-  if (a - P.s_begin >= P.s_count - P.s_nclamp) {
-    for (int k = 0; k < kSurFeat; ++k) row[k] = 0.0f;
-    return;
-  }
+// Feature row of solid particle a (free), standardised by (mean, 1/std)
+// when stats is given.
+__device__ __forceinline__ void sur_feature_row(const Dev &D, int a, const float *stats, float *row) {
   float f[kSurFeat], m[12];
   sur_own(D, a, f);
   for (int k = 0; k < 12; ++k) m[k] = 0.0f;
@@ -2591,6 +2601,51 @@ __global__ void __launch_bounds__(256) k_sur_features(Dev D, const float *stats,
   float inv = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
   for (int k = 0; k < 12; ++k) f[12 + k] = m[k] * inv;
   for (int k = 0; k < kSurFeat; ++k) row[k] = stats ? (f[k] - stats[k]) * stats[kSurFeat + k] : f[k];
+}
+
+// Features of every solid particle, in solid order (clamp rows zero),
+// standardised by (mean, 1/std) when stats is given (training data).
+__global__ void __launch_bounds__(256) k_sur_features(Dev D, const float *stats, float *x) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  const ScenePar &P = D.par[D.s_scene[a]];
+  float *row = x + (size_t)a * kSurFeat;
+  if (a - P.s_begin >= P.s_count - P.s_nclamp) {
+    for (int k = 0; k < kSurFeat; ++k) row[k] = 0.0f;
+    return;
+  }
+  sur_feature_row(D, a, stats, row);
+}
+
+// The surrogate step's features: the mode of each scene's step, standardised
+// feature rows for the scenes whose step needs the network (learned and
+// judge steps), and per 64-row tile of the network's forward pass whether any
+// of its rows does (a wavefront of 64 consecutive rows decides its tile).
+__global__ void __launch_bounds__(256) k_sur_step_features(Dev D) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  bool need = false;
+  if (a < D.ns) {
+    const int s = D.s_scene[a];
+    const ScenePar &P = D.par[s];
+    SceneState &S = D.st[s];
+    const int mode = sur_mode(S);
+    const int local = a - P.s_begin;
+    if (local == 0) {
+      S.sur = mode;
+      if (mode == kSurLearned) S.kappa = 0;  // no sub-steps this step
+    }
+    need = mode != kSurPlain;
+    if (need) {
+      float *row = D.sur_x + (size_t)a * kSurFeat;
+      if (local >= P.s_count - P.s_nclamp) {
+        for (int k = 0; k < kSurFeat; ++k) row[k] = 0.0f;
+      } else {
+        sur_feature_row(D, a, D.sur_stats, row);
+      }
+    }
+  }
+  const unsigned long long any = __ballot(need);
+  if ((threadIdx.x & 63) == 0 && a < D.ns) D.sur_blk[a >> 6] = any != 0ull ? 1 : 0;
 }
 
 // Training targets after a plain step, from the raw features of its start:
@@ -2608,11 +2663,14 @@ __global__ void __launch_bounds__(256) k_sur_targets(Dev D, const float *xraw, f
   }
 }
 
-// Predicted averages from the network output.
+// Predicted averages from the network output (learned and judge steps).
 __global__ void __launch_bounds__(256) k_sur_apply(Dev D) {
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= D.ns) return;
-  const ScenePar &P = D.par[D.s_scene[a]];
+  const int s = D.s_scene[a];
+  const int mode = D.st[s].sur;
+  if (mode != kSurLearned && mode != kSurJudge) return;
+  const ScenePar &P = D.par[s];
   const int NS = D.ns;
   bool clamp = a - P.s_begin >= P.s_count - P.s_nclamp;
   const float *mo = D.sur_stats + 2 * kSurFeat, *so = mo + kSurOut;
@@ -2625,19 +2683,21 @@ __global__ void __launch_bounds__(256) k_sur_apply(Dev D) {
   }
 }
 
-// Deformation rate from the predicted averaged velocity (the corrected
-// gradient of Section 2.2), F at the step end and P B at the mid step.
-__global__ void __launch_bounds__(256) k_sur_rate(Dev D) {
+// A learned step's solid update: deformation rate from the predicted averaged
+// velocity (the corrected gradient of Section 2.2), F at the step end, and
+// the predicted averages as the step's (Section 3.2: u and v advance by dt
+// times them; the stored acceleration becomes abar).  Reads the neighbours'
+// predicted vbar only, so particles update in place without a barrier.
+__global__ void __launch_bounds__(256) k_sur_learned(Dev D) {
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= D.ns) return;
-  const ScenePar &P = D.par[D.s_scene[a]];
+  const int s = D.s_scene[a];
+  if (D.st[s].sur != kSurLearned) return;
+  const ScenePar &P = D.par[s];
   const int NS = D.ns;
-  if (a - P.s_begin >= P.s_count - P.s_nclamp) {
-    for (int k = 0; k < 4; ++k) D.s_PB[pb_at(D, a, k)] = 0.0;
-    return;
-  }
-  const double dt = D.st[D.s_scene[a]].dt_ac;
-  double va[2] = {D.sur_vbar[a], D.sur_vbar[NS + a]};
+  if (a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  const double dt = D.st[s].dt_ac;
+  const double va[2] = {D.sur_vbar[a], D.sur_vbar[NS + a]};
   double G[4] = {0.0, 0.0, 0.0, 0.0};
   int cnt = D.s_cnt[a];
   for (int q = 0; q < cnt; ++q) {
@@ -2649,91 +2709,74 @@ __global__ void __launch_bounds__(256) k_sur_rate(Dev D) {
       for (int j = 0; j < 2; ++j) G[i * 2 + j] += dv * gv[j];
     }
   }
-  double H[4], Hm[4], B[4], PB[4], J;
+  double B[4];
   for (int k = 0; k < 4; ++k) B[k] = D.s_B[k * NS + a];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) {
       double dF = G[i * 2] * B[j * 2] + G[i * 2 + 1] * B[j * 2 + 1];
-      double h = D.s_H[(i * 2 + j) * NS + a];
-      H[i * 2 + j] = h + dt * dF;
-      Hm[i * 2 + j] = h + 0.5 * dt * dF;
-      D.sur_dF[(i * 2 + j) * NS + a] = dF;
+      D.s_H[(i * 2 + j) * NS + a] += dt * dF;
+      D.s_dF[(i * 2 + j) * NS + a] = dF;
     }
-  solid_PB<2, double>(P.material, Hm, B, (double)P.mu, (double)P.lam, PB, J);
-  for (int k = 0; k < 4; ++k) {
-    D.sur_H[k * NS + a] = H[k];
-    D.s_PB[pb_at(D, a, k)] = PB[k];
-  }
-}
-
-// One block per scene: acceleration at the predicted mid state, the scene's
-// residual and the verdict (accepted scenes skip the sub-steps).
-__global__ void __launch_bounds__(1024) k_sur_residual(Dev D) {
-  __shared__ double red[2][16];
-  const int s = blockIdx.x, NS = D.ns;
-  const ScenePar &P = D.par[s];
-  SceneState &S = D.st[s];
-  const int nfree = P.s_count - P.s_nclamp;
-  const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
-  double r2 = 0.0, n2 = 0.0;
-  for (int l = threadIdx.x; l < nfree; l += blockDim.x) {
-    int a = P.s_begin + l;
-    double PBa[4];
-    for (int k = 0; k < 4; ++k) PBa[k] = D.s_PB[pb_at(D, a, k)];
-    double acc[2] = {0.0, 0.0};
-    int cnt = D.s_cnt[a];
-    for (int q = 0; q < cnt; ++q) {
-      float4 g = D.s_nbr[(size_t)q * NS + a];
-      int b = __float_as_int(g.w);
-      double gv[2] = {g.x, g.y};
-      for (int i = 0; i < 2; ++i)
-        acc[i] += (PBa[i * 2] + D.s_PB[pb_at(D, b, i * 2)]) * gv[0] +
-                  (PBa[i * 2 + 1] + D.s_PB[pb_at(D, b, i * 2 + 1)]) * gv[1];
-    }
-    for (int k = 0; k < 2; ++k) {
-      double am = ((double)P.Vs * acc[k] + (double)D.s_fF[k * NS + a]) * m_inv + (double)P.g[k];
-      D.sur_amid[k * NS + a] = (float)am;
-      double d = (double)D.sur_abar[k * NS + a] - am;
-      r2 += d * d;
-      n2 += am * am;
-    }
-  }
-  auto add = [](double x, double y) { return x + y; };
-  r2 = block_reduce(r2, add, red[0]);
-  n2 = block_reduce(n2, add, red[1]);
-  if (threadIdx.x == 0) {
-    if (nfree == 0) {
-      S.sur = 0;
-    } else {
-      double gabs = sqrt((double)P.g[0] * P.g[0] + (double)P.g[1] * P.g[1]);
-      double res = sqrt(r2) / (sqrt(n2) + gabs * sqrt((double)nfree));
-      bool ok = res <= (double)D.sur_thr;  // false for NaN
-      S.sur = ok ? 1 : 2;
-      if (ok) S.kappa = 0;
-    }
-  }
-}
-
-// Accepted scenes take the predicted step-end state.
-__global__ void __launch_bounds__(256) k_sur_commit(Dev D) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= D.ns) return;
-  const int s = D.s_scene[a], NS = D.ns;
-  const ScenePar &P = D.par[s];
-  const SceneState &S = D.st[s];
-  if (S.sur != 1 || a - P.s_begin >= P.s_count - P.s_nclamp) return;
-  const double dt = S.dt_ac;
   for (int k = 0; k < 2; ++k) {
     float vb = D.sur_vbar[k * NS + a], ab = D.sur_abar[k * NS + a];
     D.s_u[k * NS + a] += dt * (double)vb;
     D.s_v[k * NS + a] += dt * (double)ab;
-    D.s_a[k * NS + a] = D.sur_amid[k * NS + a];
+    D.s_a[k * NS + a] = ab;
     D.s_vbar[k * NS + a] = vb;
     D.s_abar[k * NS + a] = ab;
   }
-  for (int k = 0; k < 4; ++k) {
-    D.s_H[k * NS + a] = D.sur_H[k * NS + a];
-    D.s_dF[k * NS + a] = D.sur_dF[k * NS + a];
+}
+
+// One block per scene, after the solid phase: a judge step's residual against
+// the plain averages just computed, and the schedule of the next steps.
+__global__ void __launch_bounds__(1024) k_sur_judge(Dev D) {
+  __shared__ double red[4][16];
+  const int s = blockIdx.x, NS = D.ns;
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  const int mode = S.sur;
+  const int nfree = P.s_count - P.s_nclamp;
+  double dv2 = 0.0, v2 = 0.0, da2 = 0.0, a2 = 0.0;
+  if (mode == kSurJudge)
+    for (int l = threadIdx.x; l < nfree; l += blockDim.x) {
+      const int a = P.s_begin + l;
+      for (int k = 0; k < 2; ++k) {
+        const double vb = D.s_vbar[k * NS + a], ab = D.s_abar[k * NS + a];
+        const double ev = (double)D.sur_vbar[k * NS + a] - vb, ea = (double)D.sur_abar[k * NS + a] - ab;
+        dv2 += ev * ev;
+        v2 += vb * vb;
+        da2 += ea * ea;
+        a2 += ab * ab;
+      }
+    }
+  if (mode == kSurJudge) {
+    auto add = [](double x, double y) { return x + y; };
+    dv2 = block_reduce(dv2, add, red[0]);
+    v2 = block_reduce(v2, add, red[1]);
+    da2 = block_reduce(da2, add, red[2]);
+    a2 = block_reduce(a2, add, red[3]);
+  }
+  if (threadIdx.x != 0) return;
+  const int every = D.sur_every > 0 ? D.sur_every : 1;
+  if (mode == kSurLearned) {
+    S.sur_window -= 1;  // the judge step follows the last learned step
+  } else if (mode == kSurJudge) {
+    const double gabs = sqrt((double)P.g[0] * P.g[0] + (double)P.g[1] * P.g[1]);
+    const double rn = sqrt((double)(nfree > 0 ? nfree : 1));
+    const double rv = sqrt(dv2) / (sqrt(v2) + gabs * S.dt_ac * rn + 1e-300);
+    const double ra = sqrt(da2) / (sqrt(a2) + gabs * rn + 1e-300);
+    const bool ok = nfree > 0 && fmax(rv, ra) <= (double)D.sur_thr;  // false for NaN
+    if (ok) {
+      S.sur_judge_ok += 1;
+      S.sur_window = every - 1;
+      S.sur_countdown = 0;
+    } else {
+      S.sur_judge_fail += 1;
+      S.sur_window = 0;
+      S.sur_countdown = every - 1;
+    }
+  } else if (mode == kSurPlain) {
+    S.sur_countdown -= 1;
   }
 }
 
@@ -3204,12 +3247,19 @@ void launch_sur_targets(const Dev &D, const float *xraw, float *t, hipStream_t s
   if (D.ns > 0) hipLaunchKernelGGL(k_sur_targets, grid_for(D.ns, 256), dim3(256), 0, st, D, xraw, t);
 }
 
-void launch_sur_predict(const Dev &D, hipStream_t st) {
+void launch_sur_step(const Dev &D, hipStream_t st) {
+  if (D.ns == 0) return;
+  hipLaunchKernelGGL(k_sur_step_features, grid_for(D.ns, 256), dim3(256), 0, st, D);
+}
+
+void launch_sur_update(const Dev &D, hipStream_t st) {
   if (D.ns == 0) return;
   hipLaunchKernelGGL(k_sur_apply, grid_for(D.ns, 256), dim3(256), 0, st, D);
-  hipLaunchKernelGGL(k_sur_rate, grid_for(D.ns, 256), dim3(256), 0, st, D);
-  hipLaunchKernelGGL(k_sur_residual, dim3(D.n_scenes), dim3(1024), 0, st, D);
-  hipLaunchKernelGGL(k_sur_commit, grid_for(D.ns, 256), dim3(256), 0, st, D);
+  hipLaunchKernelGGL(k_sur_learned, grid_for(D.ns, 256), dim3(256), 0, st, D);
+}
+
+void launch_sur_judge(const Dev &D, hipStream_t st) {
+  if (D.ns > 0) hipLaunchKernelGGL(k_sur_judge, dim3(D.n_scenes), dim3(1024), 0, st, D);
 }
 
 void launch_step_end(const Dev &D, hipStream_t st, bool reduced) {

@@ -62,9 +62,16 @@ struct SceneState {
   unsigned long long steps, rebuilds, substeps, interactions;
   unsigned long long acc_ff, acc_fw, acc_fs;  // pair counts being reduced after a rebuild
   int base_f, base_b;  // cell-scan prefix at the scene's first cell (rebuild)
-  int sur, pad3;       // surrogate verdict of this step: 0 none, 1 accepted, 2 fell back to sub-steps
-  unsigned long long sur_ok, sur_fallback;  // surrogate steps accepted / rejected
+  // learned sub-step: mode of this step (0 surrogate off, 1 learned step, 2
+  // judge step, 3 plain step), then the schedule the judge steps set: learned
+  // steps left in the open window, plain steps left before the next judge
+  int sur, sur_window, sur_countdown, pad3;
+  unsigned long long sur_ok, sur_fallback;          // steps taken by the network / by the plain sub-steps
+  unsigned long long sur_judge_ok, sur_judge_fail;  // judge steps passed / failed
 };
+
+// mode of a scene's acoustic step while a learned sub-step network is set
+enum SurMode { kSurOff = 0, kSurLearned = 1, kSurJudge = 2, kSurPlain = 3 };
 
 // ERR_KAPPA: the streamed solid passes were launched fewer times than the
 // scene's kappa (an inconsistency of the host's sub-step count)
@@ -156,7 +163,9 @@ struct Dev {
   float *sur_stats;                // feature mean[24], 1/std[24], output mean[4], std[4]
   float *sur_vbar, *sur_abar, *sur_amid;  // predicted averages, acceleration at the predicted mid state
   double *sur_H, *sur_dF;          // predicted F - I and dF/dt at the step end
-  float sur_thr;                   // residual threshold (0: surrogate off)
+  float sur_thr;                   // residual threshold of a judge step (0: surrogate off)
+  int sur_every;                   // judge interval: a passed judge opens sur_every - 1 learned steps
+  int *sur_blk;                    // per 64-row tile of the solid: 1 when a row of it needs the network
   double *s_r0d;                   // reference positions, FP64 (3 per particle)
   double *s_gsum;                  // sum over the reference neighbours of the stored V_b grad_a W_ab, FP64 (SoA)
   float4 *s_nbr;                   // [k * ns + a] = (V_b grad_a W_ab, b as int bits in w; in 2D z holds b - scene start)

@@ -104,7 +104,7 @@ def lib():
         L.sph_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
         L.sph_launch_config.argtypes = [vp, C.POINTER(C.c_int)]
         L.sph_solid_table.argtypes = [vp, C.POINTER(C.c_int)]
-        L.sph_set_surrogate.argtypes = [vp, vp, C.POINTER(C.c_float), C.c_float]
+        L.sph_set_surrogate.argtypes = [vp, vp, C.POINTER(C.c_float), C.c_float, C.c_int]
         L.sph_solid_features.argtypes = [vp, vp, vp]
         L.sph_solid_targets.argtypes = [vp, vp, vp]
         L.sph_surrogate_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
@@ -386,23 +386,27 @@ class Simulation:
         self._leave()
         return t
 
-    def set_surrogate(self, net, stats, threshold: float):
+    def set_surrogate(self, net, stats, threshold: float, every: int = 10):
         """net: mlp.Network (24 -> 4) or None; stats: 56 floats (feature mean,
-        feature 1/std, output mean, output std)."""
+        feature 1/std, output mean, output std); threshold and interval of the
+        judge steps (see sph_set_surrogate)."""
         if net is None:
-            self._check(self.L.sph_set_surrogate(self.ctx, None, None, 0.0))
+            self._check(self.L.sph_set_surrogate(self.ctx, None, None, 0.0, 1))
             self._net = None
             return
         st = np.ascontiguousarray(stats, dtype=np.float32)
         assert st.size == 56
         self._check(self.L.sph_set_surrogate(self.ctx, net.ctx, st.ctypes.data_as(C.POINTER(C.c_float)),
-                                             float(threshold)))
+                                             float(threshold), int(every)))
         self._net = net  # keep the network alive while the context uses it
 
     def surrogate_counters(self, scene: int = -1) -> dict:
-        out = (C.c_ulonglong * 2)()
+        """accepted: learned steps; fallback: plain-sub-step steps while a
+        network is set (judge and plain steps); judged_ok / judged_fail."""
+        out = (C.c_ulonglong * 4)()
         self._check(self.L.sph_surrogate_counters(self.ctx, int(scene), out))
-        return {"accepted": int(out[0]), "fallback": int(out[1])}
+        return {"accepted": int(out[0]), "fallback": int(out[1]), "judged_ok": int(out[2]),
+                "judged_fail": int(out[3])}
 
     def launch_config(self) -> dict:
         out = (C.c_int * 8)()

@@ -143,26 +143,39 @@ def timed_steps_per_s(sim, steps: int):
 
 
 def evaluate(scene, net, stats, threshold: float, steps: int, every: int = 10, timing_steps: int = 2000,
-             **options):
+             judge_every: int = 10, plain=None, **options):
     """Plain sub-steps against the surrogate on one scene from the same start:
     tip error of the surrogate run (the plain run is the reference), the
-    fraction of accepted surrogate steps, and steps/s of both."""
+    fraction of acoustic steps the network took (judged every `judge_every`
+    steps), and steps/s of both.  plain: a (u, t, steps_per_s) result of an
+    earlier plain run of the same scene, steps and sampling, to reuse."""
     tip = int(scene["tip_index"])
-    plain = sph.Simulation(scene, **options)
-    u_p, t_p = tip_history(plain, tip, steps, every)
-    sps_plain = timed_steps_per_s(plain, timing_steps)
-    plain.close()
+    if plain is None:
+        p = sph.Simulation(scene, **options)
+        u_p, t_p = tip_history(p, tip, steps, every)
+        sps_plain = timed_steps_per_s(p, timing_steps)
+        p.close()
+    else:
+        u_p, t_p, sps_plain = plain
     sur = sph.Simulation(scene, **options)
-    sur.set_surrogate(net, stats, threshold)
+    sur.set_surrogate(net, stats, threshold, judge_every)
     u_s, t_s = tip_history(sur, tip, steps, every)
     c = sur.surrogate_counters()
     sps_sur = timed_steps_per_s(sur, timing_steps)
     c2 = sur.surrogate_counters()
-    sur.sync()
+    unstable = False
+    try:
+        sur.sync()
+    except sph.SphError:
+        unstable = True
     sur.close()
     err, umax = tip_error(u_s, t_s, u_p, t_p)
+    if not np.isfinite(err):
+        err, unstable = float("inf"), True
     acc = c["accepted"] / max(1, c["accepted"] + c["fallback"])
     acc_t = (c2["accepted"] - c["accepted"]) / max(1, c2["accepted"] + c2["fallback"] - c["accepted"] - c["fallback"])
-    return {"threshold": threshold, "tip_error": err, "tip_max_m": umax, "accepted_fraction": acc,
-            "accepted_fraction_timed": acc_t, "steps_per_s_plain": sps_plain, "steps_per_s_surrogate": sps_sur,
-            "speedup": sps_sur / sps_plain, "eval_steps": steps, "timing_steps": timing_steps}
+    return {"threshold": threshold, "judge_every": judge_every, "tip_error": err, "tip_max_m": umax,
+            "accepted_fraction": acc, "accepted_fraction_timed": acc_t, "judged_ok": c["judged_ok"],
+            "judged_fail": c["judged_fail"], "unstable": unstable, "steps_per_s_plain": sps_plain,
+            "steps_per_s_surrogate": sps_sur, "speedup": sps_sur / sps_plain, "eval_steps": steps,
+            "timing_steps": timing_steps, "plain": (u_p, t_p, sps_plain)}

@@ -1,10 +1,11 @@
 """The learned sub-step path on the GPU against the FP64 references.
 
 A network with zero weights outputs its last-layer biases for every particle,
-so its prediction is known exactly and the surrogate step (features, apply,
-rate, residual, commit) can be checked against the FP64 surrogate reference
-on the oracle's state.  A threshold no step can meet leaves the plain method
-running bit for bit; a trained network is exercised end to end.
+so its prediction is known exactly: a learned step (features, apply, rate and
+update) and a judge step's residual are checked against the FP64 surrogate
+reference on the oracle's state, and the judge schedule is checked step by
+step.  A threshold no judge can meet leaves the plain method running bit for
+bit; a trained network is exercised end to end.
 """
 import numpy as np
 import pytest
@@ -57,39 +58,98 @@ def test_features_match_oracle(gpu):
     sim.close()
 
 
-def test_accepted_surrogate_step_matches_oracle(gpu):
+def _oracle_at_step_start(sc, steps):
+    """The oracle after `steps` plain steps, then the next step's fluid phase
+    and coupling (the state the solid phase starts from)."""
+    o = O.Oracle(sc)
+    o.step(steps)
+    if o.scalars()["need_rebuild"]:
+        o.rebuild()
+    o.fluid_step()
+    o.couple()
+    return o
+
+
+def test_learned_step_matches_oracle(gpu):
     sc = scenes.dam_break_plate(seed=1)
     out_mean = np.array([2e-5, -3e-5, 0.4, -0.8])
     out_std = np.array([1e-5, 1e-5, 0.5, 0.5])
     bias = np.array([0.5, -1.0, 0.3, 0.7])
     net = constant_network(bias)
     sim = sph.Simulation(sc)
-    sim.set_surrogate(net, stats_for(out_mean, out_std), threshold=1e30)
-    o = O.Oracle(sc)
-    for _ in range(5):  # let the state move away from rest with plain steps
-        o.step(1)
-    sim.set_surrogate(None, None, 0.0)
-    sim.advance(5)
-    sim.set_surrogate(net, stats_for(out_mean, out_std), threshold=1e30)
+    sim.advance(5)  # let the state move away from rest with plain steps
+    # judge every 2 steps, any residual passes: step 6 judges (plain), step 7 is learned
+    sim.set_surrogate(net, stats_for(out_mean, out_std), threshold=1e30, every=2)
     sim.step()
-    assert sim.surrogate_counters() == {"accepted": 1, "fallback": 0}
-    if o.scalars()["need_rebuild"]:
-        o.rebuild()
-    o.fluid_step()
-    o.couple()
+    assert sim.surrogate_counters() == {"accepted": 0, "fallback": 1, "judged_ok": 1, "judged_fail": 0}
+    sim.step()
+    assert sim.surrogate_counters() == {"accepted": 1, "fallback": 1, "judged_ok": 1, "judged_fail": 0}
+    o = _oracle_at_step_start(sc, 6)
     pairs = SO.reference_pairs(sc, o)
     y = np.tile(bias, (len(sc["x_solid"]), 1))
-    r = SO.surrogate_step(sc, o, pairs, y, out_mean, out_std)
+    r = SO.learned_step(sc, o, pairs, y, out_mean, out_std)
     nfree = len(sc["x_solid"]) - int(sc["n_clamp"])
     for f, key, tol in ((sph.S_VBAR, "vbar", 1e-5), (sph.S_ABAR, "abar", 1e-5), (sph.S_U, "u", 1e-5),
-                        (sph.S_V, "v", 1e-5), (sph.S_A, "a", 1e-3)):
+                        (sph.S_V, "v", 1e-5), (sph.S_A, "a", 1e-5), (sph.S_DF, "dF", 1e-4)):
         g = sim.read(f)[:nfree]
         err = rel_inf(g, r[key][:nfree])
         assert err <= tol, (key, err)
     Fg = sim.read(sph.S_F)[:nfree] - np.eye(2)
     assert rel_inf(Fg, r["F"][:nfree] - np.eye(2)) <= 1e-4
+    assert sim.counters()["substeps"] == o.counters()["substeps"]  # the learned step took none
     sim.sync()
     sim.close()
+
+
+def test_judge_schedule(gpu):
+    # every = 5 and a threshold every finite residual meets: steps 1, 6, 11,
+    # 16 judge (plain sub-steps), the 16 others are learned.  The scene is at
+    # rest for good (no gravity, no initial velocity, densities kept at rho0:
+    # without the re-initialisation the interface's kernel deficit would set
+    # pressures), so the zero network is exact there and every residual is 0.
+    # (A zero network over a moving solid holds the last acceleration over
+    # the learned steps, which soon drives the solid unstable.)
+    sc = scenes.periodic_box_with_solid(dim=2, n=16, amp=0.0)
+    net = constant_network([0.0, 0.0, 0.0, 0.0])
+    sim = sph.Simulation(sc, density_reinit=0)
+    sim.set_surrogate(net, stats_for(np.zeros(4), np.ones(4)), threshold=float("inf"), every=5)
+    seen = []
+    for k in range(20):
+        sim.advance(1)
+        seen.append(sim.surrogate_counters()["accepted"])
+    assert seen == [0, 1, 2, 3, 4, 4, 5, 6, 7, 8, 8, 9, 10, 11, 12, 12, 13, 14, 15, 16]
+    for f in (sph.S_V, sph.S_A, sph.S_VBAR, sph.F_V):
+        assert np.abs(sim.read(f)).max() == 0.0, f
+    assert sim.surrogate_counters() == {"accepted": 16, "fallback": 4, "judged_ok": 4, "judged_fail": 0}
+    assert sim.sync() == sph.SPH_OK
+    sim.close()
+
+
+def test_judge_residual_matches_the_oracle(gpu):
+    # The first judge step after 30 plain steps, with a constant network: the
+    # residual the oracle computes from its own plain averages decides the
+    # GPU's verdict at thresholds 0.1% above and below it.
+    sc = scenes.dam_break_plate(seed=1)
+    out_mean = np.array([1e-4, -2e-4, 0.2, -0.3])
+    out_std = np.array([1e-4, 1e-4, 0.5, 0.5])
+    bias = np.array([0.3, -0.2, 0.1, 0.4])
+    o = _oracle_at_step_start(sc, 30)
+    y = np.tile(bias, (len(sc["x_solid"]), 1))
+    vp, ap = SO.predicted_averages(sc, o, y, out_mean, out_std)
+    dt = o.scalars()["dt_ac"]
+    o.solid_substeps()
+    R = SO.judge_residual(sc, vp, ap, o.get(O.S_VBAR), o.get(O.S_ABAR), dt)
+    assert 1e-3 < R < 10.0
+    net = constant_network(bias)
+    for scale, passed in ((1.001, True), (0.999, False)):
+        sim = sph.Simulation(sc)
+        sim.advance(30)
+        sim.set_surrogate(net, stats_for(out_mean, out_std), threshold=float(R * scale), every=3)
+        sim.advance(1)
+        c = sim.surrogate_counters()
+        assert (c["judged_ok"], c["judged_fail"]) == ((1, 0) if passed else (0, 1)), (scale, c, R)
+        assert sim.sync() == (sph.SPH_OK if passed else sph.SPH_FALLBACK)
+        sim.close()
 
 
 def test_rejected_steps_leave_the_plain_method_bitwise(gpu):
@@ -97,13 +157,16 @@ def test_rejected_steps_leave_the_plain_method_bitwise(gpu):
     net = constant_network([0.1, 0.2, 0.3, 0.4])
     plain = sph.Simulation(sc)
     sur = sph.Simulation(sc)
-    sur.set_surrogate(net, stats_for(np.zeros(4), np.ones(4)), threshold=1e-30)
+    sur.set_surrogate(net, stats_for(np.zeros(4), np.ones(4)), threshold=1e-30, every=5)
     plain.advance(20)
     sur.advance(20)
-    assert sur.surrogate_counters() == {"accepted": 0, "fallback": 20}
+    assert sur.surrogate_counters() == {"accepted": 0, "fallback": 20, "judged_ok": 0, "judged_fail": 4}
     for f in (sph.F_X, sph.F_V, sph.F_RHO, sph.S_U, sph.S_V, sph.S_F, sph.S_VBAR, sph.S_ABAR):
         assert np.array_equal(plain.read(f), sur.read(f)), f
     assert plain.counters()["substeps"] == sur.counters()["substeps"]
+    # the failed judges are reported once by the next sync
+    assert sur.sync() == sph.SPH_FALLBACK
+    assert sur.sync() == sph.SPH_OK
     plain.close()
     sur.close()
 
@@ -119,9 +182,10 @@ def test_trained_surrogate_end_to_end(gpu):
     assert hist[-1][2] < hist[0][2]
     sc = scenes.dam_break_plate(seed=1)
     sim = sph.Simulation(sc)
-    sim.set_surrogate(net, stats, threshold=0.05)
+    sim.set_surrogate(net, stats, threshold=0.05, every=5)
     sim.advance(50)
     c = sim.surrogate_counters()
     assert c["accepted"] + c["fallback"] == 50
+    assert c["judged_ok"] + c["judged_fail"] >= 50 // 5
     sim.sync()
     sim.close()

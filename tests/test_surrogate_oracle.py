@@ -32,34 +32,58 @@ def test_reference_pairs_and_features_at_rest():
     assert np.abs(X).max() == 0.0
 
 
-def test_exact_averages_reproduce_the_plain_step_end():
-    sc = scenes.dam_break_plate(seed=1)
+def _plain_step_and_start(seed=1, steps=30):
+    sc = scenes.dam_break_plate(seed=seed)
     o = O.Oracle(sc)
-    o.step(30)
+    o.step(steps)
     if o.scalars()["need_rebuild"]:
         o.rebuild()
     o.fluid_step()
     o.couple()
     pairs = SO.reference_pairs(sc, o)
     X = SO.features(sc, o, pairs)
-    u0, v0 = o.get(O.S_U).copy(), o.get(O.S_V).copy()
-    state = {f: o.get(f).copy() for f in (O.S_U, O.S_V, O.S_A, O.S_F, O.S_FF, O.S_FFP)}
+    state = {f: o.get(f).copy() for f in (O.S_U, O.S_V, O.S_A, O.S_F, O.S_DF, O.S_FF, O.S_FFP)}
     dt = o.scalars()["dt_ac"]
     o.solid_substeps()
-    vbar, abar = o.get(O.S_VBAR), o.get(O.S_ABAR)
-    ue, ve = o.get(O.S_U).copy(), o.get(O.S_V).copy()
-    nfree = len(u0) - int(sc["n_clamp"])
-    # feed the exact averages back as (unstandardised) outputs at the step start
-    for f, val in state.items():
+    end = {f: o.get(f).copy() for f in (O.S_U, O.S_V, O.S_VBAR, O.S_ABAR)}
+    for f, val in state.items():  # back to the step start
         o.set(f, val)
     o.set_scalars({"dt_ac": dt})
+    return sc, o, pairs, X, end, dt
+
+
+def test_exact_averages_reproduce_the_plain_step_end_and_pass_the_judge():
+    # Fed back as the network's output, the exact averages of the plain
+    # sub-steps reproduce the plain step end (u + dt vbar, v + dt abar: the
+    # averages' definition) and give a judge residual of exactly 0, so a
+    # judge step passes them at any threshold.
+    sc, o, pairs, X, end, dt = _plain_step_and_start()
+    u0 = o.get(O.S_U)
+    nfree = len(u0) - int(sc["n_clamp"])
+    vbar, abar = end[O.S_VBAR], end[O.S_ABAR]
+    assert np.abs(abar[:nfree]).max() > 0 and np.abs(vbar[:nfree]).max() > 0
     y = np.zeros((len(u0), 4))
     y[:nfree, 0:2] = vbar[:nfree] - X[:nfree, 4:6]
     y[:nfree, 2:4] = abar[:nfree] - X[:nfree, 6:8]
-    r = SO.surrogate_step(sc, o, pairs, y, np.zeros(4), np.ones(4))
+    r = SO.learned_step(sc, o, pairs, y, np.zeros(4), np.ones(4))
+    ue, ve = end[O.S_U], end[O.S_V]
     assert np.allclose(r["u"][:nfree], ue[:nfree], rtol=0, atol=1e-15 + 1e-12 * np.abs(ue).max())
     assert np.allclose(r["v"][:nfree], ve[:nfree], rtol=0, atol=1e-15 + 1e-12 * np.abs(ve).max())
-    # the mid-step check is not exact even for the exact averages: the
-    # sub-steps resolve particle-scale oscillations a single mid-point
-    # evaluation does not (a few per cent before the water arrives)
-    assert 1e-3 < r["residual"] < 0.2
+    vp, ap = SO.predicted_averages(sc, o, y, np.zeros(4), np.ones(4))
+    assert SO.judge_residual(sc, vp, ap, vbar, abar, dt) < 1e-14
+
+
+def test_judge_residual_measures_relative_error():
+    # A uniform relative error eps in the predicted acceleration gives
+    # R = eps |abar| / (|abar| + |g| sqrt(N)) <= eps; in the velocity likewise.
+    sc, o, pairs, X, end, dt = _plain_step_and_start()
+    vbar, abar = end[O.S_VBAR], end[O.S_ABAR]
+    nfree = len(vbar) - int(sc["n_clamp"])
+    g = 9.81
+    for eps in (1e-4, 1e-2):
+        R = SO.judge_residual(sc, vbar, abar * (1 + eps), vbar, abar, dt)
+        na = np.linalg.norm(abar[:nfree])
+        assert abs(R - eps * na / (na + g * np.sqrt(nfree))) < 1e-9 * eps
+        R = SO.judge_residual(sc, vbar * (1 - eps), abar, vbar, abar, dt)
+        nv = np.linalg.norm(vbar[:nfree])
+        assert abs(R - eps * nv / (nv + g * dt * np.sqrt(nfree))) < 1e-9 * eps
