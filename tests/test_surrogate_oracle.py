@@ -1,7 +1,8 @@
 """Pins of the FP64 surrogate-step reference: the coupling force's pressure
-part, the reference neighbour count, features of a state at rest, and the
-kinematic identities u_end = u + dt vbar and v_end = v + dt abar of the plain
-step when the exact averages are fed back."""
+part, the reference neighbour count, features of a state at rest, the
+neighbour differences of a linear velocity field and of a uniform drift, and
+the kinematic identities u_end = u + dt vbar and v_end = v + dt abar of the
+plain step when the exact averages are fed back."""
 import numpy as np
 
 from oracle import oracle as O
@@ -24,12 +25,59 @@ def test_pressure_part_equals_the_whole_coupling_force_without_viscosity():
 def test_reference_pairs_and_features_at_rest():
     sc = scenes.dam_break_plate(seed=1)
     o = O.Oracle(sc)
+    o.rebuild()  # the first step's start: fluid phase and coupling done, the solid at rest
+    o.fluid_step()
+    o.couple()
     pairs = SO.reference_pairs(sc, o)
     assert sum(len(nb) for nb, _ in pairs) == o.counters()["n_ss"]
     X = SO.features(sc, o, pairs)
     # initial state: F = I, v = a = 0, no fluid contact -> every feature is zero
     assert X.shape == (len(sc["x_solid"]), 24)
     assert np.abs(X).max() == 0.0
+    # and the scale is gravity's plus the floor
+    s, dt = SO.scales(sc, o, pairs)
+    assert np.allclose(s, 9.81 + 1e-3, rtol=1e-15, atol=0) and dt == o.scalars()["dt_ac"]
+
+
+def _moving_plate():
+    sc = scenes.dam_break_plate(seed=1)
+    o = O.Oracle(sc)
+    o.step(20)
+    if o.scalars()["need_rebuild"]:
+        o.rebuild()
+    o.fluid_step()
+    o.couple()
+    return sc, o, SO.reference_pairs(sc, o)
+
+
+def test_features_of_a_linear_velocity_field_and_of_a_uniform_drift():
+    sc, o, pairs = _moving_plate()
+    x0 = o.get(O.S_X0)
+    nfree = len(x0) - int(sc["n_clamp"])
+    X = SO.features(sc, o, pairs)
+    assert np.abs(X[:nfree, 6:12]).max() > 0  # the state moves and feels the fluid
+    # v = A x0: the neighbour mean minus the own value, A (mean x0_b - x0_a),
+    # vanishes up to the lattice jitter (|delta x0| <= 1e-4 dp_S) wherever the
+    # reference neighbourhood is complete and symmetric (the plate's middle
+    # column away from its ends: all 20 lattice points within 2 h_S)
+    A = np.array([[0.3, -1.2], [2.0, 0.7]])
+    o.set(O.S_V, x0 @ A.T)
+    X = SO.features(sc, o, pairs)
+    s, dt = SO.scales(sc, o, pairs)
+    full = np.array([len(pairs[a][0]) == 20 for a in range(nfree)])
+    assert full.sum() >= 20
+    dv = X[:nfree, 16:18] * (s[:nfree, None] * dt)  # back to m/s
+    bound = np.linalg.norm(A, 2) * 2e-4 * sc["dp_s"]
+    assert np.linalg.norm(dv[full], axis=1).max() <= bound
+    assert np.linalg.norm(dv[~full], axis=1).max() > 100 * bound
+    # a uniform drift added to every velocity moves the own-velocity columns
+    # by the drift and leaves every other feature
+    drift = np.array([0.25, -0.5])
+    o.set(O.S_V, o.get(O.S_V) + drift)
+    Y = SO.features(sc, o, pairs)
+    assert np.allclose(Y[:nfree, 4:6] - X[:nfree, 4:6], drift, rtol=0, atol=1e-14)
+    others = np.r_[0:4, 6:24]
+    assert np.allclose(Y[:, others], X[:, others], rtol=1e-12, atol=1e-12 * np.abs(X[:, others]).max())
 
 
 def _plain_step_and_start(seed=1, steps=30):
@@ -62,14 +110,14 @@ def test_exact_averages_reproduce_the_plain_step_end_and_pass_the_judge():
     nfree = len(u0) - int(sc["n_clamp"])
     vbar, abar = end[O.S_VBAR], end[O.S_ABAR]
     assert np.abs(abar[:nfree]).max() > 0 and np.abs(vbar[:nfree]).max() > 0
-    y = np.zeros((len(u0), 4))
-    y[:nfree, 0:2] = vbar[:nfree] - X[:nfree, 4:6]
-    y[:nfree, 2:4] = abar[:nfree] - X[:nfree, 6:8]
+    y = SO.targets(sc, o, pairs, vbar, abar)
+    s, _ = SO.scales(sc, o, pairs)
+    assert np.abs(y[:nfree]).max() < 1e3 * np.abs(y[:nfree]).mean()  # of one size
     r = SO.learned_step(sc, o, pairs, y, np.zeros(4), np.ones(4))
     ue, ve = end[O.S_U], end[O.S_V]
     assert np.allclose(r["u"][:nfree], ue[:nfree], rtol=0, atol=1e-15 + 1e-12 * np.abs(ue).max())
     assert np.allclose(r["v"][:nfree], ve[:nfree], rtol=0, atol=1e-15 + 1e-12 * np.abs(ve).max())
-    vp, ap = SO.predicted_averages(sc, o, y, np.zeros(4), np.ones(4))
+    vp, ap = SO.predicted_averages(sc, o, pairs, y, np.zeros(4), np.ones(4))
     assert SO.judge_residual(sc, vp, ap, vbar, abar, dt) < 1e-14
 
 
