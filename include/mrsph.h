@@ -216,12 +216,17 @@ int sph_autotune(const sph_scene *scenes, int n_scenes, const sph_options *opt, 
 /* ---- learned sub-step surrogate (2D, register-resident solid kernel) ----
  * A network of include/mrsph_mlp.h with 24 inputs and 4 outputs replaces
  * the kappa solid sub-steps of acoustic steps, scene by scene, while the
- * plain sub-steps judge it.  Features of a free solid particle, in order:
- * F - I (4, row-major), v (2), a (2), the pressure and viscous parts of the
- * coupling force (2 + 2), then the mean of these 12 over the particle's
- * reference neighbours; outputs: vbar - v (2), abar - a (2), the changes of
- * the time-averaged velocity and acceleration of Section 3.2.  Per scene,
- * each acoustic step is one of:
+ * plain sub-steps judge it.  For a free solid particle with own values
+ * F - I (4, row-major), v (2), a (2) and the pressure and viscous parts
+ * fp, fv (2 + 2) of the coupling force, their means over its reference
+ * neighbours (the own values where it has none), the acceleration scale
+ * s = |a| + |mean a| + |g| + |fp + fv| / m + 1e-3 m/s^2 (m = rho0_S V_S) and
+ * the acoustic step dt, the features are, in order: F - I, v, a / s,
+ * fp / (m s), fv / (m s), then the neighbour mean minus the own value of
+ * each of the 12 (F's as is, v's divided by s dt, a's by s, the forces' by
+ * m s).  The outputs are (vbar - v) / (s dt) (2) and (abar - a) / s (2): the
+ * scaled changes of the time-averaged velocity and acceleration of Section
+ * 3.2.  Per scene, each acoustic step is one of:
  *   judge step: the plain sub-steps run and stand; the network's averages
  *     are compared with theirs over the N free particles,
  *       R = max(|vbar_net - vbar|_2 / (|vbar|_2 + |g| dt sqrt(N)),
@@ -252,15 +257,22 @@ int sph_set_surrogate(sph_ctx *ctx, struct mlp_ctx *net, const float *stats, flo
  * is NULL; call between couple and solid_substeps.  Enqueue only. */
 int sph_solid_features(sph_ctx *ctx, const float *stats_dev, float *x_dev);
 
-/* Targets after solid_substeps, from the raw features taken before it: rows
- * of (vbar - v, abar - a), 4 floats each, clamp rows zero.  Enqueue only. */
-int sph_solid_targets(sph_ctx *ctx, const float *xraw_dev, float *t_dev);
+/* Targets after solid_substeps of the step whose features sph_solid_features
+ * took (it keeps each row's s, dt, v and a): rows of ((vbar - v) / (s dt),
+ * (abar - a) / s), 4 floats each, clamp rows zero.  SPH_E_ORDER when no
+ * sph_solid_features ran in this step.  Enqueue only. */
+int sph_solid_targets(sph_ctx *ctx, float *t_dev);
 
 /* Surrogate steps of one scene (scene = -1: all) since sph_init: out[0]
  * acoustic steps the network took (learned steps), out[1] steps the plain
  * sub-steps took while a network was set (judge and plain steps), out[2]
  * judge steps passed, out[3] judge steps failed.  Synchronises. */
 int sph_surrogate_counters(sph_ctx *ctx, int scene, unsigned long long *out);
+
+/* The residual R of the scene's last judge step (NaN before the first one
+ * since sph_set_surrogate, and for a non-finite residual).  SPH_E_ARG for a
+ * scene out of range.  Synchronises. */
+int sph_surrogate_residual(sph_ctx *ctx, int scene, double *out);
 
 /* Launch configuration chosen at sph_init (no GPU work): out[0..7] = lanes
  * per fluid particle in the pair passes, lanes per solid particle in the

@@ -2,17 +2,8 @@
 // multilayer perceptron in_dim -> 128 -> 128 -> 128 -> out_dim (SiLU hidden
 // activations), bfloat16 operands with FP32 accumulation
 // (v_mfma_f32_16x16x32_bf16, gfx950's 32-deep BF16 matrix-core form), FP32
-// master weights trained with Adam.
-//
-// Matrix-core operand layout (16x16x32, wave64):
-//   A (16 x 32, rows x k):  lane l holds A[l % 16][8 (l / 16) + j], j = 0..7
-//   B (32 x 16, k x cols):  lane l holds B[8 (l / 16) + j][l % 16]
-//   D (16 x 16):            lane l holds D[4 (l / 16) + j][l % 16]
-// (the error pass through the 16-wide output layer uses the 16-deep form,
-// v_mfma_f32_16x16x16_bf16, with 4 of k per lane: A[l % 16][4 (l / 16) + j]).
-// Every operand fragment is 8 consecutive bfloat16 in an LDS row (one 16-byte
-// read): the forward pass keeps W transposed (N x K), the error pass keeps W
-// (K x N), the weight-gradient pass transposes its tiles while staging them.
+// master weights trained with Adam.  The operand layouts are described with
+// the shared building blocks (mlp_device.h).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,147 +11,37 @@
 #include <cstring>
 #include <vector>
 
+#include "mlp_device.h"
 #include "mlp_internal.h"
 #include "mrsph.h"
 #include "mrsph_mlp.h"
 
 namespace mrsph {
 
-typedef short s4 __attribute__((ext_vector_type(4)));
-typedef short s8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-// D += A B over one 16 x 16 x 32 tile (operands as 8 raw bfloat16 per lane)
-__device__ __forceinline__ f4 mfma_bf16(s8 a, s8 b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
-                                                 0);
-}
-
-// bfloat16 of an FP32 value, nearest with ties to even (NaN stays NaN)
-__device__ __forceinline__ unsigned short f2bf(float x) {
-  unsigned u = __float_as_uint(x);
-  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (unsigned short)((u >> 16) | 0x40u);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-
-__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
-__device__ __forceinline__ float silu(float z) { return z * sigmoidf(z); }
-__device__ __forceinline__ float silu_grad(float z) {
-  float s = sigmoidf(z);
-  return s * (1.0f + z * (1.0f - s));
-}
-
-// LDS row pitch in bfloat16 elements: 8 extra elements shift consecutive rows
-// by four banks and keep the 16-byte alignment of the operand reads.
-constexpr int pitch(int k) { return k + 8; }
-
-constexpr int kParamsPadded = kMlpIn * kMlpHid + kMlpHid + 2 * (kMlpHid * kMlpHid + kMlpHid) + kMlpHid * kMlpOut +
-                              kMlpOut;
-
-__device__ __forceinline__ s8 lds8(const unsigned short *p) { return *reinterpret_cast<const s8 *>(p); }
-
-// Copy a K-wide row-major bfloat16 matrix of `rows` rows into LDS rows of pitch(K).
-__device__ __forceinline__ void stage_rows(const unsigned short *src, unsigned short *dst, int rows, int K) {
-  const int per = K / 4;
-  for (int idx = threadIdx.x; idx < rows * per; idx += blockDim.x) {
-    int r = idx / per, c = (idx - r * per) * 4;
-    *reinterpret_cast<s4 *>(dst + r * pitch(K) + c) = *reinterpret_cast<const s4 *>(src + (size_t)r * K + c);
-  }
-}
-
-// One wave: D (16 rows starting at r0, N cols) = Hin (pitch(K)) x W, with W^T
-// (N rows of pitch(K)) in LDS.
-template <int K, int N>
-__device__ __forceinline__ void wave_gemm_fwd(const unsigned short *Hin, const unsigned short *WT, int r0, f4 *acc) {
-  constexpr int NT = N / 16;
-  const int l = threadIdx.x & 63, kq = (l >> 4) * 8;
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) acc[nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    s8 a = lds8(Hin + (r0 + (l & 15)) * pitch(K) + k0 + kq);
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      s8 b = lds8(WT + (nt * 16 + (l & 15)) * pitch(K) + k0 + kq);
-      acc[nt] = mfma_bf16(a, b, acc[nt]);
-    }
-  }
-}
-
-// Hidden-layer epilogue: bias, SiLU, bfloat16 into the next LDS buffer; with
-// train, the pre-activation and the next layer's input go to global memory.
-template <bool TRAIN>
-__device__ __forceinline__ void hidden_epilogue(const f4 *acc, const float *bias, unsigned short *Hout, int r0,
-                                                int row0, int rows, float *zg, unsigned short *hg) {
-  const int l = threadIdx.x & 63;
-#pragma unroll
-  for (int nt = 0; nt < kMlpHid / 16; ++nt)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int r = r0 + (l >> 4) * 4 + j, c = nt * 16 + (l & 15);
-      float z = acc[nt][j] + bias[c];
-      unsigned short h = f2bf(silu(z));
-      Hout[r * pitch(kMlpHid) + c] = h;
-      if (TRAIN && row0 + r < rows) {
-        zg[(size_t)(row0 + r) * kMlpHid + c] = z;
-        hg[(size_t)(row0 + r) * kMlpHid + c] = h;
-      }
-    }
-}
-
 // Forward pass over tiles of kMlpTile rows: all weights in LDS, each wave owns
-// 16 rows through all four layers.  tile_active (may be null): per tile, 0
-// when none of its rows is wanted (the tile is skipped, its outputs untouched).
+// 16 rows through all four layers.
 template <bool TRAIN>
-__global__ void __launch_bounds__(256) k_mlp_forward(MlpDev M, const float *x, float *yout, int rows,
-                                                     const int *tile_active) {
+__global__ void __launch_bounds__(256) k_mlp_forward(MlpDev M, const float *x, float *yout, int rows) {
   extern __shared__ __align__(16) unsigned short lds[];
-  if (tile_active && tile_active[blockIdx.x] == 0) return;  // uniform per block
-  unsigned short *WT0 = lds;                              // 128 x pitch(32)
-  unsigned short *WT1 = WT0 + kMlpHid * pitch(kMlpIn);    // 128 x pitch(128)
-  unsigned short *WT2 = WT1 + kMlpHid * pitch(kMlpHid);   // 128 x pitch(128)
-  unsigned short *WT3 = WT2 + kMlpHid * pitch(kMlpHid);   // 16 x pitch(128)
-  unsigned short *HA = WT3 + kMlpOut * pitch(kMlpHid);    // 64 x pitch(128)
-  unsigned short *HB = HA + kMlpTile * pitch(kMlpHid);    // 64 x pitch(128)
-  float *bias = reinterpret_cast<float *>(HB + kMlpTile * pitch(kMlpHid));  // 3 x 128 + 16
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const FwdLds L = fwd_lds_layout(lds);
+  const int t = threadIdx.x, l = t & 63;
   const int row0 = blockIdx.x * kMlpTile;
-  stage_rows(M.WTbf[0], WT0, kMlpHid, kMlpIn);
-  stage_rows(M.WTbf[1], WT1, kMlpHid, kMlpHid);
-  stage_rows(M.WTbf[2], WT2, kMlpHid, kMlpHid);
-  stage_rows(M.WTbf[3], WT3, kMlpOut, kMlpHid);
-  for (int i = t; i < 3 * kMlpHid + kMlpOut; i += blockDim.x) bias[i] = i < 3 * kMlpHid ? M.b[i / kMlpHid][i % kMlpHid]
-                                                                                        : M.b[3][i - 3 * kMlpHid];
+  stage_weights(M, L);
   for (int i = t; i < kMlpTile * kMlpIn; i += blockDim.x) {
     int r = i / kMlpIn, c = i % kMlpIn;
     float v = (row0 + r < rows && c < M.in_dim) ? x[(size_t)(row0 + r) * M.in_dim + c] : 0.0f;
     unsigned short h = f2bf(v);
-    HA[r * pitch(kMlpIn) + c] = h;
+    L.HA[r * pitch(kMlpIn) + c] = h;
     if (TRAIN && row0 + r < rows) M.hin[0][(size_t)(row0 + r) * kMlpIn + c] = h;
   }
   __syncthreads();
-  const int r0 = w * 16;
-  f4 acc[kMlpHid / 16];
-  wave_gemm_fwd<kMlpIn, kMlpHid>(HA, WT0, r0, acc);
-  hidden_epilogue<TRAIN>(acc, bias, HB, r0, row0, rows, M.z[0], M.hin[1]);
-  __syncthreads();
-  wave_gemm_fwd<kMlpHid, kMlpHid>(HB, WT1, r0, acc);
-  __syncthreads();  // HA is overwritten below while other waves may still read HB only
-  hidden_epilogue<TRAIN>(acc, bias + kMlpHid, HA, r0, row0, rows, M.z[1], M.hin[2]);
-  __syncthreads();
-  wave_gemm_fwd<kMlpHid, kMlpHid>(HA, WT2, r0, acc);
-  __syncthreads();
-  hidden_epilogue<TRAIN>(acc, bias + 2 * kMlpHid, HB, r0, row0, rows, M.z[2], M.hin[3]);
-  __syncthreads();
-  f4 out[1];
-  wave_gemm_fwd<kMlpHid, kMlpOut>(HB, WT3, r0, out);
+  const f4 out = forward_tile<TRAIN>(L, M, row0, rows);
+  const int r0 = (t >> 6) * 16;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     int r = r0 + (l >> 4) * 4 + j, c = l & 15;
     if (row0 + r >= rows) continue;
-    float y = out[0][j] + bias[3 * kMlpHid + c];
+    float y = out[j] + L.bias[3 * kMlpHid + c];
     if (TRAIN) M.y[(size_t)(row0 + r) * kMlpOut + c] = y;
     if (c < M.out_dim && yout) yout[(size_t)(row0 + r) * M.out_dim + c] = y;
   }
@@ -337,11 +218,6 @@ __global__ void k_mlp_to_bf16(const float *W, unsigned short *Wbf, unsigned shor
   WTbf[(size_t)n * K + k] = h;
 }
 
-constexpr size_t fwd_lds_bytes() {
-  return sizeof(unsigned short) * (size_t)(kMlpHid * pitch(kMlpIn) + 2 * kMlpHid * pitch(kMlpHid) +
-                                           kMlpOut * pitch(kMlpHid) + 2 * kMlpTile * pitch(kMlpHid)) +
-         sizeof(float) * (3 * kMlpHid + kMlpOut);
-}
 template <int K, int N>
 constexpr size_t err_lds_bytes() {
   return sizeof(unsigned short) * (size_t)(K * pitch(N) + kMlpTile * pitch(N));
@@ -351,11 +227,10 @@ constexpr size_t wgt_lds_bytes() {
   return sizeof(unsigned short) * (size_t)((K + N) * pitch(kMlpChunk));
 }
 
-void mlp_launch_forward(const MlpDev &M, const float *x, float *y, int rows, bool train, hipStream_t st,
-                        const int *tile_active) {
+void mlp_launch_forward(const MlpDev &M, const float *x, float *y, int rows, bool train, hipStream_t st) {
   dim3 grid((rows + kMlpTile - 1) / kMlpTile);
-  if (train) hipLaunchKernelGGL(k_mlp_forward<true>, grid, dim3(256), fwd_lds_bytes(), st, M, x, y, rows, tile_active);
-  else hipLaunchKernelGGL(k_mlp_forward<false>, grid, dim3(256), fwd_lds_bytes(), st, M, x, y, rows, tile_active);
+  if (train) hipLaunchKernelGGL(k_mlp_forward<true>, grid, dim3(256), fwd_lds_bytes(), st, M, x, y, rows);
+  else hipLaunchKernelGGL(k_mlp_forward<false>, grid, dim3(256), fwd_lds_bytes(), st, M, x, y, rows);
 }
 
 static hipError_t allow_lds() {
@@ -561,7 +436,7 @@ int mlp_get_grads(mlp_ctx *m, float *host, size_t n) { return copy_block(m, m ? 
 int mlp_forward(mlp_ctx *m, const float *x_dev, float *y_dev, int rows) {
   if (!m) return SPH_E_ORDER;
   if (!x_dev || !y_dev || rows < 1 || rows > m->D.max_rows) return SPH_E_ARG;
-  mlp_launch_forward(m->D, x_dev, y_dev, rows, false, m->stream, nullptr);
+  mlp_launch_forward(m->D, x_dev, y_dev, rows, false, m->stream);
   return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_HIP;
 }
 
@@ -570,7 +445,7 @@ int mlp_backward(mlp_ctx *m, const float *x_dev, const float *t_dev, int rows, d
   if (!x_dev || !t_dev || rows < 1 || rows > m->D.max_rows) return SPH_E_ARG;
   const MlpDev &D = m->D;
   hipStream_t st = m->stream;
-  mlp_launch_forward(D, x_dev, nullptr, rows, true, st, nullptr);
+  mlp_launch_forward(D, x_dev, nullptr, rows, true, st);
   int nparts = (rows * kMlpOut + 255) / 256;
   hipLaunchKernelGGL(k_mlp_out_err, dim3(nparts), dim3(256), 0, st, D, t_dev, rows);
   hipLaunchKernelGGL(k_mlp_loss_final, dim3(1), dim3(64), 0, st, D, nparts, rows);

@@ -34,9 +34,7 @@ struct MlpDev {
 
 // y (rows x out_dim) = network(x (rows x in_dim)); with train the layer inputs,
 // pre-activations and padded output are stored for the error pass.
-// tile_active (device, may be null): per kMlpTile rows, 0 skips the tile.
-void mlp_launch_forward(const MlpDev &M, const float *x, float *y, int rows, bool train, hipStream_t st,
-                        const int *tile_active);
+void mlp_launch_forward(const MlpDev &M, const float *x, float *y, int rows, bool train, hipStream_t st);
 
 }  // namespace mrsph
 

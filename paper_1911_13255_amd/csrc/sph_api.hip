@@ -44,6 +44,7 @@ struct sph_ctx {
   // boundary, 1 after neighbor_build, 2 after fluid_step, 3 after couple
   // (solid_substeps returns it to 0)
   int phase;
+  int features_taken;  // sph_solid_features ran in the current step (its scales await the targets)
   unsigned long long fallback_seen;  // surrogate fall-backs already reported by sph_sync
   double *red_scratch;  // device address of the static reduction scratch on this context's device
   char err[512];
@@ -402,14 +403,10 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.s_gcls, kNbrClasses);
   take(D.nbc_ok, 1);
   float **vec[] = {&D.s_a, &D.s_fF, &D.s_vbar, &D.s_abar, &D.s_n0, &D.s_n, &D.s_fFp,
-                   &D.sur_vbar, &D.sur_abar, &D.sur_amid};
+                   &D.sur_vbar, &D.sur_abar};
   for (float **p : vec) take(*p, 3 * ns);
-  take(D.sur_x, (size_t)kSurFeat * ns);
-  take(D.sur_blk, (ns + 63) / 64);
-  take(D.sur_y, (size_t)kSurOut * ns);
+  take(D.sur_aux, (size_t)6 * ns);
   take(D.sur_stats, 2 * kSurFeat + 2 * kSurOut);
-  take(D.sur_H, 9 * ns);
-  take(D.sur_dF, 9 * ns);
   take(D.s_r0d, 3 * ns);
   take(D.s_gsum, 3 * ns);
   take(D.s_nbr, (size_t)(P.maxn + kSolidBatch) * ns);
@@ -478,18 +475,12 @@ int read_states(sph_ctx *ctx, std::vector<SceneState> &st) {
 // pass loop: inside sph_advance it was copied to pinned memory at the end of
 // the step before (the host waits on that copy only), otherwise it is read
 // back here (this synchronises the stream).
-// Register-resident sub-steps, preceded by the learned step when a surrogate
-// is set (scenes it is accepted for skip the sub-steps).
+// Register-resident sub-steps, preceded by the surrogate pass when a network
+// is set (the solid launch then takes the learned steps and judges).
 // step_end: the solid launch also does the step-end reduction's work
 void enqueue_solid_reg(sph_ctx *ctx, bool step_end) {
-  const bool sur = ctx->net && ctx->D.sur_thr > 0.0f;
-  if (sur) {
-    launch_sur_step(ctx->D, ctx->stream);
-    mlp_launch_forward(ctx->net->D, ctx->D.sur_x, ctx->D.sur_y, ctx->D.ns, false, ctx->stream, ctx->D.sur_blk);
-    launch_sur_update(ctx->D, ctx->stream);
-  }
+  if (ctx->net && ctx->D.sur_thr > 0.0f) launch_sur_net(ctx->D, ctx->net->D, ctx->stream);
   launch_solid(ctx->D, ctx->cfg, ctx->stream, step_end);
-  if (sur) launch_sur_judge(ctx->D, ctx->stream);
 }
 
 // step_end as above; it applies to the register-resident form only (the
@@ -798,6 +789,7 @@ int neighbor_build(sph_ctx *ctx) {
   launch_rebuild(ctx->D, ctx->cfg, ctx->stream, true);
   rc = check_launch(ctx, "neighbor_build");
   if (rc == SPH_OK) ctx->phase = 1;
+  ctx->features_taken = 0;
   return rc;
 }
 
@@ -838,6 +830,7 @@ int sph_advance(sph_ctx *ctx, int n_steps) {
   if (!ctx) return SPH_E_ORDER;
   if (n_steps < 0) return SPH_E_ARG;
   if (check_phase(ctx, "sph_advance", 0) != SPH_OK) return SPH_E_ORDER;
+  if (n_steps > 0) ctx->features_taken = 0;
   // the streamed solid path reads kappa back to the host: no graph then
   if (!ctx->graph_exec && !ctx->graph_failed && ctx->stream && ctx->cfg.solid_ppt > 0) {
     // capture one acoustic step; every decision inside it is taken on the device
@@ -998,6 +991,7 @@ int sph_set_surrogate(sph_ctx *ctx, mlp_ctx *net, const float *stats, float thre
         net->D.out_dim != kSurOut || net->D.max_rows < ctx->D.ns || ctx->D.ns == 0 || every < 1 ||
         every > (1 << 20))
       return SPH_E_ARG;
+    HIPCHK(allow_sur_net_lds());
     HIPCHK(hipMemcpyAsync(ctx->D.sur_stats, stats, sizeof(float) * (2 * kSurFeat + 2 * kSurOut),
                           hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1012,6 +1006,7 @@ int sph_set_surrogate(sph_ctx *ctx, mlp_ctx *net, const float *stats, float thre
       x.sur = 0;
       x.sur_window = 0;
       x.sur_countdown = 0;
+      x.sur_last_r = std::nan("");
     }
     HIPCHK(hipMemcpy(ctx->D.st, st.data(), sizeof(SceneState) * ctx->n_scenes, hipMemcpyHostToDevice));
   }
@@ -1029,14 +1024,22 @@ int sph_solid_features(sph_ctx *ctx, const float *stats_dev, float *x_dev) {
   if (check_phase(ctx, "sph_solid_features", 3) != SPH_OK) return SPH_E_ORDER;
   if (!x_dev || ctx->dim != 2) return SPH_E_ARG;
   launch_sur_features(ctx->D, stats_dev, x_dev, ctx->stream);
-  return check_launch(ctx, "sph_solid_features");
+  int rc = check_launch(ctx, "sph_solid_features");
+  if (rc == SPH_OK) ctx->features_taken = 1;
+  return rc;
 }
 
-int sph_solid_targets(sph_ctx *ctx, const float *xraw_dev, float *t_dev) {
+int sph_solid_targets(sph_ctx *ctx, float *t_dev) {
   if (!ctx) return SPH_E_ORDER;
   if (check_phase(ctx, "sph_solid_targets", 0) != SPH_OK) return SPH_E_ORDER;
-  if (!xraw_dev || !t_dev || ctx->dim != 2) return SPH_E_ARG;
-  launch_sur_targets(ctx->D, xraw_dev, t_dev, ctx->stream);
+  if (!ctx->features_taken) {
+    std::snprintf(ctx->err, sizeof ctx->err,
+                  "sph_solid_targets: no sph_solid_features in this step (call it between couple and solid_substeps)");
+    return SPH_E_ORDER;
+  }
+  if (!t_dev || ctx->dim != 2) return SPH_E_ARG;
+  launch_sur_targets(ctx->D, t_dev, ctx->stream);
+  ctx->features_taken = 0;
   return check_launch(ctx, "sph_solid_targets");
 }
 
@@ -1054,6 +1057,16 @@ int sph_surrogate_counters(sph_ctx *ctx, int scene, unsigned long long *out) {
     out[2] += st[s].sur_judge_ok;
     out[3] += st[s].sur_judge_fail;
   }
+  return SPH_OK;
+}
+
+int sph_surrogate_residual(sph_ctx *ctx, int scene, double *out) {
+  if (!ctx) return SPH_E_ORDER;
+  if (scene < 0 || scene >= ctx->n_scenes || !out) return SPH_E_ARG;
+  std::vector<SceneState> st;
+  int rc = read_states(ctx, st);
+  if (rc != SPH_OK) return rc;
+  *out = st[scene].sur_last_r;
   return SPH_OK;
 }
 

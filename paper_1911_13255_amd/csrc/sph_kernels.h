@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "mlp_internal.h"
 #include "sph_types.h"
 
 namespace mrsph {
@@ -70,13 +71,13 @@ void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_
 // reduced: the solid launch already did the step-end reduction's work
 void launch_step_end(const Dev &D, hipStream_t st, bool reduced);
 void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t st);
-void launch_sur_targets(const Dev &D, const float *xraw, float *t, hipStream_t st);
-// learned sub-step: the step's mode per scene and the network's features
-// (before the forward pass), the predicted averages and a learned step's
-// solid update (after it), the judge and the schedule (after the solid phase)
-void launch_sur_step(const Dev &D, hipStream_t st);
-void launch_sur_update(const Dev &D, hipStream_t st);
-void launch_sur_judge(const Dev &D, hipStream_t st);
+void launch_sur_targets(const Dev &D, float *t, hipStream_t st);
+// the surrogate pass of a step, before the solid launch: each scene's mode,
+// and for learned and judge scenes the features, the network and the
+// predicted averages (the solid launch then takes the learned step or judges)
+void launch_sur_net(const Dev &D, const MlpDev &M, hipStream_t st);
+// allow the surrogate pass its dynamic LDS (once per process and device)
+hipError_t allow_sur_net_lds();
 void launch_solid_dt(const Dev &D, hipStream_t st);
 // the same reduction at a step's end, after its close, into kappa_next only
 // (the step increments and kappa stay untouched)

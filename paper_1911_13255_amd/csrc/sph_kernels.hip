@@ -11,6 +11,7 @@
 #include <mutex>
 #include <type_traits>
 
+#include "mlp_device.h"
 #include "sph_kernels.h"
 #include "sph_physics.h"
 
@@ -2070,6 +2071,108 @@ __device__ void hand_over(const Dev &D, int a) {
 
 __device__ void fluid_step_end(const Dev &D, int blk, float *shm, unsigned long long (*shc)[16]);
 
+// Sub-step surrogate schedule (2D).  Per scene and step the mode is:
+//   judge step: the plain sub-steps run and stand, and the network's
+//     averages are compared with theirs over the N free particles,
+//     R = max(|dvbar|_2 / (|vbar|_2 + |g| dt sqrt(N)),
+//             |dabar|_2 / (|abar|_2 + |g| sqrt(N)));
+//     R <= threshold opens a window of every - 1 learned steps, else every - 1
+//     plain steps follow (a non-finite R fails);
+//   learned step: the predicted averages advance the solid (u += dt vbar,
+//     v += dt abar, F from the corrected gradient of vbar, a = abar) and the
+//     sub-steps are skipped;
+//   plain step: the plain sub-steps, no network.
+// The first step after the network is set is a judge step.  Exact averages
+// give R = 0 and pass any threshold.
+
+// mode of scene S's current step from the schedule its last judge set
+__device__ __forceinline__ int sur_mode(const SceneState &S) {
+  if (S.sur_window > 0) return kSurLearned;
+  return S.sur_countdown <= 0 ? kSurJudge : kSurPlain;
+}
+
+// The schedule after a step of the given mode (one thread of the scene's
+// block; sums over the free particles for a judge step).
+__device__ __forceinline__ void sur_schedule(const Dev &D, const ScenePar &P, SceneState &S, int mode, double dv2,
+                                             double v2, double da2, double a2) {
+  const int every = D.sur_every > 0 ? D.sur_every : 1;
+  if (mode == kSurLearned) {
+    S.sur_window -= 1;  // the judge step follows the last learned step
+  } else if (mode == kSurJudge) {
+    const int nfree = P.s_count - P.s_nclamp;
+    const double gabs = sqrt((double)P.g[0] * P.g[0] + (double)P.g[1] * P.g[1]);
+    const double rn = sqrt((double)(nfree > 0 ? nfree : 1));
+    const double rv = sqrt(dv2) / (sqrt(v2) + gabs * S.dt_ac * rn + 1e-300);
+    const double ra = sqrt(da2) / (sqrt(a2) + gabs * rn + 1e-300);
+    const double R = nfree > 0 ? fmax(rv, ra) : __builtin_nan("");
+    S.sur_last_r = (rv != rv || ra != ra) ? __builtin_nan("") : R;
+    const bool ok = S.sur_last_r <= (double)D.sur_thr;  // false for NaN
+    if (ok) {
+      S.sur_judge_ok += 1;
+      S.sur_window = every - 1;
+      S.sur_countdown = 0;
+    } else {
+      S.sur_judge_fail += 1;
+      S.sur_window = 0;
+      S.sur_countdown = every - 1;
+    }
+  } else if (mode == kSurPlain) {
+    S.sur_countdown -= 1;
+  }
+}
+
+// A learned step's solid update of the block's scene: the predicted vbar of
+// its particles staged in LDS (vb, two doubles each), then per free particle
+// dF/dt = sum_b (vbar_b - vbar_a) (x) g_ab B^T (the corrected gradient of
+// Section 2.2), F += dt dF/dt, u += dt vbar, v += dt abar, and the predicted
+// averages stored as the step's, the acceleration as abar.
+__device__ void sur_learned_block(const Dev &D, const ScenePar &P, const SceneState &S, double *vb) {
+  const int NS = D.ns, base = P.s_begin, n = P.s_count, nfree = n - P.s_nclamp;
+  const int t = threadIdx.x, T = blockDim.x;
+  for (int l = t; l < n; l += T) {
+    vb[2 * l] = D.sur_vbar[base + l];
+    vb[2 * l + 1] = D.sur_vbar[NS + base + l];
+  }
+  __syncthreads();
+  const double dt = S.dt_ac;
+  for (int l = t; l < nfree; l += T) {
+    const int a = base + l;
+    const double va0 = vb[2 * l], va1 = vb[2 * l + 1];
+    double G[4] = {0.0, 0.0, 0.0, 0.0};
+    const int cnt = D.s_cnt[a];
+#pragma unroll 4
+    for (int q = 0; q < cnt; ++q) {
+      const float4 g = D.s_nbr[(size_t)q * NS + a];
+      const int b = __float_as_int(g.w) - base;
+      const double d0 = vb[2 * b] - va0, d1 = vb[2 * b + 1] - va1;
+      G[0] += d0 * (double)g.x;
+      G[1] += d0 * (double)g.y;
+      G[2] += d1 * (double)g.x;
+      G[3] += d1 * (double)g.y;
+    }
+    double B[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) B[k] = D.s_B[k * NS + a];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const double dF = G[i * 2] * B[j * 2] + G[i * 2 + 1] * B[j * 2 + 1];
+        D.s_H[(i * 2 + j) * NS + a] += dt * dF;
+        D.s_dF[(i * 2 + j) * NS + a] = dF;
+      }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const float vbk = D.sur_vbar[k * NS + a], abk = D.sur_abar[k * NS + a];
+      D.s_u[k * NS + a] += dt * (double)vbk;
+      D.s_v[k * NS + a] += dt * (double)abk;
+      D.s_a[k * NS + a] = abk;
+      D.s_vbar[k * NS + a] = vbk;
+      D.s_abar[k * NS + a] = abk;
+    }
+  }
+}
+
 // The same sub-steps for 2D scenes whose free solid fits the block with at
 // most PPT particles per thread: each thread keeps its particles' own state
 // (H, dF/dt, u in FP64; B and the step increments in FP32) in registers for
@@ -2086,6 +2189,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   __shared__ int kap_sh;
   __shared__ double del_sh;
   __shared__ unsigned long long end_c[3][16];
+  __shared__ double sur_red[4][16];
   constexpr int D2 = DIM * DIM;
   if ((int)blockIdx.x >= D.n_scenes) {
     // blocks beside the scenes' solid blocks end the step of the fluid: its
@@ -2108,9 +2212,12 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   // one LDS record per particle: a neighbour's P B (or v) arrives in wide reads
   auto PI = [&](int l, int k) { return (int)__umul24((unsigned)l, (unsigned)PR) + k; };
   auto VI = [&](int l, int k) { return l * DIM + k; };
-  if (S.sur == kSurLearned) {
-    // a learned step advanced this scene's solid: only the step end remains,
-    // from the stored state
+  const int smode = DIM == 2 ? S.sur : kSurOff;  // the surrogate's mode of this step
+  if (smode == kSurLearned) {
+    // a learned step: the network's averages advance the solid instead of
+    // the sub-steps (each thread updates the particles it ends the step of)
+    if constexpr (DIM == 2) sur_learned_block(D, P, S, Vx);
+    if (t == 0) sur_schedule(D, P, S, smode, 0.0, 0.0, 0.0, 0.0);
     if (D.solid_step_end) {
       const bool rb = rebuilds_next(S);
       float sv = 0.0f, sa = 0.0f;
@@ -2383,6 +2490,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   const double inv_dt = 1.0 / dt_ac;
   const bool step_end = D.solid_step_end != 0, rb = step_end && rebuilds_next(S);
   float end_v = 0.0f, end_a = 0.0f;
+  double jdv = 0.0, jv = 0.0, jda = 0.0, ja = 0.0;  // a judge step's sums
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     if (!own[p]) continue;
@@ -2407,6 +2515,16 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
       bad |= !isfinite(vbar[k]) || !isfinite(abar[k]);
     }
     if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
+    if (smode == kSurJudge) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const double ev = (double)D.sur_vbar[k * NS + a] - vbar[k], ea = (double)D.sur_abar[k * NS + a] - abar[k];
+        jdv += ev * ev;
+        jv += (double)vbar[k] * vbar[k];
+        jda += ea * ea;
+        ja += (double)abar[k] * abar[k];
+      }
+    }
     if (step_end) {
       hand_over_values<DIM>(D, P, a, det_F<DIM>(H[p]), vbar, abar);
       if (rb) bin_entry<DIM>(D, D.nf + P.b_begin + P.w_count + l, true, kBinSolid);
@@ -2429,6 +2547,16 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
       S.send_v = __float_as_uint(end_v);
       S.send_a = __float_as_uint(end_a);
     }
+  }
+  if (smode != kSurOff) {
+    if (smode == kSurJudge) {
+      auto add = [](double x, double y) { return x + y; };
+      jdv = block_reduce(jdv, add, sur_red[0]);
+      jv = block_reduce(jv, add, sur_red[1]);
+      jda = block_reduce(jda, add, sur_red[2]);
+      ja = block_reduce(ja, add, sur_red[3]);
+    }
+    if (t == 0) sur_schedule(D, P, S, smode, jdv, jv, jda, ja);
   }
 }
 
@@ -2546,237 +2674,262 @@ __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int bin_blocks, int 
 
 // ------------------------------------------------------------------ surrogate
 //
-// Learned replacement of the kappa solid sub-steps of one acoustic step (2D):
-// per free solid particle, 24 features (F - I, v, a and the pressure and
-// viscous parts of the coupling force, then the mean of these 12 values over
-// the particle's reference neighbours) go through the network, which predicts
-// the change of the time-averaged velocity and acceleration over the step
-// (vbar - v, abar - a; Section 3.2 defines the averages).
+// Learned replacement of the kappa solid sub-steps of one acoustic step (2D).
+// Per free solid particle the network reads 24 features and predicts the
+// change of the time-averaged velocity and acceleration over the step
+// (Section 3.2 defines the averages).  With the own values F - I, v, a and
+// the pressure and viscous parts fp, fv of the coupling force, their means
+// over the reference neighbours (the own values where there are none), the
+// row's acceleration scale s = |a| + |mean a| + |g| + |fp + fv| / m + s0
+// (m = rho0_S V_S, s0 = 1e-3 m/s^2) and the acoustic step dt, the features
+// are F - I, v, a / s, fp / (m s), fv / (m s) and the neighbour mean minus the
+// own value of each of the 12 (F's as is, v's over s dt, a's over s, the
+// forces' over m s); the network's standardised output y gives, with
+// d = y std + mean, vbar = v + s dt d_v and abar = a + s d_a.  The scale puts
+// quiet and violent states on one footing; the differences carry what the
+// neighbour means add, at the resolution of their own size.
 //
-// The plain sub-steps judge the network.  Per scene and step the mode is:
-//   judge step: the plain sub-steps run, and the network's averages are
-//     compared with theirs, R = max(|dvbar|_2 / (|vbar|_2 + |g| dt sqrt(N)),
-//     |dabar|_2 / (|abar|_2 + |g| sqrt(N))) over the N free particles; the
-//     plain result stands.  R <= threshold opens a window of every - 1
-//     learned steps, else every - 1 plain steps follow;
-//   learned step: the predicted averages advance the solid (u += dt vbar,
-//     v += dt abar, F from the corrected gradient of vbar, a = abar) and the
-//     sub-steps are skipped;
-//   plain step: the plain sub-steps, no network.
-// The first step after the network is set is a judge step.  Exact averages
-// give R = 0 and pass any threshold.
+// The plain sub-steps judge the network (the schedule and the learned update
+// run inside the solid launch, one block per scene; see k_solid_reg).
 
-// mode of scene S's current step from the schedule its last judge set
-__device__ __forceinline__ int sur_mode(const SceneState &S) {
-  if (S.sur_window > 0) return kSurLearned;
-  return S.sur_countdown <= 0 ? kSurJudge : kSurPlain;
-}
-
-// Own features of solid particle a (2D).
-__device__ __forceinline__ void sur_own(const Dev &D, int a, float *f) {
+// Own values of solid particle a: F - I and v (FP64 state), a, fp, fv.
+struct SurOwn {
+  double h[4], v[2];
+  float a[2], fp[2], fv[2];
+};
+__device__ __forceinline__ SurOwn sur_own(const Dev &D, int a) {
   const int NS = D.ns;
-  for (int k = 0; k < 4; ++k) f[k] = (float)D.s_H[k * NS + a];
+  SurOwn o;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o.h[k] = D.s_H[k * NS + a];
+#pragma unroll
   for (int k = 0; k < 2; ++k) {
-    f[4 + k] = (float)D.s_v[k * NS + a];
-    f[6 + k] = D.s_a[k * NS + a];
-    float fp = D.s_fFp[k * NS + a];
-    f[8 + k] = fp;
-    f[10 + k] = D.s_fF[k * NS + a] - fp;
+    o.v[k] = D.s_v[k * NS + a];
+    o.a[k] = D.s_a[k * NS + a];
+    const float fp = D.s_fFp[k * NS + a];
+    o.fp[k] = fp;
+    o.fv[k] = D.s_fF[k * NS + a] - fp;
+  }
+  return o;
+}
+
+// Sums over reference neighbours of (neighbour value - own value).
+struct SurDiff {
+  double h[4], v[2], a[2], fp[2], fv[2];
+};
+__device__ __forceinline__ void sur_zero(SurDiff &d) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) d.h[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) d.v[k] = d.a[k] = d.fp[k] = d.fv[k] = 0.0;
+}
+// neighbours q0, q0 + dq, ... of particle a
+__device__ __forceinline__ void sur_diffs(const Dev &D, int a, const SurOwn &o, int q0, int dq, SurDiff &d) {
+  const int cnt = D.s_cnt[a];
+  for (int q = q0; q < cnt; q += dq) {
+    const SurOwn b = sur_own(D, __float_as_int(D.s_nbr[(size_t)q * D.ns + a].w));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d.h[k] += b.h[k] - o.h[k];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      d.v[k] += b.v[k] - o.v[k];
+      d.a[k] += (double)b.a[k] - (double)o.a[k];
+      d.fp[k] += (double)b.fp[k] - (double)o.fp[k];
+      d.fv[k] += (double)b.fv[k] - (double)o.fv[k];
+    }
+  }
+}
+// sum of the partial sums of the 4 consecutive lanes that share a particle
+__device__ __forceinline__ void sur_diffs_lanes4(SurDiff &d) {
+#pragma unroll
+  for (int m = 1; m < 4; m <<= 1) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d.h[k] += __shfl_xor(d.h[k], m);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      d.v[k] += __shfl_xor(d.v[k], m);
+      d.a[k] += __shfl_xor(d.a[k], m);
+      d.fp[k] += __shfl_xor(d.fp[k], m);
+      d.fv[k] += __shfl_xor(d.fv[k], m);
+    }
   }
 }
 
-// Feature row of solid particle a (free), standardised by (mean, 1/std)
-// when stats is given.
-__device__ __forceinline__ void sur_feature_row(const Dev &D, int a, const float *stats, float *row) {
-  float f[kSurFeat], m[12];
-  sur_own(D, a, f);
-  for (int k = 0; k < 12; ++k) m[k] = 0.0f;
-  int cnt = D.s_cnt[a];
-  for (int q = 0; q < cnt; ++q) {
-    int b = __float_as_int(D.s_nbr[(size_t)q * D.ns + a].w);
-    float fb[12];
-    sur_own(D, b, fb);
-    for (int k = 0; k < 12; ++k) m[k] += fb[k];
+constexpr double kSurScaleFloor = 1e-3;  // s0, m/s^2
+
+// The 24 raw features and the scale s of a free particle with cnt neighbours.
+__device__ __forceinline__ void sur_finish(const ScenePar &P, double dt, const SurOwn &o, SurDiff d, int cnt,
+                                           float *f, double &s) {
+  const double inv = cnt > 0 ? 1.0 / (double)cnt : 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) d.h[k] *= inv;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    d.v[k] *= inv;
+    d.a[k] *= inv;
+    d.fp[k] *= inv;
+    d.fv[k] *= inv;
   }
-  float inv = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
-  for (int k = 0; k < 12; ++k) f[12 + k] = m[k] * inv;
-  for (int k = 0; k < kSurFeat; ++k) row[k] = stats ? (f[k] - stats[k]) * stats[kSurFeat + k] : f[k];
+  const double m = (double)P.rho0s * (double)P.Vs;
+  const double a0 = o.a[0], a1 = o.a[1];
+  const double f0 = (double)o.fp[0] + o.fv[0], f1 = (double)o.fp[1] + o.fv[1];
+  s = sqrt(a0 * a0 + a1 * a1) + sqrt((a0 + d.a[0]) * (a0 + d.a[0]) + (a1 + d.a[1]) * (a1 + d.a[1])) +
+      sqrt((double)P.g[0] * P.g[0] + (double)P.g[1] * P.g[1]) + sqrt(f0 * f0 + f1 * f1) / m + kSurScaleFloor;
+  const double is = 1.0 / s, ims = 1.0 / (m * s), isd = 1.0 / (s * dt);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    f[k] = (float)o.h[k];
+    f[12 + k] = (float)d.h[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    f[4 + k] = (float)o.v[k];
+    f[6 + k] = (float)(o.a[k] * is);
+    f[8 + k] = (float)(o.fp[k] * ims);
+    f[10 + k] = (float)(o.fv[k] * ims);
+    f[16 + k] = (float)(d.v[k] * isd);
+    f[18 + k] = (float)(d.a[k] * is);
+    f[20 + k] = (float)(d.fp[k] * ims);
+    f[22 + k] = (float)(d.fv[k] * ims);
+  }
 }
 
-// Features of every solid particle, in solid order (clamp rows zero),
-// standardised by (mean, 1/std) when stats is given (training data).
+// Training features of every solid particle, in solid order (clamp rows
+// zero), standardised by (mean, 1/std) when stats is given; the scale, step,
+// v and a of each row are kept for the targets of the same step.
 __global__ void __launch_bounds__(256) k_sur_features(Dev D, const float *stats, float *x) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= D.ns) return;
-  const ScenePar &P = D.par[D.s_scene[a]];
+  const int sc = D.s_scene[a];
+  const ScenePar &P = D.par[sc];
   float *row = x + (size_t)a * kSurFeat;
+  float *aux = D.sur_aux + (size_t)a * 6;
   if (a - P.s_begin >= P.s_count - P.s_nclamp) {
     for (int k = 0; k < kSurFeat; ++k) row[k] = 0.0f;
+    for (int k = 0; k < 6; ++k) aux[k] = 0.0f;
     return;
   }
-  sur_feature_row(D, a, stats, row);
+  const double dt = D.st[sc].dt_ac;
+  const SurOwn o = sur_own(D, a);
+  SurDiff d;
+  sur_zero(d);
+  sur_diffs(D, a, o, 0, 1, d);
+  float f[kSurFeat];
+  double s;
+  sur_finish(P, dt, o, d, D.s_cnt[a], f, s);
+  for (int k = 0; k < kSurFeat; ++k) row[k] = stats ? (f[k] - stats[k]) * stats[kSurFeat + k] : f[k];
+  aux[0] = (float)s;
+  aux[1] = (float)dt;
+  aux[2] = (float)o.v[0];
+  aux[3] = (float)o.v[1];
+  aux[4] = o.a[0];
+  aux[5] = o.a[1];
 }
 
-// The surrogate step's features: the mode of each scene's step, standardised
-// feature rows for the scenes whose step needs the network (learned and
-// judge steps), and per 64-row tile of the network's forward pass whether any
-// of its rows does (a wavefront of 64 consecutive rows decides its tile).
-__global__ void __launch_bounds__(256) k_sur_step_features(Dev D) {
+// Training targets after a plain step, from the references its features
+// kept: ((vbar - v) / (s dt), (abar - a) / s) per free particle, zero rows
+// for the clamp.
+__global__ void __launch_bounds__(256) k_sur_targets(Dev D, float *t) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  bool need = false;
-  if (a < D.ns) {
-    const int s = D.s_scene[a];
-    const ScenePar &P = D.par[s];
-    SceneState &S = D.st[s];
-    const int mode = sur_mode(S);
-    const int local = a - P.s_begin;
-    if (local == 0) {
-      S.sur = mode;
-      if (mode == kSurLearned) S.kappa = 0;  // no sub-steps this step
-    }
-    need = mode != kSurPlain;
-    if (need) {
-      float *row = D.sur_x + (size_t)a * kSurFeat;
-      if (local >= P.s_count - P.s_nclamp) {
-        for (int k = 0; k < kSurFeat; ++k) row[k] = 0.0f;
-      } else {
-        sur_feature_row(D, a, D.sur_stats, row);
-      }
-    }
-  }
-  const unsigned long long any = __ballot(need);
-  if ((threadIdx.x & 63) == 0 && a < D.ns) D.sur_blk[a >> 6] = any != 0ull ? 1 : 0;
-}
-
-// Training targets after a plain step, from the raw features of its start:
-// (vbar - v, abar - a) per free particle, zero rows for the clamp.
-__global__ void __launch_bounds__(256) k_sur_targets(Dev D, const float *xraw, float *t) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= D.ns) return;
   const ScenePar &P = D.par[D.s_scene[a]];
   const int NS = D.ns;
   float *row = t + (size_t)a * kSurOut;
-  bool clamp = a - P.s_begin >= P.s_count - P.s_nclamp;
+  const float *aux = D.sur_aux + (size_t)a * 6;
+  if (a - P.s_begin >= P.s_count - P.s_nclamp) {
+    for (int k = 0; k < kSurOut; ++k) row[k] = 0.0f;
+    return;
+  }
+  const double s = aux[0], dt = aux[1];
   for (int k = 0; k < 2; ++k) {
-    row[k] = clamp ? 0.0f : D.s_vbar[k * NS + a] - xraw[(size_t)a * kSurFeat + 4 + k];
-    row[2 + k] = clamp ? 0.0f : D.s_abar[k * NS + a] - xraw[(size_t)a * kSurFeat + 6 + k];
+    row[k] = (float)(((double)D.s_vbar[k * NS + a] - (double)aux[2 + k]) / (s * dt));
+    row[2 + k] = (float)(((double)D.s_abar[k * NS + a] - (double)aux[4 + k]) / s);
   }
 }
 
-// Predicted averages from the network output (learned and judge steps).
-__global__ void __launch_bounds__(256) k_sur_apply(Dev D) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= D.ns) return;
-  const int s = D.s_scene[a];
-  const int mode = D.st[s].sur;
-  if (mode != kSurLearned && mode != kSurJudge) return;
-  const ScenePar &P = D.par[s];
-  const int NS = D.ns;
-  bool clamp = a - P.s_begin >= P.s_count - P.s_nclamp;
-  const float *mo = D.sur_stats + 2 * kSurFeat, *so = mo + kSurOut;
-  const float *y = D.sur_y + (size_t)a * kSurOut;
-  for (int k = 0; k < 2; ++k) {
-    float vb = (float)D.s_v[k * NS + a] + (y[k] * so[k] + mo[k]);
-    float ab = D.s_a[k * NS + a] + (y[2 + k] * so[2 + k] + mo[2 + k]);
-    D.sur_vbar[k * NS + a] = clamp ? 0.0f : vb;
-    D.sur_abar[k * NS + a] = clamp ? 0.0f : ab;
-  }
-}
-
-// A learned step's solid update: deformation rate from the predicted averaged
-// velocity (the corrected gradient of Section 2.2), F at the step end, and
-// the predicted averages as the step's (Section 3.2: u and v advance by dt
-// times them; the stored acceleration becomes abar).  Reads the neighbours'
-// predicted vbar only, so particles update in place without a barrier.
-__global__ void __launch_bounds__(256) k_sur_learned(Dev D) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= D.ns) return;
-  const int s = D.s_scene[a];
-  if (D.st[s].sur != kSurLearned) return;
-  const ScenePar &P = D.par[s];
-  const int NS = D.ns;
-  if (a - P.s_begin >= P.s_count - P.s_nclamp) return;
-  const double dt = D.st[s].dt_ac;
-  const double va[2] = {D.sur_vbar[a], D.sur_vbar[NS + a]};
-  double G[4] = {0.0, 0.0, 0.0, 0.0};
-  int cnt = D.s_cnt[a];
-  for (int q = 0; q < cnt; ++q) {
-    float4 g = D.s_nbr[(size_t)q * NS + a];
-    int b = __float_as_int(g.w);
-    double gv[2] = {g.x, g.y};
-    for (int i = 0; i < 2; ++i) {
-      double dv = (double)D.sur_vbar[i * NS + b] - va[i];
-      for (int j = 0; j < 2; ++j) G[i * 2 + j] += dv * gv[j];
-    }
-  }
-  double B[4];
-  for (int k = 0; k < 4; ++k) B[k] = D.s_B[k * NS + a];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
-      double dF = G[i * 2] * B[j * 2] + G[i * 2 + 1] * B[j * 2 + 1];
-      D.s_H[(i * 2 + j) * NS + a] += dt * dF;
-      D.s_dF[(i * 2 + j) * NS + a] = dF;
-    }
-  for (int k = 0; k < 2; ++k) {
-    float vb = D.sur_vbar[k * NS + a], ab = D.sur_abar[k * NS + a];
-    D.s_u[k * NS + a] += dt * (double)vb;
-    D.s_v[k * NS + a] += dt * (double)ab;
-    D.s_a[k * NS + a] = ab;
-    D.s_vbar[k * NS + a] = vb;
-    D.s_abar[k * NS + a] = ab;
-  }
-}
-
-// One block per scene, after the solid phase: a judge step's residual against
-// the plain averages just computed, and the schedule of the next steps.
-__global__ void __launch_bounds__(1024) k_sur_judge(Dev D) {
-  __shared__ double red[4][16];
-  const int s = blockIdx.x, NS = D.ns;
-  const ScenePar &P = D.par[s];
-  SceneState &S = D.st[s];
-  const int mode = S.sur;
-  const int nfree = P.s_count - P.s_nclamp;
-  double dv2 = 0.0, v2 = 0.0, da2 = 0.0, a2 = 0.0;
-  if (mode == kSurJudge)
-    for (int l = threadIdx.x; l < nfree; l += blockDim.x) {
-      const int a = P.s_begin + l;
-      for (int k = 0; k < 2; ++k) {
-        const double vb = D.s_vbar[k * NS + a], ab = D.s_abar[k * NS + a];
-        const double ev = (double)D.sur_vbar[k * NS + a] - vb, ea = (double)D.sur_abar[k * NS + a] - ab;
-        dv2 += ev * ev;
-        v2 += vb * vb;
-        da2 += ea * ea;
-        a2 += ab * ab;
+// The surrogate pass of a step, one block per 64 solid rows: each row's
+// scene mode (the first row of a scene records it for the solid launch and
+// the step's close); for tiles with rows of learned or judge scenes, the
+// features (four lanes per row share its neighbours), the network on the
+// matrix cores with its weights staged in LDS, and the predicted averages.
+__global__ void __launch_bounds__(256) k_sur_net(Dev D, MlpDev M) {
+  extern __shared__ __align__(16) unsigned short lds[];
+  __shared__ float r_s[kMlpTile], r_dt[kMlpTile], r_v[kMlpTile][2], r_a[kMlpTile][2];
+  __shared__ int r_need[kMlpTile];
+  const int t = threadIdx.x, l = t & 63;
+  const int row0 = blockIdx.x * kMlpTile;
+  int need = 0;
+  if (t < kMlpTile) {
+    const int a = row0 + t;
+    if (a < D.ns) {
+      const int sc = D.s_scene[a];
+      const ScenePar &P = D.par[sc];
+      SceneState &S = D.st[sc];
+      const int mode = sur_mode(S);
+      const int local = a - P.s_begin;
+      if (local == 0) {
+        S.sur = mode;
+        if (mode == kSurLearned) S.kappa = 0;  // no sub-steps this step
       }
+      // 1: a free row, 2: a clamp row (zero averages), of a scene that needs the network
+      need = mode == kSurPlain ? 0 : (local < P.s_count - P.s_nclamp ? 1 : 2);
     }
-  if (mode == kSurJudge) {
-    auto add = [](double x, double y) { return x + y; };
-    dv2 = block_reduce(dv2, add, red[0]);
-    v2 = block_reduce(v2, add, red[1]);
-    da2 = block_reduce(da2, add, red[2]);
-    a2 = block_reduce(a2, add, red[3]);
+    r_need[t] = need;
   }
-  if (threadIdx.x != 0) return;
-  const int every = D.sur_every > 0 ? D.sur_every : 1;
-  if (mode == kSurLearned) {
-    S.sur_window -= 1;  // the judge step follows the last learned step
-  } else if (mode == kSurJudge) {
-    const double gabs = sqrt((double)P.g[0] * P.g[0] + (double)P.g[1] * P.g[1]);
-    const double rn = sqrt((double)(nfree > 0 ? nfree : 1));
-    const double rv = sqrt(dv2) / (sqrt(v2) + gabs * S.dt_ac * rn + 1e-300);
-    const double ra = sqrt(da2) / (sqrt(a2) + gabs * rn + 1e-300);
-    const bool ok = nfree > 0 && fmax(rv, ra) <= (double)D.sur_thr;  // false for NaN
-    if (ok) {
-      S.sur_judge_ok += 1;
-      S.sur_window = every - 1;
-      S.sur_countdown = 0;
-    } else {
-      S.sur_judge_fail += 1;
-      S.sur_window = 0;
-      S.sur_countdown = every - 1;
+  if (!__syncthreads_or(need != 0)) return;
+  const FwdLds L = fwd_lds_layout(lds);
+  stage_weights(M, L);
+  const float *mean = D.sur_stats, *istd = D.sur_stats + kSurFeat;
+  {
+    const int r = t >> 2, q = t & 3, a = row0 + r;
+    const int nd = r_need[r];
+    SurOwn o;
+    SurDiff d;
+    sur_zero(d);
+    if (nd == 1) {
+      o = sur_own(D, a);
+      sur_diffs(D, a, o, q, 4, d);
     }
-  } else if (mode == kSurPlain) {
-    S.sur_countdown -= 1;
+    sur_diffs_lanes4(d);
+    unsigned short *hrow = L.HA + r * pitch(kMlpIn);
+    if (q == 0) {
+      if (nd == 1) {
+        const int sc = D.s_scene[a];
+        const double dt = D.st[sc].dt_ac;
+        float f[kSurFeat];
+        double s;
+        sur_finish(D.par[sc], dt, o, d, D.s_cnt[a], f, s);
+        for (int k = 0; k < kSurFeat; ++k) hrow[k] = f2bf((f[k] - mean[k]) * istd[k]);
+        r_s[r] = (float)s;
+        r_dt[r] = (float)dt;
+        r_v[r][0] = (float)o.v[0];
+        r_v[r][1] = (float)o.v[1];
+        r_a[r][0] = o.a[0];
+        r_a[r][1] = o.a[1];
+      } else {
+        for (int k = 0; k < kSurFeat; ++k) hrow[k] = 0;
+      }
+      for (int k = kSurFeat; k < kMlpIn; ++k) hrow[k] = 0;
+    }
+  }
+  __syncthreads();
+  const f4 out = forward_tile<false>(L, M, row0, D.ns);
+  const float *mo = D.sur_stats + 2 * kSurFeat, *so = mo + kSurOut;
+  const int NS = D.ns, r0 = (t >> 6) * 16, c = l & 15;
+  if (c < kSurOut) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + (l >> 4) * 4 + j, a = row0 + r;
+      const int nd = r_need[r];
+      if (nd == 0) continue;
+      float val = 0.0f;
+      if (nd == 1) {
+        const float dd = (out[j] + L.bias[3 * kMlpHid + c]) * so[c] + mo[c];
+        val = c < 2 ? r_v[r][c] + r_s[r] * r_dt[r] * dd : r_a[r][c - 2] + r_s[r] * dd;
+      }
+      if (c < 2) D.sur_vbar[c * NS + a] = val;
+      else D.sur_abar[(c - 2) * NS + a] = val;
+    }
   }
 }
 
@@ -3243,23 +3396,18 @@ void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t
   if (D.ns > 0) hipLaunchKernelGGL(k_sur_features, grid_for(D.ns, 256), dim3(256), 0, st, D, stats, x);
 }
 
-void launch_sur_targets(const Dev &D, const float *xraw, float *t, hipStream_t st) {
-  if (D.ns > 0) hipLaunchKernelGGL(k_sur_targets, grid_for(D.ns, 256), dim3(256), 0, st, D, xraw, t);
+void launch_sur_targets(const Dev &D, float *t, hipStream_t st) {
+  if (D.ns > 0) hipLaunchKernelGGL(k_sur_targets, grid_for(D.ns, 256), dim3(256), 0, st, D, t);
 }
 
-void launch_sur_step(const Dev &D, hipStream_t st) {
-  if (D.ns == 0) return;
-  hipLaunchKernelGGL(k_sur_step_features, grid_for(D.ns, 256), dim3(256), 0, st, D);
+void launch_sur_net(const Dev &D, const MlpDev &M, hipStream_t st) {
+  if (D.ns > 0)
+    hipLaunchKernelGGL(k_sur_net, dim3((D.ns + kMlpTile - 1) / kMlpTile), dim3(256), fwd_lds_bytes(), st, D, M);
 }
 
-void launch_sur_update(const Dev &D, hipStream_t st) {
-  if (D.ns == 0) return;
-  hipLaunchKernelGGL(k_sur_apply, grid_for(D.ns, 256), dim3(256), 0, st, D);
-  hipLaunchKernelGGL(k_sur_learned, grid_for(D.ns, 256), dim3(256), 0, st, D);
-}
-
-void launch_sur_judge(const Dev &D, hipStream_t st) {
-  if (D.ns > 0) hipLaunchKernelGGL(k_sur_judge, dim3(D.n_scenes), dim3(1024), 0, st, D);
+hipError_t allow_sur_net_lds() {
+  return hipFuncSetAttribute((const void *)k_sur_net, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)fwd_lds_bytes());
 }
 
 void launch_step_end(const Dev &D, hipStream_t st, bool reduced) {

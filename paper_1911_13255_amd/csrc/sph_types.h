@@ -68,6 +68,7 @@ struct SceneState {
   int sur, sur_window, sur_countdown, pad3;
   unsigned long long sur_ok, sur_fallback;          // steps taken by the network / by the plain sub-steps
   unsigned long long sur_judge_ok, sur_judge_fail;  // judge steps passed / failed
+  double sur_last_r;                                // residual R of the last judge step
 };
 
 // mode of a scene's acoustic step while a learned sub-step network is set
@@ -158,14 +159,12 @@ struct Dev {
   float *s_fFp;                    // pressure part of the coupling force
   int *s_cpl_cnt;                  // fluid neighbours of each free solid particle (set at rebuilds)
   unsigned *s_cpl;                 // [e * ns + a]: fluid index | (cell offset id << kNbrBits), ascending
-  // sub-step surrogate (2D): features, network output, predicted state
-  float *sur_x, *sur_y;            // ns x 24 standardised features, ns x 4 standardised outputs
+  // sub-step surrogate (2D)
   float *sur_stats;                // feature mean[24], 1/std[24], output mean[4], std[4]
-  float *sur_vbar, *sur_abar, *sur_amid;  // predicted averages, acceleration at the predicted mid state
-  double *sur_H, *sur_dF;          // predicted F - I and dF/dt at the step end
+  float *sur_vbar, *sur_abar;      // predicted averages (SoA, 3 x ns)
+  float *sur_aux;                  // ns x 6 of the last training features: s, dt, v, a (targets' references)
   float sur_thr;                   // residual threshold of a judge step (0: surrogate off)
   int sur_every;                   // judge interval: a passed judge opens sur_every - 1 learned steps
-  int *sur_blk;                    // per 64-row tile of the solid: 1 when a row of it needs the network
   double *s_r0d;                   // reference positions, FP64 (3 per particle)
   double *s_gsum;                  // sum over the reference neighbours of the stored V_b grad_a W_ab, FP64 (SoA)
   float4 *s_nbr;                   // [k * ns + a] = (V_b grad_a W_ab, b as int bits in w; in 2D z holds b - scene start)

@@ -106,8 +106,9 @@ def lib():
         L.sph_solid_table.argtypes = [vp, C.POINTER(C.c_int)]
         L.sph_set_surrogate.argtypes = [vp, vp, C.POINTER(C.c_float), C.c_float, C.c_int]
         L.sph_solid_features.argtypes = [vp, vp, vp]
-        L.sph_solid_targets.argtypes = [vp, vp, vp]
+        L.sph_solid_targets.argtypes = [vp, vp]
         L.sph_surrogate_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
+        L.sph_surrogate_residual.argtypes = [vp, C.c_int, C.POINTER(C.c_double)]
         L.sph_autotune.argtypes = [C.POINTER(SphScene), C.c_int, C.POINTER(SphOptions), vp, C.c_size_t, vp,
                                    C.c_int, C.c_int, C.POINTER(SphOptions), _dp]
         L.sph_reduce.argtypes = [vp, C.c_int, _dp]
@@ -377,12 +378,14 @@ class Simulation:
         self._leave()
         return x
 
-    def solid_targets(self, xraw, out=None):
+    def solid_targets(self, out=None):
+        """(n_solid x 4) FP32 device tensor of the training targets of the
+        step whose features solid_features took (call after solid_substeps)."""
         import torch
 
         t = out if out is not None else torch.empty((self.solid_count(), 4), dtype=torch.float32, device=self.device)
         self._enter()
-        self._check(self.L.sph_solid_targets(self.ctx, C.c_void_p(xraw.data_ptr()), C.c_void_p(t.data_ptr())))
+        self._check(self.L.sph_solid_targets(self.ctx, C.c_void_p(t.data_ptr())))
         self._leave()
         return t
 
@@ -407,6 +410,12 @@ class Simulation:
         self._check(self.L.sph_surrogate_counters(self.ctx, int(scene), out))
         return {"accepted": int(out[0]), "fallback": int(out[1]), "judged_ok": int(out[2]),
                 "judged_fail": int(out[3])}
+
+    def surrogate_residual(self, scene: int = 0) -> float:
+        """R of the scene's last judge step (NaN before the first)."""
+        out = C.c_double()
+        self._check(self.L.sph_surrogate_residual(self.ctx, int(scene), C.byref(out)))
+        return float(out.value)
 
     def launch_config(self) -> dict:
         out = (C.c_int * 8)()

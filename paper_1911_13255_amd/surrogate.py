@@ -6,8 +6,8 @@ library's HIP kernels; torch holds the datasets on the device.
 
 Training data comes from plain runs of the method (the kappa sub-steps): at
 sampled acoustic steps the 24 features of every free solid particle are taken
-between `couple` and `solid_substeps`, and the targets (vbar - v, abar - a)
-right after it.
+between `couple` and `solid_substeps`, and the targets ((vbar - v) / (s dt),
+(abar - a) / s, with the row's acceleration scale s) right after it.
 """
 from __future__ import annotations
 
@@ -37,7 +37,7 @@ def collect(scenes, steps: int, every: int = 4, warmup: int = 0, **options):
             x = sim.solid_features()
         sim.solid_substeps()
         if take:
-            t = sim.solid_targets(x)
+            t = sim.solid_targets()
             xs.append(x[mask])
             ts.append(t[mask])
     sim.sync()
@@ -73,7 +73,7 @@ def torch_where_small(s):
 
 
 def fit(X, T, seconds: float = 30.0, batch: int = 8192, lr: float = 1e-3, lr_end: float = 1e-4, seed: int = 0,
-        max_epochs: int = 200, log=None):
+        max_epochs: int = 1_000_000, log=None):
     """Train a fresh network on (X, T) with Adam on minibatches for about
     `seconds` (cosine-free exponential learning-rate decay from lr to
     lr_end).  Returns (network, stats, history)."""
@@ -140,6 +140,30 @@ def timed_steps_per_s(sim, steps: int):
     e1.record(sim.stream)
     e1.synchronize()
     return steps / (e0.elapsed_time(e1) / 1e3)
+
+
+def zero_network():
+    """(network, stats) that predict no change over the step (vbar = v,
+    abar = a): all weights and biases zero, output mean zero."""
+    net = mlp.Network(N_FEAT, N_OUT, max_rows=1 << 16)
+    net.set_params([(np.zeros((a, b), np.float32), np.zeros(b, np.float32)) for a, b in mlp.layer_shapes(N_FEAT, N_OUT)])
+    stats = np.concatenate([np.zeros(N_FEAT), np.ones(N_FEAT), np.zeros(N_OUT), np.ones(N_OUT)]).astype(np.float32)
+    return net, stats
+
+
+def judge_pass_fraction(scene, net, stats, threshold: float, start: int, steps: int, **options):
+    """Fraction of acoustic steps start .. start + steps of a plain run whose
+    judge would pass the network: every step is a judge step (the plain
+    sub-steps run and stand), so the trajectory is the plain method's and the
+    count measures the network's residual on the states the method visits."""
+    sim = sph.Simulation(scene, **options)
+    sim.advance(start)
+    sim.set_surrogate(net, stats, threshold, 1)
+    sim.advance(steps)
+    c = sim.surrogate_counters()
+    sim.sync()
+    sim.close()
+    return c["judged_ok"] / max(1, c["judged_ok"] + c["judged_fail"])
 
 
 def evaluate(scene, net, stats, threshold: float, steps: int, every: int = 10, timing_steps: int = 2000,
