@@ -96,6 +96,14 @@ typedef struct {
                            (lattice count inside 2 h_F times 1 + (dp_F/dp_S)^d) */
   int serial_passes;    /* 0: in sph_advance the continuity pass runs on a second stream,
                            concurrently with the coupling and solid passes; 1: one stream */
+  int solid_parts;      /* 0: the register-resident solid kernel runs one workgroup per scene;
+                           > 0: on serial steps without a surrogate, a scene with more free solid
+                           particles than this runs on ceil(n / solid_parts) workgroups (at most
+                           256 in all; scenes with one shared step keep one), which exchange
+                           P B and v through global memory between the half sub-steps.  Results
+                           equal the one-workgroup form bit for bit; it measured slower on the
+                           channel and the batch, so 0 is the default and the autotuner keeps
+                           the caller's value */
 } sph_options;
 
 /* Field ids for sph_read / sph_write (FP64, original particle order).
@@ -274,13 +282,15 @@ int sph_surrogate_counters(sph_ctx *ctx, int scene, unsigned long long *out);
  * scene out of range.  Synchronises. */
 int sph_surrogate_residual(sph_ctx *ctx, int scene, double *out);
 
-/* Launch configuration chosen at sph_init (no GPU work): out[0..7] = lanes
+/* Launch configuration chosen at sph_init (no GPU work): out[0..9] = lanes
  * per fluid particle in the pair passes, lanes per solid particle in the
  * coupling pass, threads per block of the pair passes, solid particles per
  * thread of the register-resident solid kernel (0: streamed passes),
- * threads per scene of that kernel, fluid and boundary pair-list capacity
- * per particle, 1 when sph_advance replays a captured HIP graph (0 before
- * the first sph_advance or without a graph). */
+ * threads per workgroup of that kernel, fluid and boundary pair-list
+ * capacity per particle, 1 when sph_advance replays a captured HIP graph (0
+ * before the first sph_advance or without a graph), the split form's target
+ * of free solid particles per workgroup (0: one workgroup per scene) and its
+ * workgroups. */
 int sph_launch_config(sph_ctx *ctx, int *out);
 
 /* Reference neighbour table of the solid (Section 2.2: the gradients
@@ -353,7 +363,10 @@ int sph_pairs(sph_ctx *ctx, int which, int scene, int *start, int *idx);
 
 /* Wait for the stream; return the first latched device error, if any, else
  * SPH_FALLBACK when a learned step fell back since the last call, else
- * SPH_OK. */
+ * SPH_OK.  The errors: SPH_E_UNSTABLE (non-finite state, det F <= 0),
+ * SPH_E_CAPACITY (a table or list overflowed), SPH_E_HIP (the workgroups of
+ * a scene split over several were not resident together, so their exchange
+ * gave up waiting), SPH_E_ORDER (fewer streamed sub-step passes than kappa). */
 int sph_sync(sph_ctx *ctx);
 
 /* Text of the last error of this context (static storage of the context). */

@@ -61,6 +61,7 @@ struct Plan {
   int capf = 0, capb = 0, lw = 1;  // pair-list capacities per particle and chunk width
   std::vector<ScenePar> par;
   std::vector<int> rank_to_cell, cell_scene, bs_scene;
+  std::vector<int4> parts_map;  // split form of the block-resident solid kernel: (scene, part, parts, 0)
   LaunchCfg cfg{256, 256, 256};
 };
 
@@ -298,6 +299,35 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
   }
   P.cfg.fork = o.serial_passes ? 0 : 1;
   P.cfg.solid_lds_n = P.cfg.solid_ppt ? max_solid_scene : 0;  // confirmed against the device in sph_init
+  // split form of the block-resident solid kernel: ceil(n_free / target)
+  // workgroups per scene (one for a scene with one shared step), the target
+  // doubled until the launch holds at most 256 of them (one per CU, so that
+  // all of a scene's workgroups are resident together)
+  if (o.solid_parts < 0) {
+    err = "solid_parts must be >= 0";
+    return false;
+  }
+  P.parts_map.clear();
+  P.cfg.solid_parts = 0;
+  if (P.cfg.solid_ppt > 0 && o.solid_parts > 0) {
+    constexpr int kMaxPartsBlocks = 256;
+    for (long long target = o.solid_parts;; target *= 2) {
+      std::vector<int4> m;
+      bool split = false;
+      for (int s = 0; s < n; ++s) {
+        const long long nfree = sc[s].n_solid - sc[s].n_clamp;
+        const int k = (sc[s].single_step || nfree <= target) ? 1 : (int)((nfree + target - 1) / target);
+        split |= k > 1;
+        for (int q = 0; q < k; ++q) m.push_back(make_int4(s, q, k, 0));
+      }
+      if (!split) break;
+      if ((int)m.size() <= kMaxPartsBlocks) {
+        P.parts_map = m;
+        P.cfg.solid_parts = (int)target;
+        break;
+      }
+    }
+  }
   // pair-list capacities: particles of a lattice inside the support 2 h_F,
   // with room for compression (fluid) and for the finer solid lattice
   // (boundary: walls at dp_F plus solid at dp_S)
@@ -406,6 +436,10 @@ size_t carve(char *base, const Plan &P, Dev &D) {
                    &D.sur_vbar, &D.sur_abar};
   for (float **p : vec) take(*p, 3 * ns);
   take(D.sur_aux, (size_t)6 * ns);
+  take(D.s_parts, std::max<size_t>(1, P.parts_map.size()));
+  take(D.parts_sync, 4 * (size_t)P.n_scenes);
+  take(D.s_xpb, P.parts_map.empty() ? 1 : (size_t)P.dim * P.dim * ns);
+  take(D.s_xv, P.parts_map.empty() ? 1 : (size_t)P.dim * ns);
   take(D.sur_stats, 2 * kSurFeat + 2 * kSurOut);
   take(D.s_r0d, 3 * ns);
   take(D.s_gsum, 3 * ns);
@@ -477,10 +511,13 @@ int read_states(sph_ctx *ctx, std::vector<SceneState> &st) {
 // back here (this synchronises the stream).
 // Register-resident sub-steps, preceded by the surrogate pass when a network
 // is set (the solid launch then takes the learned steps and judges).
-// step_end: the solid launch also does the step-end reduction's work
-void enqueue_solid_reg(sph_ctx *ctx, bool step_end) {
-  if (ctx->net && ctx->D.sur_thr > 0.0f) launch_sur_net(ctx->D, ctx->net->D, ctx->stream);
-  launch_solid(ctx->D, ctx->cfg, ctx->stream, step_end);
+// step_end: the solid launch also does the step-end reduction's work;
+// alone: nothing runs beside the launch, so its split form may be used
+// (not with a surrogate, whose judge reduces over one workgroup per scene)
+void enqueue_solid_reg(sph_ctx *ctx, bool step_end, bool alone = true) {
+  const bool sur = ctx->net && ctx->D.sur_thr > 0.0f;
+  if (sur) launch_sur_net(ctx->D, ctx->net->D, ctx->stream);
+  launch_solid(ctx->D, ctx->cfg, ctx->stream, step_end, alone && !sur);
 }
 
 // step_end as above; it applies to the register-resident form only (the
@@ -531,7 +568,7 @@ int enqueue_step(sph_ctx *ctx, bool fork) {
       return SPH_E_HIP;
     launch_fluid_continuity(ctx->D, ctx->cfg, ctx->side, false);
     launch_couple(ctx->D, ctx->cfg, ctx->stream);
-    enqueue_solid_reg(ctx, false);
+    enqueue_solid_reg(ctx, false, false);
     if (hipEventRecord(ctx->ev_join, ctx->side) != hipSuccess ||
         hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0) != hipSuccess)
       return SPH_E_HIP;
@@ -695,6 +732,11 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   }
   if (P.nb)
     HIPCHK_INIT(hipMemcpyAsync(D.bs_scene, P.bs_scene.data(), sizeof(int) * P.nb, hipMemcpyHostToDevice, st));
+  D.n_parts_blocks = (int)P.parts_map.size();
+  if (!P.parts_map.empty())
+    HIPCHK_INIT(hipMemcpyAsync(D.s_parts, P.parts_map.data(), sizeof(int4) * P.parts_map.size(),
+                               hipMemcpyHostToDevice, st));
+  HIPCHK_INIT(hipMemsetAsync(D.parts_sync, 0, sizeof(unsigned) * 4 * n_scenes, st));
   for (int s = 0; s < n_scenes; ++s) {
     const sph_scene &S = scenes[s];
     int d = P.dim;
@@ -726,6 +768,7 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
     if ((rc = check_launch(ctx, "scene set-up")) != SPH_OK) return fail(rc);
   }
   launch_solid_B(D, st);
+  launch_parts_range(D, st);
   launch_refresh_vmax(D, st);
   if ((rc = check_launch(ctx, "reference configuration")) != SPH_OK) return fail(rc);
   HIPCHK_INIT(hipStreamSynchronize(st));
@@ -1074,8 +1117,8 @@ int sph_launch_config(sph_ctx *ctx, int *out) {
   if (!ctx) return SPH_E_ORDER;
   if (!out) return SPH_E_ARG;
   const LaunchCfg &c = ctx->cfg;
-  int v[8] = {c.lpp_force, c.lpp_couple, c.block_pair, c.solid_ppt, c.block_solid, ctx->D.capf, ctx->D.capb,
-              ctx->graph_exec ? 1 : 0};
+  int v[10] = {c.lpp_force, c.lpp_couple, c.block_pair, c.solid_ppt, c.block_solid, ctx->D.capf, ctx->D.capb,
+               ctx->graph_exec ? 1 : 0, c.solid_parts, ctx->D.n_parts_blocks};
   std::memcpy(out, v, sizeof v);
   return SPH_OK;
 }
@@ -1206,14 +1249,16 @@ int sph_sync(sph_ctx *ctx) {
   for (int s = 0; s < ctx->n_scenes; ++s) {
     int e = st[s].err;
     if (e) {
-      std::snprintf(ctx->err, sizeof ctx->err, "scene %d: %s%s%s%s%s", s,
+      std::snprintf(ctx->err, sizeof ctx->err, "scene %d: %s%s%s%s%s%s", s,
                     (e & ERR_NAN_FLUID) ? "non-finite fluid state " : "",
                     (e & ERR_NAN_SOLID) ? "non-finite solid state " : "", (e & ERR_JACOBIAN) ? "det F <= 0 " : "",
                     (e & ERR_CAPACITY) ? "neighbour table overflow " : "",
-                    (e & ERR_KAPPA) ? "fewer solid sub-step passes than kappa" : "");
+                    (e & ERR_KAPPA) ? "fewer solid sub-step passes than kappa " : "",
+                    (e & ERR_PARTS) ? "the solid's workgroups were not resident together" : "");
       // a state that blew up also crowds cells: instability takes precedence
       if (e & (ERR_NAN_FLUID | ERR_NAN_SOLID | ERR_JACOBIAN)) return SPH_E_UNSTABLE;
-      return (e & ERR_CAPACITY) ? SPH_E_CAPACITY : SPH_E_ORDER;
+      if (e & ERR_CAPACITY) return SPH_E_CAPACITY;
+      return (e & ERR_PARTS) ? SPH_E_HIP : SPH_E_ORDER;
     }
   }
   // info: a judge step rejected the network since the last sync
@@ -1304,42 +1349,50 @@ int sph_autotune(const sph_scene *scenes, int n_scenes, const sph_options *opt, 
     return SPH_E_HIP;
   }
   const int lpps[] = {1, 2, 4, 8, 16}, blocks[] = {64, 128, 256};
-  double best_ms = -1.0;
-  sph_options pick = *opt;
-  int rc = SPH_OK;
-  for (int serial = 0; serial < 2 && rc == SPH_OK; ++serial)
+  // (the split form of the block-resident solid kernel is not a candidate:
+  // it measured slower on every workload, its exchanges writing back and
+  // invalidating the L2 of each XCD; the caller's solid_parts is kept)
+  std::vector<sph_options> cands;
+  for (int serial = 0; serial < 2; ++serial)
     for (int lpp : lpps)
       for (int bp : blocks) {
         sph_options o = *opt;
         o.lanes_per_particle = lpp;
         o.block_pair = bp;
         o.serial_passes = serial;
-        // two timed repetitions, the faster one counts (short runs are
-        // noisy); each starts from a fresh context, so a trial never runs
-        // more than warmup + steps steps of the scenes
-        float ms = 0.0f;
-        for (int rep = 0; rep < 2 && rc == SPH_OK; ++rep) {
-          sph_ctx *ctx = nullptr;
-          float m = 0.0f;
-          rc = sph_init(scenes, n_scenes, &o, dev_arena, arena_bytes, stream, &ctx);
-          if (rc == SPH_OK) rc = sph_advance(ctx, warmup);
-          if (rc == SPH_OK && (hipStreamSynchronize(st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess))
-            rc = SPH_E_HIP;
-          if (rc == SPH_OK) rc = sph_advance(ctx, steps);
-          if (rc == SPH_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                               hipEventElapsedTime(&m, e0, e1) != hipSuccess))
-            rc = SPH_E_HIP;
-          if (rc == SPH_OK) rc = sph_sync(ctx);
-          if (ctx) sph_destroy(ctx);
-          if (rc == SPH_OK) ms = rep == 0 ? m : std::min(ms, m);
-        }
-        if (rc != SPH_OK) break;
-        double per = (double)ms / steps;
-        if (best_ms < 0.0 || per < best_ms) {
-          best_ms = per;
-          pick = o;
-        }
+        cands.push_back(o);
       }
+  double best_ms = -1.0;
+  sph_options pick = *opt;
+  int rc = SPH_OK;
+  for (size_t ci = 0; ci < cands.size() && rc == SPH_OK; ++ci) {
+    const sph_options o = cands[ci];
+    // two timed repetitions, the faster one counts (short runs are noisy);
+    // each starts from a fresh context, so a trial never runs more than
+    // warmup + steps steps of the scenes
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2 && rc == SPH_OK; ++rep) {
+      sph_ctx *ctx = nullptr;
+      float m = 0.0f;
+      rc = sph_init(scenes, n_scenes, &o, dev_arena, arena_bytes, stream, &ctx);
+      if (rc == SPH_OK) rc = sph_advance(ctx, warmup);
+      if (rc == SPH_OK && (hipStreamSynchronize(st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess))
+        rc = SPH_E_HIP;
+      if (rc == SPH_OK) rc = sph_advance(ctx, steps);
+      if (rc == SPH_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&m, e0, e1) != hipSuccess))
+        rc = SPH_E_HIP;
+      if (rc == SPH_OK) rc = sph_sync(ctx);
+      if (ctx) sph_destroy(ctx);
+      if (rc == SPH_OK) ms = rep == 0 ? m : std::min(ms, m);
+    }
+    if (rc != SPH_OK) break;
+    const double per = (double)ms / steps;
+    if (best_ms < 0.0 || per < best_ms) {
+      best_ms = per;
+      pick = o;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != SPH_OK) return rc;

@@ -37,6 +37,7 @@ struct LaunchCfg {
   int solid_ppt;     // > 0: register-resident solid kernel (2D) with this many particles per thread;
                      // 0: streamed multi-block solid passes with kappa read back to the host
   int fork;          // 1: the continuity pass runs on a second stream beside coupling and solid
+  int solid_parts;   // > 0: serial steps split scenes of the block-resident solid kernel over workgroups
 };
 
 void launch_init_scene(const Dev &D, int s, const double *x_f, const double *v_f, int has_vf, double gabs,
@@ -46,6 +47,8 @@ void launch_init_solid(const Dev &D, int s, const double *x, const double *v, in
                        hipStream_t st);
 void launch_solid_reference(const Dev &D, int s, int ns_scene, hipStream_t st);
 void launch_solid_B(const Dev &D, hipStream_t st);
+// the neighbour span of each split solid workgroup (after the reference table)
+void launch_parts_range(const Dev &D, hipStream_t st);
 // compact reference table: class gradients from scene s, then every scene's
 // pairs checked against their class (D.nbc_ok cleared on a mismatch)
 void launch_solid_classes(const Dev &D, int s, hipStream_t st);
@@ -66,8 +69,10 @@ void launch_fluid_force(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 // launch where the shapes allow; returns true when it did
 bool launch_fluid_continuity(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool with_couple);
 void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
-// step_end: the launch also does the step-end reduction's work (serial steps)
-void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_end);
+// step_end: the launch also does the step-end reduction's work (serial steps);
+// parts: scenes split over the workgroups of D.s_parts (nothing else may run
+// beside the launch: its workgroups wait for each other)
+void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_end, bool parts = false);
 // reduced: the solid launch already did the step-end reduction's work
 void launch_step_end(const Dev &D, hipStream_t st, bool reduced);
 void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t st);

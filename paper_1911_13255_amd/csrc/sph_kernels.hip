@@ -2173,6 +2173,80 @@ __device__ void sur_learned_block(const Dev &D, const ScenePar &P, const SceneSt
   }
 }
 
+// Split form of the block-resident kernel: the workgroups of one scene meet
+// at a barrier on the scene's count in global memory (thread 0 of each; the
+// caller brackets it with __syncthreads).  `round` counts the launch's
+// barriers from 1.  A wait beyond the spin limit, or one that finds the
+// scene already failed, latches ERR_PARTS and returns: the workgroups then
+// run to their end without waiting, and the step is reported.
+constexpr long long kPartsSpinLimit = 1LL << 22;
+__device__ __forceinline__ void parts_barrier(const Dev &D, int s, int nparts, unsigned round) {
+  unsigned *bar = D.parts_sync + 4 * s + 2;
+  int *err = &D.st[s].err;
+  __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned target = round * (unsigned)nparts;
+  // poll without ordering, then one acquire: the polls do not drop the caches
+  for (long long n = 0; __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++n) {
+    if (n > kPartsSpinLimit || (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_PARTS)) {
+      atomicOr(err, (int)ERR_PARTS);
+      break;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Exchange of `rec` doubles per particle between the workgroups of a scene:
+// the own slice [l0, l1) of the LDS records (stride `stride`) to global
+// memory, the barrier, then the records of the other free particles in
+// [lo, hi), the range that the slice's reference neighbours span.
+__device__ __forceinline__ void parts_exchange(const Dev &D, int s, int nparts, unsigned &round, double *lds,
+                                               int stride, int rec, double *glob, int base, int l0, int l1, int lo,
+                                               int hi) {
+  const int t = threadIdx.x, T = blockDim.x;
+  for (int i = t; i < (l1 - l0) * rec; i += T) {
+    const int l = l0 + i / rec, k = i - (i / rec) * rec;
+    glob[(size_t)(base + l) * rec + k] = lds[l * stride + k];
+  }
+  __syncthreads();
+  ++round;
+  if (t == 0) parts_barrier(D, s, nparts, round);
+  __syncthreads();
+  const int before = l0 - lo, others = before + (hi - l1);
+  for (int i = t; i < others * rec; i += T) {
+    int l = i / rec;
+    const int k = i - l * rec;
+    l += l < before ? lo : l1 - before;  // [lo, l0) then [l1, hi)
+    lds[l * stride + k] = glob[(size_t)(base + l) * rec + k];
+  }
+  __syncthreads();
+}
+
+// The range [lo, hi) of free particles that the reference neighbours of
+// each split workgroup's slice span (with the slice itself), packed into the
+// map's fourth word as lo | hi << 16; once at set-up.
+__global__ void __launch_bounds__(256) k_parts_range(Dev D) {
+  __shared__ int sh[2][16];
+  int4 &m = D.s_parts[blockIdx.x];
+  const ScenePar &P = D.par[m.x];
+  const int nfree = P.s_count - P.s_nclamp, base = P.s_begin;
+  const int chunk = (nfree + m.z - 1) / m.z;
+  const int l0 = min(nfree, m.y * chunk), l1 = min(nfree, l0 + chunk);
+  int lo = l0, hi = l1;
+  for (int l = l0 + threadIdx.x; l < l1; l += blockDim.x) {
+    const int a = base + l, cnt = D.s_cnt[a];
+    for (int q = 0; q < cnt; ++q) {
+      const int b = __float_as_int(D.s_nbr[(size_t)q * D.ns + a].w) - base;
+      if (b < nfree) {
+        lo = min(lo, b);
+        hi = max(hi, b + 1);
+      }
+    }
+  }
+  lo = block_reduce(lo, [](int x, int y) { return min(x, y); }, sh[0]);
+  hi = block_reduce(hi, [](int x, int y) { return max(x, y); }, sh[1]);
+  if (threadIdx.x == 0) m.w = lo | (hi << 16);
+}
+
 // The same sub-steps for 2D scenes whose free solid fits the block with at
 // most PPT particles per thread: each thread keeps its particles' own state
 // (H, dF/dt, u in FP64; B and the step increments in FP32) in registers for
@@ -2182,6 +2256,12 @@ __device__ void sur_learned_block(const Dev &D, const ScenePar &P, const SceneSt
 // the sub-step loop.
 // Block limits keep the register budget: 1024 threads for one particle per
 // thread (4 waves per SIMD), 768 for two (3 waves per SIMD), 512 for four.
+// With D.solid_map a scene may run on several workgroups: each keeps a
+// contiguous slice of the free particles in registers and the whole scene's
+// P B and v in LDS, and the slices' new values are exchanged through global
+// memory after each half sub-step (parts_exchange); kappa comes from the
+// scene's maxima over all slices.  The sums of every particle are the ones
+// of the single-workgroup form, term for term.
 template <int DIM, int PPT>
 __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_solid_reg(Dev D, int lds_n) {
   extern __shared__ __align__(16) double smem[];
@@ -2191,20 +2271,34 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   __shared__ unsigned long long end_c[3][16];
   __shared__ double sur_red[4][16];
   constexpr int D2 = DIM * DIM;
-  if ((int)blockIdx.x >= D.n_scenes) {
+  const int nsb = D.solid_map ? D.solid_map_n : D.n_scenes;
+  if ((int)blockIdx.x >= nsb) {
     // blocks beside the scenes' solid blocks end the step of the fluid: its
     // speed and pair-count reductions, and the binning of fluid and walls for
     // a rebuild that the closing step sets
-    const int b = blockIdx.x - D.n_scenes;
+    const int b = blockIdx.x - nsb;
     if (b < D.end_fluid_blocks) fluid_step_end(D, b, red[0], end_c);
     else bin_entry<DIM>(D, (b - D.end_fluid_blocks) * blockDim.x + threadIdx.x, true, kBinFluid | kBinWalls);
     return;
   }
-  int s = blockIdx.x;
+  int s = blockIdx.x, part = 0, nparts = 1, span = 0;
+  if (D.solid_map) {
+    const int4 m = D.solid_map[blockIdx.x];
+    s = m.x;
+    part = m.y;
+    nparts = m.z;
+    span = m.w;
+  }
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
   const int NS = D.ns;
   const int base = P.s_begin, n = P.s_count, nfree = P.s_count - P.s_nclamp;
+  // this workgroup's slice [l0, l1) of the free particles
+  const int chunk = (nfree + nparts - 1) / nparts;
+  const int l0 = min(nfree, part * chunk), l1 = min(nfree, l0 + chunk);
+  // the free particles the slice's neighbours span (split form)
+  const int lo = nparts > 1 ? (span & 0xFFFF) : 0, hi = nparts > 1 ? (span >> 16) : nfree;
+  unsigned round = 0;
   const int T = blockDim.x, t = threadIdx.x;
   constexpr int PR = solid_pb_record(DIM);
   double *PBx = smem;
@@ -2255,8 +2349,8 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   float vm = 0.0f, am = 0.0f;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    la[p] = t + p * T;
-    own[p] = la[p] < nfree;
+    la[p] = l0 + t + p * T;
+    own[p] = la[p] < l1;
     int a = base + (own[p] ? la[p] : 0);
     float v2 = 0.0f, a2 = 0.0f;
 #pragma unroll
@@ -2342,14 +2436,26 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
       red[0][0] = fmaxf(red[0][0], red[0][w]);
       red[1][0] = fmaxf(red[1][0], red[1][w]);
     }
+    float vmax = red[0][0], amax = red[1][0];
+    if (nparts > 1) {
+      // the scene's maxima over its workgroups (every one derives the same kappa)
+      atomic_max_pos(&D.parts_sync[4 * s], vmax);
+      atomic_max_pos(&D.parts_sync[4 * s + 1], amax);
+      parts_barrier(D, s, nparts, 1);
+      vmax = __uint_as_float(__hip_atomic_load(&D.parts_sync[4 * s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      amax = __uint_as_float(__hip_atomic_load(&D.parts_sync[4 * s + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
     int kap;
     double dts;
-    solid_kappa(P, S, red[0][0], red[1][0], dt_ac, kap, dts);
+    solid_kappa(P, S, vmax, amax, dt_ac, kap, dts);
     kap_sh = kap;
     del_sh = dt_ac / kap;
-    S.dt_s = dts;
-    S.kappa = kap;
+    if (part == 0) {
+      S.dt_s = dts;
+      S.kappa = kap;
+    }
   }
+  if (nparts > 1) round = 1;
   __syncthreads();
   const int kap = kap_sh;
   const double del = del_sh;
@@ -2379,6 +2485,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
   for (int p = 0; p < PPT; ++p)
     if (own[p]) first_half(p);
   __syncthreads();
+  if (nparts > 1) parts_exchange(D, s, nparts, round, PBx, PR, D2, D.s_xpb, base, l0, l1, lo, hi);
   for (int sub = 0; sub < kap; ++sub) {
     // momentum, velocity
     {
@@ -2422,6 +2529,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
       }
     }
     __syncthreads();
+    if (nparts > 1) parts_exchange(D, s, nparts, round, Vx, DIM, DIM, D.s_xv, base, l0, l1, lo, hi);
     // deformation rate with the new velocity, second half; then the next
     // sub-step's first half and stress
     const bool more = sub + 1 < kap;
@@ -2482,6 +2590,7 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
       }
     }
     __syncthreads();
+    if (nparts > 1 && more) parts_exchange(D, s, nparts, round, PBx, PR, D2, D.s_xpb, base, l0, l1, lo, hi);
   }
   if (bad_J) atomicOr(&S.err, (int)ERR_JACOBIAN);
   // write back, time averages; where this launch ends the step, the
@@ -2557,6 +2666,13 @@ __global__ void __launch_bounds__(PPT == 1 ? 1024 : (PPT == 2 ? 768 : 512)) k_so
       ja = block_reduce(ja, add, sur_red[3]);
     }
     if (t == 0) sur_schedule(D, P, S, smode, jdv, jv, jda, ja);
+  }
+  if (nparts > 1 && t == 0) {
+    // the last workgroup of the scene clears its words for the next launch
+    const unsigned done =
+        __hip_atomic_fetch_add(&D.parts_sync[4 * s + 3], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (done + 1 == (unsigned)nparts)
+      for (int k = 0; k < 4; ++k) __hip_atomic_store(&D.parts_sync[4 * s + k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -3243,6 +3359,10 @@ void launch_solid_B(const Dev &D, hipStream_t st) {
   LAUNCH_DIM(D.dim, k_solid_B, dim3(nblk(D.ns, 256)), dim3(256), st, D);
 }
 
+void launch_parts_range(const Dev &D, hipStream_t st) {
+  if (D.n_parts_blocks > 0) hipLaunchKernelGGL(k_parts_range, dim3(D.n_parts_blocks), dim3(256), 0, st, D);
+}
+
 void launch_solid_classes(const Dev &D, int s, hipStream_t st) {
   hipLaunchKernelGGL(k_solid_classes, dim3(1), dim3(kNbrClasses), 0, st, D, s);
 }
@@ -3350,18 +3470,25 @@ void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st) {
     else hipLaunchKernelGGL((k_solid_reg<2, 4>), __VA_ARGS__);                            \
   } while (0)
 
-void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_end) {
+void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_end, bool parts) {
   size_t bytes = (size_t)cfg.solid_lds_n * solid_lds_bytes_per_particle(D.dim);
   Dev Ds = D;
   Ds.solid_step_end = step_end ? 1 : 0;
   Ds.end_fluid_blocks = 0;
+  const bool split = parts && cfg.solid_parts > 0 && D.n_parts_blocks > 0;
+  Ds.solid_map = split ? D.s_parts : nullptr;
+  Ds.solid_map_n = split ? D.n_parts_blocks : 0;
   int extra = 0;
   if (step_end) {
     const int T = cfg.block_solid;
     Ds.end_fluid_blocks = D.nf > 0 ? (D.nf + T * kReduceItems - 1) / (T * kReduceItems) : 0;
     extra = Ds.end_fluid_blocks + (D.nf + D.nb + T - 1) / T;
   }
-  LAUNCH_SOLID_REG(cfg.solid_ppt, dim3(D.n_scenes + extra), dim3(cfg.block_solid), bytes, st, Ds, cfg.solid_lds_n);
+  // (the scenes' workgroups come first: they are dispatched, and resident,
+  // before the step-end blocks beside them)
+  const int scene_blocks = split ? D.n_parts_blocks : D.n_scenes;
+  LAUNCH_SOLID_REG(cfg.solid_ppt, dim3(scene_blocks + extra), dim3(cfg.block_solid), bytes, st, Ds,
+                   cfg.solid_lds_n);
 }
 
 void launch_solid_dt(const Dev &D, hipStream_t st) {

@@ -75,8 +75,17 @@ struct SceneState {
 enum SurMode { kSurOff = 0, kSurLearned = 1, kSurJudge = 2, kSurPlain = 3 };
 
 // ERR_KAPPA: the streamed solid passes were launched fewer times than the
-// scene's kappa (an inconsistency of the host's sub-step count)
-enum ErrBits { ERR_NAN_FLUID = 1, ERR_NAN_SOLID = 2, ERR_JACOBIAN = 4, ERR_CAPACITY = 8, ERR_KAPPA = 16 };
+// scene's kappa (an inconsistency of the host's sub-step count);
+// ERR_PARTS: a workgroup of a scene split over several waited at their
+// exchange longer than the spin limit (they were not all resident)
+enum ErrBits {
+  ERR_NAN_FLUID = 1,
+  ERR_NAN_SOLID = 2,
+  ERR_JACOBIAN = 4,
+  ERR_CAPACITY = 8,
+  ERR_KAPPA = 16,
+  ERR_PARTS = 32
+};
 
 // Device pointers, passed by value to every kernel.
 struct Dev {
@@ -107,6 +116,14 @@ struct Dev {
   int couple_blocks; // leading blocks of the continuity launch that run the coupling on the solid
   int solid_step_end;    // 1: the block-resident solid launch also ends the step (hand-over, binning, reductions)
   int end_fluid_blocks;  // its blocks beside the scenes' that reduce the fluid's step end
+  // the block-resident solid kernel split over several workgroups per scene:
+  // per workgroup (scene, part, parts of the scene, 0); null: one per scene
+  const int4 *solid_map;
+  int solid_map_n;       // workgroups of the split form (the scenes' blocks of its launch)
+  int4 *s_parts;         // the split form's map (set at sph_init)
+  int n_parts_blocks;    // its workgroups
+  unsigned *parts_sync;  // per scene: max |v| and |a| bits, barrier count, workgroups done
+  double *s_xpb, *s_xv;  // exchange of P B (D^2 per particle) and v (D) between a scene's workgroups
   unsigned *f_nbl;  // fluid neighbours (capf entries per particle)
   unsigned *f_bnl;  // boundary neighbours: walls and free solid (capb per particle)
   int2 *f_rowlen;  // used length of each particle's two rows

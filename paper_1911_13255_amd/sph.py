@@ -59,7 +59,7 @@ class SphOptions(C.Structure):
     _fields_ = [("riemann", C.c_int), ("density_reinit", C.c_int), ("max_solid_nbr", C.c_int),
                 ("solid_block", C.c_int), ("lanes_per_particle", C.c_int), ("block_pair", C.c_int),
                 ("solid_lds", C.c_int), ("max_fluid_nbr", C.c_int), ("max_boundary_nbr", C.c_int),
-                ("serial_passes", C.c_int)]
+                ("serial_passes", C.c_int), ("solid_parts", C.c_int)]
 
     def as_dict(self) -> dict:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -167,10 +167,10 @@ def scene_array(scenes):
 
 
 def make_options(riemann=True, density_reinit=1, max_solid_nbr=0, solid_block=0, lanes_per_particle=0,
-                 block_pair=0, solid_lds=0, max_fluid_nbr=0, max_boundary_nbr=0, serial_passes=0):
+                 block_pair=0, solid_lds=0, max_fluid_nbr=0, max_boundary_nbr=0, serial_passes=0, solid_parts=0):
     return SphOptions(int(riemann), int(density_reinit), int(max_solid_nbr), int(solid_block),
                       int(lanes_per_particle), int(block_pair), int(solid_lds), int(max_fluid_nbr),
-                      int(max_boundary_nbr), int(serial_passes))
+                      int(max_boundary_nbr), int(serial_passes), int(solid_parts))
 
 
 def workload_signature(scenes, opt: dict) -> str:
@@ -183,7 +183,8 @@ def workload_signature(scenes, opt: dict) -> str:
     for sc in scenes:
         h.update(repr((int(sc["dim"]), len(sc["x_fluid"]), len(sc["x_wall"]), len(sc["x_solid"]),
                        int(sc["n_clamp"]), float(sc["dp_f"]), float(sc["dp_s"]))).encode())
-    fixed = {k: v for k, v in opt.items() if k not in ("lanes_per_particle", "block_pair", "serial_passes")}
+    fixed = {k: v for k, v in opt.items()
+             if k not in ("lanes_per_particle", "block_pair", "serial_passes", "solid_parts")}
     h.update(json.dumps(fixed, sort_keys=True).encode())
     h.update(torch.cuda.get_device_name(0).encode())
     return h.hexdigest()[:32]
@@ -242,7 +243,7 @@ class Simulation:
     def __init__(self, scenes, riemann: bool = True, density_reinit: int = 1,
                  max_solid_nbr: int = 0, solid_block: int = 0, lanes_per_particle: int = 0,
                  block_pair: int = 0, solid_lds: int = 0, max_fluid_nbr: int = 0,
-                 max_boundary_nbr: int = 0, serial_passes: int = 0, device: int = 0,
+                 max_boundary_nbr: int = 0, serial_passes: int = 0, solid_parts: int = 0, device: int = 0,
                  arena_fill: int = None):
         """arena_fill: byte written over the whole arena before sph_init (tests
         use it to show that no result depends on the arena's prior contents)."""
@@ -259,7 +260,7 @@ class Simulation:
         self._scene_dicts = scenes
         self._scenes = arr
         self.opt = make_options(riemann, density_reinit, max_solid_nbr, solid_block, lanes_per_particle,
-                                block_pair, solid_lds, max_fluid_nbr, max_boundary_nbr, serial_passes)
+                                block_pair, solid_lds, max_fluid_nbr, max_boundary_nbr, serial_passes, solid_parts)
         nbytes = self.L.sph_arena_bytes(arr, self.n_scenes, C.byref(self.opt))
         if nbytes == 0:
             raise SphError(SPH_E_ARG, "invalid scene description")
@@ -418,10 +419,10 @@ class Simulation:
         return float(out.value)
 
     def launch_config(self) -> dict:
-        out = (C.c_int * 8)()
+        out = (C.c_int * 10)()
         self._check(self.L.sph_launch_config(self.ctx, out))
         keys = ("lpp_fluid", "lpp_couple", "block_pair", "solid_ppt", "block_solid", "cap_fluid_nbr",
-                "cap_boundary_nbr", "graph")
+                "cap_boundary_nbr", "graph", "solid_parts", "solid_workgroups")
         return dict(zip(keys, [int(x) for x in out]))
 
     def solid_table(self) -> dict:

@@ -95,3 +95,20 @@ def test_autotune_and_option_checks_without_gpu():
     # the autotuner's cache key depends on the scene shapes, not on the tuned fields
     import paper_1911_13255_amd.sph as S
     assert S.make_options(lanes_per_particle=4).as_dict()["lanes_per_particle"] == 4
+
+
+def test_split_solid_option_is_validated_and_sized():
+    # solid_parts: negative values are rejected; a target that splits the
+    # channel's plate adds the exchange buffers to the arena
+    import ctypes
+
+    from paper_1911_13255_amd import scenes, sph
+
+    L = sph.lib()
+    arr, keep = sph.scene_array([scenes.plate_behind_cylinder(seed=1)])
+    assert L.sph_arena_bytes(arr, 1, ctypes.byref(sph.make_options(solid_parts=-1))) == 0
+    plain = L.sph_arena_bytes(arr, 1, ctypes.byref(sph.make_options()))
+    split = L.sph_arena_bytes(arr, 1, ctypes.byref(sph.make_options(solid_parts=128)))
+    assert plain > 0 and split > plain
+    # a target above the plate's free particles splits nothing
+    assert L.sph_arena_bytes(arr, 1, ctypes.byref(sph.make_options(solid_parts=100000))) == plain
