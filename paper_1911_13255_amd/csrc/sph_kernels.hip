@@ -1365,21 +1365,14 @@ __device__ __forceinline__ float4 pair_shift(const ScenePar &P, bool tab_ok, con
 // Per fluid pair (e = r/|r|, du = U_L - U_R = -(v_i - v_j).e):
 //   P* = (p_i + p_j)/2 + (rho_i + rho_j)/4 clamp(3 du, 0, c) du,
 //   f_i += -2 V_i V_j P* dW e + 2 eta V_i V_j dW / |r| (v_i - v_j).
-template <int DIM, int LPP>
-__global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
-  __shared__ float4 shift_tab[27];
-  if ((int)blockIdx.x < D.sort_blocks) {
-    sort_coupling_lists(D, D.sort_blocks);
-    return;
-  }
-  // the leading blocks are a multiple of 8: the XCD of a force block is
-  // still its index modulo 8
-  int g = xcd_block(blockIdx.x - D.sort_blocks, gridDim.x - D.sort_blocks) * blockDim.x + threadIdx.x;
-  int i = g / LPP, q = g % LPP;
-  bool active = i < D.nf;
-  int ii = active ? i : 0;
-  int s = D.nf > 0 ? D.f_scene[ii] : 0;
-  const bool tab_ok = stage_shifts<DIM>(D, s, shift_tab);
+// One fluid particle's force pass (LPP lanes: lane q takes list entries q,
+// q + LPP, ...).  fetch(j, PREP) gives the neighbour's frozen position and
+// its snapshot (v^n, eps^{n+1/2}) (formed from the step-start state when
+// there is no snapshot pass); every lane of the group must call it.
+template <int DIM, int LPP, typename Fetch>
+__device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool active, int s, bool tab_ok,
+                                               const float4 *shift_tab, Fetch &&fetch) {
+  const int ii = active ? i : 0;
   const ScenePar P = D.par[s];  // by value: the pair loop keeps its fields in registers
   float dt = (float)D.st[s].dt_ac;
   float4 pi = D.f_pos[ii];
@@ -1411,16 +1404,9 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
       constexpr bool PREP = decltype(prep_tag)::value;
       for (int e = q; e < rl.x; e += LPP, lp += lstride) {
         const unsigned ent = *lp;
-        const int j = (int)(ent & kNbrMask);
         const float4 sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
-        const float4 pj = D.f_pos[j];
-        float4 vj4;
-        if (PREP) {
-          vj4 = D.f_vs[j];
-        } else {
-          vj4 = D.f_va[j];
-          vj4.w += 0.5f * dt * D.f_drho[j];
-        }
+        float4 pj, vj4;
+        fetch(ent, PREP, dt, pj, vj4);
         const float p_j = eos_p_pair(vj4.w, P, tait7);
         const float Vj = pj.w * fast_rcp(P.rho0 * (1.0f + vj4.w));
         float r[3] = {(pi.x - pj.x) - sh.x, (pi.y - pj.y) - sh.y, DIM == 3 ? (pi.z - pj.z) - sh.z : 0.0f};
@@ -1474,6 +1460,38 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
   if (!prep) D.f_vs[i] = make_float4(vi[0], vi[1], vi[2], ehi);
   D.f_p[i] = p_i;
   D.f_acc[i] = make_float4(a[0], a[1], a[2], 0.0f);
+}
+
+// neighbour state from global memory (the per-particle form)
+struct FetchGlobal {
+  const Dev &D;
+  __device__ __forceinline__ void operator()(unsigned ent, bool prep, float dt, float4 &pj, float4 &vj4) const {
+    const int j = (int)(ent & kNbrMask);
+    pj = D.f_pos[j];
+    if (prep) {
+      vj4 = D.f_vs[j];
+    } else {
+      vj4 = D.f_va[j];
+      vj4.w += 0.5f * dt * D.f_drho[j];
+    }
+  }
+};
+
+template <int DIM, int LPP>
+__global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
+  __shared__ float4 shift_tab[27];
+  if ((int)blockIdx.x < D.sort_blocks) {
+    sort_coupling_lists(D, D.sort_blocks);
+    return;
+  }
+  // the leading blocks are a multiple of 8: the XCD of a force block is
+  // still its index modulo 8
+  int g = xcd_block(blockIdx.x - D.sort_blocks, gridDim.x - D.sort_blocks) * blockDim.x + threadIdx.x;
+  int i = g / LPP, q = g % LPP;
+  bool active = i < D.nf;
+  int s = D.nf > 0 ? D.f_scene[active ? i : 0] : 0;
+  const bool tab_ok = stage_shifts<DIM>(D, s, shift_tab);
+  force_particle<DIM, LPP>(D, i, q, active, s, tab_ok, shift_tab, FetchGlobal{D});
 }
 
 // Force of the fluid on each free solid particle (Section 2.2, F:p and F:v at
