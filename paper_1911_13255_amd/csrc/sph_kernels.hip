@@ -1365,6 +1365,36 @@ __device__ __forceinline__ float4 pair_shift(const ScenePar &P, bool tab_ok, con
 // Per fluid pair (e = r/|r|, du = U_L - U_R = -(v_i - v_j).e):
 //   P* = (p_i + p_j)/2 + (rho_i + rho_j)/4 clamp(3 du, 0, c) du,
 //   f_i += -2 V_i V_j P* dW e + 2 eta V_i V_j dW / |r| (v_i - v_j).
+// Lane q's walk over a pair-list row (entries q, q + LPP, ... below n, at
+// lp, lp + lstride, ...): body(entry, a, b) for each, where load(entry, a, b)
+// gathers the neighbour's two records.  The next pair's gathers and the
+// entry after it are issued before the current pair's arithmetic, so a
+// lane's loads overlap its own arithmetic instead of waiting at every pair
+// (measured on the 3D dam break: force pass 634 -> 583 us; two pairs ahead
+// took 615 us).
+template <int LPP, typename Load, typename Body>
+__device__ __forceinline__ void walk_pairs(const unsigned *lp, size_t lstride, int q, int n, Load &&load,
+                                           Body &&body) {
+  if (q >= n) return;
+  unsigned ent = *lp;
+  float4 a, b;
+  load(ent, a, b);
+  unsigned nxt = q + LPP < n ? lp[lstride] : 0u;
+  for (int e = q;; e += LPP) {
+    const unsigned ent_c = ent;
+    const float4 a_c = a, b_c = b;
+    const bool more = e + LPP < n;
+    if (more) {
+      ent = nxt;
+      load(ent, a, b);
+      lp += lstride;
+      nxt = e + 2 * LPP < n ? lp[lstride] : 0u;
+    }
+    body(ent_c, a_c, b_c);
+    if (!more) break;
+  }
+}
+
 // One fluid particle's force pass (LPP lanes: lane q takes list entries q,
 // q + LPP, ...).  fetch(j, PREP) gives the neighbour's frozen position and
 // its snapshot (v^n, eps^{n+1/2}) (formed from the step-start state when
@@ -1402,11 +1432,9 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
     // the loop is written once and instantiated for both snapshot sources
     auto fluid_pairs = [&](auto prep_tag) {
       constexpr bool PREP = decltype(prep_tag)::value;
-      for (int e = q; e < rl.x; e += LPP, lp += lstride) {
-        const unsigned ent = *lp;
+      auto load = [&](unsigned ent, float4 &pj, float4 &vj4) { fetch(ent, PREP, dt, pj, vj4); };
+      walk_pairs<LPP>(lp, lstride, q, rl.x, load, [&](unsigned ent, const float4 &pj, const float4 &vj4) {
         const float4 sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
-        float4 pj, vj4;
-        fetch(ent, PREP, dt, pj, vj4);
         const float p_j = eos_p_pair(vj4.w, P, tait7);
         const float Vj = pj.w * fast_rcp(P.rho0 * (1.0f + vj4.w));
         float r[3] = {(pi.x - pj.x) - sh.x, (pi.y - pj.y) - sh.y, DIM == 3 ? (pi.z - pj.z) - sh.z : 0.0f};
@@ -1427,7 +1455,7 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
         const float cpress = (m2Vi * VdW) * Ps * inv_r;  // times r: the unit vector's 1/|r| folded in
         const float cvisc = (e2Vi * VdW) * inv_r;
         for (int k = 0; k < DIM; ++k) fsum[k] += cpress * r[k] + cvisc * dv[k];
-      }
+      });
     };
     if (prep) fluid_pairs(std::true_type{});
     else fluid_pairs(std::false_type{});
@@ -1590,15 +1618,16 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
     const size_t lstride = (size_t)D.nf * LPP;
     const unsigned *lp = D.f_nbl + (size_t)i * LPP + q;
     {
-      for (int e = q; e < rl.x; e += LPP, lp += lstride) {
-        const unsigned ent = *lp;
+      auto load = [&](unsigned ent, float4 &pj, float4 &vj4) {
         const int j = (int)(ent & kNbrMask);
+        pj = D.f_pos[j];
+        vj4 = D.f_vb[j];
+      };
+      walk_pairs<LPP>(lp, lstride, q, rl.x, load, [&](unsigned ent, const float4 &pj, const float4 &vj4) {
         const float4 sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
-        const float4 pj = D.f_pos[j];
-        const float4 vj4 = D.f_vb[j];
         // the force pass's pressure: recomputed from eps for gamma = 7 (the
         // same expression, so the same bits) instead of a second gather
-        const float p_j = tait7 ? eos_p_pair(vj4.w, P, true) : D.f_p[j];
+        const float p_j = tait7 ? eos_p_pair(vj4.w, P, true) : D.f_p[ent & kNbrMask];
         const float Vj = pj.w * fast_rcp(P.rho0 * (1.0f + vj4.w));
         float r[3] = {(pi.x - pj.x) - sh.x, (pi.y - pj.y) - sh.y, DIM == 3 ? (pi.z - pj.z) - sh.z : 0.0f};
         float r2 = r[0] * r[0] + r[1] * r[1];
@@ -1612,7 +1641,7 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
         const float rhoj = P.rho0 * (1.0f + vj4.w);
         const float dvs = 0.5f * (w * inv_r) + (p_i - p_j) * fast_rcp((rhoi + rhoj) * rc);
         drho += (2.0f * rhoi) * (Vj * dW) * (rc > 0.0f ? dvs : 0.5f * (w * inv_r));
-      }
+      });
     }
     lp = D.f_bnl + (size_t)i * LPP + q;
     for (int e = q; e < rl.y; e += LPP, lp += lstride) {
