@@ -1063,10 +1063,11 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         float rz = DIM == 3 ? (pi.z - pj.z) - sh[2] : 0.0f;
         float r2 = rx * rx + ry * ry + rz * rz;
         if (r2 < P.r2max_f) {
-          const double4 qj = qload();
-          double dx = (qi.x - qj.x) - shd[0], dy = (qi.y - qj.y) - shd[1];
-          double dz = DIM == 3 ? (qi.z - qj.z) - shd[2] : 0.0;
-          psi += Vf * W64(sqrt(dx * dx + dy * dy + dz * dz));
+          if constexpr (DIM == 2) {
+            const double4 qj = qload();
+            double dx = (qi.x - qj.x) - shd[0], dy = (qi.y - qj.y) - shd[1];
+            psi += Vf * W64(sqrt(dx * dx + dy * dy));
+          }
           nff++;
           hit = true;
         }
@@ -1084,11 +1085,12 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         float rz = DIM == 3 ? (pi.z - pb.z) - sh[2] : 0.0f;
         float r2 = rx * rx + ry * ry + rz * rz;
         if (r2 < P.r2max_f) {
-          const double4 qb = qload();
-          double dx = (qi.x - qb.x) - shd[0], dy = (qi.y - qb.y) - shd[1];
-          double dz = DIM == 3 ? (qi.z - qb.z) - shd[2] : 0.0;
           bool wall = nwload() > 0.0f;
-          psi += (wall ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy + dz * dz));
+          if constexpr (DIM == 2) {
+            const double4 qb = qload();
+            double dx = (qi.x - qb.x) - shd[0], dy = (qi.y - qb.y) - shd[1];
+            psi += (wall ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy));
+          }
           if (wall) {
             nfw++;
           } else {
@@ -1215,35 +1217,59 @@ __global__ void __launch_bounds__(256) k_reinit(Dev D) {
         // the same cell offset in FP64 (sh is an exact multiple of the FP32 cell size)
         double shd[3];
         for (int k = 0; k < 3; ++k) shd[k] = (double)(sh[k] / P.cs[k]) * P.csd[k];
-        // the candidates' FP64 offsets are loaded with their FP32 ones (reading
-        // them only for a match, one candidate in six, measured no faster)
+        // the candidates are tested in FP32 only; the FP64 number density
+        // is summed over the finished rows below
         const int2 se = D.fc_se[cb + nl];
         for (int j0 = se.x; j0 < se.y; j0 += LPP) {
           const int j = j0 + q;
           const bool valid = j < se.y && j != i;
           float4 pj;
-          double4 qj;
-          if (valid) {
-            pj = D.f_pos[j];
-            qj = D.f_posd[j];
-          }
-          fluid_candidate(valid, j, pj, [&] { return qj; }, sh, shd, tag);
+          if (valid) pj = D.f_pos[j];
+          fluid_candidate(valid, j, pj, [&] { return make_double4(0.0, 0.0, 0.0, 0.0); }, sh, shd, tag);
         }
         const int2 be = D.bc_se[cb + nl];
         for (int k0 = be.x; k0 < be.y; k0 += LPP) {
           const int k = k0 + q;
           const bool valid = k < be.y;
           float4 pb;
-          double4 qb;
           float nw = 0.0f;
           if (valid) {
             pb = D.b_pos[k];
-            qb = D.b_posd[k];
             nw = D.b_nrm[k].w;
           }
-          boundary_candidate(valid, k, pb, [&] { return qb; }, [&] { return nw; }, sh, shd, tag, cid);
+          boundary_candidate(valid, k, pb, [&] { return make_double4(0.0, 0.0, 0.0, 0.0); }, [&] { return nw; },
+                             sh, shd, tag, cid);
         }
       });
+      // FP64 number density over the rows just written (every entry a pair,
+      // so the lanes stay converged): lane q reads the entries it would walk
+      // in the pair passes, written by any lane of its group
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      auto shift64 = [&](unsigned ent, double *shd) {
+        const int cid = (int)(ent >> kNbrBits);
+        shd[0] = (double)(cid % 3 - 1) * P.csd[0];
+        shd[1] = (double)((cid / 3) % 3 - 1) * P.csd[1];
+        shd[2] = (double)(cid / 9 - 1) * P.csd[2];
+      };
+      const int nfl = min(lenf, D.capf), nbl = min(lenb, D.capb);
+      for (int e = q; e < nfl; e += LPP) {
+        const unsigned ent = lf[(size_t)(e / LPP) * lstride + q];
+        double shd[3];
+        shift64(ent, shd);
+        const double4 qj = D.f_posd[ent & kNbrMask];
+        const double dx = (qi.x - qj.x) - shd[0], dy = (qi.y - qj.y) - shd[1], dz = (qi.z - qj.z) - shd[2];
+        psi += Vf * W64(sqrt(dx * dx + dy * dy + dz * dz));
+      }
+      for (int e = q; e < nbl; e += LPP) {
+        const unsigned ent = lb[(size_t)(e / LPP) * lstride + q];
+        const int k = (int)(ent & kNbrMask);
+        double shd[3];
+        shift64(ent, shd);
+        const double4 qb = D.b_posd[k];
+        const double dx = (qi.x - qb.x) - shd[0], dy = (qi.y - qb.y) - shd[1], dz = (qi.z - qb.z) - shd[2];
+        psi += (D.b_nrm[k].w > 0.0f ? Vf : Vs) * W64(sqrt(dx * dx + dy * dy + dz * dz));
+      }
     }
   }
   psi = group_sum<LPP>(psi);
