@@ -104,6 +104,11 @@ typedef struct {
                            equal the one-workgroup form bit for bit; it measured slower on the
                            channel and the batch, so 0 is the default and the autotuner keeps
                            the caller's value */
+  int fluid_tiles;      /* 0: in 3D, each block of the fluid force and continuity passes stages the
+                           records of its particles' distinct fluid neighbours (at most 768) in LDS
+                           and reads them there; the rebuild rewrites those particles' fluid rows to
+                           index that set.  Results equal the per-pair gathers bit for bit.
+                           -1: per-pair gathers.  2D always uses per-pair gathers. */
 } sph_options;
 
 /* Field ids for sph_read / sph_write (FP64, original particle order).
@@ -304,6 +309,17 @@ int sph_launch_config(sph_ctx *ctx, int *out);
  * out[2] = bytes per pair that the sub-step passes read.  SPH_E_ORDER
  * without a context, SPH_E_ARG for a null out. */
 int sph_solid_table(sph_ctx *ctx, int *out);
+
+/* Neighbour tiles of the fluid force and continuity passes (Section 3.1 pair
+ * sums; sph_options.fluid_tiles) as the last rebuild left them, five values:
+ * out[0] particles per group, one block of the pair launches (0: no tiles),
+ * out[1] groups, out[2] groups whose fluid rows index their tile (the others
+ * straddle scenes or have more than 768 distinct fluid neighbours and gather
+ * per pair), out[3] distinct fluid neighbours summed over those groups,
+ * out[4] the largest such tile.  Waits for the context's stream (a device to
+ * host copy).  SPH_E_ORDER without a context, SPH_E_ARG for a null out,
+ * SPH_E_HIP on a failed copy. */
+int sph_fluid_tiles(sph_ctx *ctx, long long *out);
 
 /* FP64 reductions of one scene: out[0..2] fluid momentum, out[3..5] solid
  * momentum, out[6] fluid kinetic energy, out[7] solid kinetic energy,

@@ -59,6 +59,7 @@ struct Plan {
   int nf = 0, nw = 0, ns = 0, nb = 0, ncell = 0, maxn = 0;
   int max_count = 0;
   int capf = 0, capb = 0, lw = 1;  // pair-list capacities per particle and chunk width
+  int tile_gp = 0;                 // particles per neighbour tile (0: per-pair gathers)
   std::vector<ScenePar> par;
   std::vector<int> rank_to_cell, cell_scene, bs_scene;
   std::vector<int4> parts_map;  // split form of the block-resident solid kernel: (scene, part, parts, 0)
@@ -293,6 +294,12 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
   }
   P.cfg.block_pair = bp ? bp : 256;
   P.cfg.block_couple = 64;
+  if (o.fluid_tiles != 0 && o.fluid_tiles != -1) {
+    err = "fluid_tiles must be 0 or -1";
+    return false;
+  }
+  // neighbour tiles: one group per block of the pair launches (3D)
+  P.tile_gp = (P.dim == 3 && o.fluid_tiles == 0) ? P.cfg.block_pair / P.cfg.lpp_force : 0;
   if (o.serial_passes != 0 && o.serial_passes != 1) {
     err = "serial_passes must be 0 or 1";
     return false;
@@ -385,6 +392,11 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.f_nbl, nf * (size_t)P.capf);
   take(D.f_bnl, nf * (size_t)P.capb);
   take(D.f_rowlen, nf);
+  {
+    const size_t groups = P.tile_gp ? (nf + P.tile_gp - 1) / P.tile_gp : 0;
+    take(D.t_union, groups * kTileCap);
+    take(D.t_count, groups);
+  }
   take(D.f_speed, nf);
   take(D.fs_lin, nf);
   take(D.fs_slot, nf);
@@ -699,6 +711,7 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   for (int s = 0; s < n_scenes; ++s) D.any_single |= P.par[s].single_step;
   D.capb = P.capb;
   D.lw = P.lw;
+  D.tile_gp = P.tile_gp;
   ctx->stage_doubles = 9 * (size_t)std::max(P.max_count, 64) + 64;
   hipStream_t st = ctx->stream;
   int rc = SPH_OK;
@@ -722,6 +735,9 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   // every scene starts with its flag set
   HIPCHK_INIT(hipMemcpy(D.rebuild_count, &n_scenes, sizeof(int), hipMemcpyHostToDevice));
   if (P.ns) HIPCHK_INIT(hipMemsetAsync(D.s_cpl_cnt, 0, sizeof(int) * P.ns, st));
+  // no tile yet: rows hold neighbour indices until a group's first rebuild
+  if (P.tile_gp)
+    HIPCHK_INIT(hipMemsetAsync(D.t_count, 0xff, sizeof(int) * ((P.nf + P.tile_gp - 1) / P.tile_gp), st));
   if (P.ncell) {
     HIPCHK_INIT(hipMemcpyAsync(D.rank_to_cell, P.rank_to_cell.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
     HIPCHK_INIT(hipMemcpyAsync(D.cell_scene, P.cell_scene.data(), sizeof(int) * P.ncell, hipMemcpyHostToDevice, st));
@@ -1123,6 +1139,27 @@ int sph_launch_config(sph_ctx *ctx, int *out) {
   return SPH_OK;
 }
 
+int sph_fluid_tiles(sph_ctx *ctx, long long *out) {
+  if (!ctx) return SPH_E_ORDER;
+  if (!out) return SPH_E_ARG;
+  const Dev &D = ctx->D;
+  const int groups = D.tile_gp ? (D.nf + D.tile_gp - 1) / D.tile_gp : 0;
+  long long v[5] = {D.tile_gp, groups, 0, 0, 0};
+  if (groups) {
+    std::vector<int> cnt(groups);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpy(cnt.data(), D.t_count, sizeof(int) * groups, hipMemcpyDeviceToHost));
+    for (int c : cnt)
+      if (c >= 0) {
+        v[2] += 1;
+        v[3] += c;
+        v[4] = std::max<long long>(v[4], c);
+      }
+  }
+  std::memcpy(out, v, sizeof v);
+  return SPH_OK;
+}
+
 int sph_solid_table(sph_ctx *ctx, int *out) {
   if (!ctx) return SPH_E_ORDER;
   if (!out) return SPH_E_ARG;
@@ -1196,11 +1233,24 @@ int sph_pairs(sph_ctx *ctx, int which, int scene, int *start, int *idx) {
     }
     if (!bsrc.empty())
       HIPCHK(hipMemcpy(bsrc.data(), D.b_src + p.b_begin, sizeof(int) * p.b_count, hipMemcpyDeviceToHost));
+    // fluid rows of neighbour tiles index their group's list of neighbours
+    const int G = which == 0 ? D.tile_gp : 0;
+    const int g0 = G && n ? p.f_begin / G : 0, g1 = G && n ? (p.f_begin + n - 1) / G + 1 : 0;
+    std::vector<int> tcnt(g1 - g0);
+    std::vector<unsigned> tun((size_t)(g1 - g0) * kTileCap);
+    if (g1 > g0) {
+      HIPCHK(hipMemcpy(tcnt.data(), D.t_count + g0, sizeof(int) * (g1 - g0), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(tun.data(), D.t_union + (size_t)g0 * kTileCap, sizeof(unsigned) * tun.size(),
+                       hipMemcpyDeviceToHost));
+    }
     for (int k = 0; k < n; ++k) {
       int L = std::min(which == 0 ? len[k].x : len[k].y, cap);
       std::vector<int> &r = rows[fid[k]];
+      const int gk = G ? (p.f_begin + k) / G - g0 : 0;
+      const bool tiled = G && tcnt[gk] >= 0;
       for (int e = 0; e < L; ++e) {
         int j = (int)(ent[((size_t)(e / lw) * n + k) * lw + e % lw] & ((1u << 27) - 1u));
+        if (tiled) j = (int)tun[(size_t)gk * kTileCap + j];
         r.push_back(which == 0 ? fid[j - p.f_begin] : bsrc[j - p.b_begin]);
       }
     }

@@ -28,6 +28,10 @@ constexpr int solid_pb_record(int dim) { return dim == 2 ? 6 : dim * dim; }
 constexpr int kSurFeat = 24;
 constexpr int kSurOut = 4;
 
+// neighbour tiles of the fluid pair loops: distinct fluid neighbours held
+// per group of one block's particles (records staged in LDS, 32 B each)
+constexpr int kTileCap = 768;
+
 struct LaunchCfg {
   int block_pair;    // threads per block of the fluid pair kernels
   int block_couple;  // threads per block of the coupling kernel

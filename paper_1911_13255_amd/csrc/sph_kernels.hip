@@ -1333,6 +1333,110 @@ __device__ void sort_coupling_lists(const Dev &D, int nsort) {
   }
 }
 
+// Neighbour tiles of the fluid pair loops.  A block of the force and
+// continuity launches takes tile_gp consecutive fluid particles (Morton
+// sorted, so a compact group); their fluid neighbours together are a few
+// hundred particles (about 530 for 64 particles of the 3D dam break, against
+// about 5,000 pairs).  The pair loops stage those neighbours' records in LDS
+// once and read them there: a gather of one 16-byte record per lane costs
+// the texture data path a cache-line lookup per lane, and that path, not the
+// arithmetic, bounds the per-pair form.  After a rebuild this kernel collects
+// each group's distinct neighbours in an LDS hash table, sorts them (so the
+// staging reads runs of consecutive particles), and rewrites the low bits of
+// the group's row entries to positions in that list (the relative cell id
+// stays).  A group with more than kTileCap distinct neighbours, or one that
+// straddles two scenes, keeps neighbour indices (t_count -1).  Groups of
+// scenes that do not rebuild keep their rows and lists.  Every thread of a
+// block runs the same barriers.
+template <int LPP>
+__global__ void __launch_bounds__(256) k_tile_union(Dev D) {
+  if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
+  constexpr int kHash = 2048;         // > 2 (kTileCap + 256): probing always ends
+  __shared__ unsigned key[kHash];     // neighbour index + 1, 0: empty
+  __shared__ unsigned short rank[kHash];
+  __shared__ unsigned srt[1024];
+  __shared__ int n_key, n_put;
+  __shared__ volatile int full;
+  const int G = D.tile_gp, grp = blockIdx.x;
+  const int i0 = grp * G, i1 = min(i0 + G, D.nf);
+  const int s0 = D.f_scene[i0], s1 = D.f_scene[i1 - 1];
+  if (!D.st[s0].need_rebuild && !D.st[s1].need_rebuild) return;  // rows and list as they were
+  if (s0 != s1) {
+    if (threadIdx.x == 0) D.t_count[grp] = -1;
+    return;
+  }
+  const int p = threadIdx.x / LPP, q = threadIdx.x % LPP, i = i0 + p;
+  const int len = i < i1 ? D.f_rowlen[i].x : 0;
+  const size_t lstride = (size_t)D.nf * LPP;
+  unsigned *row = D.f_nbl + (size_t)i * LPP + q;
+  auto slot_of = [](unsigned k) { return (k * 2654435761u) >> 21; };  // 11 bits
+  for (int k = threadIdx.x; k < kHash; k += blockDim.x) key[k] = 0u;
+  if (threadIdx.x == 0) {
+    n_key = 0;
+    n_put = 0;
+    full = 0;
+  }
+  __syncthreads();
+  {
+    unsigned *lp = row;
+    for (int e = q; e < len; e += LPP, lp += lstride) {
+      if (full) break;
+      const unsigned k1 = (*lp & kNbrMask) + 1u;
+      for (unsigned h = slot_of(k1);; h = (h + 1u) & (kHash - 1)) {
+        const unsigned old = atomicCAS(&key[h], 0u, k1);
+        if (old == 0u) {
+          if (atomicAdd(&n_key, 1) >= kTileCap) full = 1;
+          break;
+        }
+        if (old == k1) break;
+      }
+    }
+  }
+  __syncthreads();
+  if (full) {
+    if (threadIdx.x == 0) D.t_count[grp] = -1;
+    return;
+  }
+  const int n = n_key;
+  const int np2 = pow2_ceil(max(n, 2));
+  for (int k = threadIdx.x; k < kHash; k += blockDim.x)
+    if (key[k]) srt[atomicAdd(&n_put, 1)] = key[k] - 1u;
+  for (int k = n + threadIdx.x; k < np2; k += blockDim.x) srt[k] = 0xffffffffu;
+  __syncthreads();
+  // bitonic sort of srt[0, np2) ascending
+  for (int size = 2; size <= np2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < np2 / 2; t += blockDim.x) {
+        const int lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const unsigned a = srt[lo], b = srt[hi];
+        if ((a > b) == up) {
+          srt[lo] = b;
+          srt[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const unsigned k1 = srt[k] + 1u;
+    unsigned h = slot_of(k1);
+    while (key[h] != k1) h = (h + 1u) & (kHash - 1);
+    rank[h] = (unsigned short)k;
+    D.t_union[(size_t)grp * kTileCap + k] = srt[k];
+  }
+  __syncthreads();
+  {
+    unsigned *lp = row;
+    for (int e = q; e < len; e += LPP, lp += lstride) {
+      const unsigned ent = *lp, k1 = (ent & kNbrMask) + 1u;
+      unsigned h = slot_of(k1);
+      while (key[h] != k1) h = (h + 1u) & (kHash - 1);
+      *lp = (ent & ~kNbrMask) | (unsigned)rank[h];
+    }
+  }
+  if (threadIdx.x == 0) D.t_count[grp] = n;
+}
+
 // ------------------------------------------------------------------ fluid step
 
 // Mid-point snapshot (v^n, eps^{n+1/2}) of every fluid particle for the
@@ -1397,27 +1501,39 @@ __device__ __forceinline__ float4 pair_shift(const ScenePar &P, bool tab_ok, con
 // entry after it are issued before the current pair's arithmetic, so a
 // lane's loads overlap its own arithmetic instead of waiting at every pair
 // (measured on the 3D dam break: force pass 634 -> 583 us; two pairs ahead
-// took 615 us).
+// took 615 us).  Two register sets take the pairs in turn, so that a pair's
+// records are summed where they were loaded instead of being copied into
+// the set the next iteration reads.
 template <int LPP, typename Load, typename Body>
 __device__ __forceinline__ void walk_pairs(const unsigned *lp, size_t lstride, int q, int n, Load &&load,
                                            Body &&body) {
   if (q >= n) return;
-  unsigned ent = *lp;
-  float4 a, b;
-  load(ent, a, b);
-  unsigned nxt = q + LPP < n ? lp[lstride] : 0u;
-  for (int e = q;; e += LPP) {
-    const unsigned ent_c = ent;
-    const float4 a_c = a, b_c = b;
-    const bool more = e + LPP < n;
-    if (more) {
-      ent = nxt;
-      load(ent, a, b);
-      lp += lstride;
-      nxt = e + 2 * LPP < n ? lp[lstride] : 0u;
-    }
-    body(ent_c, a_c, b_c);
-    if (!more) break;
+  // Every load is unconditional: a slot past the lane's last one reads that
+  // last slot again (its value then goes unused), so no loaded register has
+  // to be merged with another value, which would make the lane wait for its
+  // loads where they are issued.
+  const unsigned *pa = lp;
+  const unsigned *pb = q + LPP < n ? lp + lstride : lp;
+  unsigned ea = *pa, eb = *pb;
+  float4 a0, a1, b0, b1;
+  load(ea, a0, a1);
+  for (int e = q;; e += 2 * LPP) {
+    // set A holds entry e, eb is entry e + LPP.  The entry two ahead is read
+    // before the gathers: loads complete in order, so the gathers that use
+    // it later need not wait for the gathers issued here.
+    pa = e + 2 * LPP < n ? pb + lstride : pb;
+    const unsigned ea2 = *pa;
+    load(eb, b0, b1);
+    body(ea, a0, a1);
+    if (e + LPP >= n) break;
+    // set B holds entry e + LPP, ea2 is entry e + 2 LPP
+    pb = e + 3 * LPP < n ? pa + lstride : pa;
+    const unsigned eb2 = *pb;
+    load(ea2, a0, a1);
+    body(eb, b0, b1);
+    if (e + 2 * LPP >= n) break;
+    ea = ea2;
+    eb = eb2;
   }
 }
 
@@ -1531,6 +1647,46 @@ struct FetchGlobal {
   }
 };
 
+// Stage a block's tile: rec(j, a, b) gives neighbour j's two records, which
+// go to tp[k] and ts[k] for the tile's k-th neighbour tu[k].  Each thread
+// issues the loads of three of its neighbours before storing any (a slot past
+// the end reads the last neighbour again and is not stored).  Every thread
+// of the block calls it.
+template <typename Rec>
+__device__ __forceinline__ void stage_tile(int cnt, const unsigned *tu, float4 *tp, float4 *ts, Rec &&rec) {
+  constexpr int kUnroll = 3;
+  for (int k0 = threadIdx.x; k0 < cnt; k0 += kUnroll * (int)blockDim.x) {
+    int j[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) j[u] = (int)tu[min(k0 + u * (int)blockDim.x, cnt - 1)];
+    float4 a[kUnroll], b[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) rec(j[u], a[u], b[u]);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int k = k0 + u * (int)blockDim.x;
+      if (k < cnt) {
+        tp[k] = a[u];
+        ts[k] = b[u];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// neighbour records from the block's tile in LDS (entries index the tile)
+struct FetchTile {
+  const float4 *pos, *snap;
+  __device__ __forceinline__ void operator()(unsigned ent, float4 &pj, float4 &vj4) const {
+    const unsigned k = ent & kNbrMask;
+    pj = pos[k];
+    vj4 = snap[k];
+  }
+  __device__ __forceinline__ void operator()(unsigned ent, bool, float, float4 &pj, float4 &vj4) const {
+    (*this)(ent, pj, vj4);
+  }
+};
+
 template <int DIM, int LPP>
 __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
   __shared__ float4 shift_tab[27];
@@ -1540,11 +1696,38 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
   }
   // the leading blocks are a multiple of 8: the XCD of a force block is
   // still its index modulo 8
-  int g = xcd_block(blockIdx.x - D.sort_blocks, gridDim.x - D.sort_blocks) * blockDim.x + threadIdx.x;
+  const int b = xcd_block(blockIdx.x - D.sort_blocks, gridDim.x - D.sort_blocks);
+  int g = b * blockDim.x + threadIdx.x;
   int i = g / LPP, q = g % LPP;
   bool active = i < D.nf;
   int s = D.nf > 0 ? D.f_scene[active ? i : 0] : 0;
   const bool tab_ok = stage_shifts<DIM>(D, s, shift_tab);
+  if constexpr (DIM == 3) {
+    if (D.tile_gp > 0) {  // the same for the whole launch
+      const int cnt = D.t_count[b];  // the same for the whole block
+      if (cnt >= 0) {
+        // the group lies in one scene: its first particle's step
+        const int sg = D.f_scene[b * D.tile_gp];
+        const float dt = (float)D.st[sg].dt_ac;
+        __shared__ float4 tile_pos[kTileCap], tile_snap[kTileCap];
+        const unsigned *tu = D.t_union + (size_t)b * kTileCap;
+        // the snapshot as the per-pair gathers form it
+        if (D.fluid_prep)
+          stage_tile(cnt, tu, tile_pos, tile_snap, [&](int j, float4 &pj, float4 &vj4) {
+            pj = D.f_pos[j];
+            vj4 = D.f_vs[j];
+          });
+        else
+          stage_tile(cnt, tu, tile_pos, tile_snap, [&](int j, float4 &pj, float4 &vj4) {
+            pj = D.f_pos[j];
+            vj4 = D.f_va[j];
+            vj4.w += 0.5f * dt * D.f_drho[j];
+          });
+        force_particle<DIM, LPP>(D, i, q, active, s, tab_ok, shift_tab, FetchTile{tile_pos, tile_snap});
+        return;
+      }
+    }
+  }
   force_particle<DIM, LPP>(D, i, q, active, s, tab_ok, shift_tab, FetchGlobal{D});
 }
 
@@ -1607,22 +1790,13 @@ __global__ void __launch_bounds__(256) k_couple(Dev D) {
 // v^{n+1} at the mid-point density, plus rho_i sum_a V_a (v_i - vbar_a).grad W
 // for walls and solid; second half step of position and density; inflow
 // buffer; max speed for the next acoustic step.
-template <int DIM, int LPP>
-__global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
-  __shared__ float4 shift_tab[27];
-  // in a graph step the coupling on the solid, which reads only the force
-  // pass's snapshot, runs in the leading blocks (a multiple of 8, so the XCD
-  // of a continuity block is still its index modulo 8)
-  if ((int)blockIdx.x < D.couple_blocks) {
-    couple_entry<DIM, LPP>(D, blockIdx.x * blockDim.x + threadIdx.x);
-    return;
-  }
-  int g = xcd_block(blockIdx.x - D.couple_blocks, gridDim.x - D.couple_blocks) * blockDim.x + threadIdx.x;
-  int i = g / LPP, q = g % LPP;
-  bool active = i < D.nf;
-  int ii = active ? i : 0;
-  int s = D.nf > 0 ? D.f_scene[ii] : 0;
-  const bool tab_ok = stage_shifts<DIM>(D, s, shift_tab);
+// One fluid particle's continuity pass (LPP lanes: lane q takes list
+// entries q, q + LPP, ...).  fetch(entry, pj, vj4) gives the neighbour's
+// frozen position and its (v^{n+1}, eps^{n+1/2}); every lane of the group
+// must call it.
+template <int DIM, int LPP, typename Fetch>
+__device__ __forceinline__ void continuity_particle(const Dev &D, int i, int q, bool active, int ii, int s,
+                                                   bool tab_ok, const float4 *shift_tab, Fetch &&fetch) {
   const ScenePar P = D.par[s];  // by value: the pair loop keeps its fields in registers
   SceneState &S = D.st[s];
   float4 pi = D.f_pos[ii];
@@ -1644,16 +1818,14 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
     const size_t lstride = (size_t)D.nf * LPP;
     const unsigned *lp = D.f_nbl + (size_t)i * LPP + q;
     {
-      auto load = [&](unsigned ent, float4 &pj, float4 &vj4) {
-        const int j = (int)(ent & kNbrMask);
-        pj = D.f_pos[j];
-        vj4 = D.f_vb[j];
-      };
+      auto load = [&](unsigned ent, float4 &pj, float4 &vj4) { fetch(ent, pj, vj4); };
       walk_pairs<LPP>(lp, lstride, q, rl.x, load, [&](unsigned ent, const float4 &pj, const float4 &vj4) {
         const float4 sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
-        // the force pass's pressure: recomputed from eps for gamma = 7 (the
-        // same expression, so the same bits) instead of a second gather
-        const float p_j = tait7 ? eos_p_pair(vj4.w, P, true) : D.f_p[ent & kNbrMask];
+        // the force pass's pressure, recomputed from eps (the same
+        // expression, so the same bits) instead of a second gather: a gather
+        // taken only for gamma != 7 would make every pair wait for all of
+        // its lane's loads in flight
+        const float p_j = eos_p_pair(vj4.w, P, tait7);
         const float Vj = pj.w * fast_rcp(P.rho0 * (1.0f + vj4.w));
         float r[3] = {(pi.x - pj.x) - sh.x, (pi.y - pj.y) - sh.y, DIM == 3 ? (pi.z - pj.z) - sh.z : 0.0f};
         float r2 = r[0] * r[0] + r[1] * r[1];
@@ -1724,6 +1896,44 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
     D.f_speed[i] = speed;
     if (!(isfinite(speed) && isfinite(enew))) atomicOr(&S.err, (int)ERR_NAN_FLUID);
   }
+}
+template <int DIM, int LPP>
+__global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
+  __shared__ float4 shift_tab[27];
+  // in a graph step the coupling on the solid, which reads only the force
+  // pass's snapshot, runs in the leading blocks (a multiple of 8, so the XCD
+  // of a continuity block is still its index modulo 8)
+  if ((int)blockIdx.x < D.couple_blocks) {
+    couple_entry<DIM, LPP>(D, blockIdx.x * blockDim.x + threadIdx.x);
+    return;
+  }
+  int g = xcd_block(blockIdx.x - D.couple_blocks, gridDim.x - D.couple_blocks) * blockDim.x + threadIdx.x;
+  int i = g / LPP, q = g % LPP;
+  bool active = i < D.nf;
+  int ii = active ? i : 0;
+  int s = D.nf > 0 ? D.f_scene[ii] : 0;
+  const bool tab_ok = stage_shifts<DIM>(D, s, shift_tab);
+  if constexpr (DIM == 3) {
+    if (D.tile_gp > 0) {  // the same for the whole launch
+      const int b = xcd_block(blockIdx.x - D.couple_blocks, gridDim.x - D.couple_blocks);
+      const int cnt = D.t_count[b];  // the same for the whole block
+      if (cnt >= 0) {
+        __shared__ float4 tile_pos[kTileCap], tile_snap[kTileCap];
+        stage_tile(cnt, D.t_union + (size_t)b * kTileCap, tile_pos, tile_snap, [&](int j, float4 &pj, float4 &vj4) {
+          pj = D.f_pos[j];
+          vj4 = D.f_vb[j];
+        });
+        continuity_particle<DIM, LPP>(D, i, q, active, ii, s, tab_ok, shift_tab, FetchTile{tile_pos, tile_snap});
+        return;
+      }
+    }
+  }
+  continuity_particle<DIM, LPP>(D, i, q, active, ii, s, tab_ok, shift_tab,
+                                [&](unsigned ent, float4 &pj, float4 &vj4) {
+                                  const int j = (int)(ent & kNbrMask);
+                                  pj = D.f_pos[j];
+                                  vj4 = D.f_vb[j];
+                                });
 }
 
 // ------------------------------------------------------------------ solid sub-steps
@@ -3491,6 +3701,17 @@ void launch_rebuild(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool wit
   if (D.nf > 0)
     LAUNCH_LPP(k_reinit, cfg.lpp_reinit, D.dim, grid_for((long long)D.nf * cfg.lpp_reinit, cfg.block_pair),
                dim3(cfg.block_pair), 0, st, D);
+  if (D.nf > 0 && D.tile_gp > 0) {
+    // one block per group, the rows' lanes per particle (the list width)
+    const dim3 grid((D.nf + D.tile_gp - 1) / D.tile_gp), block(D.tile_gp * D.lw);
+    switch (D.lw) {
+    case 1: hipLaunchKernelGGL(k_tile_union<1>, grid, block, 0, st, D); break;
+    case 2: hipLaunchKernelGGL(k_tile_union<2>, grid, block, 0, st, D); break;
+    case 4: hipLaunchKernelGGL(k_tile_union<4>, grid, block, 0, st, D); break;
+    case 8: hipLaunchKernelGGL(k_tile_union<8>, grid, block, 0, st, D); break;
+    default: hipLaunchKernelGGL(k_tile_union<16>, grid, block, 0, st, D); break;
+    }
+  }
 }
 
 // coupling lists ordered by each wave of the force launch's leading blocks

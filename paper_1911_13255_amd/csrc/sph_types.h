@@ -127,6 +127,15 @@ struct Dev {
   unsigned *f_nbl;  // fluid neighbours (capf entries per particle)
   unsigned *f_bnl;  // boundary neighbours: walls and free solid (capb per particle)
   int2 *f_rowlen;  // used length of each particle's two rows
+  // Neighbour tiles of the fluid pair loops: group g is the tile_gp fluid
+  // particles g tile_gp ... of one block of the force and continuity
+  // launches; t_union holds the group's distinct fluid neighbours (sorted
+  // indices, kTileCap per group) and its particles' fluid rows index that
+  // list, t_count[g] entries long; t_count[g] = -1: the rows hold neighbour
+  // indices.  tile_gp = 0: no tiles.
+  int tile_gp;
+  unsigned *t_union;
+  int *t_count;
   float *f_speed;  // |v| after the last continuity pass (reduced per scene by the solid kernel)
   // fluid rebuild scratch (indexed by the old sorted index)
   int *fs_lin, *fs_slot, *fs_id, *f_perm, *f_pkey;

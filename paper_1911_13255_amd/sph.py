@@ -59,7 +59,7 @@ class SphOptions(C.Structure):
     _fields_ = [("riemann", C.c_int), ("density_reinit", C.c_int), ("max_solid_nbr", C.c_int),
                 ("solid_block", C.c_int), ("lanes_per_particle", C.c_int), ("block_pair", C.c_int),
                 ("solid_lds", C.c_int), ("max_fluid_nbr", C.c_int), ("max_boundary_nbr", C.c_int),
-                ("serial_passes", C.c_int), ("solid_parts", C.c_int)]
+                ("serial_passes", C.c_int), ("solid_parts", C.c_int), ("fluid_tiles", C.c_int)]
 
     def as_dict(self) -> dict:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -104,6 +104,7 @@ def lib():
         L.sph_counters.argtypes = [vp, C.c_int, C.POINTER(C.c_ulonglong)]
         L.sph_launch_config.argtypes = [vp, C.POINTER(C.c_int)]
         L.sph_solid_table.argtypes = [vp, C.POINTER(C.c_int)]
+        L.sph_fluid_tiles.argtypes = [vp, C.POINTER(C.c_longlong)]
         L.sph_set_surrogate.argtypes = [vp, vp, C.POINTER(C.c_float), C.c_float, C.c_int]
         L.sph_solid_features.argtypes = [vp, vp, vp]
         L.sph_solid_targets.argtypes = [vp, vp]
@@ -167,10 +168,11 @@ def scene_array(scenes):
 
 
 def make_options(riemann=True, density_reinit=1, max_solid_nbr=0, solid_block=0, lanes_per_particle=0,
-                 block_pair=0, solid_lds=0, max_fluid_nbr=0, max_boundary_nbr=0, serial_passes=0, solid_parts=0):
+                 block_pair=0, solid_lds=0, max_fluid_nbr=0, max_boundary_nbr=0, serial_passes=0, solid_parts=0,
+                 fluid_tiles=0):
     return SphOptions(int(riemann), int(density_reinit), int(max_solid_nbr), int(solid_block),
                       int(lanes_per_particle), int(block_pair), int(solid_lds), int(max_fluid_nbr),
-                      int(max_boundary_nbr), int(serial_passes), int(solid_parts))
+                      int(max_boundary_nbr), int(serial_passes), int(solid_parts), int(fluid_tiles))
 
 
 def workload_signature(scenes, opt: dict) -> str:
@@ -243,8 +245,8 @@ class Simulation:
     def __init__(self, scenes, riemann: bool = True, density_reinit: int = 1,
                  max_solid_nbr: int = 0, solid_block: int = 0, lanes_per_particle: int = 0,
                  block_pair: int = 0, solid_lds: int = 0, max_fluid_nbr: int = 0,
-                 max_boundary_nbr: int = 0, serial_passes: int = 0, solid_parts: int = 0, device: int = 0,
-                 arena_fill: int = None):
+                 max_boundary_nbr: int = 0, serial_passes: int = 0, solid_parts: int = 0, fluid_tiles: int = 0,
+                 device: int = 0, arena_fill: int = None):
         """arena_fill: byte written over the whole arena before sph_init (tests
         use it to show that no result depends on the arena's prior contents)."""
         import torch
@@ -260,7 +262,8 @@ class Simulation:
         self._scene_dicts = scenes
         self._scenes = arr
         self.opt = make_options(riemann, density_reinit, max_solid_nbr, solid_block, lanes_per_particle,
-                                block_pair, solid_lds, max_fluid_nbr, max_boundary_nbr, serial_passes, solid_parts)
+                                block_pair, solid_lds, max_fluid_nbr, max_boundary_nbr, serial_passes, solid_parts,
+                                fluid_tiles)
         nbytes = self.L.sph_arena_bytes(arr, self.n_scenes, C.byref(self.opt))
         if nbytes == 0:
             raise SphError(SPH_E_ARG, "invalid scene description")
@@ -429,6 +432,11 @@ class Simulation:
         out = (C.c_int * 3)()
         self._check(self.L.sph_solid_table(self.ctx, out))
         return {"compact": int(out[0]), "capacity": int(out[1]), "bytes_per_pair": int(out[2])}
+
+    def fluid_tiles(self) -> dict:
+        out = (C.c_longlong * 5)()
+        self._check(self.L.sph_fluid_tiles(self.ctx, out))
+        return dict(zip(("group", "groups", "tiled", "neighbours", "largest"), [int(x) for x in out]))
 
     def solid_register_resident(self) -> bool:
         return self.launch_config()["solid_ppt"] > 0
