@@ -1495,45 +1495,70 @@ __device__ __forceinline__ float4 pair_shift(const ScenePar &P, bool tab_ok, con
 // Per fluid pair (e = r/|r|, du = U_L - U_R = -(v_i - v_j).e):
 //   P* = (p_i + p_j)/2 + (rho_i + rho_j)/4 clamp(3 du, 0, c) du,
 //   f_i += -2 V_i V_j P* dW e + 2 eta V_i V_j dW / |r| (v_i - v_j).
+// An opaque copy of x: the compiler cannot fuse the multiply that produced x
+// into a later add or subtract, so a value formed per pair rounds in its sums
+// as the same value read from a neighbour tile does.
+__device__ __forceinline__ float unfused(float x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
+// A fluid neighbour as the pair loops read it.  Gathered per pair: a = its
+// frozen position and mass, b = its velocity and eps.  From a neighbour
+// tile: a = position and volume V_j, b = velocity and pressure p_j, s the
+// pass's density term (1 + eps_j in the force pass, rho_j in continuity),
+// formed once per neighbour by the same expressions the per-pair form
+// evaluates.
+struct NbrRec {
+  float4 a, b;
+  float s;
+  float4 sh;  // the pair's geometric cell shift, read with the record
+};
+
 // Lane q's walk over a pair-list row (entries q, q + LPP, ... below n, at
-// lp, lp + lstride, ...): body(entry, a, b) for each, where load(entry, a, b)
-// gathers the neighbour's two records.  The next pair's gathers and the
-// entry after it are issued before the current pair's arithmetic, so a
-// lane's loads overlap its own arithmetic instead of waiting at every pair
-// (measured on the 3D dam break: force pass 634 -> 583 us; two pairs ahead
-// took 615 us).  Two register sets take the pairs in turn, so that a pair's
-// records are summed where they were loaded instead of being copied into
-// the set the next iteration reads.
+// lp, lp + lstride, ...): body(entry, rec) for each, where load(entry, rec)
+// reads the neighbour's record.  A pair's record is read one pair ahead of
+// its arithmetic and its list entry three pairs ahead, so a lane's loads
+// overlap its own arithmetic (measured on the 3D dam break: force pass 634
+// -> 583 us against no look-ahead).  Four entry registers and two record
+// sets rotate over an unrolled round of four pairs: every load goes straight
+// into the register that a later pair reads, with no copy at the end of the
+// round (a copy of an entry loaded late in the round would make the lane
+// wait there for all of its loads in flight).  Every load is unconditional:
+// past the lane's last slot the walk rereads that slot (the value then goes
+// unused), so no loaded register is merged with another value either.
 template <int LPP, typename Load, typename Body>
 __device__ __forceinline__ void walk_pairs(const unsigned *lp, size_t lstride, int q, int n, Load &&load,
                                            Body &&body) {
   if (q >= n) return;
-  // Every load is unconditional: a slot past the lane's last one reads that
-  // last slot again (its value then goes unused), so no loaded register has
-  // to be merged with another value, which would make the lane wait for its
-  // loads where they are issued.
-  const unsigned *pa = lp;
-  const unsigned *pb = q + LPP < n ? lp + lstride : lp;
-  unsigned ea = *pa, eb = *pb;
-  float4 a0, a1, b0, b1;
-  load(ea, a0, a1);
-  for (int e = q;; e += 2 * LPP) {
-    // set A holds entry e, eb is entry e + LPP.  The entry two ahead is read
-    // before the gathers: loads complete in order, so the gathers that use
-    // it later need not wait for the gathers issued here.
-    pa = e + 2 * LPP < n ? pb + lstride : pb;
-    const unsigned ea2 = *pa;
-    load(eb, b0, b1);
-    body(ea, a0, a1);
+  const unsigned *p = lp;  // slot of the last entry read (kept at the last valid slot)
+  auto next = [&](int e) {  // entry e, the one after the last read
+    if (e < n) p += lstride;
+    return *p;
+  };
+  unsigned E0 = *p;
+  unsigned E1 = next(q + LPP);
+  unsigned E2 = next(q + 2 * LPP);
+  unsigned E3 = next(q + 3 * LPP);
+  NbrRec ra, rb;
+  load(E0, ra);
+  for (int e = q;; e += 4 * LPP) {
+    load(E1, rb);
+    body(E0, ra);
     if (e + LPP >= n) break;
-    // set B holds entry e + LPP, ea2 is entry e + 2 LPP
-    pb = e + 3 * LPP < n ? pa + lstride : pa;
-    const unsigned eb2 = *pb;
-    load(ea2, a0, a1);
-    body(eb, b0, b1);
+    E0 = next(e + 4 * LPP);
+    load(E2, ra);
+    body(E1, rb);
     if (e + 2 * LPP >= n) break;
-    ea = ea2;
-    eb = eb2;
+    E1 = next(e + 5 * LPP);
+    load(E3, rb);
+    body(E2, ra);
+    if (e + 3 * LPP >= n) break;
+    E2 = next(e + 6 * LPP);
+    load(E0, ra);
+    body(E3, rb);
+    if (e + 4 * LPP >= n) break;
+    E3 = next(e + 7 * LPP);
   }
 }
 
@@ -1574,11 +1599,22 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
     // the loop is written once and instantiated for both snapshot sources
     auto fluid_pairs = [&](auto prep_tag) {
       constexpr bool PREP = decltype(prep_tag)::value;
-      auto load = [&](unsigned ent, float4 &pj, float4 &vj4) { fetch(ent, PREP, dt, pj, vj4); };
-      walk_pairs<LPP>(lp, lstride, q, rl.x, load, [&](unsigned ent, const float4 &pj, const float4 &vj4) {
-        const float4 sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
-        const float p_j = eos_p_pair(vj4.w, P, tait7);
-        const float Vj = pj.w * fast_rcp(P.rho0 * (1.0f + vj4.w));
+      auto load = [&](unsigned ent, NbrRec &rec) {
+        fetch(ent, PREP, dt, rec);
+        rec.sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
+      };
+      walk_pairs<LPP>(lp, lstride, q, rl.x, load, [&](unsigned, const NbrRec &rec) {
+        const float4 &pj = rec.a, &vj4 = rec.b, &sh = rec.sh;
+        float p_j, Vj, s1;  // p_j, V_j, 1 + eps_j
+        if constexpr (std::decay_t<Fetch>::kDerived) {
+          p_j = vj4.w;
+          Vj = pj.w;
+          s1 = rec.s;
+        } else {
+          p_j = unfused(eos_p_pair(vj4.w, P, tait7));
+          s1 = 1.0f + vj4.w;
+          Vj = unfused(pj.w * fast_rcp(P.rho0 * s1));
+        }
         float r[3] = {(pi.x - pj.x) - sh.x, (pi.y - pj.y) - sh.y, DIM == 3 ? (pi.z - pj.z) - sh.z : 0.0f};
         float r2 = r[0] * r[0] + r[1] * r[1];
         if (DIM == 3) r2 += r[2] * r[2];
@@ -1591,7 +1627,7 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
         if (DIM == 3) w += dv[2] * r[2];
         w *= inv_r;  // (v_i - v_j).e = -du
         const float beta = __builtin_amdgcn_fmed3f(-3.0f * w, 0.0f, cm);
-        const float qrho = qrho_i + qrho0 * (1.0f + vj4.w);
+        const float qrho = qrho_i + qrho0 * s1;
         const float Ps = (half_pi + 0.5f * p_j) - (qrho * beta) * w;
         const float VdW = Vj * dW;
         const float cpress = (m2Vi * VdW) * Ps * inv_r;  // times r: the unit vector's 1/|r| folded in
@@ -1634,40 +1670,48 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
 
 // neighbour state from global memory (the per-particle form)
 struct FetchGlobal {
+  static constexpr bool kDerived = false;
   const Dev &D;
-  __device__ __forceinline__ void operator()(unsigned ent, bool prep, float dt, float4 &pj, float4 &vj4) const {
+  __device__ __forceinline__ void operator()(unsigned ent, bool prep, float dt, NbrRec &rec) const {
     const int j = (int)(ent & kNbrMask);
-    pj = D.f_pos[j];
+    rec.a = D.f_pos[j];
     if (prep) {
-      vj4 = D.f_vs[j];
+      rec.b = D.f_vs[j];
     } else {
-      vj4 = D.f_va[j];
-      vj4.w += 0.5f * dt * D.f_drho[j];
+      rec.b = D.f_va[j];
+      rec.b.w += 0.5f * dt * D.f_drho[j];
     }
   }
 };
 
-// Stage a block's tile: rec(j, a, b) gives neighbour j's two records, which
-// go to tp[k] and ts[k] for the tile's k-th neighbour tu[k].  Each thread
-// issues the loads of three of its neighbours before storing any (a slot past
-// the end reads the last neighbour again and is not stored).  Every thread
-// of the block calls it.
+// A block's neighbour tile in LDS: the records of the group's distinct
+// fluid neighbours (entries of its rows index them).
+struct NbrTile {
+  float4 a[kTileCap], b[kTileCap];
+  float s[kTileCap];
+};
+
+// Stage a block's tile: rec(j, r) gives neighbour j's record, stored for the
+// tile's k-th neighbour tu[k].  Each thread issues the loads of three of its
+// neighbours before storing any (a slot past the end reads the last
+// neighbour again and is not stored).  Every thread of the block calls it.
 template <typename Rec>
-__device__ __forceinline__ void stage_tile(int cnt, const unsigned *tu, float4 *tp, float4 *ts, Rec &&rec) {
+__device__ __forceinline__ void stage_tile(int cnt, const unsigned *tu, NbrTile &t, Rec &&rec) {
   constexpr int kUnroll = 3;
   for (int k0 = threadIdx.x; k0 < cnt; k0 += kUnroll * (int)blockDim.x) {
     int j[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) j[u] = (int)tu[min(k0 + u * (int)blockDim.x, cnt - 1)];
-    float4 a[kUnroll], b[kUnroll];
+    NbrRec r[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) rec(j[u], a[u], b[u]);
+    for (int u = 0; u < kUnroll; ++u) rec(j[u], r[u]);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int k = k0 + u * (int)blockDim.x;
       if (k < cnt) {
-        tp[k] = a[u];
-        ts[k] = b[u];
+        t.a[k] = r[u].a;
+        t.b[k] = r[u].b;
+        t.s[k] = r[u].s;
       }
     }
   }
@@ -1676,14 +1720,28 @@ __device__ __forceinline__ void stage_tile(int cnt, const unsigned *tu, float4 *
 
 // neighbour records from the block's tile in LDS (entries index the tile)
 struct FetchTile {
-  const float4 *pos, *snap;
-  __device__ __forceinline__ void operator()(unsigned ent, float4 &pj, float4 &vj4) const {
+  static constexpr bool kDerived = true;
+  const NbrTile &t;
+  __device__ __forceinline__ void operator()(unsigned ent, NbrRec &rec) const {
     const unsigned k = ent & kNbrMask;
-    pj = pos[k];
-    vj4 = snap[k];
+    rec.a = t.a[k];
+    rec.b = t.b[k];
+    rec.s = t.s[k];
   }
-  __device__ __forceinline__ void operator()(unsigned ent, bool, float, float4 &pj, float4 &vj4) const {
-    (*this)(ent, pj, vj4);
+  __device__ __forceinline__ void operator()(unsigned ent, bool, float, NbrRec &rec) const { (*this)(ent, rec); }
+  __device__ __forceinline__ void operator()(unsigned ent, bool, NbrRec &rec) const { (*this)(ent, rec); }
+};
+
+// the continuity pass's per-pair gathers: position and mass, (v^{n+1},
+// eps^{n+1/2}), and the force pass's pressure where it is not recomputed
+struct FetchContinuity {
+  static constexpr bool kDerived = false;
+  const Dev &D;
+  __device__ __forceinline__ void operator()(unsigned ent, bool tait7, NbrRec &rec) const {
+    const int j = (int)(ent & kNbrMask);
+    rec.a = D.f_pos[j];
+    rec.b = D.f_vb[j];
+    if (!tait7) rec.s = D.f_p[j];
   }
 };
 
@@ -1709,21 +1767,31 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
         // the group lies in one scene: its first particle's step
         const int sg = D.f_scene[b * D.tile_gp];
         const float dt = (float)D.st[sg].dt_ac;
-        __shared__ float4 tile_pos[kTileCap], tile_snap[kTileCap];
+        __shared__ NbrTile tile;
         const unsigned *tu = D.t_union + (size_t)b * kTileCap;
-        // the snapshot as the per-pair gathers form it
+        const ScenePar &P = D.par[sg];
+        // the snapshot as the per-pair gathers form it, then p_j, V_j and
+        // 1 + eps_j by the pair loop's expressions
+        auto derive = [&](NbrRec &r) {
+          const float eps = r.b.w;
+          r.s = 1.0f + eps;
+          r.a.w = r.a.w * fast_rcp(P.rho0 * r.s);
+          r.b.w = eos_p(eps, P);
+        };
         if (D.fluid_prep)
-          stage_tile(cnt, tu, tile_pos, tile_snap, [&](int j, float4 &pj, float4 &vj4) {
-            pj = D.f_pos[j];
-            vj4 = D.f_vs[j];
+          stage_tile(cnt, tu, tile, [&](int j, NbrRec &r) {
+            r.a = D.f_pos[j];
+            r.b = D.f_vs[j];
+            derive(r);
           });
         else
-          stage_tile(cnt, tu, tile_pos, tile_snap, [&](int j, float4 &pj, float4 &vj4) {
-            pj = D.f_pos[j];
-            vj4 = D.f_va[j];
-            vj4.w += 0.5f * dt * D.f_drho[j];
+          stage_tile(cnt, tu, tile, [&](int j, NbrRec &r) {
+            r.a = D.f_pos[j];
+            r.b = D.f_va[j];
+            r.b.w += 0.5f * dt * D.f_drho[j];
+            derive(r);
           });
-        force_particle<DIM, LPP>(D, i, q, active, s, tab_ok, shift_tab, FetchTile{tile_pos, tile_snap});
+        force_particle<DIM, LPP>(D, i, q, active, s, tab_ok, shift_tab, FetchTile{tile});
         return;
       }
     }
@@ -1817,16 +1885,29 @@ __device__ __forceinline__ void continuity_particle(const Dev &D, int i, int q, 
     const int2 rl = D.f_rowlen[i];
     const size_t lstride = (size_t)D.nf * LPP;
     const unsigned *lp = D.f_nbl + (size_t)i * LPP + q;
-    {
-      auto load = [&](unsigned ent, float4 &pj, float4 &vj4) { fetch(ent, pj, vj4); };
-      walk_pairs<LPP>(lp, lstride, q, rl.x, load, [&](unsigned ent, const float4 &pj, const float4 &vj4) {
-        const float4 sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
-        // the force pass's pressure, recomputed from eps (the same
-        // expression, so the same bits) instead of a second gather: a gather
-        // taken only for gamma != 7 would make every pair wait for all of
-        // its lane's loads in flight
-        const float p_j = eos_p_pair(vj4.w, P, tait7);
-        const float Vj = pj.w * fast_rcp(P.rho0 * (1.0f + vj4.w));
+    // The force pass's pressure p_j: for gamma = 7 recomputed from eps (the
+    // same expression, so the same bits), otherwise gathered; the loop is
+    // instantiated for each, so that neither carries a load taken for only
+    // some pairs (it would make every pair wait for all of its lane's loads
+    // in flight).  A tile holds p_j, V_j and rho_j already.
+    auto fluid_pairs = [&](auto t7_tag) {
+      constexpr bool T7 = decltype(t7_tag)::value;
+      auto load = [&](unsigned ent, NbrRec &rec) {
+        fetch(ent, T7, rec);
+        rec.sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
+      };
+      walk_pairs<LPP>(lp, lstride, q, rl.x, load, [&](unsigned, const NbrRec &rec) {
+        const float4 &pj = rec.a, &vj4 = rec.b, &sh = rec.sh;
+        float p_j, Vj, rhoj;
+        if constexpr (std::decay_t<Fetch>::kDerived) {
+          p_j = vj4.w;
+          Vj = pj.w;
+          rhoj = rec.s;
+        } else {
+          p_j = T7 ? unfused(eos_p_pair(vj4.w, P, true)) : rec.s;
+          rhoj = unfused(P.rho0 * (1.0f + vj4.w));
+          Vj = unfused(pj.w * fast_rcp(rhoj));
+        }
         float r[3] = {(pi.x - pj.x) - sh.x, (pi.y - pj.y) - sh.y, DIM == 3 ? (pi.z - pj.z) - sh.z : 0.0f};
         float r2 = r[0] * r[0] + r[1] * r[1];
         if (DIM == 3) r2 += r[2] * r[2];
@@ -1836,11 +1917,14 @@ __device__ __forceinline__ void continuity_particle(const Dev &D, int i, int q, 
         const float dW = (kdw * rr) * (t * t * t);
         float w = (vi[0] - vj4.x) * r[0] + (vi[1] - vj4.y) * r[1];
         if (DIM == 3) w += (vi[2] - vj4.z) * r[2];
-        const float rhoj = P.rho0 * (1.0f + vj4.w);
         const float dvs = 0.5f * (w * inv_r) + (p_i - p_j) * fast_rcp((rhoi + rhoj) * rc);
         drho += (2.0f * rhoi) * (Vj * dW) * (rc > 0.0f ? dvs : 0.5f * (w * inv_r));
       });
-    }
+    };
+    if (std::decay_t<Fetch>::kDerived || tait7)
+      fluid_pairs(std::true_type{});
+    else
+      fluid_pairs(std::false_type{});
     lp = D.f_bnl + (size_t)i * LPP + q;
     for (int e = q; e < rl.y; e += LPP, lp += lstride) {
       unsigned ent = *lp;
@@ -1918,22 +2002,25 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
       const int b = xcd_block(blockIdx.x - D.couple_blocks, gridDim.x - D.couple_blocks);
       const int cnt = D.t_count[b];  // the same for the whole block
       if (cnt >= 0) {
-        __shared__ float4 tile_pos[kTileCap], tile_snap[kTileCap];
-        stage_tile(cnt, D.t_union + (size_t)b * kTileCap, tile_pos, tile_snap, [&](int j, float4 &pj, float4 &vj4) {
-          pj = D.f_pos[j];
-          vj4 = D.f_vb[j];
+        __shared__ NbrTile tile;
+        // the group lies in one scene
+        const ScenePar &P = D.par[D.f_scene[b * D.tile_gp]];
+        // p_j, V_j and rho_j by the pair loop's expressions (the force pass
+        // stored p_j = eos_p(eps_j))
+        stage_tile(cnt, D.t_union + (size_t)b * kTileCap, tile, [&](int j, NbrRec &r) {
+          r.a = D.f_pos[j];
+          r.b = D.f_vb[j];
+          const float eps = r.b.w;
+          r.s = P.rho0 * (1.0f + eps);
+          r.a.w = r.a.w * fast_rcp(r.s);
+          r.b.w = eos_p(eps, P);
         });
-        continuity_particle<DIM, LPP>(D, i, q, active, ii, s, tab_ok, shift_tab, FetchTile{tile_pos, tile_snap});
+        continuity_particle<DIM, LPP>(D, i, q, active, ii, s, tab_ok, shift_tab, FetchTile{tile});
         return;
       }
     }
   }
-  continuity_particle<DIM, LPP>(D, i, q, active, ii, s, tab_ok, shift_tab,
-                                [&](unsigned ent, float4 &pj, float4 &vj4) {
-                                  const int j = (int)(ent & kNbrMask);
-                                  pj = D.f_pos[j];
-                                  vj4 = D.f_vb[j];
-                                });
+  continuity_particle<DIM, LPP>(D, i, q, active, ii, s, tab_ok, shift_tab, FetchContinuity{D});
 }
 
 // ------------------------------------------------------------------ solid sub-steps

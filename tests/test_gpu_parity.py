@@ -553,7 +553,10 @@ def test_kernel_timing_replays_every_kernel(gpu, solid_lds):
     sim = sph.Simulation(sc, solid_lds=solid_lds)
     sim.advance(5)
     for k in (sph.K_FLUID_FORCE, sph.K_CONTINUITY, sph.K_COUPLE, sph.K_SOLID, sph.K_REBUILD):
-        t10, t40 = sim.time_kernel(k, 10), sim.time_kernel(k, 40)
+        # the smaller of two measurements: a single one of a few microseconds
+        # can catch a stall of the device that has nothing to do with the kernel
+        t10 = min(sim.time_kernel(k, 10), sim.time_kernel(k, 10))
+        t40 = min(sim.time_kernel(k, 40), sim.time_kernel(k, 40))
         note(f"  kernel {k}: {t10 * 1e3:.2f} us (10 reps), {t40 * 1e3:.2f} us (40 reps)")
         assert 0.0 < t10 < 50.0 and 0.0 < t40 < 50.0
         assert t40 < 3.0 * t10 and t10 < 3.0 * t40
