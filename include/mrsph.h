@@ -106,8 +106,9 @@ typedef struct {
                            the caller's value */
   int fluid_tiles;      /* 0: in 3D, each block of the fluid force and continuity passes stages the
                            records of its particles' distinct fluid neighbours (at most 768) in LDS
-                           and reads them there; the rebuild rewrites those particles' fluid rows to
-                           index that set.  Results equal the per-pair gathers bit for bit.
+                           and reads them there; the rebuild writes a second, 16-bit copy of those
+                           particles' fluid rows that indexes that set (2 bytes per pair-list slot
+                           more device memory).  Results equal the per-pair gathers bit for bit.
                            -1: per-pair gathers.  2D always uses per-pair gathers. */
 } sph_options;
 

@@ -396,6 +396,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
     const size_t groups = P.tile_gp ? (nf + P.tile_gp - 1) / P.tile_gp : 0;
     take(D.t_union, groups * kTileCap);
     take(D.t_count, groups);
+    take(D.t_rows, groups ? nf * (size_t)P.capf : 0);
   }
   take(D.f_speed, nf);
   take(D.fs_lin, nf);
@@ -1233,24 +1234,11 @@ int sph_pairs(sph_ctx *ctx, int which, int scene, int *start, int *idx) {
     }
     if (!bsrc.empty())
       HIPCHK(hipMemcpy(bsrc.data(), D.b_src + p.b_begin, sizeof(int) * p.b_count, hipMemcpyDeviceToHost));
-    // fluid rows of neighbour tiles index their group's list of neighbours
-    const int G = which == 0 ? D.tile_gp : 0;
-    const int g0 = G && n ? p.f_begin / G : 0, g1 = G && n ? (p.f_begin + n - 1) / G + 1 : 0;
-    std::vector<int> tcnt(g1 - g0);
-    std::vector<unsigned> tun((size_t)(g1 - g0) * kTileCap);
-    if (g1 > g0) {
-      HIPCHK(hipMemcpy(tcnt.data(), D.t_count + g0, sizeof(int) * (g1 - g0), hipMemcpyDeviceToHost));
-      HIPCHK(hipMemcpy(tun.data(), D.t_union + (size_t)g0 * kTileCap, sizeof(unsigned) * tun.size(),
-                       hipMemcpyDeviceToHost));
-    }
     for (int k = 0; k < n; ++k) {
       int L = std::min(which == 0 ? len[k].x : len[k].y, cap);
       std::vector<int> &r = rows[fid[k]];
-      const int gk = G ? (p.f_begin + k) / G - g0 : 0;
-      const bool tiled = G && tcnt[gk] >= 0;
       for (int e = 0; e < L; ++e) {
         int j = (int)(ent[((size_t)(e / lw) * n + k) * lw + e % lw] & ((1u << 27) - 1u));
-        if (tiled) j = (int)tun[(size_t)gk * kTileCap + j];
         r.push_back(which == 0 ? fid[j - p.f_begin] : bsrc[j - p.b_begin]);
       }
     }

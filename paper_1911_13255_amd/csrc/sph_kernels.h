@@ -31,6 +31,9 @@ constexpr int kSurOut = 4;
 // neighbour tiles of the fluid pair loops: distinct fluid neighbours held
 // per group of one block's particles (records staged in LDS, 32 B each)
 constexpr int kTileCap = 768;
+// a tile row entry: position in the tile (low bits) and relative cell id
+constexpr int kTileIdxBits = 10;
+static_assert(kTileCap <= (1 << kTileIdxBits), "tile positions fit their bits");
 
 struct LaunchCfg {
   int block_pair;    // threads per block of the fluid pair kernels

@@ -1342,12 +1342,12 @@ __device__ void sort_coupling_lists(const Dev &D, int nsort) {
 // the texture data path a cache-line lookup per lane, and that path, not the
 // arithmetic, bounds the per-pair form.  After a rebuild this kernel collects
 // each group's distinct neighbours in an LDS hash table, sorts them (so the
-// staging reads runs of consecutive particles), and rewrites the low bits of
-// the group's row entries to positions in that list (the relative cell id
-// stays).  A group with more than kTileCap distinct neighbours, or one that
-// straddles two scenes, keeps neighbour indices (t_count -1).  Groups of
-// scenes that do not rebuild keep their rows and lists.  Every thread of a
-// block runs the same barriers.
+// staging reads runs of consecutive particles), and writes the group's rows
+// again as 16-bit entries: the position in that list and the relative cell
+// id (half the bytes for the pair loops to stream).  A group with more than
+// kTileCap distinct neighbours, or one that straddles two scenes, has no
+// tile (t_count -1).  Groups of scenes that do not rebuild keep their tiles.
+// Every thread of a block runs the same barriers.
 template <int LPP>
 __global__ void __launch_bounds__(256) k_tile_union(Dev D) {
   if (*D.rebuild_count == 0) return;  // no scene rebuilds this step
@@ -1367,9 +1367,18 @@ __global__ void __launch_bounds__(256) k_tile_union(Dev D) {
   }
   const int p = threadIdx.x / LPP, q = threadIdx.x % LPP, i = i0 + p;
   const int len = i < i1 ? D.f_rowlen[i].x : 0;
+  const int nq = len > q ? (len - 1 - q) / LPP + 1 : 0;  // this lane's entries
   const size_t lstride = (size_t)D.nf * LPP;
-  unsigned *row = D.f_nbl + (size_t)i * LPP + q;
+  const unsigned *row = D.f_nbl + (size_t)i * LPP + q;
+  unsigned short *trow = D.t_rows + (size_t)i * LPP + q;
   auto slot_of = [](unsigned k) { return (k * 2654435761u) >> 21; };  // 11 bits
+  // the lane's entries kBatch at a time, all loads issued before any is used
+  // (a slot past the lane's last one reads that last slot again)
+  constexpr int kBatch = 8;
+  auto batch = [&](int k0, unsigned *ent) {
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) ent[u] = row[(size_t)min(k0 + u, nq - 1) * lstride];
+  };
   for (int k = threadIdx.x; k < kHash; k += blockDim.x) key[k] = 0u;
   if (threadIdx.x == 0) {
     n_key = 0;
@@ -1377,11 +1386,14 @@ __global__ void __launch_bounds__(256) k_tile_union(Dev D) {
     full = 0;
   }
   __syncthreads();
-  {
-    unsigned *lp = row;
-    for (int e = q; e < len; e += LPP, lp += lstride) {
-      if (full) break;
-      const unsigned k1 = (*lp & kNbrMask) + 1u;
+  for (int k0 = 0; k0 < nq; k0 += kBatch) {
+    if (full) break;
+    unsigned ent[kBatch];
+    batch(k0, ent);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (k0 + u >= nq) break;
+      const unsigned k1 = (ent[u] & kNbrMask) + 1u;
       for (unsigned h = slot_of(k1);; h = (h + 1u) & (kHash - 1)) {
         const unsigned old = atomicCAS(&key[h], 0u, k1);
         if (old == 0u) {
@@ -1425,13 +1437,16 @@ __global__ void __launch_bounds__(256) k_tile_union(Dev D) {
     D.t_union[(size_t)grp * kTileCap + k] = srt[k];
   }
   __syncthreads();
-  {
-    unsigned *lp = row;
-    for (int e = q; e < len; e += LPP, lp += lstride) {
-      const unsigned ent = *lp, k1 = (ent & kNbrMask) + 1u;
+  for (int k0 = 0; k0 < nq; k0 += kBatch) {
+    unsigned ent[kBatch];
+    batch(k0, ent);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (k0 + u >= nq) break;
+      const unsigned k1 = (ent[u] & kNbrMask) + 1u;
       unsigned h = slot_of(k1);
       while (key[h] != k1) h = (h + 1u) & (kHash - 1);
-      *lp = (ent & ~kNbrMask) | (unsigned)rank[h];
+      trow[(size_t)(k0 + u) * lstride] = (unsigned short)(rank[h] | ((ent[u] >> kNbrBits) << kTileIdxBits));
     }
   }
   if (threadIdx.x == 0) D.t_count[grp] = n;
@@ -1477,12 +1492,16 @@ __device__ __forceinline__ bool stage_shifts(const Dev &D, int s, float4 *tab) {
 }
 
 template <int DIM>
-__device__ __forceinline__ float4 pair_shift(const ScenePar &P, bool tab_ok, const float4 *tab, unsigned ent) {
-  const int cid = (int)(ent >> kNbrBits);
+__device__ __forceinline__ float4 pair_shift_cid(const ScenePar &P, bool tab_ok, const float4 *tab, int cid) {
   if (tab_ok) return tab[cid];
   float sh[3];
   cell_shift<DIM>(P, cid, sh);
   return make_float4(sh[0], sh[1], sh[2], 0.0f);
+}
+
+template <int DIM>
+__device__ __forceinline__ float4 pair_shift(const ScenePar &P, bool tab_ok, const float4 *tab, unsigned ent) {
+  return pair_shift_cid<DIM>(P, tab_ok, tab, (int)(ent >> kNbrBits));
 }
 
 // Fluid acoustic step, first part (Section 3.3, Eqs. verlet-first-half and
@@ -1527,11 +1546,10 @@ struct NbrRec {
 // wait there for all of its loads in flight).  Every load is unconditional:
 // past the lane's last slot the walk rereads that slot (the value then goes
 // unused), so no loaded register is merged with another value either.
-template <int LPP, typename Load, typename Body>
-__device__ __forceinline__ void walk_pairs(const unsigned *lp, size_t lstride, int q, int n, Load &&load,
-                                           Body &&body) {
+template <int LPP, typename E, typename Load, typename Body>
+__device__ __forceinline__ void walk_pairs(const E *lp, size_t lstride, int q, int n, Load &&load, Body &&body) {
   if (q >= n) return;
-  const unsigned *p = lp;  // slot of the last entry read (kept at the last valid slot)
+  const E *p = lp;  // slot of the last entry read (kept at the last valid slot)
   auto next = [&](int e) {  // entry e, the one after the last read
     if (e < n) p += lstride;
     return *p;
@@ -1595,15 +1613,14 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
   if (active) {
     const int2 rl = D.f_rowlen[i];
     const size_t lstride = (size_t)D.nf * LPP;
-    const unsigned *lp = D.f_nbl + (size_t)i * LPP + q;
     // the loop is written once and instantiated for both snapshot sources
     auto fluid_pairs = [&](auto prep_tag) {
       constexpr bool PREP = decltype(prep_tag)::value;
       auto load = [&](unsigned ent, NbrRec &rec) {
         fetch(ent, PREP, dt, rec);
-        rec.sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
+        rec.sh = pair_shift_cid<DIM>(P, tab_ok, shift_tab, (int)(ent >> std::decay_t<Fetch>::kIdxBits));
       };
-      walk_pairs<LPP>(lp, lstride, q, rl.x, load, [&](unsigned, const NbrRec &rec) {
+      walk_pairs<LPP>(fetch.rows() + (size_t)i * LPP + q, lstride, q, rl.x, load, [&](unsigned, const NbrRec &rec) {
         const float4 &pj = rec.a, &vj4 = rec.b, &sh = rec.sh;
         float p_j, Vj, s1;  // p_j, V_j, 1 + eps_j
         if constexpr (std::decay_t<Fetch>::kDerived) {
@@ -1637,7 +1654,7 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
     };
     if (prep) fluid_pairs(std::true_type{});
     else fluid_pairs(std::false_type{});
-    lp = D.f_bnl + (size_t)i * LPP + q;
+    const unsigned *lp = D.f_bnl + (size_t)i * LPP + q;
     for (int e = q; e < rl.y; e += LPP, lp += lstride) {
       unsigned ent = *lp;
       int k = (int)(ent & kNbrMask);
@@ -1671,7 +1688,9 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
 // neighbour state from global memory (the per-particle form)
 struct FetchGlobal {
   static constexpr bool kDerived = false;
+  static constexpr int kIdxBits = kNbrBits;
   const Dev &D;
+  __device__ __forceinline__ const unsigned *rows() const { return D.f_nbl; }
   __device__ __forceinline__ void operator()(unsigned ent, bool prep, float dt, NbrRec &rec) const {
     const int j = (int)(ent & kNbrMask);
     rec.a = D.f_pos[j];
@@ -1721,9 +1740,12 @@ __device__ __forceinline__ void stage_tile(int cnt, const unsigned *tu, NbrTile 
 // neighbour records from the block's tile in LDS (entries index the tile)
 struct FetchTile {
   static constexpr bool kDerived = true;
+  static constexpr int kIdxBits = kTileIdxBits;
   const NbrTile &t;
+  const unsigned short *trows;
+  __device__ __forceinline__ const unsigned short *rows() const { return trows; }
   __device__ __forceinline__ void operator()(unsigned ent, NbrRec &rec) const {
-    const unsigned k = ent & kNbrMask;
+    const unsigned k = ent & ((1u << kTileIdxBits) - 1u);
     rec.a = t.a[k];
     rec.b = t.b[k];
     rec.s = t.s[k];
@@ -1736,7 +1758,9 @@ struct FetchTile {
 // eps^{n+1/2}), and the force pass's pressure where it is not recomputed
 struct FetchContinuity {
   static constexpr bool kDerived = false;
+  static constexpr int kIdxBits = kNbrBits;
   const Dev &D;
+  __device__ __forceinline__ const unsigned *rows() const { return D.f_nbl; }
   __device__ __forceinline__ void operator()(unsigned ent, bool tait7, NbrRec &rec) const {
     const int j = (int)(ent & kNbrMask);
     rec.a = D.f_pos[j];
@@ -1791,7 +1815,7 @@ __global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
             r.b.w += 0.5f * dt * D.f_drho[j];
             derive(r);
           });
-        force_particle<DIM, LPP>(D, i, q, active, s, tab_ok, shift_tab, FetchTile{tile});
+        force_particle<DIM, LPP>(D, i, q, active, s, tab_ok, shift_tab, FetchTile{tile, D.t_rows});
         return;
       }
     }
@@ -1884,7 +1908,6 @@ __device__ __forceinline__ void continuity_particle(const Dev &D, int i, int q, 
   if (active) {
     const int2 rl = D.f_rowlen[i];
     const size_t lstride = (size_t)D.nf * LPP;
-    const unsigned *lp = D.f_nbl + (size_t)i * LPP + q;
     // The force pass's pressure p_j: for gamma = 7 recomputed from eps (the
     // same expression, so the same bits), otherwise gathered; the loop is
     // instantiated for each, so that neither carries a load taken for only
@@ -1894,9 +1917,9 @@ __device__ __forceinline__ void continuity_particle(const Dev &D, int i, int q, 
       constexpr bool T7 = decltype(t7_tag)::value;
       auto load = [&](unsigned ent, NbrRec &rec) {
         fetch(ent, T7, rec);
-        rec.sh = pair_shift<DIM>(P, tab_ok, shift_tab, ent);
+        rec.sh = pair_shift_cid<DIM>(P, tab_ok, shift_tab, (int)(ent >> std::decay_t<Fetch>::kIdxBits));
       };
-      walk_pairs<LPP>(lp, lstride, q, rl.x, load, [&](unsigned, const NbrRec &rec) {
+      walk_pairs<LPP>(fetch.rows() + (size_t)i * LPP + q, lstride, q, rl.x, load, [&](unsigned, const NbrRec &rec) {
         const float4 &pj = rec.a, &vj4 = rec.b, &sh = rec.sh;
         float p_j, Vj, rhoj;
         if constexpr (std::decay_t<Fetch>::kDerived) {
@@ -1925,7 +1948,7 @@ __device__ __forceinline__ void continuity_particle(const Dev &D, int i, int q, 
       fluid_pairs(std::true_type{});
     else
       fluid_pairs(std::false_type{});
-    lp = D.f_bnl + (size_t)i * LPP + q;
+    const unsigned *lp = D.f_bnl + (size_t)i * LPP + q;
     for (int e = q; e < rl.y; e += LPP, lp += lstride) {
       unsigned ent = *lp;
       int k = (int)(ent & kNbrMask);
@@ -2015,7 +2038,7 @@ __global__ void __launch_bounds__(256) k_fluid_continuity(Dev D) {
           r.a.w = r.a.w * fast_rcp(r.s);
           r.b.w = eos_p(eps, P);
         });
-        continuity_particle<DIM, LPP>(D, i, q, active, ii, s, tab_ok, shift_tab, FetchTile{tile});
+        continuity_particle<DIM, LPP>(D, i, q, active, ii, s, tab_ok, shift_tab, FetchTile{tile, D.t_rows});
         return;
       }
     }

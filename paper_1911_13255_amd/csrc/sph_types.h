@@ -130,12 +130,14 @@ struct Dev {
   // Neighbour tiles of the fluid pair loops: group g is the tile_gp fluid
   // particles g tile_gp ... of one block of the force and continuity
   // launches; t_union holds the group's distinct fluid neighbours (sorted
-  // indices, kTileCap per group) and its particles' fluid rows index that
-  // list, t_count[g] entries long; t_count[g] = -1: the rows hold neighbour
-  // indices.  tile_gp = 0: no tiles.
+  // indices, kTileCap per group), t_count[g] of them, and t_rows the group's
+  // fluid rows as 16-bit entries (position in t_union, relative cell id) in
+  // f_nbl's layout; t_count[g] = -1: no tile, the passes walk f_nbl.
+  // tile_gp = 0: no tiles.
   int tile_gp;
   unsigned *t_union;
   int *t_count;
+  unsigned short *t_rows;
   float *f_speed;  // |v| after the last continuity pass (reduced per scene by the solid kernel)
   // fluid rebuild scratch (indexed by the old sorted index)
   int *fs_lin, *fs_slot, *fs_id, *f_perm, *f_pkey;
