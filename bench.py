@@ -358,7 +358,8 @@ def run_workload(name, steps, warmup, autotune, cache, kernel_reps, log, scenes_
                kappa_mean=kappa, kernel_ms_per_step={k: round(v, 6) for k, v in per_step.items()},
                kernel_roofline={k: {q: v[q] for q in ("bound", "frac", "duration_us", "alu_frac", "hbm_frac")}
                                 for k, v in roofs.items()},
-               launch=sim.launch_config(), autotuned=bool(autotune), autotune_seconds=tune_s, roofline=roof,
+               launch=sim.launch_config(), fluid_tiles=sim.fluid_tiles(), autotuned=bool(autotune),
+               autotune_seconds=tune_s, roofline=roof,
                config=dict(workload=name, scenes=len(scs), n_fluid=nf, n_solid=ns,
                            n_wall=sum(len(s["x_wall"]) for s in scs), dim=dim, dp_f=scs[0]["dp_f"],
                            dp_s=scs[0]["dp_s"]))
