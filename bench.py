@@ -482,7 +482,7 @@ def main():
         "cpu_baseline": cpu,
     }
     for k in ("interactions_per_step", "rebuilds", "kappa_mean", "kernel_ms_per_step", "kernel_roofline", "launch",
-              "autotuned", "autotune_seconds", "solid_phase"):
+              "fluid_tiles", "autotuned", "autotune_seconds", "solid_phase"):
         if k in head:
             out[k] = head[k]
     out.update(extras)
