@@ -1537,46 +1537,47 @@ struct NbrRec {
 // Lane q's walk over a pair-list row (entries q, q + LPP, ... below n, at
 // lp, lp + lstride, ...): body(entry, rec) for each, where load(entry, rec)
 // reads the neighbour's record.  A pair's record is read one pair ahead of
-// its arithmetic and its list entry three pairs ahead, so a lane's loads
-// overlap its own arithmetic (measured on the 3D dam break: force pass 634
-// -> 583 us against no look-ahead).  Four entry registers and two record
-// sets rotate over an unrolled round of four pairs: every load goes straight
-// into the register that a later pair reads, with no copy at the end of the
-// round (a copy of an entry loaded late in the round would make the lane
-// wait there for all of its loads in flight).  Every load is unconditional:
-// past the lane's last slot the walk rereads that slot (the value then goes
-// unused), so no loaded register is merged with another value either.
+// its arithmetic (measured on the 3D dam break: force pass 634 -> 583 us
+// against no look-ahead), and the entries of a round of four pairs are all
+// read at the start of the round before, so a round never waits for an
+// entry load issued late in the round before it.  Two record sets take the
+// pairs in turn, so a record is summed where it was loaded.  Every load is
+// unconditional: past the lane's last slot the walk rereads that slot (the
+// value then goes unused), so no loaded register is merged with another
+// value, which would make the lane wait for its loads in flight.
 template <int LPP, typename E, typename Load, typename Body>
 __device__ __forceinline__ void walk_pairs(const E *lp, size_t lstride, int q, int n, Load &&load, Body &&body) {
   if (q >= n) return;
   const E *p = lp;  // slot of the last entry read (kept at the last valid slot)
   auto next = [&](int e) {  // entry e, the one after the last read
     if (e < n) p += lstride;
-    return *p;
+    return (unsigned)*p;
   };
-  unsigned E0 = *p;
-  unsigned E1 = next(q + LPP);
-  unsigned E2 = next(q + 2 * LPP);
-  unsigned E3 = next(q + 3 * LPP);
+  unsigned c0 = *p, c1 = next(q + LPP), c2 = next(q + 2 * LPP), c3 = next(q + 3 * LPP);
   NbrRec ra, rb;
-  load(E0, ra);
+  load(c0, ra);
   for (int e = q;; e += 4 * LPP) {
-    load(E1, rb);
-    body(E0, ra);
+    const unsigned n0 = next(e + 4 * LPP), n1 = next(e + 5 * LPP), n2 = next(e + 6 * LPP),
+                   n3 = next(e + 7 * LPP);
+    // keep those loads here: the scheduler would otherwise sink them to
+    // where they are used, a pair before
+    __builtin_amdgcn_sched_barrier(0);
+    load(c1, rb);
+    body(c0, ra);
     if (e + LPP >= n) break;
-    E0 = next(e + 4 * LPP);
-    load(E2, ra);
-    body(E1, rb);
+    load(c2, ra);
+    body(c1, rb);
     if (e + 2 * LPP >= n) break;
-    E1 = next(e + 5 * LPP);
-    load(E3, rb);
-    body(E2, ra);
+    load(c3, rb);
+    body(c2, ra);
     if (e + 3 * LPP >= n) break;
-    E2 = next(e + 6 * LPP);
-    load(E0, ra);
-    body(E3, rb);
+    load(n0, ra);
+    body(c3, rb);
     if (e + 4 * LPP >= n) break;
-    E3 = next(e + 7 * LPP);
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
   }
 }
 
@@ -1618,7 +1619,8 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
       constexpr bool PREP = decltype(prep_tag)::value;
       auto load = [&](unsigned ent, NbrRec &rec) {
         fetch(ent, PREP, dt, rec);
-        rec.sh = pair_shift_cid<DIM>(P, tab_ok, shift_tab, (int)(ent >> std::decay_t<Fetch>::kIdxBits));
+        rec.sh = pair_shift_cid<DIM>(P, std::decay_t<Fetch>::kOneScene || tab_ok, shift_tab,
+                                     (int)(ent >> std::decay_t<Fetch>::kIdxBits));
       };
       walk_pairs<LPP>(fetch.rows() + (size_t)i * LPP + q, lstride, q, rl.x, load, [&](unsigned, const NbrRec &rec) {
         const float4 &pj = rec.a, &vj4 = rec.b, &sh = rec.sh;
@@ -1632,24 +1634,29 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
           s1 = 1.0f + vj4.w;
           Vj = unfused(pj.w * fast_rcp(P.rho0 * s1));
         }
+        // every fused multiply-add written out and no other contraction, so
+        // that the tile and per-pair instantiations of this body round alike
+        {
+#pragma clang fp contract(off)
         float r[3] = {(pi.x - pj.x) - sh.x, (pi.y - pj.y) - sh.y, DIM == 3 ? (pi.z - pj.z) - sh.z : 0.0f};
-        float r2 = r[0] * r[0] + r[1] * r[1];
-        if (DIM == 3) r2 += r[2] * r[2];
+        float r2 = fmaf(r[1], r[1], r[0] * r[0]);
+        if (DIM == 3) r2 = fmaf(r[2], r[2], r2);
         const float inv_r = __builtin_amdgcn_rsqf(r2);
         const float rr = r2 * inv_r;
-        const float t = 1.0f + kt * rr;
-        const float dW = (kdw * rr) * (t * t * t);
+        const float t = fmaf(kt, rr, 1.0f);
+        const float dW = (kdw * rr) * (t * (t * t));
         const float dv[3] = {vi[0] - vj4.x, vi[1] - vj4.y, DIM == 3 ? vi[2] - vj4.z : 0.0f};
-        float w = dv[0] * r[0] + dv[1] * r[1];
-        if (DIM == 3) w += dv[2] * r[2];
+        float w = fmaf(dv[1], r[1], dv[0] * r[0]);
+        if (DIM == 3) w = fmaf(dv[2], r[2], w);
         w *= inv_r;  // (v_i - v_j).e = -du
         const float beta = __builtin_amdgcn_fmed3f(-3.0f * w, 0.0f, cm);
-        const float qrho = qrho_i + qrho0 * s1;
-        const float Ps = (half_pi + 0.5f * p_j) - (qrho * beta) * w;
+        const float qrho = fmaf(qrho0, s1, qrho_i);
+        const float Ps = fmaf(-w, qrho * beta, fmaf(0.5f, p_j, half_pi));
         const float VdW = Vj * dW;
-        const float cpress = (m2Vi * VdW) * Ps * inv_r;  // times r: the unit vector's 1/|r| folded in
+        const float cpress = ((m2Vi * VdW) * Ps) * inv_r;  // times r: the unit vector's 1/|r| folded in
         const float cvisc = (e2Vi * VdW) * inv_r;
-        for (int k = 0; k < DIM; ++k) fsum[k] += cpress * r[k] + cvisc * dv[k];
+        for (int k = 0; k < DIM; ++k) fsum[k] += fmaf(cvisc, dv[k], cpress * r[k]);
+        }
       });
     };
     if (prep) fluid_pairs(std::true_type{});
@@ -1688,6 +1695,7 @@ __device__ __forceinline__ void force_particle(const Dev &D, int i, int q, bool 
 // neighbour state from global memory (the per-particle form)
 struct FetchGlobal {
   static constexpr bool kDerived = false;
+  static constexpr bool kOneScene = false;
   static constexpr int kIdxBits = kNbrBits;
   const Dev &D;
   __device__ __forceinline__ const unsigned *rows() const { return D.f_nbl; }
@@ -1740,6 +1748,7 @@ __device__ __forceinline__ void stage_tile(int cnt, const unsigned *tu, NbrTile 
 // neighbour records from the block's tile in LDS (entries index the tile)
 struct FetchTile {
   static constexpr bool kDerived = true;
+  static constexpr bool kOneScene = true;  // a tile's group lies in one scene: its shift table holds
   static constexpr int kIdxBits = kTileIdxBits;
   const NbrTile &t;
   const unsigned short *trows;
@@ -1758,6 +1767,7 @@ struct FetchTile {
 // eps^{n+1/2}), and the force pass's pressure where it is not recomputed
 struct FetchContinuity {
   static constexpr bool kDerived = false;
+  static constexpr bool kOneScene = false;
   static constexpr int kIdxBits = kNbrBits;
   const Dev &D;
   __device__ __forceinline__ const unsigned *rows() const { return D.f_nbl; }
@@ -1770,7 +1780,7 @@ struct FetchContinuity {
 };
 
 template <int DIM, int LPP>
-__global__ void __launch_bounds__(256) k_fluid_force(Dev D) {
+__global__ void __launch_bounds__(256, 5) k_fluid_force(Dev D) {
   __shared__ float4 shift_tab[27];
   if ((int)blockIdx.x < D.sort_blocks) {
     sort_coupling_lists(D, D.sort_blocks);
@@ -1917,7 +1927,8 @@ __device__ __forceinline__ void continuity_particle(const Dev &D, int i, int q, 
       constexpr bool T7 = decltype(t7_tag)::value;
       auto load = [&](unsigned ent, NbrRec &rec) {
         fetch(ent, T7, rec);
-        rec.sh = pair_shift_cid<DIM>(P, tab_ok, shift_tab, (int)(ent >> std::decay_t<Fetch>::kIdxBits));
+        rec.sh = pair_shift_cid<DIM>(P, std::decay_t<Fetch>::kOneScene || tab_ok, shift_tab,
+                                     (int)(ent >> std::decay_t<Fetch>::kIdxBits));
       };
       walk_pairs<LPP>(fetch.rows() + (size_t)i * LPP + q, lstride, q, rl.x, load, [&](unsigned, const NbrRec &rec) {
         const float4 &pj = rec.a, &vj4 = rec.b, &sh = rec.sh;
@@ -1931,17 +1942,23 @@ __device__ __forceinline__ void continuity_particle(const Dev &D, int i, int q, 
           rhoj = unfused(P.rho0 * (1.0f + vj4.w));
           Vj = unfused(pj.w * fast_rcp(rhoj));
         }
+        // every fused multiply-add written out and no other contraction, so
+        // that the tile and per-pair instantiations of this body round alike
+        {
+#pragma clang fp contract(off)
         float r[3] = {(pi.x - pj.x) - sh.x, (pi.y - pj.y) - sh.y, DIM == 3 ? (pi.z - pj.z) - sh.z : 0.0f};
-        float r2 = r[0] * r[0] + r[1] * r[1];
-        if (DIM == 3) r2 += r[2] * r[2];
+        float r2 = fmaf(r[1], r[1], r[0] * r[0]);
+        if (DIM == 3) r2 = fmaf(r[2], r[2], r2);
         const float inv_r = __builtin_amdgcn_rsqf(r2);
         const float rr = r2 * inv_r;
-        const float t = 1.0f + kt * rr;
-        const float dW = (kdw * rr) * (t * t * t);
-        float w = (vi[0] - vj4.x) * r[0] + (vi[1] - vj4.y) * r[1];
-        if (DIM == 3) w += (vi[2] - vj4.z) * r[2];
-        const float dvs = 0.5f * (w * inv_r) + (p_i - p_j) * fast_rcp((rhoi + rhoj) * rc);
-        drho += (2.0f * rhoi) * (Vj * dW) * (rc > 0.0f ? dvs : 0.5f * (w * inv_r));
+        const float t = fmaf(kt, rr, 1.0f);
+        const float dW = (kdw * rr) * (t * (t * t));
+        float w = fmaf(vi[1] - vj4.y, r[1], (vi[0] - vj4.x) * r[0]);
+        if (DIM == 3) w = fmaf(vi[2] - vj4.z, r[2], w);
+        const float wr = 0.5f * (w * inv_r);
+        const float dvs = fmaf(p_i - p_j, fast_rcp((rhoi + rhoj) * rc), wr);
+        drho = fmaf((2.0f * rhoi) * (Vj * dW), rc > 0.0f ? dvs : wr, drho);
+        }
       });
     };
     if (std::decay_t<Fetch>::kDerived || tait7)
