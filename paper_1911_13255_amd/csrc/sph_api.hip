@@ -707,7 +707,9 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
     D.nbr_bytes = tb < (size_t)INT_MAX ? (int)tb : 0;
   }
   D.capf = P.capf;
-  D.fluid_prep = P.nf >= 100000 ? 1 : 0;
+  // the snapshot pass saves the force pass one gather per pair; a tile forms
+  // the snapshot once per neighbour in its staging instead
+  D.fluid_prep = (P.nf >= 100000 && P.tile_gp == 0) ? 1 : 0;
   D.any_single = 0;
   for (int s = 0; s < n_scenes; ++s) D.any_single |= P.par[s].single_step;
   D.capb = P.capb;

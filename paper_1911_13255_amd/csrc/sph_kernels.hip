@@ -565,6 +565,11 @@ __global__ void k_refresh_vmax(Dev D) {
 // test, on the same values, as close_scene's.
 __device__ __forceinline__ bool rebuilds_next(const SceneState &S) { return S.adv_accum + S.dt_ac >= S.dt_ad; }
 
+// binning blocks of the step-end kernel (a grid-stride loop over the entries),
+// and the scene count up to which its blocks check the scenes' clocks first
+constexpr int kBinBlocksMax = 1024;
+constexpr int kBinSceneCheck = 8;
+
 // Bin entry t (fluid, then walls and free solid) of a rebuilding scene: new
 // cell and offset from the current position, slot within the cell, and a
 // copy of the fluid state by old index.  at_step_end: binned by the step-end
@@ -3183,8 +3188,13 @@ __global__ void __launch_bounds__(256) k_step_reduce(Dev D, int bin_blocks, int 
   __shared__ unsigned long long shc[3][16];
   if ((int)blockIdx.x < bin_blocks) {
     // the particles of scenes whose advection step ends with this step are
-    // binned for the rebuild that opens the next one
-    bin_entry<DIM>(D, blockIdx.x * blockDim.x + threadIdx.x, true);
+    // binned for the rebuild that opens the next one (most steps end none:
+    // then the blocks leave after reading the scenes' clocks)
+    bool any = D.n_scenes > kBinSceneCheck;
+    for (int s = 0; s < D.n_scenes && !any; ++s) any = rebuilds_next(D.st[s]);
+    if (!any) return;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < D.nf + D.nb; t += bin_blocks * blockDim.x)
+      bin_entry<DIM>(D, t, true);
     return;
   }
   const int blk = blockIdx.x - bin_blocks;
@@ -3960,7 +3970,7 @@ hipError_t allow_sur_net_lds() {
 
 void launch_step_end(const Dev &D, hipStream_t st, bool reduced) {
   int fb = (D.nf + 256 * kReduceItems - 1) / (256 * kReduceItems), sb = (D.ns + 255) / 256;
-  int bb = (D.nf + D.nb + 255) / 256;
+  int bb = std::min((D.nf + D.nb + 255) / 256, kBinBlocksMax);
   if (!reduced && bb + fb + sb > 0) LAUNCH_DIM(D.dim, k_step_reduce, dim3(bb + fb + sb), dim3(256), st, D, bb, fb);
   if (step_end_scan(D)) hipLaunchKernelGGL(k_step_close_scan, dim3(1), dim3(1024), 0, st, D);
   else hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
