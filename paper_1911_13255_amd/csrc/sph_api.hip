@@ -539,18 +539,20 @@ int enqueue_solid(sph_ctx *ctx, bool step_end) {
   if (ctx->cfg.solid_ppt > 0) {
     enqueue_solid_reg(ctx, step_end);
   } else if (ctx->D.ns > 0) {
-    launch_solid_dt(ctx->D, ctx->stream);
     int kmax = 0;
     if (ctx->kappa_ready) {
       // kappa as the end of the step before computed it from the same state
-      // (the averaging pass flags a scene whose kappa exceeds the passes)
+      // (the averaging pass flags a scene whose kappa exceeds the passes):
+      // the scenes adopt it, and k_solid_first starts the step's increments
       ctx->kappa_ready = 0;
+      launch_solid_dt_adopt(ctx->D, ctx->stream);
       if (hipEventSynchronize(ctx->ev_kappa) != hipSuccess) {
         std::snprintf(ctx->err, sizeof ctx->err, "solid_substeps: kappa read-back failed");
         return SPH_E_HIP;
       }
       for (int s = 0; s < ctx->n_scenes; ++s) kmax = std::max(kmax, ctx->st_host[s].kappa_next);
     } else {
+      launch_solid_dt(ctx->D, ctx->stream);
       std::vector<SceneState> st(ctx->n_scenes);
       if (hipMemcpyAsync(st.data(), ctx->D.st, sizeof(SceneState) * ctx->n_scenes, hipMemcpyDeviceToHost,
                          ctx->stream) != hipSuccess ||

@@ -94,6 +94,9 @@ void launch_solid_dt(const Dev &D, hipStream_t st);
 // the same reduction at a step's end, after its close, into kappa_next only
 // (the step increments and kappa stay untouched)
 void launch_solid_dt_next(const Dev &D, hipStream_t st);
+// the step starting now takes kappa and dt_S from launch_solid_dt_next at the
+// end of the step before (the solid state has not changed since)
+void launch_solid_dt_adopt(const Dev &D, hipStream_t st);
 void launch_solid_first(const Dev &D, hipStream_t st);
 void launch_solid_pass(const Dev &D, int sub, hipStream_t st);
 // launched: sub-step passes launched this step (scenes with a larger kappa are flagged)

@@ -2210,18 +2210,29 @@ __device__ __forceinline__ void solid_kappa(const ScenePar &P, SceneState &S, fl
   }
 }
 
+// mode 0: kappa and dt_S of the step starting now; 1: of the next step (at
+// this step's end, for the host); 2: the step starting now adopts what mode 1
+// computed from the same solid state (nothing changes the solid in between)
 __global__ void k_solid_dt_close(Dev D, int next) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= D.n_scenes) return;
   SceneState &S = D.st[s];
   int kap;
   double dts;
+  if (next == 2) {
+    S.kappa = S.kappa_next;
+    S.dt_s = S.dt_s_next;
+    S.err |= S.kappa_next_err;
+    return;
+  }
   if (next) {
-    // the error bits of a step-start evaluation are left to that one
+    // the error bits are latched by the step that adopts this evaluation
     const int err = S.err;
     solid_kappa(D.par[s], S, __uint_as_float(S.smax_v), __uint_as_float(S.smax_a), S.dt_ac, kap, dts);
+    S.kappa_next_err = S.err & ~err;
     S.err = err;
     S.kappa_next = kap;
+    S.dt_s_next = dts;
   } else {
     solid_kappa(D.par[s], S, __uint_as_float(S.smax_v), __uint_as_float(S.smax_a), S.dt_ac, kap, dts);
     S.dt_s = dts;
@@ -2240,10 +2251,12 @@ __device__ __forceinline__ void solid_first_half(const Dev &D, const ScenePar &P
     D.s_H[k * NS + a] = H[k];
     B[k] = D.s_B[k * NS + a];
   }
+  // the step's increments start here: du = the first half's, dv = 0
   for (int k = 0; k < DIM; ++k) {
     double inc = hd * D.s_v[k * NS + a];
     D.s_u[k * NS + a] += inc;
-    D.s_du[k * NS + a] += inc;
+    D.s_du[k * NS + a] = inc;
+    D.s_dv[k * NS + a] = 0.0;
   }
   double J;
   solid_PB<DIM, double>(P.material, H, B, (double)P.mu, (double)P.lam, PB, J);
@@ -3927,6 +3940,10 @@ void launch_solid_dt(const Dev &D, hipStream_t st) {
     hipLaunchKernelGGL(k_solid_dt_reduce, dim3((D.ns + 256 * kReduceItems - 1) / (256 * kReduceItems)), dim3(256), 0,
                        st, D, 0);
   hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D, 0);
+}
+
+void launch_solid_dt_adopt(const Dev &D, hipStream_t st) {
+  hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D, 2);
 }
 
 void launch_solid_dt_next(const Dev &D, hipStream_t st) {

@@ -52,8 +52,8 @@ struct ScenePar {
 struct SceneState {
   double t, dt_ac, dt_ad, dt_s, adv_accum;
   int kappa, need_rebuild, err;
-  int kappa_next;  // streamed solid: kappa of the next step, computed at this step's end for the host
-  int pad_kn;
+  int kappa_next;      // streamed solid: kappa of the next step, computed at this step's end for the host
+  int kappa_next_err;  // the error bits that evaluation would latch (latched when the step adopts it)
   int binned;  // pending rebuild prepared at the end of the last step: 1 particles binned, 2 cells scanned too
   unsigned int vmax_prev, vmax_next;  // max fluid speed (float bits): step start / being reduced
   unsigned int smax_v, smax_a;        // max solid speed and acceleration (float bits) being reduced
@@ -69,6 +69,7 @@ struct SceneState {
   unsigned long long sur_ok, sur_fallback;          // steps taken by the network / by the plain sub-steps
   unsigned long long sur_judge_ok, sur_judge_fail;  // judge steps passed / failed
   double sur_last_r;                                // residual R of the last judge step
+  double dt_s_next;  // streamed solid: the solid step that goes with kappa_next
 };
 
 // mode of a scene's acoustic step while a learned sub-step network is set
