@@ -110,6 +110,15 @@ typedef struct {
                            particles' fluid rows that indexes that set (2 bytes per pair-list slot
                            more device memory).  Results equal the per-pair gathers bit for bit.
                            -1: per-pair gathers.  2D always uses per-pair gathers. */
+  int solid_blocks;     /* 0: in 3D, where the compact reference table is on and every scene's solid
+                           sits on one lattice (one particle per cell, a bounding box of at most 4
+                           cells per particle) whose reference neighbours are exactly the lattice
+                           points within 2 h_S, the streamed sub-step passes run one workgroup per
+                           block of 4 x 4 x 16 lattice cells: it stages the P B or v of the cells
+                           within two spacings in LDS and sums over the offset classes in place of
+                           the pair table (a grid of 4 bytes per cell of the bounding boxes more
+                           device memory).  Sums run in class order, not table order, so results
+                           differ from the table walk by FP32 rounding.  -1: the pair table. */
 } sph_options;
 
 /* Field ids for sph_read / sph_write (FP64, original particle order).
@@ -307,8 +316,10 @@ int sph_launch_config(sph_ctx *ctx, int *out);
  * its lattice offset: 4 bytes per pair, the neighbour's index and the
  * offset's class), 0 for the full table (16 bytes per pair: the FP32
  * gradient and the index); out[1] = pair capacity per solid particle;
- * out[2] = bytes per pair that the sub-step passes read.  SPH_E_ORDER
- * without a context, SPH_E_ARG for a null out. */
+ * out[2] = bytes per pair that the table walk reads; out[3] = lattice
+ * blocks of the 3D streamed passes (sph_options.solid_blocks; 0 when they
+ * walk the table), out[4] = offset classes those blocks sum over.
+ * SPH_E_ORDER without a context, SPH_E_ARG for a null out. */
 int sph_solid_table(sph_ctx *ctx, int *out);
 
 /* Neighbour tiles of the fluid force and continuity passes (Section 3.1 pair

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstdint>
@@ -63,6 +64,12 @@ struct Plan {
   std::vector<ScenePar> par;
   std::vector<int> rank_to_cell, cell_scene, bs_scene;
   std::vector<int4> parts_map;  // split form of the block-resident solid kernel: (scene, part, parts, 0)
+  // lattice blocks of the streamed solid passes (3D; empty: none): the grid,
+  // per scene (grid offset, L0, L1, L2), the blocks, each particle's cell and
+  // the lattice axes slowest to fastest in storage
+  std::vector<int> lat_grid, lat_cell;
+  std::vector<int4> lat_scene, lat_blocks;
+  int lat_axis[3] = {0, 1, 2};
   LaunchCfg cfg{256, 256, 256};
 };
 
@@ -88,6 +95,81 @@ uint64_t morton_code(int d, const int *c) {
   for (int bit = 0; bit < 21; ++bit)
     for (int k = 0; k < d; ++k) code |= (uint64_t)((c[k] >> bit) & 1) << (bit * d + k);
   return code;
+}
+
+// Lattice blocks of the streamed solid passes (3D).  Every scene's solid must
+// sit on one lattice of spacing dp_S (each axis's coordinate an integer
+// number of spacings from the scene's minimum, to 1e-6 of a spacing, one
+// particle per cell) in a bounding box of at most 4 cells per particle;
+// otherwise P keeps no blocks.  Whether the reference neighbours are exactly
+// the lattice points within 2 h_S is checked by sph_init once the table is
+// built.
+void plan_lattice(const sph_scene *sc, int n, Plan &P) {
+  std::vector<int> cell((size_t)3 * P.ns);
+  long long changes[3] = {0, 0, 0};
+  for (int s = 0; s < n; ++s) {
+    const sph_scene &S = sc[s];
+    const int base = P.par[s].s_begin;
+    if (S.n_solid == 0) continue;
+    double lo[3];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = S.x_solid[k];
+      for (int i = 1; i < S.n_solid; ++i) lo[k] = std::min(lo[k], S.x_solid[3 * (size_t)i + k]);
+    }
+    for (int i = 0; i < S.n_solid; ++i)
+      for (int k = 0; k < 3; ++k) {
+        const double d = (S.x_solid[3 * (size_t)i + k] - lo[k]) / S.dp_s;
+        const double r = std::rint(d);
+        if (!(std::fabs(d - r) <= 1e-6) || r > 1e6) return;
+        cell[3 * (size_t)(base + i) + k] = (int)r;
+        if (i > 0 && cell[3 * (size_t)(base + i) + k] != cell[3 * (size_t)(base + i - 1) + k]) ++changes[k];
+      }
+  }
+  // the axis that changes least often between consecutive particles first
+  int ax[3] = {0, 1, 2};
+  std::stable_sort(ax, ax + 3, [&](int x, int y) { return changes[x] < changes[y]; });
+  std::vector<int> grid;
+  std::vector<int4> scene(n), blocks;
+  const int B[3] = {kLatB0, kLatB1, kLatB2};
+  for (int s = 0; s < n; ++s) {
+    const ScenePar &p = P.par[s];
+    scene[s] = make_int4((int)grid.size(), 0, 0, 0);
+    if (p.s_count == 0) continue;
+    int L[3] = {0, 0, 0};
+    for (int i = 0; i < p.s_count; ++i)
+      for (int k = 0; k < 3; ++k) L[k] = std::max(L[k], cell[3 * (size_t)(p.s_begin + i) + ax[k]] + 1);
+    const long long cells = (long long)L[0] * L[1] * L[2];
+    if (cells > 4LL * p.s_count + 4096 || (long long)grid.size() + cells > (1LL << 30)) return;
+    const size_t g0 = grid.size();
+    grid.resize(g0 + (size_t)cells, -1);
+    auto at = [&](int c0, int c1, int c2) { return g0 + ((size_t)c0 * L[1] + c1) * L[2] + c2; };
+    for (int i = 0; i < p.s_count; ++i) {
+      const int *c = &cell[3 * (size_t)(p.s_begin + i)];
+      int &g = grid[at(c[ax[0]], c[ax[1]], c[ax[2]])];
+      if (g >= 0) return;
+      g = p.s_begin + i;
+    }
+    scene[s] = make_int4((int)g0, L[0], L[1], L[2]);
+    const int nfree = p.s_count - p.s_nclamp;
+    for (int b0 = 0; b0 < L[0]; b0 += B[0])
+      for (int b1 = 0; b1 < L[1]; b1 += B[1])
+        for (int b2 = 0; b2 < L[2]; b2 += B[2]) {
+          bool any = false;
+          for (int c0 = b0; c0 < std::min(L[0], b0 + B[0]) && !any; ++c0)
+            for (int c1 = b1; c1 < std::min(L[1], b1 + B[1]) && !any; ++c1)
+              for (int c2 = b2; c2 < std::min(L[2], b2 + B[2]) && !any; ++c2) {
+                const int a = grid[at(c0, c1, c2)];
+                any = a >= 0 && a - p.s_begin < nfree;
+              }
+          if (any) blocks.push_back(make_int4(s, b0, b1, b2));
+        }
+  }
+  if (blocks.empty()) return;
+  P.lat_grid = std::move(grid);
+  P.lat_cell = std::move(cell);
+  P.lat_scene = std::move(scene);
+  P.lat_blocks = std::move(blocks);
+  for (int k = 0; k < 3; ++k) P.lat_axis[k] = ax[k];
 }
 
 bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std::string &err) {
@@ -300,6 +382,11 @@ bool make_plan(const sph_scene *sc, int n, const sph_options *opt, Plan &P, std:
   }
   // neighbour tiles: one group per block of the pair launches (3D)
   P.tile_gp = (P.dim == 3 && o.fluid_tiles == 0) ? P.cfg.block_pair / P.cfg.lpp_force : 0;
+  if (o.solid_blocks != 0 && o.solid_blocks != -1) {
+    err = "solid_blocks must be 0 or -1";
+    return false;
+  }
+  if (P.dim == 3 && P.ns > 0 && o.solid_blocks == 0) plan_lattice(sc, n, P);
   if (o.serial_passes != 0 && o.serial_passes != 1) {
     err = "serial_passes must be 0 or 1";
     return false;
@@ -440,11 +527,16 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   for (double **p : dvec) take(*p, 3 * ns);
   double **dten[] = {&D.s_H, &D.s_dF, &D.s_B, &D.s_PB};
   for (double **p : dten) take(*p, 9 * ns);
-  take(D.s_PBf, 9 * ns);
-  take(D.s_vf, ns);
+  take(D.s_PBf, 9 * std::max(ns, P.lat_grid.size()));
+  take(D.s_vf, std::max(ns, P.lat_grid.size()));
   take(D.s_nbc, P.dim == 3 ? (size_t)P.maxn * ns : 1);
   take(D.s_gcls, kNbrClasses);
   take(D.nbc_ok, 1);
+  take(D.lat_grid, P.lat_grid.size());
+  take(D.lat_of, P.lat_grid.empty() ? 1 : ns);
+  take(D.lat_scene, P.lat_scene.size());
+  take(D.lat_blocks, P.lat_blocks.size());
+  take(D.lat_cls, P.lat_blocks.empty() ? 1 : kNbrClasses);
   float **vec[] = {&D.s_a, &D.s_fF, &D.s_vbar, &D.s_abar, &D.s_n0, &D.s_n, &D.s_fFp,
                    &D.sur_vbar, &D.sur_abar};
   for (float **p : vec) take(*p, 3 * ns);
@@ -839,6 +931,70 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
       if ((rc = check_launch(ctx, "compact reference table")) != SPH_OK) return fail(rc);
     }
   }
+  // lattice blocks: on where the compact table is and every free particle's
+  // reference neighbours are exactly the lattice points at the offsets of
+  // nonzero class gradient (those the table holds are among them, so equal
+  // counts suffice)
+  D.lat_ncls = D.lat_nblocks = D.lat_ncells = 0;
+  if (D.nbr_compact && !P.lat_blocks.empty()) {
+    std::vector<float4> g(kNbrClasses);
+    std::vector<int> cnt(P.ns);
+    HIPCHK_INIT(hipMemcpy(g.data(), D.s_gcls, sizeof(float4) * kNbrClasses, hipMemcpyDeviceToHost));
+    HIPCHK_INIT(hipMemcpy(cnt.data(), D.s_cnt, sizeof(int) * P.ns, hipMemcpyDeviceToHost));
+    std::vector<int2> cls;
+    std::vector<std::array<int, 3>> off;
+    for (int c = 0; c < 125; ++c) {
+      if (g[c].x == 0.0f && g[c].y == 0.0f && g[c].z == 0.0f) continue;
+      const int o[3] = {c / 25 - 2, (c / 5) % 5 - 2, c % 5 - 2};
+      const int q[3] = {o[P.lat_axis[0]], o[P.lat_axis[1]], o[P.lat_axis[2]]};
+      cls.push_back(make_int2(q[1] * kLatRow + q[0] * kLatH2 + q[2], c));
+      off.push_back({q[0], q[1], q[2]});
+    }
+    bool ok = !cls.empty();
+    for (int s = 0; s < n_scenes && ok; ++s) {
+      const ScenePar &p = P.par[s];
+      const int4 L = P.lat_scene[s];
+      for (int i = 0; i < p.s_count - p.s_nclamp && ok; ++i) {
+        const int a = p.s_begin + i;
+        const int *c = &P.lat_cell[3 * (size_t)a];
+        const int c0 = c[P.lat_axis[0]], c1 = c[P.lat_axis[1]], c2 = c[P.lat_axis[2]];
+        int hits = 0;
+        for (const auto &q : off) {
+          const int x0 = c0 + q[0], x1 = c1 + q[1], x2 = c2 + q[2];
+          if (x0 < 0 || x0 >= L.y || x1 < 0 || x1 >= L.z || x2 < 0 || x2 >= L.w) continue;
+          hits += P.lat_grid[L.x + ((size_t)x0 * L.z + x1) * L.w + x2] >= 0;
+        }
+        ok = hits == cnt[a];
+      }
+    }
+    if (ok) {
+      // each particle's cell; the FP32 records move to cell order (the first
+      // solid pass of every step writes every particle's)
+      std::vector<int> of(P.ns);
+      for (int s = 0; s < n_scenes; ++s) {
+        const ScenePar &p = P.par[s];
+        const int4 L = P.lat_scene[s];
+        for (int i = 0; i < p.s_count; ++i) {
+          const int a = p.s_begin + i;
+          const int *c = &P.lat_cell[3 * (size_t)a];
+          of[a] = L.x + ((c[P.lat_axis[0]] * L.z) + c[P.lat_axis[1]]) * L.w + c[P.lat_axis[2]];
+        }
+      }
+      const size_t nrec = std::max((size_t)P.ns, P.lat_grid.size());
+      HIPCHK_INIT(hipMemcpy(D.lat_of, of.data(), sizeof(int) * P.ns, hipMemcpyHostToDevice));
+      HIPCHK_INIT(hipMemset(D.s_PBf, 0, sizeof(float) * 9 * nrec));
+      HIPCHK_INIT(hipMemset(D.s_vf, 0, sizeof(float4) * nrec));
+      D.lat_ncells = (int)P.lat_grid.size();
+      HIPCHK_INIT(hipMemcpy(D.lat_grid, P.lat_grid.data(), sizeof(int) * P.lat_grid.size(), hipMemcpyHostToDevice));
+      HIPCHK_INIT(
+          hipMemcpy(D.lat_scene, P.lat_scene.data(), sizeof(int4) * P.lat_scene.size(), hipMemcpyHostToDevice));
+      HIPCHK_INIT(
+          hipMemcpy(D.lat_blocks, P.lat_blocks.data(), sizeof(int4) * P.lat_blocks.size(), hipMemcpyHostToDevice));
+      HIPCHK_INIT(hipMemcpy(D.lat_cls, cls.data(), sizeof(int2) * cls.size(), hipMemcpyHostToDevice));
+      D.lat_ncls = (int)cls.size();
+      D.lat_nblocks = (int)P.lat_blocks.size();
+    }
+  }
 #undef HIPCHK_INIT
   ctx->prebin = 1;  // every scene starts with a rebuild
   *out = ctx;
@@ -1169,7 +1325,8 @@ int sph_solid_table(sph_ctx *ctx, int *out) {
   if (!ctx) return SPH_E_ORDER;
   if (!out) return SPH_E_ARG;
   const int compact = ctx->D.nbr_compact;
-  int v[3] = {compact, ctx->D.maxn, compact ? (int)sizeof(unsigned) : (int)sizeof(float4)};
+  int v[5] = {compact, ctx->D.maxn, compact ? (int)sizeof(unsigned) : (int)sizeof(float4), ctx->D.lat_nblocks,
+              ctx->D.lat_ncls};
   std::memcpy(out, v, sizeof v);
   return SPH_OK;
 }

@@ -35,6 +35,29 @@ constexpr int kTileCap = 768;
 constexpr int kTileIdxBits = 10;
 static_assert(kTileCap <= (1 << kTileIdxBits), "tile positions fit their bits");
 
+// lattice blocks of the streamed solid passes (3D): cells per block along
+// the lattice axes (slowest to fastest in storage), and the halo of offset
+// classes (up to 2 spacings per axis) that a block stages in LDS
+constexpr int kLatB0 = 4, kLatB1 = 4, kLatB2 = 16;
+constexpr int kLatR = 2;
+constexpr int kLatH0 = kLatB0 + 2 * kLatR, kLatH1 = kLatB1 + 2 * kLatR, kLatH2 = kLatB2 + 2 * kLatR;
+constexpr int kLatHalo = kLatH0 * kLatH1 * kLatH2;
+constexpr int kLatThreads = kLatB0 * kLatB1 * kLatB2;
+// LDS layout of a halo component: axis 2 contiguous, then axis 0, then axis 1
+// at a stride of kLatRow words (16 or 48 modulo 64), so that the four 16-lane
+// rows of a wave (one axis-0 plane, four axis-1 rows) read distinct banks
+constexpr int lat_row(int w) { return (w % 64 == 16 || w % 64 == 48) ? w : lat_row(w + 1); }
+constexpr int kLatRow = lat_row(kLatH0 * kLatH2);
+constexpr int kLatLds = kLatH1 * kLatRow;
+static_assert(kLatB2 == 16 && kLatB1 == 4 && kLatThreads % 64 == 0, "a wave is one axis-0 plane of 4 x 16 cells");
+// the hardware deals consecutive workgroups to its 8 XCDs in turn; lattice
+// blocks are launched so that each XCD runs a contiguous run of the block
+// list, whose neighbours share halo cells in that XCD's L2
+#ifndef MRSPH_LAT_XCD
+#define MRSPH_LAT_XCD 1
+#endif
+constexpr int kXcds = 8;
+
 struct LaunchCfg {
   int block_pair;    // threads per block of the fluid pair kernels
   int block_couple;  // threads per block of the coupling kernel

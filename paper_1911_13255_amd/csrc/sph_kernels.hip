@@ -36,6 +36,12 @@ __device__ __forceinline__ int particle_index() { return xcd_block() * blockDim.
 // Component k of particle a's P B (component-major: the lanes of a wave
 // gather consecutive neighbours' component k from a few cache lines).
 __device__ __forceinline__ size_t pb_at(const Dev &D, int a, int k) { return (size_t)k * D.ns + a; }
+// FP32 record slots of the streamed solid passes (s_PBf component k, s_vf):
+// particle a's own, or on lattice blocks its cell's
+__device__ __forceinline__ int rec_of(const Dev &D, int a) { return D.lat_nblocks ? D.lat_of[a] : a; }
+__device__ __forceinline__ size_t pbf_at(const Dev &D, int r, int k) {
+  return (size_t)k * (D.lat_nblocks ? D.lat_ncells : D.ns) + r;
+}
 
 // smallest power of two >= n (block-wide tree reductions over any block size)
 __device__ __forceinline__ int pow2_ceil(int n) {
@@ -2261,9 +2267,10 @@ __device__ __forceinline__ void solid_first_half(const Dev &D, const ScenePar &P
   double J;
   solid_PB<DIM, double>(P.material, H, B, (double)P.mu, (double)P.lam, PB, J);
   if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
+  const int r = rec_of(D, a);
   for (int k = 0; k < DIM * DIM; ++k) {
     D.s_PB[pb_at(D, a, k)] = PB[k];
-    D.s_PBf[pb_at(D, a, k)] = (float)PB[k];
+    D.s_PBf[pbf_at(D, r, k)] = (float)PB[k];
   }
 }
 
@@ -2276,63 +2283,41 @@ __global__ void __launch_bounds__(256) k_solid_first(Dev D) {
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
   if (a - P.s_begin >= P.s_count - P.s_nclamp) {
+    const int r = rec_of(D, a);
     for (int k = 0; k < DIM * DIM; ++k) {
       D.s_PB[pb_at(D, a, k)] = 0.0;
-      D.s_PBf[pb_at(D, a, k)] = 0.0f;
+      D.s_PBf[pbf_at(D, r, k)] = 0.0f;
     }
     const int NS = D.ns;
-    D.s_vf[a] = make_float4((float)D.s_v[a], (float)D.s_v[NS + a], DIM == 3 ? (float)D.s_v[2 * NS + a] : 0.0f, 0.0f);
+    D.s_vf[r] = make_float4((float)D.s_v[a], (float)D.s_v[NS + a], DIM == 3 ? (float)D.s_v[2 * NS + a] : 0.0f, 1.0f);
     return;
   }
   solid_first_half<DIM>(D, P, S, a, 0.5 * S.dt_ac / S.kappa);
 }
 
-// Momentum and velocity of sub-step `sub`.
+// Momentum of free particle a: sum_b (P_a B_a + P_b B_b) g_ab = P_a B_a
+// sum_b g_ab + sum_b P_b B_b g_ab, the own term in FP64 (here), the
+// neighbours' P B in FP32 (their rounding reaches the acceleration scaled by
+// about the ratio of the stress length scale to h).
 template <int DIM>
-__global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
-  __shared__ float4 gcl[kNbrClasses];
-  const bool compact = DIM == 3 && D.nbr_compact;
-  if (compact) {
-    if (threadIdx.x < kNbrClasses) gcl[threadIdx.x] = D.s_gcls[threadIdx.x];
-    __syncthreads();
+__device__ __forceinline__ void solid_momentum_own(const Dev &D, int a, double *acc) {
+  const int NS = D.ns;
+  for (int i = 0; i < DIM; ++i) {
+    acc[i] = 0.0;
+    for (int j = 0; j < DIM; ++j) acc[i] += D.s_PB[pb_at(D, a, i * DIM + j)] * D.s_gsum[j * NS + a];
   }
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= D.ns) return;
-  int s = D.s_scene[a];
-  const ScenePar &P = D.par[s];
-  SceneState &S = D.st[s];
-  if (sub >= S.kappa || a - P.s_begin >= P.s_count - P.s_nclamp) return;
+}
+
+// Momentum and velocity of free particle a in the current sub-step, its
+// velocity record at slot r; acc holds the own term and walk(accn) adds sum_b
+// P_b B_b g_ab over a's reference neighbours in FP32.
+template <int DIM, class Walk>
+__device__ __forceinline__ void solid_momentum_at(const Dev &D, const ScenePar &P, const SceneState &S, int a, int r,
+                                                  double *acc, Walk walk) {
   const int NS = D.ns;
   const double del = S.dt_ac / S.kappa;
-  // sum_b (P_a B_a + P_b B_b) g_ab = P_a B_a sum_b g_ab + sum_b P_b B_b g_ab:
-  // the own term in FP64, the neighbours' P B gathered in FP32 (the gathers
-  // bound this pass; their rounding reaches the acceleration scaled by about
-  // the ratio of the stress length scale to h)
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int i = 0; i < DIM; ++i)
-    for (int j = 0; j < DIM; ++j) acc[i] += D.s_PB[pb_at(D, a, i * DIM + j)] * D.s_gsum[j * NS + a];
   float accn[3] = {0.0f, 0.0f, 0.0f};
-  int cnt = D.s_cnt[a];
-  auto pair = [&](int b, const float4 &g) {
-    float gv[3] = {g.x, g.y, g.z};
-    float PBb[9];
-    for (int k = 0; k < DIM * DIM; ++k) PBb[k] = D.s_PBf[pb_at(D, b, k)];
-    for (int i = 0; i < DIM; ++i)
-      for (int j = 0; j < DIM; ++j) accn[i] += PBb[i * DIM + j] * gv[j];
-  };
-  if (compact) {
-#pragma unroll 4
-    for (int q = 0; q < cnt; ++q) {
-      const unsigned e = D.s_nbc[(size_t)q * NS + a];
-      pair((int)(e >> 7), gcl[e & 127u]);
-    }
-  } else {
-#pragma unroll 4
-    for (int q = 0; q < cnt; ++q) {
-      const float4 g = D.s_nbr[(size_t)q * NS + a];
-      pair(__float_as_int(g.w), g);
-    }
-  }
+  walk(accn);
   for (int i = 0; i < DIM; ++i) acc[i] += (double)accn[i];
   const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
   double vn[3] = {0.0, 0.0, 0.0};
@@ -2344,58 +2329,24 @@ __global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
     D.s_v[k * NS + a] = vn[k];
     D.s_dv[k * NS + a] += dv;
   }
-  D.s_vf[a] = make_float4((float)vn[0], (float)vn[1], (float)vn[2], 0.0f);
+  D.s_vf[r] = make_float4((float)vn[0], (float)vn[1], (float)vn[2], 1.0f);
 }
 
-// Deformation rate with the new velocity and second half of sub-step `sub`;
-// then the first half and stress of the next sub-step.
-template <int DIM>
-__global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
-  __shared__ float4 gcl[kNbrClasses];
-  const bool compact = DIM == 3 && D.nbr_compact;
-  if (compact) {
-    if (threadIdx.x < kNbrClasses) gcl[threadIdx.x] = D.s_gcls[threadIdx.x];
-    __syncthreads();
-  }
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= D.ns) return;
-  int s = D.s_scene[a];
-  const ScenePar &P = D.par[s];
-  SceneState &S = D.st[s];
-  if (sub >= S.kappa || a - P.s_begin >= P.s_count - P.s_nclamp) return;
+// Deformation rate of free particle a with the new velocity and second half
+// of sub-step `sub`; then the first half and stress of the next sub-step,
+// its FP32 P B at record slot r.  walk(Gn) adds sum_b (v_b - v_a) (x) g_ab
+// over a's reference neighbours in FP32: the neighbours' v as one FP32
+// record each, the differences v_b - v_a taken between FP32-rounded values
+// (so a rigid translation still gives exactly zero).
+template <int DIM, class Walk>
+__device__ __forceinline__ void solid_rate_at(const Dev &D, const ScenePar &P, SceneState &S, int a, int r, int sub,
+                                              Walk walk) {
   const int NS = D.ns;
   const double hd = 0.5 * S.dt_ac / S.kappa;
+  float Gn[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  walk(Gn);
   double va[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < DIM; ++k) va[k] = D.s_v[k * NS + a];
-  // the neighbours' v gathered as one FP32 record each (the gathers bound
-  // this pass); the differences v_b - v_a are taken between FP32-rounded
-  // values, so a rigid translation still gives exactly zero, and summed in
-  // FP32
-  float vaf[3] = {(float)va[0], (float)va[1], (float)va[2]};
-  float Gn[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  int cnt = D.s_cnt[a];
-  auto pair = [&](int b, const float4 &g) {
-    float gv[3] = {g.x, g.y, g.z};
-    float4 vb = D.s_vf[b];
-    float vbv[3] = {vb.x, vb.y, vb.z};
-    for (int i = 0; i < DIM; ++i) {
-      float dvi = vbv[i] - vaf[i];
-      for (int j = 0; j < DIM; ++j) Gn[i * DIM + j] += dvi * gv[j];
-    }
-  };
-  if (compact) {
-#pragma unroll 4
-    for (int q = 0; q < cnt; ++q) {
-      const unsigned e = D.s_nbc[(size_t)q * NS + a];
-      pair((int)(e >> 7), gcl[e & 127u]);
-    }
-  } else {
-#pragma unroll 4
-    for (int q = 0; q < cnt; ++q) {
-      const float4 g = D.s_nbr[(size_t)q * NS + a];
-      pair(__float_as_int(g.w), g);
-    }
-  }
   double G[9];
   for (int k = 0; k < DIM * DIM; ++k) G[k] = (double)Gn[k];
   // (v_b - v_a) (x) (B grad W) summed = G B^T; then, for a following
@@ -2429,9 +2380,233 @@ __global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
     if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
     for (int k = 0; k < DIM * DIM; ++k) {
       D.s_PB[pb_at(D, a, k)] = PB[k];
-      D.s_PBf[pb_at(D, a, k)] = (float)PB[k];
+      D.s_PBf[pbf_at(D, r, k)] = (float)PB[k];
     }
   }
+}
+
+// Momentum and velocity of sub-step `sub`, one thread per solid particle
+// walking its reference table (the neighbours' P B gathered per pair, the
+// gathers bound this pass).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_solid_momentum(Dev D, int sub) {
+  __shared__ float4 gcl[kNbrClasses];
+  const bool compact = DIM == 3 && D.nbr_compact;
+  if (compact) {
+    if (threadIdx.x < kNbrClasses) gcl[threadIdx.x] = D.s_gcls[threadIdx.x];
+    __syncthreads();
+  }
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  int s = D.s_scene[a];
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  if (sub >= S.kappa || a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  const int NS = D.ns;
+  double acc[3];
+  solid_momentum_own<DIM>(D, a, acc);
+  solid_momentum_at<DIM>(D, P, S, a, a, acc, [&](float *accn) {
+    int cnt = D.s_cnt[a];
+    auto pair = [&](int b, const float4 &g) {
+      float gv[3] = {g.x, g.y, g.z};
+      float PBb[9];
+      for (int k = 0; k < DIM * DIM; ++k) PBb[k] = D.s_PBf[pb_at(D, b, k)];
+      for (int i = 0; i < DIM; ++i)
+        for (int j = 0; j < DIM; ++j) accn[i] += PBb[i * DIM + j] * gv[j];
+    };
+    if (compact) {
+#pragma unroll 4
+      for (int q = 0; q < cnt; ++q) {
+        const unsigned e = D.s_nbc[(size_t)q * NS + a];
+        pair((int)(e >> 7), gcl[e & 127u]);
+      }
+    } else {
+#pragma unroll 4
+      for (int q = 0; q < cnt; ++q) {
+        const float4 g = D.s_nbr[(size_t)q * NS + a];
+        pair(__float_as_int(g.w), g);
+      }
+    }
+  });
+}
+
+// Deformation rate and second half of sub-step `sub` (then the next one's
+// first half), one thread per solid particle walking its reference table.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
+  __shared__ float4 gcl[kNbrClasses];
+  const bool compact = DIM == 3 && D.nbr_compact;
+  if (compact) {
+    if (threadIdx.x < kNbrClasses) gcl[threadIdx.x] = D.s_gcls[threadIdx.x];
+    __syncthreads();
+  }
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.ns) return;
+  int s = D.s_scene[a];
+  const ScenePar &P = D.par[s];
+  SceneState &S = D.st[s];
+  if (sub >= S.kappa || a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  const int NS = D.ns;
+  float vaf[3] = {0.0f, 0.0f, 0.0f};
+  for (int k = 0; k < DIM; ++k) vaf[k] = (float)D.s_v[k * NS + a];
+  solid_rate_at<DIM>(D, P, S, a, a, sub, [&](float *Gn) {
+    int cnt = D.s_cnt[a];
+    auto pair = [&](int b, const float4 &g) {
+      float gv[3] = {g.x, g.y, g.z};
+      float4 vb = D.s_vf[b];
+      float vbv[3] = {vb.x, vb.y, vb.z};
+      for (int i = 0; i < DIM; ++i) {
+        float dvi = vbv[i] - vaf[i];
+        for (int j = 0; j < DIM; ++j) Gn[i * DIM + j] += dvi * gv[j];
+      }
+    };
+    if (compact) {
+#pragma unroll 4
+      for (int q = 0; q < cnt; ++q) {
+        const unsigned e = D.s_nbc[(size_t)q * NS + a];
+        pair((int)(e >> 7), gcl[e & 127u]);
+      }
+    } else {
+#pragma unroll 4
+      for (int q = 0; q < cnt; ++q) {
+        const float4 g = D.s_nbr[(size_t)q * NS + a];
+        pair(__float_as_int(g.w), g);
+      }
+    }
+  });
+}
+
+// Lattice blocks (3D): one workgroup per block of kLatB0 x kLatB1 x kLatB2
+// lattice cells of one scene, a thread per cell (the fastest storage axis
+// fastest across the lanes).  The FP32 records are kept in cell order, so the
+// workgroup stages those of the cells within kLatR spacings (zeros for empty
+// ones) in LDS with coalesced loads and no index lookups, and each free
+// particle sums over the offset classes at fixed shifts from its own halo
+// position: every pair becomes LDS reads at an immediate offset, with no
+// table entry and no gather.  The set summed over is the reference table's
+// (checked at set-up), the order the classes'.
+
+// the block of the list this workgroup takes (-1: none)
+__device__ __forceinline__ int lat_block(const Dev &D) {
+#if MRSPH_LAT_XCD
+  const int per = (D.lat_nblocks + kXcds - 1) / kXcds;
+  const int b = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+#else
+  const int b = blockIdx.x;
+#endif
+  return b < D.lat_nblocks ? b : -1;
+}
+
+// Stage rec(cell, lds) for every halo cell of block blk: cell its grid index
+// (-1 outside the scene's bounding box), lds its LDS position.
+template <class Rec>
+__device__ __forceinline__ void lat_stage(const int4 &L, const int4 &blk, Rec rec) {
+  constexpr int kPer = (kLatHalo + kLatThreads - 1) / kLatThreads;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = threadIdx.x + q * kLatThreads;
+    if (kLatHalo % kLatThreads != 0 && i >= kLatHalo) break;
+    const int h0 = i / (kLatH1 * kLatH2), h12 = i - h0 * (kLatH1 * kLatH2);
+    const int h1 = h12 / kLatH2, h2 = h12 - h1 * kLatH2;
+    const int c0 = blk.y - kLatR + h0, c1 = blk.z - kLatR + h1, c2 = blk.w - kLatR + h2;
+    const bool in = (unsigned)c0 < (unsigned)L.y && (unsigned)c1 < (unsigned)L.z && (unsigned)c2 < (unsigned)L.w;
+    rec(in ? L.x + (c0 * L.z + c1) * L.w + c2 : -1, h1 * kLatRow + h0 * kLatH2 + h2);
+  }
+}
+
+// This thread's cell of block blk: its grid index (-1 outside the bounding
+// box) and its LDS position.
+__device__ __forceinline__ int lat_own(const int4 &L, const int4 &blk, int &pos) {
+  const int t = threadIdx.x;
+  const int t0 = t / (kLatB1 * kLatB2), t12 = t - t0 * (kLatB1 * kLatB2);
+  const int t1 = t12 / kLatB2, t2 = t12 - t1 * kLatB2;
+  pos = (t1 + kLatR) * kLatRow + (t0 + kLatR) * kLatH2 + (t2 + kLatR);
+  const int c0 = blk.y + t0, c1 = blk.z + t1, c2 = blk.w + t2;
+  const bool in = (unsigned)c0 < (unsigned)L.y && (unsigned)c1 < (unsigned)L.z && (unsigned)c2 < (unsigned)L.w;
+  return in ? L.x + (c0 * L.z + c1) * L.w + c2 : -1;
+}
+
+// Momentum pass on lattice blocks: the halo's FP32 P B in LDS.
+__global__ void __launch_bounds__(kLatThreads) k_solid_momentum_lat(Dev D, int sub) {
+  __shared__ float pb[9 * kLatLds];
+  const int bi = lat_block(D);
+  if (bi < 0) return;
+  const int4 blk = D.lat_blocks[bi];
+  const ScenePar &P = D.par[blk.x];
+  SceneState &S = D.st[blk.x];
+  if (sub >= S.kappa) return;
+  const int4 L = D.lat_scene[blk.x];
+  int pos;
+  const int cell = lat_own(L, blk, pos);
+  const int a = cell >= 0 ? D.lat_grid[cell] : -1;
+  const bool act = a >= 0 && a - P.s_begin < P.s_count - P.s_nclamp;
+  // the own term's loads in flight with the staging
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (act) solid_momentum_own<3>(D, a, acc);
+  const size_t NC = D.lat_ncells;
+  lat_stage(L, blk, [&](int c, int l) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) pb[k * kLatLds + l] = c >= 0 ? D.s_PBf[k * NC + c] : 0.0f;
+  });
+  __syncthreads();
+  if (!act) return;
+  solid_momentum_at<3>(D, P, S, a, cell, acc, [&](float *accn) {
+    const float *r0 = pb + pos;
+    const int nc = D.lat_ncls;
+#pragma unroll 4
+    for (int j = 0; j < nc; ++j) {
+      const int2 c = D.lat_cls[j];
+      const float4 g = D.s_gcls[c.y];
+      const float gv[3] = {g.x, g.y, g.z};
+      const float *r = r0 + c.x;
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) accn[i] += r[(i * 3 + k) * kLatLds] * gv[k];
+    }
+  });
+}
+
+// Rate pass on lattice blocks: the halo's FP32 v and presence weight (1 for
+// a cell with a particle, 0 for an empty one) in LDS.
+__global__ void __launch_bounds__(kLatThreads) k_solid_rate_lat(Dev D, int sub) {
+  __shared__ float vh[4 * kLatLds];
+  const int bi = lat_block(D);
+  if (bi < 0) return;
+  const int4 blk = D.lat_blocks[bi];
+  const ScenePar &P = D.par[blk.x];
+  SceneState &S = D.st[blk.x];
+  if (sub >= S.kappa) return;
+  const int4 L = D.lat_scene[blk.x];
+  int pos;
+  const int cell = lat_own(L, blk, pos);
+  const int a = cell >= 0 ? D.lat_grid[cell] : -1;
+  lat_stage(L, blk, [&](int c, int l) {
+    const float4 v = c >= 0 ? D.s_vf[c] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    vh[l] = v.x;
+    vh[kLatLds + l] = v.y;
+    vh[2 * kLatLds + l] = v.z;
+    vh[3 * kLatLds + l] = v.w;
+  });
+  __syncthreads();
+  if (a < 0 || a - P.s_begin >= P.s_count - P.s_nclamp) return;
+  solid_rate_at<3>(D, P, S, a, cell, sub, [&](float *Gn) {
+    const float *r0 = vh + pos;
+    // v_a rounded to FP32 is the particle's own record
+    const float vaf[3] = {r0[0], r0[kLatLds], r0[2 * kLatLds]};
+    const int nc = D.lat_ncls;
+#pragma unroll 4
+    for (int j = 0; j < nc; ++j) {
+      const int2 c = D.lat_cls[j];
+      const float4 g = D.s_gcls[c.y];
+      const float gv[3] = {g.x, g.y, g.z};
+      const float *r = r0 + c.x;
+      const float w = r[3 * kLatLds];
+      for (int i = 0; i < 3; ++i) {
+        // (v_b - v_a) exactly for a particle, zero for an empty cell
+        const float dvi = (r[i * kLatLds] - vaf[i]) * w;
+        for (int k = 0; k < 3; ++k) Gn[i * 3 + k] += dvi * gv[k];
+      }
+    }
+  });
 }
 
 // Time averages over the acoustic step.
@@ -3959,6 +4134,12 @@ void launch_solid_first(const Dev &D, hipStream_t st) {
 
 void launch_solid_pass(const Dev &D, int sub, hipStream_t st) {
   if (D.ns == 0) return;
+  if (D.dim == 3 && D.lat_nblocks > 0) {
+    const int grid = MRSPH_LAT_XCD ? (D.lat_nblocks + kXcds - 1) / kXcds * kXcds : D.lat_nblocks;
+    hipLaunchKernelGGL(k_solid_momentum_lat, dim3(grid), dim3(kLatThreads), 0, st, D, sub);
+    hipLaunchKernelGGL(k_solid_rate_lat, dim3(grid), dim3(kLatThreads), 0, st, D, sub);
+    return;
+  }
   LAUNCH_DIM(D.dim, k_solid_momentum, grid_for(D.ns, 256), dim3(256), st, D, sub);
   LAUNCH_DIM(D.dim, k_solid_rate, grid_for(D.ns, 256), dim3(256), st, D, sub);
 }

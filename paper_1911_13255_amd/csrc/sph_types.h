@@ -181,6 +181,22 @@ struct Dev {
   float4 *s_gcls;
   int *nbc_ok;                     // set-up: stays 1 while every pair matches its class
   int nbr_compact;                 // 1: the streamed solid passes walk s_nbc
+  // lattice blocks of the streamed solid passes (3D): every scene's solid on
+  // one lattice whose reference neighbours are exactly its points within 2 h_S.
+  // Lattice axes are ordered slowest to fastest in storage; lat_grid maps a
+  // scene's bounding box of cells, [(c0 * L1 + c1) * L2 + c2] from offset
+  // lat_scene[s].x with (L0, L1, L2) in .y .z .w, to the particle there or -1;
+  // lat_blocks[i] = (scene, first cell per axis) of a block of kLatB0 x kLatB1
+  // x kLatB2 cells holding a free particle; lat_cls[j] = (the offset's
+  // position shift in a block's halo, its class) for the lat_ncls classes of
+  // nonzero gradient.  lat_nblocks = 0: the passes walk the pair table.
+  // On lattice blocks s_PBf and s_vf are indexed by grid cell (lat_ncells of
+  // them; empty cells hold zeros, a particle's velocity record has w = 1) and
+  // lat_of[a] is particle a's cell.
+  int *lat_grid, *lat_of;
+  int4 *lat_scene, *lat_blocks;
+  int2 *lat_cls;
+  int lat_ncls, lat_nblocks, lat_ncells;
   float4 *s_vf;                    // v rounded to FP32, one 16-byte record per particle: what the streamed
                                    // rate pass gathers (free particles: written by the momentum pass of the
                                    // same sub-step; clamped ones: by the first pass of the step)

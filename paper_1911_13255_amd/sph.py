@@ -59,7 +59,8 @@ class SphOptions(C.Structure):
     _fields_ = [("riemann", C.c_int), ("density_reinit", C.c_int), ("max_solid_nbr", C.c_int),
                 ("solid_block", C.c_int), ("lanes_per_particle", C.c_int), ("block_pair", C.c_int),
                 ("solid_lds", C.c_int), ("max_fluid_nbr", C.c_int), ("max_boundary_nbr", C.c_int),
-                ("serial_passes", C.c_int), ("solid_parts", C.c_int), ("fluid_tiles", C.c_int)]
+                ("serial_passes", C.c_int), ("solid_parts", C.c_int), ("fluid_tiles", C.c_int),
+                ("solid_blocks", C.c_int)]
 
     def as_dict(self) -> dict:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -169,10 +170,11 @@ def scene_array(scenes):
 
 def make_options(riemann=True, density_reinit=1, max_solid_nbr=0, solid_block=0, lanes_per_particle=0,
                  block_pair=0, solid_lds=0, max_fluid_nbr=0, max_boundary_nbr=0, serial_passes=0, solid_parts=0,
-                 fluid_tiles=0):
+                 fluid_tiles=0, solid_blocks=0):
     return SphOptions(int(riemann), int(density_reinit), int(max_solid_nbr), int(solid_block),
                       int(lanes_per_particle), int(block_pair), int(solid_lds), int(max_fluid_nbr),
-                      int(max_boundary_nbr), int(serial_passes), int(solid_parts), int(fluid_tiles))
+                      int(max_boundary_nbr), int(serial_passes), int(solid_parts), int(fluid_tiles),
+                      int(solid_blocks))
 
 
 def workload_signature(scenes, opt: dict) -> str:
@@ -246,7 +248,7 @@ class Simulation:
                  max_solid_nbr: int = 0, solid_block: int = 0, lanes_per_particle: int = 0,
                  block_pair: int = 0, solid_lds: int = 0, max_fluid_nbr: int = 0,
                  max_boundary_nbr: int = 0, serial_passes: int = 0, solid_parts: int = 0, fluid_tiles: int = 0,
-                 device: int = 0, arena_fill: int = None):
+                 solid_blocks: int = 0, device: int = 0, arena_fill: int = None):
         """arena_fill: byte written over the whole arena before sph_init (tests
         use it to show that no result depends on the arena's prior contents)."""
         import torch
@@ -263,7 +265,7 @@ class Simulation:
         self._scenes = arr
         self.opt = make_options(riemann, density_reinit, max_solid_nbr, solid_block, lanes_per_particle,
                                 block_pair, solid_lds, max_fluid_nbr, max_boundary_nbr, serial_passes, solid_parts,
-                                fluid_tiles)
+                                fluid_tiles, solid_blocks)
         nbytes = self.L.sph_arena_bytes(arr, self.n_scenes, C.byref(self.opt))
         if nbytes == 0:
             raise SphError(SPH_E_ARG, "invalid scene description")
@@ -429,9 +431,10 @@ class Simulation:
         return dict(zip(keys, [int(x) for x in out]))
 
     def solid_table(self) -> dict:
-        out = (C.c_int * 3)()
+        out = (C.c_int * 5)()
         self._check(self.L.sph_solid_table(self.ctx, out))
-        return {"compact": int(out[0]), "capacity": int(out[1]), "bytes_per_pair": int(out[2])}
+        return {"compact": int(out[0]), "capacity": int(out[1]), "bytes_per_pair": int(out[2]),
+                "lattice_blocks": int(out[3]), "classes": int(out[4])}
 
     def fluid_tiles(self) -> dict:
         out = (C.c_longlong * 5)()

@@ -112,3 +112,27 @@ def test_split_solid_option_is_validated_and_sized():
     assert plain > 0 and split > plain
     # a target above the plate's free particles splits nothing
     assert L.sph_arena_bytes(arr, 1, ctypes.byref(sph.make_options(solid_parts=100000))) == plain
+
+
+def test_solid_blocks_option_is_validated_and_sized():
+    # solid_blocks: 0 or -1. A 3D solid on an exact lattice adds the lattice
+    # grid of its bounding box (4 bytes per cell) to the arena; a jittered
+    # reference configuration, a 2D scene and -1 add nothing
+    import ctypes
+
+    from paper_1911_13255_amd import scenes, sph
+
+    L = sph.lib()
+
+    def nbytes(sc, **o):
+        arr, keep = sph.scene_array([sc])
+        return L.sph_arena_bytes(arr, 1, ctypes.byref(sph.make_options(**o)))
+
+    lat = scenes.periodic_box_with_solid(dim=3, n=12, solid_lattice=True)
+    jit = scenes.periodic_box_with_solid(dim=3, n=12, solid_lattice=False)
+    assert nbytes(lat, solid_blocks=2) == 0 and nbytes(lat, solid_blocks=-2) == 0
+    ns = len(lat["x_solid"])
+    assert nbytes(lat) >= nbytes(lat, solid_blocks=-1) + 4 * ns
+    assert nbytes(jit) == nbytes(jit, solid_blocks=-1)
+    flat = scenes.periodic_box_with_solid(dim=2, n=12, solid_lattice=True)
+    assert nbytes(flat) == nbytes(flat, solid_blocks=-1)

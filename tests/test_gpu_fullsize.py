@@ -9,7 +9,7 @@ runs a crop of radius 4 h_F + dp_F around each sample and must give that
 particle the same acceleration as the full GPU run.
 
 The plate of the 3D dam break (354k solid particles, the streamed sub-step
-passes over 173 blocks) is checked the same way: within one acoustic step a
+passes on 1,800 lattice blocks) is checked the same way: within one acoustic step a
 solid particle's state depends on the solid within 4 h_S per sub-step (its
 neighbours' stress, which depends on their neighbours' velocities), so after
 kappa sub-steps on the solid within (4 kappa + 2) h_S, and on correct
@@ -131,8 +131,10 @@ def test_dam_break_3d_sampled_first_step(gpu):
     note(f"3D dam break full size: {nf} fluid, {ns} solid")
     sim = sph.Simulation(sc)
     # the plate's reference configuration is its lattice: the streamed solid
-    # passes walk the compact table
-    assert sim.solid_table()["compact"] == 1
+    # passes run on lattice blocks (13 x 200 x 136 cells with the clamp: 4 x
+    # 50 x 9 blocks of 4 x 4 x 16)
+    tab = sim.solid_table()
+    assert tab["compact"] == 1 and tab["lattice_blocks"] == 1800, tab
     assert not sim.solid_register_resident()
     vs, pstar = plate_bump(sc)
     assert pstar > 0.7 * ns
@@ -208,3 +210,34 @@ def test_dam_break_3d_sampled_first_step(gpu):
          ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for name, e in errs.items():
         assert e <= 1e-4, (name, e)
+
+
+def test_dam_break_3d_lattice_blocks_match_table(gpu):
+    # The streamed solid passes on lattice blocks and on the compact table sum
+    # the same pairs, in class order and in table order: with a velocity bump
+    # in the plate, over three acoustic steps, the whole plate's state agrees
+    # to the FP32 rounding of those sums.
+    sc = scenes.dam_break_plate_3d(seed=1)
+    vs, _ = plate_bump(sc)
+    out = {}
+    for blocks in (0, -1):
+        note(f"3D dam break, solid_blocks {blocks}")
+        sim = sph.Simulation(sc, solid_blocks=blocks)
+        assert (sim.solid_table()["lattice_blocks"] > 0) == (blocks == 0)
+        sim.write(sph.S_V, vs)
+        for _ in range(3):
+            sim.step()
+        out[blocks] = {name: sim.read(f) for f, name in SOLID_FIELDS}
+        out[blocks]["kappa"] = sim.scalars()["kappa"]
+        sim.sync()
+        sim.close()
+    assert out[0]["kappa"] == out[-1]["kappa"] > 1
+    errs = {}
+    for _, name in SOLID_FIELDS:
+        g, r = out[0][name], out[-1][name]
+        if name == "F":
+            g, r = g - np.eye(3), r - np.eye(3)
+        errs[name] = np.abs(g - r).max() / np.abs(r).max()
+    note("3D plate, lattice blocks against the table: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for name, e in errs.items():
+        assert e <= 1e-5, (name, e)
