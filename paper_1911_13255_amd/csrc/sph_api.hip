@@ -941,13 +941,16 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
     std::vector<int> cnt(P.ns);
     HIPCHK_INIT(hipMemcpy(g.data(), D.s_gcls, sizeof(float4) * kNbrClasses, hipMemcpyDeviceToHost));
     HIPCHK_INIT(hipMemcpy(cnt.data(), D.s_cnt, sizeof(int) * P.ns, hipMemcpyDeviceToHost));
-    std::vector<int2> cls;
+    std::vector<float4> cls;
     std::vector<std::array<int, 3>> off;
     for (int c = 0; c < 125; ++c) {
       if (g[c].x == 0.0f && g[c].y == 0.0f && g[c].z == 0.0f) continue;
       const int o[3] = {c / 25 - 2, (c / 5) % 5 - 2, c % 5 - 2};
       const int q[3] = {o[P.lat_axis[0]], o[P.lat_axis[1]], o[P.lat_axis[2]]};
-      cls.push_back(make_int2(q[1] * kLatRow + q[0] * kLatH2 + q[2], c));
+      const int shift = q[1] * kLatRow + q[0] * kLatH2 + q[2];
+      float sf;
+      std::memcpy(&sf, &shift, sizeof sf);
+      cls.push_back(make_float4(g[c].x, g[c].y, g[c].z, sf));
       off.push_back({q[0], q[1], q[2]});
     }
     bool ok = !cls.empty();
@@ -990,7 +993,7 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
           hipMemcpy(D.lat_scene, P.lat_scene.data(), sizeof(int4) * P.lat_scene.size(), hipMemcpyHostToDevice));
       HIPCHK_INIT(
           hipMemcpy(D.lat_blocks, P.lat_blocks.data(), sizeof(int4) * P.lat_blocks.size(), hipMemcpyHostToDevice));
-      HIPCHK_INIT(hipMemcpy(D.lat_cls, cls.data(), sizeof(int2) * cls.size(), hipMemcpyHostToDevice));
+      HIPCHK_INIT(hipMemcpy(D.lat_cls, cls.data(), sizeof(float4) * cls.size(), hipMemcpyHostToDevice));
       D.lat_ncls = (int)cls.size();
       D.lat_nblocks = (int)P.lat_blocks.size();
     }

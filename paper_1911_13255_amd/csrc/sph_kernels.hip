@@ -2308,28 +2308,53 @@ __device__ __forceinline__ void solid_momentum_own(const Dev &D, int a, double *
   }
 }
 
+// Own state of free particle a that the momentum update reads besides its
+// P B: the fluid force, v and the step's dv.
+struct MomOwn {
+  float fF[3];
+  double v[3], dv[3];
+};
+template <int DIM>
+__device__ __forceinline__ void solid_momentum_load(const Dev &D, int a, MomOwn &o) {
+  const int NS = D.ns;
+  for (int k = 0; k < DIM; ++k) {
+    o.fF[k] = D.s_fF[k * NS + a];
+    o.v[k] = D.s_v[k * NS + a];
+    o.dv[k] = D.s_dv[k * NS + a];
+  }
+}
+
+// Acceleration, velocity and velocity record (slot r) of free particle a
+// from the own term acc and the FP32 neighbour sum accn.
+template <int DIM>
+__device__ __forceinline__ void solid_momentum_finish(const Dev &D, const ScenePar &P, const SceneState &S, int a,
+                                                      int r, const double *acc, const float *accn, const MomOwn &o) {
+  const int NS = D.ns;
+  const double del = S.dt_ac / S.kappa;
+  const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
+  double vn[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < DIM; ++k) {
+    double ak = ((double)P.Vs * (acc[k] + (double)accn[k]) + (double)o.fF[k]) * m_inv + (double)P.g[k];
+    D.s_a[k * NS + a] = (float)ak;
+    double dv = del * ak;
+    vn[k] = o.v[k] + dv;
+    D.s_v[k * NS + a] = vn[k];
+    D.s_dv[k * NS + a] = o.dv[k] + dv;
+  }
+  D.s_vf[r] = make_float4((float)vn[0], (float)vn[1], (float)vn[2], 1.0f);
+}
+
 // Momentum and velocity of free particle a in the current sub-step, its
 // velocity record at slot r; acc holds the own term and walk(accn) adds sum_b
 // P_b B_b g_ab over a's reference neighbours in FP32.
 template <int DIM, class Walk>
 __device__ __forceinline__ void solid_momentum_at(const Dev &D, const ScenePar &P, const SceneState &S, int a, int r,
-                                                  double *acc, Walk walk) {
-  const int NS = D.ns;
-  const double del = S.dt_ac / S.kappa;
+                                                  const double *acc, Walk walk) {
   float accn[3] = {0.0f, 0.0f, 0.0f};
   walk(accn);
-  for (int i = 0; i < DIM; ++i) acc[i] += (double)accn[i];
-  const double m_inv = 1.0 / ((double)P.rho0s * (double)P.Vs);
-  double vn[3] = {0.0, 0.0, 0.0};
-  for (int k = 0; k < DIM; ++k) {
-    double ak = ((double)P.Vs * acc[k] + (double)D.s_fF[k * NS + a]) * m_inv + (double)P.g[k];
-    D.s_a[k * NS + a] = (float)ak;
-    double dv = del * ak;
-    vn[k] = D.s_v[k * NS + a] + dv;
-    D.s_v[k * NS + a] = vn[k];
-    D.s_dv[k * NS + a] += dv;
-  }
-  D.s_vf[r] = make_float4((float)vn[0], (float)vn[1], (float)vn[2], 1.0f);
+  MomOwn o;
+  solid_momentum_load<DIM>(D, a, o);
+  solid_momentum_finish<DIM>(D, P, S, a, r, acc, accn, o);
 }
 
 // Deformation rate of free particle a with the new velocity and second half
@@ -2338,11 +2363,20 @@ __device__ __forceinline__ void solid_momentum_at(const Dev &D, const ScenePar &
 // over a's reference neighbours in FP32: the neighbours' v as one FP32
 // record each, the differences v_b - v_a taken between FP32-rounded values
 // (so a rigid translation still gives exactly zero).
-template <int DIM, class Walk>
+// kPre: B and H loaded before the walk.
+template <int DIM, bool kPre = false, class Walk>
 __device__ __forceinline__ void solid_rate_at(const Dev &D, const ScenePar &P, SceneState &S, int a, int r, int sub,
                                               Walk walk) {
   const int NS = D.ns;
   const double hd = 0.5 * S.dt_ac / S.kappa;
+  double H[9], B[9];
+  auto load = [&]() {
+    for (int k = 0; k < DIM * DIM; ++k) {
+      B[k] = D.s_B[k * NS + a];
+      H[k] = D.s_H[k * NS + a];
+    }
+  };
+  if (kPre) load();
   float Gn[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   walk(Gn);
   double va[3] = {0.0, 0.0, 0.0};
@@ -2354,11 +2388,7 @@ __device__ __forceinline__ void solid_rate_at(const Dev &D, const ScenePar &P, S
   // arithmetic as solid_first_half, without reading back what was just
   // written)
   const bool more = sub + 1 < S.kappa;
-  double H[9], B[9];
-  for (int k = 0; k < DIM * DIM; ++k) {
-    B[k] = D.s_B[k * NS + a];
-    H[k] = D.s_H[k * NS + a];
-  }
+  if (!kPre) load();
   for (int i = 0; i < DIM; ++i)
     for (int j = 0; j < DIM; ++j) {
       double sum = 0.0;
@@ -2526,9 +2556,11 @@ __device__ __forceinline__ int lat_own(const int4 &L, const int4 &blk, int &pos)
   return in ? L.x + (c0 * L.z + c1) * L.w + c2 : -1;
 }
 
-// Momentum pass on lattice blocks: the halo's FP32 P B in LDS.
+// Momentum pass on lattice blocks: the halo's FP32 P B in LDS one row of
+// three components at a time (17 KB, so that LDS admits eight workgroups per
+// CU; all nine at once held it to three).
 __global__ void __launch_bounds__(kLatThreads) k_solid_momentum_lat(Dev D, int sub) {
-  __shared__ float pb[9 * kLatLds];
+  __shared__ float pb[3 * kLatLds];
   const int bi = lat_block(D);
   if (bi < 0) return;
   const int4 blk = D.lat_blocks[bi];
@@ -2540,29 +2572,39 @@ __global__ void __launch_bounds__(kLatThreads) k_solid_momentum_lat(Dev D, int s
   const int cell = lat_own(L, blk, pos);
   const int a = cell >= 0 ? D.lat_grid[cell] : -1;
   const bool act = a >= 0 && a - P.s_begin < P.s_count - P.s_nclamp;
-  // the own term's loads in flight with the staging
+  // the own term's loads in flight with the staging (the rest of the own
+  // state loaded there too measured slower)
   double acc[3] = {0.0, 0.0, 0.0};
   if (act) solid_momentum_own<3>(D, a, acc);
   const size_t NC = D.lat_ncells;
-  lat_stage(L, blk, [&](int c, int l) {
+  float accr[3] = {0.0f, 0.0f, 0.0f};
+  for (int i = 0; i < 3; ++i) {
+    if (i > 0) __syncthreads();
+    lat_stage(L, blk, [&](int c, int l) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) pb[k * kLatLds + l] = c >= 0 ? D.s_PBf[k * NC + c] : 0.0f;
-  });
-  __syncthreads();
-  if (!act) return;
-  solid_momentum_at<3>(D, P, S, a, cell, acc, [&](float *accn) {
-    const float *r0 = pb + pos;
-    const int nc = D.lat_ncls;
+      for (int k = 0; k < 3; ++k) {
+        pb[k * kLatLds + l] = c >= 0 ? D.s_PBf[(3 * i + k) * NC + c] : 0.0f;
+      }
+    });
+    __syncthreads();
+    if (act) {
+      const float *r0 = pb + pos;
+      const int nc = D.lat_ncls;
+      float sum = 0.0f;
 #pragma unroll 4
-    for (int j = 0; j < nc; ++j) {
-      const int2 c = D.lat_cls[j];
-      const float4 g = D.s_gcls[c.y];
-      const float gv[3] = {g.x, g.y, g.z};
-      const float *r = r0 + c.x;
-      for (int i = 0; i < 3; ++i)
-        for (int k = 0; k < 3; ++k) accn[i] += r[(i * 3 + k) * kLatLds] * gv[k];
+      for (int j = 0; j < nc; ++j) {
+        const float4 g = D.lat_cls[j];
+        const float gv[3] = {g.x, g.y, g.z};
+        const float *r = r0 + __float_as_int(g.w);
+        for (int k = 0; k < 3; ++k) sum += r[k * kLatLds] * gv[k];
+      }
+      accr[i] = sum;
     }
-  });
+  }
+  if (!act) return;
+  MomOwn o;
+  solid_momentum_load<3>(D, a, o);
+  solid_momentum_finish<3>(D, P, S, a, cell, acc, accr, o);
 }
 
 // Rate pass on lattice blocks: the halo's FP32 v and presence weight (1 for
@@ -2588,17 +2630,17 @@ __global__ void __launch_bounds__(kLatThreads) k_solid_rate_lat(Dev D, int sub) 
   });
   __syncthreads();
   if (a < 0 || a - P.s_begin >= P.s_count - P.s_nclamp) return;
-  solid_rate_at<3>(D, P, S, a, cell, sub, [&](float *Gn) {
+  // B and H in flight during the LDS walk
+  solid_rate_at<3, true>(D, P, S, a, cell, sub, [&](float *Gn) {
     const float *r0 = vh + pos;
     // v_a rounded to FP32 is the particle's own record
     const float vaf[3] = {r0[0], r0[kLatLds], r0[2 * kLatLds]};
     const int nc = D.lat_ncls;
-#pragma unroll 4
+#pragma unroll 8
     for (int j = 0; j < nc; ++j) {
-      const int2 c = D.lat_cls[j];
-      const float4 g = D.s_gcls[c.y];
+      const float4 g = D.lat_cls[j];
       const float gv[3] = {g.x, g.y, g.z};
-      const float *r = r0 + c.x;
+      const float *r = r0 + __float_as_int(g.w);
       const float w = r[3 * kLatLds];
       for (int i = 0; i < 3; ++i) {
         // (v_b - v_a) exactly for a particle, zero for an empty cell

@@ -187,15 +187,16 @@ struct Dev {
   // scene's bounding box of cells, [(c0 * L1 + c1) * L2 + c2] from offset
   // lat_scene[s].x with (L0, L1, L2) in .y .z .w, to the particle there or -1;
   // lat_blocks[i] = (scene, first cell per axis) of a block of kLatB0 x kLatB1
-  // x kLatB2 cells holding a free particle; lat_cls[j] = (the offset's
-  // position shift in a block's halo, its class) for the lat_ncls classes of
-  // nonzero gradient.  lat_nblocks = 0: the passes walk the pair table.
+  // x kLatB2 cells holding a free particle; lat_cls[j] = (the class gradient
+  // in xyz, the offset's position shift in a block's LDS halo as int bits in
+  // w) for the lat_ncls classes of nonzero gradient: one uniform 16-byte load
+  // per class.  lat_nblocks = 0: the passes walk the pair table.
   // On lattice blocks s_PBf and s_vf are indexed by grid cell (lat_ncells of
   // them; empty cells hold zeros, a particle's velocity record has w = 1) and
   // lat_of[a] is particle a's cell.
   int *lat_grid, *lat_of;
   int4 *lat_scene, *lat_blocks;
-  int2 *lat_cls;
+  float4 *lat_cls;
   int lat_ncls, lat_nblocks, lat_ncells;
   float4 *s_vf;                    // v rounded to FP32, one 16-byte record per particle: what the streamed
                                    // rate pass gathers (free particles: written by the momentum pass of the
