@@ -525,8 +525,9 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.s_off0, 3 * ns);
   double **dvec[] = {&D.s_u, &D.s_v, &D.s_du, &D.s_dv};
   for (double **p : dvec) take(*p, 3 * ns);
-  double **dten[] = {&D.s_H, &D.s_dF, &D.s_B, &D.s_PB};
+  double **dten[] = {&D.s_H, &D.s_dF, &D.s_B};
   for (double **p : dten) take(*p, 9 * ns);
+  take(D.s_PBg, 3 * ns);
   take(D.s_PBf, 9 * std::max(ns, P.lat_grid.size()));
   take(D.s_vf, std::max(ns, P.lat_grid.size()));
   take(D.s_nbc, P.dim == 3 ? (size_t)P.maxn * ns : 1);

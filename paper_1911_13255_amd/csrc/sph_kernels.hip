@@ -283,10 +283,8 @@ __global__ void k_init_solid(Dev D, int s, const double *x, const double *v, int
     D.s_H[k * NS + a] = 0.0;
     D.s_dF[k * NS + a] = 0.0;
   }
-  for (int k = 0; k < 9; ++k) {
-    D.s_PB[pb_at(D, a, k)] = 0.0;
-    D.s_PBf[pb_at(D, a, k)] = 0.0f;
-  }
+  for (int k = 0; k < 3; ++k) D.s_PBg[k * NS + a] = 0.0;
+  for (int k = 0; k < 9; ++k) D.s_PBf[pb_at(D, a, k)] = 0.0f;
   D.s_bslot[a] = -1;
   D.s_blin[a] = 0;
 }
@@ -2248,6 +2246,21 @@ __global__ void k_solid_dt_close(Dev D, int next) {
 }
 
 // First half of a sub-step for particle a (own state only), and its stress.
+// Particle a's stress for the momentum pass: the own term P_a B_a sum_b g_ab
+// in FP64 and P_a B_a in FP32 at record slot r (what the neighbours read).
+template <int DIM>
+__device__ __forceinline__ void solid_stress_store(const Dev &D, int a, int r, const double *PB) {
+  const int NS = D.ns;
+  double gs[3];
+  for (int j = 0; j < DIM; ++j) gs[j] = D.s_gsum[j * NS + a];
+  for (int i = 0; i < DIM; ++i) {
+    double own = 0.0;
+    for (int j = 0; j < DIM; ++j) own += PB[i * DIM + j] * gs[j];
+    D.s_PBg[i * NS + a] = own;
+  }
+  for (int k = 0; k < DIM * DIM; ++k) D.s_PBf[pbf_at(D, r, k)] = (float)PB[k];
+}
+
 template <int DIM>
 __device__ __forceinline__ void solid_first_half(const Dev &D, const ScenePar &P, SceneState &S, int a, double hd) {
   const int NS = D.ns;
@@ -2267,11 +2280,7 @@ __device__ __forceinline__ void solid_first_half(const Dev &D, const ScenePar &P
   double J;
   solid_PB<DIM, double>(P.material, H, B, (double)P.mu, (double)P.lam, PB, J);
   if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
-  const int r = rec_of(D, a);
-  for (int k = 0; k < DIM * DIM; ++k) {
-    D.s_PB[pb_at(D, a, k)] = PB[k];
-    D.s_PBf[pbf_at(D, r, k)] = (float)PB[k];
-  }
+  solid_stress_store<DIM>(D, a, rec_of(D, a), PB);
 }
 
 // First half of sub-step 0 (clamp particles: zero stress).
@@ -2284,11 +2293,9 @@ __global__ void __launch_bounds__(256) k_solid_first(Dev D) {
   SceneState &S = D.st[s];
   if (a - P.s_begin >= P.s_count - P.s_nclamp) {
     const int r = rec_of(D, a);
-    for (int k = 0; k < DIM * DIM; ++k) {
-      D.s_PB[pb_at(D, a, k)] = 0.0;
-      D.s_PBf[pbf_at(D, r, k)] = 0.0f;
-    }
     const int NS = D.ns;
+    for (int k = 0; k < DIM; ++k) D.s_PBg[k * NS + a] = 0.0;
+    for (int k = 0; k < DIM * DIM; ++k) D.s_PBf[pbf_at(D, r, k)] = 0.0f;
     D.s_vf[r] = make_float4((float)D.s_v[a], (float)D.s_v[NS + a], DIM == 3 ? (float)D.s_v[2 * NS + a] : 0.0f, 1.0f);
     return;
   }
@@ -2302,10 +2309,7 @@ __global__ void __launch_bounds__(256) k_solid_first(Dev D) {
 template <int DIM>
 __device__ __forceinline__ void solid_momentum_own(const Dev &D, int a, double *acc) {
   const int NS = D.ns;
-  for (int i = 0; i < DIM; ++i) {
-    acc[i] = 0.0;
-    for (int j = 0; j < DIM; ++j) acc[i] += D.s_PB[pb_at(D, a, i * DIM + j)] * D.s_gsum[j * NS + a];
-  }
+  for (int i = 0; i < DIM; ++i) acc[i] = D.s_PBg[i * NS + a];
 }
 
 // Own state of free particle a that the momentum update reads besides its
@@ -2408,10 +2412,7 @@ __device__ __forceinline__ void solid_rate_at(const Dev &D, const ScenePar &P, S
     double PB[9], J;
     solid_PB<DIM, double>(P.material, H, B, (double)P.mu, (double)P.lam, PB, J);
     if (!(J > 0.0)) atomicOr(&S.err, (int)ERR_JACOBIAN);
-    for (int k = 0; k < DIM * DIM; ++k) {
-      D.s_PB[pb_at(D, a, k)] = PB[k];
-      D.s_PBf[pbf_at(D, r, k)] = (float)PB[k];
-    }
+    solid_stress_store<DIM>(D, a, r, PB);
   }
 }
 

@@ -172,7 +172,8 @@ struct Dev {
   double *s_off0;  // reference offset from the reference cell, FP64
   double *s_u, *s_v, *s_du, *s_dv;  // integration state in FP64 (displacement, velocity, step increments)
   double *s_H, *s_dF, *s_B;        // H = F - I, dF/dt, B in FP64 (d*d components)
-  double *s_PB;                    // P B in FP64, component-major [k * ns + a] (9 components allocated)
+  double *s_PBg;                   // P_a B_a sum_b g_ab in FP64, [k * ns + a]: the own term of the momentum
+                                   // sum, formed where P B is (the stress pass), read by the momentum pass
   float *s_PBf;                    // the same rounded to FP32: what the streamed momentum pass gathers
   // compact reference table of lattice reference configurations (3D): per
   // pair the neighbour's index << 7 | its offset class, [q * ns + a]; the
