@@ -627,8 +627,10 @@ void enqueue_solid_reg(sph_ctx *ctx, bool step_end, bool alone = true) {
 }
 
 // step_end as above; it applies to the register-resident form only (the
-// streamed passes leave the step end to its own launch)
-int enqueue_solid(sph_ctx *ctx, bool step_end) {
+// streamed passes leave the step end to its own launch).  maxima: the
+// streamed averaging pass also reduces the solid maxima that
+// launch_solid_dt_next then takes.
+int enqueue_solid(sph_ctx *ctx, bool step_end, bool maxima = false) {
   if (ctx->cfg.solid_ppt > 0) {
     enqueue_solid_reg(ctx, step_end);
   } else if (ctx->D.ns > 0) {
@@ -657,7 +659,7 @@ int enqueue_solid(sph_ctx *ctx, bool step_end) {
     }
     launch_solid_first(ctx->D, ctx->stream);
     for (int sub = 0; sub < kmax; ++sub) launch_solid_pass(ctx->D, sub, ctx->stream);
-    launch_solid_average(ctx->D, kmax, ctx->stream);
+    launch_solid_average(ctx->D, kmax, maxima, ctx->stream);
   } else {
     launch_solid_dt(ctx->D, ctx->stream);
   }
@@ -684,10 +686,11 @@ int enqueue_step(sph_ctx *ctx, bool fork) {
     return check_launch(ctx, "acoustic step");
   }
   if (!launch_fluid_continuity(ctx->D, ctx->cfg, ctx->stream, true)) launch_couple(ctx->D, ctx->cfg, ctx->stream);
-  int rc = enqueue_solid(ctx, true);
+  const bool next_kappa = ctx->cfg.solid_ppt == 0 && ctx->D.ns > 0 && ctx->st_host;
+  int rc = enqueue_solid(ctx, true, next_kappa);
   if (rc != SPH_OK) return rc;
   launch_step_end(ctx->D, ctx->stream, ctx->cfg.solid_ppt > 0);
-  if (ctx->cfg.solid_ppt == 0 && ctx->D.ns > 0 && ctx->st_host) {
+  if (next_kappa) {
     // the next step's kappa depends only on the state this close leaves
     launch_solid_dt_next(ctx->D, ctx->stream);
     if (hipMemcpyAsync(ctx->st_host, ctx->D.st, sizeof(SceneState) * ctx->n_scenes, hipMemcpyDeviceToHost,

@@ -123,7 +123,8 @@ void launch_solid_dt_adopt(const Dev &D, hipStream_t st);
 void launch_solid_first(const Dev &D, hipStream_t st);
 void launch_solid_pass(const Dev &D, int sub, hipStream_t st);
 // launched: sub-step passes launched this step (scenes with a larger kappa are flagged)
-void launch_solid_average(const Dev &D, int launched, hipStream_t st);
+// maxima: also reduce the free solid's max |v| and |a| for launch_solid_dt_next
+void launch_solid_average(const Dev &D, int launched, bool maxima, hipStream_t st);
 void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t st);
 void launch_write(const Dev &D, int s, int field, int n, const double *in, hipStream_t st);
 // the FP64 reductions of scene s over nblocks blocks: block partials in

@@ -2163,17 +2163,10 @@ __global__ void __launch_bounds__(1024) k_step_close_scan(Dev D) {
 // Solid time step and kappa of each scene: max |v| and |a| of the free solid
 // over all solid particles (one atomic per block and scene), the step
 // increments cleared; then k_solid_dt_close, one thread per scene.
-__global__ void __launch_bounds__(256) k_solid_dt_reduce(Dev D, int next) {
-  __shared__ float shv[16], sha[16];
-  const int dim = D.dim, NS = D.ns;
-  const int span = blockDim.x * kReduceItems;
-  const int a0 = blockIdx.x * span, a1 = min(NS, a0 + span);
-  for (int a = a0 + threadIdx.x; a < a1 && !next; a += blockDim.x) {
-    for (int k = 0; k < dim; ++k) {
-      D.s_du[k * NS + a] = 0.0;
-      D.s_dv[k * NS + a] = 0.0;
-    }
-  }
+// max |v| and |a| of the free solid particles a0 .. a1 - 1 per scene into
+// smax_v and smax_a (one atomic per block and scene)
+__device__ __forceinline__ void solid_block_maxima(const Dev &D, int dim, int a0, int a1, float *shv, float *sha) {
+  const int NS = D.ns;
   const int s0 = D.s_scene[a0], s1 = D.s_scene[a1 - 1];
   auto fmx = [](float x, float y) { return fmaxf(x, y); };
   for (int s = s0; s <= s1; ++s) {
@@ -2199,6 +2192,20 @@ __global__ void __launch_bounds__(256) k_solid_dt_reduce(Dev D, int next) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_solid_dt_reduce(Dev D) {
+  __shared__ float shv[16], sha[16];
+  const int dim = D.dim, NS = D.ns;
+  const int span = blockDim.x * kReduceItems;
+  const int a0 = blockIdx.x * span, a1 = min(NS, a0 + span);
+  for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+    for (int k = 0; k < dim; ++k) {
+      D.s_du[k * NS + a] = 0.0;
+      D.s_dv[k * NS + a] = 0.0;
+    }
+  }
+  solid_block_maxima(D, dim, a0, a1, shv, sha);
+}
+
 // dt_S = cfl_s min(h_S / (c_S + |v|max), sqrt(h_S / |a|max)), kappa =
 // floor(dt_ac / dt_S) + 1 (bounded: a collapsed solid step is reported).
 __device__ __forceinline__ void solid_kappa(const ScenePar &P, SceneState &S, float vmax, float amax, double dt_ac,
@@ -2214,9 +2221,11 @@ __device__ __forceinline__ void solid_kappa(const ScenePar &P, SceneState &S, fl
   }
 }
 
-// mode 0: kappa and dt_S of the step starting now; 1: of the next step (at
-// this step's end, for the host); 2: the step starting now adopts what mode 1
-// computed from the same solid state (nothing changes the solid in between)
+// mode 0: kappa and dt_S of the step starting now (maxima from
+// k_solid_dt_reduce); 1: of the next step (at this step's end, for the host;
+// maxima from the step's k_solid_average); 2: the step starting now adopts
+// what mode 1 computed from the same solid state (nothing changes the solid
+// in between)
 __global__ void k_solid_dt_close(Dev D, int next) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= D.n_scenes) return;
@@ -2652,26 +2661,33 @@ __global__ void __launch_bounds__(kLatThreads) k_solid_rate_lat(Dev D, int sub) 
   });
 }
 
-// Time averages over the acoustic step.
+// Time averages over the acoustic step, kReduceItems particles per thread.
+// maxima: also the free solid's max |v| and |a| after the step's last
+// sub-step (as k_solid_dt_reduce takes them, for the next step's kappa; one
+// atomic per block and scene).
 template <int DIM>
-__global__ void __launch_bounds__(256) k_solid_average(Dev D, int launched) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= D.ns) return;
-  int s = D.s_scene[a];
-  const ScenePar &P = D.par[s];
-  SceneState &S = D.st[s];
-  if (a == P.s_begin && S.kappa > launched) atomicOr(&S.err, (int)ERR_KAPPA);
-  if (a - P.s_begin >= P.s_count - P.s_nclamp) return;
+__global__ void __launch_bounds__(256) k_solid_average(Dev D, int launched, int maxima) {
+  __shared__ float shv[16], sha[16];
   const int NS = D.ns;
-  const double inv_dt = 1.0 / S.dt_ac;
-  bool bad = false;
-  for (int k = 0; k < DIM; ++k) {
-    float vb = (float)(D.s_du[k * NS + a] * inv_dt), ab = (float)(D.s_dv[k * NS + a] * inv_dt);
-    D.s_vbar[k * NS + a] = vb;
-    D.s_abar[k * NS + a] = ab;
-    bad |= !isfinite(vb) || !isfinite(ab);
+  const int span = blockDim.x * kReduceItems;
+  const int a0 = blockIdx.x * span, a1 = min(NS, a0 + span);
+  for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+    const int s = D.s_scene[a];
+    const ScenePar &P = D.par[s];
+    SceneState &S = D.st[s];
+    if (a == P.s_begin && S.kappa > launched) atomicOr(&S.err, (int)ERR_KAPPA);
+    if (a - P.s_begin >= P.s_count - P.s_nclamp) continue;
+    const double inv_dt = 1.0 / S.dt_ac;
+    bool bad = false;
+    for (int k = 0; k < DIM; ++k) {
+      float vb = (float)(D.s_du[k * NS + a] * inv_dt), ab = (float)(D.s_dv[k * NS + a] * inv_dt);
+      D.s_vbar[k * NS + a] = vb;
+      D.s_abar[k * NS + a] = ab;
+      bad |= !isfinite(vb) || !isfinite(ab);
+    }
+    if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
   }
-  if (bad) atomicOr(&S.err, (int)ERR_NAN_SOLID);
+  if (maxima) solid_block_maxima(D, DIM, a0, a1, shv, sha);
 }
 
 // Hand-over of free solid particle a's step results to its boundary particle
@@ -4156,7 +4172,7 @@ void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_
 void launch_solid_dt(const Dev &D, hipStream_t st) {
   if (D.ns > 0)
     hipLaunchKernelGGL(k_solid_dt_reduce, dim3((D.ns + 256 * kReduceItems - 1) / (256 * kReduceItems)), dim3(256), 0,
-                       st, D, 0);
+                       st, D);
   hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D, 0);
 }
 
@@ -4165,9 +4181,7 @@ void launch_solid_dt_adopt(const Dev &D, hipStream_t st) {
 }
 
 void launch_solid_dt_next(const Dev &D, hipStream_t st) {
-  if (D.ns > 0)
-    hipLaunchKernelGGL(k_solid_dt_reduce, dim3((D.ns + 256 * kReduceItems - 1) / (256 * kReduceItems)), dim3(256), 0,
-                       st, D, 1);
+  // the maxima come from the step's k_solid_average (maxima on)
   hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D, 1);
 }
 
@@ -4187,8 +4201,10 @@ void launch_solid_pass(const Dev &D, int sub, hipStream_t st) {
   LAUNCH_DIM(D.dim, k_solid_rate, grid_for(D.ns, 256), dim3(256), st, D, sub);
 }
 
-void launch_solid_average(const Dev &D, int launched, hipStream_t st) {
-  if (D.ns > 0) LAUNCH_DIM(D.dim, k_solid_average, grid_for(D.ns, 256), dim3(256), st, D, launched);
+void launch_solid_average(const Dev &D, int launched, bool maxima, hipStream_t st) {
+  if (D.ns > 0)
+    LAUNCH_DIM(D.dim, k_solid_average, dim3((D.ns + 256 * kReduceItems - 1) / (256 * kReduceItems)), dim3(256), st,
+               D, launched, maxima ? 1 : 0);
 }
 
 void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t st) {
