@@ -635,12 +635,13 @@ int enqueue_solid(sph_ctx *ctx, bool step_end, bool maxima = false) {
     enqueue_solid_reg(ctx, step_end);
   } else if (ctx->D.ns > 0) {
     int kmax = 0;
+    bool adopt = false;
     if (ctx->kappa_ready) {
       // kappa as the end of the step before computed it from the same state
       // (the averaging pass flags a scene whose kappa exceeds the passes):
-      // the scenes adopt it, and k_solid_first starts the step's increments
+      // k_solid_first adopts it and starts the step's increments
       ctx->kappa_ready = 0;
-      launch_solid_dt_adopt(ctx->D, ctx->stream);
+      adopt = true;
       if (hipEventSynchronize(ctx->ev_kappa) != hipSuccess) {
         std::snprintf(ctx->err, sizeof ctx->err, "solid_substeps: kappa read-back failed");
         return SPH_E_HIP;
@@ -657,7 +658,7 @@ int enqueue_solid(sph_ctx *ctx, bool step_end, bool maxima = false) {
       }
       for (const SceneState &x : st) kmax = std::max(kmax, x.kappa);
     }
-    launch_solid_first(ctx->D, ctx->stream);
+    launch_solid_first(ctx->D, adopt, ctx->stream);
     for (int sub = 0; sub < kmax; ++sub) launch_solid_pass(ctx->D, sub, ctx->stream);
     launch_solid_average(ctx->D, kmax, maxima, ctx->stream);
   } else {
@@ -689,10 +690,9 @@ int enqueue_step(sph_ctx *ctx, bool fork) {
   const bool next_kappa = ctx->cfg.solid_ppt == 0 && ctx->D.ns > 0 && ctx->st_host;
   int rc = enqueue_solid(ctx, true, next_kappa);
   if (rc != SPH_OK) return rc;
-  launch_step_end(ctx->D, ctx->stream, ctx->cfg.solid_ppt > 0);
+  // the next step's kappa depends only on the state this close leaves
+  launch_step_end(ctx->D, ctx->stream, ctx->cfg.solid_ppt > 0, next_kappa);
   if (next_kappa) {
-    // the next step's kappa depends only on the state this close leaves
-    launch_solid_dt_next(ctx->D, ctx->stream);
     if (hipMemcpyAsync(ctx->st_host, ctx->D.st, sizeof(SceneState) * ctx->n_scenes, hipMemcpyDeviceToHost,
                        ctx->stream) != hipSuccess ||
         hipEventRecord(ctx->ev_kappa, ctx->stream) != hipSuccess)

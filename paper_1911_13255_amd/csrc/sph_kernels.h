@@ -103,8 +103,10 @@ void launch_couple(const Dev &D, const LaunchCfg &cfg, hipStream_t st);
 // parts: scenes split over the workgroups of D.s_parts (nothing else may run
 // beside the launch: its workgroups wait for each other)
 void launch_solid(const Dev &D, const LaunchCfg &cfg, hipStream_t st, bool step_end, bool parts = false);
-// reduced: the solid launch already did the step-end reduction's work
-void launch_step_end(const Dev &D, hipStream_t st, bool reduced);
+// reduced: the solid launch already did the step-end reduction's work;
+// next_kappa: the close also evaluates the streamed solid's next kappa from
+// the maxima of launch_solid_average (maxima on)
+void launch_step_end(const Dev &D, hipStream_t st, bool reduced, bool next_kappa = false);
 void launch_sur_features(const Dev &D, const float *stats, float *x, hipStream_t st);
 void launch_sur_targets(const Dev &D, float *t, hipStream_t st);
 // the surrogate pass of a step, before the solid launch: each scene's mode,
@@ -114,16 +116,13 @@ void launch_sur_net(const Dev &D, const MlpDev &M, hipStream_t st);
 // allow the surrogate pass its dynamic LDS (once per process and device)
 hipError_t allow_sur_net_lds();
 void launch_solid_dt(const Dev &D, hipStream_t st);
-// the same reduction at a step's end, after its close, into kappa_next only
-// (the step increments and kappa stay untouched)
-void launch_solid_dt_next(const Dev &D, hipStream_t st);
-// the step starting now takes kappa and dt_S from launch_solid_dt_next at the
-// end of the step before (the solid state has not changed since)
-void launch_solid_dt_adopt(const Dev &D, hipStream_t st);
-void launch_solid_first(const Dev &D, hipStream_t st);
+// adopt: the step starting now takes kappa and dt_S from the evaluation at
+// the end of the step before (launch_step_end with next_kappa; the solid
+// state has not changed since)
+void launch_solid_first(const Dev &D, bool adopt, hipStream_t st);
 void launch_solid_pass(const Dev &D, int sub, hipStream_t st);
 // launched: sub-step passes launched this step (scenes with a larger kappa are flagged)
-// maxima: also reduce the free solid's max |v| and |a| for launch_solid_dt_next
+// maxima: also reduce the free solid's max |v| and |a| for the next kappa
 void launch_solid_average(const Dev &D, int launched, bool maxima, hipStream_t st);
 void launch_read(const Dev &D, int s, int field, int n, double *out, hipStream_t st);
 void launch_write(const Dev &D, int s, int field, int n, const double *in, hipStream_t st);

@@ -2082,7 +2082,12 @@ constexpr int KAPPA_MAX = 4096;
 // the interaction counters.
 // vmax: the step's max fluid speed (float bits); counts: the pair counts
 // after a rebuild (null: take the accumulators the reduction kernel filled).
-__device__ void close_scene(const Dev &D, int s, unsigned vmax_bits, const unsigned long long *counts) {
+__device__ void solid_kappa_next(const Dev &D, int s);
+
+// next_kappa: then also the next step's kappa of the streamed solid
+// (solid_kappa_next).
+__device__ void close_scene(const Dev &D, int s, unsigned vmax_bits, const unsigned long long *counts,
+                            bool next_kappa = false) {
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
   const bool rebuilt = S.need_rebuild != 0;  // the rebuild kernels of this step ran
@@ -2126,21 +2131,22 @@ __device__ void close_scene(const Dev &D, int s, unsigned vmax_bits, const unsig
     dt = fmin(dt, solid_dt(P, __uint_as_float(S.send_v), __uint_as_float(S.send_a)));
   S.send_v = S.send_a = 0u;
   S.dt_ac = dt;
+  if (next_kappa) solid_kappa_next(D, s);
 }
 
-__global__ void k_step_close(Dev D) {
+__global__ void k_step_close(Dev D, int next_kappa) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= D.n_scenes) return;
-  close_scene(D, s, D.st[s].vmax_next, nullptr);
+  close_scene(D, s, D.st[s].vmax_next, nullptr, next_kappa != 0);
 }
 
 // The same close, one thread per scene, then (all cells in one tile) the
 // cell scan of the rebuilds it has just set, whose particles the step-end
 // reduction binned: the next step starts with the scatter.
-__global__ void __launch_bounds__(1024) k_step_close_scan(Dev D) {
+__global__ void __launch_bounds__(1024) k_step_close_scan(Dev D, int next_kappa) {
   __shared__ TileLds L;
   const int s = threadIdx.x;
-  if (s < D.n_scenes) close_scene(D, s, D.st[s].vmax_next, nullptr);
+  if (s < D.n_scenes) close_scene(D, s, D.st[s].vmax_next, nullptr, next_kappa != 0);
   __syncthreads();
   scan_one_tile(D, L);
 }
@@ -2221,36 +2227,40 @@ __device__ __forceinline__ void solid_kappa(const ScenePar &P, SceneState &S, fl
   }
 }
 
-// mode 0: kappa and dt_S of the step starting now (maxima from
-// k_solid_dt_reduce); 1: of the next step (at this step's end, for the host;
-// maxima from the step's k_solid_average); 2: the step starting now adopts
-// what mode 1 computed from the same solid state (nothing changes the solid
-// in between)
-__global__ void k_solid_dt_close(Dev D, int next) {
+// The next step's kappa and dt_S of scene s at the end of a step, from the
+// solid maxima the step's averaging pass reduced and the next acoustic step;
+// the error bits are latched by the step that adopts this evaluation.
+__device__ void solid_kappa_next(const Dev &D, int s) {
+  SceneState &S = D.st[s];
+  int kap;
+  double dts;
+  const int err = S.err;
+  solid_kappa(D.par[s], S, __uint_as_float(S.smax_v), __uint_as_float(S.smax_a), S.dt_ac, kap, dts);
+  S.kappa_next_err = S.err & ~err;
+  S.err = err;
+  S.kappa_next = kap;
+  S.dt_s_next = dts;
+  S.smax_v = S.smax_a = 0u;
+}
+
+// The step starting now adopts that evaluation (nothing changes the solid in
+// between); atomic on the error word, which passes running beside may set.
+__device__ __forceinline__ void solid_kappa_adopt(SceneState &S) {
+  S.kappa = S.kappa_next;
+  S.dt_s = S.dt_s_next;
+  if (S.kappa_next_err) atomicOr(&S.err, S.kappa_next_err);
+}
+
+// kappa and dt_S of the step starting now, from k_solid_dt_reduce's maxima
+__global__ void k_solid_dt_close(Dev D) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= D.n_scenes) return;
   SceneState &S = D.st[s];
   int kap;
   double dts;
-  if (next == 2) {
-    S.kappa = S.kappa_next;
-    S.dt_s = S.dt_s_next;
-    S.err |= S.kappa_next_err;
-    return;
-  }
-  if (next) {
-    // the error bits are latched by the step that adopts this evaluation
-    const int err = S.err;
-    solid_kappa(D.par[s], S, __uint_as_float(S.smax_v), __uint_as_float(S.smax_a), S.dt_ac, kap, dts);
-    S.kappa_next_err = S.err & ~err;
-    S.err = err;
-    S.kappa_next = kap;
-    S.dt_s_next = dts;
-  } else {
-    solid_kappa(D.par[s], S, __uint_as_float(S.smax_v), __uint_as_float(S.smax_a), S.dt_ac, kap, dts);
-    S.dt_s = dts;
-    S.kappa = kap;
-  }
+  solid_kappa(D.par[s], S, __uint_as_float(S.smax_v), __uint_as_float(S.smax_a), S.dt_ac, kap, dts);
+  S.dt_s = dts;
+  S.kappa = kap;
   S.smax_v = S.smax_a = 0u;
 }
 
@@ -2292,14 +2302,20 @@ __device__ __forceinline__ void solid_first_half(const Dev &D, const ScenePar &P
   solid_stress_store<DIM>(D, a, rec_of(D, a), PB);
 }
 
-// First half of sub-step 0 (clamp particles: zero stress).
+// First half of sub-step 0 (clamp particles: zero stress).  adopt: the step
+// takes the kappa and dt_S that the step before evaluated at its end (its
+// leading threads adopt them for every scene; the particles read kappa_next,
+// which nothing here writes).
 template <int DIM>
-__global__ void __launch_bounds__(256) k_solid_first(Dev D) {
+__global__ void __launch_bounds__(256) k_solid_first(Dev D, int adopt) {
   int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (adopt)
+    for (int s = a; s < D.n_scenes; s += gridDim.x * blockDim.x) solid_kappa_adopt(D.st[s]);
   if (a >= D.ns) return;
   int s = D.s_scene[a];
   const ScenePar &P = D.par[s];
   SceneState &S = D.st[s];
+  const int kappa = adopt ? S.kappa_next : S.kappa;
   if (a - P.s_begin >= P.s_count - P.s_nclamp) {
     const int r = rec_of(D, a);
     const int NS = D.ns;
@@ -2308,7 +2324,7 @@ __global__ void __launch_bounds__(256) k_solid_first(Dev D) {
     D.s_vf[r] = make_float4((float)D.s_v[a], (float)D.s_v[NS + a], DIM == 3 ? (float)D.s_v[2 * NS + a] : 0.0f, 1.0f);
     return;
   }
-  solid_first_half<DIM>(D, P, S, a, 0.5 * S.dt_ac / S.kappa);
+  solid_first_half<DIM>(D, P, S, a, 0.5 * S.dt_ac / kappa);
 }
 
 // Momentum of free particle a: sum_b (P_a B_a + P_b B_b) g_ab = P_a B_a
@@ -4173,20 +4189,11 @@ void launch_solid_dt(const Dev &D, hipStream_t st) {
   if (D.ns > 0)
     hipLaunchKernelGGL(k_solid_dt_reduce, dim3((D.ns + 256 * kReduceItems - 1) / (256 * kReduceItems)), dim3(256), 0,
                        st, D);
-  hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D, 0);
+  hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
 }
 
-void launch_solid_dt_adopt(const Dev &D, hipStream_t st) {
-  hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D, 2);
-}
-
-void launch_solid_dt_next(const Dev &D, hipStream_t st) {
-  // the maxima come from the step's k_solid_average (maxima on)
-  hipLaunchKernelGGL(k_solid_dt_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D, 1);
-}
-
-void launch_solid_first(const Dev &D, hipStream_t st) {
-  if (D.ns > 0) LAUNCH_DIM(D.dim, k_solid_first, grid_for(D.ns, 256), dim3(256), st, D);
+void launch_solid_first(const Dev &D, bool adopt, hipStream_t st) {
+  if (D.ns > 0) LAUNCH_DIM(D.dim, k_solid_first, grid_for(D.ns, 256), dim3(256), st, D, adopt ? 1 : 0);
 }
 
 void launch_solid_pass(const Dev &D, int sub, hipStream_t st) {
@@ -4225,12 +4232,13 @@ hipError_t allow_sur_net_lds() {
                              (int)fwd_lds_bytes());
 }
 
-void launch_step_end(const Dev &D, hipStream_t st, bool reduced) {
+void launch_step_end(const Dev &D, hipStream_t st, bool reduced, bool next_kappa) {
   int fb = (D.nf + 256 * kReduceItems - 1) / (256 * kReduceItems), sb = (D.ns + 255) / 256;
   int bb = std::min((D.nf + D.nb + 255) / 256, kBinBlocksMax);
   if (!reduced && bb + fb + sb > 0) LAUNCH_DIM(D.dim, k_step_reduce, dim3(bb + fb + sb), dim3(256), st, D, bb, fb);
-  if (step_end_scan(D)) hipLaunchKernelGGL(k_step_close_scan, dim3(1), dim3(1024), 0, st, D);
-  else hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D);
+  const int nk = next_kappa ? 1 : 0;
+  if (step_end_scan(D)) hipLaunchKernelGGL(k_step_close_scan, dim3(1), dim3(1024), 0, st, D, nk);
+  else hipLaunchKernelGGL(k_step_close, dim3(nblk(D.n_scenes, 64)), dim3(64), 0, st, D, nk);
 }
 
 int solid_lds_bytes_per_particle(int dim) { return (solid_pb_record(dim) + dim) * (int)sizeof(double); }
