@@ -2553,20 +2553,29 @@ __device__ __forceinline__ int lat_block(const Dev &D) {
   return b < D.lat_nblocks ? b : -1;
 }
 
-// Stage rec(cell, lds) for every halo cell of block blk: cell its grid index
-// (-1 outside the scene's bounding box), lds its LDS position.
+// Halo cell q of this thread (cells threadIdx.x + q * kLatThreads) of block
+// blk: c its grid index (-1 outside the scene's bounding box), l its LDS
+// position.
+constexpr int kLatPer = kLatHalo / kLatThreads;
+static_assert(kLatHalo % kLatThreads == 0, "every thread stages kLatPer halo cells");
+__device__ __forceinline__ void lat_halo_cell(const int4 &L, const int4 &blk, int q, int &c, int &l) {
+  const int i = threadIdx.x + q * kLatThreads;
+  const int h0 = i / (kLatH1 * kLatH2), h12 = i - h0 * (kLatH1 * kLatH2);
+  const int h1 = h12 / kLatH2, h2 = h12 - h1 * kLatH2;
+  const int c0 = blk.y - kLatR + h0, c1 = blk.z - kLatR + h1, c2 = blk.w - kLatR + h2;
+  const bool in = (unsigned)c0 < (unsigned)L.y && (unsigned)c1 < (unsigned)L.z && (unsigned)c2 < (unsigned)L.w;
+  c = in ? L.x + (c0 * L.z + c1) * L.w + c2 : -1;
+  l = h1 * kLatRow + h0 * kLatH2 + h2;
+}
+
+// Stage rec(cell, lds) for every halo cell of block blk.
 template <class Rec>
 __device__ __forceinline__ void lat_stage(const int4 &L, const int4 &blk, Rec rec) {
-  constexpr int kPer = (kLatHalo + kLatThreads - 1) / kLatThreads;
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kLatThreads;
-    if (kLatHalo % kLatThreads != 0 && i >= kLatHalo) break;
-    const int h0 = i / (kLatH1 * kLatH2), h12 = i - h0 * (kLatH1 * kLatH2);
-    const int h1 = h12 / kLatH2, h2 = h12 - h1 * kLatH2;
-    const int c0 = blk.y - kLatR + h0, c1 = blk.z - kLatR + h1, c2 = blk.w - kLatR + h2;
-    const bool in = (unsigned)c0 < (unsigned)L.y && (unsigned)c1 < (unsigned)L.z && (unsigned)c2 < (unsigned)L.w;
-    rec(in ? L.x + (c0 * L.z + c1) * L.w + c2 : -1, h1 * kLatRow + h0 * kLatH2 + h2);
+  for (int q = 0; q < kLatPer; ++q) {
+    int c, l;
+    lat_halo_cell(L, blk, q, c, l);
+    rec(c, l);
   }
 }
 
@@ -2604,15 +2613,29 @@ __global__ void __launch_bounds__(kLatThreads) k_solid_momentum_lat(Dev D, int s
   if (act) solid_momentum_own<3>(D, a, acc);
   const size_t NC = D.lat_ncells;
   float accr[3] = {0.0f, 0.0f, 0.0f};
-  for (int i = 0; i < 3; ++i) {
-    if (i > 0) __syncthreads();
-    lat_stage(L, blk, [&](int c, int l) {
+  // row i + 1's halo loaded into registers while row i is walked
+  float stg[kLatPer][3];
+  auto fetch = [&](int i) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        pb[k * kLatLds + l] = c >= 0 ? D.s_PBf[(3 * i + k) * NC + c] : 0.0f;
-      }
-    });
+    for (int q = 0; q < kLatPer; ++q) {
+      int c, l;
+      lat_halo_cell(L, blk, q, c, l);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) stg[q][k] = c >= 0 ? D.s_PBf[(3 * i + k) * NC + c] : 0.0f;
+    }
+  };
+  fetch(0);
+  for (int i = 0; i < 3; ++i) {
+    if (i > 0) __syncthreads();  // row i - 1 walked
+#pragma unroll
+    for (int q = 0; q < kLatPer; ++q) {
+      int c, l;
+      lat_halo_cell(L, blk, q, c, l);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pb[k * kLatLds + l] = stg[q][k];
+    }
     __syncthreads();
+    if (i < 2) fetch(i + 1);
     if (act) {
       const float *r0 = pb + pos;
       const int nc = D.lat_ncls;
