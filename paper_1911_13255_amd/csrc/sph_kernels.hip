@@ -1557,17 +1557,18 @@ struct NbrRec {
 template <int LPP, typename E, typename Load, typename Body>
 __device__ __forceinline__ void walk_pairs(const E *lp, size_t lstride, int q, int n, Load &&load, Body &&body) {
   if (q >= n) return;
-  const E *p = lp;  // slot of the last entry read (kept at the last valid slot)
-  auto next = [&](int e) {  // entry e, the one after the last read
-    if (e < n) p += lstride;
-    return (unsigned)*p;
+  // this lane's slot m, or its last valid slot past the row's end (so every
+  // load reads an entry of the row)
+  const unsigned last = (unsigned)(n - 1 - q) / LPP, lsb = (unsigned)(lstride * sizeof(E));
+  const char *lb = reinterpret_cast<const char *>(lp);
+  auto at = [&](unsigned m) {
+    return (unsigned)*reinterpret_cast<const E *>(lb + (unsigned long long)min(m, last) * lsb);
   };
-  unsigned c0 = *p, c1 = next(q + LPP), c2 = next(q + 2 * LPP), c3 = next(q + 3 * LPP);
+  unsigned c0 = *lp, c1 = at(1), c2 = at(2), c3 = at(3);
   NbrRec ra, rb;
   load(c0, ra);
-  for (int e = q;; e += 4 * LPP) {
-    const unsigned n0 = next(e + 4 * LPP), n1 = next(e + 5 * LPP), n2 = next(e + 6 * LPP),
-                   n3 = next(e + 7 * LPP);
+  for (unsigned e = q, m = 4;; e += 4 * LPP, m += 4) {
+    const unsigned n0 = at(m), n1 = at(m + 1), n2 = at(m + 2), n3 = at(m + 3);
     // keep those loads here: the scheduler would otherwise sink them to
     // where they are used, a pair before
     __builtin_amdgcn_sched_barrier(0);
