@@ -328,6 +328,27 @@ def test_compact_reference_table_3d(gpu, solid_lattice, solid_blocks):
     sim.close()
 
 
+def test_lattice_blocks_two_scenes_3d(gpu):
+    # Two 3D scenes in one context, each solid its own lattice: the grid holds
+    # both bounding boxes one after the other, the block list both scenes'
+    # blocks (6^3 and 8^3 solids: four blocks each), and each scene's block
+    # reads only its own cells. Each scene follows its own oracle.
+    scs = [scenes.periodic_box_with_solid(dim=3, n=12, eta=0.5, amp=0.3, solid_lattice=True, seed=5),
+           scenes.periodic_box_with_solid(dim=3, n=16, eta=0.5, amp=0.2, solid_lattice=True, seed=9)]
+    note("lattice blocks, two 3D scenes")
+    sim = sph.Simulation(scs, solid_lds=0)
+    tab = sim.solid_table()
+    assert tab["compact"] == 1 and tab["lattice_blocks"] == 8, tab
+    oras = [O.Oracle(sc) for sc in scs]
+    for k in range(4):
+        sim.step()
+        for i, o in enumerate(oras):
+            o.step(1)
+            compare(sim, o, scene=i, label=f"two lattices scene {i} step {k + 1}")
+    sim.sync()
+    sim.close()
+
+
 def test_channel_with_inflow(gpu):
     # Periodic channel with the inflow buffer, cylinder walls and the plate.
     sc = scenes.plate_behind_cylinder(dp_f=0.01)
