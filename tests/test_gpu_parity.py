@@ -328,6 +328,31 @@ def test_compact_reference_table_3d(gpu, solid_lattice, solid_blocks):
     sim.close()
 
 
+@pytest.mark.parametrize("solid_blocks", [0, -1])
+def test_lattice_blocks_notched_solid_3d(gpu, solid_blocks):
+    # An 8^3 lattice block with one corner octant (4^3) taken out: the notch's
+    # cells lie inside the bounding box but hold no particle, so the lattice
+    # passes stage zeros there (and a presence weight 0 in the rate pass).
+    sc = scenes.periodic_box_with_solid(dim=3, n=16, eta=0.5, amp=0.3, solid_lattice=True, seed=11)
+    xs = sc["x_solid"]
+    mid = 0.5 * (xs.min(axis=0) + xs.max(axis=0))
+    keep = ~np.all(xs > mid, axis=1)
+    assert keep.sum() == 512 - 64
+    sc["x_solid"] = np.ascontiguousarray(xs[keep])
+    sc["v_solid"] = np.ascontiguousarray(sc["v_solid"][keep])
+    note(f"notched lattice solid, solid_blocks {solid_blocks}")
+    sim = sph.Simulation(sc, solid_lds=0, solid_blocks=solid_blocks)
+    tab = sim.solid_table()
+    assert tab["compact"] == 1 and tab["lattice_blocks"] == (4 if solid_blocks == 0 else 0), tab
+    o = O.Oracle(sc)
+    for k in range(5):
+        one_step(sim, o)
+        compare(sim, o, label=f"notched blocks {solid_blocks} step {k + 1}")
+    assert o.scalars()["kappa"] > 1
+    sim.sync()
+    sim.close()
+
+
 def test_lattice_blocks_two_scenes_3d(gpu):
     # Two 3D scenes in one context, each solid its own lattice: the grid holds
     # both bounding boxes one after the other, the block list both scenes'
