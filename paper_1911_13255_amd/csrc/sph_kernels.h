@@ -53,9 +53,6 @@ static_assert(kLatB2 == 16 && kLatB1 == 4 && kLatThreads % 64 == 0, "a wave is o
 // the hardware deals consecutive workgroups to its 8 XCDs in turn; lattice
 // blocks are launched so that each XCD runs a contiguous run of the block
 // list, whose neighbours share halo cells in that XCD's L2
-#ifndef MRSPH_LAT_XCD
-#define MRSPH_LAT_XCD 1
-#endif
 constexpr int kXcds = 8;
 
 struct LaunchCfg {

@@ -2539,18 +2539,15 @@ __global__ void __launch_bounds__(256) k_solid_rate(Dev D, int sub) {
 // workgroup stages those of the cells within kLatR spacings (zeros for empty
 // ones) in LDS with coalesced loads and no index lookups, and each free
 // particle sums over the offset classes at fixed shifts from its own halo
-// position: every pair becomes LDS reads at an immediate offset, with no
-// table entry and no gather.  The set summed over is the reference table's
+// position: every pair becomes three LDS reads at the class's shift, with
+// no table entry and no gather.  The set summed over is the reference table's
 // (checked at set-up), the order the classes'.
 
-// the block of the list this workgroup takes (-1: none)
+// the block of the list this workgroup takes (-1: none); the grid is
+// kXcds * ceil(lat_nblocks / kXcds) workgroups
 __device__ __forceinline__ int lat_block(const Dev &D) {
-#if MRSPH_LAT_XCD
   const int per = (D.lat_nblocks + kXcds - 1) / kXcds;
   const int b = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
-#else
-  const int b = blockIdx.x;
-#endif
   return b < D.lat_nblocks ? b : -1;
 }
 
@@ -4223,7 +4220,7 @@ void launch_solid_first(const Dev &D, bool adopt, hipStream_t st) {
 void launch_solid_pass(const Dev &D, int sub, hipStream_t st) {
   if (D.ns == 0) return;
   if (D.dim == 3 && D.lat_nblocks > 0) {
-    const int grid = MRSPH_LAT_XCD ? (D.lat_nblocks + kXcds - 1) / kXcds * kXcds : D.lat_nblocks;
+    const int grid = (D.lat_nblocks + kXcds - 1) / kXcds * kXcds;
     hipLaunchKernelGGL(k_solid_momentum_lat, dim3(grid), dim3(kLatThreads), 0, st, D, sub);
     hipLaunchKernelGGL(k_solid_rate_lat, dim3(grid), dim3(kLatThreads), 0, st, D, sub);
     return;
