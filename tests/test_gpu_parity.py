@@ -353,6 +353,27 @@ def test_lattice_blocks_notched_solid_3d(gpu, solid_blocks):
     sim.close()
 
 
+def test_lattice_blocks_any_storage_order_3d(gpu):
+    # The lattice blocks map cells to particles through the grid, whatever the
+    # order the solid is stored in: the same 6^3 block with its particles in a
+    # seeded random order (the axis order then only steers the cell layout's
+    # locality) still follows the oracle.
+    sc = scenes.periodic_box_with_solid(dim=3, n=12, eta=0.5, amp=0.3, solid_lattice=True, seed=13)
+    perm = np.random.default_rng(13).permutation(len(sc["x_solid"]))
+    sc["x_solid"] = np.ascontiguousarray(sc["x_solid"][perm])
+    sc["v_solid"] = np.ascontiguousarray(sc["v_solid"][perm])
+    note("lattice blocks, solid in random storage order")
+    sim = sph.Simulation(sc, solid_lds=0)
+    tab = sim.solid_table()
+    assert tab["compact"] == 1 and tab["lattice_blocks"] == 4, tab
+    o = O.Oracle(sc)
+    for k in range(5):
+        one_step(sim, o)
+        compare(sim, o, label=f"permuted lattice step {k + 1}")
+    sim.sync()
+    sim.close()
+
+
 def test_lattice_blocks_two_scenes_3d(gpu):
     # Two 3D scenes in one context, each solid its own lattice: the grid holds
     # both bounding boxes one after the other, the block list both scenes'
