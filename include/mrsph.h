@@ -110,15 +110,20 @@ typedef struct {
                            particles' fluid rows that indexes that set (2 bytes per pair-list slot
                            more device memory).  Results equal the per-pair gathers bit for bit.
                            -1: per-pair gathers.  2D always uses per-pair gathers. */
-  int solid_blocks;     /* 0: in 3D, where the compact reference table is on and every scene's solid
-                           sits on one lattice (one particle per cell, a bounding box of at most 4
-                           cells per particle) whose reference neighbours are exactly the lattice
-                           points within 2 h_S, the streamed sub-step passes run one workgroup per
-                           block of 4 x 4 x 16 lattice cells: it stages the P B or v of the cells
-                           within two spacings in LDS and sums over the offset classes in place of
-                           the pair table (a grid of 4 bytes per cell of the bounding boxes more
-                           device memory).  Sums run in class order, not table order, so results
-                           differ from the table walk by FP32 rounding.  -1: the pair table. */
+  int solid_blocks;     /* 0: in 3D, where every scene's solid sits near one lattice (each particle
+                           within a quarter spacing of its own lattice point, a bounding box of at
+                           most 4 cells per particle) and its reference neighbours are exactly the
+                           lattice points at offsets that reach within 2 h_S, the streamed sub-step
+                           passes run one workgroup per block of 4 x 4 x 16 lattice cells: it stages
+                           the P B or v of the cells within two spacings in LDS and sums over the
+                           offset classes in place of the pair table.  On an exact lattice (the
+                           compact table) a class carries its gradient; otherwise each pair's
+                           gradient is formed in FP32 from the class's lattice vector and the two
+                           particles' offsets (all scenes with solid then of one spacing,
+                           smoothing length and volume).  16 bytes per cell of the bounding boxes
+                           more device memory.  Sums run in class order, not table order, so
+                           results differ from the table walk by FP32 rounding.  -1: the pair
+                           table. */
 } sph_options;
 
 /* Field ids for sph_read / sph_write (FP64, original particle order).
@@ -318,7 +323,8 @@ int sph_launch_config(sph_ctx *ctx, int *out);
  * gradient and the index); out[1] = pair capacity per solid particle;
  * out[2] = bytes per pair that the table walk reads; out[3] = lattice
  * blocks of the 3D streamed passes (sph_options.solid_blocks; 0 when they
- * walk the table), out[4] = offset classes those blocks sum over.
+ * walk the table; with out[0] = 0 they form each pair's gradient from its
+ * lattice vector and offsets), out[4] = offset classes those blocks sum over.
  * SPH_E_ORDER without a context, SPH_E_ARG for a null out. */
 int sph_solid_table(sph_ctx *ctx, int *out);
 

@@ -68,6 +68,8 @@ struct Plan {
   // per scene (grid offset, L0, L1, L2), the blocks, each particle's cell and
   // the lattice axes slowest to fastest in storage
   std::vector<int> lat_grid, lat_cell;
+  std::vector<float> lat_jit;  // each particle's offset from its lattice point (3 per particle, FP32)
+  double lat_jit_max = 0.0;    // the largest of them, in spacings
   std::vector<int4> lat_scene, lat_blocks;
   int lat_axis[3] = {0, 1, 2};
   LaunchCfg cfg{256, 256, 256};
@@ -98,14 +100,17 @@ uint64_t morton_code(int d, const int *c) {
 }
 
 // Lattice blocks of the streamed solid passes (3D).  Every scene's solid must
-// sit on one lattice of spacing dp_S (each axis's coordinate an integer
-// number of spacings from the scene's minimum, to 1e-6 of a spacing, one
-// particle per cell) in a bounding box of at most 4 cells per particle;
-// otherwise P keeps no blocks.  Whether the reference neighbours are exactly
+// sit near one lattice of spacing dp_S (each axis's coordinate within a
+// quarter spacing of an integer number of spacings from the scene's minimum,
+// one particle per cell) in a bounding box of at most 4 cells per particle;
+// otherwise P keeps no blocks.  Each particle's offset from its lattice
+// point is kept (zero to 1e-6 of a spacing on an exact lattice).  Whether the reference neighbours are exactly
 // the lattice points within 2 h_S is checked by sph_init once the table is
 // built.
 void plan_lattice(const sph_scene *sc, int n, Plan &P) {
   std::vector<int> cell((size_t)3 * P.ns);
+  std::vector<float> jit((size_t)3 * P.ns, 0.0f);
+  double jmax = 0.0;
   long long changes[3] = {0, 0, 0};
   for (int s = 0; s < n; ++s) {
     const sph_scene &S = sc[s];
@@ -120,8 +125,10 @@ void plan_lattice(const sph_scene *sc, int n, Plan &P) {
       for (int k = 0; k < 3; ++k) {
         const double d = (S.x_solid[3 * (size_t)i + k] - lo[k]) / S.dp_s;
         const double r = std::rint(d);
-        if (!(std::fabs(d - r) <= 1e-6) || r > 1e6) return;
+        if (!(std::fabs(d - r) <= 0.25) || r > 1e6) return;
         cell[3 * (size_t)(base + i) + k] = (int)r;
+        jit[3 * (size_t)(base + i) + k] = (float)(S.x_solid[3 * (size_t)i + k] - (lo[k] + r * S.dp_s));
+        jmax = std::max(jmax, std::fabs(d - r));
         if (i > 0 && cell[3 * (size_t)(base + i) + k] != cell[3 * (size_t)(base + i - 1) + k]) ++changes[k];
       }
   }
@@ -167,6 +174,8 @@ void plan_lattice(const sph_scene *sc, int n, Plan &P) {
   if (blocks.empty()) return;
   P.lat_grid = std::move(grid);
   P.lat_cell = std::move(cell);
+  P.lat_jit = std::move(jit);
+  P.lat_jit_max = jmax;
   P.lat_scene = std::move(scene);
   P.lat_blocks = std::move(blocks);
   for (int k = 0; k < 3; ++k) P.lat_axis[k] = ax[k];
@@ -535,6 +544,7 @@ size_t carve(char *base, const Plan &P, Dev &D) {
   take(D.nbc_ok, 1);
   take(D.lat_grid, P.lat_grid.size());
   take(D.lat_of, P.lat_grid.empty() ? 1 : ns);
+  take(D.lat_jit, P.lat_grid.empty() ? 1 : 3 * P.lat_grid.size());
   take(D.lat_scene, P.lat_scene.size());
   take(D.lat_blocks, P.lat_blocks.size());
   take(D.lat_cls, P.lat_blocks.empty() ? 1 : kNbrClasses);
@@ -939,28 +949,52 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
   // reference neighbours are exactly the lattice points at the offsets of
   // nonzero class gradient (those the table holds are among them, so equal
   // counts suffice)
-  D.lat_ncls = D.lat_nblocks = D.lat_ncells = 0;
-  if (D.nbr_compact && !P.lat_blocks.empty()) {
+  D.lat_ncls = D.lat_nblocks = D.lat_ncells = D.lat_jitter = 0;
+  // a solid near a lattice without the compact table: the passes form each
+  // pair's gradient from its lattice vector and the two particles' offsets
+  // (every scene with solid of one spacing, smoothing length and volume)
+  int s_ref = -1;
+  bool same = true;
+  for (int s = 0; s < n_scenes; ++s) {
+    const ScenePar &q = P.par[s];
+    if (q.s_count == 0) continue;
+    if (s_ref < 0) s_ref = s;
+    else same = same && q.dps == P.par[s_ref].dps && q.hs == P.par[s_ref].hs && q.Vs == P.par[s_ref].Vs;
+  }
+  const bool jitter = !D.nbr_compact && same && s_ref >= 0;
+  if (P.dim == 3 && !P.lat_blocks.empty() && (D.nbr_compact || jitter)) {
     std::vector<float4> g(kNbrClasses);
     std::vector<int> cnt(P.ns);
     HIPCHK_INIT(hipMemcpy(g.data(), D.s_gcls, sizeof(float4) * kNbrClasses, hipMemcpyDeviceToHost));
     HIPCHK_INIT(hipMemcpy(cnt.data(), D.s_cnt, sizeof(int) * P.ns, hipMemcpyDeviceToHost));
     std::vector<float4> cls;
-    std::vector<std::array<int, 3>> off;
+    std::vector<std::array<int, 3>> off;  // along the lattice axes
+    const double dps = jitter ? P.par[s_ref].dps : 0.0, hs = jitter ? P.par[s_ref].hs : 0.0;
+    // offsets that a pair can reach within 2 h_S with the largest offsets found
+    const double reach = 2.0 * hs + 2.0 * std::sqrt(3.0) * P.lat_jit_max * dps;
     for (int c = 0; c < 125; ++c) {
-      if (g[c].x == 0.0f && g[c].y == 0.0f && g[c].z == 0.0f) continue;
       const int o[3] = {c / 25 - 2, (c / 5) % 5 - 2, c % 5 - 2};
+      const double ol = std::sqrt((double)(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]));
+      if (jitter ? (ol == 0.0 || ol * dps >= reach) : (g[c].x == 0.0f && g[c].y == 0.0f && g[c].z == 0.0f))
+        continue;
       const int q[3] = {o[P.lat_axis[0]], o[P.lat_axis[1]], o[P.lat_axis[2]]};
       const int shift = q[1] * kLatRow + q[0] * kLatH2 + q[2];
       float sf;
       std::memcpy(&sf, &shift, sizeof sf);
-      cls.push_back(make_float4(g[c].x, g[c].y, g[c].z, sf));
+      if (jitter)
+        cls.push_back(make_float4((float)(-o[0] * dps), (float)(-o[1] * dps), (float)(-o[2] * dps), sf));
+      else
+        cls.push_back(make_float4(g[c].x, g[c].y, g[c].z, sf));
       off.push_back({q[0], q[1], q[2]});
     }
+    // every free particle's table row holds exactly the existing lattice
+    // neighbours at those offsets (the compact table's are among them; with
+    // offsets, those within 2 h_S, none within 1e-4 of it)
     bool ok = !cls.empty();
     for (int s = 0; s < n_scenes && ok; ++s) {
       const ScenePar &p = P.par[s];
       const int4 L = P.lat_scene[s];
+      const double *xs = scenes[s].x_solid;
       for (int i = 0; i < p.s_count - p.s_nclamp && ok; ++i) {
         const int a = p.s_begin + i;
         const int *c = &P.lat_cell[3 * (size_t)a];
@@ -969,9 +1003,22 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
         for (const auto &q : off) {
           const int x0 = c0 + q[0], x1 = c1 + q[1], x2 = c2 + q[2];
           if (x0 < 0 || x0 >= L.y || x1 < 0 || x1 >= L.z || x2 < 0 || x2 >= L.w) continue;
-          hits += P.lat_grid[L.x + ((size_t)x0 * L.z + x1) * L.w + x2] >= 0;
+          const int b = P.lat_grid[L.x + ((size_t)x0 * L.z + x1) * L.w + x2];
+          if (b < 0) continue;
+          if (!jitter) {
+            ++hits;
+            continue;
+          }
+          double r2 = 0.0;
+          for (int k = 0; k < 3; ++k) {
+            const double d = xs[3 * (size_t)i + k] - xs[3 * (size_t)(b - p.s_begin) + k];
+            r2 += d * d;
+          }
+          const double cut = 4.0 * hs * hs;
+          ok = ok && std::fabs(r2 - cut) > 1e-4 * cut;
+          hits += r2 < cut;
         }
-        ok = hits == cnt[a];
+        ok = ok && hits == cnt[a];
       }
     }
     if (ok) {
@@ -1000,6 +1047,14 @@ int sph_init(const sph_scene *scenes, int n_scenes, const sph_options *opt, void
       HIPCHK_INIT(hipMemcpy(D.lat_cls, cls.data(), sizeof(float4) * cls.size(), hipMemcpyHostToDevice));
       D.lat_ncls = (int)cls.size();
       D.lat_nblocks = (int)P.lat_blocks.size();
+      if (jitter) {
+        // each particle's offset from its lattice point, in cell order
+        std::vector<float> jc((size_t)3 * P.lat_grid.size(), 0.0f);
+        for (int a = 0; a < P.ns; ++a)
+          for (int k = 0; k < 3; ++k) jc[(size_t)k * P.lat_grid.size() + of[a]] = P.lat_jit[3 * (size_t)a + k];
+        HIPCHK_INIT(hipMemcpy(D.lat_jit, jc.data(), sizeof(float) * jc.size(), hipMemcpyHostToDevice));
+        D.lat_jitter = 1;
+      }
     }
   }
 #undef HIPCHK_INIT

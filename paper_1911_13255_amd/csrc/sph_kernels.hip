@@ -2589,11 +2589,38 @@ __device__ __forceinline__ int lat_own(const int4 &L, const int4 &blk, int &pos)
   return in ? L.x + (c0 * L.z + c1) * L.w + c2 : -1;
 }
 
+// Jittered lattice (lat_jitter): V_b grad_a W(r) of a pair in FP32 from
+// r = X_a - X_b = (the class's lattice vector) + (offset of a) - (offset of
+// b), the offsets staged in LDS after the pass's own components (jt), and
+// the same kernel as the reference table: g = r Vs (-5 alpha / h^2) t^3 with
+// t = max(0, 1 - |r| / (2 h)) (zero beyond the support).
+struct LatKernel {
+  float kc, inv2h;
+};
+__device__ __forceinline__ LatKernel lat_kernel(const ScenePar &P) {
+  const double h = P.hs, alpha = 21.0 / (16.0 * M_PI * h * h * h);
+  return {(float)(-5.0 * alpha * (double)P.Vs / (h * h)), (float)(0.5 / h)};
+}
+__device__ __forceinline__ void lat_pair_gradient(const LatKernel &K, const float4 &cls, const float *ja,
+                                                  const float *jb, float *g) {
+  const float r[3] = {cls.x + (ja[0] - jb[0]), cls.y + (ja[kLatLds] - jb[kLatLds]),
+                      cls.z + (ja[2 * kLatLds] - jb[2 * kLatLds])};
+  const float rr = sqrtf(fmaf(r[0], r[0], fmaf(r[1], r[1], r[2] * r[2])));
+  const float t = fmaxf(0.0f, fmaf(-rr, K.inv2h, 1.0f));
+  const float f = K.kc * (t * t * t);
+  for (int k = 0; k < 3; ++k) g[k] = r[k] * f;
+}
+
 // Momentum pass on lattice blocks: the halo's FP32 P B in LDS one row of
 // three components at a time (17 KB, so that LDS admits eight workgroups per
 // CU; all nine at once held it to three).
+//
+// kJit: all nine components and the halo's offsets at once (68 KB, two
+// workgroups per CU), each pair's gradient formed once for the three rows.
+template <bool kJit>
 __global__ void __launch_bounds__(kLatThreads) k_solid_momentum_lat(Dev D, int sub) {
-  __shared__ float pb[3 * kLatLds];
+  __shared__ float pb[(kJit ? 12 : 3) * kLatLds];
+  float *jt = pb + 9 * kLatLds;  // kJit: the halo's offsets
   const int bi = lat_block(D);
   if (bi < 0) return;
   const int4 blk = D.lat_blocks[bi];
@@ -2611,6 +2638,33 @@ __global__ void __launch_bounds__(kLatThreads) k_solid_momentum_lat(Dev D, int s
   if (act) solid_momentum_own<3>(D, a, acc);
   const size_t NC = D.lat_ncells;
   float accr[3] = {0.0f, 0.0f, 0.0f};
+  if constexpr (kJit) {
+    lat_stage(L, blk, [&](int c, int l) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) pb[k * kLatLds + l] = c >= 0 ? D.s_PBf[k * NC + c] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) jt[k * kLatLds + l] = c >= 0 ? D.lat_jit[k * NC + c] : 0.0f;
+    });
+    const LatKernel K = lat_kernel(P);
+    __syncthreads();
+    if (!act) return;
+    const float *r0 = pb + pos;
+    const int nc = D.lat_ncls;
+#pragma unroll 2
+    for (int j = 0; j < nc; ++j) {
+      const float4 e = D.lat_cls[j];
+      const int sh = __float_as_int(e.w);
+      float gv[3];
+      lat_pair_gradient(K, e, jt + pos, jt + pos + sh, gv);
+      const float *r = r0 + sh;
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) accr[i] += r[(3 * i + k) * kLatLds] * gv[k];
+    }
+    MomOwn o;
+    solid_momentum_load<3>(D, a, o);
+    solid_momentum_finish<3>(D, P, S, a, cell, acc, accr, o);
+    return;
+  }
   // row i + 1's halo loaded into registers while row i is walked
   float stg[kLatPer][3];
   auto fetch = [&](int i) {
@@ -2655,9 +2709,11 @@ __global__ void __launch_bounds__(kLatThreads) k_solid_momentum_lat(Dev D, int s
 }
 
 // Rate pass on lattice blocks: the halo's FP32 v and presence weight (1 for
-// a cell with a particle, 0 for an empty one) in LDS.
+// a cell with a particle, 0 for an empty one) in LDS (kJit: and the offsets).
+template <bool kJit>
 __global__ void __launch_bounds__(kLatThreads) k_solid_rate_lat(Dev D, int sub) {
-  __shared__ float vh[4 * kLatLds];
+  __shared__ float vh[(kJit ? 7 : 4) * kLatLds];
+  float *jt = vh + 4 * kLatLds;
   const int bi = lat_block(D);
   if (bi < 0) return;
   const int4 blk = D.lat_blocks[bi];
@@ -2674,7 +2730,13 @@ __global__ void __launch_bounds__(kLatThreads) k_solid_rate_lat(Dev D, int sub) 
     vh[kLatLds + l] = v.y;
     vh[2 * kLatLds + l] = v.z;
     vh[3 * kLatLds + l] = v.w;
+    if (kJit) {
+      const size_t NC = D.lat_ncells;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) jt[k * kLatLds + l] = c >= 0 ? D.lat_jit[k * NC + c] : 0.0f;
+    }
   });
+  const LatKernel K = lat_kernel(P);
   __syncthreads();
   if (a < 0 || a - P.s_begin >= P.s_count - P.s_nclamp) return;
   // B and H in flight during the LDS walk
@@ -2686,8 +2748,9 @@ __global__ void __launch_bounds__(kLatThreads) k_solid_rate_lat(Dev D, int sub) 
 #pragma unroll 8
     for (int j = 0; j < nc; ++j) {
       const float4 g = D.lat_cls[j];
-      const float gv[3] = {g.x, g.y, g.z};
+      float gv[3] = {g.x, g.y, g.z};
       const float *r = r0 + __float_as_int(g.w);
+      if (kJit) lat_pair_gradient(K, g, jt + pos, jt + pos + __float_as_int(g.w), gv);
       const float w = r[3 * kLatLds];
       for (int i = 0; i < 3; ++i) {
         // (v_b - v_a) exactly for a particle, zero for an empty cell
@@ -4221,8 +4284,13 @@ void launch_solid_pass(const Dev &D, int sub, hipStream_t st) {
   if (D.ns == 0) return;
   if (D.dim == 3 && D.lat_nblocks > 0) {
     const int grid = (D.lat_nblocks + kXcds - 1) / kXcds * kXcds;
-    hipLaunchKernelGGL(k_solid_momentum_lat, dim3(grid), dim3(kLatThreads), 0, st, D, sub);
-    hipLaunchKernelGGL(k_solid_rate_lat, dim3(grid), dim3(kLatThreads), 0, st, D, sub);
+    if (D.lat_jitter) {
+      hipLaunchKernelGGL(k_solid_momentum_lat<true>, dim3(grid), dim3(kLatThreads), 0, st, D, sub);
+      hipLaunchKernelGGL(k_solid_rate_lat<true>, dim3(grid), dim3(kLatThreads), 0, st, D, sub);
+    } else {
+      hipLaunchKernelGGL(k_solid_momentum_lat<false>, dim3(grid), dim3(kLatThreads), 0, st, D, sub);
+      hipLaunchKernelGGL(k_solid_rate_lat<false>, dim3(grid), dim3(kLatThreads), 0, st, D, sub);
+    }
     return;
   }
   LAUNCH_DIM(D.dim, k_solid_momentum, grid_for(D.ns, 256), dim3(256), st, D, sub);

@@ -199,6 +199,13 @@ struct Dev {
   int4 *lat_scene, *lat_blocks;
   float4 *lat_cls;
   int lat_ncls, lat_nblocks, lat_ncells;
+  // lat_jitter = 1: the solid is near a lattice but not on it (no compact
+  // table); lat_cls[j] then holds the class's lattice vector -o dp_S (xyz)
+  // and its shift, lat_jit[k * lat_ncells + cell] each particle's offset from
+  // its lattice point (zero in empty cells), and the passes form each pair's
+  // gradient from the two.
+  int lat_jitter;
+  float *lat_jit;
   float4 *s_vf;                    // v rounded to FP32, one 16-byte record per particle: what the streamed
                                    // rate pass gathers (free particles: written by the momentum pass of the
                                    // same sub-step; clamped ones: by the first pass of the step)

@@ -212,16 +212,19 @@ def test_dam_break_3d_sampled_first_step(gpu):
         assert e <= 1e-4, (name, e)
 
 
-def test_dam_break_3d_lattice_blocks_match_table(gpu):
-    # The streamed solid passes on lattice blocks and on the compact table sum
-    # the same pairs, in class order and in table order: with a velocity bump
-    # in the plate, over three acoustic steps, the whole plate's state agrees
-    # to the FP32 rounding of those sums.
-    sc = scenes.dam_break_plate_3d(seed=1)
+@pytest.mark.parametrize("solid_lattice", [True, False])
+def test_dam_break_3d_lattice_blocks_match_table(gpu, solid_lattice):
+    # The streamed solid passes on lattice blocks and on the reference table
+    # sum the same pairs, in class order and in table order (on the jittered
+    # plate with each pair's gradient formed in FP32 from its lattice vector
+    # and the two offsets, against the table's FP64 gradients rounded to
+    # FP32): with a velocity bump in the plate, over three acoustic steps,
+    # the whole plate's state agrees to the FP32 rounding of those sums.
+    sc = scenes.dam_break_plate_3d(seed=1, solid_lattice=solid_lattice)
     vs, _ = plate_bump(sc)
     out = {}
     for blocks in (0, -1):
-        note(f"3D dam break, solid_blocks {blocks}")
+        note(f"3D dam break, lattice plate {solid_lattice}, solid_blocks {blocks}")
         sim = sph.Simulation(sc, solid_blocks=blocks)
         assert (sim.solid_table()["lattice_blocks"] > 0) == (blocks == 0)
         sim.write(sph.S_V, vs)
@@ -238,6 +241,7 @@ def test_dam_break_3d_lattice_blocks_match_table(gpu):
         if name == "F":
             g, r = g - np.eye(3), r - np.eye(3)
         errs[name] = np.abs(g - r).max() / np.abs(r).max()
-    note("3D plate, lattice blocks against the table: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    note(f"3D plate (lattice {solid_lattice}), lattice blocks against the table: " +
+         ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for name, e in errs.items():
         assert e <= 1e-5, (name, e)

@@ -300,13 +300,14 @@ def test_periodic_box_with_free_solid(gpu, dim, eta, solid_lds):
     sim.close()
 
 
-@pytest.mark.parametrize("solid_lattice,solid_blocks", [(True, 0), (True, -1), (False, 0)])
+@pytest.mark.parametrize("solid_lattice,solid_blocks", [(True, 0), (True, -1), (False, 0), (False, -1)])
 def test_compact_reference_table_3d(gpu, solid_lattice, solid_blocks):
     # A solid whose reference configuration is an exact lattice lets the
     # streamed 3D passes walk the 4-byte table of lattice-offset classes, or
     # (by default) sum over the classes on lattice blocks with their halos in
-    # LDS; the default jittered one (1e-4 dp_S) keeps the full 16-byte table
-    # and no blocks. All follow the oracle.
+    # LDS; the default jittered one (1e-4 dp_S) keeps the full 16-byte table,
+    # and on lattice blocks forms each pair's gradient from its lattice vector
+    # and the two particles' offsets. All follow the oracle.
     # n = 12: a 6^3 block, whose inner particles hold every lattice offset
     # class; it spans four blocks of 4 x 4 x 16 cells, each mostly empty
     sc = scenes.periodic_box_with_solid(dim=3, n=12, eta=0.5, amp=0.3, solid_lattice=solid_lattice)
@@ -315,7 +316,7 @@ def test_compact_reference_table_3d(gpu, solid_lattice, solid_blocks):
     tab = sim.solid_table()
     assert tab["compact"] == (1 if solid_lattice else 0), tab
     assert tab["bytes_per_pair"] == (4 if solid_lattice else 16), tab
-    blocks = solid_lattice and solid_blocks == 0
+    blocks = solid_blocks == 0
     assert tab["lattice_blocks"] == (4 if blocks else 0), tab
     # offsets within 2 h_S = 2.6 dp_S: |o|^2 <= 6, 80 classes
     assert tab["classes"] == (80 if blocks else 0), tab
