@@ -115,10 +115,13 @@ def test_split_solid_option_is_validated_and_sized():
 
 
 def test_solid_blocks_option_is_validated_and_sized():
-    # solid_blocks: 0 or -1. A 3D solid on an exact lattice adds the lattice
-    # grid of its bounding box (4 bytes per cell) to the arena; a jittered
-    # reference configuration, a 2D scene and -1 add nothing
+    # solid_blocks: 0 or -1. A 3D solid on or near a lattice (the default
+    # jitter of 1e-4 dp_S) adds the lattice grid of its bounding box and the
+    # particles' offsets (16 bytes per cell) to the arena; a solid further
+    # off its lattice than a quarter spacing, a 2D scene and -1 add nothing
     import ctypes
+
+    import numpy as np
 
     from paper_1911_13255_amd import scenes, sph
 
@@ -132,7 +135,12 @@ def test_solid_blocks_option_is_validated_and_sized():
     jit = scenes.periodic_box_with_solid(dim=3, n=12, solid_lattice=False)
     assert nbytes(lat, solid_blocks=2) == 0 and nbytes(lat, solid_blocks=-2) == 0
     ns = len(lat["x_solid"])
-    assert nbytes(lat) >= nbytes(lat, solid_blocks=-1) + 4 * ns
-    assert nbytes(jit) == nbytes(jit, solid_blocks=-1)
+    assert nbytes(lat) >= nbytes(lat, solid_blocks=-1) + 16 * ns
+    assert nbytes(jit) >= nbytes(jit, solid_blocks=-1) + 16 * ns
+    off = scenes.periodic_box_with_solid(dim=3, n=12, solid_lattice=True)
+    xs = off["x_solid"].copy()
+    xs[::2, 0] += 0.4 * off["dp_s"]
+    off["x_solid"] = np.ascontiguousarray(xs)
+    assert nbytes(off) == nbytes(off, solid_blocks=-1)
     flat = scenes.periodic_box_with_solid(dim=2, n=12, solid_lattice=True)
     assert nbytes(flat) == nbytes(flat, solid_blocks=-1)
